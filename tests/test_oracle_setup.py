@@ -1,0 +1,369 @@
+"""Pins of the oracle's setup steps against what the paper and mathematics fix.
+
+Weights (Section 2.2), matching (Section 2.2, Section 3.1), Algorithm 2,
+prolongator (Section 2.2), Galerkin product (Section 2.1), double pairwise
+coarsening (Section 5 settings).  None of these tests re-types the oracle's
+formulas: they use hand-derived closed forms (tests/golden/closed_forms.json),
+brute force on tiny graphs, an independent sequential Suitor, scipy's sparse
+product, and invariants.
+"""
+import itertools
+import json
+import os
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from paper_1810_04221_amd import problems as P
+
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "closed_forms.json")))
+ULP = np.finfo(np.float64).eps
+
+
+def _sp(rp, ci, va):
+    n = len(rp) - 1
+    return sp.csr_matrix((va, ci, rp), shape=(n, n))
+
+
+def _general_spd(n, seed):
+    """Random s.p.d. matrix with off-diagonals of both signs (not an M-matrix)."""
+    rng = np.random.default_rng(seed)
+    M = sp.random(n, n, density=0.3, random_state=rng).toarray()
+    M = M + M.T
+    M[np.abs(M) > 0] *= rng.choice([-1.0, 1.0], size=int((np.abs(M) > 0).sum()))
+    M = 0.5 * (M + M.T)
+    lam = np.linalg.eigvalsh(M).min()
+    M += (abs(lam) + 0.1) * np.eye(n)
+    A = sp.csr_matrix(M)
+    A.sort_indices()
+    return A.indptr.astype(np.int32), A.indices.astype(np.int32), A.data.copy()
+
+
+# ----------------------------------------------------------------------------- weights
+def test_weights_two_by_two_hand_value(ora):
+    g = GOLD["two_by_two"]
+    A = sp.csr_matrix(np.array(g["A"]))
+    c = ora.weights(A.indptr, A.indices, A.data, np.array(g["w"]))
+    off = c[[1, 2]]
+    assert np.all(np.abs(off - g["c_num"] / g["c_den"]) <= 2 * ULP * 2)
+    assert c[0] == 0.0 and c[3] == 0.0  # diagonal is not an edge
+
+
+@pytest.mark.parametrize("gen,key", [(lambda: P.laplace1d(20), ("laplace1d", "weight")),
+                                      (lambda: P.poisson2d(8), ("poisson2d", "weight_sweep1"))])
+def test_weights_closed_forms(ora, gen, key):
+    rp, ci, va = gen()
+    c = ora.weights(rp, ci, va, np.ones(len(rp) - 1))
+    rows = np.repeat(np.arange(len(rp) - 1), np.diff(rp))
+    assert np.all(c[rows != ci] == GOLD[key[0]][key[1]])
+
+
+def test_weights_poisson3d_closed_form(ora):
+    rp, ci, va = P.poisson3d(5)
+    c = ora.weights(rp, ci, va, np.ones(125))
+    rows = np.repeat(np.arange(125), np.diff(rp))
+    num, den = GOLD["poisson3d"]["weight_sweep1"]
+    assert np.all(np.abs(c[rows != ci] - num / den) <= ULP * 2)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_weights_in_open_interval_0_2_and_symmetric(ora, seed):
+    # For an s.p.d. 2x2 principal block both quadratic forms are positive, so
+    # c = (w_perp^T B w_perp) / (w^T diag(B) w) lies in (0, 2).
+    rp, ci, va = _general_spd(30, seed) if seed % 2 else P.random_spd(40, 0.15, seed)
+    n = len(rp) - 1
+    w = np.random.default_rng(100 + seed).uniform(0.2, 2.0, n) * np.random.default_rng(seed).choice([-1, 1], n)
+    c = ora.weights(rp, ci, va, w)
+    A = _sp(rp, ci, va)
+    rows = np.repeat(np.arange(n), np.diff(rp))
+    off = rows != ci
+    assert np.all((c[off] > 0) & (c[off] < 2))
+    # bitwise equal from both ends of each edge
+    C = sp.csr_matrix((c, ci, rp), shape=(n, n))
+    assert np.array_equal(C.toarray(), C.T.toarray())
+    # quadratic-form characterisation with numpy, edge by edge
+    D = A.toarray()
+    for q in np.flatnonzero(off)[:200]:
+        i, j = rows[q], ci[q]
+        B = D[np.ix_([i, j], [i, j])]
+        wp = np.array([w[i], -w[j]])
+        ww = np.array([w[i], w[j]])
+        ref = (wp @ B @ wp) / (ww @ np.diag(np.diag(B)) @ ww)
+        assert abs(c[q] - ref) <= 8 * ULP * max(1.0, abs(ref))
+
+
+# ----------------------------------------------------------------------------- matching
+def _edges(rp, ci, c):
+    n = len(rp) - 1
+    E = {}
+    for i in range(n):
+        for q in range(rp[i], rp[i + 1]):
+            j = ci[q]
+            if j > i and np.isfinite(c[q]) and c[q] > 0:
+                E[(i, j)] = c[q]
+    return E
+
+
+def _all_matchings(n, E):
+    edges = sorted(E)
+    best = [0.0]
+
+    def rec(k, used, tot):
+        if k == len(edges):
+            best[0] = max(best[0], tot)
+            return
+        rec(k + 1, used, tot)
+        i, j = edges[k]
+        if not (used >> i) & 1 and not (used >> j) & 1:
+            rec(k + 1, used | (1 << i) | (1 << j), tot + E[(i, j)])
+
+    rec(0, 0, 0.0)
+    return best[0]
+
+
+def _suitor_sequential(n, E):
+    """Sequential Suitor (Manne and Halappanavar): every vertex proposes to its best
+    neighbour that prefers it over its current suitor; a displaced suitor proposes
+    again.  Preference at a vertex: larger weight, then larger neighbour index."""
+    nb = {u: [] for u in range(n)}
+    for (i, j), c in E.items():
+        nb[i].append((c, j))
+        nb[j].append((c, i))
+    suitor = [-1] * n
+    ws = [None] * n  # (c, proposer) of the current suitor
+
+    for u0 in range(n):
+        u = u0
+        while u >= 0:
+            best, bkey = -1, None
+            for c, v in nb[u]:
+                key = (c, u)
+                if ws[v] is None or key > ws[v]:
+                    if bkey is None or (c, v) > bkey:
+                        best, bkey = v, (c, v)
+            if best < 0:
+                break
+            y = suitor[best]
+            suitor[best] = u
+            ws[best] = (bkey[0], u)
+            u = y
+    mate = np.full(n, -1)
+    for v in range(n):
+        s = suitor[v]
+        if s >= 0 and suitor[s] == v:
+            mate[v] = s
+    return mate, suitor
+
+
+@pytest.mark.parametrize("seed", range(25))
+def test_matching_half_approx_maximal_and_equals_suitor(ora, seed):
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(4, 11))
+    rp, ci, va = P.random_spd(n, 0.35, seed, equal_weights=bool(seed % 3 == 0))
+    w = np.ones(n) if seed % 2 else rng.uniform(0.5, 1.5, n)
+    c = ora.weights(rp, ci, va, w)
+    mate = ora.match(rp, ci, c)
+    E = _edges(rp, ci, c)
+    # a matching
+    for i in range(n):
+        if mate[i] >= 0:
+            assert mate[mate[i]] == i and mate[i] != i
+            assert (min(i, mate[i]), max(i, mate[i])) in E
+    # maximal: no edge with both ends free
+    for (i, j) in E:
+        assert mate[i] >= 0 or mate[j] >= 0
+    # half approximation of the maximum weight matching (exhaustive)
+    opt = _all_matchings(n, E)
+    got = sum(E[(i, mate[i])] for i in range(n) if mate[i] > i)
+    assert got >= 0.5 * opt - 1e-12
+    # equal to the sequential Suitor result under the same preferences
+    sm, suitor = _suitor_sequential(n, E)
+    assert np.array_equal(sm, mate)
+    assert all(suitor[s] == v for v, s in enumerate(suitor) if s >= 0)  # mutual at the end
+
+
+def test_matching_adversarial_ties_closed_forms(ora):
+    # path with equal weights: pairs {n-2, n-1}, {n-4, n-3}, ...
+    rp, ci, va = P.laplace1d(9)
+    mate = ora.match(rp, ci, ora.weights(rp, ci, va, np.ones(9)))
+    assert mate.tolist() == [-1, 2, 1, 4, 3, 6, 5, 8, 7]
+    # star with equal weights: centre 0 matched to the largest leaf
+    n = 7
+    A = sp.lil_matrix((n, n))
+    for j in range(1, n):
+        A[0, j] = A[j, 0] = -1.0
+    A.setdiag([n + 1.0] + [2.0] * (n - 1))
+    A = A.tocsr(); A.sort_indices()
+    mate = ora.match(A.indptr, A.indices, ora.weights(A.indptr, A.indices, A.data, np.ones(n)))
+    assert mate[0] == n - 1 and (mate[1:n - 1] == -1).all()
+    # clique with equal weights: (n-1, n-2), (n-3, n-4), ...
+    n = 7
+    D = -np.ones((n, n)) + (n + 1.0) * np.eye(n)
+    A = sp.csr_matrix(D)
+    mate = ora.match(A.indptr, A.indices, ora.weights(A.indptr, A.indices, A.data, np.ones(n)))
+    assert mate.tolist() == [-1, 2, 1, 4, 3, 6, 5]
+    # 2-D grid, nx even: x-pairs {2k, 2k+1}
+    rp, ci, va = P.poisson2d(6)
+    mate = ora.match(rp, ci, ora.weights(rp, ci, va, np.ones(36)))
+    assert np.array_equal(mate, np.arange(36) ^ 1)
+
+
+# ----------------------------------------------------------------------------- Algorithm 2
+@pytest.mark.parametrize("seed", range(8))
+def test_aggregation_partition(ora, seed):
+    rp, ci, va = P.random_spd(60, 0.08, seed)
+    n = 60
+    mate = ora.match(rp, ci, ora.weights(rp, ci, va, np.ones(n)))
+    agg, nc, npairs, nsing = ora.aggregate(mate)
+    assert npairs == int((mate >= 0).sum()) // 2
+    assert nc == npairs + nsing and 2 * npairs + nsing == n
+    assert sorted(set(agg.tolist())) == list(range(nc))
+    for i in range(n):
+        if mate[i] >= 0:
+            assert agg[i] == agg[mate[i]]
+    # aggregates are numbered in the order of their smallest member
+    first = [min(np.flatnonzero(agg == e)) for e in range(nc)]
+    assert first == sorted(first)
+
+
+def test_aggregation_laplace1d(ora):
+    rp, ci, va = P.laplace1d(10)
+    mate = ora.match(rp, ci, ora.weights(rp, ci, va, np.ones(10)))
+    agg, nc, _, _ = ora.aggregate(mate)
+    assert nc == 5 and np.array_equal(agg, np.arange(10) // 2)
+
+
+# ----------------------------------------------------------------------------- prolongator
+@pytest.mark.parametrize("seed", range(6))
+def test_prolongator_orthonormal_and_w_in_range(ora, seed):
+    rng = np.random.default_rng(seed)
+    n = 80
+    rp, ci, va = P.random_spd(n, 0.06, seed)
+    w = rng.uniform(0.1, 3.0, n) * rng.choice([-1, 1], n)
+    mate = ora.match(rp, ci, ora.weights(rp, ci, va, w))
+    agg, nc, _, _ = ora.aggregate(mate)
+    p, wc = ora.prolong(agg, nc, w)
+    Pm = sp.csr_matrix((p, agg, np.arange(n + 1)), shape=(n, nc))
+    PtP = (Pm.T @ Pm).toarray()
+    assert np.abs(PtP - np.eye(nc)).max() <= 4 * ULP
+    assert np.all(np.abs(Pm @ wc - w) <= 4 * ULP * np.abs(w))
+    assert np.all(wc > 0)
+
+
+def test_prolongator_laplace1d(ora):
+    rp, ci, va = P.laplace1d(8)
+    mate = ora.match(rp, ci, ora.weights(rp, ci, va, np.ones(8)))
+    agg, nc, _, _ = ora.aggregate(mate)
+    p, wc = ora.prolong(agg, nc, np.ones(8))
+    assert np.all(p == 1 / np.sqrt(2.0)) and np.all(wc == np.sqrt(2.0))
+
+
+# ----------------------------------------------------------------------------- Galerkin
+@pytest.mark.parametrize("seed", range(6))
+def test_galerkin_matches_scipy_and_is_bitwise_symmetric(ora, seed):
+    rng = np.random.default_rng(seed)
+    n = 200
+    rp, ci, va = P.random_spd(n, 0.03, seed) if seed % 2 else _general_spd(60, seed)
+    n = len(rp) - 1
+    w = rng.uniform(0.5, 2.0, n)
+    mate = ora.match(rp, ci, ora.weights(rp, ci, va, w))
+    agg, nc, _, _ = ora.aggregate(mate)
+    p, wc = ora.prolong(agg, nc, w)
+    crp, cci, cva = ora.galerkin(rp, ci, va, agg, p, nc)
+    Pm = sp.csr_matrix((p, agg, np.arange(n + 1)), shape=(n, nc))
+    ref = (Pm.T @ _sp(rp, ci, va) @ Pm).toarray()
+    got = sp.csr_matrix((cva, cci, crp), shape=(nc, nc))
+    assert np.all(np.diff(crp) > 0)
+    for e in range(nc):
+        assert np.all(np.diff(cci[crp[e]:crp[e + 1]]) > 0)
+    scale = np.abs(va).max()
+    assert np.abs(got.toarray() - ref).max() <= 1e-14 * scale
+    # pattern: every structurally reachable (E, F) is stored
+    pat = (abs(Pm.T) @ (abs(_sp(rp, ci, va)) > 0).astype(float) @ abs(Pm)).toarray() > 0
+    assert np.array_equal(pat, got.toarray() != 0) or np.array_equal(pat.sum(), got.nnz)
+    G = got.toarray()
+    assert np.array_equal(G, G.T)  # bitwise
+
+
+def test_galerkin_laplace1d_half_T(ora):
+    m = 16
+    rp, ci, va = P.laplace1d(m)
+    h = ora.Hierarchy(rp, ci, va, np.ones(m), max_coarse=1, sweeps=1)
+    L1 = h.level(1)
+    A1 = _sp(L1["rowptr"], L1["col"], L1["val"]).toarray()
+    T = _sp(*P.laplace1d(m // 2)).toarray()
+    # p = fl(1/sqrt 2) squares to 1/2 only up to rounding: a few ulp
+    assert np.abs(A1 - 0.5 * T).max() <= 4 * ULP
+    assert np.all(L1["w"] == np.sqrt(2.0))
+
+
+def test_hierarchy_poisson2d_closed_form_and_sizes(ora):
+    c = P.config("G1")
+    h = ora.Hierarchy(c["rowptr"], c["col"], c["val"], c["w"], max_coarse=c["max_coarse"])
+    assert h.sizes() == [4096, 1024, 256]
+    g = GOLD["poisson2d"]
+    L1 = h.level(1)
+    A1 = _sp(L1["rowptr"], L1["col"], L1["val"])
+    ref = _sp(*P.poisson2d(32)) * (g["level1_off"] / -1.0)
+    # values involve fl(sqrt 2)^2 != 2: equal up to a few ulp of the diagonal
+    assert np.abs(A1.toarray() - ref.toarray()).max() <= 4 * ULP * g["level1_diag"]
+    assert np.array_equal(A1.toarray() != 0, ref.toarray() != 0)
+    assert np.all(np.abs(L1["w"] - g["level1_w"]) <= 4 * ULP * g["level1_w"])
+    # composed aggregates are 2x2 boxes
+    agg = h.level(0)["agg"].reshape(64, 64)
+    yy, xx = np.mgrid[0:64, 0:64]
+    assert np.array_equal(agg, (yy // 2) * 32 + xx // 2)
+
+
+def test_hierarchy_poisson3d_closed_form(ora):
+    rp, ci, va = P.poisson3d(4)
+    h = ora.Hierarchy(rp, ci, va, np.ones(64), max_coarse=1)
+    g = GOLD["poisson3d"]
+    L1 = h.level(1)
+    ref = (g["level1_diag"] * sp.identity(16)
+           + sp.kron(sp.identity(4), sp.kron(sp.identity(2), _sp(*P.laplace1d(2)) - 2 * sp.identity(2))) * -g["level1_offx"]
+           + sp.kron(sp.identity(4), sp.kron(_sp(*P.laplace1d(2)) - 2 * sp.identity(2), sp.identity(2))) * -g["level1_offy"]
+           + sp.kron(_sp(*P.laplace1d(4)) - 2 * sp.identity(4), sp.identity(4)) * -g["level1_offz"])
+    got = _sp(L1["rowptr"], L1["col"], L1["val"]).toarray()
+    assert np.abs(got - ref.toarray()).max() <= 4 * ULP * g["level1_diag"]
+    assert np.array_equal(got != 0, ref.toarray() != 0)
+    assert np.all(np.abs(L1["w"] - g["level1_w"]) <= 4 * ULP * g["level1_w"])
+
+
+@pytest.mark.parametrize("name,scale", [("G1", 0.5), ("G2", 0.16), ("G3", 0.1), ("G4", 0.1), ("G5", 0.12)])
+def test_hierarchy_invariants(ora, name, scale):
+    c = P.config(name, scale)
+    h = ora.Hierarchy(c["rowptr"], c["col"], c["val"], c["w"], max_coarse=min(c["max_coarse"], 40))
+    sizes = h.sizes()
+    assert h.nl >= 2
+    for k in range(h.nl):
+        L = h.level(k)
+        A = _sp(L["rowptr"], L["col"], L["val"])
+        D = A.toarray()
+        assert np.array_equal(D, D.T)  # bitwise symmetric
+        if L["n"] <= 3000:
+            np.linalg.cholesky(D)  # s.p.d.
+        if k < h.nl - 1:
+            # double pairwise: coarsening ratio at most 4 (Section 5 settings)
+            assert sizes[k] <= 4 * sizes[k + 1]
+            n, nc = L["n"], sizes[k + 1]
+            Pm = sp.csr_matrix((L["p"], L["agg"], np.arange(n + 1)), shape=(n, nc))
+            assert np.abs((Pm.T @ Pm).toarray() - np.eye(nc)).max() <= 8 * ULP if nc <= 3000 else True
+            wn = h.level(k + 1)["w"]
+            assert np.all(np.abs(Pm @ wn - L["w"]) <= 8 * ULP * np.abs(L["w"]))
+            assert np.bincount(L["agg"], minlength=nc).max() <= 4
+
+
+def test_setup_rejects_invalid_input(ora):
+    rp, ci, va = P.laplace1d(6)
+    with pytest.raises(ValueError):
+        ora.Hierarchy(rp, ci, va, np.array([1, 1, 0.0, 1, 1, 1]))
+    bad = va.copy()
+    bad[0] = -2.0
+    with pytest.raises(ValueError):
+        ora.Hierarchy(rp, ci, bad, np.ones(6))
+    bad = va.copy()
+    bad[3] = np.nan
+    with pytest.raises(ValueError):
+        ora.Hierarchy(rp, ci, bad, np.ones(6))

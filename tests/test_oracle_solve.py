@@ -1,0 +1,203 @@
+"""Pins of the oracle's preconditioner (Algorithm 1), flexible CG (Algorithm 3,
+read with r <- r - (alpha/rho) q and gamma_i / rho_{i-1} in the d and q
+updates), and gradient of the solve.
+
+References used: dense-matrix forms of the cycle built with numpy, the closed
+form of CG on the 1-D Laplacian (eigenvalues 4 sin^2(k pi / (2 (m + 1)))),
+scipy's CG with the same preconditioner, numpy dense solves and central finite
+differences.
+"""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+from paper_1810_04221_amd import problems as P
+
+
+def _sp(rp, ci, va):
+    n = len(rp) - 1
+    return sp.csr_matrix((va, ci, rp), shape=(n, n))
+
+
+def _jacobi_poly(A, dinv, sweeps):
+    """Dense operator of `sweeps` l1-Jacobi sweeps from zero: sum_t (I - DA)^t D."""
+    n = A.shape[0]
+    D = np.diag(dinv)
+    E = np.eye(n) - D @ A
+    S = np.zeros((n, n))
+    T = np.eye(n)
+    for _ in range(sweeps):
+        S += T @ D
+        T = T @ E
+    return S
+
+
+def test_single_level_cycle_is_20_jacobi_sweeps(ora):
+    rp, ci, va = P.random_spd(50, 0.1, 3)
+    h = ora.Hierarchy(rp, ci, va, np.ones(50), max_coarse=1000)
+    assert h.nl == 1
+    A = _sp(rp, ci, va).toarray()
+    dinv = 1.0 / np.abs(A).sum(axis=1)
+    S = _jacobi_poly(A, dinv, 20)
+    b = np.random.default_rng(0).standard_normal(50)
+    assert np.allclose(h.vcycle(b), S @ b, rtol=1e-12, atol=1e-13 * np.abs(S @ b).max())
+
+
+def test_two_level_cycle_dense_form(ora):
+    rp, ci, va = P.poisson2d(12)
+    n = 144
+    h = ora.Hierarchy(rp, ci, va, np.ones(n), max_coarse=40)
+    assert h.nl == 2
+    L0, L1 = h.level(0), h.level(1)
+    A = _sp(rp, ci, va).toarray()
+    Ac = _sp(L1["rowptr"], L1["col"], L1["val"]).toarray()
+    Pm = sp.csr_matrix((L0["p"], L0["agg"], np.arange(n + 1)), shape=(n, L1["n"])).toarray()
+    D = np.diag(1.0 / np.abs(A).sum(axis=1))
+    Sc = _jacobi_poly(Ac, 1.0 / np.abs(Ac).sum(axis=1), 20)
+    b = np.random.default_rng(1).standard_normal(n)
+    x1 = D @ b
+    x2 = x1 + Pm @ (Sc @ (Pm.T @ (b - A @ x1)))
+    x3 = x2 + D @ (b - A @ x2)
+    assert np.allclose(h.vcycle(b), x3, rtol=1e-12, atol=1e-13 * np.abs(x3).max())
+
+
+@pytest.mark.parametrize("name,scale", [("G1", 0.5), ("G2", 0.12), ("G3", 0.1), ("G4", 0.1)])
+def test_cycle_symmetric_positive_definite(ora, name, scale):
+    c = P.config(name, scale)
+    h = ora.Hierarchy(c["rowptr"], c["col"], c["val"], c["w"], max_coarse=min(c["max_coarse"], 30))
+    rng = np.random.default_rng(2)
+    for _ in range(3):
+        x, y = rng.standard_normal(h.n), rng.standard_normal(h.n)
+        Bx, By = h.vcycle(x), h.vcycle(y)
+        assert abs(Bx @ y - x @ By) <= 1e-12 * abs(Bx @ y) + 1e-14 * np.linalg.norm(Bx) * np.linalg.norm(y)
+        assert Bx @ x > 0
+
+
+def test_cg_identity_terminates_in_r_steps_on_T_m(ora):
+    # T_m has distinct eigenvalues 4 sin^2(k pi / (2(m+1))); b in the span of r
+    # eigenvectors makes CG exact after r steps.
+    m, r = 60, 5
+    rp, ci, va = P.laplace1d(m)
+    h = ora.Hierarchy(rp, ci, va, np.ones(m), max_coarse=10 ** 6)
+    j = np.arange(1, m + 1)
+    ks = [1, 7, 19, 33, 58]
+    b = sum(np.sin(k * np.pi * j / (m + 1)) * (1 + 0.1 * t) for t, k in enumerate(ks))
+    x, info = h.solve(b, tol=1e-9, precond="identity")  # step r-1 leaves ~0.5
+    assert info["status"] == 0 and info["iters"] == r
+    lam = 4 * np.sin(np.array(ks) * np.pi / (2 * (m + 1))) ** 2
+    xref = sum(np.sin(k * np.pi * j / (m + 1)) * (1 + 0.1 * t) / lam[t] for t, k in enumerate(ks))
+    assert np.allclose(x, xref, rtol=1e-9, atol=1e-9 * np.abs(xref).max())
+
+
+def test_cg_identity_respects_kappa_bound(ora):
+    m = 200
+    rp, ci, va = P.laplace1d(m)
+    h = ora.Hierarchy(rp, ci, va, np.ones(m), max_coarse=10 ** 6)
+    lmin = 4 * np.sin(np.pi / (2 * (m + 1))) ** 2
+    lmax = 4 * np.sin(m * np.pi / (2 * (m + 1))) ** 2
+    kappa = lmax / lmin
+    b = np.random.default_rng(3).standard_normal(m)
+    tol = 1e-8
+    x, info = h.solve(b, tol=tol, precond="identity", itmax=5000)
+    assert info["status"] == 0
+    # A-norm error bound 2 ((sqrt k - 1)/(sqrt k + 1))^k and ||r|| <= sqrt(kappa) ||e||_A-ish
+    rho = (np.sqrt(kappa) - 1) / (np.sqrt(kappa) + 1)
+    kmax = int(np.ceil(np.log(tol / (2 * np.sqrt(kappa))) / np.log(rho)))
+    assert info["iters"] <= kmax + 1
+
+
+@pytest.mark.parametrize("precond", ["jacobi", "identity"])
+def test_fcg_equals_textbook_pcg(ora, precond):
+    # With a fixed s.p.d. preconditioner flexible CG reduces to standard PCG.
+    rp, ci, va = P.diffusion3d(10, sigma=1.0, seed=9)
+    n = 1000
+    A = _sp(rp, ci, va)
+    h = ora.Hierarchy(rp, ci, va, np.ones(n), max_coarse=10 ** 6)
+    b = P.uniform_rhs(n, 4)
+    dinv = 1.0 / np.asarray(abs(A).sum(axis=1)).ravel()
+    M = sp.diags(dinv) if precond == "jacobi" else None
+    its = []
+    xs, _ = spla.cg(A, b, rtol=1e-10, atol=0.0, M=M, maxiter=5000, callback=lambda xk: its.append(1))
+    x, info = h.solve(b, tol=1e-10, precond=precond)
+    assert info["status"] == 0
+    assert abs(info["iters"] - len(its)) <= 1
+    assert np.linalg.norm(x - xs) <= 1e-8 * np.linalg.norm(xs)
+    # the typo-as-printed variant (r <- r + ...) would diverge: residual is small
+    assert np.linalg.norm(b - A @ x) <= 1e-10 * np.linalg.norm(b) * 1.01
+
+
+@pytest.mark.parametrize("name,scale", [("G1", 1.0), ("G2", 0.2), ("G3", 0.12), ("G4", 0.12)])
+def test_amg_fcg_converges_to_true_residual(ora, name, scale):
+    c = P.config(name, scale)
+    h = ora.Hierarchy(c["rowptr"], c["col"], c["val"], c["w"], max_coarse=c["max_coarse"])
+    x, info = h.solve(c["b"], tol=c["tol"])
+    A = _sp(c["rowptr"], c["col"], c["val"])
+    rel = np.linalg.norm(c["b"] - A @ x) / np.linalg.norm(c["b"])
+    assert info["status"] == 0 and rel <= c["tol"] and abs(rel - info["relres"]) <= 1e-3 * rel
+    assert info["iters"] < 200
+    xref = spla.spsolve(A.tocsc(), c["b"])
+    assert np.linalg.norm(x - xref) <= 1e-4 * np.linalg.norm(xref)
+
+
+def test_fcg_edge_cases(ora):
+    rp, ci, va = P.poisson2d(8)
+    h = ora.Hierarchy(rp, ci, va, np.ones(64), max_coarse=10)
+    x, info = h.solve(np.zeros(64))
+    assert info["status"] == 0 and info["iters"] == 0 and not x.any()
+    b = P.uniform_rhs(64, 0)
+    x, info = h.solve(b, tol=1e-12, itmax=1)
+    assert info["status"] == 1 and info["iters"] == 1
+    # indefinite matrix -> breakdown
+    Ad = _sp(rp, ci, va).toarray()
+    Ad -= 3.5 * np.eye(64)
+    Ai = sp.csr_matrix(np.where(_sp(rp, ci, va).toarray() != 0, Ad, 0))
+    Ai.sort_indices()
+    hi = ora.Hierarchy(Ai.indptr, Ai.indices, Ai.data, np.ones(64), max_coarse=10 ** 6)
+    x, info = hi.solve(b, tol=1e-12, precond="identity")
+    assert info["status"] in (-2, 1)
+
+
+# ----------------------------------------------------------------------------- gradient
+def test_sampled_outer_dense_reference(ora):
+    n = 120
+    rp, ci, va = P.random_spd(n, 0.05, 11)
+    A = _sp(rp, ci, va).toarray()
+    rng = np.random.default_rng(5)
+    b, xs = rng.standard_normal(n), rng.standard_normal(n)
+    h = ora.Hierarchy(rp, ci, va, np.ones(n), max_coarse=20)
+    x, _ = h.solve(b, tol=1e-14, itmax=1000)
+    lam, _ = h.solve(x - xs, tol=1e-14, itmax=1000)
+    G = ora.sampled_outer(rp, ci, lam, x)
+    xd = np.linalg.solve(A, b)
+    ld = np.linalg.solve(A, xd - xs)
+    Gd = -np.outer(ld, xd)
+    rows = np.repeat(np.arange(n), np.diff(rp))
+    assert np.allclose(G, Gd[rows, ci], rtol=1e-9, atol=1e-10 * np.abs(Gd).max())
+
+
+def test_gradient_matches_finite_differences(ora):
+    n = 64
+    rp, ci, va = P.diffusion3d(4, sigma=1.0, seed=3)
+    rng = np.random.default_rng(6)
+    b, xs = rng.standard_normal(n), rng.standard_normal(n)
+    rows = np.repeat(np.arange(n), np.diff(rp))
+
+    def loss(vals, bb):
+        x = np.linalg.solve(_sp(rp, ci, vals).toarray(), bb)
+        return 0.5 * np.sum((x - xs) ** 2)
+
+    h = ora.Hierarchy(rp, ci, va, np.ones(n), max_coarse=10)
+    x, _ = h.solve(b, tol=1e-14, itmax=1000)
+    lam, _ = h.solve(x - xs, tol=1e-14, itmax=1000)
+    G = ora.sampled_outer(rp, ci, lam, x)
+    # symmetric direction on the pattern keeps A symmetric
+    Edir = sp.csr_matrix((rng.standard_normal(len(ci)), ci, rp), shape=(n, n))
+    Edir = ((Edir + Edir.T) * 0.5).tocsr()
+    e = np.asarray(Edir[rows, ci]).ravel()
+    eps = 1e-5 * np.abs(va).max()
+    fd = (loss(va + eps * e, b) - loss(va - eps * e, b)) / (2 * eps)
+    assert abs(fd - G @ e) <= 1e-6 * abs(fd)
+    d = rng.standard_normal(n)
+    fdb = (loss(va, b + 1e-6 * d) - loss(va, b - 1e-6 * d)) / 2e-6
+    assert abs(fdb - lam @ d) <= 1e-6 * abs(fdb)
