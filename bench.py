@@ -1,0 +1,169 @@
+#!/usr/bin/env python3
+"""Benchmark of the matching-based AMG + flexible CG path on one MI355X.
+
+One step = bcm_setup (hierarchy build) + bcm_solve from x0 = 0 to true relative
+residual 1e-8 + bcm_free, on the 3-D Poisson 7-point 100^3 workload (n = 1e6),
+inputs resident in HBM before the timed region.  The headline value is the
+FP32-cycle form (float32 hierarchy and V-cycle inside float64 flexible CG); the
+plain float64 path is timed the same way and reported beside it.
+
+value = n / (mean seconds per step) / 1e6  [Mdof/s]
+
+roofline: the kernel class with the largest share of solve time, timed with
+HIP events on the library's stream during the timed steps; achieved GB/s =
+its algorithmic bytes / its event time.
+cpu_baseline: the serial oracle (one thread) running one full setup + solve of
+the same workload.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "setup+solve s to rel-res 1e-8 (Mdof/s, HBM %), FP32-cycle vs FP64 AMG-FCG"
+HBM_PEAK_GBS = 8000.0
+CLASSES = ["down0", "up0", "spmv_dots", "update", "coarse"]
+KERNEL_OF_CLASS = {"down0": "k_down", "up0": "k_up", "spmv_dots": "k_spmv_dots", "update": "k_update",
+                   "coarse": "levels>=1 cycle kernels"}
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="G2")
+    ap.add_argument("--scale", type=float, default=1.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (see DESIGN.md, sharding)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1810_04221_amd import bcm, problems
+
+    torch.cuda.set_device(0)
+    c = problems.config(args.workload, args.scale)
+    n, tol = c["n"], c["tol"]
+    log(f"workload {c['name']} n={n} nnz={len(c['col'])}")
+    dev = torch.device("cuda", 0)
+    rp = torch.as_tensor(c["rowptr"], device=dev)
+    ci = torch.as_tensor(c["col"], device=dev)
+    va = torch.as_tensor(c["val"], device=dev)
+    w = torch.as_tensor(c["w"], device=dev)
+    b = torch.as_tensor(c["b"], device=dev)
+    torch.cuda.synchronize()
+
+    def step(precision, mask):
+        h = bcm.Hierarchy(rp, ci, va, w, max_coarse=c["max_coarse"], precision=precision, profile=mask)
+        h.solve(b, tol=tol)
+        info = h.info()
+        prof = {k: h.profile(k) for k in CLASSES if mask & bcm.PROF[k]}
+        h.close()
+        return info, prof
+
+    all_mask = sum(bcm.PROF.values())
+    # warm-up, and the class with the largest share of solve time
+    share = {k: 0.0 for k in CLASSES}
+    for it in range(max(1, args.warmup)):
+        for prec in ("fp32", "fp64"):
+            info, prof = step(prec, all_mask)
+            if prec == "fp32":
+                for k, (nl_, ms, by) in prof.items():
+                    share[k] += ms
+    dom = max(share, key=share.get)
+    log(f"event share of solve kernels (fp32 cycle, ms): {share}; dominant {dom}")
+
+    results = {}
+    for prec in ("fp32", "fp64"):
+        mask = bcm.PROF[dom] if prec == "fp32" else 0
+        tot_l, tot_ms, tot_b = 0, 0.0, 0.0
+        infos = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            info, prof = step(prec, mask)
+            infos.append(info)
+            if dom in prof:
+                l_, ms, by = prof[dom]
+                tot_l += l_; tot_ms += ms; tot_b += by
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        ms_step = (t1 - t0) * 1e3 / args.steps
+        inf = infos[-1]
+        results[prec] = dict(ms_per_step=ms_step, mdofs=n / (ms_step * 1e-3) / 1e6, iters=inf["iters"],
+                             relres=inf["relres"], t_setup_ms=float(np.mean([i["t_setup_ms"] for i in infos])),
+                             t_solve_ms=float(np.mean([i["t_solve_ms"] for i in infos])), levels=inf["n"],
+                             vcmplx=inf["vcmplx"], iter_bytes=inf["iter_bytes"],
+                             prof=(tot_l, tot_ms, tot_b))
+        r = results[prec]
+        r["solve_hbm_frac"] = r["iter_bytes"] * r["iters"] / (r["t_solve_ms"] * 1e-3) / (HBM_PEAK_GBS * 1e9)
+        log(f"{prec}: {ms_step:.2f} ms/step ({r['t_setup_ms']:.2f} setup + {r['t_solve_ms']:.2f} solve), "
+            f"{r['mdofs']:.1f} Mdof/s, iters {r['iters']}, relres {r['relres']:.2e}, levels {r['levels']}")
+
+    f32 = results["fp32"]
+    l_, ms, by = f32["prof"]
+    achieved = (by / l_) / ((ms / l_) * 1e-3) / 1e9 if l_ else None
+    traffic = None
+    tpath = os.path.join(ROOT, "profiles", "traffic.json")
+    if os.path.exists(tpath):
+        src = open(os.path.join(ROOT, "paper_1810_04221_amd", "csrc", "solve.hip"), "rb").read()
+        t = json.load(open(tpath))
+        if t.get("solve_hip_sha256") == hashlib.sha256(src).hexdigest() and dom in t.get("bytes_per_launch", {}):
+            traffic = t["bytes_per_launch"][dom]
+    roofline = {"bound": "hbm", "kernel": KERNEL_OF_CLASS[dom] + " (finest level)" if dom != "coarse" else KERNEL_OF_CLASS[dom],
+                "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": traffic,
+                "algorithmic_bytes_per_launch": (by / l_) if l_ else None,
+                "avg_launch_us": (ms / l_ * 1e3) if l_ else None, "launches": l_}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import oracle
+        log("cpu baseline: serial oracle, one setup + solve of the same workload")
+        t0 = time.perf_counter()
+        ho = oracle.Hierarchy(c["rowptr"], c["col"], c["val"], c["w"], max_coarse=c["max_coarse"])
+        xo, io = ho.solve(c["b"], tol=tol)
+        t1 = time.perf_counter()
+        cpu = {"value": n / (t1 - t0) / 1e6, "unit": "Mdof/s", "cores": 1, "kind": "oracle",
+               "sample": f"one full setup + solve of {c['name']} (n={n}), {io['iters']} iterations, "
+                         f"{t1 - t0:.2f} s on one host thread"}
+        log(f"cpu baseline {cpu['value']:.3f} Mdof/s ({t1 - t0:.2f} s)")
+
+    f64 = results["fp64"]
+    out = {
+        "metric": METRIC, "value": f32["mdofs"], "unit": "Mdof/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": f32["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32 cycle + f64 outer CG", "data": "synthetic",
+        "config": {"workload": f"3-D Poisson 7-point {c['name']}, n={n}, nnz={len(c['col'])}, b~U[-1,1) seed 1, "
+                               f"w=1, coarsest<{c['max_coarse'] + 1} rows, tol {tol:g}, FP32 V-cycle in FP64 FCG"
+                   if args.workload == "G2" else c["name"]},
+        "setup_ms": f32["t_setup_ms"], "solve_ms": f32["t_solve_ms"], "iters": f32["iters"],
+        "relres": f32["relres"], "levels": f32["levels"], "vcmplx": f32["vcmplx"],
+        "solve_hbm_frac": f32["solve_hbm_frac"],
+        "fp64": {"value": f64["mdofs"], "ms_per_step": f64["ms_per_step"], "setup_ms": f64["t_setup_ms"],
+                 "solve_ms": f64["t_solve_ms"], "iters": f64["iters"], "relres": f64["relres"],
+                 "solve_hbm_frac": f64["solve_hbm_frac"]},
+        "fp32_over_fp64": f32["mdofs"] / f64["mdofs"],
+        "fp32_over_fp64_solve": f64["t_solve_ms"] / f32["t_solve_ms"],
+        "roofline": roofline, "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

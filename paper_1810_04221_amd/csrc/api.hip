@@ -1,0 +1,761 @@
+// C ABI of the library: hierarchy setup (Sections 2.1, 2.2, 3.1 of the paper),
+// flexible-CG solve with the V-cycle preconditioner (Algorithms 1 and 3,
+// Section 3.2), adjoint solve and sampled outer product for gradients.
+// Host code here only sequences kernels, reads back sizes and convergence
+// scalars, and manages device memory; all arithmetic runs in the kernels.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <string>
+
+#include "internal.h"
+
+namespace bcm {
+
+namespace {
+thread_local std::string g_err;
+thread_local double *g_pinned = nullptr;  // 64 doubles of pinned host memory per thread
+
+double *pinned() {
+    if (!g_pinned) {
+        if (hipHostMalloc((void **)&g_pinned, 64 * sizeof(double), hipHostMallocDefault) != hipSuccess)
+            g_pinned = nullptr;
+    }
+    return g_pinned;
+}
+
+double now_ms() {
+    using namespace std::chrono;
+    return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+}  // namespace
+
+void set_error(const std::string &m) { g_err = m; }
+
+// ---------------------------------------------------------------- arena
+void *Arena::raw_alloc(size_t bytes) {
+    void *p = nullptr;
+    if (alloc) {
+        p = alloc(bytes, ctx);
+    } else if (hipMalloc(&p, bytes) != hipSuccess) {
+        p = nullptr;
+    }
+    return p;
+}
+
+void Arena::raw_free(void *p, size_t bytes) {
+    if (!p) return;
+    if (dealloc) dealloc(p, bytes, ctx);
+    else (void)hipFree(p);
+}
+
+void *Arena::get(size_t bytes) {
+    bytes = (bytes + 255) & ~size_t(255);
+    if (bytes == 0) bytes = 256;
+    if (bytes > left) {
+        const size_t sz = std::max(bytes, chunk_min);
+        void *p = raw_alloc(sz);
+        if (!p) { failed = true; return nullptr; }
+        chunks.push_back({p, sz});
+        cur = static_cast<char *>(p);
+        left = sz;
+    }
+    void *r = cur;
+    cur += bytes;
+    left -= bytes;
+    return r;
+}
+
+void Arena::reserve(size_t bytes) {
+    bytes = (bytes + 255) & ~size_t(255);
+    if (left >= bytes) return;
+    void *p = raw_alloc(bytes);
+    if (!p) { failed = true; return; }
+    chunks.push_back({p, bytes});
+    cur = static_cast<char *>(p);
+    left = bytes;
+}
+
+void Arena::rewind() {
+    if (chunks.empty()) return;
+    if (chunks.size() > 1) {
+        size_t tot = 0;
+        for (auto &c : chunks) tot += c.second;
+        release();
+        reserve(tot);
+        return;
+    }
+    cur = static_cast<char *>(chunks[0].first);
+    left = chunks[0].second;
+}
+
+void Arena::release() {
+    for (auto &c : chunks) raw_free(c.first, c.second);
+    chunks.clear();
+    cur = nullptr;
+    left = 0;
+}
+
+}  // namespace bcm
+
+using namespace bcm;
+
+#define HIPCHK(expr)                                                                        \
+    do {                                                                                    \
+        hipError_t e_ = (expr);                                                             \
+        if (e_ != hipSuccess) {                                                             \
+            set_error(std::string("HIP error ") + hipGetErrorString(e_) + " in " #expr);   \
+            return BCM_EHIP;                                                                \
+        }                                                                                   \
+    } while (0)
+
+#define NOMEM(ptr)                                                    \
+    do {                                                              \
+        if (!(ptr)) {                                                 \
+            set_error("device allocation failed (" #ptr ")");         \
+            return BCM_ENOMEM;                                        \
+        }                                                             \
+    } while (0)
+
+namespace {
+
+std::string flag_text(int f) {
+    std::string s;
+    if (f & kErrRowPtr) s += " row_ptr not monotone / not 0..nnz;";
+    if (f & kErrCol) s += " column index out of [0, n);";
+    if (f & kErrUnsorted) s += " columns not strictly ascending in a row;";
+    if (f & kErrNonFinite) s += " non-finite value;";
+    if (f & kErrNoDiag) s += " missing diagonal entry;";
+    if (f & kErrDiagNonPos) s += " non-positive diagonal entry;";
+    if (f & kErrW) s += " smooth vector entry zero or not finite;";
+    if (f & kErrAsym) s += " matrix not bitwise symmetric;";
+    return s;
+}
+
+int read_back(hipStream_t s, const void *dev, size_t bytes, void *host) {
+    double *pin = pinned();
+    if (!pin || bytes > 64 * sizeof(double)) {
+        HIPCHK(hipMemcpyAsync(host, dev, bytes, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        return BCM_OK;
+    }
+    HIPCHK(hipMemcpyAsync(pin, dev, bytes, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    std::memcpy(host, pin, bytes);
+    return BCM_OK;
+}
+
+struct SweepOut {
+    int nc = 0;
+    int *agg = nullptr;
+    double *p = nullptr;
+    double *wc = nullptr;
+    int *mem2 = nullptr;
+    Csr Ac;
+};
+
+// Weights, ranks, Suitor matching and mate/leader flags on (A, w): Section 2.2
+// and 3.1.  tmp-lifetime buffers come from `tmp`.
+int match_sweep(hipStream_t s, Arena &tmp, const Csr &A, const double *w, int check_sym, int **mate_out,
+                int **leader_out, double **c_out) {
+    const int m = A.n, G = pick_G((double)A.nnz / std::max(1, m));
+    double *diag = tmp.get_n<double>(m);
+    int *flags = tmp.get_n<int>(16);
+    double *c = tmp.get_n<double>(A.nnz);
+    uint32_t *rk = tmp.get_n<uint32_t>(A.nnz);
+    unsigned long long *ws = tmp.get_n<unsigned long long>(m);
+    int *mate = tmp.get_n<int>(m);
+    int *leader = tmp.get_n<int>(m);
+    NOMEM(diag && flags && c && rk && ws && mate && leader);
+    launch_fill_i32(s, 1, flags, 0);
+    launch_validate(s, G, m, A.nnz, A.rp, A.ci, A.v, w, check_sym, diag, flags);
+    int f = 0;
+    int rc = read_back(s, flags, sizeof(int), &f);
+    if (rc) return rc;
+    if (f) {
+        set_error("invalid input:" + flag_text(f));
+        return BCM_EINVAL;
+    }
+    launch_weights(s, G, m, A.rp, A.ci, A.v, diag, w, c);
+    launch_rank(s, G, m, A.rp, A.ci, c, rk);
+    launch_fill_u64(s, m, ws, 0ull);
+    launch_suitor(s, m, A.rp, A.ci, c, rk, ws);
+    launch_mate(s, m, ws, mate, leader);
+    HIPCHK(hipGetLastError());
+    *mate_out = mate;
+    *leader_out = leader;
+    if (c_out) *c_out = c;
+    return BCM_OK;
+}
+
+// One pairwise sweep on (A, w): matching, Algorithm 2, prolongator, Galerkin.
+// Outputs that outlive the sweep come from `keep`.  out.nc == A.n means that
+// no pair was formed (nothing else is produced then).
+int pairwise_sweep(hipStream_t s, Arena &tmp, Arena &keep, const Csr &A, const double *w, SweepOut &out) {
+    const int m = A.n, G = pick_G((double)A.nnz / std::max(1, m));
+    int *mate = nullptr, *leader = nullptr;
+    int rc = match_sweep(s, tmp, A, w, 0, &mate, &leader, nullptr);
+    if (rc) return rc;
+    int *ofs = leader;  // scanned in place
+    int *dtot = tmp.get_n<int>(16);
+    void *stmp = tmp.get(scan_tmp_bytes(m));
+    NOMEM(dtot && stmp);
+    scan_exclusive(s, leader, ofs, m, dtot, stmp);
+    int nc = 0;
+    rc = read_back(s, dtot, sizeof(int), &nc);
+    if (rc) return rc;
+    out.nc = nc;
+    if (nc == m) return BCM_OK;
+    out.agg = keep.get_n<int>(m);
+    out.p = keep.get_n<double>(m);
+    out.wc = keep.get_n<double>(nc);
+    out.mem2 = keep.get_n<int>(2 * (size_t)nc);
+    NOMEM(out.agg && out.p && out.wc && out.mem2);
+    launch_aggfill(s, m, mate, ofs, w, out.agg, out.p, out.wc, out.mem2);
+    // Galerkin product: count, scan to row pointers, fill
+    int *crp = keep.get_n<int>((size_t)nc + 1);
+    int *gF = tmp.get_n<int>(A.nnz);
+    int *gU = tmp.get_n<int>(A.nnz);
+    void *stmp2 = tmp.get(scan_tmp_bytes(nc));
+    NOMEM(crp && gF && gU && stmp2);
+    launch_gal_count(s, G, nc, A.rp, A.ci, out.agg, out.mem2, crp, gF, gU);
+    scan_exclusive(s, crp, crp, nc, crp + nc, stmp2);
+    int cnnz = 0;
+    rc = read_back(s, crp + nc, sizeof(int), &cnnz);
+    if (rc) return rc;
+    out.Ac.n = nc;
+    out.Ac.nnz = cnnz;
+    out.Ac.rp = crp;
+    out.Ac.ci = keep.get_n<int>(cnnz);
+    out.Ac.v = keep.get_n<double>(cnnz);
+    NOMEM(out.Ac.ci && out.Ac.v);
+    launch_gal_fill(s, G, nc, A.rp, A.ci, A.v, out.agg, out.p, out.mem2, crp, out.Ac.ci, out.Ac.v, gF, gU);
+    HIPCHK(hipGetLastError());
+    return BCM_OK;
+}
+
+template <typename T>
+T *persist_copy(bcm_handle *h, const T *src, size_t n) {
+    T *d = h->persist.get_n<T>(n);
+    if (d && n && hipMemcpyAsync(d, src, n * sizeof(T), hipMemcpyDeviceToDevice, h->s) != hipSuccess) d = nullptr;
+    return d;
+}
+
+int build_hierarchy(bcm_handle *h, const bcm_csr *Ain, const double *win) {
+    hipStream_t s = h->s;
+    const bcm_params &P = h->prm;
+    const int n = Ain->n, nnz = Ain->nnz;
+    const bool fp32 = P.precision == BCM_FP32_CYCLE;
+    // device memory: persistent hierarchy, level-lifetime and sweep-lifetime scratch
+    const double z = nnz, nn = n;
+    h->persist.reserve((size_t)(1.5 * (16.0 * z + 48.0 * nn) + 64.0 * nn) + (size_t(4) << 20));
+    Arena keep, tmp;
+    keep.alloc = tmp.alloc = P.alloc;
+    keep.dealloc = tmp.dealloc = P.dealloc;
+    keep.ctx = tmp.ctx = P.alloc_ctx;
+    keep.reserve((size_t)(16.0 * z + 96.0 * nn) + (size_t(1) << 20));
+    tmp.reserve((size_t)(24.0 * z + 48.0 * nn) + (size_t(1) << 20));
+    struct Guard {
+        Arena &a, &b;
+        hipStream_t s;
+        ~Guard() { (void)hipStreamSynchronize(s); a.release(); b.release(); }
+    } guard{keep, tmp, s};
+    if (h->persist.failed || keep.failed || tmp.failed) { set_error("device allocation failed"); return BCM_ENOMEM; }
+
+    Level &L0 = h->lv[0];
+    L0.A.n = n;
+    L0.A.nnz = nnz;
+    L0.A.rp = persist_copy(h, Ain->row_ptr, (size_t)n + 1);
+    L0.A.ci = persist_copy(h, Ain->col, (size_t)nnz);
+    L0.A.v = persist_copy(h, Ain->val, (size_t)nnz);
+    L0.w = persist_copy(h, win, (size_t)n);
+    NOMEM(L0.A.rp && L0.A.ci && L0.A.v && L0.w);
+    {
+        // full validation of the input, symmetry included when asked
+        double *diag = tmp.get_n<double>(n);
+        int *flags = tmp.get_n<int>(16);
+        NOMEM(diag && flags);
+        launch_fill_i32(s, 1, flags, 0);
+        launch_validate(s, pick_G((double)nnz / std::max(1, n)), n, nnz, L0.A.rp, L0.A.ci, L0.A.v, L0.w,
+                        P.check ? 1 : 0, diag, flags);
+        int f = 0;
+        int rc = read_back(s, flags, sizeof(int), &f);
+        if (rc) return rc;
+        if (f) { set_error("invalid input:" + flag_text(f)); return BCM_EINVAL; }
+    }
+    const int max_coarse = P.max_coarse > 0 ? P.max_coarse : (int)std::lround(40.0 * std::cbrt((double)n));
+    int k = 0;
+    for (;;) {
+        Level &L = h->lv[k];
+        const int nk = L.A.n;
+        if (nk <= max_coarse || k + 1 >= P.max_levels || k + 1 >= kMaxLevels) break;
+        keep.rewind();
+        Csr Acur = L.A;
+        const double *wcur = L.w;
+        bool have = false;
+        int *cagg = nullptr, *cmem = nullptr;
+        double *cp = nullptr;
+        int cstride = 1;
+        for (int sw = 0; sw < P.sweeps; ++sw) {
+            tmp.rewind();
+            SweepOut so;
+            int rc = pairwise_sweep(s, tmp, keep, Acur, wcur, so);
+            if (rc) return rc;
+            if (so.nc == Acur.n) break;  // no pair formed: further sweeps would not either
+            if (!have) {
+                cagg = so.agg; cp = so.p; cmem = so.mem2; cstride = 2;
+            } else {
+                int *nagg = keep.get_n<int>(nk);
+                double *np_ = keep.get_n<double>(nk);
+                int *nmem = keep.get_n<int>((size_t)so.nc * 2 * cstride);
+                NOMEM(nagg && np_ && nmem);
+                launch_compose(s, nk, so.nc, cagg, cp, cmem, cstride, so.agg, so.p, so.mem2, nagg, np_, nmem);
+                cagg = nagg; cp = np_; cmem = nmem; cstride *= 2;
+            }
+            Acur = so.Ac;
+            wcur = so.wc;
+            have = true;
+        }
+        if (!have) break;  // stagnation: level k is the coarsest
+        Level &C = h->lv[k + 1];
+        C.A.n = Acur.n;
+        C.A.nnz = Acur.nnz;
+        C.A.rp = persist_copy(h, Acur.rp, (size_t)Acur.n + 1);
+        C.A.ci = persist_copy(h, Acur.ci, (size_t)Acur.nnz);
+        C.A.v = persist_copy(h, Acur.v, (size_t)Acur.nnz);
+        C.w = persist_copy(h, wcur, (size_t)Acur.n);
+        L.nc = Acur.n;
+        L.agg = persist_copy(h, cagg, (size_t)nk);
+        L.p = persist_copy(h, cp, (size_t)nk);
+        L.mstride = cstride;
+        L.mem = persist_copy(h, cmem, (size_t)Acur.n * cstride);
+        NOMEM(C.A.rp && C.A.ci && C.A.v && C.w && L.agg && L.p && L.mem);
+        HIPCHK(hipStreamSynchronize(s));  // keep/tmp are rewound next
+        ++k;
+    }
+    h->nl = k + 1;
+    // smoother, FP32 copies, cycle vectors
+    for (int l = 0; l < h->nl; ++l) {
+        Level &L = h->lv[l];
+        const int nl_ = L.A.n;
+        L.G = pick_G((double)L.A.nnz / std::max(1, nl_));
+        L.dinv = h->persist.get_n<double>(nl_);
+        NOMEM(L.dinv);
+        if (fp32) {
+            L.dinv32 = h->persist.get_n<float>(nl_);
+            L.A.v32 = h->persist.get_n<float>(L.A.nnz);
+            NOMEM(L.dinv32 && L.A.v32);
+            launch_cast(s, L.A.nnz, L.A.v, L.A.v32);
+            if (l < h->nl - 1) {
+                L.p32 = h->persist.get_n<float>(nl_);
+                NOMEM(L.p32);
+                launch_cast(s, nl_, L.p, L.p32);
+            }
+        }
+        launch_diag_l1(s, L.G, nl_, L.A.rp, L.A.v, L.dinv, L.dinv32);
+        if (l > 0) {
+            const size_t es = fp32 ? sizeof(float) : sizeof(double);
+            L.b = h->persist.get(es * nl_);
+            L.x = h->persist.get(es * nl_);
+            NOMEM(L.b && L.x);
+        }
+    }
+    if (h->lv[h->nl - 1].A.n > kCoarseLds) {
+        h->ctmp[0] = h->persist.get_n<double>(h->lv[h->nl - 1].A.n);
+        h->ctmp[1] = h->persist.get_n<double>(h->lv[h->nl - 1].A.n);
+        NOMEM(h->ctmp[0] && h->ctmp[1]);
+    }
+    // flexible CG state
+    h->r = h->persist.get_n<double>(n);
+    h->w = h->persist.get_n<double>(n);
+    h->d = h->persist.get_n<double>(n);
+    h->v = h->persist.get_n<double>(n);
+    h->q = h->persist.get_n<double>(n);
+    h->scal = h->persist.get_n<double>(16);
+    h->red_blocks = reduce_blocks(n);
+    h->partials = h->persist.get_n<double>(4 * (size_t)h->red_blocks);
+    h->counter = h->persist.get_n<unsigned>(16);
+    NOMEM(h->r && h->w && h->d && h->v && h->q && h->scal && h->partials && h->counter);
+    launch_fill_i32(s, 16, (int *)h->counter, 0);
+    launch_fill_i32(s, 32, (int *)h->scal, 0);
+    launch_fill_i32(s, 2 * (size_t)n, (int *)h->q, 0);
+    launch_fill_i32(s, 2 * (size_t)n, (int *)h->d, 0);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(s));
+    return BCM_OK;
+}
+
+// --------------------------------------------------------------- byte model
+// Algorithmic bytes (every array touched once; gathers assumed cached).
+double bytes_down(const bcm_handle *h, int k) {
+    const Level &L = h->lv[k];
+    const bool f32 = h->prm.precision == BCM_FP32_CYCLE;
+    const double sv = f32 ? 4 : 8, sb = (k == 0 || !f32) ? 8 : 4;
+    const double n = L.A.n, z = L.A.nnz, nc = L.nc;
+    return 4 * (n + 1) + (4 + sv) * z + sb * n + 2 * sv * n + 4.0 * nc * L.mstride + sv * nc;
+}
+double bytes_up(const bcm_handle *h, int k) {
+    const Level &L = h->lv[k];
+    const bool f32 = h->prm.precision == BCM_FP32_CYCLE;
+    const double sv = f32 ? 4 : 8, sb = (k == 0 || !f32) ? 8 : 4;
+    const double n = L.A.n, z = L.A.nnz, nc = L.nc;
+    return 4 * (n + 1) + (4 + sv) * z + 2 * sb * n + 2 * sv * n + 4 * n + sv * nc;
+}
+double bytes_coarse(const bcm_handle *h) {
+    const Level &L = h->lv[h->nl - 1];
+    const double n = L.A.n, z = L.A.nnz;
+    const double sb = (h->nl == 1 || h->prm.precision != BCM_FP32_CYCLE) ? 8 : 4;
+    return 4 * (n + 1) + 12 * z + 8 * n + 2 * sb * n;
+}
+double bytes_spmv_dots(const bcm_handle *h) {
+    const double n = h->lv[0].A.n, z = h->lv[0].A.nnz;
+    return 4 * (n + 1) + 12 * z + 32 * n;
+}
+double bytes_update(const bcm_handle *h) { return 80.0 * h->lv[0].A.n; }
+
+// --------------------------------------------------------------- profiling
+struct Prof {
+    bcm_handle *h;
+    int mask;
+    int begin(int cls) {
+        if (!(mask & (1 << cls))) return -1;
+        const int idx = (int)(h->ev_pairs.size() * 2);
+        while ((int)h->ev_pool.size() < idx + 2) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) return -1;
+            h->ev_pool.push_back(e);
+        }
+        (void)hipEventRecord(h->ev_pool[idx], h->s);
+        return idx;
+    }
+    void end(int cls, int idx, double bytes) {
+        if (idx < 0) return;
+        (void)hipEventRecord(h->ev_pool[idx + 1], h->s);
+        h->ev_pairs.push_back({cls, idx});
+        h->ev_bytes.push_back(bytes);
+    }
+};
+
+int prof_class_index(int bit) {
+    int i = 0;
+    while (bit > 1) { bit >>= 1; ++i; }
+    return i;
+}
+
+void prof_collect(bcm_handle *h) {
+    for (auto &c : h->prof) c = ProfClass{};
+    for (size_t t = 0; t < h->ev_pairs.size(); ++t) {
+        const int cls = h->ev_pairs[t].first, idx = h->ev_pairs[t].second;
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, h->ev_pool[idx], h->ev_pool[idx + 1]) == hipSuccess) {
+            h->prof[cls].launches += 1;
+            h->prof[cls].ms += ms;
+            h->prof[cls].bytes += h->ev_bytes[t];
+        }
+    }
+    h->ev_pairs.clear();
+    h->ev_bytes.clear();
+}
+
+// --------------------------------------------------------------- V-cycle
+void vcycle(bcm_handle *h, Prof &pf, const double *rin, double *wout) {
+    hipStream_t s = h->s;
+    const int fp32 = h->prm.precision == BCM_FP32_CYCLE;
+    const int nl = h->nl;
+    const int cs = h->prm.coarse_sweeps;
+    Level &C = h->lv[nl - 1];
+    if (nl == 1) {
+        int e = pf.begin(4);
+        launch_coarse(s, C, cs, rin, wout, 1, 1, h->ctmp[0], h->ctmp[1]);
+        pf.end(4, e, bytes_coarse(h));
+        return;
+    }
+    for (int k = 0; k < nl - 1; ++k) {
+        Level &L = h->lv[k];
+        const int cls = k == 0 ? 0 : 4;
+        int e = pf.begin(cls);
+        launch_down(s, L, fp32, k == 0 ? (const void *)rin : L.b, h->lv[k + 1].b, (k == 0 || !fp32) ? 1 : 0);
+        pf.end(cls, e, bytes_down(h, k));
+    }
+    {
+        int e = pf.begin(4);
+        launch_coarse(s, C, cs, C.b, C.x, !fp32, !fp32, h->ctmp[0], h->ctmp[1]);
+        pf.end(4, e, bytes_coarse(h));
+    }
+    for (int k = nl - 2; k >= 0; --k) {
+        Level &L = h->lv[k];
+        const int cls = k == 0 ? 1 : 4;
+        const int f64io = (k == 0 || !fp32) ? 1 : 0;
+        int e = pf.begin(cls);
+        launch_up(s, L, fp32, k == 0 ? (const void *)rin : L.b, h->lv[k + 1].x, k == 0 ? (void *)wout : L.x, f64io,
+                  f64io);
+        pf.end(cls, e, bytes_up(h, k));
+    }
+}
+
+int fcg(bcm_handle *h, const double *b, double *x, double tol) {
+    hipStream_t s = h->s;
+    const Level &L0 = h->lv[0];
+    const int n = L0.A.n, nb = h->red_blocks;
+    Prof pf{h, h->prm.profile};
+    h->ev_pairs.clear();
+    h->ev_bytes.clear();
+    double hs[8];
+    launch_resid(s, L0, nb, b, x, h->r, h->partials, h->counter, h->scal);
+    int rc = read_back(s, h->scal, 8 * sizeof(double), hs);
+    if (rc) return rc;
+    const double bb = hs[5];
+    int it = 0, status = BCM_OK;
+    double relres = 0.0;
+    if (!(bb > 0.0) || !std::isfinite(bb)) {
+        if (bb == 0.0) {
+            launch_fill_i32(s, 2 * (size_t)n, (int *)x, 0);
+            h->iters = 0; h->relres = 0.0; h->status = BCM_OK;
+            HIPCHK(hipStreamSynchronize(s));
+            return BCM_OK;
+        }
+        set_error("right-hand side or initial guess not finite");
+        return BCM_EINVAL;
+    }
+    const double bn = std::sqrt(bb);
+    relres = std::sqrt(hs[4]) / bn;
+    const int itmax = h->prm.itmax;
+    for (int restart = 0; restart < 4; ++restart) {
+        if (relres <= tol) { status = BCM_OK; break; }
+        if (it >= itmax) { status = BCM_MAXIT; break; }
+        int first = 1;
+        for (;;) {
+            vcycle(h, pf, h->r, h->w);
+            int e = pf.begin(2);
+            launch_spmv_dots(s, L0, nb, h->w, h->r, h->q, h->v, h->partials, h->counter, h->scal);
+            pf.end(2, e, bytes_spmv_dots(h));
+            e = pf.begin(3);
+            launch_update(s, n, nb, first, h->w, h->v, h->d, x, h->q, h->r, h->partials, h->counter, h->scal);
+            pf.end(3, e, bytes_update(h));
+            first = 0;
+            ++it;
+            rc = read_back(s, h->scal, 8 * sizeof(double), hs);
+            if (rc) return rc;
+            if (hs[6] != 0.0) {
+                h->iters = it; h->status = BCM_EBREAKDOWN;
+                set_error("flexible CG breakdown: rho <= 0 or not finite (matrix or preconditioner not s.p.d.)");
+                return BCM_EBREAKDOWN;
+            }
+            relres = std::sqrt(hs[4]) / bn;
+            if (!(relres > tol) || it >= itmax) break;
+        }
+        // true residual b - A x
+        launch_resid(s, L0, nb, b, x, h->r, h->partials, h->counter, h->scal);
+        rc = read_back(s, h->scal, 8 * sizeof(double), hs);
+        if (rc) return rc;
+        relres = std::sqrt(hs[4]) / bn;
+        if (relres <= tol) { status = BCM_OK; break; }
+        if (it >= itmax) { status = BCM_MAXIT; break; }
+        status = BCM_MAXIT;
+    }
+    HIPCHK(hipGetLastError());
+    prof_collect(h);
+    h->iters = it;
+    h->relres = relres;
+    h->status = status;
+    return status;
+}
+
+}  // namespace
+
+extern "C" {
+
+void bcm_default_params(bcm_params *p) {
+    std::memset(p, 0, sizeof(*p));
+    p->max_levels = 40;
+    p->max_coarse = 0;
+    p->sweeps = 2;
+    p->coarse_sweeps = 20;
+    p->pre = 1;
+    p->post = 1;
+    p->cycle = BCM_VCYCLE;
+    p->precision = BCM_FP64;
+    p->itmax = 5000;
+    p->check = 1;
+    p->profile = 0;
+    p->adjoint_tol = 0.0;
+}
+
+const char *bcm_last_error(void) { return g_err.c_str(); }
+
+int bcm_setup(const bcm_csr *A, const double *w, const bcm_params *p, bcm_handle **out) {
+    g_err.clear();
+    if (!out) { set_error("out is NULL"); return BCM_EINVAL; }
+    *out = nullptr;
+    if (!A || !w || !A->row_ptr || !A->col || !A->val) { set_error("NULL matrix or smooth vector"); return BCM_EINVAL; }
+    if (A->n <= 0 || A->nnz < A->n) { set_error("need n > 0 and nnz >= n (diagonal stored)"); return BCM_EINVAL; }
+    bcm_params prm;
+    if (p) prm = *p; else bcm_default_params(&prm);
+    if (prm.max_levels < 1 || prm.sweeps < 1 || prm.sweeps > 4 || prm.coarse_sweeps < 1 || prm.itmax < 1 ||
+        prm.pre != 1 || prm.post != 1 || prm.cycle != BCM_VCYCLE ||
+        (prm.precision != BCM_FP64 && prm.precision != BCM_FP32_CYCLE) || (prm.alloc == nullptr) != (prm.dealloc == nullptr)) {
+        set_error("unsupported parameters (sweeps 1..4, pre = post = 1, V-cycle, FP64 or FP32 cycle)");
+        return BCM_EINVAL;
+    }
+    const double t0 = now_ms();
+    bcm_handle *h = new bcm_handle();
+    h->prm = prm;
+    h->s = (hipStream_t)prm.stream;
+    h->persist.alloc = prm.alloc;
+    h->persist.dealloc = prm.dealloc;
+    h->persist.ctx = prm.alloc_ctx;
+    int rc = build_hierarchy(h, A, w);
+    if (rc) {
+        bcm_free(h);
+        return rc;
+    }
+    h->t_setup_ms = now_ms() - t0;
+    *out = h;
+    return BCM_OK;
+}
+
+int bcm_solve(bcm_handle *h, const double *b, double *x, double tol) {
+    g_err.clear();
+    if (!h || !b || !x) { set_error("NULL handle or vector"); return BCM_EINVAL; }
+    if (!(tol > 0.0)) { set_error("tol must be positive"); return BCM_EINVAL; }
+    const double t0 = now_ms();
+    h->last_tol = tol;
+    const int rc = fcg(h, b, x, tol);
+    h->t_solve_ms = now_ms() - t0;
+    return rc;
+}
+
+int bcm_precond(bcm_handle *h, const double *r, double *z) {
+    g_err.clear();
+    if (!h || !r || !z) { set_error("NULL handle or vector"); return BCM_EINVAL; }
+    Prof pf{h, 0};
+    vcycle(h, pf, r, z);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(h->s));
+    return BCM_OK;
+}
+
+int bcm_solve_adjoint(bcm_handle *h, const double *g, double *lambda) {
+    g_err.clear();
+    if (!h || !g || !lambda) { set_error("NULL handle or vector"); return BCM_EINVAL; }
+    const double tol = h->prm.adjoint_tol > 0.0 ? h->prm.adjoint_tol : h->last_tol;
+    if (!(tol > 0.0)) { set_error("no adjoint tolerance: set adjoint_tol or call bcm_solve first"); return BCM_EINVAL; }
+    launch_fill_i32(h->s, 2 * (size_t)h->lv[0].A.n, (int *)lambda, 0);
+    const double t0 = now_ms();
+    const int rc = fcg(h, g, lambda, tol);
+    h->t_solve_ms = now_ms() - t0;
+    return rc;
+}
+
+int bcm_sampled_outer(bcm_handle *h, const double *lambda, const double *x, double *grad_val) {
+    g_err.clear();
+    if (!h || !lambda || !x || !grad_val) { set_error("NULL handle or vector"); return BCM_EINVAL; }
+    launch_sampled_outer(h->s, h->lv[0], lambda, x, grad_val);
+    HIPCHK(hipGetLastError());
+    return BCM_OK;
+}
+
+int bcm_info(const bcm_handle *h, bcm_info_t *o) {
+    if (!h || !o) { set_error("NULL handle or output"); return BCM_EINVAL; }
+    std::memset(o, 0, sizeof(*o));
+    o->nl = h->nl;
+    o->precision = h->prm.precision;
+    o->iters = h->iters;
+    o->status = h->status;
+    double sz = 0, sr = 0;
+    for (int k = 0; k < h->nl; ++k) {
+        o->n[k] = h->lv[k].A.n;
+        o->nnz[k] = h->lv[k].A.nnz;
+        sz += h->lv[k].A.nnz;
+        if (k > 0) sr += (double)h->lv[k - 1].A.n / h->lv[k].A.n;
+    }
+    o->vcmplx = sz / h->lv[0].A.nnz;
+    o->cratio = h->nl > 1 ? sr / (h->nl - 1) : 1.0;
+    o->cratio_nl = sr / h->nl;
+    o->relres = h->relres;
+    o->t_setup_ms = h->t_setup_ms;
+    o->t_solve_ms = h->t_solve_ms;
+    double cyc = bytes_coarse(h);
+    for (int k = 0; k + 1 < h->nl; ++k) cyc += bytes_down(h, k) + bytes_up(h, k);
+    o->cycle_bytes = cyc;
+    o->iter_bytes = cyc + bytes_spmv_dots(h) + bytes_update(h);
+    return BCM_OK;
+}
+
+int bcm_level_copy(const bcm_handle *h, int32_t k, int32_t *row_ptr, int32_t *col, double *val, double *w,
+                   double *dinv, int32_t *agg, double *p) {
+    if (!h || k < 0 || k >= h->nl) { set_error("bad handle or level"); return BCM_EINVAL; }
+    const Level &L = h->lv[k];
+    hipStream_t s = h->s;
+    const size_t n = L.A.n, z = L.A.nnz;
+    if (row_ptr) HIPCHK(hipMemcpyAsync(row_ptr, L.A.rp, (n + 1) * 4, hipMemcpyDefault, s));
+    if (col) HIPCHK(hipMemcpyAsync(col, L.A.ci, z * 4, hipMemcpyDefault, s));
+    if (val) HIPCHK(hipMemcpyAsync(val, L.A.v, z * 8, hipMemcpyDefault, s));
+    if (w) HIPCHK(hipMemcpyAsync(w, L.w, n * 8, hipMemcpyDefault, s));
+    if (dinv) HIPCHK(hipMemcpyAsync(dinv, L.dinv, n * 8, hipMemcpyDefault, s));
+    if (k < h->nl - 1) {
+        if (agg) HIPCHK(hipMemcpyAsync(agg, L.agg, n * 4, hipMemcpyDefault, s));
+        if (p) HIPCHK(hipMemcpyAsync(p, L.p, n * 8, hipMemcpyDefault, s));
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    return BCM_OK;
+}
+
+int bcm_match(const bcm_csr *A, const double *w, const bcm_params *p, int32_t *mate, double *c) {
+    g_err.clear();
+    if (!A || !w || !mate || !A->row_ptr || !A->col || !A->val || A->n <= 0) {
+        set_error("NULL or empty argument");
+        return BCM_EINVAL;
+    }
+    bcm_params prm;
+    if (p) prm = *p; else bcm_default_params(&prm);
+    hipStream_t s = (hipStream_t)prm.stream;
+    Arena tmp;
+    tmp.alloc = prm.alloc;
+    tmp.dealloc = prm.dealloc;
+    tmp.ctx = prm.alloc_ctx;
+    tmp.reserve((size_t)A->nnz * 24 + (size_t)A->n * 40 + (size_t(1) << 20));
+    Csr M;
+    M.n = A->n;
+    M.nnz = A->nnz;
+    M.rp = const_cast<int *>(A->row_ptr);
+    M.ci = const_cast<int *>(A->col);
+    M.v = const_cast<double *>(A->val);
+    int *dm = nullptr, *leader = nullptr;
+    double *dc = nullptr;
+    int rc = tmp.failed ? BCM_ENOMEM : match_sweep(s, tmp, M, w, prm.check ? 1 : 0, &dm, &leader, &dc);
+    if (rc == BCM_ENOMEM) set_error("device allocation failed");
+    if (rc == BCM_OK) {
+        if (hipMemcpyAsync(mate, dm, (size_t)A->n * 4, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+            (c && hipMemcpyAsync(c, dc, (size_t)A->nnz * 8, hipMemcpyDeviceToDevice, s) != hipSuccess)) {
+            set_error("HIP copy failed");
+            rc = BCM_EHIP;
+        }
+    }
+    (void)hipStreamSynchronize(s);
+    tmp.release();
+    return rc;
+}
+
+int bcm_profile(const bcm_handle *h, int32_t kclass, int64_t *launches, double *ms, double *bytes) {
+    if (!h || kclass <= 0 || (kclass & (kclass - 1)) || kclass > BCM_PROF_CYCLE_COARSE) {
+        set_error("bad handle or kernel class");
+        return BCM_EINVAL;
+    }
+    const ProfClass &c = h->prof[prof_class_index(kclass)];
+    if (launches) *launches = c.launches;
+    if (ms) *ms = c.ms;
+    if (bytes) *bytes = c.bytes;
+    return BCM_OK;
+}
+
+void bcm_free(bcm_handle *h) {
+    if (!h) return;
+    (void)hipStreamSynchronize(h->s);
+    for (auto e : h->ev_pool) (void)hipEventDestroy(e);
+    h->persist.release();
+    delete h;
+}
+
+}  // extern "C"

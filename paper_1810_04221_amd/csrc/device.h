@@ -1,0 +1,99 @@
+// Device-side helpers shared by the gfx950 kernels of the library.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace bcm {
+
+constexpr int kBlock = 256;  // threads per workgroup of the streaming kernels
+
+// Workgroups are handed to the eight XCDs of the chip in turn (workgroup b runs on
+// XCD b % 8).  This remaps the hardware index so that every XCD gets one
+// contiguous range of logical blocks: neighbouring rows, whose gathered vector
+// entries overlap, then share the same L2.  A bijection on [0, nb).
+__device__ __forceinline__ int xcd_block(int b, int nb) {
+    constexpr int X = 8;
+    const int q = nb / X, r = nb % X;
+    const int x = b % X, i = b / X;
+    return (x < r) ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
+}
+
+// Sum over an aligned group of G lanes (G a power of two <= 64) of one wave.
+template <int G, typename T>
+__device__ __forceinline__ T group_sum(T v) {
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, G);
+    return v;
+}
+
+// Orders LDS accesses of the lanes of one wave: everything written before is
+// visible to every lane of the wave after.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <typename T>
+__device__ __forceinline__ T load_agent(const T *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Block-wide sums of K doubles; the result is valid in thread 0.  The order of
+// additions depends only on the block size.
+template <int K>
+__device__ __forceinline__ void block_sum(double (&v)[K], double *lds) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] = group_sum<64>(v[k]);
+    if (lane == 0)
+#pragma unroll
+        for (int k = 0; k < K; ++k) lds[k * 16 + wid] = v[k];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            double s = lds[k * 16];
+            for (int w = 1; w < nw; ++w) s += lds[k * 16 + w];
+            v[k] = s;
+        }
+    }
+    __syncthreads();
+}
+
+// Grid-wide deterministic sums: every block stores its K partial sums; the last
+// block to arrive adds all partials in block order, writes out[0..K) and
+// resets the arrival counter.  Returns true in the last block (all threads).
+// The result depends only on the grid and block sizes, never on timing.
+template <int K>
+__device__ __forceinline__ bool grid_sum(double (&v)[K], double *partials, unsigned *counter,
+                                         double *out) {
+    __shared__ double lds[K * 16];
+    __shared__ int last;
+    block_sum<K>(v, lds);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) partials[(size_t)k * gridDim.x + blockIdx.x] = v[k];
+        __threadfence();
+        const unsigned t = atomicAdd(counter, 1u);
+        last = (t == gridDim.x - 1);
+    }
+    __syncthreads();
+    if (!last) return false;
+    __threadfence();
+    double s[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) s[k] = 0.0;
+    for (int b = threadIdx.x; b < (int)gridDim.x; b += blockDim.x)
+#pragma unroll
+        for (int k = 0; k < K; ++k) s[k] += load_agent(&partials[(size_t)k * gridDim.x + b]);
+    block_sum<K>(s, lds);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) out[k] = s[k];
+        *counter = 0u;
+    }
+    return true;
+}
+
+}  // namespace bcm

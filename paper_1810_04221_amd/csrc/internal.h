@@ -1,0 +1,163 @@
+// Host-side internals of the library: hierarchy data layout in HBM, the device
+// arena and the kernel launchers shared between translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "bcm.h"
+
+namespace bcm {
+
+constexpr int kMaxLevels = 64;
+constexpr int kCoarseLds = 8192;  // largest coarsest level solved inside one workgroup
+
+// Error flags raised by the validation kernel.
+enum : int {
+    kErrRowPtr = 1, kErrCol = 2, kErrUnsorted = 4, kErrNonFinite = 8, kErrNoDiag = 16,
+    kErrDiagNonPos = 32, kErrW = 64, kErrAsym = 128
+};
+
+struct Status {
+    int code = BCM_OK;
+    std::string msg;
+};
+void set_error(const std::string &m);
+
+// Bump allocator over a few large device chunks obtained from the caller's
+// allocator (or hipMalloc).  Nothing is freed before release().
+struct Arena {
+    void *(*alloc)(size_t, void *) = nullptr;
+    void (*dealloc)(void *, size_t, void *) = nullptr;
+    void *ctx = nullptr;
+    std::vector<std::pair<void *, size_t>> chunks;
+    char *cur = nullptr;
+    size_t left = 0;
+    size_t chunk_min = size_t(64) << 20;
+    bool failed = false;
+
+    void *raw_alloc(size_t bytes);
+    void raw_free(void *p, size_t bytes);
+    void *get(size_t bytes);
+    template <typename T>
+    T *get_n(size_t n) { return static_cast<T *>(get(n * sizeof(T))); }
+    void reserve(size_t bytes);
+    void rewind();   // forget all sub-allocations, keep the chunks
+    void release();  // free every chunk
+};
+
+struct Csr {
+    int n = 0, nnz = 0;
+    int *rp = nullptr, *ci = nullptr;
+    double *v = nullptr;
+    float *v32 = nullptr;
+};
+
+// One level of the hierarchy.  Row i of A^k, its l1 inverse diagonal, the
+// composed prolongator P^k (one nonzero per row: column agg[i], value p[i]),
+// and the members of every coarse aggregate (P^k transposed) in ascending
+// order, mstride slots per aggregate padded with -1.
+struct Level {
+    Csr A;
+    double *w = nullptr;
+    double *dinv = nullptr;
+    float *dinv32 = nullptr;
+    int G = 8;  // lanes per row for this level's row kernels
+    int nc = 0;
+    int *agg = nullptr;
+    double *p = nullptr;
+    float *p32 = nullptr;
+    int mstride = 0;
+    int *mem = nullptr;
+    void *b = nullptr, *x = nullptr;  // cycle vectors for k >= 1 (cycle precision)
+};
+
+struct ProfClass {
+    int64_t launches = 0;
+    double ms = 0.0, bytes = 0.0;
+};
+
+}  // namespace bcm
+
+struct bcm_handle {
+    bcm_params prm{};
+    hipStream_t s = nullptr;
+    int nl = 0;
+    bcm::Level lv[bcm::kMaxLevels];
+    bcm::Arena persist, scratch;
+    // flexible CG vectors (float64, n of the finest level)
+    double *r = nullptr, *w = nullptr, *d = nullptr, *v = nullptr, *q = nullptr;
+    // device scalars: [0] alpha [1] beta [2] gamma [3] rho_prev [4] ||r||^2 [5] ||b||^2
+    // [6] breakdown flag [7] spare
+    double *scal = nullptr;
+    double *ctmp[2] = {nullptr, nullptr};  // coarsest-level sweep buffers when n > kCoarseLds
+    double *partials = nullptr;
+    unsigned *counter = nullptr;
+    double *host_scal = nullptr;  // pinned
+    int red_blocks = 0;
+    double last_tol = 0.0;
+    int iters = 0, status = 0;
+    double relres = 0.0, t_setup_ms = 0.0, t_solve_ms = 0.0;
+    // profiling
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<std::pair<int, int>> ev_pairs;  // (class, event index of the start)
+    std::vector<double> ev_bytes;
+    bcm::ProfClass prof[5];
+};
+
+namespace bcm {
+
+int pick_G(double avg_nnz_per_row);
+
+// ---- setup kernels (setup.hip) ----
+void launch_validate(hipStream_t s, int G, int n, int nnz, const int *rp, const int *ci,
+                     const double *v, const double *w, int check_sym, double *diag, int *flags);
+void launch_weights(hipStream_t s, int G, int n, const int *rp, const int *ci, const double *v,
+                    const double *diag, const double *w, double *c);
+void launch_rank(hipStream_t s, int G, int n, const int *rp, const int *ci, const double *c,
+                 uint32_t *rk);
+void launch_suitor(hipStream_t s, int n, const int *rp, const int *ci, const double *c,
+                   const uint32_t *rk, unsigned long long *ws);
+void launch_mate(hipStream_t s, int n, const unsigned long long *ws, int *mate, int *leader);
+void launch_aggfill(hipStream_t s, int n, const int *mate, const int *ofs, const double *w,
+                    int *agg, double *p, double *wc, int *mem2);
+void launch_gal_count(hipStream_t s, int G, int nc, const int *rp, const int *ci, const int *agg,
+                      const int *mem2, int *cnt, int *gF, int *gU);
+void launch_gal_fill(hipStream_t s, int G, int nc, const int *rp, const int *ci, const double *v,
+                     const int *agg, const double *p, const int *mem2, const int *crp, int *cci,
+                     double *cv, int *gF, int *gU);
+void launch_compose(hipStream_t s, int n, int nc_new, const int *agg_prev, const double *p_prev,
+                    const int *mem_prev, int stride_prev, const int *agg_s, const double *p_s,
+                    const int *mem_s, int *agg_out, double *p_out, int *mem_out);
+void launch_diag_l1(hipStream_t s, int G, int n, const int *rp, const double *v, double *dinv,
+                    float *dinv32);
+void launch_cast(hipStream_t s, size_t n, const double *src, float *dst);
+void launch_fill_i32(hipStream_t s, size_t n, int *dst, int val);
+void launch_fill_u64(hipStream_t s, size_t n, unsigned long long *dst, unsigned long long val);
+void launch_copy_f64(hipStream_t s, size_t n, const double *src, double *dst);
+
+// ---- scan (scan.hip) ----
+size_t scan_tmp_bytes(int n);
+// out[i] = sum_{j<i} in[j] (in and out may alias); total written to *total_dev.
+void scan_exclusive(hipStream_t s, const int *in, int *out, int n, int *total_dev, void *tmp);
+
+// ---- solve kernels (solve.hip) ----
+void launch_down(hipStream_t s, const Level &L, int fp32, const void *b, void *bc, int b_is_f64);
+void launch_up(hipStream_t s, const Level &L, int fp32, const void *b, const void *xc, void *x,
+               int b_is_f64, int x_is_f64);
+void launch_coarse(hipStream_t s, const Level &L, int sweeps, const void *b, void *x, int b_f64,
+                   int x_f64, void *tmp_a, void *tmp_b);
+void launch_resid(hipStream_t s, const Level &L, int nb, const double *b, const double *u, double *r,
+                  double *partials, unsigned *counter, double *scal);
+void launch_spmv_dots(hipStream_t s, const Level &L, int nb, const double *w, const double *r,
+                      const double *q, double *v, double *partials, unsigned *counter, double *scal);
+void launch_update(hipStream_t s, int n, int nb, int first, const double *w, const double *v,
+                   double *d, double *u, double *q, double *r, double *partials, unsigned *counter,
+                   double *scal);
+void launch_sampled_outer(hipStream_t s, const Level &L, const double *lam, const double *x,
+                          double *G);
+int reduce_blocks(int n);
+
+}  // namespace bcm

@@ -1,0 +1,534 @@
+// Setup-phase kernels for gfx950: input validation, compatible-matching edge
+// weights, Suitor matching, pairwise aggregation (Algorithm 2), the
+// w-normalised prolongator and the Galerkin product P^T A P (Sections 2.1, 2.2,
+// 3.1 of the paper).
+//
+// Every floating-point expression here is written so that the device and a
+// serial IEEE binary64 evaluation round identically: the file is compiled with
+// -ffp-contract=off (no FMA contraction) and each operation below is one
+// correctly rounded binary64 add, multiply, divide or square root.
+#include <type_traits>
+
+#include "device.h"
+#include "internal.h"
+
+#pragma clang fp contract(off)
+
+namespace bcm {
+
+namespace {
+
+template <typename Fn>
+void with_G(int G, Fn &&fn) {
+    switch (G) {
+        case 4: fn(std::integral_constant<int, 4>{}); break;
+        case 8: fn(std::integral_constant<int, 8>{}); break;
+        case 16: fn(std::integral_constant<int, 16>{}); break;
+        case 32: fn(std::integral_constant<int, 32>{}); break;
+        default: fn(std::integral_constant<int, 64>{}); break;
+    }
+}
+
+inline int blocks_for(long long threads) { return (int)((threads + kBlock - 1) / kBlock); }
+
+// ----------------------------------------------------------------------------
+// Validation and diagonal: one group of G lanes per row.  Every read is guarded
+// so that malformed input raises a flag instead of an out-of-bounds access.
+// ----------------------------------------------------------------------------
+template <int G>
+__global__ void __launch_bounds__(kBlock)
+k_validate(int n, int nnz, const int *__restrict__ rp, const int *__restrict__ ci,
+           const double *__restrict__ v, const double *__restrict__ w, int check_sym,
+           double *__restrict__ diag, int *__restrict__ flags) {
+    const int lane = threadIdx.x % G;
+    const int row = (blockIdx.x * kBlock + threadIdx.x) / G;
+    if (row >= n) return;
+    const int s = rp[row], e = rp[row + 1];
+    int f = 0;
+    if (s < 0 || e < s || e > nnz || (row == 0 && s != 0) || (row == n - 1 && e != nnz)) {
+        if (lane == 0) atomicOr(flags, kErrRowPtr);
+        return;
+    }
+    int has_diag = 0;
+    double dval = 0.0;
+    for (int q = s + lane; q < e; q += G) {
+        const int j = ci[q];
+        const double a = v[q];
+        if (j < 0 || j >= n) { f |= kErrCol; continue; }
+        if (q > s && ci[q - 1] >= j) f |= kErrUnsorted;
+        if (!isfinite(a)) f |= kErrNonFinite;
+        if (j == row) { has_diag = 1; dval = a; }
+        if (check_sym && j != row) {
+            const int s2 = rp[j], e2 = rp[j + 1];
+            int found = -1;
+            if (s2 >= 0 && e2 >= s2 && e2 <= nnz) {
+                int lo = s2, hi = e2 - 1;
+                while (lo <= hi) {
+                    const int mid = (lo + hi) >> 1;
+                    const int cm = ci[mid];
+                    if (cm == row) { found = mid; break; }
+                    if (cm < row) lo = mid + 1; else hi = mid - 1;
+                }
+            }
+            if (found < 0 || __double_as_longlong(v[found]) != __double_as_longlong(a)) f |= kErrAsym;
+        }
+    }
+    // one lane at most holds the diagonal
+    const int hd = group_sum<G>(has_diag);
+    const double dv = group_sum<G>(has_diag ? dval : 0.0);
+    if (lane == 0) {
+        if (hd == 0) f |= kErrNoDiag;
+        else if (!(dv > 0.0)) f |= kErrDiagNonPos;
+        diag[row] = dv;
+        const double wi = w[row];
+        if (!(isfinite(wi) && wi != 0.0)) f |= kErrW;
+    }
+    if (f) atomicOr(flags, f);
+}
+
+// ----------------------------------------------------------------------------
+// Edge weights of compatible weighted matching (Section 2.2):
+//   c_ij = 1 - 2 a_ij w_i w_j / (a_ii w_i^2 + a_jj w_j^2)
+// with m = min(i, j), M = max(i, j) fixing the operand order, so both ends of
+// an edge compute the same double.  Diagonal positions get 0.
+// ----------------------------------------------------------------------------
+template <int G>
+__global__ void __launch_bounds__(kBlock)
+k_weights(int n, const int *__restrict__ rp, const int *__restrict__ ci, const double *__restrict__ v,
+          const double *__restrict__ diag, const double *__restrict__ w, double *__restrict__ c) {
+    const int lane = threadIdx.x % G;
+    const int row = (xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x) / G;
+    if (row >= n) return;
+    const int e = rp[row + 1];
+    for (int q = rp[row] + lane; q < e; q += G) {
+        const int j = ci[q];
+        if (j == row) { c[q] = 0.0; continue; }
+        const int m = min(row, j), M = max(row, j);
+        const double wm = w[m], wM = w[M];
+        const double num = ((2.0 * v[q]) * wm) * wM;
+        const double den = (diag[m] * wm) * wm + (diag[M] * wM) * wM;
+        c[q] = 1.0 - num / den;
+    }
+}
+
+// ----------------------------------------------------------------------------
+// Row ranks for exact Suitor keys.  For the stored entry q = (u, v):
+//   rk[q] = #{ entries t of row v : c[t] < c[q] }
+// i.e. the position of c_uv among the weights seen from vertex v.  Proposals to
+// v then compare as (rk, proposer) in one 64-bit word, which orders them
+// exactly as (c_uv, u) because c_uv is the same double from both ends.
+// ----------------------------------------------------------------------------
+template <int G>
+__global__ void __launch_bounds__(kBlock)
+k_rank(int n, const int *__restrict__ rp, const int *__restrict__ ci, const double *__restrict__ c,
+       uint32_t *__restrict__ rk) {
+    const int lane = threadIdx.x % G;
+    const int row = (xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x) / G;
+    if (row >= n) return;
+    const int e = rp[row + 1];
+    for (int q = rp[row] + lane; q < e; q += G) {
+        const int vtx = ci[q];
+        if (vtx == row) { rk[q] = 0u; continue; }
+        const double cq = c[q];
+        uint32_t cnt = 0;
+        const int e2 = rp[vtx + 1];
+        for (int t = rp[vtx]; t < e2; ++t) cnt += (c[t] < cq) ? 1u : 0u;
+        rk[q] = cnt;
+    }
+}
+
+// ----------------------------------------------------------------------------
+// Suitor matching (Section 3.1).  One thread per vertex holds that vertex's
+// proposal.  A vertex u proposes to its best neighbour v, by (c_uv, v), whose
+// current suitor ranks below u; ws[v] holds the 64-bit key (rk, proposer + 1)
+// of v's best proposal so far and is raised with atomicMax.  A proposer that
+// is displaced is taken over by the displacing thread and proposes again.
+// Every successful atomicMax strictly raises one ws[] entry and a failed one
+// means another thread raised it, so the total number of loop trips is
+// bounded and every thread exits.  The final suitor pairs are mutual and equal
+// the greedy matching under (c desc, larger endpoint desc, smaller desc).
+// Only edges with a positive finite weight take part.
+// ----------------------------------------------------------------------------
+__global__ void __launch_bounds__(kBlock)
+k_suitor(int n, const int *__restrict__ rp, const int *__restrict__ ci, const double *__restrict__ c,
+         const uint32_t *__restrict__ rk, unsigned long long *ws) {
+    const int u0 = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    if (u0 >= n) return;
+    int u = u0;
+    for (;;) {
+        int best = -1;
+        double bc = 0.0;
+        unsigned long long bkey = 0ull;
+        const int e = rp[u + 1];
+        for (int q = rp[u]; q < e; ++q) {
+            const int vtx = ci[q];
+            if (vtx == u) continue;
+            const double cq = c[q];
+            if (!(cq > 0.0 && cq < INFINITY)) continue;
+            if (best >= 0 && (cq < bc || (cq == bc && vtx < best))) continue;
+            const unsigned long long key =
+                ((unsigned long long)rk[q] << 32) | (unsigned long long)(unsigned)(u + 1);
+            if (key > load_agent(&ws[vtx])) { best = vtx; bc = cq; bkey = key; }
+        }
+        if (best < 0) break;
+        const unsigned long long old = atomicMax(&ws[best], bkey);
+        if (old > bkey) continue;  // lost the race: look again for u
+        if (old == 0ull) break;    // v had no suitor: done
+        u = (int)(old & 0xffffffffull) - 1;  // displaced suitor proposes again
+    }
+}
+
+// mate[i] = s if i and its suitor s chose each other; leader[i] marks the
+// smallest member of each aggregate of Algorithm 2.
+__global__ void __launch_bounds__(kBlock)
+k_mate(int n, const unsigned long long *__restrict__ ws, int *__restrict__ mate, int *__restrict__ leader) {
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const int s = (int)(ws[i] & 0xffffffffull) - 1;
+    int m = -1;
+    if (s >= 0 && (int)(ws[s] & 0xffffffffull) - 1 == i) m = s;
+    mate[i] = m;
+    leader[i] = (m < 0 || i < m) ? 1 : 0;
+}
+
+// ----------------------------------------------------------------------------
+// Algorithm 2 with aggregates numbered in the order of their smallest member
+// (ofs = exclusive scan of leader flags), and the prolongator: orthonormal
+// projection of w on each aggregate (Section 2.2).  Pair {i < j}:
+// s = sqrt(w_i*w_i + w_j*w_j), p = w / s; singleton: s = |w_i|.  The coarse
+// smooth vector is the restriction P^T w = s.  mem2 lists each aggregate's
+// members (second = -1 for a singleton).
+// ----------------------------------------------------------------------------
+__global__ void __launch_bounds__(kBlock)
+k_aggfill(int n, const int *__restrict__ mate, const int *__restrict__ ofs, const double *__restrict__ w,
+          int *__restrict__ agg, double *__restrict__ p, double *__restrict__ wc, int *__restrict__ mem2) {
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const int m = mate[i];
+    if (!(m < 0 || i < m)) return;
+    const int E = ofs[i];
+    agg[i] = E;
+    mem2[2 * E] = i;
+    const double wi = w[i];
+    if (m >= 0) {
+        const double wm = w[m];
+        const double s = sqrt(wi * wi + wm * wm);
+        agg[m] = E;
+        mem2[2 * E + 1] = m;
+        p[i] = wi / s;
+        p[m] = wm / s;
+        wc[E] = s;
+    } else {
+        const double s = fabs(wi);
+        mem2[2 * E + 1] = -1;
+        p[i] = wi / s;
+        wc[E] = s;
+    }
+}
+
+// ----------------------------------------------------------------------------
+// Galerkin product A_c = P^T A P for one pairwise sweep (Section 2.1; the
+// paper's most expensive setup step).  One group of G lanes per coarse row E.
+// The candidate columns F = agg[j] of E's member rows are staged in LDS
+// (16 G per group; longer rows fall back to scratch arrays indexed by the
+// candidate's position in A).  Pass 0 counts distinct columns; pass 1 writes
+// them in ascending order and the value of each entry:
+//   (A_c)_EF = sum over stored (i in E, j in F) of (p_m * a_ij) * p_M,
+//   m = min(i, j), M = max(i, j), summed from the first term in ascending
+//   (m, M).  Terms sharing (m, M) (i <-> j inside one aggregate) are
+//   bitwise equal, so the sum is exactly symmetric and independent of timing.
+// ----------------------------------------------------------------------------
+__device__ __forceinline__ int find_col(const int *__restrict__ rp, const int *__restrict__ ci, int i,
+                                        int j) {
+    int lo = rp[i], hi = rp[i + 1] - 1;
+    while (lo <= hi) {
+        const int mid = (lo + hi) >> 1;
+        const int cm = ci[mid];
+        if (cm == j) return mid;
+        if (cm < j) lo = mid + 1; else hi = mid - 1;
+    }
+    return -1;
+}
+
+__device__ __forceinline__ void cswap(unsigned long long &ka, double &ta, unsigned long long &kb,
+                                      double &tb) {
+    if (kb < ka) {
+        const unsigned long long k = ka; ka = kb; kb = k;
+        const double t = ta; ta = tb; tb = t;
+    }
+}
+
+__device__ double gal_entry(int e0, int e1, int f0, int f1, const int *__restrict__ rp,
+                            const int *__restrict__ ci, const double *__restrict__ v,
+                            const double *__restrict__ p) {
+    const unsigned long long NONE = ~0ull;
+    unsigned long long k[4] = {NONE, NONE, NONE, NONE};
+    double t[4] = {0.0, 0.0, 0.0, 0.0};
+    const int es[2] = {e0, e1}, fs[2] = {f0, f1};
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            const int i = es[a], j = fs[b];
+            if (i < 0 || j < 0) continue;
+            const int q = find_col(rp, ci, i, j);
+            if (q < 0) continue;
+            const int m = min(i, j), M = max(i, j);
+            k[2 * a + b] = ((unsigned long long)(unsigned)m << 32) | (unsigned)M;
+            t[2 * a + b] = (p[m] * v[q]) * p[M];
+        }
+    }
+    cswap(k[0], t[0], k[1], t[1]);
+    cswap(k[2], t[2], k[3], t[3]);
+    cswap(k[0], t[0], k[2], t[2]);
+    cswap(k[1], t[1], k[3], t[3]);
+    cswap(k[1], t[1], k[2], t[2]);
+    double s = t[0];
+#pragma unroll
+    for (int r = 1; r < 4; ++r)
+        if (k[r] != NONE) s = s + t[r];
+    return s;
+}
+
+template <int G>
+__global__ void __launch_bounds__(kBlock)
+k_gal(int pass, int nc, const int *__restrict__ rp, const int *__restrict__ ci,
+      const double *__restrict__ v, const int *__restrict__ agg, const double *__restrict__ p,
+      const int *__restrict__ mem2, int *__restrict__ cnt, const int *__restrict__ crp,
+      int *__restrict__ cci, double *__restrict__ cv, int *__restrict__ gF, int *__restrict__ gU) {
+    constexpr int LMAX = 16 * G;
+    constexpr int NG = kBlock / G;
+    __shared__ int sF[NG * LMAX];
+    __shared__ int sU[NG * LMAX];
+    const int g = threadIdx.x / G, lane = threadIdx.x % G;
+    const int E = xcd_block(blockIdx.x, gridDim.x) * NG + g;
+    if (E >= nc) return;
+    const int e0 = mem2[2 * E], e1 = mem2[2 * E + 1];
+    const int s0 = rp[e0], L0 = rp[e0 + 1] - s0;
+    const int s1 = e1 >= 0 ? rp[e1] : 0;
+    const int L1 = e1 >= 0 ? rp[e1 + 1] - s1 : 0;
+    const int L = L0 + L1;
+    const bool staged = L <= LMAX;
+    int *F = staged ? sF + g * LMAX : gF;
+    int *U = staged ? sU + g * LMAX : gU;
+    // slot of candidate k: LDS index, or its position in A (disjoint per coarse row)
+    auto slot = [&](int k) { return staged ? k : (k < L0 ? s0 + k : s1 + (k - L0)); };
+    for (int k = lane; k < L; k += G) {
+        const int q = k < L0 ? s0 + k : s1 + (k - L0);
+        F[slot(k)] = agg[ci[q]];
+    }
+    if (staged) wave_sync(); else __threadfence_block();
+    int nu = 0;
+    for (int k = lane; k < L; k += G) {
+        const int f = F[slot(k)];
+        int first = 1;
+        for (int k2 = 0; k2 < k; ++k2)
+            if (F[slot(k2)] == f) { first = 0; break; }
+        U[slot(k)] = first;
+        nu += first;
+    }
+    if (pass == 0) {
+        nu = group_sum<G>(nu);
+        if (lane == 0) cnt[E] = nu;
+        return;
+    }
+    if (staged) wave_sync(); else __threadfence_block();
+    const int base = crp[E];
+    for (int k = lane; k < L; k += G) {
+        if (!U[slot(k)]) continue;
+        const int f = F[slot(k)];
+        int rank = 0;
+        for (int k2 = 0; k2 < L; ++k2) rank += (U[slot(k2)] && F[slot(k2)] < f) ? 1 : 0;
+        cci[base + rank] = f;
+        cv[base + rank] = gal_entry(e0, e1, mem2[2 * f], mem2[2 * f + 1], rp, ci, v, p);
+    }
+}
+
+// ----------------------------------------------------------------------------
+// Composition of the previous sweeps' prolongator with this sweep's pairwise
+// one: agg = agg_s[agg_prev], p = p_prev * p_s[agg_prev]; the members of each
+// new aggregate are the members of its (at most two) sweep aggregates, sorted
+// ascending, stride 2 * stride_prev, padded with -1.
+// ----------------------------------------------------------------------------
+__global__ void __launch_bounds__(kBlock)
+k_compose_rows(int n, const int *__restrict__ agg_prev, const double *__restrict__ p_prev,
+               const int *__restrict__ agg_s, const double *__restrict__ p_s, int *__restrict__ agg_out,
+               double *__restrict__ p_out) {
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const int a = agg_prev[i];
+    p_out[i] = p_prev[i] * p_s[a];
+    agg_out[i] = agg_s[a];
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_compose_members(int nc_new, const int *__restrict__ mem_prev, int stride_prev,
+                  const int *__restrict__ mem_s, int *__restrict__ mem_out) {
+    const int E = blockIdx.x * kBlock + threadIdx.x;
+    if (E >= nc_new) return;
+    int buf[16];
+    int cnt = 0;
+    for (int h = 0; h < 2; ++h) {
+        const int F = mem_s[2 * E + h];
+        if (F < 0) continue;
+        for (int t = 0; t < stride_prev; ++t) {
+            const int i = mem_prev[(size_t)F * stride_prev + t];
+            if (i < 0) break;
+            int pos = cnt++;
+            while (pos > 0 && buf[pos - 1] > i) { buf[pos] = buf[pos - 1]; --pos; }
+            buf[pos] = i;
+        }
+    }
+    const int so = 2 * stride_prev;
+    for (int t = 0; t < so; ++t) mem_out[(size_t)E * so + t] = t < cnt ? buf[t] : -1;
+}
+
+// l1-Jacobi (Section 3.2): dinv_i = 1 / sum_j |a_ij|.
+template <int G>
+__global__ void __launch_bounds__(kBlock)
+k_diag_l1(int n, const int *__restrict__ rp, const double *__restrict__ v, double *__restrict__ dinv,
+          float *__restrict__ dinv32) {
+    const int lane = threadIdx.x % G;
+    const int row = (xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x) / G;
+    if (row >= n) return;
+    double s = 0.0;
+    const int e = rp[row + 1];
+    for (int q = rp[row] + lane; q < e; q += G) s += fabs(v[q]);
+    s = group_sum<G>(s);
+    if (lane == 0) {
+        const double d = 1.0 / s;
+        dinv[row] = d;
+        if (dinv32) dinv32[row] = (float)d;
+    }
+}
+
+__global__ void k_cast(size_t n, const double *__restrict__ src, float *__restrict__ dst) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        dst[i] = (float)src[i];
+}
+
+__global__ void k_copy_f64(size_t n, const double *__restrict__ src, double *__restrict__ dst) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
+__global__ void k_fill_i32(size_t n, int *__restrict__ dst, int val) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        dst[i] = val;
+}
+
+__global__ void k_fill_u64(size_t n, unsigned long long *__restrict__ dst, unsigned long long val) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        dst[i] = val;
+}
+
+inline int stream_grid(size_t n) {
+    size_t b = (n + kBlock - 1) / kBlock;
+    if (b > 4096) b = 4096;
+    if (b < 1) b = 1;
+    return (int)b;
+}
+
+}  // namespace
+
+int pick_G(double avg) {
+    int G = 4;
+    while (G < 64 && G < avg) G <<= 1;
+    return G;
+}
+
+void launch_validate(hipStream_t s, int G, int n, int nnz, const int *rp, const int *ci,
+                     const double *v, const double *w, int check_sym, double *diag, int *flags) {
+    with_G(G, [&](auto gc) {
+        constexpr int g = decltype(gc)::value;
+        hipLaunchKernelGGL(k_validate<g>, dim3(blocks_for((long long)n * g)), dim3(kBlock), 0, s, n, nnz,
+                           rp, ci, v, w, check_sym, diag, flags);
+    });
+}
+
+void launch_weights(hipStream_t s, int G, int n, const int *rp, const int *ci, const double *v,
+                    const double *diag, const double *w, double *c) {
+    with_G(G, [&](auto gc) {
+        constexpr int g = decltype(gc)::value;
+        hipLaunchKernelGGL(k_weights<g>, dim3(blocks_for((long long)n * g)), dim3(kBlock), 0, s, n, rp, ci,
+                           v, diag, w, c);
+    });
+}
+
+void launch_rank(hipStream_t s, int G, int n, const int *rp, const int *ci, const double *c,
+                 uint32_t *rk) {
+    with_G(G, [&](auto gc) {
+        constexpr int g = decltype(gc)::value;
+        hipLaunchKernelGGL(k_rank<g>, dim3(blocks_for((long long)n * g)), dim3(kBlock), 0, s, n, rp, ci, c,
+                           rk);
+    });
+}
+
+void launch_suitor(hipStream_t s, int n, const int *rp, const int *ci, const double *c,
+                   const uint32_t *rk, unsigned long long *ws) {
+    hipLaunchKernelGGL(k_suitor, dim3(blocks_for(n)), dim3(kBlock), 0, s, n, rp, ci, c, rk, ws);
+}
+
+void launch_mate(hipStream_t s, int n, const unsigned long long *ws, int *mate, int *leader) {
+    hipLaunchKernelGGL(k_mate, dim3(blocks_for(n)), dim3(kBlock), 0, s, n, ws, mate, leader);
+}
+
+void launch_aggfill(hipStream_t s, int n, const int *mate, const int *ofs, const double *w, int *agg,
+                    double *p, double *wc, int *mem2) {
+    hipLaunchKernelGGL(k_aggfill, dim3(blocks_for(n)), dim3(kBlock), 0, s, n, mate, ofs, w, agg, p, wc, mem2);
+}
+
+void launch_gal_count(hipStream_t s, int G, int nc, const int *rp, const int *ci, const int *agg,
+                      const int *mem2, int *cnt, int *gF, int *gU) {
+    with_G(G, [&](auto gc) {
+        constexpr int g = decltype(gc)::value;
+        hipLaunchKernelGGL(k_gal<g>, dim3(blocks_for((long long)nc * g)), dim3(kBlock), 0, s, 0, nc, rp, ci,
+                           nullptr, agg, nullptr, mem2, cnt, nullptr, nullptr, nullptr, gF, gU);
+    });
+}
+
+void launch_gal_fill(hipStream_t s, int G, int nc, const int *rp, const int *ci, const double *v,
+                     const int *agg, const double *p, const int *mem2, const int *crp, int *cci,
+                     double *cv, int *gF, int *gU) {
+    with_G(G, [&](auto gc) {
+        constexpr int g = decltype(gc)::value;
+        hipLaunchKernelGGL(k_gal<g>, dim3(blocks_for((long long)nc * g)), dim3(kBlock), 0, s, 1, nc, rp, ci, v,
+                           agg, p, mem2, nullptr, crp, cci, cv, gF, gU);
+    });
+}
+
+void launch_compose(hipStream_t s, int n, int nc_new, const int *agg_prev, const double *p_prev,
+                    const int *mem_prev, int stride_prev, const int *agg_s, const double *p_s,
+                    const int *mem_s, int *agg_out, double *p_out, int *mem_out) {
+    hipLaunchKernelGGL(k_compose_rows, dim3(blocks_for(n)), dim3(kBlock), 0, s, n, agg_prev, p_prev, agg_s, p_s,
+                       agg_out, p_out);
+    hipLaunchKernelGGL(k_compose_members, dim3(blocks_for(nc_new)), dim3(kBlock), 0, s, nc_new, mem_prev,
+                       stride_prev, mem_s, mem_out);
+}
+
+void launch_diag_l1(hipStream_t s, int G, int n, const int *rp, const double *v, double *dinv,
+                    float *dinv32) {
+    with_G(G, [&](auto gc) {
+        constexpr int g = decltype(gc)::value;
+        hipLaunchKernelGGL(k_diag_l1<g>, dim3(blocks_for((long long)n * g)), dim3(kBlock), 0, s, n, rp, v, dinv,
+                           dinv32);
+    });
+}
+
+void launch_cast(hipStream_t s, size_t n, const double *src, float *dst) {
+    hipLaunchKernelGGL(k_cast, dim3(stream_grid(n)), dim3(kBlock), 0, s, n, src, dst);
+}
+
+void launch_copy_f64(hipStream_t s, size_t n, const double *src, double *dst) {
+    hipLaunchKernelGGL(k_copy_f64, dim3(stream_grid(n)), dim3(kBlock), 0, s, n, src, dst);
+}
+
+void launch_fill_i32(hipStream_t s, size_t n, int *dst, int val) {
+    hipLaunchKernelGGL(k_fill_i32, dim3(stream_grid(n)), dim3(kBlock), 0, s, n, dst, val);
+}
+
+void launch_fill_u64(hipStream_t s, size_t n, unsigned long long *dst, unsigned long long val) {
+    hipLaunchKernelGGL(k_fill_u64, dim3(stream_grid(n)), dim3(kBlock), 0, s, n, dst, val);
+}
+
+}  // namespace bcm

@@ -1,0 +1,247 @@
+"""GPU parity against the serial oracle, through the C ABI.
+
+Bars: matchings, aggregates, prolongators and coarse matrices bit-exact (the
+weights are FP64 without FMA contraction; the Galerkin sums run in one fixed
+order on both sides); l1 diagonals within (row length) ulp; one FP64 cycle within 1e-12
+relative; FP64 solves reach the true residual with the iteration count within
++-1 of the oracle's; the FP32-cycle form reaches the same FP64 residual and its
+cycle error against the FP64 oracle is bounded as stated below.
+"""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from paper_1810_04221_amd import problems as P
+
+pytestmark = pytest.mark.gpu
+ULP = np.finfo(np.float64).eps
+
+
+def say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def B():
+    import torch
+    from paper_1810_04221_amd import bcm
+    bcm.load_library()
+    assert torch.cuda.is_available(), "GPU tests need a visible gfx950 GPU"
+    return bcm
+
+
+def _bits(a):
+    return np.ascontiguousarray(a, dtype=np.float64).view(np.uint64)
+
+
+def _star(n):
+    A = sp.lil_matrix((n, n))
+    for j in range(1, n):
+        A[0, j] = A[j, 0] = -1.0
+    A.setdiag([n + 1.0] + [2.0] * (n - 1))
+    A = A.tocsr()
+    A.sort_indices()
+    return A.indptr.astype(np.int32), A.indices.astype(np.int32), A.data.copy()
+
+
+def _clique(n):
+    A = sp.csr_matrix(-np.ones((n, n)) + (n + 1.0) * np.eye(n))
+    return A.indptr.astype(np.int32), A.indices.astype(np.int32), A.data.copy()
+
+
+MATCH_CASES = {
+    "path9": lambda: (*P.laplace1d(9), None),
+    "path4097": lambda: (*P.laplace1d(4097), None),
+    "star65": lambda: (*_star(65), None),
+    "clique40": lambda: (*_clique(40), None),
+    "rand500_eq": lambda: (*P.random_spd(500, 0.01, 3, equal_weights=True), None),
+    "rand5000_w": lambda: (*P.random_spd(5000, 0.002, 4), np.random.default_rng(9).uniform(0.2, 3, 5000)),
+    "G1": lambda: (*[P.config("G1")[k] for k in ("rowptr", "col", "val")], None),
+    "G2_30": lambda: (*[P.config("G2", 0.3)[k] for k in ("rowptr", "col", "val")], None),
+    "G3_32": lambda: (*[P.config("G3", 0.2)[k] for k in ("rowptr", "col", "val")], None),
+    "G4_10": lambda: (*[P.config("G4", 0.21)[k] for k in ("rowptr", "col", "val")], None),
+}
+
+
+@pytest.mark.parametrize("case", list(MATCH_CASES))
+def test_matching_bitexact(B, ora, case):
+    rp, ci, va, w = MATCH_CASES[case]()
+    n = len(rp) - 1
+    w = np.ones(n) if w is None else w
+    c_ref = ora.weights(rp, ci, va, w)
+    mate_ref = ora.match(rp, ci, c_ref)
+    for rep in range(3):
+        say(f"match {case} n={n} nnz={len(ci)} rep={rep}")
+        mate, c = B.match(rp, ci, va, w)
+        assert np.array_equal(_bits(c.cpu().numpy()), _bits(c_ref)), "edge weights differ"
+        assert np.array_equal(mate.cpu().numpy(), mate_ref), "matching differs from greedy"
+
+
+HIER_CASES = [("G1", 1.0), ("G2", 0.3), ("G3", 0.2), ("G4", 0.21), ("G5", 0.2), ("G2", 1.0)]
+
+
+def _compare_hierarchy(h, ho):
+    inf = h.info()
+    assert inf["nl"] == ho.nl
+    assert inf["n"] == ho.sizes() and inf["nnz"] == ho.nnzs()
+    for k in range(ho.nl):
+        g, o = h.level(k), ho.level(k)
+        assert np.array_equal(g["rowptr"], o["rowptr"]), f"level {k} row_ptr"
+        assert np.array_equal(g["col"], o["col"]), f"level {k} col"
+        assert np.array_equal(_bits(g["val"]), _bits(o["val"])), f"level {k} values"
+        assert np.array_equal(_bits(g["w"]), _bits(o["w"])), f"level {k} smooth vector"
+        # sum of |a_ij| in another order: error bound (row length) ulp
+        rl = np.diff(o["rowptr"]).astype(float)
+        err = np.abs(g["dinv"] - o["dinv"]) / (rl * ULP * np.abs(o["dinv"]))
+        assert err.max() <= 1.0, f"level {k} dinv: {err.max():.2f} x bound"
+        if k < ho.nl - 1:
+            assert np.array_equal(g["agg"], o["agg"]), f"level {k} aggregates"
+            assert np.array_equal(_bits(g["p"]), _bits(o["p"])), f"level {k} prolongator"
+
+
+@pytest.mark.parametrize("name,scale", HIER_CASES)
+def test_hierarchy_bitexact(B, ora, name, scale):
+    c = P.config(name, scale)
+    say(f"setup {c['name']} n={c['n']}")
+    h = B.Hierarchy(c["rowptr"], c["col"], c["val"], c["w"], max_coarse=c["max_coarse"])
+    ho = ora.Hierarchy(c["rowptr"], c["col"], c["val"], c["w"], max_coarse=c["max_coarse"])
+    _compare_hierarchy(h, ho)
+    h.close()
+
+
+def test_hierarchy_sweeps_1_and_3_and_random_w(B, ora):
+    c = P.config("G3", 0.15)
+    w = np.random.default_rng(1).uniform(0.5, 2.0, c["n"])
+    for sweeps in (1, 3):
+        say(f"setup sweeps={sweeps} {c['name']}")
+        h = B.Hierarchy(c["rowptr"], c["col"], c["val"], w, max_coarse=30, sweeps=sweeps)
+        ho = ora.Hierarchy(c["rowptr"], c["col"], c["val"], w, max_coarse=30, sweeps=sweeps)
+        _compare_hierarchy(h, ho)
+
+
+@pytest.mark.parametrize("name,scale", [("G1", 1.0), ("G2", 0.3), ("G4", 0.21), ("G3", 0.2)])
+def test_precond_fp64_parity(B, ora, name, scale):
+    c = P.config(name, scale)
+    say(f"precond fp64 {c['name']}")
+    h = B.Hierarchy(c["rowptr"], c["col"], c["val"], c["w"], max_coarse=c["max_coarse"])
+    ho = ora.Hierarchy(c["rowptr"], c["col"], c["val"], c["w"], max_coarse=c["max_coarse"])
+    r = P.uniform_rhs(c["n"], 11)
+    z = h.precond(r).cpu().numpy()
+    zo = ho.vcycle(r)
+    assert np.linalg.norm(z - zo) <= 1e-12 * np.linalg.norm(zo)
+
+
+@pytest.mark.parametrize("name,scale", [("G1", 1.0), ("G2", 0.3), ("G4", 0.21)])
+def test_precond_fp32_cycle_error_bound(B, ora, name, scale):
+    # FP32 storage and accumulation: error vs the FP64 oracle stated as 1e-5 relative
+    c = P.config(name, scale)
+    say(f"precond fp32 {c['name']}")
+    h = B.Hierarchy(c["rowptr"], c["col"], c["val"], c["w"], max_coarse=c["max_coarse"], precision="fp32")
+    ho = ora.Hierarchy(c["rowptr"], c["col"], c["val"], c["w"], max_coarse=c["max_coarse"])
+    r = P.uniform_rhs(c["n"], 12)
+    z = h.precond(r).cpu().numpy()
+    zo = ho.vcycle(r)
+    assert np.linalg.norm(z - zo) <= 1e-5 * np.linalg.norm(zo)
+
+
+SOLVE_CASES = [("G1", 1.0), ("G2", 0.3), ("G3", 0.2), ("G4", 0.21), ("G2", 1.0)]
+
+
+@pytest.mark.parametrize("name,scale", SOLVE_CASES)
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_solve_parity(B, ora, name, scale, precision):
+    c = P.config(name, scale)
+    say(f"solve {precision} {c['name']}")
+    h = B.Hierarchy(c["rowptr"], c["col"], c["val"], c["w"], max_coarse=c["max_coarse"], precision=precision)
+    x = h.solve(c["b"], tol=c["tol"]).cpu().numpy()
+    inf = h.info()
+    A = sp.csr_matrix((c["val"], c["col"], c["rowptr"]), shape=(c["n"], c["n"]))
+    rel = np.linalg.norm(c["b"] - A @ x) / np.linalg.norm(c["b"])
+    assert rel <= c["tol"], rel
+    assert abs(inf["relres"] - rel) <= 1e-3 * rel + 1e-15
+    ho = ora.Hierarchy(c["rowptr"], c["col"], c["val"], c["w"], max_coarse=c["max_coarse"])
+    xo, io = ho.solve(c["b"], tol=c["tol"])
+    if precision == "fp64":
+        assert abs(inf["iters"] - io["iters"]) <= 1, (inf["iters"], io["iters"])
+    else:
+        # FP32 cycle: a perturbed preconditioner; stated bound on extra iterations
+        assert inf["iters"] <= io["iters"] + max(2, io["iters"] // 5), (inf["iters"], io["iters"])
+    say(f"solve {precision} {c['name']} iters gpu={inf['iters']} oracle={io['iters']} relres={rel:.3e}")
+
+
+def test_solve_edge_cases(B):
+    c = P.config("G1", 0.5)
+    h = B.Hierarchy(c["rowptr"], c["col"], c["val"], max_coarse=c["max_coarse"], itmax=1)
+    say("solve zero rhs")
+    x = h.solve(np.zeros(c["n"]))
+    assert not x.any().item() and h.info()["iters"] == 0
+    say("solve itmax=1")
+    x = h.solve(c["b"], tol=1e-12, allow_maxit=True)
+    assert h.info()["status"] == B.BCM_MAXIT and h.info()["iters"] == 1
+    with pytest.raises(B.BcmError):
+        h.solve(c["b"], tol=1e-12)
+    say("solve with exact initial guess")
+    h2 = B.Hierarchy(c["rowptr"], c["col"], c["val"], max_coarse=c["max_coarse"])
+    x = h2.solve(c["b"], tol=1e-10)
+    x2 = h2.solve(c["b"], x0=x, tol=1e-8)
+    assert h2.info()["iters"] == 0 and np.array_equal(x.cpu().numpy(), x2.cpu().numpy())
+
+
+def test_single_level_and_tiny(B, ora):
+    rp, ci, va = P.laplace1d(7)
+    say("single level n=7")
+    h = B.Hierarchy(rp, ci, va, max_coarse=100)
+    ho = ora.Hierarchy(rp, ci, va, np.ones(7), max_coarse=100)
+    assert h.info()["nl"] == 1
+    r = P.uniform_rhs(7, 1)
+    assert np.allclose(h.precond(r).cpu().numpy(), ho.vcycle(r), rtol=1e-13, atol=1e-15)
+    x = h.solve(r, tol=1e-10).cpu().numpy()
+    assert np.allclose(x, np.linalg.solve(sp.csr_matrix((va, ci, rp)).toarray(), r), rtol=1e-8)
+    say("n=1")
+    h1 = B.Hierarchy(np.array([0, 1]), np.array([0]), np.array([3.0]))
+    assert np.allclose(h1.solve(np.array([6.0]), tol=1e-12).cpu().numpy(), [2.0])
+
+
+def test_large_coarsest_level_global_sweeps(B, ora):
+    # coarsest level above the one-workgroup LDS bound: global Jacobi sweeps
+    c = P.config("G2", 0.4)  # 40^3 -> 16000 rows after one double-pairwise level
+    say(f"large coarsest {c['name']} n={c['n']}")
+    h = B.Hierarchy(c["rowptr"], c["col"], c["val"], max_coarse=20000)
+    ho = ora.Hierarchy(c["rowptr"], c["col"], c["val"], c["w"], max_coarse=20000)
+    assert h.info()["n"][-1] > 8192
+    r = P.uniform_rhs(c["n"], 3)
+    z, zo = h.precond(r).cpu().numpy(), ho.vcycle(r)
+    assert np.linalg.norm(z - zo) <= 1e-12 * np.linalg.norm(zo)
+
+
+def test_invalid_inputs_rejected(B):
+    rp, ci, va = P.poisson2d(6)
+    n = 36
+    bad = []
+    v = va.copy(); v[5] = np.nan; bad.append(("nan", rp, ci, v, None))
+    v = va.copy(); v[0] = -4.0; bad.append(("diag<=0", rp, ci, v, None))
+    v = va.copy(); v[1] = -0.5; bad.append(("asym", rp, ci, v, None))
+    c2 = ci.copy(); c2[1], c2[2] = c2[2], c2[1]; bad.append(("unsorted", rp, c2, va, None))
+    c3 = ci.copy(); c3[3] = 99; bad.append(("col range", rp, c3, va, None))
+    r2 = rp.copy(); r2[4] = r2[5] + 1; bad.append(("rowptr", r2, ci, va, None))
+    w = np.ones(n); w[7] = 0.0; bad.append(("w=0", rp, ci, va, w))
+    for name, a, b_, c_, w_ in bad:
+        say(f"invalid input {name}")
+        with pytest.raises(B.BcmError) as e:
+            B.Hierarchy(a, b_, c_, w_)
+        assert e.value.code == B.BCM_EINVAL
+
+
+def test_indefinite_matrix_breakdown(B):
+    rp, ci, va = P.poisson2d(8)
+    v = va.copy()
+    v[np.repeat(np.arange(64), np.diff(rp)) == ci] = 0.6  # diagonal too small: indefinite
+    say("indefinite")
+    try:
+        h = B.Hierarchy(rp, ci, v, max_coarse=100)
+    except B.BcmError as e:  # a coarse level may already fail the s.p.d. checks
+        assert e.code == B.BCM_EINVAL
+        return
+    with pytest.raises(B.BcmError) as e:
+        h.solve(P.uniform_rhs(64, 0), tol=1e-10)
+    assert e.value.code in (B.BCM_EBREAKDOWN,)
