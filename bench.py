@@ -27,9 +27,10 @@ sys.path.insert(0, ROOT)
 
 METRIC = "setup+solve s to rel-res 1e-8 (Mdof/s, HBM %), FP32-cycle vs FP64 AMG-FCG"
 HBM_PEAK_GBS = 8000.0
-CLASSES = ["down0", "up0", "spmv_dots", "update", "coarse"]
-KERNEL_OF_CLASS = {"down0": "k_down", "up0": "k_up", "spmv_dots": "k_spmv_dots", "update": "k_update",
-                   "coarse": "levels>=1 cycle kernels"}
+CLASSES = ["down0", "up0", "spmv_dots", "update", "coarse", "mid"]
+SINGLE_KERNEL = ["down0", "up0", "spmv_dots", "update", "coarse"]  # one launch per iteration
+KERNEL_OF_CLASS = {"down0": "k_down_seq (finest level)", "up0": "k_up (finest level)",
+                   "spmv_dots": "k_spmv_dots", "update": "k_update", "coarse": "k_coarse_dense"}
 
 
 def log(msg):
@@ -85,7 +86,7 @@ def main():
             if prec == "fp32":
                 for k, (nl_, ms, by) in prof.items():
                     share[k] += ms
-    dom = max(share, key=share.get)
+    dom = max(SINGLE_KERNEL, key=share.get)
     log(f"event share of solve kernels (fp32 cycle, ms): {share}; dominant {dom}")
 
     results = {}
@@ -125,7 +126,7 @@ def main():
         t = json.load(open(tpath))
         if t.get("solve_hip_sha256") == hashlib.sha256(src).hexdigest() and dom in t.get("bytes_per_launch", {}):
             traffic = t["bytes_per_launch"][dom]
-    roofline = {"bound": "hbm", "kernel": KERNEL_OF_CLASS[dom] + " (finest level)" if dom != "coarse" else KERNEL_OF_CLASS[dom],
+    roofline = {"bound": "hbm", "kernel": KERNEL_OF_CLASS[dom],
                 "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": traffic,
                 "algorithmic_bytes_per_launch": (by / l_) if l_ else None,

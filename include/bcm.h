@@ -208,7 +208,8 @@ enum {
     BCM_PROF_CYCLE_UP0 = 2,    /* finest-level prolongation + post-smooth */
     BCM_PROF_SPMV_DOTS = 4,    /* v = A w fused with the three dot products */
     BCM_PROF_UPDATE = 8,       /* the four fused vector updates + ||r||^2 */
-    BCM_PROF_CYCLE_COARSE = 16 /* every kernel of levels >= 1 */
+    BCM_PROF_CYCLE_COARSE = 16, /* the coarsest-level solve */
+    BCM_PROF_CYCLE_MID = 32     /* every cycle kernel of levels 1 .. nl - 2 (several per cycle) */
 };
 
 /*

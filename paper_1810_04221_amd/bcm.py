@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(HERE, "libbcm.so")
 
 BCM_OK, BCM_MAXIT, BCM_EINVAL, BCM_EBREAKDOWN, BCM_ENOMEM, BCM_EHIP = 0, 1, -1, -2, -3, -4
 BCM_FP64, BCM_FP32_CYCLE = 0, 1
-PROF = {"down0": 1, "up0": 2, "spmv_dots": 4, "update": 8, "coarse": 16}
+PROF = {"down0": 1, "up0": 2, "spmv_dots": 4, "update": 8, "coarse": 16, "mid": 32}
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
 DEALLOC_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_size_t, C.c_void_p)

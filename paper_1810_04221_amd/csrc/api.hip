@@ -361,6 +361,15 @@ int build_hierarchy(bcm_handle *h, const bcm_csr *Ain, const double *win) {
             NOMEM(L.b && L.x);
         }
     }
+    {
+        // coarsest level: precompute the sweep operator when it is small
+        Level &C = h->lv[h->nl - 1];
+        if (C.A.n <= kCoarseDense) {
+            C.S = h->persist.get_n<double>((size_t)C.A.n * C.A.n);
+            NOMEM(C.S);
+            launch_coarse_build(s, C, P.coarse_sweeps, C.S);
+        }
+    }
     if (h->lv[h->nl - 1].A.n > kCoarseLds) {
         h->ctmp[0] = h->persist.get_n<double>(h->lv[h->nl - 1].A.n);
         h->ctmp[1] = h->persist.get_n<double>(h->lv[h->nl - 1].A.n);
@@ -375,9 +384,7 @@ int build_hierarchy(bcm_handle *h, const bcm_csr *Ain, const double *win) {
     h->scal = h->persist.get_n<double>(16);
     h->red_blocks = reduce_blocks(n);
     h->partials = h->persist.get_n<double>(4 * (size_t)h->red_blocks);
-    h->counter = h->persist.get_n<unsigned>(16);
-    NOMEM(h->r && h->w && h->d && h->v && h->q && h->scal && h->partials && h->counter);
-    launch_fill_i32(s, 16, (int *)h->counter, 0);
+    NOMEM(h->r && h->w && h->d && h->v && h->q && h->scal && h->partials);
     launch_fill_i32(s, 32, (int *)h->scal, 0);
     launch_fill_i32(s, 2 * (size_t)n, (int *)h->q, 0);
     launch_fill_i32(s, 2 * (size_t)n, (int *)h->d, 0);
@@ -473,7 +480,7 @@ void vcycle(bcm_handle *h, Prof &pf, const double *rin, double *wout) {
     }
     for (int k = 0; k < nl - 1; ++k) {
         Level &L = h->lv[k];
-        const int cls = k == 0 ? 0 : 4;
+        const int cls = k == 0 ? 0 : 5;
         int e = pf.begin(cls);
         launch_down(s, L, fp32, k == 0 ? (const void *)rin : L.b, h->lv[k + 1].b, (k == 0 || !fp32) ? 1 : 0);
         pf.end(cls, e, bytes_down(h, k));
@@ -485,7 +492,7 @@ void vcycle(bcm_handle *h, Prof &pf, const double *rin, double *wout) {
     }
     for (int k = nl - 2; k >= 0; --k) {
         Level &L = h->lv[k];
-        const int cls = k == 0 ? 1 : 4;
+        const int cls = k == 0 ? 1 : 5;
         const int f64io = (k == 0 || !fp32) ? 1 : 0;
         int e = pf.begin(cls);
         launch_up(s, L, fp32, k == 0 ? (const void *)rin : L.b, h->lv[k + 1].x, k == 0 ? (void *)wout : L.x, f64io,
@@ -501,9 +508,9 @@ int fcg(bcm_handle *h, const double *b, double *x, double tol) {
     Prof pf{h, h->prm.profile};
     h->ev_pairs.clear();
     h->ev_bytes.clear();
-    double hs[8];
-    launch_resid(s, L0, nb, b, x, h->r, h->partials, h->counter, h->scal);
-    int rc = read_back(s, h->scal, 8 * sizeof(double), hs);
+    double hs[16];
+    launch_resid(s, L0, nb, b, x, h->r, h->partials, h->scal);
+    int rc = read_back(s, h->scal, 10 * sizeof(double), hs);
     if (rc) return rc;
     const double bb = hs[5];
     int it = 0, status = BCM_OK;
@@ -528,14 +535,14 @@ int fcg(bcm_handle *h, const double *b, double *x, double tol) {
         for (;;) {
             vcycle(h, pf, h->r, h->w);
             int e = pf.begin(2);
-            launch_spmv_dots(s, L0, nb, h->w, h->r, h->q, h->v, h->partials, h->counter, h->scal);
+            launch_spmv_dots(s, L0, nb, first, h->w, h->r, h->q, h->v, h->partials, h->scal);
             pf.end(2, e, bytes_spmv_dots(h));
             e = pf.begin(3);
-            launch_update(s, n, nb, first, h->w, h->v, h->d, x, h->q, h->r, h->partials, h->counter, h->scal);
+            launch_update(s, n, nb, first, h->w, h->v, h->d, x, h->q, h->r, h->partials, h->scal);
             pf.end(3, e, bytes_update(h));
             first = 0;
             ++it;
-            rc = read_back(s, h->scal, 8 * sizeof(double), hs);
+            rc = read_back(s, h->scal, 10 * sizeof(double), hs);
             if (rc) return rc;
             if (hs[6] != 0.0) {
                 h->iters = it; h->status = BCM_EBREAKDOWN;
@@ -546,8 +553,8 @@ int fcg(bcm_handle *h, const double *b, double *x, double tol) {
             if (!(relres > tol) || it >= itmax) break;
         }
         // true residual b - A x
-        launch_resid(s, L0, nb, b, x, h->r, h->partials, h->counter, h->scal);
-        rc = read_back(s, h->scal, 8 * sizeof(double), hs);
+        launch_resid(s, L0, nb, b, x, h->r, h->partials, h->scal);
+        rc = read_back(s, h->scal, 10 * sizeof(double), hs);
         if (rc) return rc;
         relres = std::sqrt(hs[4]) / bn;
         if (relres <= tol) { status = BCM_OK; break; }
@@ -739,7 +746,7 @@ int bcm_match(const bcm_csr *A, const double *w, const bcm_params *p, int32_t *m
 }
 
 int bcm_profile(const bcm_handle *h, int32_t kclass, int64_t *launches, double *ms, double *bytes) {
-    if (!h || kclass <= 0 || (kclass & (kclass - 1)) || kclass > BCM_PROF_CYCLE_COARSE) {
+    if (!h || kclass <= 0 || (kclass & (kclass - 1)) || kclass > BCM_PROF_CYCLE_MID) {
         set_error("bad handle or kernel class");
         return BCM_EINVAL;
     }

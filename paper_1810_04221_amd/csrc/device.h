@@ -61,39 +61,17 @@ __device__ __forceinline__ void block_sum(double (&v)[K], double *lds) {
     __syncthreads();
 }
 
-// Grid-wide deterministic sums: every block stores its K partial sums; the last
-// block to arrive adds all partials in block order, writes out[0..K) and
-// resets the arrival counter.  Returns true in the last block (all threads).
-// The result depends only on the grid and block sizes, never on timing.
+// Block partial sums: thread 0 of every block stores the block's K sums at
+// partials[k * gridDim.x + blockIdx.x].  No inter-block synchronisation: a
+// following single-block kernel adds the partials in block order, so the
+// result depends only on the grid and block sizes, never on timing.
 template <int K>
-__device__ __forceinline__ bool grid_sum(double (&v)[K], double *partials, unsigned *counter,
-                                         double *out) {
+__device__ __forceinline__ void block_partials(double (&v)[K], double *partials) {
     __shared__ double lds[K * 16];
-    __shared__ int last;
     block_sum<K>(v, lds);
-    if (threadIdx.x == 0) {
+    if (threadIdx.x == 0)
 #pragma unroll
         for (int k = 0; k < K; ++k) partials[(size_t)k * gridDim.x + blockIdx.x] = v[k];
-        __threadfence();
-        const unsigned t = atomicAdd(counter, 1u);
-        last = (t == gridDim.x - 1);
-    }
-    __syncthreads();
-    if (!last) return false;
-    __threadfence();
-    double s[K];
-#pragma unroll
-    for (int k = 0; k < K; ++k) s[k] = 0.0;
-    for (int b = threadIdx.x; b < (int)gridDim.x; b += blockDim.x)
-#pragma unroll
-        for (int k = 0; k < K; ++k) s[k] += load_agent(&partials[(size_t)k * gridDim.x + b]);
-    block_sum<K>(s, lds);
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int k = 0; k < K; ++k) out[k] = s[k];
-        *counter = 0u;
-    }
-    return true;
 }
 
 }  // namespace bcm

@@ -12,7 +12,8 @@
 namespace bcm {
 
 constexpr int kMaxLevels = 64;
-constexpr int kCoarseLds = 8192;  // largest coarsest level solved inside one workgroup
+constexpr int kCoarseLds = 8192;   // largest coarsest level solved inside one workgroup
+constexpr int kCoarseDense = 1024; // largest coarsest level applied as a precomputed dense operator
 
 // Error flags raised by the validation kernel.
 enum : int {
@@ -72,6 +73,7 @@ struct Level {
     int mstride = 0;
     int *mem = nullptr;
     void *b = nullptr, *x = nullptr;  // cycle vectors for k >= 1 (cycle precision)
+    double *S = nullptr;  // coarsest level only: dense sweep operator (n <= kCoarseDense)
 };
 
 struct ProfClass {
@@ -89,12 +91,11 @@ struct bcm_handle {
     bcm::Arena persist, scratch;
     // flexible CG vectors (float64, n of the finest level)
     double *r = nullptr, *w = nullptr, *d = nullptr, *v = nullptr, *q = nullptr;
-    // device scalars: [0] alpha [1] beta [2] gamma [3] rho_prev [4] ||r||^2 [5] ||b||^2
-    // [6] breakdown flag [7] spare
+    // device scalars: [0] alpha [1] beta [2] gamma [3] rho of the last step [4] ||r||^2
+    // [5] ||b||^2 [6] breakdown flag [8] gamma_i / rho_{i-1} [9] alpha_i / rho_i
     double *scal = nullptr;
     double *ctmp[2] = {nullptr, nullptr};  // coarsest-level sweep buffers when n > kCoarseLds
     double *partials = nullptr;
-    unsigned *counter = nullptr;
     double *host_scal = nullptr;  // pinned
     int red_blocks = 0;
     double last_tol = 0.0;
@@ -104,7 +105,7 @@ struct bcm_handle {
     std::vector<hipEvent_t> ev_pool;
     std::vector<std::pair<int, int>> ev_pairs;  // (class, event index of the start)
     std::vector<double> ev_bytes;
-    bcm::ProfClass prof[5];
+    bcm::ProfClass prof[6];
 };
 
 namespace bcm {
@@ -149,13 +150,16 @@ void launch_up(hipStream_t s, const Level &L, int fp32, const void *b, const voi
                int b_is_f64, int x_is_f64);
 void launch_coarse(hipStream_t s, const Level &L, int sweeps, const void *b, void *x, int b_f64,
                    int x_f64, void *tmp_a, void *tmp_b);
+// Each of these is a streaming kernel writing block partials plus a one-block
+// finalize kernel that sums them in block order into scal[].
+// S = sum_{t < sweeps} (I - D A)^t D of the coarsest level, column by column
+void launch_coarse_build(hipStream_t s, const Level &L, int sweeps, double *S);
 void launch_resid(hipStream_t s, const Level &L, int nb, const double *b, const double *u, double *r,
-                  double *partials, unsigned *counter, double *scal);
-void launch_spmv_dots(hipStream_t s, const Level &L, int nb, const double *w, const double *r,
-                      const double *q, double *v, double *partials, unsigned *counter, double *scal);
+                  double *partials, double *scal);
+void launch_spmv_dots(hipStream_t s, const Level &L, int nb, int first, const double *w, const double *r,
+                      const double *q, double *v, double *partials, double *scal);
 void launch_update(hipStream_t s, int n, int nb, int first, const double *w, const double *v,
-                   double *d, double *u, double *q, double *r, double *partials, unsigned *counter,
-                   double *scal);
+                   double *d, double *u, double *q, double *r, double *partials, double *scal);
 void launch_sampled_outer(hipStream_t s, const Level &L, const double *lam, const double *x,
                           double *G);
 int reduce_blocks(int n);

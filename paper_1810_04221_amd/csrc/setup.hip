@@ -152,23 +152,41 @@ k_rank(int n, const int *__restrict__ rp, const int *__restrict__ ci, const doub
 __global__ void __launch_bounds__(kBlock)
 k_suitor(int n, const int *__restrict__ rp, const int *__restrict__ ci, const double *__restrict__ c,
          const uint32_t *__restrict__ rk, unsigned long long *ws) {
-    const int u0 = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
-    if (u0 >= n) return;
+    // Highest vertices first: workgroups are dispatched roughly in index order,
+    // and the greedy order settles large indices first on equal weights, so
+    // early proposals are rarely displaced.
+    const int u0 = n - 1 - (int)(blockIdx.x * kBlock + threadIdx.x);
+    if (u0 < 0) return;
     int u = u0;
     for (;;) {
         int best = -1;
         double bc = 0.0;
         unsigned long long bkey = 0ull;
         const int e = rp[u + 1];
-        for (int q = rp[u]; q < e; ++q) {
-            const int vtx = ci[q];
-            if (vtx == u) continue;
-            const double cq = c[q];
-            if (!(cq > 0.0 && cq < INFINITY)) continue;
-            if (best >= 0 && (cq < bc || (cq == bc && vtx < best))) continue;
-            const unsigned long long key =
-                ((unsigned long long)rk[q] << 32) | (unsigned long long)(unsigned)(u + 1);
-            if (key > load_agent(&ws[vtx])) { best = vtx; bc = cq; bkey = key; }
+        // the row is scanned in chunks of 8 whose ws[] loads are all in flight together
+        for (int q0 = rp[u]; q0 < e; q0 += 8) {
+            int vv[8];
+            double cc[8];
+            unsigned long long kk[8], cur[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const int q = q0 + k;
+                const bool in = q < e;
+                const int qs = in ? q : q0;
+                vv[k] = in ? ci[qs] : u;
+                cc[k] = c[qs];
+                kk[k] = ((unsigned long long)rk[qs] << 32) | (unsigned long long)(unsigned)(u + 1);
+            }
+#pragma unroll
+            for (int k = 0; k < 8; ++k) cur[k] = load_agent(&ws[vv[k]]);
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const int vtx = vv[k];
+                const double cq = cc[k];
+                const bool elig = vtx != u && cq > 0.0 && cq < INFINITY && kk[k] > cur[k];
+                const bool better = best < 0 || cq > bc || (cq == bc && vtx > best);
+                if (elig && better) { best = vtx; bc = cq; bkey = kk[k]; }
+            }
         }
         if (best < 0) break;
         const unsigned long long old = atomicMax(&ws[best], bkey);

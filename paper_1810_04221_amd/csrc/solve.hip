@@ -30,18 +30,78 @@ void with_G(int G, Fn &&fn) {
 
 inline int blocks_for(long long threads) { return (int)((threads + kBlock - 1) / kBlock); }
 
+// R rows per group of G lanes.  All loads of the first pass over the R rows
+// are issued before any result is used (out-of-row lanes read entry beg[k] and
+// discard it), which keeps R times more memory requests in flight per lane than
+// one row at a time.  Rows longer than G finish in a second loop.
+// s[k] = sum_q a[q] * f(ci[q]) over row rows[k] (rows[k] < 0: empty).
+template <int G, int R, typename V, typename F>
+__device__ __forceinline__ void rows_dot(const int *__restrict__ rp, const int *__restrict__ ci,
+                                         const V *__restrict__ a, const int (&rows)[R], V (&s)[R], F f) {
+    const int lane = threadIdx.x % G;
+    int beg[R], end[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        const int i = rows[k] < 0 ? 0 : rows[k];
+        beg[k] = rp[i];
+        end[k] = rows[k] < 0 ? beg[k] : rp[i + 1];
+    }
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        const int q = beg[k] + lane;
+        const bool in = q < end[k];
+        const int qs = in ? q : (end[k] > beg[k] ? beg[k] : 0);
+        const int j = ci[qs];
+        const V t = a[qs] * f(j);
+        s[k] = in ? t : V(0);
+    }
+#pragma unroll
+    for (int k = 0; k < R; ++k)
+        for (int q = beg[k] + lane + G; q < end[k]; q += G) s[k] += a[q] * f(ci[q]);
+#pragma unroll
+    for (int k = 0; k < R; ++k) s[k] = group_sum<G>(s[k]);
+}
+
 // ----------------------------------------------------------------------------
 // Down leg of the cycle at level k (Algorithm 1, zero initial guess):
 //   x = x + M^{-1}(b - A x) with x = 0   ->  x_j = dinv_j * b_j
 //   b_c[E] = sum_{i in E} p_i (b_i - sum_j a_ij x_j)      (restriction)
-// One group per coarse aggregate E walks its members in ascending order; x is
-// never stored, it is recomputed from b and dinv where it is gathered.
+// x is never stored: it is recomputed from b and dinv where it is gathered.
+// One group of G lanes per aggregate; the member rows are processed together
+// (k_down_seq, S = 1, 2 or 4 members) or one after the other (k_down_loop).
 // ----------------------------------------------------------------------------
+// S members (template) of one aggregate, all rows in flight at once; summed
+// in ascending member order.
+template <int G, int S, typename V, typename VB>
+__global__ void __launch_bounds__(kBlock)
+k_down_seq(int nc, const int *__restrict__ mem, const int *__restrict__ rp, const int *__restrict__ ci,
+           const V *__restrict__ a, const V *__restrict__ dinv, const V *__restrict__ p,
+           const VB *__restrict__ b, V *__restrict__ bc) {
+    const int lane = threadIdx.x % G;
+    int E = (xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x) / G;
+    const bool live = E < nc;
+    if (!live) E = nc - 1;
+    int rows[S];
+#pragma unroll
+    for (int t = 0; t < S; ++t) rows[t] = mem[(size_t)E * S + t];
+    V s[S];
+    rows_dot<G, S, V>(rp, ci, a, rows, s, [&](int j) { return dinv[j] * (V)b[j]; });
+    V acc = V(0);
+#pragma unroll
+    for (int t = 0; t < S; ++t) {
+        const int i = rows[t] < 0 ? 0 : rows[t];
+        const V c = p[i] * ((V)b[i] - s[t]);
+        acc += rows[t] < 0 ? V(0) : c;
+    }
+    if (lane == 0 && live) bc[E] = acc;
+}
+
+// Any number of members (wide composed aggregates): one member row at a time.
 template <int G, typename V, typename VB>
 __global__ void __launch_bounds__(kBlock)
-k_down(int nc, int mstride, const int *__restrict__ mem, const int *__restrict__ rp,
-       const int *__restrict__ ci, const V *__restrict__ a, const V *__restrict__ dinv,
-       const V *__restrict__ p, const VB *__restrict__ b, V *__restrict__ bc) {
+k_down_loop(int nc, int mstride, const int *__restrict__ mem, const int *__restrict__ rp,
+            const int *__restrict__ ci, const V *__restrict__ a, const V *__restrict__ dinv,
+            const V *__restrict__ p, const VB *__restrict__ b, V *__restrict__ bc) {
     const int lane = threadIdx.x % G;
     const int E = (xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x) / G;
     if (E >= nc) return;
@@ -56,8 +116,7 @@ k_down(int nc, int mstride, const int *__restrict__ mem, const int *__restrict__
             s += a[q] * (dinv[j] * (V)b[j]);
         }
         s = group_sum<G>(s);
-        const V r = (V)b[i] - s;
-        acc += p[i] * r;
+        acc += p[i] * ((V)b[i] - s);
     }
     if (lane == 0) bc[E] = acc;
 }
@@ -68,66 +127,113 @@ k_down(int nc, int mstride, const int *__restrict__ mem, const int *__restrict__
 //   x_j = dinv_j b_j + p_j xc[agg_j]          (pre-smoothed x plus P x_c)
 //   x_i <- x_i + dinv_i (b_i - sum_j a_ij x_j)
 // ----------------------------------------------------------------------------
-template <int G, typename V, typename VB, typename VX>
+template <int G, int R, typename V, typename VB, typename VX>
 __global__ void __launch_bounds__(kBlock)
 k_up(int n, const int *__restrict__ rp, const int *__restrict__ ci, const V *__restrict__ a,
      const V *__restrict__ dinv, const V *__restrict__ p, const int *__restrict__ agg,
      const VB *__restrict__ b, const V *__restrict__ xc, VX *__restrict__ x) {
+    constexpr int NG = kBlock / G;
     const int lane = threadIdx.x % G;
-    const int i = (xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x) / G;
-    if (i >= n) return;
-    V s = V(0);
-    const int e = rp[i + 1];
-    for (int q = rp[i] + lane; q < e; q += G) {
-        const int j = ci[q];
-        const V xj = dinv[j] * (V)b[j] + p[j] * xc[agg[j]];
-        s += a[q] * xj;
-    }
-    s = group_sum<G>(s);
+    const int base = xcd_block(blockIdx.x, gridDim.x) * NG * R + threadIdx.x / G;
+    int rows[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) rows[k] = base + k * NG < n ? base + k * NG : -1;
+    V s[R];
+    rows_dot<G, R, V>(rp, ci, a, rows, s, [&](int j) { return dinv[j] * (V)b[j] + p[j] * xc[agg[j]]; });
     if (lane == 0) {
-        const V bi = (V)b[i];
-        const V di = dinv[i];
-        const V xi = di * bi + p[i] * xc[agg[i]];
-        x[i] = (VX)(xi + di * (bi - s));
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            const int i = rows[k];
+            if (i < 0) continue;
+            const V bi = (V)b[i];
+            const V di = dinv[i];
+            const V xi = di * bi + p[i] * xc[agg[i]];
+            x[i] = (VX)(xi + di * (bi - s[k]));
+        }
     }
 }
 
 // ----------------------------------------------------------------------------
 // Coarsest level: `sweeps` l1-Jacobi sweeps from zero in float64, inside one
-// workgroup with x held in LDS (n <= 8192).  Each sweep computes all new values
-// from the old x before any is written back, i.e. plain Jacobi.
+// workgroup with x in LDS (n <= 8192).  When the level's matrix also fits, it
+// is staged in LDS once so the sweeps never touch global memory.  Each row is
+// owned by lpr lanes (the largest power of two <= 16 with n * lpr <= 1024),
+// so a sweep costs a few LDS round trips.  Each sweep computes all new values
+// from the old x before any is written back (Jacobi).
 // ----------------------------------------------------------------------------
+constexpr int kCoarseLdsBytes = 65536;
+
+// unit_rhs: the right-hand side is the unit vector e_j with j = blockIdx.x and
+// the result goes to column j of x (n x n, column-major): this builds the dense
+// matrix of the whole sweep operator, one workgroup per column.
 template <typename VB, typename VX>
 __global__ void __launch_bounds__(1024)
-k_coarse(int n, const int *__restrict__ rp, const int *__restrict__ ci, const double *__restrict__ a,
-         const double *__restrict__ dinv, const VB *__restrict__ b, VX *__restrict__ x, int sweeps) {
-    __shared__ double xs[kCoarseLds];
+k_coarse(int n, int nnz, const int *__restrict__ rp_g, const int *__restrict__ ci_g,
+         const double *__restrict__ a_g, const double *__restrict__ dinv_g, const VB *__restrict__ b,
+         VX *__restrict__ x, int sweeps, int unit_rhs) {
+    __shared__ __align__(16) char lds[kCoarseLdsBytes];
     constexpr int R = kCoarseLds / 1024;
+    double *xs = reinterpret_cast<double *>(lds);
+    const size_t stage = (size_t)n * 16 + (size_t)nnz * 12 + (size_t)(n + 1) * 4;
+    const bool staged = stage <= (size_t)kCoarseLdsBytes;
+    const int *rp = rp_g, *ci = ci_g;
+    const double *a = a_g, *dinv = dinv_g;
+    if (staged) {
+        double *ds = xs + n, *as = ds + n;
+        int *rps = reinterpret_cast<int *>(as + nnz), *cis = rps + n + 1;
+        for (int i = threadIdx.x; i < n; i += blockDim.x) ds[i] = dinv_g[i];
+        for (int i = threadIdx.x; i <= n; i += blockDim.x) rps[i] = rp_g[i];
+        for (int q = threadIdx.x; q < nnz; q += blockDim.x) { as[q] = a_g[q]; cis[q] = ci_g[q]; }
+        rp = rps; ci = cis; a = as; dinv = ds;
+    }
+    int lpr = 1;
+    while (lpr < 16 && n * (lpr * 2) <= (int)blockDim.x) lpr *= 2;
+    const int lane = threadIdx.x % lpr, grp = threadIdx.x / lpr, ngrp = blockDim.x / lpr;
+    double bl[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        const int i = grp + k * ngrp;
+        bl[k] = i < n ? (unit_rhs ? (i == (int)blockIdx.x ? 1.0 : 0.0) : (double)b[i]) : 0.0;
+    }
+    if (unit_rhs) x += (size_t)blockIdx.x * n;
     for (int i = threadIdx.x; i < n; i += blockDim.x) xs[i] = 0.0;
     __syncthreads();
     for (int t = 0; t < sweeps; ++t) {
         double xn[R];
 #pragma unroll
         for (int k = 0; k < R; ++k) {
-            const int i = threadIdx.x + k * blockDim.x;
+            const int i = grp + k * ngrp;
             xn[k] = 0.0;
             if (i < n) {
                 double s = 0.0;
                 const int e = rp[i + 1];
-                for (int q = rp[i]; q < e; ++q) s = s + a[q] * xs[ci[q]];
-                const double r = (double)b[i] - s;
-                xn[k] = xs[i] + dinv[i] * r;
+                for (int q = rp[i] + lane; q < e; q += lpr) s = s + a[q] * xs[ci[q]];
+                for (int o = lpr / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, lpr);
+                xn[k] = xs[i] + dinv[i] * (bl[k] - s);
             }
         }
         __syncthreads();
 #pragma unroll
         for (int k = 0; k < R; ++k) {
-            const int i = threadIdx.x + k * blockDim.x;
-            if (i < n) xs[i] = xn[k];
+            const int i = grp + k * ngrp;
+            if (i < n && lane == 0) xs[i] = xn[k];
         }
         __syncthreads();
     }
     for (int i = threadIdx.x; i < n; i += blockDim.x) x[i] = (VX)xs[i];
+}
+
+// Coarsest level with its sweep operator S precomputed (symmetric, n <= 1024):
+// x = S b.  One wave per row i reads row i of S contiguously.
+template <typename VB, typename VX>
+__global__ void __launch_bounds__(64)
+k_coarse_dense(int n, const double *__restrict__ S, const VB *__restrict__ b, VX *__restrict__ x) {
+    const int i = blockIdx.x, lane = threadIdx.x;
+    const double *row = S + (size_t)i * n;
+    double s = 0.0;
+    for (int j = lane; j < n; j += 64) s += row[j] * (double)b[j];
+    s = group_sum<64>(s);
+    if (lane == 0) x[i] = (VX)s;
 }
 
 // One global l1-Jacobi sweep (coarsest levels larger than the LDS bound).
@@ -155,80 +261,125 @@ __global__ void k_store(int n, const double *__restrict__ src, VX *__restrict__ 
 
 // ----------------------------------------------------------------------------
 // Flexible CG kernels (Algorithm 3).  Fixed grid of nb blocks with a
-// grid-stride loop over row groups; reductions are deterministic for a fixed
-// grid (block partials summed in block order by the last block).
-// scal: [0] alpha [1] beta [2] gamma [3] rho_{i-1} [4] ||r||^2 [5] ||b||^2
-//       [6] breakdown flag
+// grid-stride loop over row groups; every block stores its partial sums and a
+// one-block finalize kernel adds them in block order (deterministic).
+// scal: [0] alpha [1] beta [2] gamma [3] rho (of the last step) [4] ||r||^2
+//       [5] ||b||^2 [6] breakdown flag [8] gamma_i / rho_{i-1} [9] alpha_i / rho_i
 // ----------------------------------------------------------------------------
 
-// r = b - A u, ||r||^2 -> scal[4], ||b||^2 -> scal[5]
+constexpr int kRows = 4;  // rows per lane group in the streaming row kernels
+
+// r = b - A u; partials of ||r||^2 and ||b||^2
 template <int G>
 __global__ void __launch_bounds__(kBlock)
 k_resid(int n, const int *__restrict__ rp, const int *__restrict__ ci, const double *__restrict__ a,
         const double *__restrict__ b, const double *__restrict__ u, double *__restrict__ r,
-        double *partials, unsigned *counter, double *scal) {
-    constexpr int NG = kBlock / G;
+        double *__restrict__ partials) {
+    constexpr int NG = kBlock / G, R = kRows;
     const int lane = threadIdx.x % G;
     const int blk = xcd_block(blockIdx.x, gridDim.x);
     double acc[2] = {0.0, 0.0};
-    for (int i = blk * NG + threadIdx.x / G; i < n; i += gridDim.x * NG) {
-        double s = 0.0;
-        const int e = rp[i + 1];
-        for (int q = rp[i] + lane; q < e; q += G) s += a[q] * u[ci[q]];
-        s = group_sum<G>(s);
+    for (int base = blk * NG * R + threadIdx.x / G; base < n; base += gridDim.x * NG * R) {
+        int rows[R];
+#pragma unroll
+        for (int k = 0; k < R; ++k) rows[k] = base + k * NG < n ? base + k * NG : -1;
+        double s[R];
+        rows_dot<G, R, double>(rp, ci, a, rows, s, [&](int j) { return u[j]; });
         if (lane == 0) {
-            const double bi = b[i];
-            const double ri = bi - s;
-            r[i] = ri;
-            acc[0] += ri * ri;
-            acc[1] += bi * bi;
+#pragma unroll
+            for (int k = 0; k < R; ++k) {
+                if (rows[k] < 0) continue;
+                const double bi = b[rows[k]];
+                const double ri = bi - s[k];
+                r[rows[k]] = ri;
+                acc[0] += ri * ri;
+                acc[1] += bi * bi;
+            }
         }
     }
-    grid_sum<2>(acc, partials, counter, scal + 4);
+    block_partials<2>(acc, partials);
 }
 
-// v = A w with alpha = w.r, beta = w.v, gamma = w.q in the same pass -> scal[0..2]
+// v = A w with partials of alpha = w.r, beta = w.v, gamma = w.q in the same pass
 template <int G>
 __global__ void __launch_bounds__(kBlock)
 k_spmv_dots(int n, const int *__restrict__ rp, const int *__restrict__ ci, const double *__restrict__ a,
             const double *__restrict__ w, const double *__restrict__ r, const double *__restrict__ q,
-            double *__restrict__ v, double *partials, unsigned *counter, double *scal) {
-    constexpr int NG = kBlock / G;
+            double *__restrict__ v, double *__restrict__ partials) {
+    constexpr int NG = kBlock / G, R = kRows;
     const int lane = threadIdx.x % G;
     const int blk = xcd_block(blockIdx.x, gridDim.x);
     double acc[3] = {0.0, 0.0, 0.0};
-    for (int i = blk * NG + threadIdx.x / G; i < n; i += gridDim.x * NG) {
-        double s = 0.0;
-        const int e = rp[i + 1];
-        for (int k = rp[i] + lane; k < e; k += G) s += a[k] * w[ci[k]];
-        s = group_sum<G>(s);
+    for (int base = blk * NG * R + threadIdx.x / G; base < n; base += gridDim.x * NG * R) {
+        int rows[R];
+#pragma unroll
+        for (int k = 0; k < R; ++k) rows[k] = base + k * NG < n ? base + k * NG : -1;
+        double s[R];
+        rows_dot<G, R, double>(rp, ci, a, rows, s, [&](int j) { return w[j]; });
         if (lane == 0) {
-            const double wi = w[i];
-            v[i] = s;
-            acc[0] += wi * r[i];
-            acc[1] += wi * s;
-            acc[2] += wi * q[i];
+#pragma unroll
+            for (int k = 0; k < R; ++k) {
+                const int i = rows[k];
+                if (i < 0) continue;
+                const double wi = w[i];
+                v[i] = s[k];
+                acc[0] += wi * r[i];
+                acc[1] += wi * s[k];
+                acc[2] += wi * q[i];
+            }
         }
     }
-    grid_sum<3>(acc, partials, counter, scal);
+    block_partials<3>(acc, partials);
 }
 
-// The two fused AXPY pairs of Algorithm 3 and ||r||^2:
-//   rho_i = beta - gamma^2 / rho_{i-1}
-//   d = w - (gamma/rho_{i-1}) d ; u += (alpha/rho_i) d
-//   q = v - (gamma/rho_{i-1}) q ; r -= (alpha/rho_i) q
-// first step: rho_0 = beta, d = w, q = v.  On rho <= 0 or not finite nothing is
-// updated and scal[6] = 1.
+// Finalize: sums the block partials in block order, then
+//   mode 0 (residual):  scal[4] = ||r||^2, scal[5] = ||b||^2
+//   mode 1 (dots):      alpha, beta, gamma and the scalars of Algorithm 3:
+//                       rho_i = beta - gamma^2 / rho_{i-1} (first step: beta),
+//                       scal[8] = gamma / rho_{i-1}, scal[9] = alpha / rho_i,
+//                       scal[6] = 1 if rho_i <= 0 or not finite (breakdown)
+//   mode 2 (norm):      scal[4] = ||r||^2
+template <int K>
+__global__ void __launch_bounds__(kBlock) k_finalize(int nb, const double *__restrict__ partials,
+                                                     double *__restrict__ scal, int mode, int first) {
+    __shared__ double lds[K * 16];
+    double s[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) s[k] = 0.0;
+    for (int bk = threadIdx.x; bk < nb; bk += blockDim.x)
+#pragma unroll
+        for (int k = 0; k < K; ++k) s[k] += partials[(size_t)k * nb + bk];
+    block_sum<K>(s, lds);
+    if (threadIdx.x != 0) return;
+    if (mode == 0) {
+        scal[4] = s[0];
+        scal[5] = s[1 % K];
+    } else if (mode == 2) {
+        scal[4] = s[0];
+    } else {
+        const double alpha = s[0], beta = s[1 % K], gamma = s[2 % K];
+        double rho, g;
+        if (first) { rho = beta; g = 0.0; }
+        else { const double rho_prev = scal[3]; rho = beta - gamma * gamma / rho_prev; g = gamma / rho_prev; }
+        const double an = alpha / rho;
+        const bool ok = (rho > 0.0) && isfinite(rho) && isfinite(an) && isfinite(g);
+        scal[0] = alpha;
+        scal[1] = beta;
+        scal[2] = gamma;
+        scal[6] = ok ? 0.0 : 1.0;
+        if (ok) { scal[3] = rho; scal[8] = g; scal[9] = an; }
+    }
+}
+
+// The two fused AXPY pairs of Algorithm 3 and partials of ||r||^2:
+//   d = w - g d ; u += an d ; q = v - g q ; r -= an q   (first step: d = w, q = v)
+// with g = gamma_i / rho_{i-1} and an = alpha_i / rho_i from the finalize step.
 __global__ void __launch_bounds__(kBlock)
 k_update(int n, int first, const double *__restrict__ w, const double *__restrict__ v, double *__restrict__ d,
-         double *__restrict__ u, double *__restrict__ q, double *__restrict__ r, double *partials,
-         unsigned *counter, double *scal) {
-    const double alpha = scal[0], beta = scal[1], gamma = scal[2], rho_prev = scal[3];
-    double rho, g;
-    if (first) { rho = beta; g = 0.0; }
-    else { rho = beta - gamma * gamma / rho_prev; g = gamma / rho_prev; }
-    const double an = alpha / rho;
-    const bool ok = (rho > 0.0) && isfinite(rho) && isfinite(an) && isfinite(g);
+         double *__restrict__ u, double *__restrict__ q, double *__restrict__ r,
+         const double *__restrict__ scal, double *__restrict__ partials) {
+    const bool ok = scal[6] == 0.0;
+    const double g = scal[8], an = scal[9];
     double acc[1] = {0.0};
     if (ok) {
         const int blk = xcd_block(blockIdx.x, gridDim.x);
@@ -245,10 +396,7 @@ k_update(int n, int first, const double *__restrict__ w, const double *__restric
             acc[0] += ri * ri;
         }
     }
-    if (grid_sum<1>(acc, partials, counter, scal + 4) && threadIdx.x == 0) {
-        scal[3] = rho;
-        scal[6] = ok ? 0.0 : 1.0;
-    }
+    block_partials<1>(acc, partials);
 }
 
 // dL/da_ij = -lambda_i x_j on the stored pattern
@@ -264,12 +412,28 @@ k_sampled_outer(int n, const int *__restrict__ rp, const int *__restrict__ ci, c
     for (int q = rp[i] + lane; q < e; q += G) out[q] = -(li * x[ci[q]]);
 }
 
+template <int G, typename V, typename VB>
+void down_dispatch(hipStream_t s, const Level &L, const V *a, const V *dinv, const V *p, const VB *b, V *bc) {
+    const int S = L.mstride;
+    const dim3 grid(blocks_for((long long)L.nc * G));
+    auto seq = [&](auto sc) {
+        constexpr int SS = decltype(sc)::value;
+        hipLaunchKernelGGL((k_down_seq<G, SS, V, VB>), grid, dim3(kBlock), 0, s, L.nc, L.mem, L.A.rp, L.A.ci, a,
+                           dinv, p, b, bc);
+    };
+    if (S == 1) seq(std::integral_constant<int, 1>{});
+    else if (S == 2) seq(std::integral_constant<int, 2>{});
+    else if (S == 4) seq(std::integral_constant<int, 4>{});
+    else
+        hipLaunchKernelGGL((k_down_loop<G, V, VB>), grid, dim3(kBlock), 0, s, L.nc, L.mstride, L.mem, L.A.rp,
+                           L.A.ci, a, dinv, p, b, bc);
+}
+
 template <typename V, typename VB>
 void down_t(hipStream_t s, const Level &L, const V *a, const V *dinv, const V *p, const VB *b, V *bc) {
     with_G(L.G, [&](auto gc) {
         constexpr int g = decltype(gc)::value;
-        hipLaunchKernelGGL((k_down<g, V, VB>), dim3(blocks_for((long long)L.nc * g)), dim3(kBlock), 0, s, L.nc,
-                           L.mstride, L.mem, L.A.rp, L.A.ci, a, dinv, p, b, bc);
+        down_dispatch<g, V, VB>(s, L, a, dinv, p, b, bc);
     });
 }
 
@@ -278,17 +442,22 @@ void up_t(hipStream_t s, const Level &L, const V *a, const V *dinv, const V *p, 
           VX *x) {
     with_G(L.G, [&](auto gc) {
         constexpr int g = decltype(gc)::value;
-        hipLaunchKernelGGL((k_up<g, V, VB, VX>), dim3(blocks_for((long long)L.A.n * g)), dim3(kBlock), 0, s,
-                           L.A.n, L.A.rp, L.A.ci, a, dinv, p, L.agg, b, xc, x);
+        constexpr int R = 2;
+        hipLaunchKernelGGL((k_up<g, R, V, VB, VX>), dim3(blocks_for(((long long)L.A.n * g + R - 1) / R)),
+                           dim3(kBlock), 0, s, L.A.n, L.A.rp, L.A.ci, a, dinv, p, L.agg, b, xc, x);
     });
 }
 
 template <typename VB, typename VX>
 void coarse_t(hipStream_t s, const Level &L, int sweeps, const VB *b, VX *x, double *ta, double *tb) {
     const int n = L.A.n;
+    if (L.S) {
+        hipLaunchKernelGGL((k_coarse_dense<VB, VX>), dim3(n), dim3(64), 0, s, n, L.S, b, x);
+        return;
+    }
     if (n <= kCoarseLds) {
-        hipLaunchKernelGGL((k_coarse<VB, VX>), dim3(1), dim3(1024), 0, s, n, L.A.rp, L.A.ci, L.A.v, L.dinv, b, x,
-                           sweeps);
+        hipLaunchKernelGGL((k_coarse<VB, VX>), dim3(1), dim3(1024), 0, s, n, L.A.nnz, L.A.rp, L.A.ci, L.A.v, L.dinv,
+                           b, x, sweeps, 0);
         return;
     }
     double *xo = ta, *xn = tb;
@@ -338,28 +507,35 @@ void launch_coarse(hipStream_t s, const Level &L, int sweeps, const void *b, voi
     else coarse_t<float, float>(s, L, sweeps, (const float *)b, (float *)x, ta, tb);
 }
 
+void launch_coarse_build(hipStream_t s, const Level &L, int sweeps, double *S) {
+    hipLaunchKernelGGL((k_coarse<double, double>), dim3(L.A.n), dim3(1024), 0, s, L.A.n, L.A.nnz, L.A.rp, L.A.ci,
+                       L.A.v, L.dinv, (const double *)nullptr, S, sweeps, 1);
+}
+
 void launch_resid(hipStream_t s, const Level &L, int nb, const double *b, const double *u, double *r,
-                  double *partials, unsigned *counter, double *scal) {
+                  double *partials, double *scal) {
     with_G(L.G, [&](auto gc) {
         constexpr int g = decltype(gc)::value;
         hipLaunchKernelGGL(k_resid<g>, dim3(nb), dim3(kBlock), 0, s, L.A.n, L.A.rp, L.A.ci, L.A.v, b, u, r,
-                           partials, counter, scal);
+                           partials);
     });
+    hipLaunchKernelGGL(k_finalize<2>, dim3(1), dim3(kBlock), 0, s, nb, partials, scal, 0, 0);
 }
 
-void launch_spmv_dots(hipStream_t s, const Level &L, int nb, const double *w, const double *r, const double *q,
-                      double *v, double *partials, unsigned *counter, double *scal) {
+void launch_spmv_dots(hipStream_t s, const Level &L, int nb, int first, const double *w, const double *r,
+                      const double *q, double *v, double *partials, double *scal) {
     with_G(L.G, [&](auto gc) {
         constexpr int g = decltype(gc)::value;
         hipLaunchKernelGGL(k_spmv_dots<g>, dim3(nb), dim3(kBlock), 0, s, L.A.n, L.A.rp, L.A.ci, L.A.v, w, r, q, v,
-                           partials, counter, scal);
+                           partials);
     });
+    hipLaunchKernelGGL(k_finalize<3>, dim3(1), dim3(kBlock), 0, s, nb, partials, scal, 1, first);
 }
 
 void launch_update(hipStream_t s, int n, int nb, int first, const double *w, const double *v, double *d,
-                   double *u, double *q, double *r, double *partials, unsigned *counter, double *scal) {
-    hipLaunchKernelGGL(k_update, dim3(nb), dim3(kBlock), 0, s, n, first, w, v, d, u, q, r, partials, counter,
-                       scal);
+                   double *u, double *q, double *r, double *partials, double *scal) {
+    hipLaunchKernelGGL(k_update, dim3(nb), dim3(kBlock), 0, s, n, first, w, v, d, u, q, r, scal, partials);
+    hipLaunchKernelGGL(k_finalize<1>, dim3(1), dim3(kBlock), 0, s, nb, partials, scal, 2, 0);
 }
 
 void launch_sampled_outer(hipStream_t s, const Level &L, const double *lam, const double *x, double *G) {
