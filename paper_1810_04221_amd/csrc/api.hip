@@ -163,11 +163,12 @@ int match_sweep(hipStream_t s, Arena &tmp, const Csr &A, const double *w, int ch
     double *diag = tmp.get_n<double>(m);
     int *flags = tmp.get_n<int>(16);
     double *c = tmp.get_n<double>(A.nnz);
-    uint32_t *rk = tmp.get_n<uint32_t>(A.nnz);
+    unsigned long long *cand = tmp.get_n<unsigned long long>(A.nnz);
     unsigned long long *ws = tmp.get_n<unsigned long long>(m);
+    int *pos = tmp.get_n<int>(m);
     int *mate = tmp.get_n<int>(m);
     int *leader = tmp.get_n<int>(m);
-    NOMEM(diag && flags && c && rk && ws && mate && leader);
+    NOMEM(diag && flags && c && cand && ws && pos && mate && leader);
     launch_fill_i32(s, 1, flags, 0);
     launch_validate(s, G, m, A.nnz, A.rp, A.ci, A.v, w, check_sym, diag, flags);
     int f = 0;
@@ -178,9 +179,9 @@ int match_sweep(hipStream_t s, Arena &tmp, const Csr &A, const double *w, int ch
         return BCM_EINVAL;
     }
     launch_weights(s, G, m, A.rp, A.ci, A.v, diag, w, c);
-    launch_rank(s, G, m, A.rp, A.ci, c, rk);
+    launch_candidates(s, G, m, A.rp, A.ci, c, cand, pos);
     launch_fill_u64(s, m, ws, 0ull);
-    launch_suitor(s, m, A.rp, A.ci, c, rk, ws);
+    launch_suitor(s, m, A.rp, cand, pos, ws);
     launch_mate(s, m, ws, mate, leader);
     HIPCHK(hipGetLastError());
     *mate_out = mate;
@@ -255,7 +256,7 @@ int build_hierarchy(bcm_handle *h, const bcm_csr *Ain, const double *win) {
     keep.dealloc = tmp.dealloc = P.dealloc;
     keep.ctx = tmp.ctx = P.alloc_ctx;
     keep.reserve((size_t)(16.0 * z + 96.0 * nn) + (size_t(1) << 20));
-    tmp.reserve((size_t)(24.0 * z + 48.0 * nn) + (size_t(1) << 20));
+    tmp.reserve((size_t)(32.0 * z + 56.0 * nn) + (size_t(1) << 20));
     struct Guard {
         Arena &a, &b;
         hipStream_t s;
@@ -436,11 +437,12 @@ struct Prof {
         (void)hipEventRecord(h->ev_pool[idx], h->s);
         return idx;
     }
-    void end(int cls, int idx, double bytes) {
+    void end(int cls, int idx, double bytes, int iter) {
         if (idx < 0) return;
         (void)hipEventRecord(h->ev_pool[idx + 1], h->s);
         h->ev_pairs.push_back({cls, idx});
         h->ev_bytes.push_back(bytes);
+        h->ev_iter.push_back(iter);
     }
 };
 
@@ -450,9 +452,12 @@ int prof_class_index(int bit) {
     return i;
 }
 
-void prof_collect(bcm_handle *h) {
+// Accumulates the event pairs of iterations < iters (launches of a batch after
+// the solve ended returned at once and are not counted).
+void prof_collect(bcm_handle *h, int iters) {
     for (auto &c : h->prof) c = ProfClass{};
     for (size_t t = 0; t < h->ev_pairs.size(); ++t) {
+        if (h->ev_iter[t] >= iters) continue;
         const int cls = h->ev_pairs[t].first, idx = h->ev_pairs[t].second;
         float ms = 0.f;
         if (hipEventElapsedTime(&ms, h->ev_pool[idx], h->ev_pool[idx + 1]) == hipSuccess) {
@@ -463,10 +468,12 @@ void prof_collect(bcm_handle *h) {
     }
     h->ev_pairs.clear();
     h->ev_bytes.clear();
+    h->ev_iter.clear();
 }
 
 // --------------------------------------------------------------- V-cycle
-void vcycle(bcm_handle *h, Prof &pf, const double *rin, double *wout) {
+// One cycle of Algorithm 1 from a zero guess: z = B(r).  done: see launch_down.
+void vcycle(bcm_handle *h, Prof &pf, const double *rin, double *wout, const double *done, int iter) {
     hipStream_t s = h->s;
     const int fp32 = h->prm.precision == BCM_FP32_CYCLE;
     const int nl = h->nl;
@@ -474,21 +481,21 @@ void vcycle(bcm_handle *h, Prof &pf, const double *rin, double *wout) {
     Level &C = h->lv[nl - 1];
     if (nl == 1) {
         int e = pf.begin(4);
-        launch_coarse(s, C, cs, rin, wout, 1, 1, h->ctmp[0], h->ctmp[1]);
-        pf.end(4, e, bytes_coarse(h));
+        launch_coarse(s, C, cs, rin, wout, 1, 1, h->ctmp[0], h->ctmp[1], done);
+        pf.end(4, e, bytes_coarse(h), iter);
         return;
     }
     for (int k = 0; k < nl - 1; ++k) {
         Level &L = h->lv[k];
         const int cls = k == 0 ? 0 : 5;
         int e = pf.begin(cls);
-        launch_down(s, L, fp32, k == 0 ? (const void *)rin : L.b, h->lv[k + 1].b, (k == 0 || !fp32) ? 1 : 0);
-        pf.end(cls, e, bytes_down(h, k));
+        launch_down(s, L, fp32, k == 0 ? (const void *)rin : L.b, h->lv[k + 1].b, (k == 0 || !fp32) ? 1 : 0, done);
+        pf.end(cls, e, bytes_down(h, k), iter);
     }
     {
         int e = pf.begin(4);
-        launch_coarse(s, C, cs, C.b, C.x, !fp32, !fp32, h->ctmp[0], h->ctmp[1]);
-        pf.end(4, e, bytes_coarse(h));
+        launch_coarse(s, C, cs, C.b, C.x, !fp32, !fp32, h->ctmp[0], h->ctmp[1], done);
+        pf.end(4, e, bytes_coarse(h), iter);
     }
     for (int k = nl - 2; k >= 0; --k) {
         Level &L = h->lv[k];
@@ -496,11 +503,18 @@ void vcycle(bcm_handle *h, Prof &pf, const double *rin, double *wout) {
         const int f64io = (k == 0 || !fp32) ? 1 : 0;
         int e = pf.begin(cls);
         launch_up(s, L, fp32, k == 0 ? (const void *)rin : L.b, h->lv[k + 1].x, k == 0 ? (void *)wout : L.x, f64io,
-                  f64io);
-        pf.end(cls, e, bytes_up(h, k));
+                  f64io, done);
+        pf.end(cls, e, bytes_up(h, k), iter);
     }
 }
 
+// Flexible CG, Algorithm 3 (read with r_{i+1} = r_i - (alpha/rho_i) q_i and
+// gamma_i/rho_{i-1} in the d and q updates).  Iterations are launched in
+// batches: the finalize kernel counts iterations on the device and raises the
+// solve-ended flag when ||r|| <= tol ||b|| or itmax is reached, after which every
+// kernel of the batch returns at once.  The host reads the scalars once per
+// batch and sizes the next batch from the observed convergence rate, so the
+// iteration count is exactly the one a per-iteration test gives.
 int fcg(bcm_handle *h, const double *b, double *x, double tol) {
     hipStream_t s = h->s;
     const Level &L0 = h->lv[0];
@@ -508,9 +522,10 @@ int fcg(bcm_handle *h, const double *b, double *x, double tol) {
     Prof pf{h, h->prm.profile};
     h->ev_pairs.clear();
     h->ev_bytes.clear();
+    h->ev_iter.clear();
     double hs[16];
     launch_resid(s, L0, nb, b, x, h->r, h->partials, h->scal);
-    int rc = read_back(s, h->scal, 10 * sizeof(double), hs);
+    int rc = read_back(s, h->scal, 16 * sizeof(double), hs);
     if (rc) return rc;
     const double bb = hs[5];
     int it = 0, status = BCM_OK;
@@ -528,33 +543,53 @@ int fcg(bcm_handle *h, const double *b, double *x, double tol) {
     const double bn = std::sqrt(bb);
     relres = std::sqrt(hs[4]) / bn;
     const int itmax = h->prm.itmax;
+    const double *done = h->scal + 10;
+    double ctl_local[4];
+    double *ctl = pinned() ? pinned() + 32 : ctl_local;
     for (int restart = 0; restart < 4; ++restart) {
         if (relres <= tol) { status = BCM_OK; break; }
         if (it >= itmax) { status = BCM_MAXIT; break; }
-        int first = 1;
+        // arm the device-side loop control: flag, count, threshold, itmax
+        ctl[0] = 0.0; ctl[1] = (double)it; ctl[2] = tol * tol * bb; ctl[3] = (double)itmax;
+        HIPCHK(hipMemcpyAsync(h->scal + 10, ctl, 4 * sizeof(double), hipMemcpyHostToDevice, s));
+        int first = 1, batch = 4, launched = it;
+        double rel_prev = relres;
+        int it_prev = it;
         for (;;) {
-            vcycle(h, pf, h->r, h->w);
-            int e = pf.begin(2);
-            launch_spmv_dots(s, L0, nb, first, h->w, h->r, h->q, h->v, h->partials, h->scal);
-            pf.end(2, e, bytes_spmv_dots(h));
-            e = pf.begin(3);
-            launch_update(s, n, nb, first, h->w, h->v, h->d, x, h->q, h->r, h->partials, h->scal);
-            pf.end(3, e, bytes_update(h));
-            first = 0;
-            ++it;
-            rc = read_back(s, h->scal, 10 * sizeof(double), hs);
+            const int nb_it = std::min(batch, itmax - launched);
+            for (int t = 0; t < nb_it; ++t) {
+                vcycle(h, pf, h->r, h->w, done, launched);
+                int e = pf.begin(2);
+                launch_spmv_dots(s, L0, nb, first, h->w, h->r, h->q, h->v, h->partials, h->scal);
+                pf.end(2, e, bytes_spmv_dots(h), launched);
+                e = pf.begin(3);
+                launch_update(s, n, nb, first, h->w, h->v, h->d, x, h->q, h->r, h->partials, h->scal);
+                pf.end(3, e, bytes_update(h), launched);
+                first = 0;
+                ++launched;
+            }
+            rc = read_back(s, h->scal, 16 * sizeof(double), hs);
             if (rc) return rc;
+            it = (int)hs[11];
             if (hs[6] != 0.0) {
                 h->iters = it; h->status = BCM_EBREAKDOWN;
+                prof_collect(h, it);
                 set_error("flexible CG breakdown: rho <= 0 or not finite (matrix or preconditioner not s.p.d.)");
                 return BCM_EBREAKDOWN;
             }
             relres = std::sqrt(hs[4]) / bn;
-            if (!(relres > tol) || it >= itmax) break;
+            if (hs[10] != 0.0 || it >= itmax) break;
+            // next batch: iterations the observed rate needs to reach tol
+            const double rate = it > it_prev && rel_prev > 0.0 ? std::pow(relres / rel_prev, 1.0 / (it - it_prev)) : 1.0;
+            int need = 4;
+            if (rate > 0.0 && rate < 0.999) need = (int)std::ceil(std::log(tol / relres) / std::log(rate));
+            batch = std::max(1, std::min(32, need));
+            rel_prev = relres;
+            it_prev = it;
         }
         // true residual b - A x
         launch_resid(s, L0, nb, b, x, h->r, h->partials, h->scal);
-        rc = read_back(s, h->scal, 10 * sizeof(double), hs);
+        rc = read_back(s, h->scal, 16 * sizeof(double), hs);
         if (rc) return rc;
         relres = std::sqrt(hs[4]) / bn;
         if (relres <= tol) { status = BCM_OK; break; }
@@ -562,7 +597,7 @@ int fcg(bcm_handle *h, const double *b, double *x, double tol) {
         status = BCM_MAXIT;
     }
     HIPCHK(hipGetLastError());
-    prof_collect(h);
+    prof_collect(h, it);
     h->iters = it;
     h->relres = relres;
     h->status = status;
@@ -637,7 +672,7 @@ int bcm_precond(bcm_handle *h, const double *r, double *z) {
     g_err.clear();
     if (!h || !r || !z) { set_error("NULL handle or vector"); return BCM_EINVAL; }
     Prof pf{h, 0};
-    vcycle(h, pf, r, z);
+    vcycle(h, pf, r, z, nullptr, 0);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(h->s));
     return BCM_OK;
@@ -722,7 +757,7 @@ int bcm_match(const bcm_csr *A, const double *w, const bcm_params *p, int32_t *m
     tmp.alloc = prm.alloc;
     tmp.dealloc = prm.dealloc;
     tmp.ctx = prm.alloc_ctx;
-    tmp.reserve((size_t)A->nnz * 24 + (size_t)A->n * 40 + (size_t(1) << 20));
+    tmp.reserve((size_t)A->nnz * 24 + (size_t)A->n * 48 + (size_t(1) << 20));
     Csr M;
     M.n = A->n;
     M.nnz = A->nnz;

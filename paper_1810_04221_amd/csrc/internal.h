@@ -93,6 +93,7 @@ struct bcm_handle {
     double *r = nullptr, *w = nullptr, *d = nullptr, *v = nullptr, *q = nullptr;
     // device scalars: [0] alpha [1] beta [2] gamma [3] rho of the last step [4] ||r||^2
     // [5] ||b||^2 [6] breakdown flag [8] gamma_i / rho_{i-1} [9] alpha_i / rho_i
+    // [10] solve-ended flag [11] iterations done [12] tol^2 ||b||^2 [13] itmax
     double *scal = nullptr;
     double *ctmp[2] = {nullptr, nullptr};  // coarsest-level sweep buffers when n > kCoarseLds
     double *partials = nullptr;
@@ -105,6 +106,7 @@ struct bcm_handle {
     std::vector<hipEvent_t> ev_pool;
     std::vector<std::pair<int, int>> ev_pairs;  // (class, event index of the start)
     std::vector<double> ev_bytes;
+    std::vector<int> ev_iter;
     bcm::ProfClass prof[6];
 };
 
@@ -117,10 +119,10 @@ void launch_validate(hipStream_t s, int G, int n, int nnz, const int *rp, const 
                      const double *v, const double *w, int check_sym, double *diag, int *flags);
 void launch_weights(hipStream_t s, int G, int n, const int *rp, const int *ci, const double *v,
                     const double *diag, const double *w, double *c);
-void launch_rank(hipStream_t s, int G, int n, const int *rp, const int *ci, const double *c,
-                 uint32_t *rk);
-void launch_suitor(hipStream_t s, int n, const int *rp, const int *ci, const double *c,
-                   const uint32_t *rk, unsigned long long *ws);
+void launch_candidates(hipStream_t s, int G, int n, const int *rp, const int *ci, const double *c,
+                       unsigned long long *cand, int *pos);
+void launch_suitor(hipStream_t s, int n, const int *rp, const unsigned long long *cand, int *pos,
+                   unsigned long long *ws);
 void launch_mate(hipStream_t s, int n, const unsigned long long *ws, int *mate, int *leader);
 void launch_aggfill(hipStream_t s, int n, const int *mate, const int *ofs, const double *w,
                     int *agg, double *p, double *wc, int *mem2);
@@ -145,11 +147,14 @@ size_t scan_tmp_bytes(int n);
 void scan_exclusive(hipStream_t s, const int *in, int *out, int n, int *total_dev, void *tmp);
 
 // ---- solve kernels (solve.hip) ----
-void launch_down(hipStream_t s, const Level &L, int fp32, const void *b, void *bc, int b_is_f64);
+// Cycle kernels return at once when done != NULL and *done != 0 (the flexible
+// CG loop's "solve ended" flag); done = NULL outside that loop.
+void launch_down(hipStream_t s, const Level &L, int fp32, const void *b, void *bc, int b_is_f64,
+                 const double *done);
 void launch_up(hipStream_t s, const Level &L, int fp32, const void *b, const void *xc, void *x,
-               int b_is_f64, int x_is_f64);
+               int b_is_f64, int x_is_f64, const double *done);
 void launch_coarse(hipStream_t s, const Level &L, int sweeps, const void *b, void *x, int b_f64,
-                   int x_f64, void *tmp_a, void *tmp_b);
+                   int x_f64, void *tmp_a, void *tmp_b, const double *done);
 // Each of these is a streaming kernel writing block partials plus a one-block
 // finalize kernel that sums them in block order into scal[].
 // S = sum_{t < sweeps} (I - D A)^t D of the coarsest level, column by column

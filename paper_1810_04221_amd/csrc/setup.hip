@@ -112,87 +112,87 @@ k_weights(int n, const int *__restrict__ rp, const int *__restrict__ ci, const d
 }
 
 // ----------------------------------------------------------------------------
-// Row ranks for exact Suitor keys.  For the stored entry q = (u, v):
-//   rk[q] = #{ entries t of row v : c[t] < c[q] }
-// i.e. the position of c_uv among the weights seen from vertex v.  Proposals to
-// v then compare as (rk, proposer) in one 64-bit word, which orders them
-// exactly as (c_uv, u) because c_uv is the same double from both ends.
+// Suitor candidate lists.  For row u, the eligible entries (off-diagonal, weight
+// positive and finite) are written in preference order of u -- weight
+// descending, then neighbour index descending -- as 64-bit words
+//   cand = rk << 32 | v,   rk = #{ entries t of row v : c[t] < c_uv }
+// where rk is the position of c_uv among the weights seen from v.  A proposal
+// from u to v then compares at v as (rk << 32 | u + 1), which orders proposals
+// exactly as (c_uv, u) because c_uv is the same double from both ends.  After
+// the eligible entries the row holds the sentinel ~0.  pos[u] = row start.
 // ----------------------------------------------------------------------------
 template <int G>
 __global__ void __launch_bounds__(kBlock)
-k_rank(int n, const int *__restrict__ rp, const int *__restrict__ ci, const double *__restrict__ c,
-       uint32_t *__restrict__ rk) {
+k_candidates(int n, const int *__restrict__ rp, const int *__restrict__ ci, const double *__restrict__ c,
+             unsigned long long *__restrict__ cand, int *__restrict__ pos) {
     const int lane = threadIdx.x % G;
     const int row = (xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x) / G;
     if (row >= n) return;
-    const int e = rp[row + 1];
-    for (int q = rp[row] + lane; q < e; q += G) {
+    const int s0 = rp[row], e = rp[row + 1];
+    int nelig = 0;
+    for (int q = s0 + lane; q < e; q += G) {
         const int vtx = ci[q];
-        if (vtx == row) { rk[q] = 0u; continue; }
         const double cq = c[q];
-        uint32_t cnt = 0;
+        if (!(vtx != row && cq > 0.0 && cq < INFINITY)) continue;
+        ++nelig;
+        unsigned rk = 0;
         const int e2 = rp[vtx + 1];
-        for (int t = rp[vtx]; t < e2; ++t) cnt += (c[t] < cq) ? 1u : 0u;
-        rk[q] = cnt;
+        for (int t = rp[vtx]; t < e2; ++t) rk += (c[t] < cq) ? 1u : 0u;
+        int before = 0;
+        for (int t = s0; t < e; ++t) {
+            const int vt = ci[t];
+            const double ct = c[t];
+            const bool elig = vt != row && ct > 0.0 && ct < INFINITY;
+            before += (elig && (ct > cq || (ct == cq && vt > vtx))) ? 1 : 0;
+        }
+        cand[s0 + before] = ((unsigned long long)rk << 32) | (unsigned)vtx;
     }
+    nelig = group_sum<G>(nelig);
+    for (int q = s0 + nelig + lane; q < e; q += G) cand[q] = ~0ull;
+    if (lane == 0) pos[row] = s0;
 }
 
 // ----------------------------------------------------------------------------
 // Suitor matching (Section 3.1).  One thread per vertex holds that vertex's
-// proposal.  A vertex u proposes to its best neighbour v, by (c_uv, v), whose
-// current suitor ranks below u; ws[v] holds the 64-bit key (rk, proposer + 1)
-// of v's best proposal so far and is raised with atomicMax.  A proposer that
-// is displaced is taken over by the displacing thread and proposes again.
-// Every successful atomicMax strictly raises one ws[] entry and a failed one
-// means another thread raised it, so the total number of loop trips is
-// bounded and every thread exits.  The final suitor pairs are mutual and equal
-// the greedy matching under (c desc, larger endpoint desc, smaller desc).
-// Only edges with a positive finite weight take part.
+// proposal.  Vertex u walks its candidate list from its resume position and
+// proposes to the first v whose current suitor ranks below u; ws[v] holds the
+// key (rk << 32 | proposer + 1) of v's best proposal so far and is raised with
+// atomicMax.  A displaced proposer is taken over by the displacing thread and
+// resumes after the candidate it lost: ws[] only grows, so every candidate it
+// passed stays unavailable.  A stale resume position only rescans.  Every
+// successful atomicMax strictly raises one ws[] entry and a failed one means
+// another thread raised it, so the total number of loop trips is bounded and
+// every thread exits.  The final suitor pairs are mutual and equal the greedy
+// matching under (c desc, larger endpoint desc, smaller desc).
 // ----------------------------------------------------------------------------
 __global__ void __launch_bounds__(kBlock)
-k_suitor(int n, const int *__restrict__ rp, const int *__restrict__ ci, const double *__restrict__ c,
-         const uint32_t *__restrict__ rk, unsigned long long *ws) {
+k_suitor(int n, const int *__restrict__ rp, const unsigned long long *__restrict__ cand, int *pos,
+         unsigned long long *ws) {
     // Highest vertices first: workgroups are dispatched roughly in index order,
-    // and the greedy order settles large indices first on equal weights, so
-    // early proposals are rarely displaced.
+    // and the greedy order settles large indices first on equal weights.
     const int u0 = n - 1 - (int)(blockIdx.x * kBlock + threadIdx.x);
     if (u0 < 0) return;
     int u = u0;
+    int t = rp[u], end = rp[u + 1];
     for (;;) {
-        int best = -1;
-        double bc = 0.0;
-        unsigned long long bkey = 0ull;
-        const int e = rp[u + 1];
-        // the row is scanned in chunks of 8 whose ws[] loads are all in flight together
-        for (int q0 = rp[u]; q0 < e; q0 += 8) {
-            int vv[8];
-            double cc[8];
-            unsigned long long kk[8], cur[8];
-#pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                const int q = q0 + k;
-                const bool in = q < e;
-                const int qs = in ? q : q0;
-                vv[k] = in ? ci[qs] : u;
-                cc[k] = c[qs];
-                kk[k] = ((unsigned long long)rk[qs] << 32) | (unsigned long long)(unsigned)(u + 1);
-            }
-#pragma unroll
-            for (int k = 0; k < 8; ++k) cur[k] = load_agent(&ws[vv[k]]);
-#pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                const int vtx = vv[k];
-                const double cq = cc[k];
-                const bool elig = vtx != u && cq > 0.0 && cq < INFINITY && kk[k] > cur[k];
-                const bool better = best < 0 || cq > bc || (cq == bc && vtx > best);
-                if (elig && better) { best = vtx; bc = cq; bkey = kk[k]; }
-            }
+        int v = -1;
+        unsigned long long key = 0ull;
+        for (; t < end; ++t) {
+            const unsigned long long e = cand[t];
+            if (e == ~0ull) break;
+            const unsigned long long k = (e & 0xffffffff00000000ull) | (unsigned long long)(unsigned)(u + 1);
+            const int vt = (int)(e & 0xffffffffull);
+            if (k > load_agent(&ws[vt])) { v = vt; key = k; break; }
         }
-        if (best < 0) break;
-        const unsigned long long old = atomicMax(&ws[best], bkey);
-        if (old > bkey) continue;  // lost the race: look again for u
-        if (old == 0ull) break;    // v had no suitor: done
-        u = (int)(old & 0xffffffffull) - 1;  // displaced suitor proposes again
+        if (v < 0) break;  // no candidate left: u stays unmatched
+        __hip_atomic_store(&pos[u], t + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned long long old = atomicMax(&ws[v], key);
+        if (old > key) { ++t; continue; }  // lost v for good (ws only grows): next candidate
+        if (old == 0ull) break;   // v had no suitor: done
+        u = (int)(old & 0xffffffffull) - 1;  // displaced suitor resumes its list
+        end = rp[u + 1];
+        const int p0 = __hip_atomic_load(&pos[u], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        t = min(max(p0, rp[u]), end);
     }
 }
 
@@ -473,18 +473,18 @@ void launch_weights(hipStream_t s, int G, int n, const int *rp, const int *ci, c
     });
 }
 
-void launch_rank(hipStream_t s, int G, int n, const int *rp, const int *ci, const double *c,
-                 uint32_t *rk) {
+void launch_candidates(hipStream_t s, int G, int n, const int *rp, const int *ci, const double *c,
+                       unsigned long long *cand, int *pos) {
     with_G(G, [&](auto gc) {
         constexpr int g = decltype(gc)::value;
-        hipLaunchKernelGGL(k_rank<g>, dim3(blocks_for((long long)n * g)), dim3(kBlock), 0, s, n, rp, ci, c,
-                           rk);
+        hipLaunchKernelGGL(k_candidates<g>, dim3(blocks_for((long long)n * g)), dim3(kBlock), 0, s, n, rp, ci, c,
+                           cand, pos);
     });
 }
 
-void launch_suitor(hipStream_t s, int n, const int *rp, const int *ci, const double *c,
-                   const uint32_t *rk, unsigned long long *ws) {
-    hipLaunchKernelGGL(k_suitor, dim3(blocks_for(n)), dim3(kBlock), 0, s, n, rp, ci, c, rk, ws);
+void launch_suitor(hipStream_t s, int n, const int *rp, const unsigned long long *cand, int *pos,
+                   unsigned long long *ws) {
+    hipLaunchKernelGGL(k_suitor, dim3(blocks_for(n)), dim3(kBlock), 0, s, n, rp, cand, pos, ws);
 }
 
 void launch_mate(hipStream_t s, int n, const unsigned long long *ws, int *mate, int *leader) {

@@ -76,7 +76,8 @@ template <int G, int S, typename V, typename VB>
 __global__ void __launch_bounds__(kBlock)
 k_down_seq(int nc, const int *__restrict__ mem, const int *__restrict__ rp, const int *__restrict__ ci,
            const V *__restrict__ a, const V *__restrict__ dinv, const V *__restrict__ p,
-           const VB *__restrict__ b, V *__restrict__ bc) {
+           const VB *__restrict__ b, V *__restrict__ bc, const double *__restrict__ done) {
+    if (done && *done != 0.0) return;
     const int lane = threadIdx.x % G;
     int E = (xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x) / G;
     const bool live = E < nc;
@@ -101,7 +102,9 @@ template <int G, typename V, typename VB>
 __global__ void __launch_bounds__(kBlock)
 k_down_loop(int nc, int mstride, const int *__restrict__ mem, const int *__restrict__ rp,
             const int *__restrict__ ci, const V *__restrict__ a, const V *__restrict__ dinv,
-            const V *__restrict__ p, const VB *__restrict__ b, V *__restrict__ bc) {
+            const V *__restrict__ p, const VB *__restrict__ b, V *__restrict__ bc,
+            const double *__restrict__ done) {
+    if (done && *done != 0.0) return;
     const int lane = threadIdx.x % G;
     const int E = (xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x) / G;
     if (E >= nc) return;
@@ -131,7 +134,8 @@ template <int G, int R, typename V, typename VB, typename VX>
 __global__ void __launch_bounds__(kBlock)
 k_up(int n, const int *__restrict__ rp, const int *__restrict__ ci, const V *__restrict__ a,
      const V *__restrict__ dinv, const V *__restrict__ p, const int *__restrict__ agg,
-     const VB *__restrict__ b, const V *__restrict__ xc, VX *__restrict__ x) {
+     const VB *__restrict__ b, const V *__restrict__ xc, VX *__restrict__ x, const double *__restrict__ done) {
+    if (done && *done != 0.0) return;
     constexpr int NG = kBlock / G;
     const int lane = threadIdx.x % G;
     const int base = xcd_block(blockIdx.x, gridDim.x) * NG * R + threadIdx.x / G;
@@ -170,7 +174,8 @@ template <typename VB, typename VX>
 __global__ void __launch_bounds__(1024)
 k_coarse(int n, int nnz, const int *__restrict__ rp_g, const int *__restrict__ ci_g,
          const double *__restrict__ a_g, const double *__restrict__ dinv_g, const VB *__restrict__ b,
-         VX *__restrict__ x, int sweeps, int unit_rhs) {
+         VX *__restrict__ x, int sweeps, int unit_rhs, const double *__restrict__ done) {
+    if (done && *done != 0.0) return;
     __shared__ __align__(16) char lds[kCoarseLdsBytes];
     constexpr int R = kCoarseLds / 1024;
     double *xs = reinterpret_cast<double *>(lds);
@@ -227,7 +232,9 @@ k_coarse(int n, int nnz, const int *__restrict__ rp_g, const int *__restrict__ c
 // x = S b.  One wave per row i reads row i of S contiguously.
 template <typename VB, typename VX>
 __global__ void __launch_bounds__(64)
-k_coarse_dense(int n, const double *__restrict__ S, const VB *__restrict__ b, VX *__restrict__ x) {
+k_coarse_dense(int n, const double *__restrict__ S, const VB *__restrict__ b, VX *__restrict__ x,
+               const double *__restrict__ done) {
+    if (done && *done != 0.0) return;
     const int i = blockIdx.x, lane = threadIdx.x;
     const double *row = S + (size_t)i * n;
     double s = 0.0;
@@ -241,7 +248,8 @@ template <typename VB>
 __global__ void __launch_bounds__(kBlock)
 k_jacobi_sweep(int n, const int *__restrict__ rp, const int *__restrict__ ci, const double *__restrict__ a,
                const double *__restrict__ dinv, const VB *__restrict__ b, const double *__restrict__ xo,
-               double *__restrict__ xn, int first) {
+               double *__restrict__ xn, int first, const double *__restrict__ done) {
+    if (done && *done != 0.0) return;
     const int i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
     double s = 0.0;
@@ -254,7 +262,8 @@ k_jacobi_sweep(int n, const int *__restrict__ rp, const int *__restrict__ ci, co
 }
 
 template <typename VX>
-__global__ void k_store(int n, const double *__restrict__ src, VX *__restrict__ dst) {
+__global__ void k_store(int n, const double *__restrict__ src, VX *__restrict__ dst, const double *__restrict__ done) {
+    if (done && *done != 0.0) return;
     const int i = blockIdx.x * kBlock + threadIdx.x;
     if (i < n) dst[i] = (VX)src[i];
 }
@@ -305,7 +314,8 @@ template <int G>
 __global__ void __launch_bounds__(kBlock)
 k_spmv_dots(int n, const int *__restrict__ rp, const int *__restrict__ ci, const double *__restrict__ a,
             const double *__restrict__ w, const double *__restrict__ r, const double *__restrict__ q,
-            double *__restrict__ v, double *__restrict__ partials) {
+            double *__restrict__ v, double *__restrict__ partials, const double *__restrict__ done) {
+    if (done && *done != 0.0) return;
     constexpr int NG = kBlock / G, R = kRows;
     const int lane = threadIdx.x % G;
     const int blk = xcd_block(blockIdx.x, gridDim.x);
@@ -338,10 +348,15 @@ k_spmv_dots(int n, const int *__restrict__ rp, const int *__restrict__ ci, const
 //                       rho_i = beta - gamma^2 / rho_{i-1} (first step: beta),
 //                       scal[8] = gamma / rho_{i-1}, scal[9] = alpha / rho_i,
 //                       scal[6] = 1 if rho_i <= 0 or not finite (breakdown)
-//   mode 2 (norm):      scal[4] = ||r||^2
+//   mode 2 (norm):      scal[4] = ||r||^2, scal[11] += 1 (iterations done)
+// In the iteration loop (modes 1, 2) scal[10] != 0 means the solve has ended:
+// every kernel of a later iteration returns at once.  Mode 2 sets it when
+// ||r||^2 <= scal[12] (= tol^2 ||b||^2) or scal[11] >= scal[13] (itmax); mode 1
+// sets it, with scal[6], on breakdown.
 template <int K>
 __global__ void __launch_bounds__(kBlock) k_finalize(int nb, const double *__restrict__ partials,
                                                      double *__restrict__ scal, int mode, int first) {
+    if (mode != 0 && scal[10] != 0.0) return;
     __shared__ double lds[K * 16];
     double s[K];
 #pragma unroll
@@ -356,6 +371,10 @@ __global__ void __launch_bounds__(kBlock) k_finalize(int nb, const double *__res
         scal[5] = s[1 % K];
     } else if (mode == 2) {
         scal[4] = s[0];
+        const double it = scal[11] + 1.0;
+        scal[11] = it;
+        if (!isfinite(s[0])) { scal[6] = 1.0; scal[10] = 1.0; }
+        else if (s[0] <= scal[12] || it >= scal[13]) scal[10] = 1.0;
     } else {
         const double alpha = s[0], beta = s[1 % K], gamma = s[2 % K];
         double rho, g;
@@ -368,6 +387,7 @@ __global__ void __launch_bounds__(kBlock) k_finalize(int nb, const double *__res
         scal[2] = gamma;
         scal[6] = ok ? 0.0 : 1.0;
         if (ok) { scal[3] = rho; scal[8] = g; scal[9] = an; }
+        else scal[10] = 1.0;
     }
 }
 
@@ -378,6 +398,7 @@ __global__ void __launch_bounds__(kBlock)
 k_update(int n, int first, const double *__restrict__ w, const double *__restrict__ v, double *__restrict__ d,
          double *__restrict__ u, double *__restrict__ q, double *__restrict__ r,
          const double *__restrict__ scal, double *__restrict__ partials) {
+    if (scal[10] != 0.0) return;
     const bool ok = scal[6] == 0.0;
     const double g = scal[8], an = scal[9];
     double acc[1] = {0.0};
@@ -413,60 +434,63 @@ k_sampled_outer(int n, const int *__restrict__ rp, const int *__restrict__ ci, c
 }
 
 template <int G, typename V, typename VB>
-void down_dispatch(hipStream_t s, const Level &L, const V *a, const V *dinv, const V *p, const VB *b, V *bc) {
+void down_dispatch(hipStream_t s, const Level &L, const V *a, const V *dinv, const V *p, const VB *b, V *bc,
+                   const double *done) {
     const int S = L.mstride;
     const dim3 grid(blocks_for((long long)L.nc * G));
     auto seq = [&](auto sc) {
         constexpr int SS = decltype(sc)::value;
         hipLaunchKernelGGL((k_down_seq<G, SS, V, VB>), grid, dim3(kBlock), 0, s, L.nc, L.mem, L.A.rp, L.A.ci, a,
-                           dinv, p, b, bc);
+                           dinv, p, b, bc, done);
     };
     if (S == 1) seq(std::integral_constant<int, 1>{});
     else if (S == 2) seq(std::integral_constant<int, 2>{});
     else if (S == 4) seq(std::integral_constant<int, 4>{});
     else
         hipLaunchKernelGGL((k_down_loop<G, V, VB>), grid, dim3(kBlock), 0, s, L.nc, L.mstride, L.mem, L.A.rp,
-                           L.A.ci, a, dinv, p, b, bc);
+                           L.A.ci, a, dinv, p, b, bc, done);
 }
 
 template <typename V, typename VB>
-void down_t(hipStream_t s, const Level &L, const V *a, const V *dinv, const V *p, const VB *b, V *bc) {
+void down_t(hipStream_t s, const Level &L, const V *a, const V *dinv, const V *p, const VB *b, V *bc,
+            const double *done) {
     with_G(L.G, [&](auto gc) {
         constexpr int g = decltype(gc)::value;
-        down_dispatch<g, V, VB>(s, L, a, dinv, p, b, bc);
+        down_dispatch<g, V, VB>(s, L, a, dinv, p, b, bc, done);
     });
 }
 
 template <typename V, typename VB, typename VX>
 void up_t(hipStream_t s, const Level &L, const V *a, const V *dinv, const V *p, const VB *b, const V *xc,
-          VX *x) {
+          VX *x, const double *done) {
     with_G(L.G, [&](auto gc) {
         constexpr int g = decltype(gc)::value;
         constexpr int R = 2;
         hipLaunchKernelGGL((k_up<g, R, V, VB, VX>), dim3(blocks_for(((long long)L.A.n * g + R - 1) / R)),
-                           dim3(kBlock), 0, s, L.A.n, L.A.rp, L.A.ci, a, dinv, p, L.agg, b, xc, x);
+                           dim3(kBlock), 0, s, L.A.n, L.A.rp, L.A.ci, a, dinv, p, L.agg, b, xc, x, done);
     });
 }
 
 template <typename VB, typename VX>
-void coarse_t(hipStream_t s, const Level &L, int sweeps, const VB *b, VX *x, double *ta, double *tb) {
+void coarse_t(hipStream_t s, const Level &L, int sweeps, const VB *b, VX *x, double *ta, double *tb,
+              const double *done) {
     const int n = L.A.n;
     if (L.S) {
-        hipLaunchKernelGGL((k_coarse_dense<VB, VX>), dim3(n), dim3(64), 0, s, n, L.S, b, x);
+        hipLaunchKernelGGL((k_coarse_dense<VB, VX>), dim3(n), dim3(64), 0, s, n, L.S, b, x, done);
         return;
     }
     if (n <= kCoarseLds) {
         hipLaunchKernelGGL((k_coarse<VB, VX>), dim3(1), dim3(1024), 0, s, n, L.A.nnz, L.A.rp, L.A.ci, L.A.v, L.dinv,
-                           b, x, sweeps, 0);
+                           b, x, sweeps, 0, done);
         return;
     }
     double *xo = ta, *xn = tb;
     for (int t = 0; t < sweeps; ++t) {
         hipLaunchKernelGGL((k_jacobi_sweep<VB>), dim3(blocks_for(n)), dim3(kBlock), 0, s, n, L.A.rp, L.A.ci,
-                           L.A.v, L.dinv, b, xo, xn, t == 0 ? 1 : 0);
+                           L.A.v, L.dinv, b, xo, xn, t == 0 ? 1 : 0, done);
         double *tmp = xo; xo = xn; xn = tmp;
     }
-    hipLaunchKernelGGL((k_store<VX>), dim3(blocks_for(n)), dim3(kBlock), 0, s, n, xo, x);
+    hipLaunchKernelGGL((k_store<VX>), dim3(blocks_for(n)), dim3(kBlock), 0, s, n, xo, x, done);
 }
 
 }  // namespace
@@ -478,38 +502,41 @@ int reduce_blocks(int n) {
     return (int)b;
 }
 
-void launch_down(hipStream_t s, const Level &L, int fp32, const void *b, void *bc, int b_is_f64) {
+void launch_down(hipStream_t s, const Level &L, int fp32, const void *b, void *bc, int b_is_f64,
+                 const double *done) {
     if (!fp32) {
-        down_t<double, double>(s, L, L.A.v, L.dinv, L.p, (const double *)b, (double *)bc);
+        down_t<double, double>(s, L, L.A.v, L.dinv, L.p, (const double *)b, (double *)bc, done);
     } else if (b_is_f64) {
-        down_t<float, double>(s, L, L.A.v32, L.dinv32, L.p32, (const double *)b, (float *)bc);
+        down_t<float, double>(s, L, L.A.v32, L.dinv32, L.p32, (const double *)b, (float *)bc, done);
     } else {
-        down_t<float, float>(s, L, L.A.v32, L.dinv32, L.p32, (const float *)b, (float *)bc);
+        down_t<float, float>(s, L, L.A.v32, L.dinv32, L.p32, (const float *)b, (float *)bc, done);
     }
 }
 
 void launch_up(hipStream_t s, const Level &L, int fp32, const void *b, const void *xc, void *x, int b_is_f64,
-               int x_is_f64) {
+               int x_is_f64, const double *done) {
     if (!fp32) {
-        up_t<double, double, double>(s, L, L.A.v, L.dinv, L.p, (const double *)b, (const double *)xc, (double *)x);
+        up_t<double, double, double>(s, L, L.A.v, L.dinv, L.p, (const double *)b, (const double *)xc, (double *)x,
+                                     done);
     } else if (b_is_f64 && x_is_f64) {
         up_t<float, double, double>(s, L, L.A.v32, L.dinv32, L.p32, (const double *)b, (const float *)xc,
-                                    (double *)x);
+                                    (double *)x, done);
     } else {
-        up_t<float, float, float>(s, L, L.A.v32, L.dinv32, L.p32, (const float *)b, (const float *)xc, (float *)x);
+        up_t<float, float, float>(s, L, L.A.v32, L.dinv32, L.p32, (const float *)b, (const float *)xc, (float *)x,
+                                  done);
     }
 }
 
 void launch_coarse(hipStream_t s, const Level &L, int sweeps, const void *b, void *x, int b_f64, int x_f64,
-                   void *tmp_a, void *tmp_b) {
+                   void *tmp_a, void *tmp_b, const double *done) {
     double *ta = (double *)tmp_a, *tb = (double *)tmp_b;
-    if (b_f64 && x_f64) coarse_t<double, double>(s, L, sweeps, (const double *)b, (double *)x, ta, tb);
-    else coarse_t<float, float>(s, L, sweeps, (const float *)b, (float *)x, ta, tb);
+    if (b_f64 && x_f64) coarse_t<double, double>(s, L, sweeps, (const double *)b, (double *)x, ta, tb, done);
+    else coarse_t<float, float>(s, L, sweeps, (const float *)b, (float *)x, ta, tb, done);
 }
 
 void launch_coarse_build(hipStream_t s, const Level &L, int sweeps, double *S) {
     hipLaunchKernelGGL((k_coarse<double, double>), dim3(L.A.n), dim3(1024), 0, s, L.A.n, L.A.nnz, L.A.rp, L.A.ci,
-                       L.A.v, L.dinv, (const double *)nullptr, S, sweeps, 1);
+                       L.A.v, L.dinv, (const double *)nullptr, S, sweeps, 1, (const double *)nullptr);
 }
 
 void launch_resid(hipStream_t s, const Level &L, int nb, const double *b, const double *u, double *r,
@@ -527,7 +554,7 @@ void launch_spmv_dots(hipStream_t s, const Level &L, int nb, int first, const do
     with_G(L.G, [&](auto gc) {
         constexpr int g = decltype(gc)::value;
         hipLaunchKernelGGL(k_spmv_dots<g>, dim3(nb), dim3(kBlock), 0, s, L.A.n, L.A.rp, L.A.ci, L.A.v, w, r, q, v,
-                           partials);
+                           partials, scal + 10);
     });
     hipLaunchKernelGGL(k_finalize<3>, dim3(1), dim3(kBlock), 0, s, nb, partials, scal, 1, first);
 }
