@@ -355,6 +355,10 @@ int build_hierarchy(bcm_handle *h, const bcm_csr *Ain, const double *win) {
             }
         }
         launch_diag_l1(s, L.G, nl_, L.A.rp, L.A.v, L.dinv, L.dinv32);
+        if (l < h->nl - 1 && nl_ >= kSplitUp) {
+            L.xp = h->persist.get((fp32 ? sizeof(float) : sizeof(double)) * nl_);
+            NOMEM(L.xp);
+        }
         if (l > 0) {
             const size_t es = fp32 ? sizeof(float) : sizeof(double);
             L.b = h->persist.get(es * nl_);
@@ -369,6 +373,31 @@ int build_hierarchy(bcm_handle *h, const bcm_csr *Ain, const double *win) {
             C.S = h->persist.get_n<double>((size_t)C.A.n * C.A.n);
             NOMEM(C.S);
             launch_coarse_build(s, C, P.coarse_sweeps, C.S);
+        }
+    }
+    {
+        // tail kernel: the smallest levels (and the coarsest solve) in one workgroup
+        int kt = h->nl - 1;
+        while (kt > 1 && h->lv[kt - 1].A.n <= kTailRows) --kt;
+        const Level &C = h->lv[h->nl - 1];
+        if (kt < h->nl - 1 && C.A.n <= kTailRows) {
+            std::vector<TailLevel> tv(h->nl);
+            for (int l = 0; l < h->nl; ++l) {
+                const Level &L = h->lv[l];
+                TailLevel t{};
+                t.n = L.A.n; t.nc = L.nc; t.mstride = L.mstride;
+                t.rp = L.A.rp; t.ci = L.A.ci; t.agg = L.agg; t.mem = L.mem;
+                t.a = fp32 ? (const void *)L.A.v32 : (const void *)L.A.v;
+                t.dinv = fp32 ? (const void *)L.dinv32 : (const void *)L.dinv;
+                t.p = fp32 ? (const void *)L.p32 : (const void *)L.p;
+                t.b = L.b; t.x = L.x;
+                tv[l] = t;
+            }
+            h->tail = h->persist.get_n<TailLevel>(h->nl);
+            NOMEM(h->tail);
+            HIPCHK(hipMemcpyAsync(h->tail, tv.data(), sizeof(TailLevel) * h->nl, hipMemcpyHostToDevice, s));
+            HIPCHK(hipStreamSynchronize(s));
+            h->kt = kt;
         }
     }
     if (h->lv[h->nl - 1].A.n > kCoarseLds) {
@@ -403,11 +432,14 @@ double bytes_down(const bcm_handle *h, int k) {
     const double n = L.A.n, z = L.A.nnz, nc = L.nc;
     return 4 * (n + 1) + (4 + sv) * z + sb * n + 2 * sv * n + 4.0 * nc * L.mstride + sv * nc;
 }
+// up leg: fused k_up, or k_prolong + k_smooth on large levels (xp written and read once)
 double bytes_up(const bcm_handle *h, int k) {
     const Level &L = h->lv[k];
     const bool f32 = h->prm.precision == BCM_FP32_CYCLE;
     const double sv = f32 ? 4 : 8, sb = (k == 0 || !f32) ? 8 : 4;
     const double n = L.A.n, z = L.A.nnz, nc = L.nc;
+    if (L.xp && L.A.n >= kSplitUp)
+        return (sb * n + 2 * sv * n + 4 * n + sv * nc + sv * n) + (4 * (n + 1) + (4 + sv) * z + 2 * sv * n + 2 * sb * n);
     return 4 * (n + 1) + (4 + sv) * z + 2 * sb * n + 2 * sv * n + 4 * n + sv * nc;
 }
 double bytes_coarse(const bcm_handle *h) {
@@ -485,7 +517,8 @@ void vcycle(bcm_handle *h, Prof &pf, const double *rin, double *wout, const doub
         pf.end(4, e, bytes_coarse(h), iter);
         return;
     }
-    for (int k = 0; k < nl - 1; ++k) {
+    const int kt = h->kt > 0 ? h->kt : nl - 1;
+    for (int k = 0; k < kt; ++k) {
         Level &L = h->lv[k];
         const int cls = k == 0 ? 0 : 5;
         int e = pf.begin(cls);
@@ -494,10 +527,16 @@ void vcycle(bcm_handle *h, Prof &pf, const double *rin, double *wout, const doub
     }
     {
         int e = pf.begin(4);
-        launch_coarse(s, C, cs, C.b, C.x, !fp32, !fp32, h->ctmp[0], h->ctmp[1], done);
-        pf.end(4, e, bytes_coarse(h), iter);
+        if (h->kt > 0) {
+            launch_tail(s, fp32, kt, nl, h->tail, C, cs, done);
+        } else {
+            launch_coarse(s, C, cs, C.b, C.x, !fp32, !fp32, h->ctmp[0], h->ctmp[1], done);
+        }
+        double by = bytes_coarse(h);
+        for (int k = kt; k < nl - 1; ++k) by += bytes_down(h, k) + bytes_up(h, k);
+        pf.end(4, e, by, iter);
     }
-    for (int k = nl - 2; k >= 0; --k) {
+    for (int k = kt - 1; k >= 0; --k) {
         Level &L = h->lv[k];
         const int cls = k == 0 ? 1 : 5;
         const int f64io = (k == 0 || !fp32) ? 1 : 0;

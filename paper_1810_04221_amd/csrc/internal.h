@@ -14,6 +14,7 @@ namespace bcm {
 constexpr int kMaxLevels = 64;
 constexpr int kCoarseLds = 8192;   // largest coarsest level solved inside one workgroup
 constexpr int kCoarseDense = 1024; // largest coarsest level applied as a precomputed dense operator
+constexpr int kSplitUp = 65536;    // levels at least this large run the up leg as prolong + smooth
 
 // Error flags raised by the validation kernel.
 enum : int {
@@ -73,8 +74,19 @@ struct Level {
     int mstride = 0;
     int *mem = nullptr;
     void *b = nullptr, *x = nullptr;  // cycle vectors for k >= 1 (cycle precision)
+    void *xp = nullptr;               // prolonged iterate of the split up leg (cycle precision)
     double *S = nullptr;  // coarsest level only: dense sweep operator (n <= kCoarseDense)
 };
+
+// Device-side view of one level for the single-workgroup tail kernel
+// (value arrays in cycle precision).
+struct TailLevel {
+    int n, nc, mstride, pad;
+    const int *rp, *ci, *agg, *mem;
+    const void *a, *dinv, *p;
+    void *b, *x;
+};
+constexpr int kTailRows = 512;  // levels up to this size run inside the tail kernel
 
 struct ProfClass {
     int64_t launches = 0;
@@ -96,6 +108,8 @@ struct bcm_handle {
     // [10] solve-ended flag [11] iterations done [12] tol^2 ||b||^2 [13] itmax
     double *scal = nullptr;
     double *ctmp[2] = {nullptr, nullptr};  // coarsest-level sweep buffers when n > kCoarseLds
+    bcm::TailLevel *tail = nullptr;        // device table of levels for the tail kernel
+    int kt = -1;                           // first level handled by the tail kernel (-1: none)
     double *partials = nullptr;
     double *host_scal = nullptr;  // pinned
     int red_blocks = 0;
@@ -157,6 +171,9 @@ void launch_coarse(hipStream_t s, const Level &L, int sweeps, const void *b, voi
                    int x_f64, void *tmp_a, void *tmp_b, const double *done);
 // Each of these is a streaming kernel writing block partials plus a one-block
 // finalize kernel that sums them in block order into scal[].
+// levels kt .. nl-1 (tail table tl, coarsest level C) in one workgroup
+void launch_tail(hipStream_t s, int fp32, int kt, int nl, const TailLevel *tl, const Level &C, int sweeps,
+                 const double *done);
 // S = sum_{t < sweeps} (I - D A)^t D of the coarsest level, column by column
 void launch_coarse_build(hipStream_t s, const Level &L, int sweeps, double *S);
 void launch_resid(hipStream_t s, const Level &L, int nb, const double *b, const double *u, double *r,

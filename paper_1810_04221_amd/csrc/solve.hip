@@ -157,6 +157,42 @@ k_up(int n, const int *__restrict__ rp, const int *__restrict__ ci, const V *__r
     }
 }
 
+// Large levels: the up leg as two streaming kernels.  k_prolong writes the
+// pre-smoothed, corrected iterate xp = dinv o b + P xc (all reads coalesced);
+// k_smooth then gathers only xp:  x_i = xp_i + dinv_i (b_i - sum_j a_ij xp_j).
+// Same arithmetic as k_up, one gathered array per nonzero instead of five.
+template <typename V, typename VB>
+__global__ void __launch_bounds__(kBlock)
+k_prolong(int n, const V *__restrict__ dinv, const V *__restrict__ p, const int *__restrict__ agg,
+          const VB *__restrict__ b, const V *__restrict__ xc, V *__restrict__ xp, const double *__restrict__ done) {
+    if (done && *done != 0.0) return;
+    const int i = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    if (i >= n) return;
+    xp[i] = dinv[i] * (V)b[i] + p[i] * xc[agg[i]];
+}
+
+template <int G, int R, typename V, typename VB, typename VX>
+__global__ void __launch_bounds__(kBlock)
+k_smooth(int n, const int *__restrict__ rp, const int *__restrict__ ci, const V *__restrict__ a,
+         const V *__restrict__ dinv, const VB *__restrict__ b, const V *__restrict__ xp, VX *__restrict__ x,
+         const double *__restrict__ done) {
+    if (done && *done != 0.0) return;
+    constexpr int NG = kBlock / G;
+    const int lane = threadIdx.x % G;
+    const int base = xcd_block(blockIdx.x, gridDim.x) * NG * R + threadIdx.x / G;
+    int rows[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) rows[k] = base + k * NG < n ? base + k * NG : -1;
+    V s[R];
+    rows_dot<G, R, V>(rp, ci, a, rows, s, [&](int j) { return xp[j]; });
+    // lane k of the group finishes row k
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        const int i = rows[k];
+        if (lane == k % G && i >= 0) x[i] = (VX)(xp[i] + dinv[i] * ((V)b[i] - s[k]));
+    }
+}
+
 // ----------------------------------------------------------------------------
 // Coarsest level: `sweeps` l1-Jacobi sweeps from zero in float64, inside one
 // workgroup with x in LDS (n <= 8192).  When the level's matrix also fits, it
@@ -241,6 +277,116 @@ k_coarse_dense(int n, const double *__restrict__ S, const VB *__restrict__ b, VX
     for (int j = lane; j < n; j += 64) s += row[j] * (double)b[j];
     s = group_sum<64>(s);
     if (lane == 0) x[i] = (VX)s;
+}
+
+// ----------------------------------------------------------------------------
+// Tail of the cycle: every level k >= kt (all with at most kTailRows rows) and
+// the coarsest solve, inside one workgroup of 1024 threads, with phases
+// separated by barriers instead of kernel launches.  Down legs (one thread per
+// aggregate, members in ascending order), then the coarsest solve (dense
+// operator, or l1-Jacobi sweeps with x in LDS), then the up legs.  Same
+// arithmetic as the per-level kernels.
+// ----------------------------------------------------------------------------
+template <typename V>
+__global__ void __launch_bounds__(1024)
+k_tail(int kt, int nl, const TailLevel *__restrict__ tl, const double *__restrict__ S,
+       const double *__restrict__ cdinv, const double *__restrict__ ca, int sweeps,
+       const double *__restrict__ done) {
+    if (done && *done != 0.0) return;
+    __shared__ double xs[kTailRows];
+    const int tid = threadIdx.x, nt = blockDim.x;
+    for (int k = kt; k < nl - 1; ++k) {
+        const TailLevel L = tl[k];
+        const V *a = (const V *)L.a, *dinv = (const V *)L.dinv, *p = (const V *)L.p;
+        const V *b = (const V *)L.b;
+        V *bc = (V *)tl[k + 1].b;
+        int lpr = 1;
+        while (lpr < 16 && L.nc * (lpr * 2) <= nt) lpr *= 2;
+        const int lane = tid % lpr, ngrp = nt / lpr;
+        for (int E = tid / lpr; E < L.nc; E += ngrp) {
+            V acc = V(0);
+            for (int t = 0; t < L.mstride; ++t) {
+                const int i = L.mem[(size_t)E * L.mstride + t];
+                if (i < 0) break;
+                V s = V(0);
+                for (int q = L.rp[i] + lane; q < L.rp[i + 1]; q += lpr) {
+                    const int j = L.ci[q];
+                    s += a[q] * (dinv[j] * b[j]);
+                }
+                for (int o = lpr / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, lpr);
+                acc += p[i] * (b[i] - s);
+            }
+            if (lane == 0) bc[E] = acc;
+        }
+        __syncthreads();
+    }
+    {
+        const TailLevel C = tl[nl - 1];
+        const V *b = (const V *)C.b;
+        V *x = (V *)C.x;
+        const int n = C.n;
+        if (S) {
+            int lpr = 1;
+            while (lpr < 64 && n * (lpr * 2) <= nt) lpr *= 2;
+            const int lane = tid % lpr, ngrp = nt / lpr;
+            for (int i = tid / lpr; i < n; i += ngrp) {
+                double s = 0.0;
+                for (int j = lane; j < n; j += lpr) s += S[(size_t)i * n + j] * (double)b[j];
+                for (int o = lpr / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, lpr);
+                if (lane == 0) x[i] = (V)s;
+            }
+        } else {
+            for (int i = tid; i < n; i += nt) xs[i] = 0.0;
+            __syncthreads();
+            constexpr int R = (kTailRows + 1023) / 1024;
+            for (int t = 0; t < sweeps; ++t) {
+                double xn[R];
+#pragma unroll
+                for (int k = 0; k < R; ++k) {
+                    const int i = tid + k * nt;
+                    xn[k] = 0.0;
+                    if (i < n) {
+                        double s = 0.0;
+                        for (int q = C.rp[i]; q < C.rp[i + 1]; ++q) s = s + ca[q] * xs[C.ci[q]];
+                        xn[k] = xs[i] + cdinv[i] * ((double)b[i] - s);
+                    }
+                }
+                __syncthreads();
+#pragma unroll
+                for (int k = 0; k < R; ++k) {
+                    const int i = tid + k * nt;
+                    if (i < n) xs[i] = xn[k];
+                }
+                __syncthreads();
+            }
+            for (int i = tid; i < n; i += nt) x[i] = (V)xs[i];
+        }
+        __syncthreads();
+    }
+    for (int k = nl - 2; k >= kt; --k) {
+        const TailLevel L = tl[k];
+        const V *a = (const V *)L.a, *dinv = (const V *)L.dinv, *p = (const V *)L.p;
+        const V *b = (const V *)L.b;
+        const V *xc = (const V *)tl[k + 1].x;
+        V *x = (V *)L.x;
+        int lpr = 1;
+        while (lpr < 16 && L.n * (lpr * 2) <= nt) lpr *= 2;
+        const int lane = tid % lpr, ngrp = nt / lpr;
+        for (int i = tid / lpr; i < L.n; i += ngrp) {
+            V s = V(0);
+            for (int q = L.rp[i] + lane; q < L.rp[i + 1]; q += lpr) {
+                const int j = L.ci[q];
+                s += a[q] * (dinv[j] * b[j] + p[j] * xc[L.agg[j]]);
+            }
+            for (int o = lpr / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, lpr);
+            if (lane == 0) {
+                const V bi = b[i], di = dinv[i];
+                const V xi = di * bi + p[i] * xc[L.agg[i]];
+                x[i] = xi + di * (bi - s);
+            }
+        }
+        __syncthreads();
+    }
 }
 
 // One global l1-Jacobi sweep (coarsest levels larger than the LDS bound).
@@ -463,6 +609,18 @@ void down_t(hipStream_t s, const Level &L, const V *a, const V *dinv, const V *p
 template <typename V, typename VB, typename VX>
 void up_t(hipStream_t s, const Level &L, const V *a, const V *dinv, const V *p, const VB *b, const V *xc,
           VX *x, const double *done) {
+    if (L.xp && L.A.n >= kSplitUp) {
+        V *xp = (V *)L.xp;
+        hipLaunchKernelGGL((k_prolong<V, VB>), dim3(blocks_for(L.A.n)), dim3(kBlock), 0, s, L.A.n, dinv, p, L.agg, b,
+                           xc, xp, done);
+        with_G(L.G, [&](auto gc) {
+            constexpr int g = decltype(gc)::value;
+            constexpr int R = 2;
+            hipLaunchKernelGGL((k_smooth<g, R, V, VB, VX>), dim3(blocks_for(((long long)L.A.n * g + R - 1) / R)),
+                               dim3(kBlock), 0, s, L.A.n, L.A.rp, L.A.ci, a, dinv, b, xp, x, done);
+        });
+        return;
+    }
     with_G(L.G, [&](auto gc) {
         constexpr int g = decltype(gc)::value;
         constexpr int R = 2;
@@ -532,6 +690,14 @@ void launch_coarse(hipStream_t s, const Level &L, int sweeps, const void *b, voi
     double *ta = (double *)tmp_a, *tb = (double *)tmp_b;
     if (b_f64 && x_f64) coarse_t<double, double>(s, L, sweeps, (const double *)b, (double *)x, ta, tb, done);
     else coarse_t<float, float>(s, L, sweeps, (const float *)b, (float *)x, ta, tb, done);
+}
+
+void launch_tail(hipStream_t s, int fp32, int kt, int nl, const TailLevel *tl, const Level &C, int sweeps,
+                 const double *done) {
+    if (fp32)
+        hipLaunchKernelGGL((k_tail<float>), dim3(1), dim3(1024), 0, s, kt, nl, tl, C.S, C.dinv, C.A.v, sweeps, done);
+    else
+        hipLaunchKernelGGL((k_tail<double>), dim3(1), dim3(1024), 0, s, kt, nl, tl, C.S, C.dinv, C.A.v, sweeps, done);
 }
 
 void launch_coarse_build(hipStream_t s, const Level &L, int sweeps, double *S) {
