@@ -250,7 +250,7 @@ int build_hierarchy(bcm_handle *h, const bcm_csr *Ain, const double *win) {
     const bool fp32 = P.precision == BCM_FP32_CYCLE;
     // device memory: persistent hierarchy, level-lifetime and sweep-lifetime scratch
     const double z = nnz, nn = n;
-    h->persist.reserve((size_t)(1.5 * (16.0 * z + 48.0 * nn) + 64.0 * nn) + (size_t(4) << 20));
+    h->persist.reserve((size_t)(1.5 * (16.0 * z + 48.0 * nn) + 64.0 * nn + 1.3 * 24.0 * z) + (size_t(4) << 20));
     Arena keep, tmp;
     keep.alloc = tmp.alloc = P.alloc;
     keep.dealloc = tmp.dealloc = P.dealloc;
@@ -367,6 +367,39 @@ int build_hierarchy(bcm_handle *h, const bcm_csr *Ain, const double *win) {
         }
     }
     {
+        // sliced ELL copies: the finest level (flexible CG products) and every
+        // level that runs the split up leg
+        std::vector<int> lv_sell;
+        for (int l = 0; l < h->nl; ++l)
+            if (l == 0 || h->lv[l].xp) lv_sell.push_back(l);
+        std::vector<int *> cnts(lv_sell.size());
+        int *tot = h->persist.get_n<int>(64);
+        NOMEM(tot);
+        for (size_t t = 0; t < lv_sell.size(); ++t) {
+            Level &L = h->lv[lv_sell[t]];
+            const int ns = (L.A.n + kSlice - 1) / kSlice;
+            L.E.nslices = ns;
+            L.E.sp = h->persist.get_n<int>((size_t)ns + 1);
+            void *stmp = keep.get(scan_tmp_bytes(ns));
+            NOMEM(L.E.sp && stmp);
+            launch_sell_width(s, L.A.n, L.A.rp, L.E.sp);
+            scan_exclusive(s, L.E.sp, L.E.sp, ns, L.E.sp + ns, stmp);  // sp[ns] = total slots
+            HIPCHK(hipMemcpyAsync(tot + t, L.E.sp + ns, sizeof(int), hipMemcpyDeviceToDevice, s));
+        }
+        int tots[64];
+        int rc = read_back(s, tot, sizeof(int) * lv_sell.size(), tots);
+        if (rc) return rc;
+        for (size_t t = 0; t < lv_sell.size(); ++t) {
+            Level &L = h->lv[lv_sell[t]];
+            const size_t ne = (size_t)tots[t];
+            L.E.sc = h->persist.get_n<int>(ne);
+            L.E.sv = h->persist.get_n<double>(ne);
+            if (fp32) L.E.sv32 = h->persist.get_n<float>(ne);
+            NOMEM(L.E.sc && L.E.sv && (!fp32 || L.E.sv32));
+            launch_sell_fill(s, L.A.n, L.A.rp, L.A.ci, L.A.v, L.E.sp, L.E.sc, L.E.sv, L.E.sv32);
+        }
+    }
+    {
         // coarsest level: precompute the sweep operator when it is small
         Level &C = h->lv[h->nl - 1];
         if (C.A.n <= kCoarseDense) {
@@ -425,12 +458,15 @@ int build_hierarchy(bcm_handle *h, const bcm_csr *Ain, const double *win) {
 
 // --------------------------------------------------------------- byte model
 // Algorithmic bytes (every array touched once; gathers assumed cached).
+// down leg: fused k_down_*, or residual + restriction on large levels (p r written and read once)
 double bytes_down(const bcm_handle *h, int k) {
     const Level &L = h->lv[k];
     const bool f32 = h->prm.precision == BCM_FP32_CYCLE;
     const double sv = f32 ? 4 : 8, sb = (k == 0 || !f32) ? 8 : 4;
     const double n = L.A.n, z = L.A.nnz, nc = L.nc;
-    return 4 * (n + 1) + (4 + sv) * z + sb * n + 2 * sv * n + 4.0 * nc * L.mstride + sv * nc;
+    const double base = 4 * (n + 1) + (4 + sv) * z + sb * n + 2 * sv * n + 4.0 * nc * L.mstride + sv * nc;
+    if (L.E.sp && L.xp && (L.mstride == 2 || L.mstride == 4)) return base + 2 * sv * n;
+    return base;
 }
 // up leg: fused k_up, or k_prolong + k_smooth on large levels (xp written and read once)
 double bytes_up(const bcm_handle *h, int k) {
@@ -450,7 +486,7 @@ double bytes_coarse(const bcm_handle *h) {
 }
 double bytes_spmv_dots(const bcm_handle *h) {
     const double n = h->lv[0].A.n, z = h->lv[0].A.nnz;
-    return 4 * (n + 1) + 12 * z + 32 * n;
+    return 4 * (n + 1) + 12 * z + 32 * n;  // algorithmic: CSR entries once (ELL padding not counted)
 }
 double bytes_update(const bcm_handle *h) { return 80.0 * h->lv[0].A.n; }
 

@@ -57,12 +57,26 @@ struct Csr {
     float *v32 = nullptr;
 };
 
+// Sliced ELL copy of a CSR matrix for the row-parallel solve kernels: rows in
+// slices of 64 (one wave), slice s holds width w_s = its longest row; entry k
+// of row 64 s + l sits at sp[s] + 64 k + l.  Rows keep their CSR column order
+// and are padded with (col = row, value = 0), so a row sum taken left to right
+// equals the CSR one.
+constexpr int kSlice = 64;
+struct Sell {
+    int nslices = 0;
+    int *sp = nullptr, *sc = nullptr;
+    double *sv = nullptr;
+    float *sv32 = nullptr;
+};
+
 // One level of the hierarchy.  Row i of A^k, its l1 inverse diagonal, the
 // composed prolongator P^k (one nonzero per row: column agg[i], value p[i]),
 // and the members of every coarse aggregate (P^k transposed) in ascending
 // order, mstride slots per aggregate padded with -1.
 struct Level {
     Csr A;
+    Sell E;  // sliced ELL copy (finest level, and levels that run the split up leg)
     double *w = nullptr;
     double *dinv = nullptr;
     float *dinv32 = nullptr;
@@ -151,6 +165,10 @@ void launch_compose(hipStream_t s, int n, int nc_new, const int *agg_prev, const
 void launch_diag_l1(hipStream_t s, int G, int n, const int *rp, const double *v, double *dinv,
                     float *dinv32);
 void launch_cast(hipStream_t s, size_t n, const double *src, float *dst);
+// slice widths (64 * longest row of each slice) -> cnt[nslices]
+void launch_sell_width(hipStream_t s, int n, const int *rp, int *cnt);
+void launch_sell_fill(hipStream_t s, int n, const int *rp, const int *ci, const double *v, const int *sp, int *sc,
+                      double *sv, float *sv32);
 void launch_fill_i32(hipStream_t s, size_t n, int *dst, int val);
 void launch_fill_u64(hipStream_t s, size_t n, unsigned long long *dst, unsigned long long val);
 void launch_copy_f64(hipStream_t s, size_t n, const double *src, double *dst);
@@ -182,6 +200,11 @@ void launch_spmv_dots(hipStream_t s, const Level &L, int nb, int first, const do
                       const double *q, double *v, double *partials, double *scal);
 void launch_update(hipStream_t s, int n, int nb, int first, const double *w, const double *v,
                    double *d, double *u, double *q, double *r, double *partials, double *scal);
+// sliced-ELL variants of the row-parallel solve kernels (level must hold E)
+void launch_resid_sell(hipStream_t s, const Level &L, int nb, const double *b, const double *u, double *r,
+                       double *partials, double *scal);
+void launch_spmv_dots_sell(hipStream_t s, const Level &L, int nb, int first, const double *w, const double *r,
+                           const double *q, double *v, double *partials, double *scal);
 void launch_sampled_outer(hipStream_t s, const Level &L, const double *lam, const double *x,
                           double *G);
 int reduce_blocks(int n);

@@ -420,6 +420,37 @@ k_diag_l1(int n, const int *__restrict__ rp, const double *__restrict__ v, doubl
     }
 }
 
+// Sliced ELL: width of slice s (times 64) = 64 * max row length over its rows.
+__global__ void __launch_bounds__(kBlock) k_sell_width(int n, const int *__restrict__ rp, int *__restrict__ cnt) {
+    const int sl = blockIdx.x * kBlock + threadIdx.x;
+    const int ns = (n + kSlice - 1) / kSlice;
+    if (sl >= ns) return;
+    int w = 0;
+    const int r1 = min(n, (sl + 1) * kSlice);
+    for (int i = sl * kSlice; i < r1; ++i) w = max(w, rp[i + 1] - rp[i]);
+    cnt[sl] = w * kSlice;
+}
+
+// One thread per row writes its entries in column-major slot order; padding
+// slots get (col = row, value = 0).
+__global__ void __launch_bounds__(kBlock)
+k_sell_fill(int n, const int *__restrict__ rp, const int *__restrict__ ci, const double *__restrict__ v,
+            const int *__restrict__ sp, int *__restrict__ sc, double *__restrict__ sv, float *__restrict__ sv32) {
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const int sl = i / kSlice, lane = i % kSlice;
+    const int base = sp[sl] + lane, w = (sp[sl + 1] - sp[sl]) / kSlice;
+    const int q0 = rp[i], len = rp[i + 1] - q0;
+    for (int k = 0; k < w; ++k) {
+        const bool in = k < len;
+        const int col = in ? ci[q0 + k] : i;
+        const double val = in ? v[q0 + k] : 0.0;
+        sc[base + k * kSlice] = col;
+        sv[base + k * kSlice] = val;
+        if (sv32) sv32[base + k * kSlice] = (float)val;
+    }
+}
+
 __global__ void k_cast(size_t n, const double *__restrict__ src, float *__restrict__ dst) {
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
         dst[i] = (float)src[i];
@@ -531,6 +562,16 @@ void launch_diag_l1(hipStream_t s, int G, int n, const int *rp, const double *v,
         hipLaunchKernelGGL(k_diag_l1<g>, dim3(blocks_for((long long)n * g)), dim3(kBlock), 0, s, n, rp, v, dinv,
                            dinv32);
     });
+}
+
+void launch_sell_width(hipStream_t s, int n, const int *rp, int *cnt) {
+    const int ns = (n + kSlice - 1) / kSlice;
+    hipLaunchKernelGGL(k_sell_width, dim3(blocks_for(ns)), dim3(kBlock), 0, s, n, rp, cnt);
+}
+
+void launch_sell_fill(hipStream_t s, int n, const int *rp, const int *ci, const double *v, const int *sp, int *sc,
+                      double *sv, float *sv32) {
+    hipLaunchKernelGGL(k_sell_fill, dim3(blocks_for(n)), dim3(kBlock), 0, s, n, rp, ci, v, sp, sc, sv, sv32);
 }
 
 void launch_cast(hipStream_t s, size_t n, const double *src, float *dst) {

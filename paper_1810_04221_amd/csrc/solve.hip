@@ -62,6 +62,22 @@ __device__ __forceinline__ void rows_dot(const int *__restrict__ rp, const int *
     for (int k = 0; k < R; ++k) s[k] = group_sum<G>(s[k]);
 }
 
+// Row i of a sliced ELL matrix: sum_k a_k * f(col_k), left to right over the
+// row's slots (CSR order, then zero padding).  Lane i % 64 of a wave owns row i,
+// so every slot load of the wave is one contiguous 256/512-byte access.
+template <typename V, typename F>
+__device__ __forceinline__ V sell_row(const int *__restrict__ sp, const int *__restrict__ sc,
+                                      const V *__restrict__ sv, int i, F f) {
+    const int sl = i / kSlice, lane = i % kSlice;
+    const int beg = sp[sl], w = (sp[sl + 1] - beg) / kSlice;
+    const int *c = sc + beg + lane;
+    const V *a = sv + beg + lane;
+    V s = V(0);
+#pragma unroll 8
+    for (int k = 0; k < w; ++k) s += a[k * kSlice] * f(c[k * kSlice]);
+    return s;
+}
+
 // ----------------------------------------------------------------------------
 // Down leg of the cycle at level k (Algorithm 1, zero initial guess):
 //   x = x + M^{-1}(b - A x) with x = 0   ->  x_j = dinv_j * b_j
@@ -122,6 +138,38 @@ k_down_loop(int nc, int mstride, const int *__restrict__ mem, const int *__restr
         acc += p[i] * ((V)b[i] - s);
     }
     if (lane == 0) bc[E] = acc;
+}
+
+// Large levels: the down leg as a row-parallel residual on the sliced ELL copy,
+//   pr_i = p_i (b_i - sum_j a_ij dinv_j b_j),
+// followed by the restriction b_c[E] = sum of pr over E's members in ascending
+// order (the order a serial P^T r takes).
+template <typename V, typename VB>
+__global__ void __launch_bounds__(kBlock)
+k_down_res_sell(int n, const int *__restrict__ sp, const int *__restrict__ sc, const V *__restrict__ sv,
+                const V *__restrict__ dinv, const V *__restrict__ p, const VB *__restrict__ b, V *__restrict__ pr,
+                const double *__restrict__ done) {
+    if (done && *done != 0.0) return;
+    const int i = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const V s = sell_row<V>(sp, sc, sv, i, [&](int j) { return dinv[j] * (V)b[j]; });
+    pr[i] = p[i] * ((V)b[i] - s);
+}
+
+template <typename V, int S>
+__global__ void __launch_bounds__(kBlock)
+k_restrict(int nc, const int *__restrict__ mem, const V *__restrict__ pr, V *__restrict__ bc,
+           const double *__restrict__ done) {
+    if (done && *done != 0.0) return;
+    const int E = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    if (E >= nc) return;
+    int m[S];
+#pragma unroll
+    for (int t = 0; t < S; ++t) m[t] = mem[(size_t)E * S + t];
+    V acc = V(0);
+#pragma unroll
+    for (int t = 0; t < S; ++t) acc += m[t] >= 0 ? pr[m[t]] : V(0);
+    bc[E] = acc;
 }
 
 // ----------------------------------------------------------------------------
@@ -191,6 +239,19 @@ k_smooth(int n, const int *__restrict__ rp, const int *__restrict__ ci, const V 
         const int i = rows[k];
         if (lane == k % G && i >= 0) x[i] = (VX)(xp[i] + dinv[i] * ((V)b[i] - s[k]));
     }
+}
+
+// k_smooth on the sliced ELL copy, one thread per row.
+template <typename V, typename VB, typename VX>
+__global__ void __launch_bounds__(kBlock)
+k_smooth_sell(int n, const int *__restrict__ sp, const int *__restrict__ sc, const V *__restrict__ sv,
+              const V *__restrict__ dinv, const VB *__restrict__ b, const V *__restrict__ xp, VX *__restrict__ x,
+              const double *__restrict__ done) {
+    if (done && *done != 0.0) return;
+    const int i = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const V s = sell_row<V>(sp, sc, sv, i, [&](int j) { return xp[j]; });
+    x[i] = (VX)(xp[i] + dinv[i] * ((V)b[i] - s));
 }
 
 // ----------------------------------------------------------------------------
@@ -488,6 +549,43 @@ k_spmv_dots(int n, const int *__restrict__ rp, const int *__restrict__ ci, const
     block_partials<3>(acc, partials);
 }
 
+// Sliced-ELL variants: one thread per row, grid-stride; each row sum is taken
+// left to right exactly as a serial CSR product.
+__global__ void __launch_bounds__(kBlock)
+k_resid_sell(int n, const int *__restrict__ sp, const int *__restrict__ sc, const double *__restrict__ sv,
+             const double *__restrict__ b, const double *__restrict__ u, double *__restrict__ r,
+             double *__restrict__ partials) {
+    const int blk = xcd_block(blockIdx.x, gridDim.x);
+    double acc[2] = {0.0, 0.0};
+    for (int i = blk * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+        const double s = sell_row<double>(sp, sc, sv, i, [&](int j) { return u[j]; });
+        const double bi = b[i];
+        const double ri = bi - s;
+        r[i] = ri;
+        acc[0] += ri * ri;
+        acc[1] += bi * bi;
+    }
+    block_partials<2>(acc, partials);
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_spmv_dots_sell(int n, const int *__restrict__ sp, const int *__restrict__ sc, const double *__restrict__ sv,
+                 const double *__restrict__ w, const double *__restrict__ r, const double *__restrict__ q,
+                 double *__restrict__ v, double *__restrict__ partials, const double *__restrict__ done) {
+    if (done && *done != 0.0) return;
+    const int blk = xcd_block(blockIdx.x, gridDim.x);
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (int i = blk * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+        const double s = sell_row<double>(sp, sc, sv, i, [&](int j) { return w[j]; });
+        const double wi = w[i];
+        v[i] = s;
+        acc[0] += wi * r[i];
+        acc[1] += wi * s;
+        acc[2] += wi * q[i];
+    }
+    block_partials<3>(acc, partials);
+}
+
 // Finalize: sums the block partials in block order, then
 //   mode 0 (residual):  scal[4] = ||r||^2, scal[5] = ||b||^2
 //   mode 1 (dots):      alpha, beta, gamma and the scalars of Algorithm 3:
@@ -600,6 +698,19 @@ void down_dispatch(hipStream_t s, const Level &L, const V *a, const V *dinv, con
 template <typename V, typename VB>
 void down_t(hipStream_t s, const Level &L, const V *a, const V *dinv, const V *p, const VB *b, V *bc,
             const double *done) {
+    if (L.E.sp && L.xp && (L.mstride == 2 || L.mstride == 4)) {
+        V *pr = (V *)L.xp;  // free during the down leg: the up leg of this level runs later
+        const V *sv = std::is_same<V, float>::value ? (const V *)L.E.sv32 : (const V *)L.E.sv;
+        hipLaunchKernelGGL((k_down_res_sell<V, VB>), dim3(blocks_for(L.A.n)), dim3(kBlock), 0, s, L.A.n, L.E.sp,
+                           L.E.sc, sv, dinv, p, b, pr, done);
+        if (L.mstride == 4)
+            hipLaunchKernelGGL((k_restrict<V, 4>), dim3(blocks_for(L.nc)), dim3(kBlock), 0, s, L.nc, L.mem, pr, bc,
+                               done);
+        else
+            hipLaunchKernelGGL((k_restrict<V, 2>), dim3(blocks_for(L.nc)), dim3(kBlock), 0, s, L.nc, L.mem, pr, bc,
+                               done);
+        return;
+    }
     with_G(L.G, [&](auto gc) {
         constexpr int g = decltype(gc)::value;
         down_dispatch<g, V, VB>(s, L, a, dinv, p, b, bc, done);
@@ -613,6 +724,12 @@ void up_t(hipStream_t s, const Level &L, const V *a, const V *dinv, const V *p, 
         V *xp = (V *)L.xp;
         hipLaunchKernelGGL((k_prolong<V, VB>), dim3(blocks_for(L.A.n)), dim3(kBlock), 0, s, L.A.n, dinv, p, L.agg, b,
                            xc, xp, done);
+        if (L.E.sp) {
+            const V *sv = std::is_same<V, float>::value ? (const V *)L.E.sv32 : (const V *)L.E.sv;
+            hipLaunchKernelGGL((k_smooth_sell<V, VB, VX>), dim3(blocks_for(L.A.n)), dim3(kBlock), 0, s, L.A.n, L.E.sp,
+                               L.E.sc, sv, dinv, b, xp, x, done);
+            return;
+        }
         with_G(L.G, [&](auto gc) {
             constexpr int g = decltype(gc)::value;
             constexpr int R = 2;
@@ -707,6 +824,12 @@ void launch_coarse_build(hipStream_t s, const Level &L, int sweeps, double *S) {
 
 void launch_resid(hipStream_t s, const Level &L, int nb, const double *b, const double *u, double *r,
                   double *partials, double *scal) {
+    if (L.E.sp) {
+        hipLaunchKernelGGL(k_resid_sell, dim3(nb), dim3(kBlock), 0, s, L.A.n, L.E.sp, L.E.sc, L.E.sv, b, u, r,
+                           partials);
+        hipLaunchKernelGGL(k_finalize<2>, dim3(1), dim3(kBlock), 0, s, nb, partials, scal, 0, 0);
+        return;
+    }
     with_G(L.G, [&](auto gc) {
         constexpr int g = decltype(gc)::value;
         hipLaunchKernelGGL(k_resid<g>, dim3(nb), dim3(kBlock), 0, s, L.A.n, L.A.rp, L.A.ci, L.A.v, b, u, r,
@@ -717,6 +840,12 @@ void launch_resid(hipStream_t s, const Level &L, int nb, const double *b, const 
 
 void launch_spmv_dots(hipStream_t s, const Level &L, int nb, int first, const double *w, const double *r,
                       const double *q, double *v, double *partials, double *scal) {
+    if (L.E.sp) {
+        hipLaunchKernelGGL(k_spmv_dots_sell, dim3(nb), dim3(kBlock), 0, s, L.A.n, L.E.sp, L.E.sc, L.E.sv, w, r, q, v,
+                           partials, scal + 10);
+        hipLaunchKernelGGL(k_finalize<3>, dim3(1), dim3(kBlock), 0, s, nb, partials, scal, 1, first);
+        return;
+    }
     with_G(L.G, [&](auto gc) {
         constexpr int g = decltype(gc)::value;
         hipLaunchKernelGGL(k_spmv_dots<g>, dim3(nb), dim3(kBlock), 0, s, L.A.n, L.A.rp, L.A.ci, L.A.v, w, r, q, v,
