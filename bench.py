@@ -45,6 +45,8 @@ def main():
     ap.add_argument("--workload", default="G2")
     ap.add_argument("--scale", type=float, default=1.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibration-copy-mb", type=int, default=0,
+                    help="run one device copy of this many MiB first (reference for HBM counters)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -68,6 +70,14 @@ def main():
     w = torch.as_tensor(c["w"], device=dev)
     b = torch.as_tensor(c["b"], device=dev)
     torch.cuda.synchronize()
+    if args.calibration_copy_mb:
+        src = torch.empty(args.calibration_copy_mb << 17, dtype=torch.float64, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"calibration copy: {args.calibration_copy_mb} MiB read + written")
+        del src, dst
 
     def step(precision, mask):
         h = bcm.Hierarchy(rp, ci, va, w, max_coarse=c["max_coarse"], precision=precision, profile=mask)
