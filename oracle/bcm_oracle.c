@@ -61,7 +61,7 @@ typedef struct {
 typedef struct {
     int nl;
     int coarse_sweeps;
-    int cycle; /* 1 = V, 2 = W */
+    int cycle; /* coarse corrections per level: 1 = V-cycle, 2 = W-cycle */
     olevel lv[ORA_MAXLEV];
     /* per-level statistics of the last setup */
     int npairs[ORA_MAXLEV][8];
@@ -472,29 +472,43 @@ static void jacobi_sweep(const olevel *L, const double *b, double *x, double *r)
     for (int i = 0; i < L->A.n; i++) x[i] = x[i] + L->dinv[i] * r[i];
 }
 
-/* cycle(k): on entry L->b holds the right-hand side and L->x the initial guess */
+/*
+ * cycle(k) (Algorithm 1; W-cycle for h->cycle = 2): on entry L->b holds the
+ * right-hand side; on exit L->x holds the result, from a zero initial guess.
+ * The coarse problem A^{k+1} x_c = P^T r is solved by h->cycle successive
+ * cycles: x_c = cycle(b_c), then x_c = x_c + cycle(b_c - A^{k+1} x_c).
+ */
 static void cycle(ohier *h, int k) {
     olevel *L = &h->lv[k];
     int n = L->A.n;
+    memset(L->x, 0, sizeof(double) * (size_t)n);
     if (k == h->nl - 1) {
         for (int t = 0; t < h->coarse_sweeps; t++) jacobi_sweep(L, L->b, L->x, L->r);
         return;
     }
     olevel *C = &h->lv[k + 1];
+    int nc = C->A.n;
     /* pre-smoothing */
     jacobi_sweep(L, L->b, L->x, L->r);
-    for (int g = 0; g < h->cycle; g++) {
-        /* restriction of the residual: b_c = P^T (b - A x) */
-        spmv(&L->A, L->x, L->r);
-        for (int i = 0; i < n; i++) L->r[i] = L->b[i] - L->r[i];
-        for (int e = 0; e < C->A.n; e++) C->b[e] = 0.0;
-        for (int i = 0; i < n; i++) C->b[L->agg[i]] = C->b[L->agg[i]] + L->p[i] * L->r[i];
-        /* coarse correction from zero */
-        for (int e = 0; e < C->A.n; e++) C->x[e] = 0.0;
+    /* restriction of the residual: b_c = P^T (b - A x) */
+    spmv(&L->A, L->x, L->r);
+    for (int i = 0; i < n; i++) L->r[i] = L->b[i] - L->r[i];
+    double *bc = xmalloc(sizeof(double) * (size_t)nc), *xc = xmalloc(sizeof(double) * (size_t)nc);
+    for (int e = 0; e < nc; e++) bc[e] = 0.0;
+    for (int i = 0; i < n; i++) bc[L->agg[i]] = bc[L->agg[i]] + L->p[i] * L->r[i];
+    /* coarse correction: h->cycle cycles on the coarse problem */
+    memcpy(C->b, bc, sizeof(double) * (size_t)nc);
+    cycle(h, k + 1);
+    memcpy(xc, C->x, sizeof(double) * (size_t)nc);
+    for (int g = 1; g < h->cycle; g++) {
+        spmv(&C->A, xc, C->b);
+        for (int e = 0; e < nc; e++) C->b[e] = bc[e] - C->b[e];
         cycle(h, k + 1);
-        /* prolongation: x = x + P x_c */
-        for (int i = 0; i < n; i++) L->x[i] = L->x[i] + L->p[i] * C->x[L->agg[i]];
+        for (int e = 0; e < nc; e++) xc[e] = xc[e] + C->x[e];
     }
+    /* prolongation: x = x + P x_c */
+    for (int i = 0; i < n; i++) L->x[i] = L->x[i] + L->p[i] * xc[L->agg[i]];
+    free(bc); free(xc);
     /* post-smoothing (M^{-T} = M^{-1} for a diagonal M) */
     jacobi_sweep(L, L->b, L->x, L->r);
 }
@@ -504,7 +518,6 @@ int ora_vcycle(void *hv, const double *b, double *x) {
     ohier *h = hv;
     olevel *L = &h->lv[0];
     memcpy(L->b, b, sizeof(double) * (size_t)L->A.n);
-    memset(L->x, 0, sizeof(double) * (size_t)L->A.n);
     cycle(h, 0);
     memcpy(x, L->x, sizeof(double) * (size_t)L->A.n);
     return 0;

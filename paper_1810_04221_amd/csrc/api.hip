@@ -191,9 +191,14 @@ int match_sweep(hipStream_t s, Arena &tmp, const Csr &A, const double *w, int ch
 }
 
 // One pairwise sweep on (A, w): matching, Algorithm 2, prolongator, Galerkin.
-// Outputs that outlive the sweep come from `keep`.  out.nc == A.n means that
-// no pair was formed (nothing else is produced then).
-int pairwise_sweep(hipStream_t s, Arena &tmp, Arena &keep, const Csr &A, const double *w, SweepOut &out) {
+// Outputs that outlive the sweep come from `keep`, except that the coarse
+// matrix and w come from finA and the prolongator from finP when those are
+// given (the level's final outputs, allocated where they stay).  out.nc == A.n
+// means that no pair was formed (nothing else is produced then).
+int pairwise_sweep(hipStream_t s, Arena &tmp, Arena &keep, const Csr &A, const double *w, SweepOut &out,
+                   Arena *finA, Arena *finP) {
+    Arena &oa = finA ? *finA : keep;
+    Arena &op = finP ? *finP : keep;
     const int m = A.n, G = pick_G((double)A.nnz / std::max(1, m));
     int *mate = nullptr, *leader = nullptr;
     int rc = match_sweep(s, tmp, A, w, 0, &mate, &leader, nullptr);
@@ -208,14 +213,14 @@ int pairwise_sweep(hipStream_t s, Arena &tmp, Arena &keep, const Csr &A, const d
     if (rc) return rc;
     out.nc = nc;
     if (nc == m) return BCM_OK;
-    out.agg = keep.get_n<int>(m);
-    out.p = keep.get_n<double>(m);
-    out.wc = keep.get_n<double>(nc);
-    out.mem2 = keep.get_n<int>(2 * (size_t)nc);
+    out.agg = op.get_n<int>(m);
+    out.p = op.get_n<double>(m);
+    out.wc = oa.get_n<double>(nc);
+    out.mem2 = op.get_n<int>(2 * (size_t)nc);
     NOMEM(out.agg && out.p && out.wc && out.mem2);
     launch_aggfill(s, m, mate, ofs, w, out.agg, out.p, out.wc, out.mem2);
     // Galerkin product: count, scan to row pointers, fill
-    int *crp = keep.get_n<int>((size_t)nc + 1);
+    int *crp = oa.get_n<int>((size_t)nc + 1);
     int *gF = tmp.get_n<int>(A.nnz);
     int *gU = tmp.get_n<int>(A.nnz);
     void *stmp2 = tmp.get(scan_tmp_bytes(nc));
@@ -228,8 +233,8 @@ int pairwise_sweep(hipStream_t s, Arena &tmp, Arena &keep, const Csr &A, const d
     out.Ac.n = nc;
     out.Ac.nnz = cnnz;
     out.Ac.rp = crp;
-    out.Ac.ci = keep.get_n<int>(cnnz);
-    out.Ac.v = keep.get_n<double>(cnnz);
+    out.Ac.ci = oa.get_n<int>(cnnz);
+    out.Ac.v = oa.get_n<double>(cnnz);
     NOMEM(out.Ac.ci && out.Ac.v);
     launch_gal_fill(s, G, nc, A.rp, A.ci, A.v, out.agg, out.p, out.mem2, crp, out.Ac.ci, out.Ac.v, gF, gU);
     HIPCHK(hipGetLastError());
@@ -298,18 +303,22 @@ int build_hierarchy(bcm_handle *h, const bcm_csr *Ain, const double *win) {
         int *cagg = nullptr, *cmem = nullptr;
         double *cp = nullptr;
         int cstride = 1;
+        bool final_done = false;  // the last sweep ran: its outputs already live in persist
         for (int sw = 0; sw < P.sweeps; ++sw) {
             tmp.rewind();
             SweepOut so;
-            int rc = pairwise_sweep(s, tmp, keep, Acur, wcur, so);
+            const bool last = sw == P.sweeps - 1;
+            int rc = pairwise_sweep(s, tmp, keep, Acur, wcur, so, last ? &h->persist : nullptr,
+                                    last && !have ? &h->persist : nullptr);
             if (rc) return rc;
             if (so.nc == Acur.n) break;  // no pair formed: further sweeps would not either
             if (!have) {
                 cagg = so.agg; cp = so.p; cmem = so.mem2; cstride = 2;
             } else {
-                int *nagg = keep.get_n<int>(nk);
-                double *np_ = keep.get_n<double>(nk);
-                int *nmem = keep.get_n<int>((size_t)so.nc * 2 * cstride);
+                Arena &ca = last ? h->persist : keep;
+                int *nagg = ca.get_n<int>(nk);
+                double *np_ = ca.get_n<double>(nk);
+                int *nmem = ca.get_n<int>((size_t)so.nc * 2 * cstride);
                 NOMEM(nagg && np_ && nmem);
                 launch_compose(s, nk, so.nc, cagg, cp, cmem, cstride, so.agg, so.p, so.mem2, nagg, np_, nmem);
                 cagg = nagg; cp = np_; cmem = nmem; cstride *= 2;
@@ -317,20 +326,26 @@ int build_hierarchy(bcm_handle *h, const bcm_csr *Ain, const double *win) {
             Acur = so.Ac;
             wcur = so.wc;
             have = true;
+            final_done = last;
         }
         if (!have) break;  // stagnation: level k is the coarsest
         Level &C = h->lv[k + 1];
         C.A.n = Acur.n;
         C.A.nnz = Acur.nnz;
-        C.A.rp = persist_copy(h, Acur.rp, (size_t)Acur.n + 1);
-        C.A.ci = persist_copy(h, Acur.ci, (size_t)Acur.nnz);
-        C.A.v = persist_copy(h, Acur.v, (size_t)Acur.nnz);
-        C.w = persist_copy(h, wcur, (size_t)Acur.n);
         L.nc = Acur.n;
-        L.agg = persist_copy(h, cagg, (size_t)nk);
-        L.p = persist_copy(h, cp, (size_t)nk);
         L.mstride = cstride;
-        L.mem = persist_copy(h, cmem, (size_t)Acur.n * cstride);
+        if (final_done) {
+            C.A.rp = Acur.rp; C.A.ci = Acur.ci; C.A.v = Acur.v; C.w = const_cast<double *>(wcur);
+            L.agg = cagg; L.p = cp; L.mem = cmem;
+        } else {  // a later sweep formed no pair: the outputs are still in level scratch
+            C.A.rp = persist_copy(h, Acur.rp, (size_t)Acur.n + 1);
+            C.A.ci = persist_copy(h, Acur.ci, (size_t)Acur.nnz);
+            C.A.v = persist_copy(h, Acur.v, (size_t)Acur.nnz);
+            C.w = persist_copy(h, wcur, (size_t)Acur.n);
+            L.agg = persist_copy(h, cagg, (size_t)nk);
+            L.p = persist_copy(h, cp, (size_t)nk);
+            L.mem = persist_copy(h, cmem, (size_t)Acur.n * cstride);
+        }
         NOMEM(C.A.rp && C.A.ci && C.A.v && C.w && L.agg && L.p && L.mem);
         HIPCHK(hipStreamSynchronize(s));  // keep/tmp are rewound next
         ++k;

@@ -85,6 +85,40 @@ __global__ void __launch_bounds__(kBlock) k_scan_add(int *__restrict__ out, int 
     }
 }
 
+// Whole scan in one workgroup of 1024 threads for n <= kScanSmall: thread t
+// owns items [t K, t K + K), K = ceil(n / 1024).
+constexpr int kScanSmall = 16384;
+
+__global__ void __launch_bounds__(1024) k_scan_single(const int *__restrict__ in, int *__restrict__ out, int n,
+                                                        int *__restrict__ total) {
+    __shared__ int wsum[16];
+    const int K = (n + 1023) / 1024;
+    const int b = threadIdx.x * K;
+    int v[kScanSmall / 1024];
+    int s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanSmall / 1024; ++k) {
+        v[k] = (k < K && b + k < n) ? in[b + k] : 0;
+        s += v[k];
+    }
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int inc = wave_incl(s);
+    if (lane == 63) wsum[wid] = inc;
+    __syncthreads();
+    int base = 0, tot = 0;
+    for (int w = 0; w < 16; ++w) {
+        if (w < wid) base += wsum[w];
+        tot += wsum[w];
+    }
+    int run = base + inc - s;
+#pragma unroll
+    for (int k = 0; k < kScanSmall / 1024; ++k) {
+        if (k < K && b + k < n) out[b + k] = run;
+        run += v[k];
+    }
+    if (threadIdx.x == 0) *total = tot;
+}
+
 }  // namespace
 
 size_t scan_tmp_bytes(int n) { return sizeof(int) * (size_t)((n + kTile - 1) / kTile + 1); }
@@ -94,6 +128,10 @@ void scan_exclusive(hipStream_t s, const int *in, int *out, int n, int *total_de
     int *tsum = static_cast<int *>(tmp);
     if (nt == 0) {
         launch_fill_i32(s, 1, total_dev, 0);
+        return;
+    }
+    if (n <= kScanSmall) {
+        hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(1024), 0, s, in, out, n, total_dev);
         return;
     }
     hipLaunchKernelGGL(k_scan_tiles, dim3(nt), dim3(kBlock), 0, s, in, out, n, tsum);

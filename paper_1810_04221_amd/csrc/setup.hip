@@ -250,62 +250,19 @@ k_aggfill(int n, const int *__restrict__ mate, const int *__restrict__ ofs, cons
 // The candidate columns F = agg[j] of E's member rows are staged in LDS
 // (16 G per group; longer rows fall back to scratch arrays indexed by the
 // candidate's position in A).  Pass 0 counts distinct columns; pass 1 writes
-// them in ascending order and the value of each entry:
+// them in ascending order and the value of each entry, whose terms are the
+// (at most four) staged candidates with the same column:
 //   (A_c)_EF = sum over stored (i in E, j in F) of (p_m * a_ij) * p_M,
 //   m = min(i, j), M = max(i, j), summed from the first term in ascending
 //   (m, M).  Terms sharing (m, M) (i <-> j inside one aggregate) are
 //   bitwise equal, so the sum is exactly symmetric and independent of timing.
 // ----------------------------------------------------------------------------
-__device__ __forceinline__ int find_col(const int *__restrict__ rp, const int *__restrict__ ci, int i,
-                                        int j) {
-    int lo = rp[i], hi = rp[i + 1] - 1;
-    while (lo <= hi) {
-        const int mid = (lo + hi) >> 1;
-        const int cm = ci[mid];
-        if (cm == j) return mid;
-        if (cm < j) lo = mid + 1; else hi = mid - 1;
-    }
-    return -1;
-}
-
 __device__ __forceinline__ void cswap(unsigned long long &ka, double &ta, unsigned long long &kb,
                                       double &tb) {
     if (kb < ka) {
         const unsigned long long k = ka; ka = kb; kb = k;
         const double t = ta; ta = tb; tb = t;
     }
-}
-
-__device__ double gal_entry(int e0, int e1, int f0, int f1, const int *__restrict__ rp,
-                            const int *__restrict__ ci, const double *__restrict__ v,
-                            const double *__restrict__ p) {
-    const unsigned long long NONE = ~0ull;
-    unsigned long long k[4] = {NONE, NONE, NONE, NONE};
-    double t[4] = {0.0, 0.0, 0.0, 0.0};
-    const int es[2] = {e0, e1}, fs[2] = {f0, f1};
-#pragma unroll
-    for (int a = 0; a < 2; ++a) {
-#pragma unroll
-        for (int b = 0; b < 2; ++b) {
-            const int i = es[a], j = fs[b];
-            if (i < 0 || j < 0) continue;
-            const int q = find_col(rp, ci, i, j);
-            if (q < 0) continue;
-            const int m = min(i, j), M = max(i, j);
-            k[2 * a + b] = ((unsigned long long)(unsigned)m << 32) | (unsigned)M;
-            t[2 * a + b] = (p[m] * v[q]) * p[M];
-        }
-    }
-    cswap(k[0], t[0], k[1], t[1]);
-    cswap(k[2], t[2], k[3], t[3]);
-    cswap(k[0], t[0], k[2], t[2]);
-    cswap(k[1], t[1], k[3], t[3]);
-    cswap(k[1], t[1], k[2], t[2]);
-    double s = t[0];
-#pragma unroll
-    for (int r = 1; r < 4; ++r)
-        if (k[r] != NONE) s = s + t[r];
-    return s;
 }
 
 template <int G>
@@ -352,13 +309,49 @@ k_gal(int pass, int nc, const int *__restrict__ rp, const int *__restrict__ ci,
     }
     if (staged) wave_sync(); else __threadfence_block();
     const int base = crp[E];
+    const unsigned long long NONE = ~0ull;
     for (int k = lane; k < L; k += G) {
         if (!U[slot(k)]) continue;
         const int f = F[slot(k)];
-        int rank = 0;
-        for (int k2 = 0; k2 < L; ++k2) rank += (U[slot(k2)] && F[slot(k2)] < f) ? 1 : 0;
+        // rank among the distinct columns, and the (at most four) candidates of
+        // column f: one per stored (i in E, j in F)
+        int rank = 0, c0 = -1, c1 = -1, c2 = -1, c3 = -1;
+        for (int k2 = 0; k2 < L; ++k2) {
+            const int f2 = F[slot(k2)];
+            rank += (U[slot(k2)] && f2 < f) ? 1 : 0;
+            if (f2 == f) {
+                if (c0 < 0) c0 = k2;
+                else if (c1 < 0) c1 = k2;
+                else if (c2 < 0) c2 = k2;
+                else c3 = k2;
+            }
+        }
+        unsigned long long key[4];
+        double t[4];
+        const int cs[4] = {c0, c1, c2, c3};
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            key[r] = NONE;
+            t[r] = 0.0;
+            const int kk = cs[r];
+            if (kk < 0) continue;
+            const int q = kk < L0 ? s0 + kk : s1 + (kk - L0);
+            const int i = kk < L0 ? e0 : e1, j = ci[q];
+            const int m = min(i, j), M = max(i, j);
+            key[r] = ((unsigned long long)(unsigned)m << 32) | (unsigned)M;
+            t[r] = (p[m] * v[q]) * p[M];
+        }
+        cswap(key[0], t[0], key[1], t[1]);
+        cswap(key[2], t[2], key[3], t[3]);
+        cswap(key[0], t[0], key[2], t[2]);
+        cswap(key[1], t[1], key[3], t[3]);
+        cswap(key[1], t[1], key[2], t[2]);
+        double sum = t[0];
+#pragma unroll
+        for (int r = 1; r < 4; ++r)
+            if (key[r] != NONE) sum = sum + t[r];
         cci[base + rank] = f;
-        cv[base + rank] = gal_entry(e0, e1, mem2[2 * f], mem2[2 * f + 1], rp, ci, v, p);
+        cv[base + rank] = sum;
     }
 }
 

@@ -201,3 +201,59 @@ def test_gradient_matches_finite_differences(ora):
     d = rng.standard_normal(n)
     fdb = (loss(va, b + 1e-6 * d) - loss(va, b - 1e-6 * d)) / 2e-6
     assert abs(fdb - lam @ d) <= 1e-6 * abs(fdb)
+
+
+# ----------------------------------------------------------------------------- W-cycle
+def _dense_gamma_cycle(h, gamma):
+    """Recursive dense form of the cycle: the coarse problem is solved by gamma
+    cycles, the second on the coarse residual (Algorithm 1 with gamma = 2 for W)."""
+    levels = [h.level(k) for k in range(h.nl)]
+    mats = [_sp(L["rowptr"], L["col"], L["val"]).toarray() for L in levels]
+    D = [np.diag(1.0 / np.abs(M).sum(axis=1)) for M in mats]
+    Sc = _jacobi_poly(mats[-1], np.diag(D[-1]), 20)
+    Ps = []
+    for k in range(h.nl - 1):
+        L = levels[k]
+        Ps.append(sp.csr_matrix((L["p"], L["agg"], np.arange(L["n"] + 1)), shape=(L["n"], levels[k + 1]["n"])).toarray())
+
+    def B(k, b):
+        if k == h.nl - 1:
+            return Sc @ b
+        A = mats[k]
+        x1 = D[k] @ b
+        bc = Ps[k].T @ (b - A @ x1)
+        xc = B(k + 1, bc)
+        for _ in range(gamma - 1):
+            xc = xc + B(k + 1, bc - mats[k + 1] @ xc)
+        x2 = x1 + Ps[k] @ xc
+        return x2 + D[k] @ (b - A @ x2)
+
+    return B
+
+
+def test_w_cycle_dense_form_three_levels(ora):
+    rp, ci, va = P.poisson2d(16)
+    h = ora.Hierarchy(rp, ci, va, np.ones(256), max_coarse=16, cycle="W")
+    assert h.nl == 3
+    b = np.random.default_rng(8).standard_normal(256)
+    ref = _dense_gamma_cycle(h, 2)(0, b)
+    assert np.allclose(h.vcycle(b), ref, rtol=1e-12, atol=1e-13 * np.abs(ref).max())
+    hv = ora.Hierarchy(rp, ci, va, np.ones(256), max_coarse=16)
+    refv = _dense_gamma_cycle(hv, 1)(0, b)
+    assert np.allclose(hv.vcycle(b), refv, rtol=1e-12, atol=1e-13 * np.abs(refv).max())
+    assert not np.allclose(ref, refv)
+
+
+@pytest.mark.parametrize("name,scale", [("G1", 0.5), ("G2", 0.15), ("G3", 0.1)])
+def test_w_cycle_spd_and_fewer_iterations(ora, name, scale):
+    c = P.config(name, scale)
+    hw = ora.Hierarchy(c["rowptr"], c["col"], c["val"], c["w"], max_coarse=min(c["max_coarse"], 30), cycle="W")
+    hv = ora.Hierarchy(c["rowptr"], c["col"], c["val"], c["w"], max_coarse=min(c["max_coarse"], 30))
+    rng = np.random.default_rng(4)
+    x, y = rng.standard_normal(hw.n), rng.standard_normal(hw.n)
+    Bx, By = hw.vcycle(x), hw.vcycle(y)
+    assert abs(Bx @ y - x @ By) <= 1e-12 * abs(Bx @ y) + 1e-14 * np.linalg.norm(Bx) * np.linalg.norm(y)
+    assert Bx @ x > 0
+    _, iw = hw.solve(c["b"], tol=1e-8)
+    _, iv = hv.solve(c["b"], tol=1e-8)
+    assert iw["status"] == 0 and iw["iters"] <= iv["iters"]
