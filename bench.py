@@ -47,6 +47,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibration-copy-mb", type=int, default=0,
                     help="run one device copy of this many MiB first (reference for HBM counters)")
+    ap.add_argument("--ablation", choices=["miniwarp", "cycles"], default=None,
+                    help="instead of the benchmark line: time setup + solve under each lane-width "
+                         "setting (miniwarp) or each cycle type (cycles) and print one JSON line")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -79,13 +82,17 @@ def main():
         log(f"calibration copy: {args.calibration_copy_mb} MiB read + written")
         del src, dst
 
-    def step(precision, mask):
-        h = bcm.Hierarchy(rp, ci, va, w, max_coarse=c["max_coarse"], precision=precision, profile=mask)
+    def step(precision, mask, **kw):
+        h = bcm.Hierarchy(rp, ci, va, w, max_coarse=c["max_coarse"], precision=precision, profile=mask, **kw)
         h.solve(b, tol=tol)
         info = h.info()
         prof = {k: h.profile(k) for k in CLASSES if mask & bcm.PROF[k]}
         h.close()
         return info, prof
+
+    if args.ablation:
+        ablation(args, c, step)
+        return
 
     all_mask = sum(bcm.PROF.values())
     # warm-up, and the class with the largest share of solve time
@@ -174,6 +181,46 @@ def main():
         "roofline": roofline, "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+
+
+ABLATIONS = {
+    # lane width of the CSR row kernels (the paper's miniwarp), with and without
+    # the sliced-ELL copies of the finest and large levels
+    "miniwarp": [("rule (4..64 from nnz/row) + SELL", "fp64", dict(group=0, sell=True)),
+                 ("rule, CSR only", "fp64", dict(group=0, sell=False)),
+                 ("4 lanes, CSR only", "fp64", dict(group=4, sell=False)),
+                 ("8 lanes, CSR only", "fp64", dict(group=8, sell=False)),
+                 ("16 lanes, CSR only", "fp64", dict(group=16, sell=False)),
+                 ("32 lanes, CSR only", "fp64", dict(group=32, sell=False)),
+                 ("64 lanes (one wavefront per row), CSR only", "fp64", dict(group=64, sell=False)),
+                 ("timed per level, CSR only", "fp64", dict(group=-1, sell=False)),
+                 ("timed per level + SELL", "fp64", dict(group=-1, sell=True))],
+    "cycles": [(f"{cy}{'' if kl == 0 else f' (K on {kl} levels)'} {pr}", pr, dict(cycle=cy, kcycle_levels=kl))
+               for pr in ("fp64", "fp32") for cy, kl in (("V", 0), ("W", 0), ("K", 0), ("K", 1))],
+}
+
+
+def ablation(args, c, step):
+    import torch
+    rows = []
+    for label, prec, kw in ABLATIONS[args.ablation]:
+        for _ in range(max(1, args.warmup)):
+            step(prec, 0, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        infos = [step(prec, 0, **kw)[0] for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / args.steps
+        inf = infos[-1]
+        row = {"setting": label, "precision": prec, "ms_per_step": ms, "mdofs": c["n"] / (ms * 1e-3) / 1e6,
+               "setup_ms": sum(i["t_setup_ms"] for i in infos) / len(infos),
+               "solve_ms": sum(i["t_solve_ms"] for i in infos) / len(infos), "iters": inf["iters"],
+               "relres": inf["relres"], "levels": len(inf["n"])}
+        rows.append(row)
+        log(f"{label:48s} {ms:8.2f} ms/step  setup {row['setup_ms']:7.2f}  solve {row['solve_ms']:7.2f}  "
+            f"iters {row['iters']:4d}  relres {row['relres']:.2e}")
+    print(json.dumps({"ablation": args.ablation, "workload": c["name"], "n": c["n"], "steps": args.steps,
+                      "rows": rows}), flush=True)
 
 
 if __name__ == "__main__":

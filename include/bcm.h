@@ -46,7 +46,7 @@ enum {
 };
 
 enum { BCM_FP64 = 0, BCM_FP32_CYCLE = 1 };
-enum { BCM_VCYCLE = 1 };
+enum { BCM_VCYCLE = 1, BCM_WCYCLE = 2, BCM_KCYCLE = 3 };
 
 typedef struct bcm_handle bcm_handle;
 
@@ -68,7 +68,16 @@ typedef struct {
  *   coarse_sweeps  20    l1-Jacobi sweeps from zero at the coarsest level
  *   pre, post      1, 1  l1-Jacobi sweeps before/after the coarse correction
  *                        (only 1, 1 is implemented)
- *   cycle          BCM_VCYCLE (Algorithm 1)
+ *   cycle          BCM_VCYCLE (Algorithm 1), BCM_WCYCLE (Section 2.1: the
+ *                        coarse problem of every level solved by two cycles,
+ *                        the second on the coarse residual) or BCM_KCYCLE
+ *                        (Sections 2.1 and 3.2, Krylov-based cycle: the coarse
+ *                        problem of a level solved by two flexible-CG
+ *                        iterations from zero, preconditioned by the coarse
+ *                        level's cycle; the preconditioner is then nonlinear)
+ *   kcycle_levels  0     BCM_KCYCLE: levels k < kcycle_levels (0 = finest)
+ *                        use the Krylov coarse solve, the others one cycle;
+ *                        0 = every level
  *   precision      BCM_FP64: hierarchy and cycle in float64.
  *                  BCM_FP32_CYCLE: hierarchy stored and cycle run in float32
  *                  with float32 accumulation; the coarsest solve, the outer
@@ -84,6 +93,21 @@ typedef struct {
  *   profile              bit mask of kernel classes (BCM_PROF_*) whose
  *                        launches are bracketed by HIP events during
  *                        bcm_solve; read back with bcm_profile().
+ *   graph          1     replay one flexible-CG iteration (cycle, SpMV, updates)
+ *                        from a HIP graph captured on the handle's first solve;
+ *                        0 = launch every kernel.  A profile mask of exactly one
+ *                        of the classes down0, up0, spmv_dots, update, coarse is
+ *                        timed inside the graph; other masks launch eagerly.
+ *   group          0     lanes per matrix row in the CSR row kernels (the
+ *                        miniwarp of Sections 3.1 and 3.2): 0 = the smallest
+ *                        power of two >= the level's average nonzeros per row,
+ *                        clamped to 4..64; 4, 8, 16, 32 or 64 = that width on
+ *                        every level; -1 = the rule during setup, then the
+ *                        fastest width per cycle level, timed at the end of
+ *                        setup (the solve's rounding then depends on timing)
+ *   sell           1     sliced-ELL copies (64-row slices) of the finest level
+ *                        and of levels >= 65536 rows for the row-parallel solve
+ *                        kernels; 0 = CSR row kernels everywhere
  */
 typedef struct {
     int32_t max_levels;
@@ -93,11 +117,14 @@ typedef struct {
     int32_t pre;
     int32_t post;
     int32_t cycle;
+    int32_t kcycle_levels;
     int32_t precision;
     int32_t itmax;
     int32_t check;
     int32_t profile;
-    int32_t reserved;
+    int32_t graph;
+    int32_t group;
+    int32_t sell;
     double adjoint_tol;
     void *(*alloc)(size_t bytes, void *ctx);
     void (*dealloc)(void *ptr, size_t bytes, void *ctx);

@@ -31,6 +31,11 @@
  *   - l1-Jacobi smoother (Section 3.2): d_i = sum_j |a_ij|, x += (b - A x) / d.
  *   - V-cycle: Algorithm 1, one pre- and one post-smoothing sweep, a fixed
  *     number of l1-Jacobi sweeps from zero at the coarsest level.
+ *   - W- and K-cycles (Section 2.1 names both beside Algorithm 1): the W-cycle
+ *     solves each coarse problem by two cycles, the second on the coarse
+ *     residual; the K-cycle by two iterations of the flexible CG below,
+ *     preconditioned by the coarse level's cycle (Krylov-based cycle of Notay
+ *     and Vassilevski, the reason Section 3.2 gives for the flexible CG).
  *   - flexible CG: Algorithm 3 with its sign and index typos read as
  *     r <- r - (alpha/rho) q and d, q updated with gamma_i / rho_{i-1}.
  */
@@ -61,7 +66,8 @@ typedef struct {
 typedef struct {
     int nl;
     int coarse_sweeps;
-    int cycle; /* coarse corrections per level: 1 = V-cycle, 2 = W-cycle */
+    int cycle;   /* 1 = V-cycle, 2 = W-cycle, 3 = K-cycle */
+    int klevels; /* K-cycle: levels k < klevels accelerate their coarse solve (0: all) */
     olevel lv[ORA_MAXLEV];
     /* per-level statistics of the last setup */
     int npairs[ORA_MAXLEV][8];
@@ -353,9 +359,13 @@ void ora_free(void *hv) {
  */
 void *ora_setup(int n, const int *rp, const int *ci, const double *v, const double *w,
                 int max_levels, int max_coarse, int sweeps, int coarse_sweeps, int cycle,
-                int *status) {
+                int klevels, int *status) {
     *status = 0;
-    if (max_levels < 1 || max_levels > ORA_MAXLEV || sweeps < 1 || sweeps > 8) { *status = -1; return NULL; }
+    if (max_levels < 1 || max_levels > ORA_MAXLEV || sweeps < 1 || sweeps > 8 || cycle < 1 || cycle > 3 ||
+        klevels < 0) {
+        *status = -1;
+        return NULL;
+    }
     for (int i = 0; i < n; i++) {
         if (!(isfinite(w[i]) && w[i] != 0.0)) { *status = -1; return NULL; }
         int hasd = 0;
@@ -368,6 +378,7 @@ void *ora_setup(int n, const int *rp, const int *ci, const double *v, const doub
     ohier *h = calloc(1, sizeof(ohier));
     h->coarse_sweeps = coarse_sweeps;
     h->cycle = cycle;
+    h->klevels = klevels;
     csr_copy(&h->lv[0].A, n, rp, ci, v);
     h->lv[0].w = xmalloc(sizeof(double) * (size_t)n);
     memcpy(h->lv[0].w, w, sizeof(double) * (size_t)n);
@@ -472,11 +483,60 @@ static void jacobi_sweep(const olevel *L, const double *b, double *x, double *r)
     for (int i = 0; i < L->A.n; i++) x[i] = x[i] + L->dinv[i] * r[i];
 }
 
+static double dot(int n, const double *a, const double *b) {
+    double s = 0.0;
+    for (int i = 0; i < n; i++) s = s + a[i] * b[i];
+    return s;
+}
+
+static void cycle(ohier *h, int k);
+
 /*
- * cycle(k) (Algorithm 1; W-cycle for h->cycle = 2): on entry L->b holds the
- * right-hand side; on exit L->x holds the result, from a zero initial guess.
- * The coarse problem A^{k+1} x_c = P^T r is solved by h->cycle successive
- * cycles: x_c = cycle(b_c), then x_c = x_c + cycle(b_c - A^{k+1} x_c).
+ * K-cycle coarse solve at level k: x_c ~ (A^{k+1})^{-1} b_c by two iterations
+ * of the flexible CG of Algorithm 3 (same reading as ora_fcg) from x_c = 0,
+ * preconditioned by cycle(k + 1).  If rho is not positive and finite (b_c = 0,
+ * or a second direction parallel to the first) the iteration stops and x_c
+ * keeps what it has.
+ */
+static void kcycle_coarse(ohier *h, int k, const double *bc, double *xc) {
+    olevel *C = &h->lv[k + 1];
+    int n = C->A.n;
+    size_t bytes = sizeof(double) * (size_t)n;
+    double *r = xmalloc(bytes), *w = xmalloc(bytes), *v = xmalloc(bytes);
+    double *d = calloc((size_t)n, sizeof(double)), *q = calloc((size_t)n, sizeof(double));
+    memcpy(r, bc, bytes);
+    memset(xc, 0, bytes);
+    double rho = 0.0;
+    for (int it = 0; it < 2; it++) {
+        memcpy(C->b, r, bytes);
+        cycle(h, k + 1);
+        memcpy(w, C->x, bytes);
+        spmv(&C->A, w, v);
+        double alpha = dot(n, w, r);
+        double beta = dot(n, w, v);
+        double rho_new = beta, g = 0.0;
+        if (it > 0) {
+            double gamma = dot(n, w, q);
+            rho_new = beta - gamma * gamma / rho;
+            g = gamma / rho;
+        }
+        if (!(rho_new > 0.0) || !isfinite(rho_new)) break;
+        double an = alpha / rho_new;
+        for (int i = 0; i < n; i++) d[i] = w[i] - g * d[i];
+        for (int i = 0; i < n; i++) xc[i] = xc[i] + an * d[i];
+        for (int i = 0; i < n; i++) q[i] = v[i] - g * q[i];
+        for (int i = 0; i < n; i++) r[i] = r[i] - an * q[i];
+        rho = rho_new;
+    }
+    free(r); free(w); free(v); free(d); free(q);
+}
+
+/*
+ * cycle(k) (Algorithm 1): on entry L->b holds the right-hand side; on exit
+ * L->x holds the result, from a zero initial guess.  The coarse problem
+ * A^{k+1} x_c = P^T r is solved by one cycle of level k + 1 (V), by two
+ * successive cycles x_c = cycle(b_c), x_c = x_c + cycle(b_c - A^{k+1} x_c) (W),
+ * or by kcycle_coarse on the K-accelerated levels (K).
  */
 static void cycle(ohier *h, int k) {
     olevel *L = &h->lv[k];
@@ -496,15 +556,18 @@ static void cycle(ohier *h, int k) {
     double *bc = xmalloc(sizeof(double) * (size_t)nc), *xc = xmalloc(sizeof(double) * (size_t)nc);
     for (int e = 0; e < nc; e++) bc[e] = 0.0;
     for (int i = 0; i < n; i++) bc[L->agg[i]] = bc[L->agg[i]] + L->p[i] * L->r[i];
-    /* coarse correction: h->cycle cycles on the coarse problem */
-    memcpy(C->b, bc, sizeof(double) * (size_t)nc);
-    cycle(h, k + 1);
-    memcpy(xc, C->x, sizeof(double) * (size_t)nc);
-    for (int g = 1; g < h->cycle; g++) {
-        spmv(&C->A, xc, C->b);
-        for (int e = 0; e < nc; e++) C->b[e] = bc[e] - C->b[e];
+    if (h->cycle == 3 && (h->klevels == 0 || k < h->klevels)) {
+        kcycle_coarse(h, k, bc, xc);
+    } else {
+        memcpy(C->b, bc, sizeof(double) * (size_t)nc);
         cycle(h, k + 1);
-        for (int e = 0; e < nc; e++) xc[e] = xc[e] + C->x[e];
+        memcpy(xc, C->x, sizeof(double) * (size_t)nc);
+        if (h->cycle == 2) {
+            spmv(&C->A, xc, C->b);
+            for (int e = 0; e < nc; e++) C->b[e] = bc[e] - C->b[e];
+            cycle(h, k + 1);
+            for (int e = 0; e < nc; e++) xc[e] = xc[e] + C->x[e];
+        }
     }
     /* prolongation: x = x + P x_c */
     for (int i = 0; i < n; i++) L->x[i] = L->x[i] + L->p[i] * xc[L->agg[i]];
@@ -521,12 +584,6 @@ int ora_vcycle(void *hv, const double *b, double *x) {
     cycle(h, 0);
     memcpy(x, L->x, sizeof(double) * (size_t)L->A.n);
     return 0;
-}
-
-static double dot(int n, const double *a, const double *b) {
-    double s = 0.0;
-    for (int i = 0; i < n; i++) s = s + a[i] * b[i];
-    return s;
 }
 
 /* preconditioner: 0 identity, 1 multigrid cycle, 2 one l1-Jacobi step from zero */

@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(HERE, "libbcm.so")
 
 BCM_OK, BCM_MAXIT, BCM_EINVAL, BCM_EBREAKDOWN, BCM_ENOMEM, BCM_EHIP = 0, 1, -1, -2, -3, -4
 BCM_FP64, BCM_FP32_CYCLE = 0, 1
+CYCLES = {"V": 1, "W": 2, "K": 3}  # BCM_VCYCLE, BCM_WCYCLE, BCM_KCYCLE
 PROF = {"down0": 1, "up0": 2, "spmv_dots": 4, "update": 8, "coarse": 16, "mid": 32}
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
@@ -31,8 +32,9 @@ class BcmCsr(C.Structure):
 class BcmParams(C.Structure):
     _fields_ = [("max_levels", C.c_int32), ("max_coarse", C.c_int32), ("sweeps", C.c_int32),
                 ("coarse_sweeps", C.c_int32), ("pre", C.c_int32), ("post", C.c_int32), ("cycle", C.c_int32),
-                ("precision", C.c_int32), ("itmax", C.c_int32), ("check", C.c_int32), ("profile", C.c_int32),
-                ("reserved", C.c_int32), ("adjoint_tol", C.c_double), ("alloc", ALLOC_FN),
+                ("kcycle_levels", C.c_int32), ("precision", C.c_int32), ("itmax", C.c_int32),
+                ("check", C.c_int32), ("profile", C.c_int32), ("graph", C.c_int32), ("group", C.c_int32),
+                ("sell", C.c_int32), ("adjoint_tol", C.c_double), ("alloc", ALLOC_FN),
                 ("dealloc", DEALLOC_FN), ("alloc_ctx", C.c_void_p), ("stream", C.c_void_p)]
 
 
@@ -120,9 +122,14 @@ class _TorchAllocator:
 
 
 def make_params(precision="fp64", max_levels=40, max_coarse=0, sweeps=2, coarse_sweeps=20, itmax=5000,
-                check=True, adjoint_tol=0.0, profile=0, stream=None, allocator=None) -> BcmParams:
+                check=True, adjoint_tol=0.0, profile=0, stream=None, allocator=None, cycle="V",
+                graph=True, kcycle_levels=0, group=0, sell=True) -> BcmParams:
     p = BcmParams()
     load_library().bcm_default_params(C.byref(p))
+    p.cycle = CYCLES[cycle]
+    p.kcycle_levels = kcycle_levels
+    p.group, p.sell = group, int(bool(sell))
+    p.graph = int(bool(graph))
     p.max_levels, p.max_coarse, p.sweeps, p.coarse_sweeps = max_levels, max_coarse, sweeps, coarse_sweeps
     p.precision = {"fp64": BCM_FP64, "fp32": BCM_FP32_CYCLE}[precision]
     p.itmax, p.check, p.adjoint_tol, p.profile = itmax, int(bool(check)), adjoint_tol, profile
@@ -138,7 +145,8 @@ class Hierarchy:
     tensors; they are copied to the device as int32 / float64."""
 
     def __init__(self, rowptr, col, val, w=None, *, precision="fp64", max_levels=40, max_coarse=0, sweeps=2,
-                 coarse_sweeps=20, itmax=5000, check=True, adjoint_tol=0.0, profile=0, device=None):
+                 coarse_sweeps=20, itmax=5000, check=True, adjoint_tol=0.0, profile=0, device=None, cycle="V",
+                 graph=True, kcycle_levels=0, group=0, sell=True):
         L = _gpu_lib()
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         self.stream = torch.cuda.current_stream(self.device).cuda_stream
@@ -150,7 +158,8 @@ class Hierarchy:
         w = torch.ones(self.n, dtype=torch.float64, device=self.device) if w is None else _dev(w, torch.float64, self.device)
         self._alloc = _TorchAllocator(self.device, self.stream)
         self.params = make_params(precision, max_levels, max_coarse, sweeps, coarse_sweeps, itmax, check,
-                                  adjoint_tol, profile, self.stream, self._alloc)
+                                  adjoint_tol, profile, self.stream, self._alloc, cycle, graph, kcycle_levels,
+                                  group, sell)
         A = BcmCsr(self.n, self.nnz, self.rowptr.data_ptr(), self.col.data_ptr(), self.val.data_ptr())
         h = C.c_void_p()
         _check(L.bcm_setup(C.byref(A), C.c_void_p(w.data_ptr()), C.byref(self.params), C.byref(h)))

@@ -157,9 +157,17 @@ struct SweepOut {
 
 // Weights, ranks, Suitor matching and mate/leader flags on (A, w): Section 2.2
 // and 3.1.  tmp-lifetime buffers come from `tmp`.
-int match_sweep(hipStream_t s, Arena &tmp, const Csr &A, const double *w, int check_sym, int **mate_out,
+// Lanes per row of the CSR row kernels: the forced width of the parameters,
+// else the rule on the average row length.
+int lanes_for(int group, const Csr &A) {
+    return group > 0 ? group : pick_G((double)A.nnz / std::max(1, A.n));
+}
+
+bool valid_group(int g) { return g == 0 || g == -1 || g == 4 || g == 8 || g == 16 || g == 32 || g == 64; }
+
+int match_sweep(hipStream_t s, Arena &tmp, const Csr &A, const double *w, int check_sym, int group, int **mate_out,
                 int **leader_out, double **c_out) {
-    const int m = A.n, G = pick_G((double)A.nnz / std::max(1, m));
+    const int m = A.n, G = lanes_for(group, A);
     double *diag = tmp.get_n<double>(m);
     int *flags = tmp.get_n<int>(16);
     double *c = tmp.get_n<double>(A.nnz);
@@ -195,13 +203,13 @@ int match_sweep(hipStream_t s, Arena &tmp, const Csr &A, const double *w, int ch
 // matrix and w come from finA and the prolongator from finP when those are
 // given (the level's final outputs, allocated where they stay).  out.nc == A.n
 // means that no pair was formed (nothing else is produced then).
-int pairwise_sweep(hipStream_t s, Arena &tmp, Arena &keep, const Csr &A, const double *w, SweepOut &out,
+int pairwise_sweep(hipStream_t s, Arena &tmp, Arena &keep, const Csr &A, const double *w, int group, SweepOut &out,
                    Arena *finA, Arena *finP) {
     Arena &oa = finA ? *finA : keep;
     Arena &op = finP ? *finP : keep;
-    const int m = A.n, G = pick_G((double)A.nnz / std::max(1, m));
+    const int m = A.n, G = lanes_for(group, A);
     int *mate = nullptr, *leader = nullptr;
-    int rc = match_sweep(s, tmp, A, w, 0, &mate, &leader, nullptr);
+    int rc = match_sweep(s, tmp, A, w, 0, group, &mate, &leader, nullptr);
     if (rc) return rc;
     int *ofs = leader;  // scanned in place
     int *dtot = tmp.get_n<int>(16);
@@ -248,6 +256,59 @@ T *persist_copy(bcm_handle *h, const T *src, size_t n) {
     return d;
 }
 
+// group = -1: every level whose cycle legs run CSR row kernels (levels of the
+// tail kernel and levels running entirely on the sliced-ELL copy excluded)
+// gets the lane width whose down + up legs ran fastest, over three timed
+// repetitions per width on zero vectors.
+int autotune_lanes(bcm_handle *h) {
+    hipStream_t s = h->s;
+    const int fp32 = h->prm.precision == BCM_FP32_CYCLE;
+    const size_t es = fp32 ? sizeof(float) : sizeof(double);
+    hipEvent_t ev[2];
+    HIPCHK(hipEventCreate(&ev[0]));
+    if (hipEventCreate(&ev[1]) != hipSuccess) {
+        (void)hipEventDestroy(ev[0]);
+        set_error("hipEventCreate failed");
+        return BCM_EHIP;
+    }
+    launch_fill_i32(s, 2 * (size_t)h->lv[0].A.n, (int *)h->r, 0);
+    const int last = h->kt > 0 ? h->kt : h->nl - 1;
+    hipError_t err = hipSuccess;
+    for (int l = 0; l < last && err == hipSuccess; ++l) {
+        Level &L = h->lv[l];
+        Level &C = h->lv[l + 1];
+        if (L.E.sp && L.xp && (L.mstride == 2 || L.mstride == 4) && L.A.n >= kSplitUp) continue;
+        if (l > 0) launch_fill_i32(s, es * L.A.n / 4, (int *)L.b, 0);
+        launch_fill_i32(s, es * C.A.n / 4, (int *)C.x, 0);
+        const void *b = l == 0 ? (const void *)h->r : L.b;
+        void *x = l == 0 ? (void *)h->w : L.x;
+        const int io = (l == 0 || !fp32) ? 1 : 0;
+        float best = 0.f;
+        int best_g = L.G;
+        for (int g = 4; g <= 64 && err == hipSuccess; g *= 2) {
+            L.G = g;
+            for (int t = 0; t < 4; ++t) {
+                if (t == 1) (void)hipEventRecord(ev[0], s);
+                launch_down(s, L, fp32, b, C.b, io, nullptr);
+                launch_up(s, L, fp32, b, C.x, x, io, io, nullptr);
+            }
+            (void)hipEventRecord(ev[1], s);
+            err = hipEventSynchronize(ev[1]);
+            float ms = 0.f;
+            if (err == hipSuccess) err = hipEventElapsedTime(&ms, ev[0], ev[1]);
+            if (err == hipSuccess && (g == 4 || ms < best)) { best = ms; best_g = g; }
+        }
+        L.G = best_g;
+    }
+    (void)hipEventDestroy(ev[0]);
+    (void)hipEventDestroy(ev[1]);
+    if (err != hipSuccess) {
+        set_error(std::string("lane-width timing failed: ") + hipGetErrorString(err));
+        return BCM_EHIP;
+    }
+    return BCM_OK;
+}
+
 int build_hierarchy(bcm_handle *h, const bcm_csr *Ain, const double *win) {
     hipStream_t s = h->s;
     const bcm_params &P = h->prm;
@@ -283,7 +344,7 @@ int build_hierarchy(bcm_handle *h, const bcm_csr *Ain, const double *win) {
         int *flags = tmp.get_n<int>(16);
         NOMEM(diag && flags);
         launch_fill_i32(s, 1, flags, 0);
-        launch_validate(s, pick_G((double)nnz / std::max(1, n)), n, nnz, L0.A.rp, L0.A.ci, L0.A.v, L0.w,
+        launch_validate(s, lanes_for(P.group, L0.A), n, nnz, L0.A.rp, L0.A.ci, L0.A.v, L0.w,
                         P.check ? 1 : 0, diag, flags);
         int f = 0;
         int rc = read_back(s, flags, sizeof(int), &f);
@@ -308,7 +369,7 @@ int build_hierarchy(bcm_handle *h, const bcm_csr *Ain, const double *win) {
             tmp.rewind();
             SweepOut so;
             const bool last = sw == P.sweeps - 1;
-            int rc = pairwise_sweep(s, tmp, keep, Acur, wcur, so, last ? &h->persist : nullptr,
+            int rc = pairwise_sweep(s, tmp, keep, Acur, wcur, P.group, so, last ? &h->persist : nullptr,
                                     last && !have ? &h->persist : nullptr);
             if (rc) return rc;
             if (so.nc == Acur.n) break;  // no pair formed: further sweeps would not either
@@ -355,7 +416,7 @@ int build_hierarchy(bcm_handle *h, const bcm_csr *Ain, const double *win) {
     for (int l = 0; l < h->nl; ++l) {
         Level &L = h->lv[l];
         const int nl_ = L.A.n;
-        L.G = pick_G((double)L.A.nnz / std::max(1, nl_));
+        L.G = lanes_for(P.group, L.A);
         L.dinv = h->persist.get_n<double>(nl_);
         NOMEM(L.dinv);
         if (fp32) {
@@ -379,13 +440,21 @@ int build_hierarchy(bcm_handle *h, const bcm_csr *Ain, const double *win) {
             L.b = h->persist.get(es * nl_);
             L.x = h->persist.get(es * nl_);
             NOMEM(L.b && L.x);
+            if (P.cycle != BCM_VCYCLE) {
+                L.xs = h->persist.get(es * nl_);
+                NOMEM(L.xs);
+            }
+            if (P.cycle == BCM_KCYCLE && (P.kcycle_levels == 0 || l - 1 < P.kcycle_levels)) {
+                L.kv = h->persist.get(es * nl_);
+                NOMEM(L.kv);
+            }
         }
     }
     {
         // sliced ELL copies: the finest level (flexible CG products) and every
         // level that runs the split up leg
         std::vector<int> lv_sell;
-        for (int l = 0; l < h->nl; ++l)
+        for (int l = 0; l < h->nl && P.sell; ++l)
             if (l == 0 || h->lv[l].xp) lv_sell.push_back(l);
         std::vector<int *> cnts(lv_sell.size());
         int *tot = h->persist.get_n<int>(64);
@@ -428,7 +497,7 @@ int build_hierarchy(bcm_handle *h, const bcm_csr *Ain, const double *win) {
         int kt = h->nl - 1;
         while (kt > 1 && h->lv[kt - 1].A.n <= kTailRows) --kt;
         const Level &C = h->lv[h->nl - 1];
-        if (kt < h->nl - 1 && C.A.n <= kTailRows) {
+        if (P.cycle == BCM_VCYCLE && kt < h->nl - 1 && C.A.n <= kTailRows) {
             std::vector<TailLevel> tv(h->nl);
             for (int l = 0; l < h->nl; ++l) {
                 const Level &L = h->lv[l];
@@ -459,16 +528,31 @@ int build_hierarchy(bcm_handle *h, const bcm_csr *Ain, const double *win) {
     h->d = h->persist.get_n<double>(n);
     h->v = h->persist.get_n<double>(n);
     h->q = h->persist.get_n<double>(n);
+    h->u = h->persist.get_n<double>(n);
     h->scal = h->persist.get_n<double>(16);
     h->red_blocks = reduce_blocks(n);
     h->partials = h->persist.get_n<double>(4 * (size_t)h->red_blocks);
-    NOMEM(h->r && h->w && h->d && h->v && h->q && h->scal && h->partials);
+    NOMEM(h->r && h->w && h->d && h->v && h->q && h->u && h->scal && h->partials);
+    if (P.cycle == BCM_KCYCLE) {
+        h->kpart = h->persist.get_n<double>(3 * (size_t)kKPartBlocks);
+        h->ks = h->persist.get_n<double>(8 * (size_t)h->nl);
+        NOMEM(h->kpart && h->ks);
+    }
     launch_fill_i32(s, 32, (int *)h->scal, 0);
     launch_fill_i32(s, 2 * (size_t)n, (int *)h->q, 0);
     launch_fill_i32(s, 2 * (size_t)n, (int *)h->d, 0);
     HIPCHK(hipGetLastError());
+    if (P.group == -1) {
+        const int rc = autotune_lanes(h);
+        if (rc) return rc;
+    }
     HIPCHK(hipStreamSynchronize(s));
     return BCM_OK;
+}
+
+// Level k solves its coarse problem with the K-cycle's two flexible-CG iterations.
+bool kcycle_at(const bcm_handle *h, int k) {
+    return h->prm.cycle == BCM_KCYCLE && (h->prm.kcycle_levels == 0 || k < h->prm.kcycle_levels);
 }
 
 // --------------------------------------------------------------- byte model
@@ -499,17 +583,85 @@ double bytes_coarse(const bcm_handle *h) {
     const double sb = (h->nl == 1 || h->prm.precision != BCM_FP32_CYCLE) ? 8 : 4;
     return 4 * (n + 1) + 12 * z + 8 * n + 2 * sb * n;
 }
+// one preconditioner application: every level's legs times the number of
+// times the level is visited (doubling below each W- or K-accelerated level),
+// plus the W residual/add and the K-cycle products and combinations
+double bytes_cycle(const bcm_handle *h) {
+    const double sv = h->prm.precision == BCM_FP32_CYCLE ? 4 : 8;
+    double total = 0.0, visits = 1.0;
+    for (int k = 0; k + 1 < h->nl; ++k) {
+        total += visits * (bytes_down(h, k) + bytes_up(h, k));
+        const Level &C = h->lv[k + 1];
+        const double n = C.A.n, spmv = 4 * (n + 1) + (4 + sv) * C.A.nnz;
+        if (kcycle_at(h, k)) {
+            total += visits * (2 * (spmv + 3 * sv * n) + 6 * sv * n);
+            visits *= 2;
+        } else if (h->prm.cycle == BCM_WCYCLE) {
+            total += visits * (spmv + 6 * sv * n);
+            visits *= 2;
+        }
+    }
+    return total + visits * bytes_coarse(h);
+}
 double bytes_spmv_dots(const bcm_handle *h) {
     const double n = h->lv[0].A.n, z = h->lv[0].A.nnz;
     return 4 * (n + 1) + 12 * z + 32 * n;  // algorithmic: CSR entries once (ELL padding not counted)
 }
 double bytes_update(const bcm_handle *h) { return 80.0 * h->lv[0].A.n; }
 
+// Bytes of one bracket of a class launched once per iteration (0..4).
+double class_bytes(const bcm_handle *h, int cls) {
+    switch (cls) {
+    case 0: return bytes_down(h, 0);
+    case 1: return bytes_up(h, 0);
+    case 2: return bytes_spmv_dots(h);
+    case 3: return bytes_update(h);
+    default: {
+        double by = bytes_coarse(h);
+        const int kt = h->kt > 0 ? h->kt : h->nl - 1;
+        for (int k = kt; k < h->nl - 1; ++k) by += bytes_down(h, k) + bytes_up(h, k);
+        return by;
+    }
+    }
+}
+
 // --------------------------------------------------------------- profiling
+// Capture of one iteration cut into segments: in capture mode the bracket of
+// the profiled class ends the current graph and starts a new one, so that the
+// bracket's kernels form a graph of their own, replayed between two event
+// records issued on the stream.
+struct SegCapture {
+    hipStream_t st = nullptr;
+    std::vector<hipGraph_t> graphs;
+    hipError_t err = hipSuccess;
+    void begin() {
+        if (err == hipSuccess) err = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+    }
+    void end() {
+        hipGraph_t g = nullptr;
+        const hipError_t e = hipStreamEndCapture(st, &g);
+        if (err == hipSuccess) err = e;
+        graphs.push_back(g);
+    }
+    void cut() {
+        end();
+        begin();
+    }
+};
+
+// Event timing of kernel classes: one event pair per bracketed launch, from the
+// handle's pool.  In capture mode (cap != NULL) the bracket of class gcls only
+// cuts the captured iteration into segments.
 struct Prof {
     bcm_handle *h;
     int mask;
+    int gcls = -1;
+    SegCapture *cap = nullptr;
     int begin(int cls) {
+        if (cap) {
+            if (cls == gcls) cap->cut();
+            return -1;
+        }
         if (!(mask & (1 << cls))) return -1;
         const int idx = (int)(h->ev_pairs.size() * 2);
         while ((int)h->ev_pool.size() < idx + 2) {
@@ -521,6 +673,10 @@ struct Prof {
         return idx;
     }
     void end(int cls, int idx, double bytes, int iter) {
+        if (cap) {
+            if (cls == gcls) cap->cut();
+            return;
+        }
         if (idx < 0) return;
         (void)hipEventRecord(h->ev_pool[idx + 1], h->s);
         h->ev_pairs.push_back({cls, idx});
@@ -554,6 +710,53 @@ void prof_collect(bcm_handle *h, int iters) {
     h->ev_iter.clear();
 }
 
+// --------------------------------------------------------------- W- and K-cycles
+// Recursive cycle of a level k >= 1 (right-hand side in lv[k].b, result in
+// lv[k].x), and the solve of the coarse problem of a level k (right-hand side
+// lv[k+1].b, result lv[k+1].x): one cycle (V); two cycles, the second on the
+// coarse residual and written to the level's save buffer (W); or two
+// flexible-CG iterations preconditioned by the coarse cycle (K, on levels
+// k < kcycle_levels).
+void cycle_level(bcm_handle *h, Prof &pf, int k, const double *done, int iter);
+
+void coarse_solve(bcm_handle *h, Prof &pf, int k, const double *done, int iter) {
+    hipStream_t s = h->s;
+    const int fp32 = h->prm.precision == BCM_FP32_CYCLE;
+    Level &C = h->lv[k + 1];
+    cycle_level(h, pf, k + 1, done, iter);
+    if (kcycle_at(h, k)) {
+        double *ks = h->ks + 8 * k;
+        launch_kcycle_step1(s, C, fp32, C.x, C.b, C.kv, h->kpart, ks, done);
+        std::swap(C.x, C.xs);
+        cycle_level(h, pf, k + 1, done, iter);
+        std::swap(C.x, C.xs);
+        launch_kcycle_step2(s, C, fp32, C.xs, C.b, C.kv, C.x, h->kpart, ks, done);
+    } else if (h->prm.cycle == BCM_WCYCLE) {
+        launch_resid_inplace(s, C, fp32, C.x, C.b, done);
+        std::swap(C.x, C.xs);
+        cycle_level(h, pf, k + 1, done, iter);
+        std::swap(C.x, C.xs);
+        launch_add(s, C.A.n, fp32, C.xs, C.x, done);
+    }
+}
+
+void cycle_level(bcm_handle *h, Prof &pf, int k, const double *done, int iter) {
+    hipStream_t s = h->s;
+    const int fp32 = h->prm.precision == BCM_FP32_CYCLE;
+    Level &L = h->lv[k];
+    if (k == h->nl - 1) {
+        int e = pf.begin(5);
+        launch_coarse(s, L, h->prm.coarse_sweeps, L.b, L.x, !fp32, !fp32, h->ctmp[0], h->ctmp[1], done);
+        pf.end(5, e, bytes_coarse(h), iter);
+        return;
+    }
+    Level &C = h->lv[k + 1];
+    const int f64io = !fp32;
+    launch_down(s, L, fp32, L.b, C.b, f64io, done);
+    coarse_solve(h, pf, k, done, iter);
+    launch_up(s, L, fp32, L.b, C.x, L.x, f64io, f64io, done);
+}
+
 // --------------------------------------------------------------- V-cycle
 // One cycle of Algorithm 1 from a zero guess: z = B(r).  done: see launch_down.
 void vcycle(bcm_handle *h, Prof &pf, const double *rin, double *wout, const double *done, int iter) {
@@ -566,6 +769,18 @@ void vcycle(bcm_handle *h, Prof &pf, const double *rin, double *wout, const doub
         int e = pf.begin(4);
         launch_coarse(s, C, cs, rin, wout, 1, 1, h->ctmp[0], h->ctmp[1], done);
         pf.end(4, e, bytes_coarse(h), iter);
+        return;
+    }
+    if (h->prm.cycle != BCM_VCYCLE) {
+        // finest level here (f64 in/out), coarse levels recursively
+        Level &L = h->lv[0], &N = h->lv[1];
+        int e = pf.begin(0);
+        launch_down(s, L, fp32, rin, N.b, 1, done);
+        pf.end(0, e, bytes_down(h, 0), iter);
+        coarse_solve(h, pf, 0, done, iter);
+        e = pf.begin(1);
+        launch_up(s, L, fp32, rin, N.x, wout, 1, 1, done);
+        pf.end(1, e, bytes_up(h, 0), iter);
         return;
     }
     const int kt = h->kt > 0 ? h->kt : nl - 1;
@@ -583,9 +798,7 @@ void vcycle(bcm_handle *h, Prof &pf, const double *rin, double *wout, const doub
         } else {
             launch_coarse(s, C, cs, C.b, C.x, !fp32, !fp32, h->ctmp[0], h->ctmp[1], done);
         }
-        double by = bytes_coarse(h);
-        for (int k = kt; k < nl - 1; ++k) by += bytes_down(h, k) + bytes_up(h, k);
-        pf.end(4, e, by, iter);
+        pf.end(4, e, class_bytes(h, 4), iter);
     }
     for (int k = kt - 1; k >= 0; --k) {
         Level &L = h->lv[k];
@@ -605,16 +818,83 @@ void vcycle(bcm_handle *h, Prof &pf, const double *rin, double *wout, const doub
 // kernel of the batch returns at once.  The host reads the scalars once per
 // batch and sizes the next batch from the observed convergence rate, so the
 // iteration count is exactly the one a per-iteration test gives.
-int fcg(bcm_handle *h, const double *b, double *x, double tol) {
+// Captures one general iteration (cycle, SpMV + dots, updates; first = 0) on
+// the handle's vectors into HIP graphs: one graph, or with prof_cls >= 0 (a
+// class bracketed once per iteration) three: before the class, the class's
+// kernels, after it.  Recaptured when prof_cls changes.
+void destroy_iteration_graphs(bcm_handle *h) {
+    for (auto &g : h->iter_exec)
+        if (g) { (void)hipGraphExecDestroy(g); g = nullptr; }
+    h->n_exec = 0;
+}
+
+int capture_iteration(bcm_handle *h, int prof_cls) {
+    if (h->n_exec > 0 && h->graph_prof_cls == prof_cls) return BCM_OK;
+    destroy_iteration_graphs(h);
+    if (!h->cap) HIPCHK(hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking));
+    const Level &L0 = h->lv[0];
+    const int n = L0.A.n, nb = h->red_blocks;
+    SegCapture sc;
+    sc.st = h->cap;
+    Prof gp{h, 0, prof_cls, &sc};
+    hipStream_t keep = h->s;
+    h->s = h->cap;
+    sc.begin();
+    vcycle(h, gp, h->r, h->w, h->scal + 10, 0);
+    int e = gp.begin(2);
+    launch_spmv_dots(h->cap, L0, nb, 0, h->w, h->r, h->q, h->v, h->partials, h->scal);
+    gp.end(2, e, 0.0, 0);
+    launch_finalize(h->cap, 1, nb, 0, h->partials, h->scal);
+    e = gp.begin(3);
+    launch_update(h->cap, n, nb, 0, h->w, h->v, h->d, h->u, h->q, h->r, h->partials, h->scal);
+    gp.end(3, e, 0.0, 0);
+    launch_finalize(h->cap, 2, nb, 0, h->partials, h->scal);
+    sc.end();
+    h->s = keep;
+    hipError_t err = sc.err;
+    if (err == hipSuccess && sc.graphs.size() != 1 && sc.graphs.size() != 3) err = hipErrorInvalidValue;
+    for (size_t i = 0; i < sc.graphs.size(); ++i) {
+        hipGraph_t g = sc.graphs[i];
+        size_t nodes = 0;
+        if (err == hipSuccess && g) err = hipGraphGetNodes(g, nullptr, &nodes);
+        if (err == hipSuccess && g && nodes > 0) err = hipGraphInstantiate(&h->iter_exec[i], g, nullptr, nullptr, 0);
+        if (g) (void)hipGraphDestroy(g);
+    }
+    if (err != hipSuccess) {
+        destroy_iteration_graphs(h);
+        set_error(std::string("HIP graph capture failed: ") + hipGetErrorString(err));
+        return BCM_EHIP;
+    }
+    h->n_exec = (int)sc.graphs.size();
+    h->graph_prof_cls = prof_cls;
+    return BCM_OK;
+}
+
+int fcg_run(bcm_handle *h, const double *b, double *x_user, double tol) {
     hipStream_t s = h->s;
     const Level &L0 = h->lv[0];
     const int n = L0.A.n, nb = h->red_blocks;
     Prof pf{h, h->prm.profile};
+    // graph mode: a profile mask of one class bracketed once per iteration
+    // (down0, up0, spmv_dots, update, coarse) is timed by events recorded
+    // around that class's own graph; other masks launch every iteration eagerly
+    int gcls = -1;
+    for (int c = 0; c < 5; ++c)
+        if (h->prm.profile == (1 << c)) gcls = c;
+    const bool use_graph = h->prm.graph && (!h->prm.profile || gcls >= 0);
+    if (use_graph) {
+        const int rcg = capture_iteration(h, gcls);
+        if (rcg) return rcg;
+    }
+
+    double *x = h->u;
+    launch_copy_f64(s, n, x_user, x);
     h->ev_pairs.clear();
     h->ev_bytes.clear();
     h->ev_iter.clear();
     double hs[16];
     launch_resid(s, L0, nb, b, x, h->r, h->partials, h->scal);
+    launch_finalize(s, 0, nb, 0, h->partials, h->scal);
     int rc = read_back(s, h->scal, 16 * sizeof(double), hs);
     if (rc) return rc;
     const double bb = hs[5];
@@ -648,13 +928,26 @@ int fcg(bcm_handle *h, const double *b, double *x, double tol) {
         for (;;) {
             const int nb_it = std::min(batch, itmax - launched);
             for (int t = 0; t < nb_it; ++t) {
+                if (use_graph && !first) {
+                    // segments: [before] [profiled class] [after], or one graph
+                    int e = -1;
+                    for (int g = 0; g < h->n_exec; ++g) {
+                        if (h->n_exec == 3 && g == 1) e = pf.begin(gcls);
+                        if (h->iter_exec[g]) HIPCHK(hipGraphLaunch(h->iter_exec[g], s));
+                        if (h->n_exec == 3 && g == 1) pf.end(gcls, e, class_bytes(h, gcls), launched);
+                    }
+                    ++launched;
+                    continue;
+                }
                 vcycle(h, pf, h->r, h->w, done, launched);
                 int e = pf.begin(2);
                 launch_spmv_dots(s, L0, nb, first, h->w, h->r, h->q, h->v, h->partials, h->scal);
                 pf.end(2, e, bytes_spmv_dots(h), launched);
+                launch_finalize(s, 1, nb, first, h->partials, h->scal);
                 e = pf.begin(3);
                 launch_update(s, n, nb, first, h->w, h->v, h->d, x, h->q, h->r, h->partials, h->scal);
                 pf.end(3, e, bytes_update(h), launched);
+                launch_finalize(s, 2, nb, 0, h->partials, h->scal);
                 first = 0;
                 ++launched;
             }
@@ -679,6 +972,7 @@ int fcg(bcm_handle *h, const double *b, double *x, double tol) {
         }
         // true residual b - A x
         launch_resid(s, L0, nb, b, x, h->r, h->partials, h->scal);
+        launch_finalize(s, 0, nb, 0, h->partials, h->scal);
         rc = read_back(s, h->scal, 16 * sizeof(double), hs);
         if (rc) return rc;
         relres = std::sqrt(hs[4]) / bn;
@@ -694,6 +988,16 @@ int fcg(bcm_handle *h, const double *b, double *x, double tol) {
     return status;
 }
 
+// flexible CG on the handle's iterate; the caller's x is copied in and back out
+int fcg(bcm_handle *h, const double *b, double *x, double tol) {
+    const int rc = fcg_run(h, b, x, tol);
+    if (rc == BCM_OK || rc == BCM_MAXIT || rc == BCM_EBREAKDOWN) {
+        launch_copy_f64(h->s, h->lv[0].A.n, h->u, x);
+        HIPCHK(hipStreamSynchronize(h->s));
+    }
+    return rc;
+}
+
 }  // namespace
 
 extern "C" {
@@ -707,10 +1011,14 @@ void bcm_default_params(bcm_params *p) {
     p->pre = 1;
     p->post = 1;
     p->cycle = BCM_VCYCLE;
+    p->kcycle_levels = 0;
     p->precision = BCM_FP64;
     p->itmax = 5000;
     p->check = 1;
     p->profile = 0;
+    p->graph = 1;
+    p->group = 0;
+    p->sell = 1;
     p->adjoint_tol = 0.0;
 }
 
@@ -725,9 +1033,11 @@ int bcm_setup(const bcm_csr *A, const double *w, const bcm_params *p, bcm_handle
     bcm_params prm;
     if (p) prm = *p; else bcm_default_params(&prm);
     if (prm.max_levels < 1 || prm.sweeps < 1 || prm.sweeps > 4 || prm.coarse_sweeps < 1 || prm.itmax < 1 ||
-        prm.pre != 1 || prm.post != 1 || prm.cycle != BCM_VCYCLE ||
+        prm.pre != 1 || prm.post != 1 || prm.cycle < BCM_VCYCLE || prm.cycle > BCM_KCYCLE || prm.kcycle_levels < 0 ||
+        !valid_group(prm.group) ||
         (prm.precision != BCM_FP64 && prm.precision != BCM_FP32_CYCLE) || (prm.alloc == nullptr) != (prm.dealloc == nullptr)) {
-        set_error("unsupported parameters (sweeps 1..4, pre = post = 1, V-cycle, FP64 or FP32 cycle)");
+        set_error("unsupported parameters (sweeps 1..4, pre = post = 1, V-, W- or K-cycle, kcycle_levels >= 0, "
+                  "group 0, -1, 4, 8, 16, 32 or 64, FP64 or FP32 cycle)");
         return BCM_EINVAL;
     }
     const double t0 = now_ms();
@@ -808,8 +1118,7 @@ int bcm_info(const bcm_handle *h, bcm_info_t *o) {
     o->relres = h->relres;
     o->t_setup_ms = h->t_setup_ms;
     o->t_solve_ms = h->t_solve_ms;
-    double cyc = bytes_coarse(h);
-    for (int k = 0; k + 1 < h->nl; ++k) cyc += bytes_down(h, k) + bytes_up(h, k);
+    const double cyc = bytes_cycle(h);
     o->cycle_bytes = cyc;
     o->iter_bytes = cyc + bytes_spmv_dots(h) + bytes_update(h);
     return BCM_OK;
@@ -842,6 +1151,10 @@ int bcm_match(const bcm_csr *A, const double *w, const bcm_params *p, int32_t *m
     }
     bcm_params prm;
     if (p) prm = *p; else bcm_default_params(&prm);
+    if (!valid_group(prm.group) || (prm.alloc == nullptr) != (prm.dealloc == nullptr)) {
+        set_error("unsupported parameters (group 0, -1, 4, 8, 16, 32 or 64; alloc and dealloc both or neither)");
+        return BCM_EINVAL;
+    }
     hipStream_t s = (hipStream_t)prm.stream;
     Arena tmp;
     tmp.alloc = prm.alloc;
@@ -856,7 +1169,7 @@ int bcm_match(const bcm_csr *A, const double *w, const bcm_params *p, int32_t *m
     M.v = const_cast<double *>(A->val);
     int *dm = nullptr, *leader = nullptr;
     double *dc = nullptr;
-    int rc = tmp.failed ? BCM_ENOMEM : match_sweep(s, tmp, M, w, prm.check ? 1 : 0, &dm, &leader, &dc);
+    int rc = tmp.failed ? BCM_ENOMEM : match_sweep(s, tmp, M, w, prm.check ? 1 : 0, prm.group, &dm, &leader, &dc);
     if (rc == BCM_ENOMEM) set_error("device allocation failed");
     if (rc == BCM_OK) {
         if (hipMemcpyAsync(mate, dm, (size_t)A->n * 4, hipMemcpyDeviceToDevice, s) != hipSuccess ||
@@ -885,6 +1198,8 @@ int bcm_profile(const bcm_handle *h, int32_t kclass, int64_t *launches, double *
 void bcm_free(bcm_handle *h) {
     if (!h) return;
     (void)hipStreamSynchronize(h->s);
+    destroy_iteration_graphs(h);
+    if (h->cap) (void)hipStreamDestroy(h->cap);
     for (auto e : h->ev_pool) (void)hipEventDestroy(e);
     h->persist.release();
     delete h;

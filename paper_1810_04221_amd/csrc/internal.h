@@ -89,6 +89,8 @@ struct Level {
     int *mem = nullptr;
     void *b = nullptr, *x = nullptr;  // cycle vectors for k >= 1 (cycle precision)
     void *xp = nullptr;               // prolonged iterate of the split up leg (cycle precision)
+    void *xs = nullptr;               // W/K-cycle: result of the second coarse cycle (cycle precision)
+    void *kv = nullptr;               // K-cycle: A c1, the product of the first coarse direction
     double *S = nullptr;  // coarsest level only: dense sweep operator (n <= kCoarseDense)
 };
 
@@ -101,6 +103,7 @@ struct TailLevel {
     void *b, *x;
 };
 constexpr int kTailRows = 512;  // levels up to this size run inside the tail kernel
+constexpr int kKPartBlocks = 1024;  // K-cycle dot products: at most this many block partials
 
 struct ProfClass {
     int64_t launches = 0;
@@ -117,6 +120,13 @@ struct bcm_handle {
     bcm::Arena persist, scratch;
     // flexible CG vectors (float64, n of the finest level)
     double *r = nullptr, *w = nullptr, *d = nullptr, *v = nullptr, *q = nullptr;
+    double *u = nullptr;                  // iterate of the solve (the caller's x is copied in and out)
+    hipStream_t cap = nullptr;            // internal stream used only to capture the iteration graph
+    // one general flexible-CG iteration as one graph, or three when one kernel
+    // class is profiled (before it, the class, after it); null: empty segment
+    hipGraphExec_t iter_exec[3] = {nullptr, nullptr, nullptr};
+    int n_exec = 0;
+    int graph_prof_cls = -1;  // class the segments are cut at (-1: none)
     // device scalars: [0] alpha [1] beta [2] gamma [3] rho of the last step [4] ||r||^2
     // [5] ||b||^2 [6] breakdown flag [8] gamma_i / rho_{i-1} [9] alpha_i / rho_i
     // [10] solve-ended flag [11] iterations done [12] tol^2 ||b||^2 [13] itmax
@@ -125,6 +135,8 @@ struct bcm_handle {
     bcm::TailLevel *tail = nullptr;        // device table of levels for the tail kernel
     int kt = -1;                           // first level handled by the tail kernel (-1: none)
     double *partials = nullptr;
+    double *kpart = nullptr;  // K-cycle block partials (3 * kKPartBlocks)
+    double *ks = nullptr;     // K-cycle scalars, 8 per level
     double *host_scal = nullptr;  // pinned
     int red_blocks = 0;
     double last_tol = 0.0;
@@ -172,6 +184,7 @@ void launch_sell_fill(hipStream_t s, int n, const int *rp, const int *ci, const 
 void launch_fill_i32(hipStream_t s, size_t n, int *dst, int val);
 void launch_fill_u64(hipStream_t s, size_t n, unsigned long long *dst, unsigned long long val);
 void launch_copy_f64(hipStream_t s, size_t n, const double *src, double *dst);
+// dst = src on the finest level's vector length; also a graph-safe fill (no memset node)
 
 // ---- scan (scan.hip) ----
 size_t scan_tmp_bytes(int n);
@@ -187,8 +200,19 @@ void launch_up(hipStream_t s, const Level &L, int fp32, const void *b, const voi
                int b_is_f64, int x_is_f64, const double *done);
 void launch_coarse(hipStream_t s, const Level &L, int sweeps, const void *b, void *x, int b_f64,
                    int x_f64, void *tmp_a, void *tmp_b, const double *done);
-// Each of these is a streaming kernel writing block partials plus a one-block
-// finalize kernel that sums them in block order into scal[].
+// Each of these is a streaming kernel writing block partials; launch_finalize
+// (mode 0 after resid, 1 after spmv_dots, 2 after update) then sums them in
+// block order into scal[].
+// W-cycle: b <- b - A x in place on a level >= 1, and x <- x + y
+void launch_resid_inplace(hipStream_t s, const Level &L, int fp32, const void *x, void *b, const double *done);
+void launch_add(hipStream_t s, int n, int fp32, const void *y, void *x, const double *done);
+// K-cycle coarse solve on level C: step 1 after the first coarse cycle (c1 in
+// x): v1 = A c1, scalars, b <- b - (alpha1/rho1) v1; step 2 after the second
+// (c2): scalars, x <- (alpha1/rho1) c1 + (alpha2/rho2)(c2 - (gamma/rho1) c1).
+void launch_kcycle_step1(hipStream_t s, const Level &C, int fp32, const void *c1, const void *b, void *v1,
+                         double *partials, double *ks, const double *done);
+void launch_kcycle_step2(hipStream_t s, const Level &C, int fp32, const void *c2, const void *b, const void *v1,
+                         void *x, double *partials, double *ks, const double *done);
 // levels kt .. nl-1 (tail table tl, coarsest level C) in one workgroup
 void launch_tail(hipStream_t s, int fp32, int kt, int nl, const TailLevel *tl, const Level &C, int sweeps,
                  const double *done);
@@ -200,6 +224,7 @@ void launch_spmv_dots(hipStream_t s, const Level &L, int nb, int first, const do
                       const double *q, double *v, double *partials, double *scal);
 void launch_update(hipStream_t s, int n, int nb, int first, const double *w, const double *v,
                    double *d, double *u, double *q, double *r, double *partials, double *scal);
+void launch_finalize(hipStream_t s, int mode, int nb, int first, const double *partials, double *scal);
 // sliced-ELL variants of the row-parallel solve kernels (level must hold E)
 void launch_resid_sell(hipStream_t s, const Level &L, int nb, const double *b, const double *u, double *r,
                        double *partials, double *scal);

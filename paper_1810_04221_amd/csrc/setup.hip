@@ -165,13 +165,19 @@ k_candidates(int n, const int *__restrict__ rp, const int *__restrict__ ci, cons
 // every thread exits.  The final suitor pairs are mutual and equal the greedy
 // matching under (c desc, larger endpoint desc, smaller desc).
 // ----------------------------------------------------------------------------
+// Read ws[v] before the atomic: skips atomics that would lose, at the price of
+// one more memory round trip on every successful proposal.
+constexpr bool kSuitorPrecheck = true;
+
 __global__ void __launch_bounds__(kBlock)
-k_suitor(int n, const int *__restrict__ rp, const unsigned long long *__restrict__ cand, int *pos,
-         unsigned long long *ws) {
-    // Highest vertices first: workgroups are dispatched roughly in index order,
-    // and the greedy order settles large indices first on equal weights.
-    const int u0 = n - 1 - (int)(blockIdx.x * kBlock + threadIdx.x);
-    if (u0 < 0) return;
+k_suitor(int n, int first, int count, const int *__restrict__ rp, const unsigned long long *__restrict__ cand,
+         int *pos, unsigned long long *ws) {
+    // Vertices n-1-first-t for t < count: highest vertices first.  Workgroups
+    // are dispatched roughly in index order, and the greedy order settles large
+    // indices first on equal weights.
+    const int t0 = (int)(blockIdx.x * kBlock + threadIdx.x);
+    if (t0 >= count) return;
+    const int u0 = n - 1 - first - t0;
     int u = u0;
     int t = rp[u], end = rp[u + 1];
     for (;;) {
@@ -182,7 +188,7 @@ k_suitor(int n, const int *__restrict__ rp, const unsigned long long *__restrict
             if (e == ~0ull) break;
             const unsigned long long k = (e & 0xffffffff00000000ull) | (unsigned long long)(unsigned)(u + 1);
             const int vt = (int)(e & 0xffffffffull);
-            if (k > load_agent(&ws[vt])) { v = vt; key = k; break; }
+            if (!kSuitorPrecheck || k > load_agent(&ws[vt])) { v = vt; key = k; break; }
         }
         if (v < 0) break;  // no candidate left: u stays unmatched
         __hip_atomic_store(&pos[u], t + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -506,9 +512,19 @@ void launch_candidates(hipStream_t s, int G, int n, const int *rp, const int *ci
     });
 }
 
+// The vertices are handed out in launches of kSuitorChunk, highest first.  The
+// matching does not depend on the order in which vertices propose; the
+// chunks only keep low vertices from proposing before the high ones settled,
+// which on equal weights shortens the chains of displaced suitors.
+constexpr int kSuitorChunk = 1 << 30;
+
 void launch_suitor(hipStream_t s, int n, const int *rp, const unsigned long long *cand, int *pos,
                    unsigned long long *ws) {
-    hipLaunchKernelGGL(k_suitor, dim3(blocks_for(n)), dim3(kBlock), 0, s, n, rp, cand, pos, ws);
+    for (long long first = 0; first < n; first += kSuitorChunk) {
+        const int count = (int)(n - first < kSuitorChunk ? n - first : kSuitorChunk);
+        hipLaunchKernelGGL(k_suitor, dim3(blocks_for(count)), dim3(kBlock), 0, s, n, (int)first, count, rp, cand,
+                           pos, ws);
+    }
 }
 
 void launch_mate(hipStream_t s, int n, const unsigned long long *ws, int *mate, int *leader) {

@@ -254,6 +254,142 @@ k_smooth_sell(int n, const int *__restrict__ sp, const int *__restrict__ sc, con
     x[i] = (VX)(xp[i] + dinv[i] * ((V)b[i] - s));
 }
 
+// W-cycle helpers (levels >= 1, cycle precision): the coarse residual in place,
+// b_i <- b_i - sum_j a_ij x_j, and x <- x + y.
+template <int G, typename V>
+__global__ void __launch_bounds__(kBlock)
+k_resid_inplace(int n, const int *__restrict__ rp, const int *__restrict__ ci, const V *__restrict__ a,
+                const V *__restrict__ x, V *__restrict__ b, const double *__restrict__ done) {
+    if (done && *done != 0.0) return;
+    const int lane = threadIdx.x % G;
+    const int i = (xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x) / G;
+    if (i >= n) return;
+    V s = V(0);
+    const int e = rp[i + 1];
+    for (int q = rp[i] + lane; q < e; q += G) s += a[q] * x[ci[q]];
+    s = group_sum<G>(s);
+    if (lane == 0) b[i] = b[i] - s;
+}
+
+template <typename V>
+__global__ void __launch_bounds__(kBlock)
+k_add(int n, const V *__restrict__ y, V *__restrict__ x, const double *__restrict__ done) {
+    if (done && *done != 0.0) return;
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) x[i] = x[i] + y[i];
+}
+
+// ----------------------------------------------------------------------------
+// K-cycle coarse solve on a level C (cycle precision V): two flexible-CG
+// iterations from zero on A_C x = b, preconditioned by C's cycle, written with
+// the two preconditioned directions c1 = B(b) and c2 = B(b~):
+//   step 1: v1 = A c1, rho1 = c1'v1, alpha1 = c1'b, b~ = b - (alpha1/rho1) v1
+//   step 2: gamma = c2'v1, beta = c2'A c2, alpha2 = c2'b~,
+//           rho2 = beta - gamma^2 / rho1
+//   x = (alpha1/rho1) c1 + (alpha2/rho2) (c2 - (gamma/rho1) c1)
+// (the iterates of the flexible CG loop: d1 = c1, d2 = c2 - (gamma/rho1) d1).
+// An iteration whose rho is not positive and finite ends the coarse CG with
+// the directions kept so far.  Dot products accumulate in float64 through
+// block partials summed in block order (k_kfinal).
+// ks[]: [0] rho1 [1] alpha1/rho1 [2] gamma/rho1 [3] alpha2/rho2 [4] directions kept
+// ----------------------------------------------------------------------------
+// step 1 (c = c1, vout = v1): acc = {c'Ac, c'b};  step 2 (c = c2, vin = v1):
+// acc = {c'v1, c'Ac, c'b}.  Rows in a grid-stride loop, G lanes per row.
+template <int G, typename V, int STEP>
+__global__ void __launch_bounds__(kBlock)
+k_kdots(int n, const int *__restrict__ rp, const int *__restrict__ ci, const V *__restrict__ a,
+        const V *__restrict__ c, const V *__restrict__ b, const V *__restrict__ vin, V *__restrict__ vout,
+        double *__restrict__ partials, const double *__restrict__ done) {
+    if (done && *done != 0.0) return;
+    constexpr int K = STEP == 1 ? 2 : 3;
+    double acc[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) acc[k] = 0.0;
+    const int lane = threadIdx.x % G;
+    const int rows_per_grid = gridDim.x * (kBlock / G);
+    for (int i = (xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x) / G; i < n; i += rows_per_grid) {
+        V s = V(0);
+        const int e = rp[i + 1];
+        for (int q = rp[i] + lane; q < e; q += G) s += a[q] * c[ci[q]];
+        s = group_sum<G>(s);
+        if (lane == 0) {
+            const double ci_ = (double)c[i];
+            if (STEP == 1) {
+                vout[i] = s;
+                acc[0] += ci_ * (double)s;
+                acc[1] += ci_ * (double)b[i];
+            } else {
+                acc[0] += ci_ * (double)vin[i];
+                acc[1] += ci_ * (double)s;
+                acc[2] += ci_ * (double)b[i];
+            }
+        }
+    }
+    block_partials<K>(acc, partials);
+}
+
+template <int STEP>
+__global__ void __launch_bounds__(kBlock) k_kfinal(int nb, const double *__restrict__ partials,
+                                                   double *__restrict__ ks, const double *__restrict__ done) {
+    if (done && *done != 0.0) return;
+    constexpr int K = STEP == 1 ? 2 : 3;
+    __shared__ double lds[K * 16];
+    double s[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) s[k] = 0.0;
+    for (int bk = threadIdx.x; bk < nb; bk += blockDim.x)
+#pragma unroll
+        for (int k = 0; k < K; ++k) s[k] += partials[(size_t)k * nb + bk];
+    block_sum<K>(s, lds);
+    if (threadIdx.x != 0) return;
+    if (STEP == 1) {
+        const double rho = s[0];
+        const bool ok = rho > 0.0 && isfinite(rho);
+        ks[0] = rho;
+        ks[1] = ok ? s[1 % K] / rho : 0.0;
+        ks[2] = 0.0;
+        ks[3] = 0.0;
+        ks[4] = ok ? 1.0 : 0.0;
+    } else {
+        if (ks[4] != 1.0) return;
+        const double gamma = s[0], beta = s[1 % K], alpha = s[2 % K], rho1 = ks[0];
+        const double rho = beta - gamma * gamma / rho1;
+        if (!(rho > 0.0) || !isfinite(rho)) return;
+        ks[2] = gamma / rho1;
+        ks[3] = alpha / rho;
+        ks[4] = 2.0;
+    }
+}
+
+// b <- b - (alpha1/rho1) v1
+template <typename V>
+__global__ void __launch_bounds__(kBlock)
+k_kresid(int n, const V *__restrict__ v1, const double *__restrict__ ks, V *__restrict__ b,
+         const double *__restrict__ done) {
+    if (done && *done != 0.0) return;
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const V a1 = (V)ks[1];
+    b[i] = b[i] - a1 * v1[i];
+}
+
+// x <- (alpha1/rho1) c1 + (alpha2/rho2) (c2 - (gamma/rho1) c1), with c1 in x
+template <typename V>
+__global__ void __launch_bounds__(kBlock)
+k_kcombine(int n, const V *__restrict__ c2, const double *__restrict__ ks, V *__restrict__ x,
+           const double *__restrict__ done) {
+    if (done && *done != 0.0) return;
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const double kept = ks[4];
+    const V a1 = (V)ks[1], g = (V)ks[2], a2 = (V)ks[3];
+    const V c1 = x[i];
+    V r = V(0);
+    if (kept == 2.0) r = a1 * c1 + a2 * (c2[i] - g * c1);
+    else if (kept == 1.0) r = a1 * c1;
+    x[i] = r;
+}
+
 // ----------------------------------------------------------------------------
 // Coarsest level: `sweeps` l1-Jacobi sweeps from zero in float64, inside one
 // workgroup with x in LDS (n <= 8192).  When the level's matrix also fits, it
@@ -817,6 +953,80 @@ void launch_tail(hipStream_t s, int fp32, int kt, int nl, const TailLevel *tl, c
         hipLaunchKernelGGL((k_tail<double>), dim3(1), dim3(1024), 0, s, kt, nl, tl, C.S, C.dinv, C.A.v, sweeps, done);
 }
 
+void launch_resid_inplace(hipStream_t s, const Level &L, int fp32, const void *x, void *b, const double *done) {
+    with_G(L.G, [&](auto gc) {
+        constexpr int g = decltype(gc)::value;
+        if (fp32)
+            hipLaunchKernelGGL((k_resid_inplace<g, float>), dim3(blocks_for((long long)L.A.n * g)), dim3(kBlock), 0, s,
+                               L.A.n, L.A.rp, L.A.ci, L.A.v32, (const float *)x, (float *)b, done);
+        else
+            hipLaunchKernelGGL((k_resid_inplace<g, double>), dim3(blocks_for((long long)L.A.n * g)), dim3(kBlock), 0,
+                               s, L.A.n, L.A.rp, L.A.ci, L.A.v, (const double *)x, (double *)b, done);
+    });
+}
+
+void launch_add(hipStream_t s, int n, int fp32, const void *y, void *x, const double *done) {
+    if (fp32)
+        hipLaunchKernelGGL((k_add<float>), dim3(blocks_for(n)), dim3(kBlock), 0, s, n, (const float *)y, (float *)x,
+                           done);
+    else
+        hipLaunchKernelGGL((k_add<double>), dim3(blocks_for(n)), dim3(kBlock), 0, s, n, (const double *)y,
+                           (double *)x, done);
+}
+
+int kcycle_blocks(const Level &L) {
+    long long b = ((long long)L.A.n * L.G + kBlock - 1) / kBlock;
+    if (b > kKPartBlocks) b = kKPartBlocks;
+    if (b < 1) b = 1;
+    return (int)b;
+}
+
+void launch_kcycle_step1(hipStream_t s, const Level &C, int fp32, const void *c1, const void *b, void *v1,
+                         double *partials, double *ks, const double *done) {
+    const int nb = kcycle_blocks(C);
+    with_G(C.G, [&](auto gc) {
+        constexpr int g = decltype(gc)::value;
+        if (fp32)
+            hipLaunchKernelGGL((k_kdots<g, float, 1>), dim3(nb), dim3(kBlock), 0, s, C.A.n, C.A.rp, C.A.ci, C.A.v32,
+                               (const float *)c1, (const float *)b, (const float *)nullptr, (float *)v1, partials,
+                               done);
+        else
+            hipLaunchKernelGGL((k_kdots<g, double, 1>), dim3(nb), dim3(kBlock), 0, s, C.A.n, C.A.rp, C.A.ci, C.A.v,
+                               (const double *)c1, (const double *)b, (const double *)nullptr, (double *)v1,
+                               partials, done);
+    });
+    hipLaunchKernelGGL(k_kfinal<1>, dim3(1), dim3(kBlock), 0, s, nb, partials, ks, done);
+    if (fp32)
+        hipLaunchKernelGGL((k_kresid<float>), dim3(blocks_for(C.A.n)), dim3(kBlock), 0, s, C.A.n, (const float *)v1,
+                           ks, (float *)b, done);
+    else
+        hipLaunchKernelGGL((k_kresid<double>), dim3(blocks_for(C.A.n)), dim3(kBlock), 0, s, C.A.n,
+                           (const double *)v1, ks, (double *)b, done);
+}
+
+void launch_kcycle_step2(hipStream_t s, const Level &C, int fp32, const void *c2, const void *b, const void *v1,
+                         void *x, double *partials, double *ks, const double *done) {
+    const int nb = kcycle_blocks(C);
+    with_G(C.G, [&](auto gc) {
+        constexpr int g = decltype(gc)::value;
+        if (fp32)
+            hipLaunchKernelGGL((k_kdots<g, float, 2>), dim3(nb), dim3(kBlock), 0, s, C.A.n, C.A.rp, C.A.ci, C.A.v32,
+                               (const float *)c2, (const float *)b, (const float *)v1, (float *)nullptr, partials,
+                               done);
+        else
+            hipLaunchKernelGGL((k_kdots<g, double, 2>), dim3(nb), dim3(kBlock), 0, s, C.A.n, C.A.rp, C.A.ci, C.A.v,
+                               (const double *)c2, (const double *)b, (const double *)v1, (double *)nullptr,
+                               partials, done);
+    });
+    hipLaunchKernelGGL(k_kfinal<2>, dim3(1), dim3(kBlock), 0, s, nb, partials, ks, done);
+    if (fp32)
+        hipLaunchKernelGGL((k_kcombine<float>), dim3(blocks_for(C.A.n)), dim3(kBlock), 0, s, C.A.n,
+                           (const float *)c2, ks, (float *)x, done);
+    else
+        hipLaunchKernelGGL((k_kcombine<double>), dim3(blocks_for(C.A.n)), dim3(kBlock), 0, s, C.A.n,
+                           (const double *)c2, ks, (double *)x, done);
+}
+
 void launch_coarse_build(hipStream_t s, const Level &L, int sweeps, double *S) {
     hipLaunchKernelGGL((k_coarse<double, double>), dim3(L.A.n), dim3(1024), 0, s, L.A.n, L.A.nnz, L.A.rp, L.A.ci,
                        L.A.v, L.dinv, (const double *)nullptr, S, sweeps, 1, (const double *)nullptr);
@@ -827,7 +1037,6 @@ void launch_resid(hipStream_t s, const Level &L, int nb, const double *b, const 
     if (L.E.sp) {
         hipLaunchKernelGGL(k_resid_sell, dim3(nb), dim3(kBlock), 0, s, L.A.n, L.E.sp, L.E.sc, L.E.sv, b, u, r,
                            partials);
-        hipLaunchKernelGGL(k_finalize<2>, dim3(1), dim3(kBlock), 0, s, nb, partials, scal, 0, 0);
         return;
     }
     with_G(L.G, [&](auto gc) {
@@ -835,7 +1044,6 @@ void launch_resid(hipStream_t s, const Level &L, int nb, const double *b, const 
         hipLaunchKernelGGL(k_resid<g>, dim3(nb), dim3(kBlock), 0, s, L.A.n, L.A.rp, L.A.ci, L.A.v, b, u, r,
                            partials);
     });
-    hipLaunchKernelGGL(k_finalize<2>, dim3(1), dim3(kBlock), 0, s, nb, partials, scal, 0, 0);
 }
 
 void launch_spmv_dots(hipStream_t s, const Level &L, int nb, int first, const double *w, const double *r,
@@ -843,7 +1051,6 @@ void launch_spmv_dots(hipStream_t s, const Level &L, int nb, int first, const do
     if (L.E.sp) {
         hipLaunchKernelGGL(k_spmv_dots_sell, dim3(nb), dim3(kBlock), 0, s, L.A.n, L.E.sp, L.E.sc, L.E.sv, w, r, q, v,
                            partials, scal + 10);
-        hipLaunchKernelGGL(k_finalize<3>, dim3(1), dim3(kBlock), 0, s, nb, partials, scal, 1, first);
         return;
     }
     with_G(L.G, [&](auto gc) {
@@ -851,13 +1058,17 @@ void launch_spmv_dots(hipStream_t s, const Level &L, int nb, int first, const do
         hipLaunchKernelGGL(k_spmv_dots<g>, dim3(nb), dim3(kBlock), 0, s, L.A.n, L.A.rp, L.A.ci, L.A.v, w, r, q, v,
                            partials, scal + 10);
     });
-    hipLaunchKernelGGL(k_finalize<3>, dim3(1), dim3(kBlock), 0, s, nb, partials, scal, 1, first);
 }
 
 void launch_update(hipStream_t s, int n, int nb, int first, const double *w, const double *v, double *d,
                    double *u, double *q, double *r, double *partials, double *scal) {
     hipLaunchKernelGGL(k_update, dim3(nb), dim3(kBlock), 0, s, n, first, w, v, d, u, q, r, scal, partials);
-    hipLaunchKernelGGL(k_finalize<1>, dim3(1), dim3(kBlock), 0, s, nb, partials, scal, 2, 0);
+}
+
+void launch_finalize(hipStream_t s, int mode, int nb, int first, const double *partials, double *scal) {
+    if (mode == 0) hipLaunchKernelGGL(k_finalize<2>, dim3(1), dim3(kBlock), 0, s, nb, partials, scal, 0, 0);
+    else if (mode == 1) hipLaunchKernelGGL(k_finalize<3>, dim3(1), dim3(kBlock), 0, s, nb, partials, scal, 1, first);
+    else hipLaunchKernelGGL(k_finalize<1>, dim3(1), dim3(kBlock), 0, s, nb, partials, scal, 2, 0);
 }
 
 void launch_sampled_outer(hipStream_t s, const Level &L, const double *lam, const double *x, double *G) {

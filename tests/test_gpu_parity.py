@@ -245,3 +245,129 @@ def test_indefinite_matrix_breakdown(B):
     with pytest.raises(B.BcmError) as e:
         h.solve(P.uniform_rhs(64, 0), tol=1e-10)
     assert e.value.code in (B.BCM_EBREAKDOWN,)
+
+
+# ----------------------------------------------------------------------------- lane width (miniwarp)
+@pytest.mark.parametrize("name,scale,group,sell", [("G2", 0.3, 4, False), ("G2", 0.3, 64, False),
+                                                   ("G4", 0.21, 16, True), ("G4", 0.21, 64, False),
+                                                   ("G3", 0.2, -1, False), ("G2", 0.3, -1, True)])
+def test_lane_width_and_sell_settings(B, ora, name, scale, group, sell):
+    # the hierarchy is bit-identical for every lane width (setup sums in a fixed
+    # order); the cycle, with or without the sliced-ELL copies, within rounding
+    c = P.config(name, scale)
+    say(f"lane width {group} sell={sell} {c['name']}")
+    h = B.Hierarchy(c["rowptr"], c["col"], c["val"], c["w"], max_coarse=c["max_coarse"], group=group, sell=sell)
+    ho = ora.Hierarchy(c["rowptr"], c["col"], c["val"], c["w"], max_coarse=c["max_coarse"])
+    _compare_hierarchy(h, ho)
+    r = P.uniform_rhs(c["n"], 16)
+    z, zo = h.precond(r).cpu().numpy(), ho.vcycle(r)
+    assert np.linalg.norm(z - zo) <= 1e-12 * np.linalg.norm(zo)
+    x = h.solve(c["b"], tol=c["tol"]).cpu().numpy()
+    _, io = ho.solve(c["b"], tol=c["tol"])
+    A = sp.csr_matrix((c["val"], c["col"], c["rowptr"]), shape=(c["n"], c["n"]))
+    assert np.linalg.norm(c["b"] - A @ x) <= c["tol"] * np.linalg.norm(c["b"])
+    assert abs(h.info()["iters"] - io["iters"]) <= 1
+
+
+# ----------------------------------------------------------------------------- W-cycle
+@pytest.mark.parametrize("name,scale,precision", [("G1", 1.0, "fp64"), ("G2", 0.3, "fp64"), ("G4", 0.21, "fp64"),
+                                                  ("G2", 0.3, "fp32")])
+def test_w_cycle_parity(B, ora, name, scale, precision):
+    c = P.config(name, scale)
+    say(f"W-cycle {precision} {c['name']}")
+    h = B.Hierarchy(c["rowptr"], c["col"], c["val"], c["w"], max_coarse=c["max_coarse"], cycle="W",
+                    precision=precision)
+    ho = ora.Hierarchy(c["rowptr"], c["col"], c["val"], c["w"], max_coarse=c["max_coarse"], cycle="W")
+    r = P.uniform_rhs(c["n"], 13)
+    z, zo = h.precond(r).cpu().numpy(), ho.vcycle(r)
+    bound = 1e-12 if precision == "fp64" else 1e-5
+    assert np.linalg.norm(z - zo) <= bound * np.linalg.norm(zo)
+    x = h.solve(c["b"], tol=c["tol"]).cpu().numpy()
+    xo, io = ho.solve(c["b"], tol=c["tol"])
+    inf = h.info()
+    A = sp.csr_matrix((c["val"], c["col"], c["rowptr"]), shape=(c["n"], c["n"]))
+    assert np.linalg.norm(c["b"] - A @ x) <= c["tol"] * np.linalg.norm(c["b"])
+    if precision == "fp64":
+        assert abs(inf["iters"] - io["iters"]) <= 1, (inf["iters"], io["iters"])
+    say(f"W-cycle {precision} {c['name']} iters gpu={inf['iters']} oracle={io['iters']}")
+
+
+# ----------------------------------------------------------------------------- K-cycle
+@pytest.mark.parametrize("name,scale,precision,klevels", [("G1", 1.0, "fp64", 0), ("G2", 0.3, "fp64", 0),
+                                                          ("G2", 0.3, "fp64", 1), ("G3", 0.2, "fp64", 2),
+                                                          ("G4", 0.21, "fp64", 0), ("G2", 0.3, "fp32", 0)])
+def test_k_cycle_parity(B, ora, name, scale, precision, klevels):
+    c = P.config(name, scale)
+    say(f"K-cycle {precision} {c['name']} kcycle_levels={klevels}")
+    h = B.Hierarchy(c["rowptr"], c["col"], c["val"], c["w"], max_coarse=c["max_coarse"], cycle="K",
+                    kcycle_levels=klevels, precision=precision)
+    ho = ora.Hierarchy(c["rowptr"], c["col"], c["val"], c["w"], max_coarse=c["max_coarse"], cycle="K",
+                       kcycle_levels=klevels)
+    r = P.uniform_rhs(c["n"], 14)
+    z, zo = h.precond(r).cpu().numpy(), ho.vcycle(r)
+    err = np.linalg.norm(z - zo) / np.linalg.norm(zo)
+    say(f"K-cycle {precision} {c['name']} precond rel err {err:.2e}")
+    assert err <= (1e-11 if precision == "fp64" else 1e-4)
+    x = h.solve(c["b"], tol=c["tol"]).cpu().numpy()
+    xo, io = ho.solve(c["b"], tol=c["tol"])
+    inf = h.info()
+    A = sp.csr_matrix((c["val"], c["col"], c["rowptr"]), shape=(c["n"], c["n"]))
+    assert np.linalg.norm(c["b"] - A @ x) <= c["tol"] * np.linalg.norm(c["b"])
+    say(f"K-cycle {precision} {c['name']} iters gpu={inf['iters']} oracle={io['iters']}")
+    if precision == "fp64":
+        assert abs(inf["iters"] - io["iters"]) <= max(1, int(0.03 * io["iters"])), (inf["iters"], io["iters"])
+
+
+def test_k_cycle_zero_and_scaled_rhs(B):
+    # b = 0 ends the coarse flexible CG at once (rho = 0): B(0) = 0; the cycle
+    # is homogeneous: B(2r) = 2 B(r) bit for bit
+    c = P.config("G2", 0.3)
+    say("K-cycle zero and scaled right-hand side")
+    h = B.Hierarchy(c["rowptr"], c["col"], c["val"], max_coarse=c["max_coarse"], cycle="K")
+    assert not h.precond(np.zeros(c["n"])).any().item()
+    r = P.uniform_rhs(c["n"], 15)
+    z1 = h.precond(r).cpu().numpy()
+    z2 = h.precond(2.0 * r).cpu().numpy()
+    assert np.array_equal(z2, 2.0 * z1)
+
+
+# ----------------------------------------------------------------------------- HIP graph replay
+@pytest.mark.parametrize("cycle,precision", [("V", "fp64"), ("V", "fp32"), ("W", "fp64"), ("K", "fp64"),
+                                             ("K", "fp32")])
+def test_graph_replay_equals_eager(B, cycle, precision):
+    # the captured iteration is replayed across several solves, with eager work in
+    # between; every result must equal the eager solve bit for bit
+    c = P.config("G2", 0.3)
+    say(f"graph replay {cycle} {precision}")
+    he = B.Hierarchy(c["rowptr"], c["col"], c["val"], max_coarse=c["max_coarse"], cycle=cycle,
+                     precision=precision, graph=False)
+    hg = B.Hierarchy(c["rowptr"], c["col"], c["val"], max_coarse=c["max_coarse"], cycle=cycle,
+                     precision=precision, graph=True)
+    for seed in (1, 2, 1):
+        b = P.uniform_rhs(c["n"], seed)
+        xe = he.solve(b, tol=1e-9).cpu().numpy()
+        ie = he.info()["iters"]
+        z = hg.precond(b)  # eager work on the same handle between replays
+        xg = hg.solve(b, tol=1e-9).cpu().numpy()
+        assert hg.info()["iters"] == ie
+        assert np.array_equal(xg.view(np.uint64), xe.view(np.uint64))
+        assert z.isfinite().all().item()
+
+
+@pytest.mark.parametrize("cls", ["spmv_dots", "down0", "coarse"])
+def test_graph_profiling_times_one_class(B, cls):
+    # with a one-class profile mask the iteration still runs from the graph; the
+    # class is timed by event nodes inside it and the result is unchanged
+    c = P.config("G2", 0.3)
+    say(f"graph profiling {cls}")
+    b = P.uniform_rhs(c["n"], 3)
+    he = B.Hierarchy(c["rowptr"], c["col"], c["val"], max_coarse=c["max_coarse"], graph=False)
+    hg = B.Hierarchy(c["rowptr"], c["col"], c["val"], max_coarse=c["max_coarse"], graph=True,
+                     profile=B.PROF[cls])
+    xe = he.solve(b, tol=1e-9).cpu().numpy()
+    xg = hg.solve(b, tol=1e-9).cpu().numpy()
+    assert np.array_equal(xg.view(np.uint64), xe.view(np.uint64))
+    launches, ms, by = hg.profile(cls)
+    # the eager first iteration plus at least one replay sample
+    assert 2 <= launches <= hg.info()["iters"]
+    assert ms > 0.0 and by > 0.0

@@ -257,3 +257,131 @@ def test_w_cycle_spd_and_fewer_iterations(ora, name, scale):
     _, iw = hw.solve(c["b"], tol=1e-8)
     _, iv = hv.solve(c["b"], tol=1e-8)
     assert iw["status"] == 0 and iw["iters"] <= iv["iters"]
+
+
+# ----------------------------------------------------------------------------- K-cycle
+def _dense_kcycle(h, klevels):
+    """Dense recursive K-cycle written with the explicit two-direction formula of
+    the Krylov-based cycle: with c1 = B(b), rho1 = c1'A c1, alpha1 = c1'b,
+    rt = b - (alpha1/rho1) A c1, c2 = B(rt), gamma = c2'A c1, rho2 = c2'A c2 -
+    gamma^2/rho1, alpha2 = c2'rt:
+        x_c = (alpha1/rho1) c1 + (alpha2/rho2) (c2 - (gamma/rho1) c1)."""
+    levels = [h.level(k) for k in range(h.nl)]
+    mats = [_sp(L["rowptr"], L["col"], L["val"]).toarray() for L in levels]
+    D = [np.diag(1.0 / np.abs(M).sum(axis=1)) for M in mats]
+    Sc = _jacobi_poly(mats[-1], np.diag(D[-1]), 20)
+    Ps = []
+    for k in range(h.nl - 1):
+        L = levels[k]
+        Ps.append(sp.csr_matrix((L["p"], L["agg"], np.arange(L["n"] + 1)), shape=(L["n"], levels[k + 1]["n"])).toarray())
+
+    def two_step(Ac, M, b):
+        c1 = M(b)
+        v1 = Ac @ c1
+        rho1, alpha1 = c1 @ v1, c1 @ b
+        rt = b - (alpha1 / rho1) * v1
+        c2 = M(rt)
+        gamma, beta, alpha2 = c2 @ v1, c2 @ (Ac @ c2), c2 @ rt
+        rho2 = beta - gamma * gamma / rho1
+        return (alpha1 / rho1) * c1 + (alpha2 / rho2) * (c2 - (gamma / rho1) * c1)
+
+    def B(k, b):
+        if k == h.nl - 1:
+            return Sc @ b
+        A = mats[k]
+        x1 = D[k] @ b
+        bc = Ps[k].T @ (b - A @ x1)
+        if klevels == 0 or k < klevels:
+            xc = two_step(mats[k + 1], lambda r: B(k + 1, r), bc)
+        else:
+            xc = B(k + 1, bc)
+        x2 = x1 + Ps[k] @ xc
+        return x2 + D[k] @ (b - A @ x2)
+
+    return B, mats, D, Ps
+
+
+def _pcg_two_steps(A, M, b):
+    """Two steps of textbook preconditioned CG (Hestenes-Stiefel with the
+    Fletcher-Reeves beta = r1'z1 / r0'z0) from zero: equal to the flexible form
+    when M is linear and s.p.d."""
+    r = b.copy()
+    z = M @ r
+    p = z.copy()
+    rz = r @ z
+    a = rz / (p @ A @ p)
+    x = a * p
+    r = r - a * (A @ p)
+    z = M @ r
+    rz2 = r @ z
+    p = z + (rz2 / rz) * p
+    return x + (rz2 / (p @ A @ p)) * p
+
+
+@pytest.mark.parametrize("klevels", [0, 1, 2])
+def test_k_cycle_dense_two_direction_form(ora, klevels):
+    rp, ci, va = P.poisson2d(24)
+    n = 576
+    h = ora.Hierarchy(rp, ci, va, np.ones(n), max_coarse=10, cycle="K", kcycle_levels=klevels)
+    assert h.nl >= 3
+    b = np.random.default_rng(11).standard_normal(n)
+    ref = _dense_kcycle(h, klevels)[0](0, b)
+    assert np.allclose(h.vcycle(b), ref, rtol=1e-11, atol=1e-12 * np.abs(ref).max())
+
+
+def test_k_cycle_first_level_equals_textbook_pcg(ora):
+    # K only at the finest level: the coarse solve is two PCG steps with the
+    # (linear, s.p.d.) V-cycle of level 1 as preconditioner
+    rp, ci, va = P.poisson2d(24)
+    n = 576
+    hk = ora.Hierarchy(rp, ci, va, np.ones(n), max_coarse=10, cycle="K", kcycle_levels=1)
+    hv = ora.Hierarchy(rp, ci, va, np.ones(n), max_coarse=10)
+    B, mats, D, Ps = _dense_kcycle(hv, -1)  # klevels -1: plain V recursion
+    n1 = mats[1].shape[0]
+    M1 = np.column_stack([B(1, e) for e in np.eye(n1)])
+    b = np.random.default_rng(12).standard_normal(n)
+    x1 = D[0] @ b
+    xc = _pcg_two_steps(mats[1], M1, Ps[0].T @ (b - mats[0] @ x1))
+    x2 = x1 + Ps[0] @ xc
+    ref = x2 + D[0] @ (b - mats[0] @ x2)
+    assert np.allclose(hk.vcycle(b), ref, rtol=1e-10, atol=1e-11 * np.abs(ref).max())
+    assert not np.allclose(hk.vcycle(b), hv.vcycle(b), rtol=1e-6)
+
+
+def test_k_cycle_homogeneous_not_linear(ora):
+    # the Krylov coefficients scale away exactly for powers of two (B(2b) = 2B(b),
+    # B(-b) = -B(b) bit for bit), but the cycle is not additive
+    c = P.config("G1", 1.0)
+    h = ora.Hierarchy(c["rowptr"], c["col"], c["val"], c["w"], max_coarse=20, cycle="K")
+    rng = np.random.default_rng(13)
+    x, y = rng.standard_normal(h.n), rng.standard_normal(h.n)
+    Bx = h.vcycle(x)
+    assert np.array_equal(h.vcycle(2.0 * x), 2.0 * Bx)
+    assert np.array_equal(h.vcycle(-x), -Bx)
+    assert np.linalg.norm(h.vcycle(x + y) - Bx - h.vcycle(y)) > 1e-6 * np.linalg.norm(Bx)
+
+
+def test_k_cycle_zero_rhs(ora):
+    rp, ci, va = P.poisson2d(24)
+    n = 576
+    h = ora.Hierarchy(rp, ci, va, np.ones(n), max_coarse=10, cycle="K")
+    assert np.array_equal(h.vcycle(np.zeros(n)), np.zeros(n))  # rho = 0 stops the coarse CG
+
+
+@pytest.mark.parametrize("name,scale", [("G1", 0.5), ("G2", 0.15), ("G3", 0.1), ("G4", 0.25)])
+def test_k_cycle_converges(ora, name, scale):
+    # scalar diffusion: fewer outer iterations than the V-cycle.  Elasticity
+    # with l1-Jacobi: the one-direction flexible CG of Algorithm 3 loses to the
+    # V-cycle there (the K-cycle varies too much from one residual to the next
+    # for a single kept direction), but still converges
+    c = P.config(name, scale)
+    mc = min(c["max_coarse"], 30)
+    hk = ora.Hierarchy(c["rowptr"], c["col"], c["val"], c["w"], max_coarse=mc, cycle="K")
+    hv = ora.Hierarchy(c["rowptr"], c["col"], c["val"], c["w"], max_coarse=mc)
+    xk, ik = hk.solve(c["b"], tol=1e-8)
+    _, iv = hv.solve(c["b"], tol=1e-8)
+    assert ik["status"] == 0 and ik["relres"] <= 1e-8
+    A = _sp(c["rowptr"], c["col"], c["val"])
+    assert np.linalg.norm(c["b"] - A @ xk) <= 1e-8 * np.linalg.norm(c["b"])
+    if name != "G4":
+        assert ik["iters"] <= iv["iters"]
