@@ -47,9 +47,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibration-copy-mb", type=int, default=0,
                     help="run one device copy of this many MiB first (reference for HBM counters)")
-    ap.add_argument("--ablation", choices=["miniwarp", "cycles"], default=None,
-                    help="instead of the benchmark line: time setup + solve under each lane-width "
-                         "setting (miniwarp) or each cycle type (cycles) and print one JSON line")
+    ap.add_argument("--ablation", choices=sorted(ABLATIONS), default=None,
+                    help="instead of the benchmark line: time setup + solve under each setting of one "
+                         "knob (lane width, cycle type, sweeps per level, smooth vector) and print one "
+                         "JSON line")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -82,8 +83,9 @@ def main():
         log(f"calibration copy: {args.calibration_copy_mb} MiB read + written")
         del src, dst
 
-    def step(precision, mask, **kw):
-        h = bcm.Hierarchy(rp, ci, va, w, max_coarse=c["max_coarse"], precision=precision, profile=mask, **kw)
+    def step(precision, mask, wvec=None, **kw):
+        h = bcm.Hierarchy(rp, ci, va, w if wvec is None else wvec, max_coarse=c["max_coarse"],
+                          precision=precision, profile=mask, **kw)
         h.solve(b, tol=tol)
         info = h.info()
         prof = {k: h.profile(k) for k in CLASSES if mask & bcm.PROF[k]}
@@ -197,13 +199,35 @@ ABLATIONS = {
                  ("timed per level + SELL", "fp64", dict(group=-1, sell=True))],
     "cycles": [(f"{cy}{'' if kl == 0 else f' (K on {kl} levels)'} {pr}", pr, dict(cycle=cy, kcycle_levels=kl))
                for pr in ("fp64", "fp32") for cy, kl in (("V", 0), ("W", 0), ("K", 0), ("K", 1))],
+    # pairwise sweeps composed per level (aggregates of up to 2^sweeps rows)
+    "coarsening": [(f"{sw} sweep{'s' if sw > 1 else ''} per level {pr}", pr, dict(sweeps=sw))
+                   for pr in ("fp64", "fp32") for sw in (1, 2, 3, 4)],
+    # the smooth vector w the matching weights and prolongator are built from
+    "smoothvec": [(f"w = {wk} {pr}", pr, dict(wvec=wk)) for pr in ("fp64", "fp32")
+                  for wk in ("ones", "uniform[0.5,1.5)", "grid sine (lowest Laplacian mode)")],
 }
 
 
 def ablation(args, c, step):
+    import numpy as np
     import torch
+    from paper_1810_04221_amd import problems
     rows = []
     for label, prec, kw in ABLATIONS[args.ablation]:
+        kw = dict(kw)
+        if "wvec" in kw:
+            wk = kw.pop("wvec")
+            if wk == "ones":
+                wv = np.ones(c["n"])
+            elif wk.startswith("uniform"):
+                wv = np.random.default_rng(17).uniform(0.5, 1.5, c["n"])
+            else:
+                nx = int(round(c["n"] ** (1.0 / 3.0)))
+                if nx ** 3 != c["n"] or not c["name"].startswith("poisson3d"):
+                    log(f"skipping '{label}': needs a cubic 3-D Poisson grid")
+                    continue
+                wv = problems.grid_sine_vector(nx)
+            kw["wvec"] = torch.as_tensor(wv, device="cuda")
         for _ in range(max(1, args.warmup)):
             step(prec, 0, **kw)
         torch.cuda.synchronize()

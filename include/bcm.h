@@ -63,6 +63,10 @@ typedef struct {
  *   max_levels     40    maximum number of levels
  *   max_coarse     0     stop coarsening once n_k <= max_coarse;
  *                        0 means round(40 * n^(1/3))
+ *   min_ratio      0     a level formed with n_{k-1} / n_k < min_ratio is the
+ *                        coarsest (coarsening has stalled); 0 means
+ *                        sqrt(2^sweeps), i.e. 2 for double pairwise
+ *                        aggregation; 1 stops only when the size is unchanged
  *   sweeps         2     pairwise matching sweeps composed per level
  *                        (2 = double pairwise aggregation, ratio <= 4); 1..4
  *   coarse_sweeps  20    l1-Jacobi sweeps from zero at the coarsest level
@@ -126,6 +130,7 @@ typedef struct {
     int32_t group;
     int32_t sell;
     double adjoint_tol;
+    double min_ratio;
     void *(*alloc)(size_t bytes, void *ctx);
     void (*dealloc)(void *ptr, size_t bytes, void *ctx);
     void *alloc_ctx;

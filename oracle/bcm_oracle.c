@@ -353,13 +353,18 @@ void ora_free(void *hv) {
 
 /*
  * Builds the hierarchy.  Level k is the coarsest when n_k <= max_coarse, or
- * k + 1 == max_levels, or its coarsening left the size unchanged.  Each
+ * k + 1 == max_levels, or its coarsening left the size unchanged, or it was
+ * formed with a size ratio n_{k-1} / n_k below min_ratio (<= 0: the square root
+ * of the largest ratio 2^sweeps, i.e. 2 for double pairwise aggregation).
+ * Section 5 fixes the coarsest size, the level limit and the largest ratio but
+ * not what ends a stalled coarsening; below that ratio the matching no longer
+ * halves the size per level and further levels only add cost.  Each
  * coarsening composes `sweeps` pairwise sweeps; a sweep that forms no pair is
  * skipped.  Returns NULL on invalid input (status < 0).
  */
 void *ora_setup(int n, const int *rp, const int *ci, const double *v, const double *w,
                 int max_levels, int max_coarse, int sweeps, int coarse_sweeps, int cycle,
-                int klevels, int *status) {
+                int klevels, double min_ratio, int *status) {
     *status = 0;
     if (max_levels < 1 || max_levels > ORA_MAXLEV || sweeps < 1 || sweeps > 8 || cycle < 1 || cycle > 3 ||
         klevels < 0) {
@@ -375,6 +380,7 @@ void *ora_setup(int n, const int *rp, const int *ci, const double *v, const doub
         }
         if (!hasd) { *status = -1; return NULL; }
     }
+    const double rmin = min_ratio > 0.0 ? min_ratio : sqrt(ldexp(1.0, sweeps));
     ohier *h = calloc(1, sizeof(ohier));
     h->coarse_sweeps = coarse_sweeps;
     h->cycle = cycle;
@@ -434,6 +440,8 @@ void *ora_setup(int n, const int *rp, const int *ci, const double *v, const doub
         h->lv[k + 1].A = Acur;
         h->lv[k + 1].w = wcur;
         k++;
+        /* coarsening has stalled: the new level is the coarsest */
+        if ((double)nk < rmin * (double)Acur.n) break;
     }
     h->nl = k + 1;
     for (int l = 0; l < h->nl; l++) level_alloc_vectors(&h->lv[l]);

@@ -45,7 +45,7 @@ def lib():
         L.ora_prolong.argtypes = [I, P, I, P, P, P]
         L.ora_galerkin.argtypes = [I, P, P, P, P, P, I, P, P, P]
         L.ora_l1_dinv.argtypes = [I, P, P, P, P]
-        L.ora_setup.argtypes = [I, P, P, P, P, I, I, I, I, I, I, C.POINTER(I)]
+        L.ora_setup.argtypes = [I, P, P, P, P, I, I, I, I, I, I, D, C.POINTER(I)]
         L.ora_setup.restype = P
         L.ora_free.argtypes = [P]
         L.ora_nlevels.argtypes = [P]
@@ -146,7 +146,7 @@ class Hierarchy:
     and the composed prolongators P^k (column agg, value p)."""
 
     def __init__(self, rp, ci, va, w, max_levels=40, max_coarse=None, sweeps=2,
-                 coarse_sweeps=20, cycle="V", kcycle_levels=0):
+                 coarse_sweeps=20, cycle="V", kcycle_levels=0, min_ratio=0.0):
         self._keep = [_i32(rp), _i32(ci), _f64(va), _f64(w)]
         rp, ci, va, w = self._keep
         n = len(rp) - 1
@@ -154,7 +154,8 @@ class Hierarchy:
             max_coarse = int(round(40.0 * float(np.cbrt(n))))
         st = C.c_int()
         self.h = lib().ora_setup(n, _p(rp), _p(ci), _p(va), _p(w), max_levels, max_coarse,
-                                 sweeps, coarse_sweeps, CYCLES[cycle], kcycle_levels, C.byref(st))
+                                 sweeps, coarse_sweeps, CYCLES[cycle], kcycle_levels, float(min_ratio),
+                                 C.byref(st))
         if not self.h:
             raise ValueError(f"oracle setup rejected the input (status {st.value})")
         self.n = n

@@ -165,11 +165,15 @@ int lanes_for(int group, const Csr &A) {
 
 bool valid_group(int g) { return g == 0 || g == -1 || g == 4 || g == 8 || g == 16 || g == 32 || g == 64; }
 
+// With flags_dev given, the validation flags are left there for the caller
+// to read with its next read-back (only for matrices already known to be well
+// formed: the validated input and the coarse matrices built from it; a bad
+// value there makes weights ineligible, never an out-of-bounds access).
 int match_sweep(hipStream_t s, Arena &tmp, const Csr &A, const double *w, int check_sym, int group, int **mate_out,
-                int **leader_out, double **c_out) {
+                int **leader_out, double **c_out, int *flags_dev = nullptr) {
     const int m = A.n, G = lanes_for(group, A);
     double *diag = tmp.get_n<double>(m);
-    int *flags = tmp.get_n<int>(16);
+    int *flags = flags_dev ? flags_dev : tmp.get_n<int>(16);
     double *c = tmp.get_n<double>(A.nnz);
     unsigned long long *cand = tmp.get_n<unsigned long long>(A.nnz);
     unsigned long long *ws = tmp.get_n<unsigned long long>(m);
@@ -179,12 +183,14 @@ int match_sweep(hipStream_t s, Arena &tmp, const Csr &A, const double *w, int ch
     NOMEM(diag && flags && c && cand && ws && pos && mate && leader);
     launch_fill_i32(s, 1, flags, 0);
     launch_validate(s, G, m, A.nnz, A.rp, A.ci, A.v, w, check_sym, diag, flags);
-    int f = 0;
-    int rc = read_back(s, flags, sizeof(int), &f);
-    if (rc) return rc;
-    if (f) {
-        set_error("invalid input:" + flag_text(f));
-        return BCM_EINVAL;
+    if (!flags_dev) {
+        int f = 0;
+        int rc = read_back(s, flags, sizeof(int), &f);
+        if (rc) return rc;
+        if (f) {
+            set_error("invalid input:" + flag_text(f));
+            return BCM_EINVAL;
+        }
     }
     launch_weights(s, G, m, A.rp, A.ci, A.v, diag, w, c);
     launch_candidates(s, G, m, A.rp, A.ci, c, cand, pos);
@@ -209,16 +215,22 @@ int pairwise_sweep(hipStream_t s, Arena &tmp, Arena &keep, const Csr &A, const d
     Arena &op = finP ? *finP : keep;
     const int m = A.n, G = lanes_for(group, A);
     int *mate = nullptr, *leader = nullptr;
-    int rc = match_sweep(s, tmp, A, w, 0, group, &mate, &leader, nullptr);
+    int *ctl = tmp.get_n<int>(32);  // [0] validation flags, [16] number of aggregates
+    NOMEM(ctl);
+    int rc = match_sweep(s, tmp, A, w, 0, group, &mate, &leader, nullptr, ctl);
     if (rc) return rc;
     int *ofs = leader;  // scanned in place
-    int *dtot = tmp.get_n<int>(16);
     void *stmp = tmp.get(scan_tmp_bytes(m));
-    NOMEM(dtot && stmp);
-    scan_exclusive(s, leader, ofs, m, dtot, stmp);
-    int nc = 0;
-    rc = read_back(s, dtot, sizeof(int), &nc);
+    NOMEM(stmp);
+    scan_exclusive(s, leader, ofs, m, ctl + 16, stmp);
+    int hc[17];
+    rc = read_back(s, ctl, sizeof(hc), hc);
     if (rc) return rc;
+    if (hc[0]) {
+        set_error("invalid coarse-level matrix:" + flag_text(hc[0]));
+        return BCM_EINVAL;
+    }
+    const int nc = hc[16];
     out.nc = nc;
     if (nc == m) return BCM_OK;
     out.agg = op.get_n<int>(m);
@@ -352,6 +364,7 @@ int build_hierarchy(bcm_handle *h, const bcm_csr *Ain, const double *win) {
         if (f) { set_error("invalid input:" + flag_text(f)); return BCM_EINVAL; }
     }
     const int max_coarse = P.max_coarse > 0 ? P.max_coarse : (int)std::lround(40.0 * std::cbrt((double)n));
+    const double rmin = P.min_ratio > 0.0 ? P.min_ratio : std::sqrt(std::ldexp(1.0, P.sweeps));
     int k = 0;
     for (;;) {
         Level &L = h->lv[k];
@@ -408,8 +421,10 @@ int build_hierarchy(bcm_handle *h, const bcm_csr *Ain, const double *win) {
             L.mem = persist_copy(h, cmem, (size_t)Acur.n * cstride);
         }
         NOMEM(C.A.rp && C.A.ci && C.A.v && C.w && L.agg && L.p && L.mem);
-        HIPCHK(hipStreamSynchronize(s));  // keep/tmp are rewound next
+        // keep/tmp are rewound next: their memory is reused by later work on the
+        // same stream, which runs after everything that reads it now
         ++k;
+        if ((double)nk < rmin * (double)C.A.n) break;  // coarsening has stalled: C is the coarsest
     }
     h->nl = k + 1;
     // smoother, FP32 copies, cycle vectors
@@ -456,9 +471,11 @@ int build_hierarchy(bcm_handle *h, const bcm_csr *Ain, const double *win) {
         std::vector<int> lv_sell;
         for (int l = 0; l < h->nl && P.sell; ++l)
             if (l == 0 || h->lv[l].xp) lv_sell.push_back(l);
-        std::vector<int *> cnts(lv_sell.size());
+        // per level t: tot[t] = total slots, tot[32 + t] = largest |col - row|
+        if (lv_sell.size() > 32) lv_sell.resize(32);  // deeper levels keep the CSR kernels
         int *tot = h->persist.get_n<int>(64);
         NOMEM(tot);
+        launch_fill_i32(s, 64, tot, 0);
         for (size_t t = 0; t < lv_sell.size(); ++t) {
             Level &L = h->lv[lv_sell[t]];
             const int ns = (L.A.n + kSlice - 1) / kSlice;
@@ -466,21 +483,22 @@ int build_hierarchy(bcm_handle *h, const bcm_csr *Ain, const double *win) {
             L.E.sp = h->persist.get_n<int>((size_t)ns + 1);
             void *stmp = keep.get(scan_tmp_bytes(ns));
             NOMEM(L.E.sp && stmp);
-            launch_sell_width(s, L.A.n, L.A.rp, L.E.sp);
+            launch_sell_width(s, L.A.n, L.A.rp, L.A.ci, L.E.sp, tot + 32 + t);
             scan_exclusive(s, L.E.sp, L.E.sp, ns, L.E.sp + ns, stmp);  // sp[ns] = total slots
             HIPCHK(hipMemcpyAsync(tot + t, L.E.sp + ns, sizeof(int), hipMemcpyDeviceToDevice, s));
         }
         int tots[64];
-        int rc = read_back(s, tot, sizeof(int) * lv_sell.size(), tots);
+        int rc = read_back(s, tot, sizeof(tots), tots);
         if (rc) return rc;
         for (size_t t = 0; t < lv_sell.size(); ++t) {
             Level &L = h->lv[lv_sell[t]];
             const size_t ne = (size_t)tots[t];
-            L.E.sc = h->persist.get_n<int>(ne);
+            if (tots[32 + t] <= 32767) L.E.sd = h->persist.get_n<short>(ne);
+            else L.E.sc = h->persist.get_n<int>(ne);
             L.E.sv = h->persist.get_n<double>(ne);
             if (fp32) L.E.sv32 = h->persist.get_n<float>(ne);
-            NOMEM(L.E.sc && L.E.sv && (!fp32 || L.E.sv32));
-            launch_sell_fill(s, L.A.n, L.A.rp, L.A.ci, L.A.v, L.E.sp, L.E.sc, L.E.sv, L.E.sv32);
+            NOMEM((L.E.sc || L.E.sd) && L.E.sv && (!fp32 || L.E.sv32));
+            launch_sell_fill(s, L.A.n, L.A.rp, L.A.ci, L.A.v, L.E.sp, L.E.sc, L.E.sd, L.E.sv, L.E.sv32);
         }
     }
     {
@@ -558,14 +576,19 @@ bool kcycle_at(const bcm_handle *h, int k) {
 // --------------------------------------------------------------- byte model
 // Algorithmic bytes (every array touched once; gathers assumed cached).
 // down leg: fused k_down_*, or residual + restriction on large levels (p r written and read once)
+// Bytes of one column index of the matrix a row-parallel kernel reads: int16
+// offsets on a sliced-ELL copy that has them, else int32.
+double index_bytes(const Level &L, bool sell_path) { return sell_path && L.E.sd ? 2.0 : 4.0; }
+
 double bytes_down(const bcm_handle *h, int k) {
     const Level &L = h->lv[k];
     const bool f32 = h->prm.precision == BCM_FP32_CYCLE;
     const double sv = f32 ? 4 : 8, sb = (k == 0 || !f32) ? 8 : 4;
     const double n = L.A.n, z = L.A.nnz, nc = L.nc;
-    const double base = 4 * (n + 1) + (4 + sv) * z + sb * n + 2 * sv * n + 4.0 * nc * L.mstride + sv * nc;
-    if (L.E.sp && L.xp && (L.mstride == 2 || L.mstride == 4)) return base + 2 * sv * n;
-    return base;
+    const bool sell = L.E.sp && L.xp && (L.mstride == 2 || L.mstride == 4);
+    const double base = 4 * (n + 1) + (index_bytes(L, sell) + sv) * z + sb * n + 2 * sv * n +
+                        4.0 * nc * L.mstride + sv * nc;
+    return sell ? base + 2 * sv * n : base;
 }
 // up leg: fused k_up, or k_prolong + k_smooth on large levels (xp written and read once)
 double bytes_up(const bcm_handle *h, int k) {
@@ -574,7 +597,8 @@ double bytes_up(const bcm_handle *h, int k) {
     const double sv = f32 ? 4 : 8, sb = (k == 0 || !f32) ? 8 : 4;
     const double n = L.A.n, z = L.A.nnz, nc = L.nc;
     if (L.xp && L.A.n >= kSplitUp)
-        return (sb * n + 2 * sv * n + 4 * n + sv * nc + sv * n) + (4 * (n + 1) + (4 + sv) * z + 2 * sv * n + 2 * sb * n);
+        return (sb * n + 2 * sv * n + 4 * n + sv * nc + sv * n) +
+               (4 * (n + 1) + (index_bytes(L, L.E.sp != nullptr) + sv) * z + 2 * sv * n + 2 * sb * n);
     return 4 * (n + 1) + (4 + sv) * z + 2 * sb * n + 2 * sv * n + 4 * n + sv * nc;
 }
 double bytes_coarse(const bcm_handle *h) {
@@ -604,8 +628,10 @@ double bytes_cycle(const bcm_handle *h) {
     return total + visits * bytes_coarse(h);
 }
 double bytes_spmv_dots(const bcm_handle *h) {
-    const double n = h->lv[0].A.n, z = h->lv[0].A.nnz;
-    return 4 * (n + 1) + 12 * z + 32 * n;  // algorithmic: CSR entries once (ELL padding not counted)
+    const Level &L = h->lv[0];
+    const double n = L.A.n, z = L.A.nnz;
+    // algorithmic: every stored entry once (ELL padding not counted)
+    return 4 * (n + 1) + (index_bytes(L, L.E.sp != nullptr) + 8) * z + 32 * n;
 }
 double bytes_update(const bcm_handle *h) { return 80.0 * h->lv[0].A.n; }
 
@@ -1020,6 +1046,7 @@ void bcm_default_params(bcm_params *p) {
     p->group = 0;
     p->sell = 1;
     p->adjoint_tol = 0.0;
+    p->min_ratio = 0.0;
 }
 
 const char *bcm_last_error(void) { return g_err.c_str(); }
@@ -1034,7 +1061,7 @@ int bcm_setup(const bcm_csr *A, const double *w, const bcm_params *p, bcm_handle
     if (p) prm = *p; else bcm_default_params(&prm);
     if (prm.max_levels < 1 || prm.sweeps < 1 || prm.sweeps > 4 || prm.coarse_sweeps < 1 || prm.itmax < 1 ||
         prm.pre != 1 || prm.post != 1 || prm.cycle < BCM_VCYCLE || prm.cycle > BCM_KCYCLE || prm.kcycle_levels < 0 ||
-        !valid_group(prm.group) ||
+        !valid_group(prm.group) || !(prm.min_ratio >= 0.0) ||
         (prm.precision != BCM_FP64 && prm.precision != BCM_FP32_CYCLE) || (prm.alloc == nullptr) != (prm.dealloc == nullptr)) {
         set_error("unsupported parameters (sweeps 1..4, pre = post = 1, V-, W- or K-cycle, kcycle_levels >= 0, "
                   "group 0, -1, 4, 8, 16, 32 or 64, FP64 or FP32 cycle)");

@@ -61,11 +61,13 @@ struct Csr {
 // slices of 64 (one wave), slice s holds width w_s = its longest row; entry k
 // of row 64 s + l sits at sp[s] + 64 k + l.  Rows keep their CSR column order
 // and are padded with (col = row, value = 0), so a row sum taken left to right
-// equals the CSR one.
+// equals the CSR one.  Columns are stored as int16 offsets col - row when every
+// offset of the level fits (sd), else as int32 columns (sc).
 constexpr int kSlice = 64;
 struct Sell {
     int nslices = 0;
     int *sp = nullptr, *sc = nullptr;
+    short *sd = nullptr;
     double *sv = nullptr;
     float *sv32 = nullptr;
 };
@@ -177,10 +179,12 @@ void launch_compose(hipStream_t s, int n, int nc_new, const int *agg_prev, const
 void launch_diag_l1(hipStream_t s, int G, int n, const int *rp, const double *v, double *dinv,
                     float *dinv32);
 void launch_cast(hipStream_t s, size_t n, const double *src, float *dst);
-// slice widths (64 * longest row of each slice) -> cnt[nslices]
-void launch_sell_width(hipStream_t s, int n, const int *rp, int *cnt);
+// slice widths (64 * longest row of each slice) -> cnt[nslices]; *maxoff is
+// raised to the largest |col - row| of the matrix (start it at 0)
+void launch_sell_width(hipStream_t s, int n, const int *rp, const int *ci, int *cnt, int *maxoff);
+// fills the slots: int32 columns into sc, or int16 offsets into sd (one is null)
 void launch_sell_fill(hipStream_t s, int n, const int *rp, const int *ci, const double *v, const int *sp, int *sc,
-                      double *sv, float *sv32);
+                      short *sd, double *sv, float *sv32);
 void launch_fill_i32(hipStream_t s, size_t n, int *dst, int val);
 void launch_fill_u64(hipStream_t s, size_t n, unsigned long long *dst, unsigned long long val);
 void launch_copy_f64(hipStream_t s, size_t n, const double *src, double *dst);
@@ -225,11 +229,6 @@ void launch_spmv_dots(hipStream_t s, const Level &L, int nb, int first, const do
 void launch_update(hipStream_t s, int n, int nb, int first, const double *w, const double *v,
                    double *d, double *u, double *q, double *r, double *partials, double *scal);
 void launch_finalize(hipStream_t s, int mode, int nb, int first, const double *partials, double *scal);
-// sliced-ELL variants of the row-parallel solve kernels (level must hold E)
-void launch_resid_sell(hipStream_t s, const Level &L, int nb, const double *b, const double *u, double *r,
-                       double *partials, double *scal);
-void launch_spmv_dots_sell(hipStream_t s, const Level &L, int nb, int first, const double *w, const double *r,
-                           const double *q, double *v, double *partials, double *scal);
 void launch_sampled_outer(hipStream_t s, const Level &L, const double *lam, const double *x,
                           double *G);
 int reduce_blocks(int n);

@@ -420,21 +420,30 @@ k_diag_l1(int n, const int *__restrict__ rp, const double *__restrict__ v, doubl
 }
 
 // Sliced ELL: width of slice s (times 64) = 64 * max row length over its rows.
-__global__ void __launch_bounds__(kBlock) k_sell_width(int n, const int *__restrict__ rp, int *__restrict__ cnt) {
+__global__ void __launch_bounds__(kBlock)
+k_sell_width(int n, const int *__restrict__ rp, const int *__restrict__ ci, int *__restrict__ cnt,
+             int *__restrict__ maxoff) {
     const int sl = blockIdx.x * kBlock + threadIdx.x;
     const int ns = (n + kSlice - 1) / kSlice;
     if (sl >= ns) return;
-    int w = 0;
+    int w = 0, off = 0;
     const int r1 = min(n, (sl + 1) * kSlice);
-    for (int i = sl * kSlice; i < r1; ++i) w = max(w, rp[i + 1] - rp[i]);
+    for (int i = sl * kSlice; i < r1; ++i) {
+        const int q0 = rp[i], q1 = rp[i + 1];
+        w = max(w, q1 - q0);
+        // columns are sorted: the extreme offsets are the first and the last
+        if (q1 > q0) off = max(off, max(abs(ci[q0] - i), abs(ci[q1 - 1] - i)));
+    }
     cnt[sl] = w * kSlice;
+    atomicMax(maxoff, off);
 }
 
 // One thread per row writes its entries in column-major slot order; padding
 // slots get (col = row, value = 0).
 __global__ void __launch_bounds__(kBlock)
 k_sell_fill(int n, const int *__restrict__ rp, const int *__restrict__ ci, const double *__restrict__ v,
-            const int *__restrict__ sp, int *__restrict__ sc, double *__restrict__ sv, float *__restrict__ sv32) {
+            const int *__restrict__ sp, int *__restrict__ sc, short *__restrict__ sd, double *__restrict__ sv,
+            float *__restrict__ sv32) {
     const int i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
     const int sl = i / kSlice, lane = i % kSlice;
@@ -444,7 +453,8 @@ k_sell_fill(int n, const int *__restrict__ rp, const int *__restrict__ ci, const
         const bool in = k < len;
         const int col = in ? ci[q0 + k] : i;
         const double val = in ? v[q0 + k] : 0.0;
-        sc[base + k * kSlice] = col;
+        if (sd) sd[base + k * kSlice] = (short)(col - i);
+        else sc[base + k * kSlice] = col;
         sv[base + k * kSlice] = val;
         if (sv32) sv32[base + k * kSlice] = (float)val;
     }
@@ -573,14 +583,14 @@ void launch_diag_l1(hipStream_t s, int G, int n, const int *rp, const double *v,
     });
 }
 
-void launch_sell_width(hipStream_t s, int n, const int *rp, int *cnt) {
+void launch_sell_width(hipStream_t s, int n, const int *rp, const int *ci, int *cnt, int *maxoff) {
     const int ns = (n + kSlice - 1) / kSlice;
-    hipLaunchKernelGGL(k_sell_width, dim3(blocks_for(ns)), dim3(kBlock), 0, s, n, rp, cnt);
+    hipLaunchKernelGGL(k_sell_width, dim3(blocks_for(ns)), dim3(kBlock), 0, s, n, rp, ci, cnt, maxoff);
 }
 
 void launch_sell_fill(hipStream_t s, int n, const int *rp, const int *ci, const double *v, const int *sp, int *sc,
-                      double *sv, float *sv32) {
-    hipLaunchKernelGGL(k_sell_fill, dim3(blocks_for(n)), dim3(kBlock), 0, s, n, rp, ci, v, sp, sc, sv, sv32);
+                      short *sd, double *sv, float *sv32) {
+    hipLaunchKernelGGL(k_sell_fill, dim3(blocks_for(n)), dim3(kBlock), 0, s, n, rp, ci, v, sp, sc, sd, sv, sv32);
 }
 
 void launch_cast(hipStream_t s, size_t n, const double *src, float *dst) {

@@ -218,6 +218,19 @@ def uniform_rhs(n: int, seed: int) -> np.ndarray:
     return np.random.default_rng(seed).uniform(-1.0, 1.0, n)
 
 
+def grid_sine_vector(nx: int, ny: int | None = None, nz: int | None = None) -> np.ndarray:
+    """sin(pi x) sin(pi y) sin(pi z) at the nodes (x = (i+1)/(nx+1), ...) of an
+    nx*ny*nz grid in lexicographic order (x fastest): the eigenvector of the
+    smallest eigenvalue of the 7-point Dirichlet Laplacian, a user-supplied
+    smooth vector for that operator."""
+    ny = nx if ny is None else ny
+    nz = nx if nz is None else nz
+    fx = np.sin(np.pi * np.arange(1, nx + 1) / (nx + 1))
+    fy = np.sin(np.pi * np.arange(1, ny + 1) / (ny + 1))
+    fz = np.sin(np.pi * np.arange(1, nz + 1) / (nz + 1))
+    return (fz[:, None, None] * fy[None, :, None] * fx[None, None, :]).ravel()
+
+
 def default_max_coarse(n: int) -> int:
     """The paper's coarsest-size bound maxcoarseset * n^(1/3) with maxcoarseset = 40,
     rounded to the nearest integer (Section 5, experimental settings)."""

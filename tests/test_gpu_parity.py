@@ -77,7 +77,8 @@ def test_matching_bitexact(B, ora, case):
         assert np.array_equal(mate.cpu().numpy(), mate_ref), "matching differs from greedy"
 
 
-HIER_CASES = [("G1", 1.0), ("G2", 0.3), ("G3", 0.2), ("G4", 0.21), ("G5", 0.2), ("G2", 1.0)]
+HIER_CASES = [("G1", 1.0), ("G2", 0.3), ("G3", 0.2), ("G4", 0.21), ("G5", 0.2), ("G2", 1.0), ("G5", 0.5),
+              ("G3", 0.5)]
 
 
 def _compare_hierarchy(h, ho):
@@ -144,7 +145,7 @@ def test_precond_fp32_cycle_error_bound(B, ora, name, scale):
     assert np.linalg.norm(z - zo) <= 1e-5 * np.linalg.norm(zo)
 
 
-SOLVE_CASES = [("G1", 1.0), ("G2", 0.3), ("G3", 0.2), ("G4", 0.21), ("G2", 1.0)]
+SOLVE_CASES = [("G1", 1.0), ("G2", 0.3), ("G3", 0.2), ("G4", 0.21), ("G2", 1.0), ("G5", 0.5)]
 
 
 @pytest.mark.parametrize("name,scale", SOLVE_CASES)
@@ -266,6 +267,26 @@ def test_lane_width_and_sell_settings(B, ora, name, scale, group, sell):
     _, io = ho.solve(c["b"], tol=c["tol"])
     A = sp.csr_matrix((c["val"], c["col"], c["rowptr"]), shape=(c["n"], c["n"]))
     assert np.linalg.norm(c["b"] - A @ x) <= c["tol"] * np.linalg.norm(c["b"])
+    assert abs(h.info()["iters"] - io["iters"]) <= 1
+
+
+def test_sell_int32_columns_for_long_range_couplings(B, ora):
+    # offsets |col - row| beyond int16: the sliced-ELL copies keep int32 columns
+    rp, ci, va = P.random_spd(70000, 4e-5, 23)
+    n = len(rp) - 1
+    assert np.abs(ci - np.repeat(np.arange(n), np.diff(rp))).max() > 32767
+    say(f"sliced ELL with int32 columns n={n}")
+    h = B.Hierarchy(rp, ci, va, max_coarse=200)
+    ho = ora.Hierarchy(rp, ci, va, np.ones(n), max_coarse=200)
+    _compare_hierarchy(h, ho)
+    r = P.uniform_rhs(n, 18)
+    z, zo = h.precond(r).cpu().numpy(), ho.vcycle(r)
+    assert np.linalg.norm(z - zo) <= 1e-12 * np.linalg.norm(zo)
+    b = P.uniform_rhs(n, 19)
+    x = h.solve(b, tol=1e-8).cpu().numpy()
+    _, io = ho.solve(b, tol=1e-8)
+    A = sp.csr_matrix((va, ci, rp), shape=(n, n))
+    assert np.linalg.norm(b - A @ x) <= 1e-8 * np.linalg.norm(b)
     assert abs(h.info()["iters"] - io["iters"]) <= 1
 
 

@@ -367,3 +367,31 @@ def test_setup_rejects_invalid_input(ora):
     bad[3] = np.nan
     with pytest.raises(ValueError):
         ora.Hierarchy(rp, ci, bad, np.ones(6))
+
+
+def test_stalled_coarsening_ends_the_hierarchy(ora):
+    # heterogeneous diffusion: the matching stops halving the size per level a
+    # few levels down; the first level formed with a ratio below
+    # sqrt(2^sweeps) = 2 is the coarsest.  min_ratio = 1 keeps coarsening until
+    # the size is unchanged or the level limit is hit.
+    c = P.config("G5", 0.5)
+    h = ora.Hierarchy(c["rowptr"], c["col"], c["val"], c["w"], max_coarse=c["max_coarse"])
+    s = h.sizes()
+    r = [a / b for a, b in zip(s[:-1], s[1:])]
+    assert all(x >= 2.0 for x in r[:-1]) and r[-1] < 2.0
+    assert s[-1] > c["max_coarse"]
+    h1 = ora.Hierarchy(c["rowptr"], c["col"], c["val"], c["w"], max_coarse=c["max_coarse"], min_ratio=1.0)
+    s1 = h1.sizes()
+    assert s1[:len(s)] == s and len(s1) > len(s) + 5
+    _, i = h.solve(c["b"], tol=1e-8)
+    _, i1 = h1.solve(c["b"], tol=1e-8)
+    assert i["status"] == 0 and i["iters"] < i1["iters"]
+
+
+def test_ratio_rule_leaves_regular_grids_alone(ora):
+    for name, scale in [("G1", 1.0), ("G2", 0.5)]:
+        c = P.config(name, scale)
+        h = ora.Hierarchy(c["rowptr"], c["col"], c["val"], c["w"], max_coarse=c["max_coarse"])
+        h1 = ora.Hierarchy(c["rowptr"], c["col"], c["val"], c["w"], max_coarse=c["max_coarse"], min_ratio=1.0)
+        assert h.sizes() == h1.sizes()
+        assert h.sizes()[-1] <= c["max_coarse"]
