@@ -10,8 +10,10 @@ plain float64 path is timed the same way and reported beside it.
 value = n / (mean seconds per step) / 1e6  [Mdof/s]
 
 roofline: the kernel class with the largest share of solve time, timed with
-HIP events on the library's stream during the timed steps; achieved GB/s =
-its algorithmic bytes / its event time.
+HIP events on the library's stream during a third timed leg (the FP32 form
+with eager launches, so that the event pair brackets exactly that kernel);
+achieved GB/s = its algorithmic bytes / its event time.  The two headline
+legs run without events.
 cpu_baseline: the serial oracle (one thread) running one full setup + solve of
 the same workload.
 """
@@ -29,8 +31,11 @@ METRIC = "setup+solve s to rel-res 1e-8 (Mdof/s, HBM %), FP32-cycle vs FP64 AMG-
 HBM_PEAK_GBS = 8000.0
 CLASSES = ["down0", "up0", "spmv_dots", "update", "coarse", "mid"]
 SINGLE_KERNEL = ["down0", "up0", "spmv_dots", "update", "coarse"]  # one launch per iteration
-KERNEL_OF_CLASS = {"down0": "k_down_seq (finest level)", "up0": "k_up (finest level)",
-                   "spmv_dots": "k_spmv_dots", "update": "k_update", "coarse": "k_coarse_dense"}
+KERNEL_OF_CLASS = {"down0": "k_down_res_sell + k_restrict (finest level, down leg)",
+                   "up0": "k_prolong + k_smooth_sell (finest level, up leg)",
+                   "spmv_dots": "k_spmv_dots_sell (v = A w and three dot products, finest level, FP64)",
+                   "update": "k_update (four vector updates and ||r||^2)",
+                   "coarse": "coarsest-level solve (k_tail, k_coarse_dense or k_coarse)"}
 
 
 def log(msg):
@@ -108,15 +113,21 @@ def main():
     dom = max(SINGLE_KERNEL, key=share.get)
     log(f"event share of solve kernels (fp32 cycle, ms): {share}; dominant {dom}")
 
+    # timed legs: FP32 cycle (the headline) and FP64, no profiling; then a third
+    # timed leg of the FP32 form with the dominant kernel bracketed by HIP
+    # events on the library's stream, for the roofline (all legs launch every
+    # kernel eagerly: faster here than replaying the iteration from a graph)
     results = {}
-    for prec in ("fp32", "fp64"):
-        mask = bcm.PROF[dom] if prec == "fp32" else 0
+    for leg in ("fp32", "fp64", "roofline"):
+        prec = "fp64" if leg == "fp64" else "fp32"
+        mask = bcm.PROF[dom] if leg == "roofline" else 0
+        kw = dict(graph=False) if leg == "roofline" else {}
         tot_l, tot_ms, tot_b = 0, 0.0, 0.0
         infos = []
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(args.steps):
-            info, prof = step(prec, mask)
+            info, prof = step(prec, mask, **kw)
             infos.append(info)
             if dom in prof:
                 l_, ms, by = prof[dom]
@@ -124,6 +135,7 @@ def main():
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         ms_step = (t1 - t0) * 1e3 / args.steps
+        prec = leg
         inf = infos[-1]
         results[prec] = dict(ms_per_step=ms_step, mdofs=n / (ms_step * 1e-3) / 1e6, iters=inf["iters"],
                              relres=inf["relres"], t_setup_ms=float(np.mean([i["t_setup_ms"] for i in infos])),
@@ -136,7 +148,7 @@ def main():
             f"{r['mdofs']:.1f} Mdof/s, iters {r['iters']}, relres {r['relres']:.2e}, levels {r['levels']}")
 
     f32 = results["fp32"]
-    l_, ms, by = f32["prof"]
+    l_, ms, by = results["roofline"]["prof"]
     achieved = (by / l_) / ((ms / l_) * 1e-3) / 1e9 if l_ else None
     traffic = None
     tpath = os.path.join(ROOT, "profiles", "traffic.json")
@@ -149,7 +161,9 @@ def main():
                 "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": traffic,
                 "algorithmic_bytes_per_launch": (by / l_) if l_ else None,
-                "avg_launch_us": (ms / l_ * 1e3) if l_ else None, "launches": l_}
+                "avg_launch_us": (ms / l_ * 1e3) if l_ else None, "launches": l_,
+                "timed_leg": "FP32 cycle, eager launches, HIP events around the kernel",
+                "timed_leg_ms_per_step": results["roofline"]["ms_per_step"]}
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -202,6 +216,9 @@ ABLATIONS = {
     # pairwise sweeps composed per level (aggregates of up to 2^sweeps rows)
     "coarsening": [(f"{sw} sweep{'s' if sw > 1 else ''} per level {pr}", pr, dict(sweeps=sw))
                    for pr in ("fp64", "fp32") for sw in (1, 2, 3, 4)],
+    # one flexible-CG iteration replayed from a HIP graph, or every kernel launched
+    "graph": [(f"{cy} {pr} {'graph replay' if g else 'eager launches'}", pr, dict(cycle=cy, graph=g))
+              for cy in ("V", "W") for pr in ("fp64", "fp32") for g in (True, False)],
     # the smooth vector w the matching weights and prolongator are built from
     "smoothvec": [(f"w = {wk} {pr}", pr, dict(wvec=wk)) for pr in ("fp64", "fp32")
                   for wk in ("ones", "uniform[0.5,1.5)", "grid sine (lowest Laplacian mode)")],

@@ -97,9 +97,10 @@ typedef struct {
  *   profile              bit mask of kernel classes (BCM_PROF_*) whose
  *                        launches are bracketed by HIP events during
  *                        bcm_solve; read back with bcm_profile().
- *   graph          1     replay one flexible-CG iteration (cycle, SpMV, updates)
- *                        from a HIP graph captured on the handle's first solve;
- *                        0 = launch every kernel.  A profile mask of exactly one
+ *   graph          0     1 = replay one flexible-CG iteration (cycle, SpMV,
+ *                        updates) from a HIP graph captured on the handle's
+ *                        first solve; 0 = launch every kernel (measured faster
+ *                        on MI355X for this iteration).  A profile mask of exactly one
  *                        of the classes down0, up0, spmv_dots, update, coarse is
  *                        timed inside the graph; other masks launch eagerly.
  *   group          0     lanes per matrix row in the CSR row kernels (the

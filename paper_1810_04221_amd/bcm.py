@@ -123,7 +123,7 @@ class _TorchAllocator:
 
 def make_params(precision="fp64", max_levels=40, max_coarse=0, sweeps=2, coarse_sweeps=20, itmax=5000,
                 check=True, adjoint_tol=0.0, profile=0, stream=None, allocator=None, cycle="V",
-                graph=True, kcycle_levels=0, group=0, sell=True, min_ratio=0.0) -> BcmParams:
+                graph=False, kcycle_levels=0, group=0, sell=True, min_ratio=0.0) -> BcmParams:
     p = BcmParams()
     load_library().bcm_default_params(C.byref(p))
     p.cycle = CYCLES[cycle]
@@ -147,7 +147,7 @@ class Hierarchy:
 
     def __init__(self, rowptr, col, val, w=None, *, precision="fp64", max_levels=40, max_coarse=0, sweeps=2,
                  coarse_sweeps=20, itmax=5000, check=True, adjoint_tol=0.0, profile=0, device=None, cycle="V",
-                 graph=True, kcycle_levels=0, group=0, sell=True, min_ratio=0.0):
+                 graph=False, kcycle_levels=0, group=0, sell=True, min_ratio=0.0):
         L = _gpu_lib()
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         self.stream = torch.cuda.current_stream(self.device).cuda_stream

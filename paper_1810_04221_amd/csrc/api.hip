@@ -7,6 +7,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <functional>
 #include <string>
 
 #include "internal.h"
@@ -170,8 +171,8 @@ bool valid_group(int g) { return g == 0 || g == -1 || g == 4 || g == 8 || g == 1
 // formed: the validated input and the coarse matrices built from it; a bad
 // value there makes weights ineligible, never an out-of-bounds access).
 int match_sweep(hipStream_t s, Arena &tmp, const Csr &A, const double *w, int check_sym, int group, int **mate_out,
-                int **leader_out, double **c_out, int *flags_dev = nullptr) {
-    const int m = A.n, G = lanes_for(group, A);
+                int **leader_out, double **c_out, int *flags_dev = nullptr, int G_hint = 0) {
+    const int m = A.n, G = G_hint > 0 ? G_hint : lanes_for(group, A);
     double *diag = tmp.get_n<double>(m);
     int *flags = flags_dev ? flags_dev : tmp.get_n<int>(16);
     double *c = tmp.get_n<double>(A.nnz);
@@ -182,7 +183,7 @@ int match_sweep(hipStream_t s, Arena &tmp, const Csr &A, const double *w, int ch
     int *leader = tmp.get_n<int>(m);
     NOMEM(diag && flags && c && cand && ws && pos && mate && leader);
     launch_fill_i32(s, 1, flags, 0);
-    launch_validate(s, G, m, A.nnz, A.rp, A.ci, A.v, w, check_sym, diag, flags);
+    launch_validate(s, G, m, A.nnz_dev ? -1 : A.nnz, A.rp, A.ci, A.v, w, check_sym, diag, flags);
     if (!flags_dev) {
         int f = 0;
         int rc = read_back(s, flags, sizeof(int), &f);
@@ -209,28 +210,35 @@ int match_sweep(hipStream_t s, Arena &tmp, const Csr &A, const double *w, int ch
 // matrix and w come from finA and the prolongator from finP when those are
 // given (the level's final outputs, allocated where they stay).  out.nc == A.n
 // means that no pair was formed (nothing else is produced then).
-int pairwise_sweep(hipStream_t s, Arena &tmp, Arena &keep, const Csr &A, const double *w, int group, SweepOut &out,
-                   Arena *finA, Arena *finP) {
+int pairwise_sweep(hipStream_t s, Arena &tmp, Arena &keep, Csr &A, const double *w, int group, int G_hint,
+                   SweepOut &out, Arena *finA, Arena *finP) {
+    // A's exact entry count, when still on the device, comes back with this
+    // sweep's first read-back (G_hint sizes the lanes of the kernels before it)
     Arena &oa = finA ? *finA : keep;
     Arena &op = finP ? *finP : keep;
-    const int m = A.n, G = lanes_for(group, A);
+    const int m = A.n;
     int *mate = nullptr, *leader = nullptr;
-    int *ctl = tmp.get_n<int>(32);  // [0] validation flags, [16] number of aggregates
+    int *ctl = tmp.get_n<int>(32);  // [0] validation flags, [16] aggregates, [17] A's entries
     NOMEM(ctl);
-    int rc = match_sweep(s, tmp, A, w, 0, group, &mate, &leader, nullptr, ctl);
+    int rc = match_sweep(s, tmp, A, w, 0, group, &mate, &leader, nullptr, ctl, A.nnz_dev ? G_hint : 0);
     if (rc) return rc;
     int *ofs = leader;  // scanned in place
     void *stmp = tmp.get(scan_tmp_bytes(m));
     NOMEM(stmp);
     scan_exclusive(s, leader, ofs, m, ctl + 16, stmp);
-    int hc[17];
+    if (A.nnz_dev) HIPCHK(hipMemcpyAsync(ctl + 17, A.nnz_dev, sizeof(int), hipMemcpyDeviceToDevice, s));
+    int hc[18];
     rc = read_back(s, ctl, sizeof(hc), hc);
     if (rc) return rc;
     if (hc[0]) {
         set_error("invalid coarse-level matrix:" + flag_text(hc[0]));
         return BCM_EINVAL;
     }
-    const int nc = hc[16];
+    if (A.nnz_dev) {
+        A.nnz = hc[17];
+        A.nnz_dev = nullptr;
+    }
+    const int nc = hc[16], G = lanes_for(group, A);
     out.nc = nc;
     if (nc == m) return BCM_OK;
     out.agg = op.get_n<int>(m);
@@ -239,7 +247,10 @@ int pairwise_sweep(hipStream_t s, Arena &tmp, Arena &keep, const Csr &A, const d
     out.mem2 = op.get_n<int>(2 * (size_t)nc);
     NOMEM(out.agg && out.p && out.wc && out.mem2);
     launch_aggfill(s, m, mate, ofs, w, out.agg, out.p, out.wc, out.mem2);
-    // Galerkin product: count, scan to row pointers, fill
+    // Galerkin product: count, scan to row pointers, fill.  Every coarse entry
+    // (E, F) comes from at least one stored a_ij (i in E, j in F), so A's entry
+    // count bounds the coarse one; the exact count stays on the device
+    // (row_ptr[nc]) until the next read-back.
     int *crp = oa.get_n<int>((size_t)nc + 1);
     int *gF = tmp.get_n<int>(A.nnz);
     int *gU = tmp.get_n<int>(A.nnz);
@@ -247,14 +258,12 @@ int pairwise_sweep(hipStream_t s, Arena &tmp, Arena &keep, const Csr &A, const d
     NOMEM(crp && gF && gU && stmp2);
     launch_gal_count(s, G, nc, A.rp, A.ci, out.agg, out.mem2, crp, gF, gU);
     scan_exclusive(s, crp, crp, nc, crp + nc, stmp2);
-    int cnnz = 0;
-    rc = read_back(s, crp + nc, sizeof(int), &cnnz);
-    if (rc) return rc;
     out.Ac.n = nc;
-    out.Ac.nnz = cnnz;
+    out.Ac.nnz = A.nnz;
+    out.Ac.nnz_dev = crp + nc;
     out.Ac.rp = crp;
-    out.Ac.ci = oa.get_n<int>(cnnz);
-    out.Ac.v = oa.get_n<double>(cnnz);
+    out.Ac.ci = oa.get_n<int>(A.nnz);
+    out.Ac.v = oa.get_n<double>(A.nnz);
     NOMEM(out.Ac.ci && out.Ac.v);
     launch_gal_fill(s, G, nc, A.rp, A.ci, A.v, out.agg, out.p, out.mem2, crp, out.Ac.ci, out.Ac.v, gF, gU);
     HIPCHK(hipGetLastError());
@@ -366,6 +375,7 @@ int build_hierarchy(bcm_handle *h, const bcm_csr *Ain, const double *win) {
     const int max_coarse = P.max_coarse > 0 ? P.max_coarse : (int)std::lround(40.0 * std::cbrt((double)n));
     const double rmin = P.min_ratio > 0.0 ? P.min_ratio : std::sqrt(std::ldexp(1.0, P.sweeps));
     int k = 0;
+    int g_prev = lanes_for(P.group, L0.A);
     for (;;) {
         Level &L = h->lv[k];
         const int nk = L.A.n;
@@ -373,6 +383,7 @@ int build_hierarchy(bcm_handle *h, const bcm_csr *Ain, const double *win) {
         keep.rewind();
         Csr Acur = L.A;
         const double *wcur = L.w;
+        int g_hint = g_prev;
         bool have = false;
         int *cagg = nullptr, *cmem = nullptr;
         double *cp = nullptr;
@@ -382,9 +393,14 @@ int build_hierarchy(bcm_handle *h, const bcm_csr *Ain, const double *win) {
             tmp.rewind();
             SweepOut so;
             const bool last = sw == P.sweeps - 1;
-            int rc = pairwise_sweep(s, tmp, keep, Acur, wcur, P.group, so, last ? &h->persist : nullptr,
+            int rc = pairwise_sweep(s, tmp, keep, Acur, wcur, P.group, g_hint, so, last ? &h->persist : nullptr,
                                     last && !have ? &h->persist : nullptr);
             if (rc) return rc;
+            if (sw == 0 && L.A.nnz_dev) {  // the level's own entry count is known now
+                L.A.nnz = Acur.nnz;
+                L.A.nnz_dev = nullptr;
+            }
+            g_hint = g_prev = lanes_for(P.group, Acur);
             if (so.nc == Acur.n) break;  // no pair formed: further sweeps would not either
             if (!have) {
                 cagg = so.agg; cp = so.p; cmem = so.mem2; cstride = 2;
@@ -410,6 +426,7 @@ int build_hierarchy(bcm_handle *h, const bcm_csr *Ain, const double *win) {
         L.mstride = cstride;
         if (final_done) {
             C.A.rp = Acur.rp; C.A.ci = Acur.ci; C.A.v = Acur.v; C.w = const_cast<double *>(wcur);
+            C.A.nnz_dev = Acur.nnz_dev;
             L.agg = cagg; L.p = cp; L.mem = cmem;
         } else {  // a later sweep formed no pair: the outputs are still in level scratch
             C.A.rp = persist_copy(h, Acur.rp, (size_t)Acur.n + 1);
@@ -427,6 +444,14 @@ int build_hierarchy(bcm_handle *h, const bcm_csr *Ain, const double *win) {
         if ((double)nk < rmin * (double)C.A.n) break;  // coarsening has stalled: C is the coarsest
     }
     h->nl = k + 1;
+    {
+        Csr &Ac = h->lv[h->nl - 1].A;  // the coarsest level ran no sweep: its entry count is still pending
+        if (Ac.nnz_dev) {
+            int rc = read_back(s, Ac.nnz_dev, sizeof(int), &Ac.nnz);
+            if (rc) return rc;
+            Ac.nnz_dev = nullptr;
+        }
+    }
     // smoother, FP32 copies, cycle vectors
     for (int l = 0; l < h->nl; ++l) {
         Level &L = h->lv[l];
@@ -515,7 +540,9 @@ int build_hierarchy(bcm_handle *h, const bcm_csr *Ain, const double *win) {
         int kt = h->nl - 1;
         while (kt > 1 && h->lv[kt - 1].A.n <= kTailRows) --kt;
         const Level &C = h->lv[h->nl - 1];
-        if (P.cycle == BCM_VCYCLE && kt < h->nl - 1 && C.A.n <= kTailRows) {
+        // K levels need dot products between cycles: the tail takes V and W levels only
+        const bool plain = P.cycle != BCM_KCYCLE || (P.kcycle_levels > 0 && P.kcycle_levels <= kt);
+        if (plain && kt < h->nl - 1 && C.A.n <= kTailRows) {
             std::vector<TailLevel> tv(h->nl);
             for (int l = 0; l < h->nl; ++l) {
                 const Level &L = h->lv[l];
@@ -525,17 +552,39 @@ int build_hierarchy(bcm_handle *h, const bcm_csr *Ain, const double *win) {
                 t.a = fp32 ? (const void *)L.A.v32 : (const void *)L.A.v;
                 t.dinv = fp32 ? (const void *)L.dinv32 : (const void *)L.dinv;
                 t.p = fp32 ? (const void *)L.p32 : (const void *)L.p;
-                t.b = L.b; t.x = L.x;
+                t.b = L.b; t.x = L.x; t.xs = L.xs;
                 tv[l] = t;
             }
+            // the tail's program: the cycle of level kt (Algorithm 1; W-cycle: the
+            // coarse problem of every level solved by two cycles, the second on the
+            // coarse residual and written to the save buffer, then added)
+            std::vector<int> ops;
+            const int nl_ = h->nl;
+            const bool w = P.cycle == BCM_WCYCLE;
+            auto op = [&](int o, int k, int sel) { ops.push_back(o | (k << 8) | (sel << 16)); };
+            std::function<void(int, int)> cyc = [&](int k, int sel) {
+                if (k == nl_ - 1) { op(kTailCoarse, k, sel); return; }
+                op(kTailDown, k, 0);
+                cyc(k + 1, 0);
+                if (w) {
+                    op(kTailResid, k + 1, 0);
+                    cyc(k + 1, 1);
+                    op(kTailAdd, k + 1, 0);
+                }
+                op(kTailUp, k, sel);
+            };
+            cyc(kt, 0);
             h->tail = h->persist.get_n<TailLevel>(h->nl);
-            NOMEM(h->tail);
+            h->tail_ops = h->persist.get_n<int>(ops.size());
+            NOMEM(h->tail && h->tail_ops);
             HIPCHK(hipMemcpyAsync(h->tail, tv.data(), sizeof(TailLevel) * h->nl, hipMemcpyHostToDevice, s));
+            HIPCHK(hipMemcpyAsync(h->tail_ops, ops.data(), sizeof(int) * ops.size(), hipMemcpyHostToDevice, s));
             HIPCHK(hipStreamSynchronize(s));
+            h->n_tail_ops = (int)ops.size();
             h->kt = kt;
         }
     }
-    if (h->lv[h->nl - 1].A.n > kCoarseLds) {
+    if (!h->lv[h->nl - 1].S && !coarse_in_lds(h->lv[h->nl - 1].A.n, h->lv[h->nl - 1].A.nnz)) {
         h->ctmp[0] = h->persist.get_n<double>(h->lv[h->nl - 1].A.n);
         h->ctmp[1] = h->persist.get_n<double>(h->lv[h->nl - 1].A.n);
         NOMEM(h->ctmp[0] && h->ctmp[1]);
@@ -770,6 +819,13 @@ void cycle_level(bcm_handle *h, Prof &pf, int k, const double *done, int iter) {
     hipStream_t s = h->s;
     const int fp32 = h->prm.precision == BCM_FP32_CYCLE;
     Level &L = h->lv[k];
+    if (k == h->kt) {  // this level and every coarser one in one workgroup
+        int e = pf.begin(5);
+        launch_tail(s, fp32, k, h->nl, h->tail, h->lv[h->nl - 1], h->prm.coarse_sweeps, h->tail_ops, h->n_tail_ops,
+                    L.x, done);
+        pf.end(5, e, 0.0, iter);
+        return;
+    }
     if (k == h->nl - 1) {
         int e = pf.begin(5);
         launch_coarse(s, L, h->prm.coarse_sweeps, L.b, L.x, !fp32, !fp32, h->ctmp[0], h->ctmp[1], done);
@@ -820,7 +876,7 @@ void vcycle(bcm_handle *h, Prof &pf, const double *rin, double *wout, const doub
     {
         int e = pf.begin(4);
         if (h->kt > 0) {
-            launch_tail(s, fp32, kt, nl, h->tail, C, cs, done);
+            launch_tail(s, fp32, kt, nl, h->tail, C, cs, h->tail_ops, h->n_tail_ops, h->lv[kt].x, done);
         } else {
             launch_coarse(s, C, cs, C.b, C.x, !fp32, !fp32, h->ctmp[0], h->ctmp[1], done);
         }
@@ -1042,7 +1098,7 @@ void bcm_default_params(bcm_params *p) {
     p->itmax = 5000;
     p->check = 1;
     p->profile = 0;
-    p->graph = 1;
+    p->graph = 0;
     p->group = 0;
     p->sell = 1;
     p->adjoint_tol = 0.0;

@@ -55,6 +55,9 @@ struct Csr {
     int *rp = nullptr, *ci = nullptr;
     double *v = nullptr;
     float *v32 = nullptr;
+    // set while the exact entry count is still on the device only (setup): nnz
+    // then holds an upper bound, the capacity of ci and v
+    const int *nnz_dev = nullptr;
 };
 
 // Sliced ELL copy of a CSR matrix for the row-parallel solve kernels: rows in
@@ -102,9 +105,12 @@ struct TailLevel {
     int n, nc, mstride, pad;
     const int *rp, *ci, *agg, *mem;
     const void *a, *dinv, *p;
-    void *b, *x;
+    void *b, *x, *xs;
 };
 constexpr int kTailRows = 512;  // levels up to this size run inside the tail kernel
+// Operations of the tail kernel's program, one int each: op | level << 8 | sel << 16
+// (sel = 1: UP / COARSE write the level's save buffer xs instead of x).
+enum : int { kTailDown = 1, kTailUp = 2, kTailCoarse = 3, kTailResid = 4, kTailAdd = 5 };
 constexpr int kKPartBlocks = 1024;  // K-cycle dot products: at most this many block partials
 
 struct ProfClass {
@@ -136,6 +142,8 @@ struct bcm_handle {
     double *ctmp[2] = {nullptr, nullptr};  // coarsest-level sweep buffers when n > kCoarseLds
     bcm::TailLevel *tail = nullptr;        // device table of levels for the tail kernel
     int kt = -1;                           // first level handled by the tail kernel (-1: none)
+    int *tail_ops = nullptr;               // the tail kernel's program (device)
+    int n_tail_ops = 0;
     double *partials = nullptr;
     double *kpart = nullptr;  // K-cycle block partials (3 * kKPartBlocks)
     double *ks = nullptr;     // K-cycle scalars, 8 per level
@@ -204,6 +212,9 @@ void launch_up(hipStream_t s, const Level &L, int fp32, const void *b, const voi
                int b_is_f64, int x_is_f64, const double *done);
 void launch_coarse(hipStream_t s, const Level &L, int sweeps, const void *b, void *x, int b_f64,
                    int x_f64, void *tmp_a, void *tmp_b, const double *done);
+// true when the coarsest level (without a dense operator) runs in one workgroup
+// with everything in LDS; otherwise launch_coarse needs two n-vectors tmp_a/b
+bool coarse_in_lds(int n, int nnz);
 // Each of these is a streaming kernel writing block partials; launch_finalize
 // (mode 0 after resid, 1 after spmv_dots, 2 after update) then sums them in
 // block order into scal[].
@@ -217,9 +228,10 @@ void launch_kcycle_step1(hipStream_t s, const Level &C, int fp32, const void *c1
                          double *partials, double *ks, const double *done);
 void launch_kcycle_step2(hipStream_t s, const Level &C, int fp32, const void *c2, const void *b, const void *v1,
                          void *x, double *partials, double *ks, const double *done);
-// levels kt .. nl-1 (tail table tl, coarsest level C) in one workgroup
+// the cycle of levels kt .. nl-1 in one workgroup: runs the nops operations of
+// ops (from b of level kt into x_out); tail table tl, coarsest level C
 void launch_tail(hipStream_t s, int fp32, int kt, int nl, const TailLevel *tl, const Level &C, int sweeps,
-                 const double *done);
+                 const int *ops, int nops, void *x_out, const double *done);
 // S = sum_{t < sweeps} (I - D A)^t D of the coarsest level, column by column
 void launch_coarse_build(hipStream_t s, const Level &L, int sweeps, double *S);
 void launch_resid(hipStream_t s, const Level &L, int nb, const double *b, const double *u, double *r,

@@ -45,7 +45,8 @@ k_validate(int n, int nnz, const int *__restrict__ rp, const int *__restrict__ c
     if (row >= n) return;
     const int s = rp[row], e = rp[row + 1];
     int f = 0;
-    if (s < 0 || e < s || e > nnz || (row == 0 && s != 0) || (row == n - 1 && e != nnz)) {
+    // nnz < 0: a matrix built here whose entry count is not known on the host
+    if (s < 0 || e < s || (nnz >= 0 && (e > nnz || (row == n - 1 && e != nnz))) || (row == 0 && s != 0)) {
         if (lane == 0) atomicOr(flags, kErrRowPtr);
         return;
     }
@@ -61,7 +62,7 @@ k_validate(int n, int nnz, const int *__restrict__ rp, const int *__restrict__ c
         if (check_sym && j != row) {
             const int s2 = rp[j], e2 = rp[j + 1];
             int found = -1;
-            if (s2 >= 0 && e2 >= s2 && e2 <= nnz) {
+            if (s2 >= 0 && e2 >= s2 && (nnz < 0 || e2 <= nnz)) {
                 int lo = s2, hi = e2 - 1;
                 while (lo <= hi) {
                     const int mid = (lo + hi) >> 1;
@@ -155,42 +156,35 @@ k_candidates(int n, const int *__restrict__ rp, const int *__restrict__ ci, cons
 // ----------------------------------------------------------------------------
 // Suitor matching (Section 3.1).  One thread per vertex holds that vertex's
 // proposal.  Vertex u walks its candidate list from its resume position and
-// proposes to the first v whose current suitor ranks below u; ws[v] holds the
-// key (rk << 32 | proposer + 1) of v's best proposal so far and is raised with
-// atomicMax.  A displaced proposer is taken over by the displacing thread and
-// resumes after the candidate it lost: ws[] only grows, so every candidate it
-// passed stays unavailable.  A stale resume position only rescans.  Every
-// successful atomicMax strictly raises one ws[] entry and a failed one means
-// another thread raised it, so the total number of loop trips is bounded and
-// every thread exits.  The final suitor pairs are mutual and equal the greedy
-// matching under (c desc, larger endpoint desc, smaller desc).
+// proposes to each candidate v in turn until one accepts; ws[v] holds the key
+// (rk << 32 | proposer + 1) of v's best proposal so far and is raised with
+// atomicMax, whose old value says whether u won.  A displaced proposer is
+// taken over by the displacing thread and resumes after the candidate it lost:
+// ws[] only grows, so every candidate it passed stays unavailable.  A stale
+// resume position only rescans.  Every successful atomicMax strictly raises
+// one ws[] entry (finitely many times) and a failed one moves u to its next
+// candidate, so the total number of loop trips is bounded and every thread
+// exits.  The final suitor pairs are mutual and equal the greedy matching
+// under (c desc, larger endpoint desc, smaller desc).
 // ----------------------------------------------------------------------------
-// Read ws[v] before the atomic: skips atomics that would lose, at the price of
-// one more memory round trip on every successful proposal.
-constexpr bool kSuitorPrecheck = true;
-
 __global__ void __launch_bounds__(kBlock)
-k_suitor(int n, int first, int count, const int *__restrict__ rp, const unsigned long long *__restrict__ cand,
-         int *pos, unsigned long long *ws) {
-    // Vertices n-1-first-t for t < count: highest vertices first.  Workgroups
-    // are dispatched roughly in index order, and the greedy order settles large
-    // indices first on equal weights.
-    const int t0 = (int)(blockIdx.x * kBlock + threadIdx.x);
-    if (t0 >= count) return;
-    const int u0 = n - 1 - first - t0;
+k_suitor(int n, const int *__restrict__ rp, const unsigned long long *__restrict__ cand, int *pos,
+         unsigned long long *ws) {
+    // Highest vertices first: workgroups are dispatched roughly in index order,
+    // and the greedy order settles large indices first on equal weights.  (Cut
+    // into several launches, highest chunk first, this ran slower.)
+    const int u0 = n - 1 - (int)(blockIdx.x * kBlock + threadIdx.x);
+    if (u0 < 0) return;
     int u = u0;
     int t = rp[u], end = rp[u + 1];
     for (;;) {
-        int v = -1;
-        unsigned long long key = 0ull;
-        for (; t < end; ++t) {
-            const unsigned long long e = cand[t];
-            if (e == ~0ull) break;
-            const unsigned long long k = (e & 0xffffffff00000000ull) | (unsigned long long)(unsigned)(u + 1);
-            const int vt = (int)(e & 0xffffffffull);
-            if (!kSuitorPrecheck || k > load_agent(&ws[vt])) { v = vt; key = k; break; }
-        }
-        if (v < 0) break;  // no candidate left: u stays unmatched
+        // u's next candidate; ws[v] is not read first: the atomic itself tells
+        // whether u lost, and a read would add a memory round trip per proposal
+        if (t >= end) break;
+        const unsigned long long e = cand[t];
+        if (e == ~0ull) break;  // no candidate left: u stays unmatched
+        const unsigned long long key = (e & 0xffffffff00000000ull) | (unsigned long long)(unsigned)(u + 1);
+        const int v = (int)(e & 0xffffffffull);
         __hip_atomic_store(&pos[u], t + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         const unsigned long long old = atomicMax(&ws[v], key);
         if (old > key) { ++t; continue; }  // lost v for good (ws only grows): next candidate
@@ -423,19 +417,27 @@ k_diag_l1(int n, const int *__restrict__ rp, const double *__restrict__ v, doubl
 __global__ void __launch_bounds__(kBlock)
 k_sell_width(int n, const int *__restrict__ rp, const int *__restrict__ ci, int *__restrict__ cnt,
              int *__restrict__ maxoff) {
-    const int sl = blockIdx.x * kBlock + threadIdx.x;
+    // one wave per slice, lane l on row 64 s + l
+    static_assert(kBlock % kSlice == 0, "a block must hold whole slices");
+    const int gid = blockIdx.x * kBlock + threadIdx.x;
+    const int sl = gid / kSlice, i = gid;
     const int ns = (n + kSlice - 1) / kSlice;
-    if (sl >= ns) return;
+    if (sl >= ns) return;  // whole waves only: kBlock is a multiple of kSlice
     int w = 0, off = 0;
-    const int r1 = min(n, (sl + 1) * kSlice);
-    for (int i = sl * kSlice; i < r1; ++i) {
+    if (i < n) {
         const int q0 = rp[i], q1 = rp[i + 1];
-        w = max(w, q1 - q0);
+        w = q1 - q0;
         // columns are sorted: the extreme offsets are the first and the last
-        if (q1 > q0) off = max(off, max(abs(ci[q0] - i), abs(ci[q1 - 1] - i)));
+        if (q1 > q0) off = max(abs(ci[q0] - i), abs(ci[q1 - 1] - i));
     }
-    cnt[sl] = w * kSlice;
-    atomicMax(maxoff, off);
+    for (int o = kSlice / 2; o > 0; o >>= 1) {
+        w = max(w, __shfl_xor(w, o, kSlice));
+        off = max(off, __shfl_xor(off, o, kSlice));
+    }
+    if (i % kSlice == 0) {
+        cnt[sl] = w * kSlice;
+        atomicMax(maxoff, off);
+    }
 }
 
 // One thread per row writes its entries in column-major slot order; padding
@@ -522,19 +524,9 @@ void launch_candidates(hipStream_t s, int G, int n, const int *rp, const int *ci
     });
 }
 
-// The vertices are handed out in launches of kSuitorChunk, highest first.  The
-// matching does not depend on the order in which vertices propose; the
-// chunks only keep low vertices from proposing before the high ones settled,
-// which on equal weights shortens the chains of displaced suitors.
-constexpr int kSuitorChunk = 1 << 30;
-
 void launch_suitor(hipStream_t s, int n, const int *rp, const unsigned long long *cand, int *pos,
                    unsigned long long *ws) {
-    for (long long first = 0; first < n; first += kSuitorChunk) {
-        const int count = (int)(n - first < kSuitorChunk ? n - first : kSuitorChunk);
-        hipLaunchKernelGGL(k_suitor, dim3(blocks_for(count)), dim3(kBlock), 0, s, n, (int)first, count, rp, cand,
-                           pos, ws);
-    }
+    hipLaunchKernelGGL(k_suitor, dim3(blocks_for(n)), dim3(kBlock), 0, s, n, rp, cand, pos, ws);
 }
 
 void launch_mate(hipStream_t s, int n, const unsigned long long *ws, int *mate, int *leader) {
@@ -585,7 +577,8 @@ void launch_diag_l1(hipStream_t s, int G, int n, const int *rp, const double *v,
 
 void launch_sell_width(hipStream_t s, int n, const int *rp, const int *ci, int *cnt, int *maxoff) {
     const int ns = (n + kSlice - 1) / kSlice;
-    hipLaunchKernelGGL(k_sell_width, dim3(blocks_for(ns)), dim3(kBlock), 0, s, n, rp, ci, cnt, maxoff);
+    hipLaunchKernelGGL(k_sell_width, dim3(blocks_for((long long)ns * kSlice)), dim3(kBlock), 0, s, n, rp, ci, cnt,
+                       maxoff);
 }
 
 void launch_sell_fill(hipStream_t s, int n, const int *rp, const int *ci, const double *v, const int *sp, int *sc,

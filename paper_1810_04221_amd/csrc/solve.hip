@@ -404,6 +404,16 @@ k_kcombine(int n, const V *__restrict__ c2, const double *__restrict__ ks, V *__
 // ----------------------------------------------------------------------------
 constexpr int kCoarseLdsBytes = 65536;
 
+}  // namespace
+
+// The coarsest level is solved inside one workgroup when its matrix, inverse
+// diagonal and iterate fit that workgroup's LDS; otherwise one launch per sweep.
+bool coarse_in_lds(int n, int nnz) {
+    return n <= kCoarseLds && (size_t)n * 16 + (size_t)nnz * 12 + (size_t)(n + 1) * 4 <= (size_t)kCoarseLdsBytes;
+}
+
+namespace {
+
 // unit_rhs: the right-hand side is the unit vector e_j with j = blockIdx.x and
 // the result goes to column j of x (n x n, column-major): this builds the dense
 // matrix of the whole sweep operator, one workgroup per column.
@@ -491,99 +501,112 @@ k_coarse_dense(int n, const double *__restrict__ S, const VB *__restrict__ b, VX
 template <typename V>
 __global__ void __launch_bounds__(1024)
 k_tail(int kt, int nl, const TailLevel *__restrict__ tl, const double *__restrict__ S,
-       const double *__restrict__ cdinv, const double *__restrict__ ca, int sweeps,
-       const double *__restrict__ done) {
+       const double *__restrict__ cdinv, const double *__restrict__ ca, int sweeps, const int *__restrict__ ops,
+       int nops, V *__restrict__ x_out, const double *__restrict__ done) {
     if (done && *done != 0.0) return;
     __shared__ double xs[kTailRows];
     const int tid = threadIdx.x, nt = blockDim.x;
-    for (int k = kt; k < nl - 1; ++k) {
+    for (int o = 0; o < nops; ++o) {
+        const int op = ops[o] & 0xff, k = (ops[o] >> 8) & 0xff, sel = (ops[o] >> 16) & 0xff;
         const TailLevel L = tl[k];
         const V *a = (const V *)L.a, *dinv = (const V *)L.dinv, *p = (const V *)L.p;
-        const V *b = (const V *)L.b;
-        V *bc = (V *)tl[k + 1].b;
-        int lpr = 1;
-        while (lpr < 16 && L.nc * (lpr * 2) <= nt) lpr *= 2;
-        const int lane = tid % lpr, ngrp = nt / lpr;
-        for (int E = tid / lpr; E < L.nc; E += ngrp) {
-            V acc = V(0);
-            for (int t = 0; t < L.mstride; ++t) {
-                const int i = L.mem[(size_t)E * L.mstride + t];
-                if (i < 0) break;
+        V *b = (V *)L.b;
+        // output of UP / COARSE: x, or the level's save buffer, or the caller's
+        // vector for the top level's x
+        V *xo = sel ? (V *)L.xs : (k == kt ? x_out : (V *)L.x);
+        if (op == kTailDown) {
+            // b_c[E] = sum_{i in E} p_i (b_i - sum_j a_ij dinv_j b_j)
+            V *bc = (V *)tl[k + 1].b;
+            int lpr = 1;
+            while (lpr < 16 && L.nc * (lpr * 2) <= nt) lpr *= 2;
+            const int lane = tid % lpr, ngrp = nt / lpr;
+            for (int E = tid / lpr; E < L.nc; E += ngrp) {
+                V acc = V(0);
+                for (int t = 0; t < L.mstride; ++t) {
+                    const int i = L.mem[(size_t)E * L.mstride + t];
+                    if (i < 0) break;
+                    V s = V(0);
+                    for (int q = L.rp[i] + lane; q < L.rp[i + 1]; q += lpr) {
+                        const int j = L.ci[q];
+                        s += a[q] * (dinv[j] * b[j]);
+                    }
+                    for (int m = lpr / 2; m > 0; m >>= 1) s += __shfl_xor(s, m, lpr);
+                    acc += p[i] * (b[i] - s);
+                }
+                if (lane == 0) bc[E] = acc;
+            }
+        } else if (op == kTailUp) {
+            // x = D b + P x_c, then x += D (b - A x), with x formed on the fly
+            const V *xc = (const V *)tl[k + 1].x;
+            int lpr = 1;
+            while (lpr < 16 && L.n * (lpr * 2) <= nt) lpr *= 2;
+            const int lane = tid % lpr, ngrp = nt / lpr;
+            for (int i = tid / lpr; i < L.n; i += ngrp) {
                 V s = V(0);
                 for (int q = L.rp[i] + lane; q < L.rp[i + 1]; q += lpr) {
                     const int j = L.ci[q];
-                    s += a[q] * (dinv[j] * b[j]);
+                    s += a[q] * (dinv[j] * b[j] + p[j] * xc[L.agg[j]]);
                 }
-                for (int o = lpr / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, lpr);
-                acc += p[i] * (b[i] - s);
+                for (int m = lpr / 2; m > 0; m >>= 1) s += __shfl_xor(s, m, lpr);
+                if (lane == 0) {
+                    const V bi = b[i], di = dinv[i];
+                    const V xi = di * bi + p[i] * xc[L.agg[i]];
+                    xo[i] = xi + di * (bi - s);
+                }
             }
-            if (lane == 0) bc[E] = acc;
-        }
-        __syncthreads();
-    }
-    {
-        const TailLevel C = tl[nl - 1];
-        const V *b = (const V *)C.b;
-        V *x = (V *)C.x;
-        const int n = C.n;
-        if (S) {
+        } else if (op == kTailResid) {
+            // W-cycle: b <- b - A x on this level
+            const V *x = (const V *)L.x;
             int lpr = 1;
-            while (lpr < 64 && n * (lpr * 2) <= nt) lpr *= 2;
+            while (lpr < 16 && L.n * (lpr * 2) <= nt) lpr *= 2;
             const int lane = tid % lpr, ngrp = nt / lpr;
-            for (int i = tid / lpr; i < n; i += ngrp) {
-                double s = 0.0;
-                for (int j = lane; j < n; j += lpr) s += S[(size_t)i * n + j] * (double)b[j];
-                for (int o = lpr / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, lpr);
-                if (lane == 0) x[i] = (V)s;
+            for (int i = tid / lpr; i < L.n; i += ngrp) {
+                V s = V(0);
+                for (int q = L.rp[i] + lane; q < L.rp[i + 1]; q += lpr) s += a[q] * x[L.ci[q]];
+                for (int m = lpr / 2; m > 0; m >>= 1) s += __shfl_xor(s, m, lpr);
+                if (lane == 0) b[i] = b[i] - s;
             }
-        } else {
-            for (int i = tid; i < n; i += nt) xs[i] = 0.0;
-            __syncthreads();
-            constexpr int R = (kTailRows + 1023) / 1024;
-            for (int t = 0; t < sweeps; ++t) {
-                double xn[R];
+        } else if (op == kTailAdd) {
+            V *x = (V *)L.x;
+            const V *y = (const V *)L.xs;
+            for (int i = tid; i < L.n; i += nt) x[i] = x[i] + y[i];
+        } else {  // kTailCoarse: 20 l1-Jacobi sweeps from zero in float64 (dense operator when built)
+            const int n = L.n;
+            if (S) {
+                int lpr = 1;
+                while (lpr < 64 && n * (lpr * 2) <= nt) lpr *= 2;
+                const int lane = tid % lpr, ngrp = nt / lpr;
+                for (int i = tid / lpr; i < n; i += ngrp) {
+                    double s = 0.0;
+                    for (int j = lane; j < n; j += lpr) s += S[(size_t)i * n + j] * (double)b[j];
+                    for (int m = lpr / 2; m > 0; m >>= 1) s += __shfl_xor(s, m, lpr);
+                    if (lane == 0) xo[i] = (V)s;
+                }
+            } else {
+                for (int i = tid; i < n; i += nt) xs[i] = 0.0;
+                __syncthreads();
+                constexpr int R = (kTailRows + 1023) / 1024;
+                for (int t = 0; t < sweeps; ++t) {
+                    double xn[R];
 #pragma unroll
-                for (int k = 0; k < R; ++k) {
-                    const int i = tid + k * nt;
-                    xn[k] = 0.0;
-                    if (i < n) {
-                        double s = 0.0;
-                        for (int q = C.rp[i]; q < C.rp[i + 1]; ++q) s = s + ca[q] * xs[C.ci[q]];
-                        xn[k] = xs[i] + cdinv[i] * ((double)b[i] - s);
+                    for (int r = 0; r < R; ++r) {
+                        const int i = tid + r * nt;
+                        xn[r] = 0.0;
+                        if (i < n) {
+                            double s = 0.0;
+                            for (int q = L.rp[i]; q < L.rp[i + 1]; ++q) s = s + ca[q] * xs[L.ci[q]];
+                            xn[r] = xs[i] + cdinv[i] * ((double)b[i] - s);
+                        }
                     }
-                }
-                __syncthreads();
+                    __syncthreads();
 #pragma unroll
-                for (int k = 0; k < R; ++k) {
-                    const int i = tid + k * nt;
-                    if (i < n) xs[i] = xn[k];
+                    for (int r = 0; r < R; ++r) {
+                        const int i = tid + r * nt;
+                        if (i < n) xs[i] = xn[r];
+                    }
+                    __syncthreads();
                 }
-                __syncthreads();
-            }
-            for (int i = tid; i < n; i += nt) x[i] = (V)xs[i];
-        }
-        __syncthreads();
-    }
-    for (int k = nl - 2; k >= kt; --k) {
-        const TailLevel L = tl[k];
-        const V *a = (const V *)L.a, *dinv = (const V *)L.dinv, *p = (const V *)L.p;
-        const V *b = (const V *)L.b;
-        const V *xc = (const V *)tl[k + 1].x;
-        V *x = (V *)L.x;
-        int lpr = 1;
-        while (lpr < 16 && L.n * (lpr * 2) <= nt) lpr *= 2;
-        const int lane = tid % lpr, ngrp = nt / lpr;
-        for (int i = tid / lpr; i < L.n; i += ngrp) {
-            V s = V(0);
-            for (int q = L.rp[i] + lane; q < L.rp[i + 1]; q += lpr) {
-                const int j = L.ci[q];
-                s += a[q] * (dinv[j] * b[j] + p[j] * xc[L.agg[j]]);
-            }
-            for (int o = lpr / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, lpr);
-            if (lane == 0) {
-                const V bi = b[i], di = dinv[i];
-                const V xi = di * bi + p[i] * xc[L.agg[i]];
-                x[i] = xi + di * (bi - s);
+                for (int i = tid; i < n; i += nt) xo[i] = (V)xs[i];
             }
         }
         __syncthreads();
@@ -591,21 +614,32 @@ k_tail(int kt, int nl, const TailLevel *__restrict__ tl, const double *__restric
 }
 
 // One global l1-Jacobi sweep (coarsest levels larger than the LDS bound).
-template <typename VB>
+// One l1-Jacobi sweep of a coarsest level too large for one workgroup's LDS:
+// xn = xo + D (b - A xo) (first: xo = 0, so xn = D b).  G lanes per row and R
+// rows per group, as in the cycle kernels.
+template <int G, int R, typename VB>
 __global__ void __launch_bounds__(kBlock)
 k_jacobi_sweep(int n, const int *__restrict__ rp, const int *__restrict__ ci, const double *__restrict__ a,
                const double *__restrict__ dinv, const VB *__restrict__ b, const double *__restrict__ xo,
                double *__restrict__ xn, int first, const double *__restrict__ done) {
     if (done && *done != 0.0) return;
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i >= n) return;
-    double s = 0.0;
-    if (!first) {
-        const int e = rp[i + 1];
-        for (int q = rp[i]; q < e; ++q) s = s + a[q] * xo[ci[q]];
+    const int lane = threadIdx.x % G;
+    const int g = (xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x) / G;
+    int rows[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) rows[k] = g * R + k < n ? g * R + k : -1;
+    double s[R];
+    if (first) {
+#pragma unroll
+        for (int k = 0; k < R; ++k) s[k] = 0.0;
+    } else {
+        rows_dot<G, R, double>(rp, ci, a, rows, s, [&](int j) { return xo[j]; });
     }
-    const double r = (double)b[i] - s;
-    xn[i] = (first ? 0.0 : xo[i]) + dinv[i] * r;
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        const int i = rows[k];
+        if (lane == k % G && i >= 0) xn[i] = (first ? 0.0 : xo[i]) + dinv[i] * ((double)b[i] - s[k]);
+    }
 }
 
 template <typename VX>
@@ -904,17 +938,22 @@ void coarse_t(hipStream_t s, const Level &L, int sweeps, const VB *b, VX *x, dou
         hipLaunchKernelGGL((k_coarse_dense<VB, VX>), dim3(n), dim3(64), 0, s, n, L.S, b, x, done);
         return;
     }
-    if (n <= kCoarseLds) {
+    if (coarse_in_lds(n, L.A.nnz)) {
         hipLaunchKernelGGL((k_coarse<VB, VX>), dim3(1), dim3(1024), 0, s, n, L.A.nnz, L.A.rp, L.A.ci, L.A.v, L.dinv,
                            b, x, sweeps, 0, done);
         return;
     }
     double *xo = ta, *xn = tb;
-    for (int t = 0; t < sweeps; ++t) {
-        hipLaunchKernelGGL((k_jacobi_sweep<VB>), dim3(blocks_for(n)), dim3(kBlock), 0, s, n, L.A.rp, L.A.ci,
-                           L.A.v, L.dinv, b, xo, xn, t == 0 ? 1 : 0, done);
-        double *tmp = xo; xo = xn; xn = tmp;
-    }
+    with_G(L.G, [&](auto gc) {
+        constexpr int g = decltype(gc)::value;
+        constexpr int R = 2;
+        for (int t = 0; t < sweeps; ++t) {
+            hipLaunchKernelGGL((k_jacobi_sweep<g, R, VB>), dim3(blocks_for(((long long)n + R - 1) / R * g)),
+                               dim3(kBlock), 0, s, n, L.A.rp, L.A.ci, L.A.v, L.dinv, b, xo, xn, t == 0 ? 1 : 0,
+                               done);
+            double *tmp = xo; xo = xn; xn = tmp;
+        }
+    });
     hipLaunchKernelGGL((k_store<VX>), dim3(blocks_for(n)), dim3(kBlock), 0, s, n, xo, x, done);
 }
 
@@ -960,11 +999,13 @@ void launch_coarse(hipStream_t s, const Level &L, int sweeps, const void *b, voi
 }
 
 void launch_tail(hipStream_t s, int fp32, int kt, int nl, const TailLevel *tl, const Level &C, int sweeps,
-                 const double *done) {
+                 const int *ops, int nops, void *x_out, const double *done) {
     if (fp32)
-        hipLaunchKernelGGL((k_tail<float>), dim3(1), dim3(1024), 0, s, kt, nl, tl, C.S, C.dinv, C.A.v, sweeps, done);
+        hipLaunchKernelGGL((k_tail<float>), dim3(1), dim3(1024), 0, s, kt, nl, tl, C.S, C.dinv, C.A.v, sweeps, ops,
+                           nops, (float *)x_out, done);
     else
-        hipLaunchKernelGGL((k_tail<double>), dim3(1), dim3(1024), 0, s, kt, nl, tl, C.S, C.dinv, C.A.v, sweeps, done);
+        hipLaunchKernelGGL((k_tail<double>), dim3(1), dim3(1024), 0, s, kt, nl, tl, C.S, C.dinv, C.A.v, sweeps, ops,
+                           nops, (double *)x_out, done);
 }
 
 void launch_resid_inplace(hipStream_t s, const Level &L, int fp32, const void *x, void *b, const double *done) {
