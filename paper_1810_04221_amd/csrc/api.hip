@@ -496,11 +496,12 @@ int build_hierarchy(bcm_handle *h, const bcm_csr *Ain, const double *win) {
         std::vector<int> lv_sell;
         for (int l = 0; l < h->nl && P.sell; ++l)
             if (l == 0 || h->lv[l].xp) lv_sell.push_back(l);
-        // per level t: tot[t] = total slots, tot[32 + t] = largest |col - row|
+        // per level t: tot[t] = total slots, tot[32 + t] = largest |col - row|,
+        // tot[64 + t] = 1 if some value is not exactly a float32
         if (lv_sell.size() > 32) lv_sell.resize(32);  // deeper levels keep the CSR kernels
-        int *tot = h->persist.get_n<int>(64);
+        int *tot = h->persist.get_n<int>(96);
         NOMEM(tot);
-        launch_fill_i32(s, 64, tot, 0);
+        launch_fill_i32(s, 96, tot, 0);
         for (size_t t = 0; t < lv_sell.size(); ++t) {
             Level &L = h->lv[lv_sell[t]];
             const int ns = (L.A.n + kSlice - 1) / kSlice;
@@ -508,11 +509,11 @@ int build_hierarchy(bcm_handle *h, const bcm_csr *Ain, const double *win) {
             L.E.sp = h->persist.get_n<int>((size_t)ns + 1);
             void *stmp = keep.get(scan_tmp_bytes(ns));
             NOMEM(L.E.sp && stmp);
-            launch_sell_width(s, L.A.n, L.A.rp, L.A.ci, L.E.sp, tot + 32 + t);
+            launch_sell_width(s, L.A.n, L.A.rp, L.A.ci, L.A.v, L.E.sp, tot + 32 + t, tot + 64 + t);
             scan_exclusive(s, L.E.sp, L.E.sp, ns, L.E.sp + ns, stmp);  // sp[ns] = total slots
             HIPCHK(hipMemcpyAsync(tot + t, L.E.sp + ns, sizeof(int), hipMemcpyDeviceToDevice, s));
         }
-        int tots[64];
+        int tots[96];
         int rc = read_back(s, tot, sizeof(tots), tots);
         if (rc) return rc;
         for (size_t t = 0; t < lv_sell.size(); ++t) {
@@ -520,9 +521,10 @@ int build_hierarchy(bcm_handle *h, const bcm_csr *Ain, const double *win) {
             const size_t ne = (size_t)tots[t];
             if (tots[32 + t] <= 32767) L.E.sd = h->persist.get_n<short>(ne);
             else L.E.sc = h->persist.get_n<int>(ne);
-            L.E.sv = h->persist.get_n<double>(ne);
-            if (fp32) L.E.sv32 = h->persist.get_n<float>(ne);
-            NOMEM((L.E.sc || L.E.sd) && L.E.sv && (!fp32 || L.E.sv32));
+            const bool exact32 = tots[64 + t] == 0;
+            if (!exact32) L.E.sv = h->persist.get_n<double>(ne);
+            if (fp32 || exact32) L.E.sv32 = h->persist.get_n<float>(ne);
+            NOMEM((L.E.sc || L.E.sd) && (L.E.sv || L.E.sv32));
             launch_sell_fill(s, L.A.n, L.A.rp, L.A.ci, L.A.v, L.E.sp, L.E.sc, L.E.sd, L.E.sv, L.E.sv32);
         }
     }
@@ -628,6 +630,11 @@ bool kcycle_at(const bcm_handle *h, int k) {
 // Bytes of one column index of the matrix a row-parallel kernel reads: int16
 // offsets on a sliced-ELL copy that has them, else int32.
 double index_bytes(const Level &L, bool sell_path) { return sell_path && L.E.sd ? 2.0 : 4.0; }
+// Bytes of one matrix value: float32 arithmetic, or a float64 kernel on a
+// sliced-ELL copy whose values are all exact float32, reads 4.
+double value_bytes(const Level &L, bool sell_path, bool f32) {
+    return f32 || (sell_path && !L.E.sv && L.E.sv32) ? 4.0 : 8.0;
+}
 
 double bytes_down(const bcm_handle *h, int k) {
     const Level &L = h->lv[k];
@@ -635,7 +642,7 @@ double bytes_down(const bcm_handle *h, int k) {
     const double sv = f32 ? 4 : 8, sb = (k == 0 || !f32) ? 8 : 4;
     const double n = L.A.n, z = L.A.nnz, nc = L.nc;
     const bool sell = L.E.sp && L.xp && (L.mstride == 2 || L.mstride == 4);
-    const double base = 4 * (n + 1) + (index_bytes(L, sell) + sv) * z + sb * n + 2 * sv * n +
+    const double base = 4 * (n + 1) + (index_bytes(L, sell) + value_bytes(L, sell, f32)) * z + sb * n + 2 * sv * n +
                         4.0 * nc * L.mstride + sv * nc;
     return sell ? base + 2 * sv * n : base;
 }
@@ -647,7 +654,8 @@ double bytes_up(const bcm_handle *h, int k) {
     const double n = L.A.n, z = L.A.nnz, nc = L.nc;
     if (L.xp && L.A.n >= kSplitUp)
         return (sb * n + 2 * sv * n + 4 * n + sv * nc + sv * n) +
-               (4 * (n + 1) + (index_bytes(L, L.E.sp != nullptr) + sv) * z + 2 * sv * n + 2 * sb * n);
+               (4 * (n + 1) + (index_bytes(L, L.E.sp != nullptr) + value_bytes(L, L.E.sp != nullptr, f32)) * z +
+                2 * sv * n + 2 * sb * n);
     return 4 * (n + 1) + (4 + sv) * z + 2 * sb * n + 2 * sv * n + 4 * n + sv * nc;
 }
 double bytes_coarse(const bcm_handle *h) {
@@ -680,7 +688,7 @@ double bytes_spmv_dots(const bcm_handle *h) {
     const Level &L = h->lv[0];
     const double n = L.A.n, z = L.A.nnz;
     // algorithmic: every stored entry once (ELL padding not counted)
-    return 4 * (n + 1) + (index_bytes(L, L.E.sp != nullptr) + 8) * z + 32 * n;
+    return 4 * (n + 1) + (index_bytes(L, L.E.sp != nullptr) + value_bytes(L, L.E.sp != nullptr, false)) * z + 32 * n;
 }
 double bytes_update(const bcm_handle *h) { return 80.0 * h->lv[0].A.n; }
 

@@ -65,7 +65,10 @@ struct Csr {
 // of row 64 s + l sits at sp[s] + 64 k + l.  Rows keep their CSR column order
 // and are padded with (col = row, value = 0), so a row sum taken left to right
 // equals the CSR one.  Columns are stored as int16 offsets col - row when every
-// offset of the level fits (sd), else as int32 columns (sc).
+// offset of the level fits (sd), else as int32 columns (sc).  Values: float64
+// (sv) and, for float32 cycles, float32 (sv32); when every value of the level
+// is exactly a float32 only sv32 is kept and the float64 kernels widen it
+// (exactly) on load.
 constexpr int kSlice = 64;
 struct Sell {
     int nslices = 0;
@@ -188,8 +191,10 @@ void launch_diag_l1(hipStream_t s, int G, int n, const int *rp, const double *v,
                     float *dinv32);
 void launch_cast(hipStream_t s, size_t n, const double *src, float *dst);
 // slice widths (64 * longest row of each slice) -> cnt[nslices]; *maxoff is
-// raised to the largest |col - row| of the matrix (start it at 0)
-void launch_sell_width(hipStream_t s, int n, const int *rp, const int *ci, int *cnt, int *maxoff);
+// raised to the largest |col - row| of the matrix, *inexact to 1 if a value is
+// not exactly a float32 (start both at 0)
+void launch_sell_width(hipStream_t s, int n, const int *rp, const int *ci, const double *v, int *cnt, int *maxoff,
+                       int *inexact);
 // fills the slots: int32 columns into sc, or int16 offsets into sd (one is null)
 void launch_sell_fill(hipStream_t s, int n, const int *rp, const int *ci, const double *v, const int *sp, int *sc,
                       short *sd, double *sv, float *sv32);

@@ -415,28 +415,40 @@ k_diag_l1(int n, const int *__restrict__ rp, const double *__restrict__ v, doubl
 
 // Sliced ELL: width of slice s (times 64) = 64 * max row length over its rows.
 __global__ void __launch_bounds__(kBlock)
-k_sell_width(int n, const int *__restrict__ rp, const int *__restrict__ ci, int *__restrict__ cnt,
-             int *__restrict__ maxoff) {
-    // one wave per slice, lane l on row 64 s + l
+k_sell_width(int n, const int *__restrict__ rp, const int *__restrict__ ci, const double *__restrict__ v,
+             int *__restrict__ cnt, int *__restrict__ maxoff, int *__restrict__ inexact) {
+    // one wave per slice (lane l on row 64 s + l), waves striding over slices;
+    // the largest offset is reduced per block, then one atomic per block
     static_assert(kBlock % kSlice == 0, "a block must hold whole slices");
-    const int gid = blockIdx.x * kBlock + threadIdx.x;
-    const int sl = gid / kSlice, i = gid;
+    constexpr int kWaves = kBlock / kSlice;
+    __shared__ int red[kWaves], redx[kWaves];
     const int ns = (n + kSlice - 1) / kSlice;
-    if (sl >= ns) return;  // whole waves only: kBlock is a multiple of kSlice
-    int w = 0, off = 0;
-    if (i < n) {
-        const int q0 = rp[i], q1 = rp[i + 1];
-        w = q1 - q0;
-        // columns are sorted: the extreme offsets are the first and the last
-        if (q1 > q0) off = max(abs(ci[q0] - i), abs(ci[q1 - 1] - i));
+    const int lane = threadIdx.x % kSlice, wv = threadIdx.x / kSlice;
+    int off = 0, inx = 0;
+    for (int sl = blockIdx.x * kWaves + wv; sl < ns; sl += gridDim.x * kWaves) {
+        const int i = sl * kSlice + lane;
+        int w = 0;
+        if (i < n) {
+            const int q0 = rp[i], q1 = rp[i + 1];
+            w = q1 - q0;
+            // columns are sorted: the extreme offsets are the first and the last
+            if (q1 > q0) off = max(off, max(abs(ci[q0] - i), abs(ci[q1 - 1] - i)));
+            for (int q = q0; q < q1; ++q) inx |= (double)(float)v[q] != v[q] ? 1 : 0;
+        }
+        for (int o = kSlice / 2; o > 0; o >>= 1) w = max(w, __shfl_xor(w, o, kSlice));
+        if (lane == 0) cnt[sl] = w * kSlice;
     }
     for (int o = kSlice / 2; o > 0; o >>= 1) {
-        w = max(w, __shfl_xor(w, o, kSlice));
         off = max(off, __shfl_xor(off, o, kSlice));
+        inx |= __shfl_xor(inx, o, kSlice);
     }
-    if (i % kSlice == 0) {
-        cnt[sl] = w * kSlice;
-        atomicMax(maxoff, off);
+    if (lane == 0) { red[wv] = off; redx[wv] = inx; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int m = red[0], x = redx[0];
+        for (int k = 1; k < kWaves; ++k) { m = max(m, red[k]); x |= redx[k]; }
+        atomicMax(maxoff, m);
+        if (x) atomicMax(inexact, 1);
     }
 }
 
@@ -457,7 +469,7 @@ k_sell_fill(int n, const int *__restrict__ rp, const int *__restrict__ ci, const
         const double val = in ? v[q0 + k] : 0.0;
         if (sd) sd[base + k * kSlice] = (short)(col - i);
         else sc[base + k * kSlice] = col;
-        sv[base + k * kSlice] = val;
+        if (sv) sv[base + k * kSlice] = val;
         if (sv32) sv32[base + k * kSlice] = (float)val;
     }
 }
@@ -575,10 +587,11 @@ void launch_diag_l1(hipStream_t s, int G, int n, const int *rp, const double *v,
     });
 }
 
-void launch_sell_width(hipStream_t s, int n, const int *rp, const int *ci, int *cnt, int *maxoff) {
+void launch_sell_width(hipStream_t s, int n, const int *rp, const int *ci, const double *v, int *cnt, int *maxoff,
+                       int *inexact) {
     const int ns = (n + kSlice - 1) / kSlice;
-    hipLaunchKernelGGL(k_sell_width, dim3(blocks_for((long long)ns * kSlice)), dim3(kBlock), 0, s, n, rp, ci, cnt,
-                       maxoff);
+    const int nb = std::min(blocks_for((long long)ns * kSlice), 512);
+    hipLaunchKernelGGL(k_sell_width, dim3(nb), dim3(kBlock), 0, s, n, rp, ci, v, cnt, maxoff, inexact);
 }
 
 void launch_sell_fill(hipStream_t s, int n, const int *rp, const int *ci, const double *v, const int *sp, int *sc,

@@ -30,6 +30,25 @@ void with_G(int G, Fn &&fn) {
 
 inline int blocks_for(long long threads) { return (int)((threads + kBlock - 1) / kBlock); }
 
+// Calls fn(index pointer, value pointer) with the sliced-ELL arrays a kernel of
+// arithmetic type V reads: int16 offsets or int32 columns, and float64 values,
+// or float32 values (float32 arithmetic, or values that are exact floats).
+template <typename V, typename Fn>
+void with_sell(const Sell &E, Fn &&fn) {
+    if constexpr (std::is_same<V, float>::value) {
+        if (E.sd) fn(E.sd, E.sv32);
+        else fn(E.sc, E.sv32);
+    } else {
+        if (E.sd) {
+            if (E.sv) fn(E.sd, E.sv);
+            else fn(E.sd, E.sv32);
+        } else {
+            if (E.sv) fn(E.sc, E.sv);
+            else fn(E.sc, E.sv32);
+        }
+    }
+}
+
 // R rows per group of G lanes.  All loads of the first pass over the R rows
 // are issued before any result is used (out-of-row lanes read entry beg[k] and
 // discard it), which keeps R times more memory requests in flight per lane than
@@ -69,16 +88,18 @@ __device__ __forceinline__ int sell_col(short d, int i) { return i + (int)d; }
 // Row i of a sliced ELL matrix: sum_k a_k * f(col_k), left to right over the
 // row's slots (CSR order, then zero padding).  Lane i % 64 of a wave owns row i,
 // so every slot load of the wave is one contiguous access (64 x 2, 4 or 8 B).
-template <typename V, typename I, typename F>
+// Values are stored as S and multiplied as V (S = float under V = double only
+// when every value of the level is exactly a float: the conversion is exact).
+template <typename V, typename S, typename I, typename F>
 __device__ __forceinline__ V sell_row(const int *__restrict__ sp, const I *__restrict__ sc,
-                                      const V *__restrict__ sv, int i, F f) {
+                                      const S *__restrict__ sv, int i, F f) {
     const int sl = i / kSlice, lane = i % kSlice;
     const int beg = sp[sl], w = (sp[sl + 1] - beg) / kSlice;
     const I *c = sc + beg + lane;
-    const V *a = sv + beg + lane;
+    const S *a = sv + beg + lane;
     V s = V(0);
 #pragma unroll 8
-    for (int k = 0; k < w; ++k) s += a[k * kSlice] * f(sell_col(c[k * kSlice], i));
+    for (int k = 0; k < w; ++k) s += (V)a[k * kSlice] * f(sell_col(c[k * kSlice], i));
     return s;
 }
 
@@ -148,15 +169,15 @@ k_down_loop(int nc, int mstride, const int *__restrict__ mem, const int *__restr
 //   pr_i = p_i (b_i - sum_j a_ij dinv_j b_j),
 // followed by the restriction b_c[E] = sum of pr over E's members in ascending
 // order (the order a serial P^T r takes).
-template <typename V, typename VB, typename I>
+template <typename V, typename VB, typename I, typename S>
 __global__ void __launch_bounds__(kBlock)
-k_down_res_sell(int n, const int *__restrict__ sp, const I *__restrict__ sc, const V *__restrict__ sv,
+k_down_res_sell(int n, const int *__restrict__ sp, const I *__restrict__ sc, const S *__restrict__ sv,
                 const V *__restrict__ dinv, const V *__restrict__ p, const VB *__restrict__ b, V *__restrict__ pr,
                 const double *__restrict__ done) {
     if (done && *done != 0.0) return;
     const int i = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
     if (i >= n) return;
-    const V s = sell_row<V, I>(sp, sc, sv, i, [&](int j) { return dinv[j] * (V)b[j]; });
+    const V s = sell_row<V, S, I>(sp, sc, sv, i, [&](int j) { return dinv[j] * (V)b[j]; });
     pr[i] = p[i] * ((V)b[i] - s);
 }
 
@@ -246,15 +267,15 @@ k_smooth(int n, const int *__restrict__ rp, const int *__restrict__ ci, const V 
 }
 
 // k_smooth on the sliced ELL copy, one thread per row.
-template <typename V, typename VB, typename VX, typename I>
+template <typename V, typename VB, typename VX, typename I, typename S>
 __global__ void __launch_bounds__(kBlock)
-k_smooth_sell(int n, const int *__restrict__ sp, const I *__restrict__ sc, const V *__restrict__ sv,
+k_smooth_sell(int n, const int *__restrict__ sp, const I *__restrict__ sc, const S *__restrict__ sv,
               const V *__restrict__ dinv, const VB *__restrict__ b, const V *__restrict__ xp, VX *__restrict__ x,
               const double *__restrict__ done) {
     if (done && *done != 0.0) return;
     const int i = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
     if (i >= n) return;
-    const V s = sell_row<V, I>(sp, sc, sv, i, [&](int j) { return xp[j]; });
+    const V s = sell_row<V, S, I>(sp, sc, sv, i, [&](int j) { return xp[j]; });
     x[i] = (VX)(xp[i] + dinv[i] * ((V)b[i] - s));
 }
 
@@ -725,15 +746,15 @@ k_spmv_dots(int n, const int *__restrict__ rp, const int *__restrict__ ci, const
 
 // Sliced-ELL variants: one thread per row, grid-stride; each row sum is taken
 // left to right exactly as a serial CSR product.
-template <typename I>
+template <typename I, typename S>
 __global__ void __launch_bounds__(kBlock)
-k_resid_sell(int n, const int *__restrict__ sp, const I *__restrict__ sc, const double *__restrict__ sv,
+k_resid_sell(int n, const int *__restrict__ sp, const I *__restrict__ sc, const S *__restrict__ sv,
              const double *__restrict__ b, const double *__restrict__ u, double *__restrict__ r,
              double *__restrict__ partials) {
     const int blk = xcd_block(blockIdx.x, gridDim.x);
     double acc[2] = {0.0, 0.0};
     for (int i = blk * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
-        const double s = sell_row<double, I>(sp, sc, sv, i, [&](int j) { return u[j]; });
+        const double s = sell_row<double, S, I>(sp, sc, sv, i, [&](int j) { return u[j]; });
         const double bi = b[i];
         const double ri = bi - s;
         r[i] = ri;
@@ -743,16 +764,16 @@ k_resid_sell(int n, const int *__restrict__ sp, const I *__restrict__ sc, const 
     block_partials<2>(acc, partials);
 }
 
-template <typename I>
+template <typename I, typename S>
 __global__ void __launch_bounds__(kBlock)
-k_spmv_dots_sell(int n, const int *__restrict__ sp, const I *__restrict__ sc, const double *__restrict__ sv,
+k_spmv_dots_sell(int n, const int *__restrict__ sp, const I *__restrict__ sc, const S *__restrict__ sv,
                  const double *__restrict__ w, const double *__restrict__ r, const double *__restrict__ q,
                  double *__restrict__ v, double *__restrict__ partials, const double *__restrict__ done) {
     if (done && *done != 0.0) return;
     const int blk = xcd_block(blockIdx.x, gridDim.x);
     double acc[3] = {0.0, 0.0, 0.0};
     for (int i = blk * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
-        const double s = sell_row<double, I>(sp, sc, sv, i, [&](int j) { return w[j]; });
+        const double s = sell_row<double, S, I>(sp, sc, sv, i, [&](int j) { return w[j]; });
         const double wi = w[i];
         v[i] = s;
         acc[0] += wi * r[i];
@@ -876,13 +897,12 @@ void down_t(hipStream_t s, const Level &L, const V *a, const V *dinv, const V *p
             const double *done) {
     if (L.E.sp && L.xp && (L.mstride == 2 || L.mstride == 4)) {
         V *pr = (V *)L.xp;  // free during the down leg: the up leg of this level runs later
-        const V *sv = std::is_same<V, float>::value ? (const V *)L.E.sv32 : (const V *)L.E.sv;
-        if (L.E.sd)
-            hipLaunchKernelGGL((k_down_res_sell<V, VB, short>), dim3(blocks_for(L.A.n)), dim3(kBlock), 0, s, L.A.n,
-                               L.E.sp, L.E.sd, sv, dinv, p, b, pr, done);
-        else
-            hipLaunchKernelGGL((k_down_res_sell<V, VB, int>), dim3(blocks_for(L.A.n)), dim3(kBlock), 0, s, L.A.n,
-                               L.E.sp, L.E.sc, sv, dinv, p, b, pr, done);
+        with_sell<V>(L.E, [&](auto *ix, auto *vals) {
+            using I = std::remove_const_t<std::remove_pointer_t<decltype(ix)>>;
+            using S = std::remove_const_t<std::remove_pointer_t<decltype(vals)>>;
+            hipLaunchKernelGGL((k_down_res_sell<V, VB, I, S>), dim3(blocks_for(L.A.n)), dim3(kBlock), 0, s, L.A.n,
+                               L.E.sp, ix, vals, dinv, p, b, pr, done);
+        });
         if (L.mstride == 4)
             hipLaunchKernelGGL((k_restrict<V, 4>), dim3(blocks_for(L.nc)), dim3(kBlock), 0, s, L.nc, L.mem, pr, bc,
                                done);
@@ -905,13 +925,12 @@ void up_t(hipStream_t s, const Level &L, const V *a, const V *dinv, const V *p, 
         hipLaunchKernelGGL((k_prolong<V, VB>), dim3(blocks_for(L.A.n)), dim3(kBlock), 0, s, L.A.n, dinv, p, L.agg, b,
                            xc, xp, done);
         if (L.E.sp) {
-            const V *sv = std::is_same<V, float>::value ? (const V *)L.E.sv32 : (const V *)L.E.sv;
-            if (L.E.sd)
-                hipLaunchKernelGGL((k_smooth_sell<V, VB, VX, short>), dim3(blocks_for(L.A.n)), dim3(kBlock), 0, s,
-                                   L.A.n, L.E.sp, L.E.sd, sv, dinv, b, xp, x, done);
-            else
-                hipLaunchKernelGGL((k_smooth_sell<V, VB, VX, int>), dim3(blocks_for(L.A.n)), dim3(kBlock), 0, s,
-                                   L.A.n, L.E.sp, L.E.sc, sv, dinv, b, xp, x, done);
+            with_sell<V>(L.E, [&](auto *ix, auto *vals) {
+                using I = std::remove_const_t<std::remove_pointer_t<decltype(ix)>>;
+                using S = std::remove_const_t<std::remove_pointer_t<decltype(vals)>>;
+                hipLaunchKernelGGL((k_smooth_sell<V, VB, VX, I, S>), dim3(blocks_for(L.A.n)), dim3(kBlock), 0, s,
+                                   L.A.n, L.E.sp, ix, vals, dinv, b, xp, x, done);
+            });
             return;
         }
         with_G(L.G, [&](auto gc) {
@@ -1090,12 +1109,12 @@ void launch_coarse_build(hipStream_t s, const Level &L, int sweeps, double *S) {
 void launch_resid(hipStream_t s, const Level &L, int nb, const double *b, const double *u, double *r,
                   double *partials, double *scal) {
     if (L.E.sp) {
-        if (L.E.sd)
-            hipLaunchKernelGGL(k_resid_sell<short>, dim3(nb), dim3(kBlock), 0, s, L.A.n, L.E.sp, L.E.sd, L.E.sv, b, u,
-                               r, partials);
-        else
-            hipLaunchKernelGGL(k_resid_sell<int>, dim3(nb), dim3(kBlock), 0, s, L.A.n, L.E.sp, L.E.sc, L.E.sv, b, u,
-                               r, partials);
+        with_sell<double>(L.E, [&](auto *ix, auto *vals) {
+            using I = std::remove_const_t<std::remove_pointer_t<decltype(ix)>>;
+            using S = std::remove_const_t<std::remove_pointer_t<decltype(vals)>>;
+            hipLaunchKernelGGL((k_resid_sell<I, S>), dim3(nb), dim3(kBlock), 0, s, L.A.n, L.E.sp, ix, vals, b, u, r,
+                               partials);
+        });
         return;
     }
     with_G(L.G, [&](auto gc) {
@@ -1108,12 +1127,12 @@ void launch_resid(hipStream_t s, const Level &L, int nb, const double *b, const 
 void launch_spmv_dots(hipStream_t s, const Level &L, int nb, int first, const double *w, const double *r,
                       const double *q, double *v, double *partials, double *scal) {
     if (L.E.sp) {
-        if (L.E.sd)
-            hipLaunchKernelGGL(k_spmv_dots_sell<short>, dim3(nb), dim3(kBlock), 0, s, L.A.n, L.E.sp, L.E.sd, L.E.sv, w,
-                               r, q, v, partials, scal + 10);
-        else
-            hipLaunchKernelGGL(k_spmv_dots_sell<int>, dim3(nb), dim3(kBlock), 0, s, L.A.n, L.E.sp, L.E.sc, L.E.sv, w,
-                               r, q, v, partials, scal + 10);
+        with_sell<double>(L.E, [&](auto *ix, auto *vals) {
+            using I = std::remove_const_t<std::remove_pointer_t<decltype(ix)>>;
+            using S = std::remove_const_t<std::remove_pointer_t<decltype(vals)>>;
+            hipLaunchKernelGGL((k_spmv_dots_sell<I, S>), dim3(nb), dim3(kBlock), 0, s, L.A.n, L.E.sp, ix, vals, w, r,
+                               q, v, partials, scal + 10);
+        });
         return;
     }
     with_G(L.G, [&](auto gc) {
