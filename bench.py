@@ -31,8 +31,8 @@ METRIC = "setup+solve s to rel-res 1e-8 (Mdof/s, HBM %), FP32-cycle vs FP64 AMG-
 HBM_PEAK_GBS = 8000.0
 CLASSES = ["down0", "up0", "spmv_dots", "update", "coarse", "mid"]
 SINGLE_KERNEL = ["down0", "up0", "spmv_dots", "update", "coarse"]  # one launch per iteration
-KERNEL_OF_CLASS = {"down0": "k_down_res_sell + k_restrict (finest level, down leg)",
-                   "up0": "k_prolong + k_smooth_sell (finest level, up leg)",
+KERNEL_OF_CLASS = {"down0": "k_down_res_sell (finest level: p * (b - A D b), the down leg's residual)",
+                   "up0": "k_smooth_sell (finest level: post-smoothing of the prolonged iterate)",
                    "spmv_dots": "k_spmv_dots_sell (v = A w and three dot products, finest level, FP64)",
                    "update": "k_update (four vector updates and ||r||^2)",
                    "coarse": "coarsest-level solve (k_tail, k_coarse_dense or k_coarse)"}

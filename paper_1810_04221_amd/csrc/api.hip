@@ -658,6 +658,24 @@ double bytes_up(const bcm_handle *h, int k) {
                 2 * sv * n + 2 * sb * n);
     return 4 * (n + 1) + (4 + sv) * z + 2 * sb * n + 2 * sv * n + 4 * n + sv * nc;
 }
+// the main kernel of a level's leg alone: the residual of a split down leg
+// (p r written once), the smoothing of a split up leg; else the fused leg
+double bytes_down_main(const bcm_handle *h, int k) {
+    const Level &L = h->lv[k];
+    const bool f32 = h->prm.precision == BCM_FP32_CYCLE;
+    const double sv = f32 ? 4 : 8, sb = (k == 0 || !f32) ? 8 : 4, n = L.A.n, z = L.A.nnz;
+    const bool sell = L.E.sp && L.xp && (L.mstride == 2 || L.mstride == 4);
+    if (!sell) return bytes_down(h, k);
+    return 4 * (n + 1) + (index_bytes(L, true) + value_bytes(L, true, f32)) * z + sb * n + 3 * sv * n;
+}
+double bytes_up_main(const bcm_handle *h, int k) {
+    const Level &L = h->lv[k];
+    const bool f32 = h->prm.precision == BCM_FP32_CYCLE;
+    const double sv = f32 ? 4 : 8, sb = (k == 0 || !f32) ? 8 : 4, n = L.A.n, z = L.A.nnz;
+    if (!(L.xp && L.A.n >= kSplitUp)) return bytes_up(h, k);
+    return 4 * (n + 1) + (index_bytes(L, L.E.sp != nullptr) + value_bytes(L, L.E.sp != nullptr, f32)) * z +
+           2 * sv * n + 2 * sb * n;
+}
 double bytes_coarse(const bcm_handle *h) {
     const Level &L = h->lv[h->nl - 1];
     const double n = L.A.n, z = L.A.nnz;
@@ -695,8 +713,8 @@ double bytes_update(const bcm_handle *h) { return 80.0 * h->lv[0].A.n; }
 // Bytes of one bracket of a class launched once per iteration (0..4).
 double class_bytes(const bcm_handle *h, int cls) {
     switch (cls) {
-    case 0: return bytes_down(h, 0);
-    case 1: return bytes_up(h, 0);
+    case 0: return bytes_down_main(h, 0);
+    case 1: return bytes_up_main(h, 0);
     case 2: return bytes_spmv_dots(h);
     case 3: return bytes_update(h);
     default: {
@@ -865,21 +883,31 @@ void vcycle(bcm_handle *h, Prof &pf, const double *rin, double *wout, const doub
         // finest level here (f64 in/out), coarse levels recursively
         Level &L = h->lv[0], &N = h->lv[1];
         int e = pf.begin(0);
-        launch_down(s, L, fp32, rin, N.b, 1, done);
-        pf.end(0, e, bytes_down(h, 0), iter);
+        launch_down(s, L, fp32, rin, N.b, 1, done, 1);
+        pf.end(0, e, class_bytes(h, 0), iter);
+        launch_down(s, L, fp32, rin, N.b, 1, done, 2);
         coarse_solve(h, pf, 0, done, iter);
+        launch_up(s, L, fp32, rin, N.x, wout, 1, 1, done, 1);
         e = pf.begin(1);
-        launch_up(s, L, fp32, rin, N.x, wout, 1, 1, done);
-        pf.end(1, e, bytes_up(h, 0), iter);
+        launch_up(s, L, fp32, rin, N.x, wout, 1, 1, done, 2);
+        pf.end(1, e, class_bytes(h, 1), iter);
         return;
     }
     const int kt = h->kt > 0 ? h->kt : nl - 1;
     for (int k = 0; k < kt; ++k) {
         Level &L = h->lv[k];
-        const int cls = k == 0 ? 0 : 5;
-        int e = pf.begin(cls);
-        launch_down(s, L, fp32, k == 0 ? (const void *)rin : L.b, h->lv[k + 1].b, (k == 0 || !fp32) ? 1 : 0, done);
-        pf.end(cls, e, bytes_down(h, k), iter);
+        const void *bk = k == 0 ? (const void *)rin : L.b;
+        const int io = (k == 0 || !fp32) ? 1 : 0;
+        if (k == 0) {  // the finest level's main kernel alone is class 0
+            int e = pf.begin(0);
+            launch_down(s, L, fp32, bk, h->lv[1].b, io, done, 1);
+            pf.end(0, e, class_bytes(h, 0), iter);
+            launch_down(s, L, fp32, bk, h->lv[1].b, io, done, 2);
+        } else {
+            int e = pf.begin(5);
+            launch_down(s, L, fp32, bk, h->lv[k + 1].b, io, done);
+            pf.end(5, e, bytes_down(h, k), iter);
+        }
     }
     {
         int e = pf.begin(4);
@@ -892,12 +920,19 @@ void vcycle(bcm_handle *h, Prof &pf, const double *rin, double *wout, const doub
     }
     for (int k = kt - 1; k >= 0; --k) {
         Level &L = h->lv[k];
-        const int cls = k == 0 ? 1 : 5;
         const int f64io = (k == 0 || !fp32) ? 1 : 0;
-        int e = pf.begin(cls);
-        launch_up(s, L, fp32, k == 0 ? (const void *)rin : L.b, h->lv[k + 1].x, k == 0 ? (void *)wout : L.x, f64io,
-                  f64io, done);
-        pf.end(cls, e, bytes_up(h, k), iter);
+        const void *bk = k == 0 ? (const void *)rin : L.b;
+        void *xk = k == 0 ? (void *)wout : L.x;
+        if (k == 0) {  // the finest level's main kernel alone is class 1
+            launch_up(s, L, fp32, bk, h->lv[1].x, xk, f64io, f64io, done, 1);
+            int e = pf.begin(1);
+            launch_up(s, L, fp32, bk, h->lv[1].x, xk, f64io, f64io, done, 2);
+            pf.end(1, e, class_bytes(h, 1), iter);
+        } else {
+            int e = pf.begin(5);
+            launch_up(s, L, fp32, bk, h->lv[k + 1].x, xk, f64io, f64io, done);
+            pf.end(5, e, bytes_up(h, k), iter);
+        }
     }
 }
 

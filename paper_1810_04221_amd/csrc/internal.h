@@ -211,10 +211,12 @@ void scan_exclusive(hipStream_t s, const int *in, int *out, int n, int *total_de
 // ---- solve kernels (solve.hip) ----
 // Cycle kernels return at once when done != NULL and *done != 0 (the flexible
 // CG loop's "solve ended" flag); done = NULL outside that loop.
+// part: 0 = the whole leg; 1 / 2 = its first / second kernel only (a leg of one
+// kernel: that kernel is part 1 of the down leg and part 2 of the up leg)
 void launch_down(hipStream_t s, const Level &L, int fp32, const void *b, void *bc, int b_is_f64,
-                 const double *done);
+                 const double *done, int part = 0);
 void launch_up(hipStream_t s, const Level &L, int fp32, const void *b, const void *xc, void *x,
-               int b_is_f64, int x_is_f64, const double *done);
+               int b_is_f64, int x_is_f64, const double *done, int part = 0);
 void launch_coarse(hipStream_t s, const Level &L, int sweeps, const void *b, void *x, int b_f64,
                    int x_f64, void *tmp_a, void *tmp_b, const double *done);
 // true when the coarsest level (without a dense operator) runs in one workgroup

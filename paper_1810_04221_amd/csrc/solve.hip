@@ -892,17 +892,21 @@ void down_dispatch(hipStream_t s, const Level &L, const V *a, const V *dinv, con
                            L.A.ci, a, dinv, p, b, bc, done);
 }
 
+// part: 0 = the whole leg, 1 = its first kernel, 2 = its second kernel (a
+// leg of one kernel has it as part 1 of the down leg and part 2 of the up leg)
 template <typename V, typename VB>
 void down_t(hipStream_t s, const Level &L, const V *a, const V *dinv, const V *p, const VB *b, V *bc,
-            const double *done) {
+            const double *done, int part) {
     if (L.E.sp && L.xp && (L.mstride == 2 || L.mstride == 4)) {
         V *pr = (V *)L.xp;  // free during the down leg: the up leg of this level runs later
-        with_sell<V>(L.E, [&](auto *ix, auto *vals) {
-            using I = std::remove_const_t<std::remove_pointer_t<decltype(ix)>>;
-            using S = std::remove_const_t<std::remove_pointer_t<decltype(vals)>>;
-            hipLaunchKernelGGL((k_down_res_sell<V, VB, I, S>), dim3(blocks_for(L.A.n)), dim3(kBlock), 0, s, L.A.n,
-                               L.E.sp, ix, vals, dinv, p, b, pr, done);
-        });
+        if (part != 2)
+            with_sell<V>(L.E, [&](auto *ix, auto *vals) {
+                using I = std::remove_const_t<std::remove_pointer_t<decltype(ix)>>;
+                using S = std::remove_const_t<std::remove_pointer_t<decltype(vals)>>;
+                hipLaunchKernelGGL((k_down_res_sell<V, VB, I, S>), dim3(blocks_for(L.A.n)), dim3(kBlock), 0, s,
+                                   L.A.n, L.E.sp, ix, vals, dinv, p, b, pr, done);
+            });
+        if (part == 1) return;
         if (L.mstride == 4)
             hipLaunchKernelGGL((k_restrict<V, 4>), dim3(blocks_for(L.nc)), dim3(kBlock), 0, s, L.nc, L.mem, pr, bc,
                                done);
@@ -911,6 +915,7 @@ void down_t(hipStream_t s, const Level &L, const V *a, const V *dinv, const V *p
                                done);
         return;
     }
+    if (part == 2) return;
     with_G(L.G, [&](auto gc) {
         constexpr int g = decltype(gc)::value;
         down_dispatch<g, V, VB>(s, L, a, dinv, p, b, bc, done);
@@ -919,11 +924,13 @@ void down_t(hipStream_t s, const Level &L, const V *a, const V *dinv, const V *p
 
 template <typename V, typename VB, typename VX>
 void up_t(hipStream_t s, const Level &L, const V *a, const V *dinv, const V *p, const VB *b, const V *xc,
-          VX *x, const double *done) {
+          VX *x, const double *done, int part) {
     if (L.xp && L.A.n >= kSplitUp) {
         V *xp = (V *)L.xp;
-        hipLaunchKernelGGL((k_prolong<V, VB>), dim3(blocks_for(L.A.n)), dim3(kBlock), 0, s, L.A.n, dinv, p, L.agg, b,
-                           xc, xp, done);
+        if (part != 2)
+            hipLaunchKernelGGL((k_prolong<V, VB>), dim3(blocks_for(L.A.n)), dim3(kBlock), 0, s, L.A.n, dinv, p, L.agg,
+                               b, xc, xp, done);
+        if (part == 1) return;
         if (L.E.sp) {
             with_sell<V>(L.E, [&](auto *ix, auto *vals) {
                 using I = std::remove_const_t<std::remove_pointer_t<decltype(ix)>>;
@@ -941,6 +948,7 @@ void up_t(hipStream_t s, const Level &L, const V *a, const V *dinv, const V *p, 
         });
         return;
     }
+    if (part == 1) return;
     with_G(L.G, [&](auto gc) {
         constexpr int g = decltype(gc)::value;
         constexpr int R = 2;
@@ -986,27 +994,27 @@ int reduce_blocks(int n) {
 }
 
 void launch_down(hipStream_t s, const Level &L, int fp32, const void *b, void *bc, int b_is_f64,
-                 const double *done) {
+                 const double *done, int part) {
     if (!fp32) {
-        down_t<double, double>(s, L, L.A.v, L.dinv, L.p, (const double *)b, (double *)bc, done);
+        down_t<double, double>(s, L, L.A.v, L.dinv, L.p, (const double *)b, (double *)bc, done, part);
     } else if (b_is_f64) {
-        down_t<float, double>(s, L, L.A.v32, L.dinv32, L.p32, (const double *)b, (float *)bc, done);
+        down_t<float, double>(s, L, L.A.v32, L.dinv32, L.p32, (const double *)b, (float *)bc, done, part);
     } else {
-        down_t<float, float>(s, L, L.A.v32, L.dinv32, L.p32, (const float *)b, (float *)bc, done);
+        down_t<float, float>(s, L, L.A.v32, L.dinv32, L.p32, (const float *)b, (float *)bc, done, part);
     }
 }
 
 void launch_up(hipStream_t s, const Level &L, int fp32, const void *b, const void *xc, void *x, int b_is_f64,
-               int x_is_f64, const double *done) {
+               int x_is_f64, const double *done, int part) {
     if (!fp32) {
         up_t<double, double, double>(s, L, L.A.v, L.dinv, L.p, (const double *)b, (const double *)xc, (double *)x,
-                                     done);
+                                     done, part);
     } else if (b_is_f64 && x_is_f64) {
         up_t<float, double, double>(s, L, L.A.v32, L.dinv32, L.p32, (const double *)b, (const float *)xc,
-                                    (double *)x, done);
+                                    (double *)x, done, part);
     } else {
         up_t<float, float, float>(s, L, L.A.v32, L.dinv32, L.p32, (const float *)b, (const float *)xc, (float *)x,
-                                  done);
+                                  done, part);
     }
 }
 
