@@ -98,7 +98,7 @@ __device__ __forceinline__ V sell_row(const int *__restrict__ sp, const I *__res
     const I *c = sc + beg + lane;
     const S *a = sv + beg + lane;
     V s = V(0);
-#pragma unroll 8
+#pragma unroll 4
     for (int k = 0; k < w; ++k) s += (V)a[k * kSlice] * f(sell_col(c[k * kSlice], i));
     return s;
 }
