@@ -177,11 +177,12 @@ int match_sweep(hipStream_t s, Arena &tmp, const Csr &A, const double *w, int ch
     int *flags = flags_dev ? flags_dev : tmp.get_n<int>(16);
     double *c = tmp.get_n<double>(A.nnz);
     unsigned long long *cand = tmp.get_n<unsigned long long>(A.nnz);
+    unsigned *rk = tmp.get_n<unsigned>(A.nnz);
     unsigned long long *ws = tmp.get_n<unsigned long long>(m);
     int *pos = tmp.get_n<int>(m);
     int *mate = tmp.get_n<int>(m);
     int *leader = tmp.get_n<int>(m);
-    NOMEM(diag && flags && c && cand && ws && pos && mate && leader);
+    NOMEM(diag && flags && c && cand && rk && ws && pos && mate && leader);
     launch_fill_i32(s, 1, flags, 0);
     launch_validate(s, G, m, A.nnz_dev ? -1 : A.nnz, A.rp, A.ci, A.v, w, check_sym, diag, flags);
     if (!flags_dev) {
@@ -194,7 +195,7 @@ int match_sweep(hipStream_t s, Arena &tmp, const Csr &A, const double *w, int ch
         }
     }
     launch_weights(s, G, m, A.rp, A.ci, A.v, diag, w, c);
-    launch_candidates(s, G, m, A.rp, A.ci, c, cand, pos);
+    launch_candidates(s, G, m, A.nnz, A.rp, A.ci, c, rk, cand, pos);
     launch_fill_u64(s, m, ws, 0ull);
     launch_suitor(s, m, A.rp, cand, pos, ws);
     launch_mate(s, m, ws, mate, leader);
@@ -256,7 +257,8 @@ int pairwise_sweep(hipStream_t s, Arena &tmp, Arena &keep, Csr &A, const double 
     int *gU = tmp.get_n<int>(A.nnz);
     void *stmp2 = tmp.get(scan_tmp_bytes(nc));
     NOMEM(crp && gF && gU && stmp2);
-    launch_gal_count(s, G, nc, A.rp, A.ci, out.agg, out.mem2, crp, gF, gU);
+    const bool gsorted = A.nnz >= (long long)kSortedCandidatesAvg * A.n;
+    launch_gal_count(s, G, nc, A.rp, A.ci, out.agg, out.mem2, crp, gF, gU, gsorted);
     scan_exclusive(s, crp, crp, nc, crp + nc, stmp2);
     out.Ac.n = nc;
     out.Ac.nnz = A.nnz;
@@ -265,7 +267,7 @@ int pairwise_sweep(hipStream_t s, Arena &tmp, Arena &keep, Csr &A, const double 
     out.Ac.ci = oa.get_n<int>(A.nnz);
     out.Ac.v = oa.get_n<double>(A.nnz);
     NOMEM(out.Ac.ci && out.Ac.v);
-    launch_gal_fill(s, G, nc, A.rp, A.ci, A.v, out.agg, out.p, out.mem2, crp, out.Ac.ci, out.Ac.v, gF, gU);
+    launch_gal_fill(s, G, nc, A.rp, A.ci, A.v, out.agg, out.p, out.mem2, crp, out.Ac.ci, out.Ac.v, gF, gU, gsorted);
     HIPCHK(hipGetLastError());
     return BCM_OK;
 }

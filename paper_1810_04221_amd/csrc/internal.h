@@ -172,18 +172,21 @@ void launch_validate(hipStream_t s, int G, int n, int nnz, const int *rp, const 
                      const double *v, const double *w, int check_sym, double *diag, int *flags);
 void launch_weights(hipStream_t s, int G, int n, const int *rp, const int *ci, const double *v,
                     const double *diag, const double *w, double *c);
-void launch_candidates(hipStream_t s, int G, int n, const int *rp, const int *ci, const double *c,
-                       unsigned long long *cand, int *pos);
+// Suitor candidate lists; matrices averaging at least kSortedCandidatesAvg
+// entries per row sort each row (own-row ranks in rk[nnz], scratch)
+constexpr int kSortedCandidatesAvg = 24;
+void launch_candidates(hipStream_t s, int G, int n, int nnz, const int *rp, const int *ci, const double *c,
+                       unsigned *rk, unsigned long long *cand, int *pos);
 void launch_suitor(hipStream_t s, int n, const int *rp, const unsigned long long *cand, int *pos,
                    unsigned long long *ws);
 void launch_mate(hipStream_t s, int n, const unsigned long long *ws, int *mate, int *leader);
 void launch_aggfill(hipStream_t s, int n, const int *mate, const int *ofs, const double *w,
                     int *agg, double *p, double *wc, int *mem2);
 void launch_gal_count(hipStream_t s, int G, int nc, const int *rp, const int *ci, const int *agg,
-                      const int *mem2, int *cnt, int *gF, int *gU);
+                      const int *mem2, int *cnt, int *gF, int *gU, bool sorted);
 void launch_gal_fill(hipStream_t s, int G, int nc, const int *rp, const int *ci, const double *v,
                      const int *agg, const double *p, const int *mem2, const int *crp, int *cci,
-                     double *cv, int *gF, int *gU);
+                     double *cv, int *gF, int *gU, bool sorted);
 void launch_compose(hipStream_t s, int n, int nc_new, const int *agg_prev, const double *p_prev,
                     const int *mem_prev, int stride_prev, const int *agg_s, const double *p_s,
                     const int *mem_s, int *agg_out, double *p_out, int *mem_out);

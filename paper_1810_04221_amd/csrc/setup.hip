@@ -113,19 +113,14 @@ k_weights(int n, const int *__restrict__ rp, const int *__restrict__ ci, const d
 }
 
 // ----------------------------------------------------------------------------
-// Suitor candidate lists.  For row u, the eligible entries (off-diagonal, weight
-// positive and finite) are written in preference order of u -- weight
-// descending, then neighbour index descending -- as 64-bit words
-//   cand = rk << 32 | v,   rk = #{ entries t of row v : c[t] < c_uv }
-// where rk is the position of c_uv among the weights seen from v.  A proposal
-// from u to v then compares at v as (rk << 32 | u + 1), which orders proposals
-// exactly as (c_uv, u) because c_uv is the same double from both ends.  After
-// the eligible entries the row holds the sentinel ~0.  pos[u] = row start.
+// Suitor candidate lists by direct counting (short rows): each eligible entry
+// (u, v) counts its rank among row v's weights and its place in u's order.
+// Same output as k_candidates below; see there.
 // ----------------------------------------------------------------------------
 template <int G>
 __global__ void __launch_bounds__(kBlock)
-k_candidates(int n, const int *__restrict__ rp, const int *__restrict__ ci, const double *__restrict__ c,
-             unsigned long long *__restrict__ cand, int *__restrict__ pos) {
+k_candidates_direct(int n, const int *__restrict__ rp, const int *__restrict__ ci, const double *__restrict__ c,
+                    unsigned long long *__restrict__ cand, int *__restrict__ pos) {
     const int lane = threadIdx.x % G;
     const int row = (xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x) / G;
     if (row >= n) return;
@@ -150,6 +145,168 @@ k_candidates(int n, const int *__restrict__ rp, const int *__restrict__ ci, cons
     }
     nelig = group_sum<G>(nelig);
     for (int q = s0 + nelig + lane; q < e; q += G) cand[q] = ~0ull;
+    if (lane == 0) pos[row] = s0;
+}
+
+// ----------------------------------------------------------------------------
+// Sorting inside a group of G lanes (a wave or part of one): bitonic network
+// over P (a power of two) 64-bit keys in the group's LDS slots, ascending.
+// Only the group's own lanes touch its slots, so wave-level ordering suffices.
+// ----------------------------------------------------------------------------
+template <int G>
+__device__ __forceinline__ void group_sort(unsigned long long *keys, int P, int lane) {
+    for (int size = 2; size <= P; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int t = lane; t < (P >> 1); t += G) {
+                const int lo = 2 * stride * (t / stride) + (t % stride), hi = lo + stride;
+                const bool up = (lo & size) == 0;
+                const unsigned long long a = keys[lo], b = keys[hi];
+                if ((a > b) == up) {
+                    keys[lo] = b;
+                    keys[hi] = a;
+                }
+            }
+            wave_sync();
+        }
+    }
+}
+
+__device__ __forceinline__ int pow2_at_least(int x) {
+    int p = 1;
+    while (p < x) p <<= 1;
+    return p;
+}
+
+// Order-preserving image of a double in the unsigned integers (NaN above +inf).
+__device__ __forceinline__ unsigned long long order_key(double x) {
+    if (x != x) return ~0ull - 1;
+    const unsigned long long b = (unsigned long long)__double_as_longlong(x);
+    return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
+
+// first index k < cnt with keys[k] >= key (keys ascending)
+__device__ __forceinline__ int lower_bound_u64(const unsigned long long *keys, int cnt, unsigned long long key) {
+    int lo = 0, hi = cnt;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (keys[mid] < key) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+// ----------------------------------------------------------------------------
+// Rank of every weight within its own row: rk[q] = #{ t in row(q) : c[t] < c[q] }
+// (the count a row's neighbours need for their Suitor keys).  The row's weights
+// are sorted in LDS and each rank is a binary search; rows longer than the LDS
+// slots count directly.
+// ----------------------------------------------------------------------------
+template <int G>
+__global__ void __launch_bounds__(kBlock)
+k_rank(int n, const int *__restrict__ rp, const double *__restrict__ c, unsigned *__restrict__ rk) {
+    constexpr int LMAX = 16 * G;
+    constexpr int NG = kBlock / G;
+    __shared__ unsigned long long sk[NG * LMAX];
+    const int g = threadIdx.x / G, lane = threadIdx.x % G;
+    const int row = (xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x) / G;
+    if (row >= n) return;
+    const int s0 = rp[row], d = rp[row + 1] - s0;
+    if (d <= LMAX) {
+        unsigned long long *keys = sk + g * LMAX;
+        const int P = pow2_at_least(d);
+        for (int k = lane; k < P; k += G) keys[k] = k < d ? order_key(c[s0 + k]) : ~0ull;
+        wave_sync();
+        group_sort<G>(keys, P, lane);
+        for (int k = lane; k < d; k += G) rk[s0 + k] = (unsigned)lower_bound_u64(keys, d, order_key(c[s0 + k]));
+    } else {
+        for (int k = lane; k < d; k += G) {
+            const double cq = c[s0 + k];
+            unsigned r = 0;
+            for (int t = 0; t < d; ++t) r += (c[s0 + t] < cq) ? 1u : 0u;
+            rk[s0 + k] = r;
+        }
+    }
+}
+
+// ----------------------------------------------------------------------------
+// Suitor candidate lists.  For row u, the eligible entries (off-diagonal, weight
+// positive and finite) are written in preference order of u -- weight
+// descending, then neighbour index descending -- as 64-bit words
+//   cand = rk << 32 | v,   rk = #{ entries t of row v : c[t] < c_uv }
+// where rk is the position of c_uv among the weights seen from v (the own-row
+// rank of the transposed entry, c being the same double from both ends).  A
+// proposal from u to v then compares at v as (rk << 32 | u + 1), which orders
+// proposals exactly as (c_uv, u).  After the eligible entries the row holds
+// the sentinel ~0.  pos[u] = row start.  The preference order is a sort of
+// (own-row rank desc, v desc) in LDS; rows longer than the LDS slots are
+// placed by direct counting.
+// ----------------------------------------------------------------------------
+template <int G>
+__global__ void __launch_bounds__(kBlock)
+k_candidates(int n, const int *__restrict__ rp, const int *__restrict__ ci, const double *__restrict__ c,
+             const unsigned *__restrict__ rk_own, unsigned long long *__restrict__ cand, int *__restrict__ pos) {
+    constexpr int LMAX = 16 * G;
+    constexpr int NG = kBlock / G;
+    __shared__ unsigned long long sk[NG * LMAX];
+    const int g = threadIdx.x / G, lane = threadIdx.x % G;
+    const int row = (xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x) / G;
+    if (row >= n) return;
+    const int s0 = rp[row], e = rp[row + 1], d = e - s0;
+    // rank of c_uv seen from v: the own-row rank of (v, u), found by binary search
+    auto rank_at = [&](int vtx) -> unsigned {
+        int lo = rp[vtx], hi = rp[vtx + 1];
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (ci[mid] < row) lo = mid + 1; else hi = mid;
+        }
+        return rk_own[lo];
+    };
+    if (d <= LMAX) {
+        unsigned long long *keys = sk + g * LMAX;
+        const int P = pow2_at_least(d);
+        int nelig = 0;
+        for (int k = lane; k < P; k += G) {
+            unsigned long long key = ~0ull;
+            if (k < d) {
+                const int vtx = ci[s0 + k];
+                const double cq = c[s0 + k];
+                if (vtx != row && cq > 0.0 && cq < INFINITY) {
+                    // ascending (rank, index) complement = descending preference
+                    key = ((unsigned long long)(0x7fffffffu - rk_own[s0 + k]) << 32) | (0x7fffffffu - (unsigned)vtx);
+                    ++nelig;
+                }
+            }
+            keys[k] = key;
+        }
+        wave_sync();
+        group_sort<G>(keys, P, lane);
+        nelig = group_sum<G>(nelig);
+        for (int k = lane; k < d; k += G) {
+            unsigned long long out = ~0ull;
+            if (k < nelig) {
+                const int vtx = (int)(0x7fffffffu - (unsigned)(keys[k] & 0xffffffffull));
+                out = ((unsigned long long)rank_at(vtx) << 32) | (unsigned)vtx;
+            }
+            cand[s0 + k] = out;
+        }
+    } else {
+        int nelig = 0;
+        for (int q = s0 + lane; q < e; q += G) {
+            const int vtx = ci[q];
+            const double cq = c[q];
+            if (!(vtx != row && cq > 0.0 && cq < INFINITY)) continue;
+            ++nelig;
+            int before = 0;
+            for (int t = s0; t < e; ++t) {
+                const int vt = ci[t];
+                const double ct = c[t];
+                const bool elig = vt != row && ct > 0.0 && ct < INFINITY;
+                before += (elig && (ct > cq || (ct == cq && vt > vtx))) ? 1 : 0;
+            }
+            cand[s0 + before] = ((unsigned long long)rank_at(vtx) << 32) | (unsigned)vtx;
+        }
+        nelig = group_sum<G>(nelig);
+        for (int q = s0 + nelig + lane; q < e; q += G) cand[q] = ~0ull;
+    }
     if (lane == 0) pos[row] = s0;
 }
 
@@ -265,27 +422,16 @@ __device__ __forceinline__ void cswap(unsigned long long &ka, double &ta, unsign
     }
 }
 
+// One coarse row E (members e0 < e1 or e1 = -1) of k_gal: F / U are the
+// group's LDS slots (staged) or the scratch arrays indexed by position in A.
 template <int G>
-__global__ void __launch_bounds__(kBlock)
-k_gal(int pass, int nc, const int *__restrict__ rp, const int *__restrict__ ci,
-      const double *__restrict__ v, const int *__restrict__ agg, const double *__restrict__ p,
-      const int *__restrict__ mem2, int *__restrict__ cnt, const int *__restrict__ crp,
-      int *__restrict__ cci, double *__restrict__ cv, int *__restrict__ gF, int *__restrict__ gU) {
-    constexpr int LMAX = 16 * G;
-    constexpr int NG = kBlock / G;
-    __shared__ int sF[NG * LMAX];
-    __shared__ int sU[NG * LMAX];
-    const int g = threadIdx.x / G, lane = threadIdx.x % G;
-    const int E = xcd_block(blockIdx.x, gridDim.x) * NG + g;
-    if (E >= nc) return;
-    const int e0 = mem2[2 * E], e1 = mem2[2 * E + 1];
-    const int s0 = rp[e0], L0 = rp[e0 + 1] - s0;
-    const int s1 = e1 >= 0 ? rp[e1] : 0;
-    const int L1 = e1 >= 0 ? rp[e1 + 1] - s1 : 0;
+__device__ __forceinline__ void gal_row(int pass, int E, int lane, const int *__restrict__ rp,
+                                        const int *__restrict__ ci, const double *__restrict__ v,
+                                        const int *__restrict__ agg, const double *__restrict__ p, int e0, int e1,
+                                        int s0, int L0, int s1, int L1, int *__restrict__ cnt,
+                                        const int *__restrict__ crp, int *__restrict__ cci, double *__restrict__ cv,
+                                        int *F, int *U, bool staged) {
     const int L = L0 + L1;
-    const bool staged = L <= LMAX;
-    int *F = staged ? sF + g * LMAX : gF;
-    int *U = staged ? sU + g * LMAX : gU;
     // slot of candidate k: LDS index, or its position in A (disjoint per coarse row)
     auto slot = [&](int k) { return staged ? k : (k < L0 ? s0 + k : s1 + (k - L0)); };
     for (int k = lane; k < L; k += G) {
@@ -527,12 +673,21 @@ void launch_weights(hipStream_t s, int G, int n, const int *rp, const int *ci, c
     });
 }
 
-void launch_candidates(hipStream_t s, int G, int n, const int *rp, const int *ci, const double *c,
-                       unsigned long long *cand, int *pos) {
+// Rows of a few dozen entries count directly (one kernel); longer rows sort
+// (k_rank + k_candidates: O(d log d) per row instead of O(d^2)).
+void launch_candidates(hipStream_t s, int G, int n, int nnz, const int *rp, const int *ci, const double *c,
+                       unsigned *rk, unsigned long long *cand, int *pos) {
+    const bool sorted = nnz >= (long long)kSortedCandidatesAvg * n;
     with_G(G, [&](auto gc) {
         constexpr int g = decltype(gc)::value;
+        if (!sorted) {
+            hipLaunchKernelGGL(k_candidates_direct<g>, dim3(blocks_for((long long)n * g)), dim3(kBlock), 0, s, n, rp,
+                               ci, c, cand, pos);
+            return;
+        }
+        hipLaunchKernelGGL(k_rank<g>, dim3(blocks_for((long long)n * g)), dim3(kBlock), 0, s, n, rp, c, rk);
         hipLaunchKernelGGL(k_candidates<g>, dim3(blocks_for((long long)n * g)), dim3(kBlock), 0, s, n, rp, ci, c,
-                           cand, pos);
+                           rk, cand, pos);
     });
 }
 
@@ -550,22 +705,143 @@ void launch_aggfill(hipStream_t s, int n, const int *mate, const int *ofs, const
     hipLaunchKernelGGL(k_aggfill, dim3(blocks_for(n)), dim3(kBlock), 0, s, n, mate, ofs, w, agg, p, wc, mem2);
 }
 
+template <int G>
+__global__ void __launch_bounds__(kBlock)
+k_gal(int pass, int nc, const int *__restrict__ rp, const int *__restrict__ ci,
+      const double *__restrict__ v, const int *__restrict__ agg, const double *__restrict__ p,
+      const int *__restrict__ mem2, int *__restrict__ cnt, const int *__restrict__ crp,
+      int *__restrict__ cci, double *__restrict__ cv, int *__restrict__ gF, int *__restrict__ gU) {
+    constexpr int LMAX = 16 * G;
+    constexpr int NG = kBlock / G;
+    __shared__ int sF[NG * LMAX];
+    __shared__ int sU[NG * LMAX];
+    const int g = threadIdx.x / G, lane = threadIdx.x % G;
+    const int E = xcd_block(blockIdx.x, gridDim.x) * NG + g;
+    if (E >= nc) return;
+    const int e0 = mem2[2 * E], e1 = mem2[2 * E + 1];
+    const int s0 = rp[e0], L0 = rp[e0 + 1] - s0;
+    const int s1 = e1 >= 0 ? rp[e1] : 0;
+    const int L1 = e1 >= 0 ? rp[e1 + 1] - s1 : 0;
+    const bool staged = L0 + L1 <= LMAX;
+    gal_row<G>(pass, E, lane, rp, ci, v, agg, p, e0, e1, s0, L0, s1, L1, cnt, crp, cci, cv,
+               staged ? sF + g * LMAX : gF, staged ? sU + g * LMAX : gU, staged);
+}
+
+// Galerkin product for long rows: the same entries and sums as k_gal, with the
+// candidate columns of a coarse row sorted in LDS as (F << 32 | candidate)
+// instead of compared pairwise.  Equal columns are then adjacent (at most four
+// candidates each), the distinct columns come out in ascending order, and a
+// scan over the group's lanes gives each column its position in the row.
+// Rows with more candidates than the LDS slots use k_gal's scratch path.
+template <int G>
+__global__ void __launch_bounds__(kBlock)
+k_gal_sorted(int pass, int nc, const int *__restrict__ rp, const int *__restrict__ ci,
+             const double *__restrict__ v, const int *__restrict__ agg, const double *__restrict__ p,
+             const int *__restrict__ mem2, int *__restrict__ cnt, const int *__restrict__ crp,
+             int *__restrict__ cci, double *__restrict__ cv, int *__restrict__ gF, int *__restrict__ gU) {
+    constexpr int LMAX = 16 * G;
+    constexpr int NG = kBlock / G;
+    __shared__ unsigned long long sk[NG * LMAX];
+    const int g = threadIdx.x / G, lane = threadIdx.x % G;
+    const int E = xcd_block(blockIdx.x, gridDim.x) * NG + g;
+    if (E >= nc) return;
+    const int e0 = mem2[2 * E], e1 = mem2[2 * E + 1];
+    const int s0 = rp[e0], L0 = rp[e0 + 1] - s0;
+    const int s1 = e1 >= 0 ? rp[e1] : 0;
+    const int L1 = e1 >= 0 ? rp[e1 + 1] - s1 : 0;
+    const int L = L0 + L1;
+    if (L > LMAX) {  // more candidates than LDS slots: k_gal's scratch path
+        gal_row<G>(pass, E, lane, rp, ci, v, agg, p, e0, e1, s0, L0, s1, L1, cnt, crp, cci, cv, gF, gU, false);
+        return;
+    }
+    unsigned long long *keys = sk + g * LMAX;
+    const int P = pow2_at_least(L);
+    for (int k = lane; k < P; k += G) {
+        unsigned long long key = ~0ull;
+        if (k < L) {
+            const int q = k < L0 ? s0 + k : s1 + (k - L0);
+            key = ((unsigned long long)(unsigned)agg[ci[q]] << 32) | (unsigned)k;
+        }
+        keys[k] = key;
+    }
+    wave_sync();
+    group_sort<G>(keys, P, lane);
+    auto col = [&](int k) { return (int)(keys[k] >> 32); };
+    auto starts = [&](int k) { return k < L && (k == 0 || col(k) != col(k - 1)); };
+    // contiguous chunk of sorted positions per lane; exclusive scan of segment starts
+    const int C = (L + G - 1) / G;
+    const int k0 = min(lane * C, L), k1 = min(k0 + C, L);
+    int mine = 0;
+    for (int k = k0; k < k1; ++k) mine += starts(k) ? 1 : 0;
+    int incl = mine;
+    for (int o = 1; o < G; o <<= 1) {
+        const int t = __shfl_up(incl, o, G);
+        if (lane >= o) incl += t;
+    }
+    if (pass == 0) {
+        if (lane == G - 1) cnt[E] = incl;
+        return;
+    }
+    int rank = incl - mine;
+    const int base = crp[E];
+    const unsigned long long NONE = ~0ull;
+    for (int k = k0; k < k1; ++k) {
+        if (!starts(k)) continue;
+        const int f = col(k);
+        unsigned long long key[4];
+        double t[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            key[r] = NONE;
+            t[r] = 0.0;
+            const int kk = k + r;
+            if (kk >= L || col(kk) != f) continue;
+            const int cidx = (int)(keys[kk] & 0xffffffffull);
+            const int q = cidx < L0 ? s0 + cidx : s1 + (cidx - L0);
+            const int i = cidx < L0 ? e0 : e1, j = ci[q];
+            const int m = min(i, j), M = max(i, j);
+            key[r] = ((unsigned long long)(unsigned)m << 32) | (unsigned)M;
+            t[r] = (p[m] * v[q]) * p[M];
+        }
+        cswap(key[0], t[0], key[1], t[1]);
+        cswap(key[2], t[2], key[3], t[3]);
+        cswap(key[0], t[0], key[2], t[2]);
+        cswap(key[1], t[1], key[3], t[3]);
+        cswap(key[1], t[1], key[2], t[2]);
+        double sum = t[0];
+#pragma unroll
+        for (int r = 1; r < 4; ++r)
+            if (key[r] != NONE) sum = sum + t[r];
+        cci[base + rank] = f;
+        cv[base + rank] = sum;
+        ++rank;
+    }
+}
+
 void launch_gal_count(hipStream_t s, int G, int nc, const int *rp, const int *ci, const int *agg,
-                      const int *mem2, int *cnt, int *gF, int *gU) {
+                      const int *mem2, int *cnt, int *gF, int *gU, bool sorted) {
     with_G(G, [&](auto gc) {
         constexpr int g = decltype(gc)::value;
-        hipLaunchKernelGGL(k_gal<g>, dim3(blocks_for((long long)nc * g)), dim3(kBlock), 0, s, 0, nc, rp, ci,
-                           nullptr, agg, nullptr, mem2, cnt, nullptr, nullptr, nullptr, gF, gU);
+        if (sorted)
+            hipLaunchKernelGGL(k_gal_sorted<g>, dim3(blocks_for((long long)nc * g)), dim3(kBlock), 0, s, 0, nc, rp, ci,
+                               nullptr, agg, nullptr, mem2, cnt, nullptr, nullptr, nullptr, gF, gU);
+        else
+            hipLaunchKernelGGL(k_gal<g>, dim3(blocks_for((long long)nc * g)), dim3(kBlock), 0, s, 0, nc, rp, ci,
+                               nullptr, agg, nullptr, mem2, cnt, nullptr, nullptr, nullptr, gF, gU);
     });
 }
 
 void launch_gal_fill(hipStream_t s, int G, int nc, const int *rp, const int *ci, const double *v,
                      const int *agg, const double *p, const int *mem2, const int *crp, int *cci,
-                     double *cv, int *gF, int *gU) {
+                     double *cv, int *gF, int *gU, bool sorted) {
     with_G(G, [&](auto gc) {
         constexpr int g = decltype(gc)::value;
-        hipLaunchKernelGGL(k_gal<g>, dim3(blocks_for((long long)nc * g)), dim3(kBlock), 0, s, 1, nc, rp, ci, v,
-                           agg, p, mem2, nullptr, crp, cci, cv, gF, gU);
+        if (sorted)
+            hipLaunchKernelGGL(k_gal_sorted<g>, dim3(blocks_for((long long)nc * g)), dim3(kBlock), 0, s, 1, nc, rp, ci,
+                               v, agg, p, mem2, nullptr, crp, cci, cv, gF, gU);
+        else
+            hipLaunchKernelGGL(k_gal<g>, dim3(blocks_for((long long)nc * g)), dim3(kBlock), 0, s, 1, nc, rp, ci, v,
+                               agg, p, mem2, nullptr, crp, cci, cv, gF, gU);
     });
 }
 

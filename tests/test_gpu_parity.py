@@ -270,6 +270,44 @@ def test_lane_width_and_sell_settings(B, ora, name, scale, group, sell):
     assert abs(h.info()["iters"] - io["iters"]) <= 1
 
 
+def _cliques_and_hubs(nb=120, b=30, hubs=3, hub_deg=700, seed=5):
+    # dense diagonal blocks (average row length >= 24: the sort-based rank,
+    # candidate and Galerkin kernels) plus hub rows much longer than any lane
+    # group's LDS slots (their direct-counting fallbacks)
+    rng = np.random.default_rng(seed)
+    n = nb * b + hubs
+    rows, cols, vals = [], [], []
+    for k in range(nb):
+        idx = np.arange(k * b, (k + 1) * b)
+        I, J = np.meshgrid(idx, idx, indexing="ij")
+        off = I != J
+        rows.append(I[off]); cols.append(J[off])
+        vals.append(-rng.uniform(0.5, 1.5, off.sum()))
+    for h in range(hubs):
+        hub = nb * b + h
+        nbrs = rng.choice(nb * b, hub_deg, replace=False)
+        a = -rng.uniform(0.2, 0.8, hub_deg)
+        rows += [np.full(hub_deg, hub), nbrs]; cols += [nbrs, np.full(hub_deg, hub)]; vals += [a, a]
+    A = sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))), shape=(n, n)).tocsr()
+    A = (A + A.T) * 0.5
+    A = A + sp.diags(np.asarray(abs(A).sum(axis=1)).ravel() + 1.0)
+    A = A.tocsr()
+    A.sort_indices()
+    return A.indptr.astype(np.int32), A.indices.astype(np.int32), A.data.copy()
+
+
+@pytest.mark.parametrize("group", [0, 4, 16])
+def test_hierarchy_dense_blocks_and_hub_rows(B, ora, group):
+    rp, ci, va = _cliques_and_hubs()
+    n = len(rp) - 1
+    assert len(ci) >= 24 * n and np.diff(rp).max() > 16 * 32
+    say(f"dense blocks and hubs n={n} nnz={len(ci)} group={group}")
+    h = B.Hierarchy(rp, ci, va, max_coarse=40, group=group)
+    ho = ora.Hierarchy(rp, ci, va, np.ones(n), max_coarse=40)
+    _compare_hierarchy(h, ho)
+    h.close()
+
+
 def test_sell_int32_columns_for_long_range_couplings(B, ora):
     # offsets |col - row| beyond int16: the sliced-ELL copies keep int32 columns
     rp, ci, va = P.random_spd(70000, 4e-5, 23)
