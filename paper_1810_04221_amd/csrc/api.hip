@@ -179,10 +179,9 @@ int match_sweep(hipStream_t s, Arena &tmp, const Csr &A, const double *w, int ch
     unsigned long long *cand = tmp.get_n<unsigned long long>(A.nnz);
     unsigned *rk = tmp.get_n<unsigned>(A.nnz);
     unsigned long long *ws = tmp.get_n<unsigned long long>(m);
-    int *pos = tmp.get_n<int>(m);
     int *mate = tmp.get_n<int>(m);
     int *leader = tmp.get_n<int>(m);
-    NOMEM(diag && flags && c && cand && rk && ws && pos && mate && leader);
+    NOMEM(diag && flags && c && cand && rk && ws && mate && leader);
     launch_fill_i32(s, 1, flags, 0);
     launch_validate(s, G, m, A.nnz_dev ? -1 : A.nnz, A.rp, A.ci, A.v, w, check_sym, diag, flags);
     if (!flags_dev) {
@@ -195,10 +194,10 @@ int match_sweep(hipStream_t s, Arena &tmp, const Csr &A, const double *w, int ch
         }
     }
     launch_weights(s, G, m, A.rp, A.ci, A.v, diag, w, c);
-    launch_candidates(s, G, m, A.nnz, A.rp, A.ci, c, rk, cand, pos);
+    launch_candidates(s, G, m, A.nnz, A.rp, A.ci, c, rk, cand);
     launch_fill_u64(s, m, ws, 0ull);
-    launch_suitor(s, m, A.rp, cand, pos, ws);
-    launch_mate(s, m, ws, mate, leader);
+    launch_suitor(s, m, A.rp, cand, ws);
+    launch_mate(s, m, A.rp, A.ci, ws, mate, leader);
     HIPCHK(hipGetLastError());
     *mate_out = mate;
     *leader_out = leader;

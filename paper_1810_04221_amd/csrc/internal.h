@@ -176,10 +176,10 @@ void launch_weights(hipStream_t s, int G, int n, const int *rp, const int *ci, c
 // entries per row sort each row (own-row ranks in rk[nnz], scratch)
 constexpr int kSortedCandidatesAvg = 24;
 void launch_candidates(hipStream_t s, int G, int n, int nnz, const int *rp, const int *ci, const double *c,
-                       unsigned *rk, unsigned long long *cand, int *pos);
-void launch_suitor(hipStream_t s, int n, const int *rp, const unsigned long long *cand, int *pos,
-                   unsigned long long *ws);
-void launch_mate(hipStream_t s, int n, const unsigned long long *ws, int *mate, int *leader);
+                       unsigned *rk, unsigned long long *cand);
+void launch_suitor(hipStream_t s, int n, const int *rp, const unsigned long long *cand, unsigned long long *ws);
+void launch_mate(hipStream_t s, int n, const int *rp, const int *ci, const unsigned long long *ws, int *mate,
+                 int *leader);
 void launch_aggfill(hipStream_t s, int n, const int *mate, const int *ofs, const double *w,
                     int *agg, double *p, double *wc, int *mem2);
 void launch_gal_count(hipStream_t s, int G, int nc, const int *rp, const int *ci, const int *agg,

@@ -120,7 +120,7 @@ k_weights(int n, const int *__restrict__ rp, const int *__restrict__ ci, const d
 template <int G>
 __global__ void __launch_bounds__(kBlock)
 k_candidates_direct(int n, const int *__restrict__ rp, const int *__restrict__ ci, const double *__restrict__ c,
-                    unsigned long long *__restrict__ cand, int *__restrict__ pos) {
+                    unsigned long long *__restrict__ cand) {
     const int lane = threadIdx.x % G;
     const int row = (xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x) / G;
     if (row >= n) return;
@@ -141,11 +141,10 @@ k_candidates_direct(int n, const int *__restrict__ rp, const int *__restrict__ c
             const bool elig = vt != row && ct > 0.0 && ct < INFINITY;
             before += (elig && (ct > cq || (ct == cq && vt > vtx))) ? 1 : 0;
         }
-        cand[s0 + before] = ((unsigned long long)rk << 32) | (unsigned)vtx;
+        if (s0 + before < e - 1) cand[s0 + before] = ((unsigned long long)rk << 32) | (unsigned)vtx;
     }
-    nelig = group_sum<G>(nelig);
+    nelig = min(group_sum<G>(nelig), max(e - s0 - 1, 0));
     for (int q = s0 + nelig + lane; q < e; q += G) cand[q] = ~0ull;
-    if (lane == 0) pos[row] = s0;
 }
 
 // ----------------------------------------------------------------------------
@@ -234,16 +233,19 @@ k_rank(int n, const int *__restrict__ rp, const double *__restrict__ c, unsigned
 //   cand = rk << 32 | v,   rk = #{ entries t of row v : c[t] < c_uv }
 // where rk is the position of c_uv among the weights seen from v (the own-row
 // rank of the transposed entry, c being the same double from both ends).  A
-// proposal from u to v then compares at v as (rk << 32 | u + 1), which orders
-// proposals exactly as (c_uv, u).  After the eligible entries the row holds
-// the sentinel ~0.  pos[u] = row start.  The preference order is a sort of
+// proposal from u to v then compares at v as (rk << 32 | t + 1), t being the
+// slot of v in u's list: slots grow with u (rows are stored in order), so this
+// orders proposals exactly as (c_uv, u).  After the eligible entries the row
+// holds the sentinel ~0, at least in its last slot (the diagonal is never
+// eligible; a row without one drops its last candidate, which validation
+// rejects anyway).  The preference order is a sort of
 // (own-row rank desc, v desc) in LDS; rows longer than the LDS slots are
 // placed by direct counting.
 // ----------------------------------------------------------------------------
 template <int G>
 __global__ void __launch_bounds__(kBlock)
 k_candidates(int n, const int *__restrict__ rp, const int *__restrict__ ci, const double *__restrict__ c,
-             const unsigned *__restrict__ rk_own, unsigned long long *__restrict__ cand, int *__restrict__ pos) {
+             const unsigned *__restrict__ rk_own, unsigned long long *__restrict__ cand) {
     constexpr int LMAX = 16 * G;
     constexpr int NG = kBlock / G;
     __shared__ unsigned long long sk[NG * LMAX];
@@ -279,7 +281,7 @@ k_candidates(int n, const int *__restrict__ rp, const int *__restrict__ ci, cons
         }
         wave_sync();
         group_sort<G>(keys, P, lane);
-        nelig = group_sum<G>(nelig);
+        nelig = min(group_sum<G>(nelig), d - 1);
         for (int k = lane; k < d; k += G) {
             unsigned long long out = ~0ull;
             if (k < nelig) {
@@ -302,66 +304,72 @@ k_candidates(int n, const int *__restrict__ rp, const int *__restrict__ ci, cons
                 const bool elig = vt != row && ct > 0.0 && ct < INFINITY;
                 before += (elig && (ct > cq || (ct == cq && vt > vtx))) ? 1 : 0;
             }
-            cand[s0 + before] = ((unsigned long long)rank_at(vtx) << 32) | (unsigned)vtx;
+            if (before < d - 1) cand[s0 + before] = ((unsigned long long)rank_at(vtx) << 32) | (unsigned)vtx;
         }
-        nelig = group_sum<G>(nelig);
+        nelig = min(group_sum<G>(nelig), d - 1);
         for (int q = s0 + nelig + lane; q < e; q += G) cand[q] = ~0ull;
     }
-    if (lane == 0) pos[row] = s0;
 }
 
 // ----------------------------------------------------------------------------
 // Suitor matching (Section 3.1).  One thread per vertex holds that vertex's
-// proposal.  Vertex u walks its candidate list from its resume position and
-// proposes to each candidate v in turn until one accepts; ws[v] holds the key
-// (rk << 32 | proposer + 1) of v's best proposal so far and is raised with
-// atomicMax, whose old value says whether u won.  A displaced proposer is
-// taken over by the displacing thread and resumes after the candidate it lost:
-// ws[] only grows, so every candidate it passed stays unavailable.  A stale
-// resume position only rescans.  Every successful atomicMax strictly raises
-// one ws[] entry (finitely many times) and a failed one moves u to its next
-// candidate, so the total number of loop trips is bounded and every thread
-// exits.  The final suitor pairs are mutual and equal the greedy matching
-// under (c desc, larger endpoint desc, smaller desc).
+// proposal.  A proposal is the candidate slot t of u's list (cand[t] names v);
+// u proposes to each candidate in turn until one accepts.  ws[v] holds the key
+// (rk << 32 | t + 1) of v's best proposal so far and is raised with atomicMax,
+// whose old value says whether u won.  A displaced proposal is taken over by
+// the displacing thread and resumes at the slot after the one it lost (its
+// key holds that slot, so no per-vertex position is kept): ws[] only grows,
+// so every candidate it passed stays unavailable.  One proposal step is thus
+// an atomic and the load of the next candidate.  Every successful atomicMax
+// strictly raises one ws[] entry (finitely many times) and a failed one moves
+// to the next slot, which ends at the row's sentinel, so every thread exits.
+// The final suitor pairs are mutual and equal the greedy matching under
+// (c desc, larger endpoint desc, smaller desc).
 // ----------------------------------------------------------------------------
 __global__ void __launch_bounds__(kBlock)
-k_suitor(int n, const int *__restrict__ rp, const unsigned long long *__restrict__ cand, int *pos,
-         unsigned long long *ws) {
+k_suitor(int n, const int *__restrict__ rp, const unsigned long long *__restrict__ cand, unsigned long long *ws) {
     // Highest vertices first: workgroups are dispatched roughly in index order,
     // and the greedy order settles large indices first on equal weights.  (Cut
     // into several launches, highest chunk first, this ran slower.)
-    const int u0 = n - 1 - (int)(blockIdx.x * kBlock + threadIdx.x);
-    if (u0 < 0) return;
-    int u = u0;
-    int t = rp[u], end = rp[u + 1];
+    const int u = n - 1 - (int)(blockIdx.x * kBlock + threadIdx.x);
+    if (u < 0) return;
+    int t = rp[u];
+    if (t == rp[u + 1]) return;  // empty row: no slot of its own
     for (;;) {
-        // u's next candidate; ws[v] is not read first: the atomic itself tells
-        // whether u lost, and a read would add a memory round trip per proposal
-        if (t >= end) break;
+        // ws[v] is not read first: the atomic itself tells whether the proposal
+        // lost, and a read would add a memory round trip per step
         const unsigned long long e = cand[t];
-        if (e == ~0ull) break;  // no candidate left: u stays unmatched
-        const unsigned long long key = (e & 0xffffffff00000000ull) | (unsigned long long)(unsigned)(u + 1);
+        if (e == ~0ull) break;  // no candidate left: this vertex stays unmatched
+        const unsigned long long key = (e & 0xffffffff00000000ull) | (unsigned long long)(unsigned)(t + 1);
         const int v = (int)(e & 0xffffffffull);
-        __hip_atomic_store(&pos[u], t + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         const unsigned long long old = atomicMax(&ws[v], key);
-        if (old > key) { ++t; continue; }  // lost v for good (ws only grows): next candidate
-        if (old == 0ull) break;   // v had no suitor: done
-        u = (int)(old & 0xffffffffull) - 1;  // displaced suitor resumes its list
-        end = rp[u + 1];
-        const int p0 = __hip_atomic_load(&pos[u], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        t = min(max(p0, rp[u]), end);
+        if (old > key) { ++t; continue; }  // lost v for good (ws only grows): next slot
+        if (old == 0ull) break;            // v had no suitor: done
+        t = (int)(old & 0xffffffffull);    // displaced proposal (slot old - 1) resumes after it
     }
 }
 
 // mate[i] = s if i and its suitor s chose each other; leader[i] marks the
 // smallest member of each aggregate of Algorithm 2.
 __global__ void __launch_bounds__(kBlock)
-k_mate(int n, const unsigned long long *__restrict__ ws, int *__restrict__ mate, int *__restrict__ leader) {
+k_mate(int n, const int *__restrict__ rp, const int *__restrict__ ci, const unsigned long long *__restrict__ ws,
+       int *__restrict__ mate, int *__restrict__ leader) {
     const int i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
-    const int s = (int)(ws[i] & 0xffffffffull) - 1;
+    // the suitor of i is the neighbour whose row holds the winning slot ts:
+    // the last neighbour j of i with rp[j] <= ts (columns ascending, rp monotone)
+    const int ts = (int)(ws[i] & 0xffffffffull) - 1;
     int m = -1;
-    if (s >= 0 && (int)(ws[s] & 0xffffffffull) - 1 == i) m = s;
+    if (ts >= 0 && rp[i] < rp[i + 1]) {
+        int lo = rp[i], hi = rp[i + 1] - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (rp[ci[mid]] <= ts) lo = mid; else hi = mid - 1;
+        }
+        const int s = ci[lo];
+        const int tb = (int)(ws[s] & 0xffffffffull) - 1;
+        if (ts >= rp[s] && ts < rp[s + 1] && tb >= rp[i] && tb < rp[i + 1]) m = s;
+    }
     mate[i] = m;
     leader[i] = (m < 0 || i < m) ? 1 : 0;
 }
@@ -676,28 +684,28 @@ void launch_weights(hipStream_t s, int G, int n, const int *rp, const int *ci, c
 // Rows of a few dozen entries count directly (one kernel); longer rows sort
 // (k_rank + k_candidates: O(d log d) per row instead of O(d^2)).
 void launch_candidates(hipStream_t s, int G, int n, int nnz, const int *rp, const int *ci, const double *c,
-                       unsigned *rk, unsigned long long *cand, int *pos) {
+                       unsigned *rk, unsigned long long *cand) {
     const bool sorted = nnz >= (long long)kSortedCandidatesAvg * n;
     with_G(G, [&](auto gc) {
         constexpr int g = decltype(gc)::value;
         if (!sorted) {
             hipLaunchKernelGGL(k_candidates_direct<g>, dim3(blocks_for((long long)n * g)), dim3(kBlock), 0, s, n, rp,
-                               ci, c, cand, pos);
+                               ci, c, cand);
             return;
         }
         hipLaunchKernelGGL(k_rank<g>, dim3(blocks_for((long long)n * g)), dim3(kBlock), 0, s, n, rp, c, rk);
         hipLaunchKernelGGL(k_candidates<g>, dim3(blocks_for((long long)n * g)), dim3(kBlock), 0, s, n, rp, ci, c,
-                           rk, cand, pos);
+                           rk, cand);
     });
 }
 
-void launch_suitor(hipStream_t s, int n, const int *rp, const unsigned long long *cand, int *pos,
-                   unsigned long long *ws) {
-    hipLaunchKernelGGL(k_suitor, dim3(blocks_for(n)), dim3(kBlock), 0, s, n, rp, cand, pos, ws);
+void launch_suitor(hipStream_t s, int n, const int *rp, const unsigned long long *cand, unsigned long long *ws) {
+    hipLaunchKernelGGL(k_suitor, dim3(blocks_for(n)), dim3(kBlock), 0, s, n, rp, cand, ws);
 }
 
-void launch_mate(hipStream_t s, int n, const unsigned long long *ws, int *mate, int *leader) {
-    hipLaunchKernelGGL(k_mate, dim3(blocks_for(n)), dim3(kBlock), 0, s, n, ws, mate, leader);
+void launch_mate(hipStream_t s, int n, const int *rp, const int *ci, const unsigned long long *ws, int *mate,
+                 int *leader) {
+    hipLaunchKernelGGL(k_mate, dim3(blocks_for(n)), dim3(kBlock), 0, s, n, rp, ci, ws, mate, leader);
 }
 
 void launch_aggfill(hipStream_t s, int n, const int *mate, const int *ofs, const double *w, int *agg,
