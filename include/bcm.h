@@ -113,6 +113,12 @@ typedef struct {
  *   sell           1     sliced-ELL copies (64-row slices) of the finest level
  *                        and of levels >= 65536 rows for the row-parallel solve
  *                        kernels; 0 = CSR row kernels everywhere
+ *   fold           1     V-cycle: the cycle from the first level k >= 1 with at
+ *                        most 2048 rows down to the coarsest (a fixed linear
+ *                        map, pre = post = 1) is formed once in float64 at
+ *                        setup and applied as one dense product; the same
+ *                        operator as the level-by-level cycle up to rounding,
+ *                        also under BCM_FP32_CYCLE.  0 = level by level.
  */
 typedef struct {
     int32_t max_levels;
@@ -130,6 +136,7 @@ typedef struct {
     int32_t graph;
     int32_t group;
     int32_t sell;
+    int32_t fold;
     double adjoint_tol;
     double min_ratio;
     void *(*alloc)(size_t bytes, void *ctx);

@@ -34,7 +34,7 @@ class BcmParams(C.Structure):
                 ("coarse_sweeps", C.c_int32), ("pre", C.c_int32), ("post", C.c_int32), ("cycle", C.c_int32),
                 ("kcycle_levels", C.c_int32), ("precision", C.c_int32), ("itmax", C.c_int32),
                 ("check", C.c_int32), ("profile", C.c_int32), ("graph", C.c_int32), ("group", C.c_int32),
-                ("sell", C.c_int32), ("adjoint_tol", C.c_double), ("min_ratio", C.c_double), ("alloc", ALLOC_FN),
+                ("sell", C.c_int32), ("fold", C.c_int32), ("adjoint_tol", C.c_double), ("min_ratio", C.c_double), ("alloc", ALLOC_FN),
                 ("dealloc", DEALLOC_FN), ("alloc_ctx", C.c_void_p), ("stream", C.c_void_p)]
 
 
@@ -123,12 +123,12 @@ class _TorchAllocator:
 
 def make_params(precision="fp64", max_levels=40, max_coarse=0, sweeps=2, coarse_sweeps=20, itmax=5000,
                 check=True, adjoint_tol=0.0, profile=0, stream=None, allocator=None, cycle="V",
-                graph=False, kcycle_levels=0, group=0, sell=True, min_ratio=0.0) -> BcmParams:
+                graph=False, kcycle_levels=0, group=0, sell=True, min_ratio=0.0, fold=True) -> BcmParams:
     p = BcmParams()
     load_library().bcm_default_params(C.byref(p))
     p.cycle = CYCLES[cycle]
     p.kcycle_levels = kcycle_levels
-    p.group, p.sell = group, int(bool(sell))
+    p.group, p.sell, p.fold = group, int(bool(sell)), int(bool(fold))
     p.min_ratio = float(min_ratio)
     p.graph = int(bool(graph))
     p.max_levels, p.max_coarse, p.sweeps, p.coarse_sweeps = max_levels, max_coarse, sweeps, coarse_sweeps
@@ -147,7 +147,7 @@ class Hierarchy:
 
     def __init__(self, rowptr, col, val, w=None, *, precision="fp64", max_levels=40, max_coarse=0, sweeps=2,
                  coarse_sweeps=20, itmax=5000, check=True, adjoint_tol=0.0, profile=0, device=None, cycle="V",
-                 graph=False, kcycle_levels=0, group=0, sell=True, min_ratio=0.0):
+                 graph=False, kcycle_levels=0, group=0, sell=True, min_ratio=0.0, fold=True):
         L = _gpu_lib()
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         self.stream = torch.cuda.current_stream(self.device).cuda_stream
@@ -160,7 +160,7 @@ class Hierarchy:
         self._alloc = _TorchAllocator(self.device, self.stream)
         self.params = make_params(precision, max_levels, max_coarse, sweeps, coarse_sweeps, itmax, check,
                                   adjoint_tol, profile, self.stream, self._alloc, cycle, graph, kcycle_levels,
-                                  group, sell, min_ratio)
+                                  group, sell, min_ratio, fold)
         A = BcmCsr(self.n, self.nnz, self.rowptr.data_ptr(), self.col.data_ptr(), self.val.data_ptr())
         h = C.c_void_p()
         _check(L.bcm_setup(C.byref(A), C.c_void_p(w.data_ptr()), C.byref(self.params), C.byref(h)))

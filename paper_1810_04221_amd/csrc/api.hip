@@ -538,7 +538,29 @@ int build_hierarchy(bcm_handle *h, const bcm_csr *Ain, const double *win) {
             launch_coarse_build(s, C, P.coarse_sweeps, C.S);
         }
     }
-    {
+    if (P.fold && P.cycle == BCM_VCYCLE && h->nl >= 3 && h->lv[h->nl - 1].S) {
+        // V-cycle: the levels from the first k >= 1 with at most kFoldRows rows
+        // down to the coarsest, formed once as one dense operator (built upwards
+        // from the coarsest level's sweep operator)
+        int kf = h->nl - 1;
+        while (kf > 1 && h->lv[kf - 1].A.n <= kFoldRows) --kf;
+        if (kf < h->nl - 1) {
+            tmp.rewind();
+            const double *Tc = h->lv[h->nl - 1].S;
+            for (int k = h->nl - 2; k >= kf; --k) {
+                const Level &L = h->lv[k];
+                const size_t nn2 = (size_t)L.A.n * L.A.n;
+                double *T = k == kf ? h->persist.get_n<double>(nn2) : tmp.get_n<double>(nn2);
+                double *H = tmp.get_n<double>(nn2);
+                NOMEM(T && H);
+                launch_fold_level(s, L, Tc, h->lv[k + 1].A.n, H, T);
+                Tc = T;
+            }
+            h->kf = kf;
+            h->fold = const_cast<double *>(Tc);
+        }
+    }
+    if (h->kf == 0) {
         // tail kernel: the smallest levels (and the coarsest solve) in one workgroup
         int kt = h->nl - 1;
         while (kt > 1 && h->lv[kt - 1].A.n <= kTailRows) --kt;
@@ -683,12 +705,22 @@ double bytes_coarse(const bcm_handle *h) {
     const double sb = (h->nl == 1 || h->prm.precision != BCM_FP32_CYCLE) ? 8 : 4;
     return 4 * (n + 1) + 12 * z + 8 * n + 2 * sb * n;
 }
+// the folded operator: every entry once, b in and x out
+double bytes_fold(const bcm_handle *h) {
+    const double n = h->lv[h->kf].A.n;
+    const double sb = h->prm.precision == BCM_FP32_CYCLE ? 4 : 8;
+    return 8 * n * n + 2 * sb * n;
+}
 // one preconditioner application: every level's legs times the number of
 // times the level is visited (doubling below each W- or K-accelerated level),
 // plus the W residual/add and the K-cycle products and combinations
 double bytes_cycle(const bcm_handle *h) {
     const double sv = h->prm.precision == BCM_FP32_CYCLE ? 4 : 8;
     double total = 0.0, visits = 1.0;
+    if (h->kf > 0) {
+        for (int k = 0; k < h->kf; ++k) total += bytes_down(h, k) + bytes_up(h, k);
+        return total + bytes_fold(h);
+    }
     for (int k = 0; k + 1 < h->nl; ++k) {
         total += visits * (bytes_down(h, k) + bytes_up(h, k));
         const Level &C = h->lv[k + 1];
@@ -719,6 +751,7 @@ double class_bytes(const bcm_handle *h, int cls) {
     case 2: return bytes_spmv_dots(h);
     case 3: return bytes_update(h);
     default: {
+        if (h->kf > 0) return bytes_fold(h);
         double by = bytes_coarse(h);
         const int kt = h->kt > 0 ? h->kt : h->nl - 1;
         for (int k = kt; k < h->nl - 1; ++k) by += bytes_down(h, k) + bytes_up(h, k);
@@ -894,7 +927,8 @@ void vcycle(bcm_handle *h, Prof &pf, const double *rin, double *wout, const doub
         pf.end(1, e, class_bytes(h, 1), iter);
         return;
     }
-    const int kt = h->kt > 0 ? h->kt : nl - 1;
+    // levels below kt: the folded operator, the tail kernel, or the coarsest solve
+    const int kt = h->kf > 0 ? h->kf : (h->kt > 0 ? h->kt : nl - 1);
     for (int k = 0; k < kt; ++k) {
         Level &L = h->lv[k];
         const void *bk = k == 0 ? (const void *)rin : L.b;
@@ -912,7 +946,9 @@ void vcycle(bcm_handle *h, Prof &pf, const double *rin, double *wout, const doub
     }
     {
         int e = pf.begin(4);
-        if (h->kt > 0) {
+        if (h->kf > 0) {
+            launch_dense(s, h->lv[kt].A.n, h->fold, h->lv[kt].b, h->lv[kt].x, !fp32, !fp32, done);
+        } else if (h->kt > 0) {
             launch_tail(s, fp32, kt, nl, h->tail, C, cs, h->tail_ops, h->n_tail_ops, h->lv[kt].x, done);
         } else {
             launch_coarse(s, C, cs, C.b, C.x, !fp32, !fp32, h->ctmp[0], h->ctmp[1], done);
@@ -1145,6 +1181,7 @@ void bcm_default_params(bcm_params *p) {
     p->graph = 0;
     p->group = 0;
     p->sell = 1;
+    p->fold = 1;
     p->adjoint_tol = 0.0;
     p->min_ratio = 0.0;
 }
@@ -1161,10 +1198,10 @@ int bcm_setup(const bcm_csr *A, const double *w, const bcm_params *p, bcm_handle
     if (p) prm = *p; else bcm_default_params(&prm);
     if (prm.max_levels < 1 || prm.sweeps < 1 || prm.sweeps > 4 || prm.coarse_sweeps < 1 || prm.itmax < 1 ||
         prm.pre != 1 || prm.post != 1 || prm.cycle < BCM_VCYCLE || prm.cycle > BCM_KCYCLE || prm.kcycle_levels < 0 ||
-        !valid_group(prm.group) || !(prm.min_ratio >= 0.0) ||
+        !valid_group(prm.group) || !(prm.min_ratio >= 0.0) || (prm.fold != 0 && prm.fold != 1) ||
         (prm.precision != BCM_FP64 && prm.precision != BCM_FP32_CYCLE) || (prm.alloc == nullptr) != (prm.dealloc == nullptr)) {
         set_error("unsupported parameters (sweeps 1..4, pre = post = 1, V-, W- or K-cycle, kcycle_levels >= 0, "
-                  "group 0, -1, 4, 8, 16, 32 or 64, FP64 or FP32 cycle)");
+                  "group 0, -1, 4, 8, 16, 32 or 64, fold 0 or 1, FP64 or FP32 cycle)");
         return BCM_EINVAL;
     }
     const double t0 = now_ms();

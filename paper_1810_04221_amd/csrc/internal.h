@@ -14,6 +14,7 @@ namespace bcm {
 constexpr int kMaxLevels = 64;
 constexpr int kCoarseLds = 8192;   // largest coarsest level solved inside one workgroup
 constexpr int kCoarseDense = 1024; // largest coarsest level applied as a precomputed dense operator
+constexpr int kFoldRows = 2048;    // V-cycle: levels from the first this small on form one dense operator
 constexpr int kSplitUp = 65536;    // levels at least this large run the up leg as prolong + smooth
 
 // Error flags raised by the validation kernel.
@@ -145,6 +146,8 @@ struct bcm_handle {
     double *ctmp[2] = {nullptr, nullptr};  // coarsest-level sweep buffers when n > kCoarseLds
     bcm::TailLevel *tail = nullptr;        // device table of levels for the tail kernel
     int kt = -1;                           // first level handled by the tail kernel (-1: none)
+    int kf = 0;                            // first level of the folded dense operator (0: none)
+    double *fold = nullptr;                // that operator, n_kf x n_kf row-major, float64
     int *tail_ops = nullptr;               // the tail kernel's program (device)
     int n_tail_ops = 0;
     double *partials = nullptr;
@@ -244,6 +247,13 @@ void launch_tail(hipStream_t s, int fp32, int kt, int nl, const TailLevel *tl, c
                  const int *ops, int nops, void *x_out, const double *done);
 // S = sum_{t < sweeps} (I - D A)^t D of the coarsest level, column by column
 void launch_coarse_build(hipStream_t s, const Level &L, int sweeps, double *S);
+// Folded V-cycle of level L (pre = post = 1) from the coarser level's map Tc
+// (nc x nc): T = D + (I - D A)(D + P Tc P^T (I - A D)), n x n row-major; H is
+// n x n scratch.  A must be exactly symmetric (every coarse level is).
+void launch_fold_level(hipStream_t s, const Level &L, const double *Tc, int nc, double *H, double *T);
+// x = T b with a dense n x n row-major float64 operator (float64 accumulation)
+void launch_dense(hipStream_t s, int n, const double *T, const void *b, void *x, int b_f64, int x_f64,
+                  const double *done);
 void launch_resid(hipStream_t s, const Level &L, int nb, const double *b, const double *u, double *r,
                   double *partials, double *scal);
 void launch_spmv_dots(hipStream_t s, const Level &L, int nb, int first, const double *w, const double *r,

@@ -512,6 +512,49 @@ k_coarse_dense(int n, const double *__restrict__ S, const VB *__restrict__ b, VX
 }
 
 // ----------------------------------------------------------------------------
+// Folded coarse levels.  With one l1-Jacobi sweep from zero before and one
+// after the coarse correction, the cycle of level k is the linear map
+//   T_k = D + (I - D A)(D + P T_{k+1} P^T (I - A D))
+// (D = diag(dinv), P the level's prolongator, T_{k+1} the coarser level's map;
+// the coarsest level's map is its sweep operator S).  On the smallest levels
+// it is formed once, densely, and the cycle from such a level is one dense
+// product: the same operator as the level-by-level cycle, rounded differently.
+// One thread per entry (i, j), j fastest.
+// ----------------------------------------------------------------------------
+// H = D + G (I - A D) with G = P Tc P^T, G_ij = p_i p_j Tc[agg_i][agg_j]:
+//   H_ij = [i = j] dinv_i + G_ij - dinv_j sum_{k in row j} G_ik a_jk
+// (a_kj = a_jk: A is symmetric).
+__global__ void __launch_bounds__(kBlock)
+k_fold_h(int n, int nc, const int *__restrict__ rp, const int *__restrict__ ci, const double *__restrict__ a,
+         const double *__restrict__ dinv, const double *__restrict__ p, const int *__restrict__ agg,
+         const double *__restrict__ Tc, double *__restrict__ H) {
+    const long long idx = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (idx >= (long long)n * n) return;
+    const int i = (int)(idx / n), j = (int)(idx % n);
+    const double *trow = Tc + (size_t)agg[i] * nc;
+    const double pi = p[i];
+    double s = 0.0;
+    for (int q = rp[j]; q < rp[j + 1]; ++q) {
+        const int k = ci[q];
+        s += ((pi * p[k]) * trow[agg[k]]) * a[q];
+    }
+    const double gij = (pi * p[j]) * trow[agg[j]];
+    H[idx] = (i == j ? dinv[i] : 0.0) + gij - dinv[j] * s;
+}
+
+// T = D + (I - D A) H:  T_ij = [i = j] dinv_i + H_ij - dinv_i sum_{k in row i} a_ik H_kj
+__global__ void __launch_bounds__(kBlock)
+k_fold_t(int n, const int *__restrict__ rp, const int *__restrict__ ci, const double *__restrict__ a,
+         const double *__restrict__ dinv, const double *__restrict__ H, double *__restrict__ T) {
+    const long long idx = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (idx >= (long long)n * n) return;
+    const int i = (int)(idx / n), j = (int)(idx % n);
+    double s = 0.0;
+    for (int q = rp[i]; q < rp[i + 1]; ++q) s += a[q] * H[(size_t)ci[q] * n + j];
+    T[idx] = (i == j ? dinv[i] : 0.0) + H[idx] - dinv[i] * s;
+}
+
+// ----------------------------------------------------------------------------
 // Tail of the cycle: every level k >= kt (all with at most kTailRows rows) and
 // the coarsest solve, inside one workgroup of 1024 threads, with phases
 // separated by barriers instead of kernel launches.  Down legs (one thread per
@@ -1107,6 +1150,23 @@ void launch_kcycle_step2(hipStream_t s, const Level &C, int fp32, const void *c2
     else
         hipLaunchKernelGGL((k_kcombine<double>), dim3(blocks_for(C.A.n)), dim3(kBlock), 0, s, C.A.n,
                            (const double *)c2, ks, (double *)x, done);
+}
+
+void launch_fold_level(hipStream_t s, const Level &L, const double *Tc, int nc, double *H, double *T) {
+    const int n = L.A.n;
+    const int nb = blocks_for((long long)n * n);
+    hipLaunchKernelGGL(k_fold_h, dim3(nb), dim3(kBlock), 0, s, n, nc, L.A.rp, L.A.ci, L.A.v, L.dinv, L.p, L.agg, Tc, H);
+    hipLaunchKernelGGL(k_fold_t, dim3(nb), dim3(kBlock), 0, s, n, L.A.rp, L.A.ci, L.A.v, L.dinv, H, T);
+}
+
+void launch_dense(hipStream_t s, int n, const double *T, const void *b, void *x, int b_f64, int x_f64,
+                  const double *done) {
+    if (b_f64 && x_f64)
+        hipLaunchKernelGGL((k_coarse_dense<double, double>), dim3(n), dim3(64), 0, s, n, T, (const double *)b,
+                           (double *)x, done);
+    else
+        hipLaunchKernelGGL((k_coarse_dense<float, float>), dim3(n), dim3(64), 0, s, n, T, (const float *)b,
+                           (float *)x, done);
 }
 
 void launch_coarse_build(hipStream_t s, const Level &L, int sweeps, double *S) {

@@ -42,7 +42,7 @@ def test_default_params_and_error_string(lib):
     lib.bcm_default_params(C.byref(p))
     assert (p.max_levels, p.max_coarse, p.sweeps, p.coarse_sweeps, p.pre, p.post) == (40, 0, 2, 20, 1, 1)
     assert (p.itmax, p.precision, p.check) == (5000, bcm.BCM_FP64, 1)
-    assert (p.cycle, p.kcycle_levels, p.graph, p.group, p.sell, p.min_ratio) == (1, 0, 0, 0, 1, 0.0)
+    assert (p.cycle, p.kcycle_levels, p.graph, p.group, p.sell, p.min_ratio, p.fold) == (1, 0, 0, 0, 1, 0.0, 1)
     assert lib.bcm_last_error() == b""
 
 

@@ -145,6 +145,30 @@ def test_precond_fp32_cycle_error_bound(B, ora, name, scale):
     assert np.linalg.norm(z - zo) <= 1e-5 * np.linalg.norm(zo)
 
 
+@pytest.mark.parametrize("name,scale", [("G1", 1.0), ("G2", 0.3), ("G5", 0.2), ("G4", 0.21)])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_folded_coarse_levels(B, ora, name, scale, precision):
+    # the small levels' cycle applied as one precomputed float64 operator
+    # (the default) against the level-by-level cycle and the oracle: the same
+    # linear map, rounded differently (fold from level 1 in G1 and G4, from
+    # level 2 over four levels in G2)
+    c = P.config(name, scale)
+    say(f"folded levels {precision} {c['name']}")
+    ho = ora.Hierarchy(c["rowptr"], c["col"], c["val"], c["w"], max_coarse=c["max_coarse"])
+    r = P.uniform_rhs(c["n"], 21)
+    zo = ho.vcycle(r)
+    zs = []
+    for fold in (True, False):
+        h = B.Hierarchy(c["rowptr"], c["col"], c["val"], c["w"], max_coarse=c["max_coarse"], precision=precision,
+                        fold=fold)
+        zs.append(h.precond(r).cpu().numpy())
+        h.close()
+    bound = 1e-12 if precision == "fp64" else 1e-5
+    for z in zs:
+        assert np.linalg.norm(z - zo) <= bound * np.linalg.norm(zo)
+    assert np.linalg.norm(zs[0] - zs[1]) <= bound * np.linalg.norm(zo)
+
+
 SOLVE_CASES = [("G1", 1.0), ("G2", 0.3), ("G3", 0.2), ("G4", 0.21), ("G2", 1.0), ("G5", 0.5)]
 
 
