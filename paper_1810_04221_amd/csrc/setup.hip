@@ -713,16 +713,24 @@ void launch_aggfill(hipStream_t s, int n, const int *mate, const int *ofs, const
     hipLaunchKernelGGL(k_aggfill, dim3(blocks_for(n)), dim3(kBlock), 0, s, n, mate, ofs, w, agg, p, wc, mem2);
 }
 
+// Rows with at most 4 G candidates: each candidate's column F, key (m, M) and
+// term (p_m a_ij) p_M are formed once, with all loads of the row in flight
+// together, and kept in LDS; the distinct columns, their ranks and their (at
+// most four) terms are then found by comparing LDS entries only.  Longer rows
+// take gal_row's scratch path.
 template <int G>
 __global__ void __launch_bounds__(kBlock)
 k_gal(int pass, int nc, const int *__restrict__ rp, const int *__restrict__ ci,
       const double *__restrict__ v, const int *__restrict__ agg, const double *__restrict__ p,
       const int *__restrict__ mem2, int *__restrict__ cnt, const int *__restrict__ crp,
       int *__restrict__ cci, double *__restrict__ cv, int *__restrict__ gF, int *__restrict__ gU) {
-    constexpr int LMAX = 16 * G;
+    constexpr int SL = 4;  // candidate slots per lane
+    constexpr int LS = SL * G;
     constexpr int NG = kBlock / G;
-    __shared__ int sF[NG * LMAX];
-    __shared__ int sU[NG * LMAX];
+    __shared__ int sf[NG * LS];
+    __shared__ int sfirst[NG * LS];
+    __shared__ unsigned long long skey[NG * LS];
+    __shared__ double st[NG * LS];
     const int g = threadIdx.x / G, lane = threadIdx.x % G;
     const int E = xcd_block(blockIdx.x, gridDim.x) * NG + g;
     if (E >= nc) return;
@@ -730,9 +738,81 @@ k_gal(int pass, int nc, const int *__restrict__ rp, const int *__restrict__ ci,
     const int s0 = rp[e0], L0 = rp[e0 + 1] - s0;
     const int s1 = e1 >= 0 ? rp[e1] : 0;
     const int L1 = e1 >= 0 ? rp[e1 + 1] - s1 : 0;
-    const bool staged = L0 + L1 <= LMAX;
-    gal_row<G>(pass, E, lane, rp, ci, v, agg, p, e0, e1, s0, L0, s1, L1, cnt, crp, cci, cv,
-               staged ? sF + g * LMAX : gF, staged ? sU + g * LMAX : gU, staged);
+    const int L = L0 + L1;
+    if (L > LS) {
+        gal_row<G>(pass, E, lane, rp, ci, v, agg, p, e0, e1, s0, L0, s1, L1, cnt, crp, cci, cv, gF, gU, false);
+        return;
+    }
+    int *F = sf + g * LS, *first = sfirst + g * LS;
+    unsigned long long *K = skey + g * LS;
+    double *T = st + g * LS;
+    const double pe0 = pass ? p[e0] : 0.0, pe1 = (pass && e1 >= 0) ? p[e1] : 0.0;
+#pragma unroll
+    for (int sl = 0; sl < SL; ++sl) {
+        const int k = lane + sl * G;
+        if (k >= L) continue;
+        const int q = k < L0 ? s0 + k : s1 + (k - L0);
+        const int j = ci[q];
+        F[k] = agg[j];
+        if (pass) {
+            const int i = k < L0 ? e0 : e1;
+            const double pi = k < L0 ? pe0 : pe1, pj = p[j], a = v[q];
+            const bool ilo = i <= j;
+            K[k] = ((unsigned long long)(unsigned)(ilo ? i : j) << 32) | (unsigned)(ilo ? j : i);
+            T[k] = ((ilo ? pi : pj) * a) * (ilo ? pj : pi);
+        }
+    }
+    wave_sync();
+    // first occurrence of each column among the candidates
+    int nu = 0;
+#pragma unroll
+    for (int sl = 0; sl < SL; ++sl) {
+        const int k = lane + sl * G;
+        if (k >= L) continue;
+        const int f = F[k];
+        int fk = 1;
+        for (int k2 = 0; k2 < k; ++k2) fk = (F[k2] == f) ? 0 : fk;
+        first[k] = fk;
+        nu += fk;
+    }
+    if (pass == 0) {
+        nu = group_sum<G>(nu);
+        if (lane == 0) cnt[E] = nu;
+        return;
+    }
+    wave_sync();
+    const int base = crp[E];
+    const unsigned long long NONE = ~0ull;
+#pragma unroll
+    for (int sl = 0; sl < SL; ++sl) {
+        const int k = lane + sl * G;
+        if (k >= L || !first[k]) continue;
+        const int f = F[k];
+        // rank among the distinct columns; the terms of column f in candidate order
+        int rank = 0, nt = 0;
+        unsigned long long key[4] = {NONE, NONE, NONE, NONE};
+        double t[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int k2 = 0; k2 < L; ++k2) {
+            const int f2 = F[k2];
+            rank += (first[k2] && f2 < f) ? 1 : 0;
+            if (f2 == f && nt < 4) {
+                key[nt] = K[k2];
+                t[nt] = T[k2];
+                ++nt;
+            }
+        }
+        cswap(key[0], t[0], key[1], t[1]);
+        cswap(key[2], t[2], key[3], t[3]);
+        cswap(key[0], t[0], key[2], t[2]);
+        cswap(key[1], t[1], key[3], t[3]);
+        cswap(key[1], t[1], key[2], t[2]);
+        double sum = t[0];
+#pragma unroll
+        for (int r = 1; r < 4; ++r)
+            if (key[r] != NONE) sum = sum + t[r];
+        cci[base + rank] = f;
+        cv[base + rank] = sum;
+    }
 }
 
 // Galerkin product for long rows: the same entries and sums as k_gal, with the
