@@ -193,8 +193,10 @@ int match_sweep(hipStream_t s, Arena &tmp, const Csr &A, const double *w, int ch
             return BCM_EINVAL;
         }
     }
-    launch_weights(s, G, m, A.rp, A.ci, A.v, diag, w, c);
-    launch_candidates(s, G, m, A.nnz, A.rp, A.ci, c, rk, cand);
+    // rows of a few dozen entries: own-row ranks with the weights; longer: sorted
+    const bool sorted = A.nnz >= (long long)kSortedCandidatesAvg * m;
+    launch_weights(s, G, m, A.rp, A.ci, A.v, diag, w, c, sorted ? nullptr : rk);
+    launch_candidates(s, G, m, sorted, A.rp, A.ci, c, rk, cand);
     launch_fill_u64(s, m, ws, 0ull);
     launch_suitor(s, m, A.rp, cand, ws);
     launch_mate(s, m, A.rp, A.ci, ws, mate, leader);

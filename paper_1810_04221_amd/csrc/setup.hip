@@ -91,59 +91,107 @@ k_validate(int n, int nnz, const int *__restrict__ rp, const int *__restrict__ c
 // Edge weights of compatible weighted matching (Section 2.2):
 //   c_ij = 1 - 2 a_ij w_i w_j / (a_ii w_i^2 + a_jj w_j^2)
 // with m = min(i, j), M = max(i, j) fixing the operand order, so both ends of
-// an edge compute the same double.  Diagonal positions get 0.
+// an edge compute the same double.  Diagonal positions get 0.  With rk given,
+// also the own-row rank of every weight, rk[q] = #{ t in row(q) : c[t] < c[q] }
+// (needed by the candidate lists), compared in LDS for rows of at most 4 G
+// entries and in global memory for longer ones.
 // ----------------------------------------------------------------------------
 template <int G>
 __global__ void __launch_bounds__(kBlock)
 k_weights(int n, const int *__restrict__ rp, const int *__restrict__ ci, const double *__restrict__ v,
-          const double *__restrict__ diag, const double *__restrict__ w, double *__restrict__ c) {
-    const int lane = threadIdx.x % G;
+          const double *__restrict__ diag, const double *__restrict__ w, double *__restrict__ c,
+          unsigned *__restrict__ rk) {
+    constexpr int LS = 4 * G;
+    constexpr int NG = kBlock / G;
+    __shared__ double sc[NG * LS];
+    const int g = threadIdx.x / G, lane = threadIdx.x % G;
     const int row = (xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x) / G;
     if (row >= n) return;
-    const int e = rp[row + 1];
-    for (int q = rp[row] + lane; q < e; q += G) {
+    const int s0 = rp[row], e = rp[row + 1], d = e - s0;
+    const bool staged = rk && d <= LS;
+    double *C = sc + g * LS;
+    for (int q = s0 + lane; q < e; q += G) {
         const int j = ci[q];
-        if (j == row) { c[q] = 0.0; continue; }
-        const int m = min(row, j), M = max(row, j);
-        const double wm = w[m], wM = w[M];
-        const double num = ((2.0 * v[q]) * wm) * wM;
-        const double den = (diag[m] * wm) * wm + (diag[M] * wM) * wM;
-        c[q] = 1.0 - num / den;
+        double cq = 0.0;
+        if (j != row) {
+            const int m = min(row, j), M = max(row, j);
+            const double wm = w[m], wM = w[M];
+            const double num = ((2.0 * v[q]) * wm) * wM;
+            const double den = (diag[m] * wm) * wm + (diag[M] * wM) * wM;
+            cq = 1.0 - num / den;
+        }
+        c[q] = cq;
+        if (staged) C[q - s0] = cq;
+    }
+    if (!rk) return;
+    if (staged) wave_sync(); else __threadfence_block();
+    const double *R = staged ? C : c + s0;
+    for (int k = lane; k < d; k += G) {
+        const double cq = R[k];
+        unsigned r = 0;
+        for (int t = 0; t < d; ++t) r += (R[t] < cq) ? 1u : 0u;
+        rk[s0 + k] = r;
     }
 }
 
 // ----------------------------------------------------------------------------
-// Suitor candidate lists by direct counting (short rows): each eligible entry
-// (u, v) counts its rank among row v's weights and its place in u's order.
-// Same output as k_candidates below; see there.
+// Suitor candidate lists for short rows (same output as k_candidates below;
+// see there): the row's weights and columns are held in LDS (rows of at most
+// 4 G entries) and each eligible entry counts its place in the row's order
+// there; the rank of c_uv seen from v is the own-row rank (k_weights) of the
+// transposed entry, found by binary search.
 // ----------------------------------------------------------------------------
 template <int G>
 __global__ void __launch_bounds__(kBlock)
 k_candidates_direct(int n, const int *__restrict__ rp, const int *__restrict__ ci, const double *__restrict__ c,
-                    unsigned long long *__restrict__ cand) {
-    const int lane = threadIdx.x % G;
+                    const unsigned *__restrict__ rk_own, unsigned long long *__restrict__ cand) {
+    constexpr int LS = 4 * G;
+    constexpr int NG = kBlock / G;
+    __shared__ double sc[NG * LS];
+    __shared__ int sv[NG * LS];
+    const int g = threadIdx.x / G, lane = threadIdx.x % G;
     const int row = (xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x) / G;
     if (row >= n) return;
-    const int s0 = rp[row], e = rp[row + 1];
+    const int s0 = rp[row], e = rp[row + 1], d = e - s0;
+    // (a pattern that is not symmetric, accepted without the symmetry check,
+    // may lack the entry: rank 0 then, and no read outside row v)
+    auto rank_at = [&](int vtx) -> unsigned {
+        const int e2 = rp[vtx + 1];
+        int lo = rp[vtx], hi = e2;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (ci[mid] < row) lo = mid + 1; else hi = mid;
+        }
+        return lo < e2 ? rk_own[lo] : 0u;
+    };
+    const bool staged = d <= LS;
+    double *C = sc + g * LS;
+    int *V = sv + g * LS;
+    if (staged) {
+        for (int k = lane; k < d; k += G) {
+            C[k] = c[s0 + k];
+            V[k] = ci[s0 + k];
+        }
+        wave_sync();
+    }
+    const double *Cr = staged ? C : c + s0;
+    const int *Vr = staged ? V : ci + s0;
     int nelig = 0;
-    for (int q = s0 + lane; q < e; q += G) {
-        const int vtx = ci[q];
-        const double cq = c[q];
+    for (int k = lane; k < d; k += G) {
+        const int vtx = Vr[k];
+        const double cq = Cr[k];
         if (!(vtx != row && cq > 0.0 && cq < INFINITY)) continue;
         ++nelig;
-        unsigned rk = 0;
-        const int e2 = rp[vtx + 1];
-        for (int t = rp[vtx]; t < e2; ++t) rk += (c[t] < cq) ? 1u : 0u;
         int before = 0;
-        for (int t = s0; t < e; ++t) {
-            const int vt = ci[t];
-            const double ct = c[t];
+        for (int t = 0; t < d; ++t) {
+            const int vt = Vr[t];
+            const double ct = Cr[t];
             const bool elig = vt != row && ct > 0.0 && ct < INFINITY;
             before += (elig && (ct > cq || (ct == cq && vt > vtx))) ? 1 : 0;
         }
-        if (s0 + before < e - 1) cand[s0 + before] = ((unsigned long long)rk << 32) | (unsigned)vtx;
+        if (before < d - 1) cand[s0 + before] = ((unsigned long long)rank_at(vtx) << 32) | (unsigned)vtx;
     }
-    nelig = min(group_sum<G>(nelig), max(e - s0 - 1, 0));
+    nelig = min(group_sum<G>(nelig), max(d - 1, 0));
     for (int q = s0 + nelig + lane; q < e; q += G) cand[q] = ~0ull;
 }
 
@@ -254,13 +302,16 @@ k_candidates(int n, const int *__restrict__ rp, const int *__restrict__ ci, cons
     if (row >= n) return;
     const int s0 = rp[row], e = rp[row + 1], d = e - s0;
     // rank of c_uv seen from v: the own-row rank of (v, u), found by binary search
+    // (a pattern that is not symmetric, accepted without the symmetry check,
+    // may lack the entry: rank 0 then, and no read outside row v)
     auto rank_at = [&](int vtx) -> unsigned {
-        int lo = rp[vtx], hi = rp[vtx + 1];
+        const int e2 = rp[vtx + 1];
+        int lo = rp[vtx], hi = e2;
         while (lo < hi) {
             const int mid = (lo + hi) >> 1;
             if (ci[mid] < row) lo = mid + 1; else hi = mid;
         }
-        return rk_own[lo];
+        return lo < e2 ? rk_own[lo] : 0u;
     };
     if (d <= LMAX) {
         unsigned long long *keys = sk + g * LMAX;
@@ -672,25 +723,25 @@ void launch_validate(hipStream_t s, int G, int n, int nnz, const int *rp, const 
     });
 }
 
-void launch_weights(hipStream_t s, int G, int n, const int *rp, const int *ci, const double *v,
-                    const double *diag, const double *w, double *c) {
+void launch_weights(hipStream_t s, int G, int n, const int *rp, const int *ci, const double *v, const double *diag,
+                    const double *w, double *c, unsigned *rk) {
     with_G(G, [&](auto gc) {
         constexpr int g = decltype(gc)::value;
         hipLaunchKernelGGL(k_weights<g>, dim3(blocks_for((long long)n * g)), dim3(kBlock), 0, s, n, rp, ci,
-                           v, diag, w, c);
+                           v, diag, w, c, rk);
     });
 }
 
-// Rows of a few dozen entries count directly (one kernel); longer rows sort
-// (k_rank + k_candidates: O(d log d) per row instead of O(d^2)).
-void launch_candidates(hipStream_t s, int G, int n, int nnz, const int *rp, const int *ci, const double *c,
+// Rows of a few dozen entries compare directly (own-row ranks from
+// k_weights); longer rows sort (k_rank + k_candidates: O(d log d) per row
+// instead of O(d^2)).
+void launch_candidates(hipStream_t s, int G, int n, bool sorted, const int *rp, const int *ci, const double *c,
                        unsigned *rk, unsigned long long *cand) {
-    const bool sorted = nnz >= (long long)kSortedCandidatesAvg * n;
     with_G(G, [&](auto gc) {
         constexpr int g = decltype(gc)::value;
         if (!sorted) {
             hipLaunchKernelGGL(k_candidates_direct<g>, dim3(blocks_for((long long)n * g)), dim3(kBlock), 0, s, n, rp,
-                               ci, c, cand);
+                               ci, c, rk, cand);
             return;
         }
         hipLaunchKernelGGL(k_rank<g>, dim3(blocks_for((long long)n * g)), dim3(kBlock), 0, s, n, rp, c, rk);

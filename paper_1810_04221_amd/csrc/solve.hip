@@ -61,9 +61,11 @@ __device__ __forceinline__ void rows_dot(const int *__restrict__ rp, const int *
     int beg[R], end[R];
 #pragma unroll
     for (int k = 0; k < R; ++k) {
+        // both bounds loaded unconditionally: no branch between the R rows' loads
         const int i = rows[k] < 0 ? 0 : rows[k];
-        beg[k] = rp[i];
-        end[k] = rows[k] < 0 ? beg[k] : rp[i + 1];
+        const int b0 = rp[i], b1 = rp[i + 1];
+        beg[k] = b0;
+        end[k] = rows[k] < 0 ? b0 : b1;
     }
 #pragma unroll
     for (int k = 0; k < R; ++k) {
@@ -118,7 +120,8 @@ __global__ void __launch_bounds__(kBlock)
 k_down_seq(int nc, const int *__restrict__ mem, const int *__restrict__ rp, const int *__restrict__ ci,
            const V *__restrict__ a, const V *__restrict__ dinv, const V *__restrict__ p,
            const VB *__restrict__ b, V *__restrict__ bc, const double *__restrict__ done) {
-    if (done && *done != 0.0) return;
+    // small levels: the solve-ended flag is only tested before the store, so
+    // its load overlaps the row loads instead of preceding them
     const int lane = threadIdx.x % G;
     int E = (xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x) / G;
     const bool live = E < nc;
@@ -135,7 +138,7 @@ k_down_seq(int nc, const int *__restrict__ mem, const int *__restrict__ rp, cons
         const V c = p[i] * ((V)b[i] - s[t]);
         acc += rows[t] < 0 ? V(0) : c;
     }
-    if (lane == 0 && live) bc[E] = acc;
+    if (lane == 0 && live && !(done && *done != 0.0)) bc[E] = acc;
 }
 
 // Any number of members (wide composed aggregates): one member row at a time.
@@ -208,7 +211,7 @@ __global__ void __launch_bounds__(kBlock)
 k_up(int n, const int *__restrict__ rp, const int *__restrict__ ci, const V *__restrict__ a,
      const V *__restrict__ dinv, const V *__restrict__ p, const int *__restrict__ agg,
      const VB *__restrict__ b, const V *__restrict__ xc, VX *__restrict__ x, const double *__restrict__ done) {
-    if (done && *done != 0.0) return;
+    // the solve-ended flag is tested before the stores only (as in k_down_seq)
     constexpr int NG = kBlock / G;
     const int lane = threadIdx.x % G;
     const int base = xcd_block(blockIdx.x, gridDim.x) * NG * R + threadIdx.x / G;
@@ -217,7 +220,7 @@ k_up(int n, const int *__restrict__ rp, const int *__restrict__ ci, const V *__r
     for (int k = 0; k < R; ++k) rows[k] = base + k * NG < n ? base + k * NG : -1;
     V s[R];
     rows_dot<G, R, V>(rp, ci, a, rows, s, [&](int j) { return dinv[j] * (V)b[j] + p[j] * xc[agg[j]]; });
-    if (lane == 0) {
+    if (lane == 0 && !(done && *done != 0.0)) {
 #pragma unroll
         for (int k = 0; k < R; ++k) {
             const int i = rows[k];
@@ -496,19 +499,22 @@ k_coarse(int n, int nnz, const int *__restrict__ rp_g, const int *__restrict__ c
     for (int i = threadIdx.x; i < n; i += blockDim.x) x[i] = (VX)xs[i];
 }
 
-// Coarsest level with its sweep operator S precomputed (symmetric, n <= 1024):
-// x = S b.  One wave per row i reads row i of S contiguously.
+// Dense operator applied to b: x = S b, S row-major n x n float64 (the
+// coarsest level's sweep operator, or the folded small levels).  One workgroup
+// per row i, four waves splitting the row so that enough loads are in flight.
 template <typename VB, typename VX>
-__global__ void __launch_bounds__(64)
+__global__ void __launch_bounds__(kBlock)
 k_coarse_dense(int n, const double *__restrict__ S, const VB *__restrict__ b, VX *__restrict__ x,
                const double *__restrict__ done) {
-    if (done && *done != 0.0) return;
-    const int i = blockIdx.x, lane = threadIdx.x;
+    // the solve-ended flag is tested before the store only (as in k_down_seq)
+    const int i = blockIdx.x;
     const double *row = S + (size_t)i * n;
-    double s = 0.0;
-    for (int j = lane; j < n; j += 64) s += row[j] * (double)b[j];
-    s = group_sum<64>(s);
-    if (lane == 0) x[i] = (VX)s;
+    double s[1] = {0.0};
+#pragma unroll 4
+    for (int j = threadIdx.x; j < n; j += kBlock) s[0] += row[j] * (double)b[j];
+    __shared__ double lds[16];
+    block_sum<1>(s, lds);
+    if (threadIdx.x == 0 && !(done && *done != 0.0)) x[i] = (VX)s[0];
 }
 
 // ----------------------------------------------------------------------------
@@ -1005,7 +1011,7 @@ void coarse_t(hipStream_t s, const Level &L, int sweeps, const VB *b, VX *x, dou
               const double *done) {
     const int n = L.A.n;
     if (L.S) {
-        hipLaunchKernelGGL((k_coarse_dense<VB, VX>), dim3(n), dim3(64), 0, s, n, L.S, b, x, done);
+        hipLaunchKernelGGL((k_coarse_dense<VB, VX>), dim3(n), dim3(kBlock), 0, s, n, L.S, b, x, done);
         return;
     }
     if (coarse_in_lds(n, L.A.nnz)) {
@@ -1162,10 +1168,10 @@ void launch_fold_level(hipStream_t s, const Level &L, const double *Tc, int nc, 
 void launch_dense(hipStream_t s, int n, const double *T, const void *b, void *x, int b_f64, int x_f64,
                   const double *done) {
     if (b_f64 && x_f64)
-        hipLaunchKernelGGL((k_coarse_dense<double, double>), dim3(n), dim3(64), 0, s, n, T, (const double *)b,
+        hipLaunchKernelGGL((k_coarse_dense<double, double>), dim3(n), dim3(kBlock), 0, s, n, T, (const double *)b,
                            (double *)x, done);
     else
-        hipLaunchKernelGGL((k_coarse_dense<float, float>), dim3(n), dim3(64), 0, s, n, T, (const float *)b,
+        hipLaunchKernelGGL((k_coarse_dense<float, float>), dim3(n), dim3(kBlock), 0, s, n, T, (const float *)b,
                            (float *)x, done);
 }
 
