@@ -14,6 +14,8 @@
 
 namespace bcm {
 
+thread_local KernelEvents g_kernel_events;
+
 namespace {
 thread_local std::string g_err;
 thread_local double *g_pinned = nullptr;  // 64 doubles of pinned host memory per thread
@@ -794,7 +796,11 @@ struct Prof {
     int mask;
     int gcls = -1;
     SegCapture *cap = nullptr;
-    int begin(int cls) {
+    // Classes 0-3 are single kernels: their events are taken by that kernel's
+    // own dispatch (launch_k), so the time excludes the launch gap.  Other
+    // classes, and any class bracketing a graph segment (stream = true), record
+    // the events on the stream around the bracket.
+    int begin(int cls, bool stream = false) {
         if (cap) {
             if (cls == gcls) cap->cut();
             return -1;
@@ -806,16 +812,22 @@ struct Prof {
             if (hipEventCreate(&e) != hipSuccess) return -1;
             h->ev_pool.push_back(e);
         }
-        (void)hipEventRecord(h->ev_pool[idx], h->s);
+        if (cls <= 3 && !stream) g_kernel_events = KernelEvents{h->ev_pool[idx], h->ev_pool[idx + 1]};
+        else (void)hipEventRecord(h->ev_pool[idx], h->s);
         return idx;
     }
-    void end(int cls, int idx, double bytes, int iter) {
+    void end(int cls, int idx, double bytes, int iter, bool stream = false) {
         if (cap) {
             if (cls == gcls) cap->cut();
             return;
         }
         if (idx < 0) return;
-        (void)hipEventRecord(h->ev_pool[idx + 1], h->s);
+        if (cls <= 3 && !stream) {
+            // no kernel took the events (a bracket without a launch_k): no sample
+            if (g_kernel_events.start) { g_kernel_events = KernelEvents{}; return; }
+        } else {
+            (void)hipEventRecord(h->ev_pool[idx + 1], h->s);
+        }
         h->ev_pairs.push_back({cls, idx});
         h->ev_bytes.push_back(bytes);
         h->ev_iter.push_back(iter);
@@ -1096,9 +1108,9 @@ int fcg_run(bcm_handle *h, const double *b, double *x_user, double tol) {
                     // segments: [before] [profiled class] [after], or one graph
                     int e = -1;
                     for (int g = 0; g < h->n_exec; ++g) {
-                        if (h->n_exec == 3 && g == 1) e = pf.begin(gcls);
+                        if (h->n_exec == 3 && g == 1) e = pf.begin(gcls, true);
                         if (h->iter_exec[g]) HIPCHK(hipGraphLaunch(h->iter_exec[g], s));
-                        if (h->n_exec == 3 && g == 1) pf.end(gcls, e, class_bytes(h, gcls), launched);
+                        if (h->n_exec == 3 && g == 1) pf.end(gcls, e, class_bytes(h, gcls), launched, true);
                     }
                     ++launched;
                     continue;

@@ -1,6 +1,7 @@
 // Host-side internals of the library: hierarchy data layout in HBM, the device
 // arena and the kernel launchers shared between translation units.
 #pragma once
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -10,6 +11,26 @@
 #include "bcm.h"
 
 namespace bcm {
+
+// Timing of a single kernel by its own dispatch.  While armed (start set), the
+// next launch through launch_k takes start/stop as that kernel's own start and
+// end timestamps (hipExtLaunchKernelGGL) and disarms them; otherwise launch_k
+// is an ordinary launch.  Per host thread.
+struct KernelEvents {
+    hipEvent_t start = nullptr, stop = nullptr;
+};
+extern thread_local KernelEvents g_kernel_events;
+
+template <typename F, typename... Args>
+inline void launch_k(F kernel, dim3 grid, dim3 block, hipStream_t s, Args... args) {
+    if (g_kernel_events.start) {
+        const KernelEvents e = g_kernel_events;
+        g_kernel_events = KernelEvents{};
+        hipExtLaunchKernelGGL(kernel, grid, block, 0, s, e.start, e.stop, 0, args...);
+    } else {
+        hipLaunchKernelGGL(kernel, grid, block, 0, s, args...);
+    }
+}
 
 constexpr int kMaxLevels = 64;
 constexpr int kCoarseLds = 8192;   // largest coarsest level solved inside one workgroup

@@ -930,14 +930,14 @@ void down_dispatch(hipStream_t s, const Level &L, const V *a, const V *dinv, con
     const dim3 grid(blocks_for((long long)L.nc * G));
     auto seq = [&](auto sc) {
         constexpr int SS = decltype(sc)::value;
-        hipLaunchKernelGGL((k_down_seq<G, SS, V, VB>), grid, dim3(kBlock), 0, s, L.nc, L.mem, L.A.rp, L.A.ci, a,
+        launch_k((k_down_seq<G, SS, V, VB>), grid, dim3(kBlock), s, L.nc, L.mem, L.A.rp, L.A.ci, a,
                            dinv, p, b, bc, done);
     };
     if (S == 1) seq(std::integral_constant<int, 1>{});
     else if (S == 2) seq(std::integral_constant<int, 2>{});
     else if (S == 4) seq(std::integral_constant<int, 4>{});
     else
-        hipLaunchKernelGGL((k_down_loop<G, V, VB>), grid, dim3(kBlock), 0, s, L.nc, L.mstride, L.mem, L.A.rp,
+        launch_k((k_down_loop<G, V, VB>), grid, dim3(kBlock), s, L.nc, L.mstride, L.mem, L.A.rp,
                            L.A.ci, a, dinv, p, b, bc, done);
 }
 
@@ -952,7 +952,7 @@ void down_t(hipStream_t s, const Level &L, const V *a, const V *dinv, const V *p
             with_sell<V>(L.E, [&](auto *ix, auto *vals) {
                 using I = std::remove_const_t<std::remove_pointer_t<decltype(ix)>>;
                 using S = std::remove_const_t<std::remove_pointer_t<decltype(vals)>>;
-                hipLaunchKernelGGL((k_down_res_sell<V, VB, I, S>), dim3(blocks_for(L.A.n)), dim3(kBlock), 0, s,
+                launch_k((k_down_res_sell<V, VB, I, S>), dim3(blocks_for(L.A.n)), dim3(kBlock), s,
                                    L.A.n, L.E.sp, ix, vals, dinv, p, b, pr, done);
             });
         if (part == 1) return;
@@ -984,7 +984,7 @@ void up_t(hipStream_t s, const Level &L, const V *a, const V *dinv, const V *p, 
             with_sell<V>(L.E, [&](auto *ix, auto *vals) {
                 using I = std::remove_const_t<std::remove_pointer_t<decltype(ix)>>;
                 using S = std::remove_const_t<std::remove_pointer_t<decltype(vals)>>;
-                hipLaunchKernelGGL((k_smooth_sell<V, VB, VX, I, S>), dim3(blocks_for(L.A.n)), dim3(kBlock), 0, s,
+                launch_k((k_smooth_sell<V, VB, VX, I, S>), dim3(blocks_for(L.A.n)), dim3(kBlock), s,
                                    L.A.n, L.E.sp, ix, vals, dinv, b, xp, x, done);
             });
             return;
@@ -992,8 +992,8 @@ void up_t(hipStream_t s, const Level &L, const V *a, const V *dinv, const V *p, 
         with_G(L.G, [&](auto gc) {
             constexpr int g = decltype(gc)::value;
             constexpr int R = 2;
-            hipLaunchKernelGGL((k_smooth<g, R, V, VB, VX>), dim3(blocks_for(((long long)L.A.n * g + R - 1) / R)),
-                               dim3(kBlock), 0, s, L.A.n, L.A.rp, L.A.ci, a, dinv, b, xp, x, done);
+            launch_k((k_smooth<g, R, V, VB, VX>), dim3(blocks_for(((long long)L.A.n * g + R - 1) / R)),
+                               dim3(kBlock), s, L.A.n, L.A.rp, L.A.ci, a, dinv, b, xp, x, done);
         });
         return;
     }
@@ -1001,8 +1001,8 @@ void up_t(hipStream_t s, const Level &L, const V *a, const V *dinv, const V *p, 
     with_G(L.G, [&](auto gc) {
         constexpr int g = decltype(gc)::value;
         constexpr int R = 2;
-        hipLaunchKernelGGL((k_up<g, R, V, VB, VX>), dim3(blocks_for(((long long)L.A.n * g + R - 1) / R)),
-                           dim3(kBlock), 0, s, L.A.n, L.A.rp, L.A.ci, a, dinv, p, L.agg, b, xc, x, done);
+        launch_k((k_up<g, R, V, VB, VX>), dim3(blocks_for(((long long)L.A.n * g + R - 1) / R)),
+                           dim3(kBlock), s, L.A.n, L.A.rp, L.A.ci, a, dinv, p, L.agg, b, xc, x, done);
     });
 }
 
@@ -1204,21 +1204,21 @@ void launch_spmv_dots(hipStream_t s, const Level &L, int nb, int first, const do
         with_sell<double>(L.E, [&](auto *ix, auto *vals) {
             using I = std::remove_const_t<std::remove_pointer_t<decltype(ix)>>;
             using S = std::remove_const_t<std::remove_pointer_t<decltype(vals)>>;
-            hipLaunchKernelGGL((k_spmv_dots_sell<I, S>), dim3(nb), dim3(kBlock), 0, s, L.A.n, L.E.sp, ix, vals, w, r,
+            launch_k((k_spmv_dots_sell<I, S>), dim3(nb), dim3(kBlock), s, L.A.n, L.E.sp, ix, vals, w, r,
                                q, v, partials, scal + 10);
         });
         return;
     }
     with_G(L.G, [&](auto gc) {
         constexpr int g = decltype(gc)::value;
-        hipLaunchKernelGGL(k_spmv_dots<g>, dim3(nb), dim3(kBlock), 0, s, L.A.n, L.A.rp, L.A.ci, L.A.v, w, r, q, v,
+        launch_k((k_spmv_dots<g>), dim3(nb), dim3(kBlock), s, L.A.n, L.A.rp, L.A.ci, L.A.v, w, r, q, v,
                            partials, scal + 10);
     });
 }
 
 void launch_update(hipStream_t s, int n, int nb, int first, const double *w, const double *v, double *d,
                    double *u, double *q, double *r, double *partials, double *scal) {
-    hipLaunchKernelGGL(k_update, dim3(nb), dim3(kBlock), 0, s, n, first, w, v, d, u, q, r, scal, partials);
+    launch_k((k_update), dim3(nb), dim3(kBlock), s, n, first, w, v, d, u, q, r, scal, partials);
 }
 
 void launch_finalize(hipStream_t s, int mode, int nb, int first, const double *partials, double *scal) {
