@@ -537,9 +537,24 @@ int build_hierarchy(bcm_handle *h, const bcm_csr *Ain, const double *win) {
         // coarsest level: precompute the sweep operator when it is small
         Level &C = h->lv[h->nl - 1];
         if (C.A.n <= kCoarseDense) {
-            C.S = h->persist.get_n<double>((size_t)C.A.n * C.A.n);
+            const size_t nn2 = (size_t)C.A.n * C.A.n;
+            C.S = h->persist.get_n<double>(nn2);
             NOMEM(C.S);
-            launch_coarse_build(s, C, P.coarse_sweeps, C.S);
+            if (C.A.n <= kCoarseBuildSweeps) {
+                // one workgroup per unit vector runs the sweeps
+                launch_coarse_build(s, C, P.coarse_sweeps, C.S);
+            } else {
+                // S_{t+1} = D + (I - DA) S_t from S_0 = 0 on the whole matrix at once
+                tmp.rewind();
+                double *W = tmp.get_n<double>(nn2);
+                NOMEM(W);
+                double *cur = (P.coarse_sweeps % 2) ? W : C.S, *nxt = (P.coarse_sweeps % 2) ? C.S : W;
+                launch_fill_i32(s, 2 * nn2, (int *)cur, 0);
+                for (int t = 0; t < P.coarse_sweeps; ++t) {
+                    launch_fold_left(s, C, cur, nxt);
+                    std::swap(cur, nxt);
+                }
+            }
         }
     }
     if (P.fold && P.cycle == BCM_VCYCLE && h->nl >= 3 && h->lv[h->nl - 1].S) {

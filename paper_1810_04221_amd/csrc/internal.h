@@ -34,7 +34,8 @@ inline void launch_k(F kernel, dim3 grid, dim3 block, hipStream_t s, Args... arg
 
 constexpr int kMaxLevels = 64;
 constexpr int kCoarseLds = 8192;   // largest coarsest level solved inside one workgroup
-constexpr int kCoarseDense = 1024; // largest coarsest level applied as a precomputed dense operator
+constexpr int kCoarseDense = 2048; // largest coarsest level applied as a precomputed dense operator
+constexpr int kCoarseBuildSweeps = 1024;  // up to this size S is built by sweeps on unit vectors
 constexpr int kFoldRows = 2048;    // V-cycle: levels from the first this small on form one dense operator
 constexpr int kSplitUp = 65536;    // levels at least this large run the up leg as prolong + smooth
 
@@ -272,6 +273,8 @@ void launch_coarse_build(hipStream_t s, const Level &L, int sweeps, double *S);
 // (nc x nc): T = D + (I - D A)(D + P Tc P^T (I - A D)), n x n row-major; H is
 // n x n scratch.  A must be exactly symmetric (every coarse level is).
 void launch_fold_level(hipStream_t s, const Level &L, const double *Tc, int nc, double *H, double *T);
+// T = D + (I - D A) H for dense n x n row-major H and T (level L's matrix)
+void launch_fold_left(hipStream_t s, const Level &L, const double *H, double *T);
 // x = T b with a dense n x n row-major float64 operator (float64 accumulation)
 void launch_dense(hipStream_t s, int n, const double *T, const void *b, void *x, int b_f64, int x_f64,
                   const double *done);

@@ -1165,6 +1165,12 @@ void launch_fold_level(hipStream_t s, const Level &L, const double *Tc, int nc, 
     hipLaunchKernelGGL(k_fold_t, dim3(nb), dim3(kBlock), 0, s, n, L.A.rp, L.A.ci, L.A.v, L.dinv, H, T);
 }
 
+void launch_fold_left(hipStream_t s, const Level &L, const double *H, double *T) {
+    const int n = L.A.n;
+    hipLaunchKernelGGL(k_fold_t, dim3(blocks_for((long long)n * n)), dim3(kBlock), 0, s, n, L.A.rp, L.A.ci, L.A.v,
+                       L.dinv, H, T);
+}
+
 void launch_dense(hipStream_t s, int n, const double *T, const void *b, void *x, int b_f64, int x_f64,
                   const double *done) {
     if (b_f64 && x_f64)
