@@ -502,35 +502,47 @@ int build_hierarchy(bcm_handle *h, const bcm_csr *Ain, const double *win) {
         for (int l = 0; l < h->nl && P.sell; ++l)
             if (l == 0 || h->lv[l].xp) lv_sell.push_back(l);
         // per level t: tot[t] = total slots, tot[32 + t] = largest |col - row|,
-        // tot[64 + t] = 1 if some value is not exactly a float32
+        // tot[64 + t] = 1 if some value is not exactly a float32, tot[96 + t] =
+        // slots of the slices without uniform column offsets
         if (lv_sell.size() > 32) lv_sell.resize(32);  // deeper levels keep the CSR kernels
-        int *tot = h->persist.get_n<int>(96);
+        int *tot = h->persist.get_n<int>(128);
         NOMEM(tot);
-        launch_fill_i32(s, 96, tot, 0);
+        launch_fill_i32(s, 128, tot, 0);
+        std::vector<int *> uni(lv_sell.size());
         for (size_t t = 0; t < lv_sell.size(); ++t) {
             Level &L = h->lv[lv_sell[t]];
             const int ns = (L.A.n + kSlice - 1) / kSlice;
             L.E.nslices = ns;
             L.E.sp = h->persist.get_n<int>((size_t)ns + 1);
+            uni[t] = h->persist.get_n<int>(ns);
             void *stmp = keep.get(scan_tmp_bytes(ns));
-            NOMEM(L.E.sp && stmp);
-            launch_sell_width(s, L.A.n, L.A.rp, L.A.ci, L.A.v, L.E.sp, tot + 32 + t, tot + 64 + t);
+            NOMEM(L.E.sp && uni[t] && stmp);
+            launch_sell_width(s, L.A.n, L.A.rp, L.A.ci, L.A.v, L.E.sp, uni[t], tot + 32 + t, tot + 64 + t,
+                              tot + 96 + t);
             scan_exclusive(s, L.E.sp, L.E.sp, ns, L.E.sp + ns, stmp);  // sp[ns] = total slots
             HIPCHK(hipMemcpyAsync(tot + t, L.E.sp + ns, sizeof(int), hipMemcpyDeviceToDevice, s));
         }
-        int tots[96];
+        int tots[128];
         int rc = read_back(s, tot, sizeof(tots), tots);
         if (rc) return rc;
         for (size_t t = 0; t < lv_sell.size(); ++t) {
             Level &L = h->lv[lv_sell[t]];
             const size_t ne = (size_t)tots[t];
-            if (tots[32 + t] <= 32767) L.E.sd = h->persist.get_n<short>(ne);
-            else L.E.sc = h->persist.get_n<int>(ne);
+            if (tots[32 + t] <= 32767) {
+                L.E.sd = h->persist.get_n<short>(ne);
+                L.E.su = h->persist.get_n<short>(ne / kSlice);
+                L.E.uni = uni[t];
+                NOMEM(L.E.sd && L.E.su);
+                L.E.mixed = ne ? (double)tots[96 + t] / (double)ne : 1.0;
+            } else {
+                L.E.sc = h->persist.get_n<int>(ne);
+            }
             const bool exact32 = tots[64 + t] == 0;
             if (!exact32) L.E.sv = h->persist.get_n<double>(ne);
             if (fp32 || exact32) L.E.sv32 = h->persist.get_n<float>(ne);
             NOMEM((L.E.sc || L.E.sd) && (L.E.sv || L.E.sv32));
-            launch_sell_fill(s, L.A.n, L.A.rp, L.A.ci, L.A.v, L.E.sp, L.E.sc, L.E.sd, L.E.sv, L.E.sv32);
+            launch_sell_fill(s, L.A.n, L.A.rp, L.A.ci, L.A.v, L.E.sp, uni[t], L.E.su, L.E.sc, L.E.sd, L.E.sv,
+                             L.E.sv32);
         }
     }
     {
@@ -670,8 +682,9 @@ bool kcycle_at(const bcm_handle *h, int k) {
 // Algorithmic bytes (every array touched once; gathers assumed cached).
 // down leg: fused k_down_*, or residual + restriction on large levels (p r written and read once)
 // Bytes of one column index of the matrix a row-parallel kernel reads: int16
-// offsets on a sliced-ELL copy that has them, else int32.
-double index_bytes(const Level &L, bool sell_path) { return sell_path && L.E.sd ? 2.0 : 4.0; }
+// offsets on a sliced-ELL copy that has them (none in its uniform slices, which
+// hold one offset per slot column), else int32.
+double index_bytes(const Level &L, bool sell_path) { return sell_path && L.E.sd ? 2.0 * L.E.mixed : 4.0; }
 // Bytes of one matrix value: float32 arithmetic, or a float64 kernel on a
 // sliced-ELL copy whose values are all exact float32, reads 4.
 double value_bytes(const Level &L, bool sell_path, bool f32) {

@@ -97,8 +97,13 @@ struct Sell {
     int nslices = 0;
     int *sp = nullptr, *sc = nullptr;
     short *sd = nullptr;
+    // int16 copies only: uni[s] = 1 when the rows of slice s share one list of
+    // column offsets, held in su from index sp[s] / 64 (one per slot column)
+    int *uni = nullptr;
+    short *su = nullptr;
     double *sv = nullptr;
     float *sv32 = nullptr;
+    double mixed = 1.0;  // fraction of the slots in slices that are not uniform
 };
 
 // One level of the hierarchy.  Row i of A^k, its l1 inverse diagonal, the
@@ -221,11 +226,11 @@ void launch_cast(hipStream_t s, size_t n, const double *src, float *dst);
 // slice widths (64 * longest row of each slice) -> cnt[nslices]; *maxoff is
 // raised to the largest |col - row| of the matrix, *inexact to 1 if a value is
 // not exactly a float32 (start both at 0)
-void launch_sell_width(hipStream_t s, int n, const int *rp, const int *ci, const double *v, int *cnt, int *maxoff,
-                       int *inexact);
+void launch_sell_width(hipStream_t s, int n, const int *rp, const int *ci, const double *v, int *cnt, int *uni,
+                       int *maxoff, int *inexact, int *mixed);
 // fills the slots: int32 columns into sc, or int16 offsets into sd (one is null)
-void launch_sell_fill(hipStream_t s, int n, const int *rp, const int *ci, const double *v, const int *sp, int *sc,
-                      short *sd, double *sv, float *sv32);
+void launch_sell_fill(hipStream_t s, int n, const int *rp, const int *ci, const double *v, const int *sp,
+                      const int *uni, short *su, int *sc, short *sd, double *sv, float *sv32);
 void launch_fill_i32(hipStream_t s, size_t n, int *dst, int val);
 void launch_fill_u64(hipStream_t s, size_t n, unsigned long long *dst, unsigned long long val);
 void launch_copy_f64(hipStream_t s, size_t n, const double *src, double *dst);

@@ -619,63 +619,111 @@ k_diag_l1(int n, const int *__restrict__ rp, const double *__restrict__ v, doubl
 }
 
 // Sliced ELL: width of slice s (times 64) = 64 * max row length over its rows.
+// A slice is uniform when every row's column offsets (col - row, ascending) are
+// a subsequence of those of its first full-width row, the template: uni[s] = 1,
+// and the slots of the slices that are not add up in *mixed.
 __global__ void __launch_bounds__(kBlock)
 k_sell_width(int n, const int *__restrict__ rp, const int *__restrict__ ci, const double *__restrict__ v,
-             int *__restrict__ cnt, int *__restrict__ maxoff, int *__restrict__ inexact) {
+             int *__restrict__ cnt, int *__restrict__ uni, int *__restrict__ maxoff, int *__restrict__ inexact,
+             int *__restrict__ mixed) {
     // one wave per slice (lane l on row 64 s + l), waves striding over slices;
     // the largest offset is reduced per block, then one atomic per block
     static_assert(kBlock % kSlice == 0, "a block must hold whole slices");
     constexpr int kWaves = kBlock / kSlice;
-    __shared__ int red[kWaves], redx[kWaves];
+    __shared__ int red[kWaves], redx[kWaves], redm[kWaves];
     const int ns = (n + kSlice - 1) / kSlice;
     const int lane = threadIdx.x % kSlice, wv = threadIdx.x / kSlice;
-    int off = 0, inx = 0;
+    int off = 0, inx = 0, mix = 0;
     for (int sl = blockIdx.x * kWaves + wv; sl < ns; sl += gridDim.x * kWaves) {
         const int i = sl * kSlice + lane;
-        int w = 0;
+        int w = 0, len = -1, q0 = 0;
         if (i < n) {
-            const int q0 = rp[i], q1 = rp[i + 1];
-            w = q1 - q0;
+            q0 = rp[i];
+            const int q1 = rp[i + 1];
+            w = len = q1 - q0;
             // columns are sorted: the extreme offsets are the first and the last
             if (q1 > q0) off = max(off, max(abs(ci[q0] - i), abs(ci[q1 - 1] - i)));
             for (int q = q0; q < q1; ++q) inx |= (double)(float)v[q] != v[q] ? 1 : 0;
         }
         for (int o = kSlice / 2; o > 0; o >>= 1) w = max(w, __shfl_xor(w, o, kSlice));
-        if (lane == 0) cnt[sl] = w * kSlice;
+        const int t = __ffsll((unsigned long long)__ballot(len == w)) - 1;
+        const int it = sl * kSlice + t, qt = rp[it];
+        int ok = 1;
+        if (i < n) {
+            // merge walk: each offset of this row must appear in the template, in order
+            int k = 0;
+            for (int j = 0; j < len && ok; ++j) {
+                const int o = ci[q0 + j] - i;
+                while (k < w && ci[qt + k] - it != o) ++k;
+                if (k == w) ok = 0;
+                ++k;
+            }
+        }
+        const bool u = __ballot(!ok) == 0;
+        if (lane == 0) {
+            cnt[sl] = w * kSlice;
+            uni[sl] = u ? 1 : 0;
+            if (!u) mix += w * kSlice;
+        }
     }
     for (int o = kSlice / 2; o > 0; o >>= 1) {
         off = max(off, __shfl_xor(off, o, kSlice));
         inx |= __shfl_xor(inx, o, kSlice);
     }
-    if (lane == 0) { red[wv] = off; redx[wv] = inx; }
+    if (lane == 0) { red[wv] = off; redx[wv] = inx; redm[wv] = mix; }
     __syncthreads();
     if (threadIdx.x == 0) {
-        int m = red[0], x = redx[0];
-        for (int k = 1; k < kWaves; ++k) { m = max(m, red[k]); x |= redx[k]; }
+        int m = red[0], x = redx[0], mx = redm[0];
+        for (int k = 1; k < kWaves; ++k) { m = max(m, red[k]); x |= redx[k]; mx += redm[k]; }
         atomicMax(maxoff, m);
         if (x) atomicMax(inexact, 1);
+        if (mx) atomicAdd(mixed, mx);
     }
 }
 
-// One thread per row writes its entries in column-major slot order; padding
-// slots get (col = row, value = 0).
+// One thread per row writes its entries in column-major slot order.  Slices
+// that are not uniform (or without su): CSR order, then padding slots with
+// (col = row, value = 0).  Uniform slices: the template's offsets go to su and
+// each entry to the slot of its offset; the other slots get value 0 and the
+// template's column, clamped to the row itself where it would leave the matrix
+// (the column the uniform read takes too).
 __global__ void __launch_bounds__(kBlock)
 k_sell_fill(int n, const int *__restrict__ rp, const int *__restrict__ ci, const double *__restrict__ v,
-            const int *__restrict__ sp, int *__restrict__ sc, short *__restrict__ sd, double *__restrict__ sv,
-            float *__restrict__ sv32) {
+            const int *__restrict__ sp, const int *__restrict__ uni, short *__restrict__ su, int *__restrict__ sc,
+            short *__restrict__ sd, double *__restrict__ sv, float *__restrict__ sv32) {
     const int i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
     const int sl = i / kSlice, lane = i % kSlice;
     const int base = sp[sl] + lane, w = (sp[sl + 1] - sp[sl]) / kSlice;
     const int q0 = rp[i], len = rp[i + 1] - q0;
-    for (int k = 0; k < w; ++k) {
-        const bool in = k < len;
-        const int col = in ? ci[q0 + k] : i;
-        const double val = in ? v[q0 + k] : 0.0;
+    auto put = [&](int k, int col, double val) {
         if (sd) sd[base + k * kSlice] = (short)(col - i);
         else sc[base + k * kSlice] = col;
         if (sv) sv[base + k * kSlice] = val;
         if (sv32) sv32[base + k * kSlice] = (float)val;
+    };
+    if (su && uni[sl]) {
+        // the slice's template: its first row of full width (rows past n are inactive)
+        const int t = __ffsll((unsigned long long)__ballot(len == w)) - 1;
+        const int it = sl * kSlice + t, qt = rp[it];
+        if (lane == t) {  // the template row is always active; the slice's last rows may not be
+            short *u = su + sp[sl] / kSlice;
+            for (int k = 0; k < w; ++k) u[k] = (short)(ci[qt + k] - it);
+        }
+        int j = 0;
+        for (int k = 0; k < w; ++k) {
+            const int o = ci[qt + k] - it;
+            const bool hit = j < len && ci[q0 + j] - i == o;
+            int col = i + o;
+            if ((unsigned)col >= (unsigned)n) col = i;
+            put(k, hit ? ci[q0 + j] : col, hit ? v[q0 + j] : 0.0);
+            if (hit) ++j;
+        }
+        return;
+    }
+    for (int k = 0; k < w; ++k) {
+        const bool in = k < len;
+        put(k, in ? ci[q0 + k] : i, in ? v[q0 + k] : 0.0);
     }
 }
 
@@ -1002,16 +1050,17 @@ void launch_diag_l1(hipStream_t s, int G, int n, const int *rp, const double *v,
     });
 }
 
-void launch_sell_width(hipStream_t s, int n, const int *rp, const int *ci, const double *v, int *cnt, int *maxoff,
-                       int *inexact) {
+void launch_sell_width(hipStream_t s, int n, const int *rp, const int *ci, const double *v, int *cnt, int *uni,
+                       int *maxoff, int *inexact, int *mixed) {
     const int ns = (n + kSlice - 1) / kSlice;
     const int nb = std::min(blocks_for((long long)ns * kSlice), 512);
-    hipLaunchKernelGGL(k_sell_width, dim3(nb), dim3(kBlock), 0, s, n, rp, ci, v, cnt, maxoff, inexact);
+    hipLaunchKernelGGL(k_sell_width, dim3(nb), dim3(kBlock), 0, s, n, rp, ci, v, cnt, uni, maxoff, inexact, mixed);
 }
 
-void launch_sell_fill(hipStream_t s, int n, const int *rp, const int *ci, const double *v, const int *sp, int *sc,
-                      short *sd, double *sv, float *sv32) {
-    hipLaunchKernelGGL(k_sell_fill, dim3(blocks_for(n)), dim3(kBlock), 0, s, n, rp, ci, v, sp, sc, sd, sv, sv32);
+void launch_sell_fill(hipStream_t s, int n, const int *rp, const int *ci, const double *v, const int *sp,
+                      const int *uni, short *su, int *sc, short *sd, double *sv, float *sv32) {
+    hipLaunchKernelGGL(k_sell_fill, dim3(blocks_for(n)), dim3(kBlock), 0, s, n, rp, ci, v, sp, uni, su, sc, sd, sv,
+                       sv32);
 }
 
 void launch_cast(hipStream_t s, size_t n, const double *src, float *dst) {

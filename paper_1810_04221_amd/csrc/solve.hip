@@ -88,18 +88,34 @@ __device__ __forceinline__ int sell_col(int c, int) { return c; }
 __device__ __forceinline__ int sell_col(short d, int i) { return i + (int)d; }
 
 // Row i of a sliced ELL matrix: sum_k a_k * f(col_k), left to right over the
-// row's slots (CSR order, then zero padding).  Lane i % 64 of a wave owns row i,
-// so every slot load of the wave is one contiguous access (64 x 2, 4 or 8 B).
-// Values are stored as S and multiplied as V (S = float under V = double only
-// when every value of the level is exactly a float: the conversion is exact).
+// row's slots (CSR order, with zero terms in between or after).  Lane i % 64 of
+// a wave owns row i, so every slot load of the wave is one contiguous access
+// (64 x 2, 4 or 8 B); the caller's waves are aligned to slices.  Values are
+// stored as S and multiplied as V (S = float under V = double only when every
+// value of the level is exactly a float: the conversion is exact).
+// A uniform slice (uni[s] = 1: every row's offsets are a subsequence of one
+// list) reads its column offsets from that list (su, from sp[s] / 64), one per
+// slot for the whole wave, instead of one per entry; a slot a row does not
+// have holds the value 0 (its column clamped into the matrix when it would
+// leave it).
 template <typename V, typename S, typename I, typename F>
-__device__ __forceinline__ V sell_row(const int *__restrict__ sp, const I *__restrict__ sc,
+__device__ __forceinline__ V sell_row(int n, const int *__restrict__ sp, const int *__restrict__ uni,
+                                      const short *__restrict__ su, const I *__restrict__ sc,
                                       const S *__restrict__ sv, int i, F f) {
-    const int sl = i / kSlice, lane = i % kSlice;
+    const int sl = __builtin_amdgcn_readfirstlane(i / kSlice), lane = i % kSlice;
     const int beg = sp[sl], w = (sp[sl + 1] - beg) / kSlice;
-    const I *c = sc + beg + lane;
     const S *a = sv + beg + lane;
     V s = V(0);
+    if (uni && uni[sl]) {
+        const short *u = su + beg / kSlice;
+#pragma unroll 4
+        for (int k = 0; k < w; ++k) {
+            const int c = i + (int)u[k];
+            s += (V)a[k * kSlice] * f((unsigned)c < (unsigned)n ? c : i);
+        }
+        return s;
+    }
+    const I *c = sc + beg + lane;
 #pragma unroll 4
     for (int k = 0; k < w; ++k) s += (V)a[k * kSlice] * f(sell_col(c[k * kSlice], i));
     return s;
@@ -174,13 +190,15 @@ k_down_loop(int nc, int mstride, const int *__restrict__ mem, const int *__restr
 // order (the order a serial P^T r takes).
 template <typename V, typename VB, typename I, typename S>
 __global__ void __launch_bounds__(kBlock)
-k_down_res_sell(int n, const int *__restrict__ sp, const I *__restrict__ sc, const S *__restrict__ sv,
+k_down_res_sell(int n, const int *__restrict__ sp, const int *__restrict__ uni,
+                const short *__restrict__ su, const I *__restrict__ sc,
+                const S *__restrict__ sv,
                 const V *__restrict__ dinv, const V *__restrict__ p, const VB *__restrict__ b, V *__restrict__ pr,
                 const double *__restrict__ done) {
     if (done && *done != 0.0) return;
     const int i = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
     if (i >= n) return;
-    const V s = sell_row<V, S, I>(sp, sc, sv, i, [&](int j) { return dinv[j] * (V)b[j]; });
+    const V s = sell_row<V, S, I>(n, sp, uni, su, sc, sv, i, [&](int j) { return dinv[j] * (V)b[j]; });
     pr[i] = p[i] * ((V)b[i] - s);
 }
 
@@ -272,13 +290,15 @@ k_smooth(int n, const int *__restrict__ rp, const int *__restrict__ ci, const V 
 // k_smooth on the sliced ELL copy, one thread per row.
 template <typename V, typename VB, typename VX, typename I, typename S>
 __global__ void __launch_bounds__(kBlock)
-k_smooth_sell(int n, const int *__restrict__ sp, const I *__restrict__ sc, const S *__restrict__ sv,
+k_smooth_sell(int n, const int *__restrict__ sp, const int *__restrict__ uni,
+                const short *__restrict__ su, const I *__restrict__ sc,
+              const S *__restrict__ sv,
               const V *__restrict__ dinv, const VB *__restrict__ b, const V *__restrict__ xp, VX *__restrict__ x,
               const double *__restrict__ done) {
     if (done && *done != 0.0) return;
     const int i = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
     if (i >= n) return;
-    const V s = sell_row<V, S, I>(sp, sc, sv, i, [&](int j) { return xp[j]; });
+    const V s = sell_row<V, S, I>(n, sp, uni, su, sc, sv, i, [&](int j) { return xp[j]; });
     x[i] = (VX)(xp[i] + dinv[i] * ((V)b[i] - s));
 }
 
@@ -797,13 +817,15 @@ k_spmv_dots(int n, const int *__restrict__ rp, const int *__restrict__ ci, const
 // left to right exactly as a serial CSR product.
 template <typename I, typename S>
 __global__ void __launch_bounds__(kBlock)
-k_resid_sell(int n, const int *__restrict__ sp, const I *__restrict__ sc, const S *__restrict__ sv,
+k_resid_sell(int n, const int *__restrict__ sp, const int *__restrict__ uni,
+                const short *__restrict__ su, const I *__restrict__ sc,
+             const S *__restrict__ sv,
              const double *__restrict__ b, const double *__restrict__ u, double *__restrict__ r,
              double *__restrict__ partials) {
     const int blk = xcd_block(blockIdx.x, gridDim.x);
     double acc[2] = {0.0, 0.0};
     for (int i = blk * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
-        const double s = sell_row<double, S, I>(sp, sc, sv, i, [&](int j) { return u[j]; });
+        const double s = sell_row<double, S, I>(n, sp, uni, su, sc, sv, i, [&](int j) { return u[j]; });
         const double bi = b[i];
         const double ri = bi - s;
         r[i] = ri;
@@ -815,14 +837,16 @@ k_resid_sell(int n, const int *__restrict__ sp, const I *__restrict__ sc, const 
 
 template <typename I, typename S>
 __global__ void __launch_bounds__(kBlock)
-k_spmv_dots_sell(int n, const int *__restrict__ sp, const I *__restrict__ sc, const S *__restrict__ sv,
+k_spmv_dots_sell(int n, const int *__restrict__ sp, const int *__restrict__ uni,
+                const short *__restrict__ su, const I *__restrict__ sc,
+                 const S *__restrict__ sv,
                  const double *__restrict__ w, const double *__restrict__ r, const double *__restrict__ q,
                  double *__restrict__ v, double *__restrict__ partials, const double *__restrict__ done) {
     if (done && *done != 0.0) return;
     const int blk = xcd_block(blockIdx.x, gridDim.x);
     double acc[3] = {0.0, 0.0, 0.0};
     for (int i = blk * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
-        const double s = sell_row<double, S, I>(sp, sc, sv, i, [&](int j) { return w[j]; });
+        const double s = sell_row<double, S, I>(n, sp, uni, su, sc, sv, i, [&](int j) { return w[j]; });
         const double wi = w[i];
         v[i] = s;
         acc[0] += wi * r[i];
@@ -953,7 +977,7 @@ void down_t(hipStream_t s, const Level &L, const V *a, const V *dinv, const V *p
                 using I = std::remove_const_t<std::remove_pointer_t<decltype(ix)>>;
                 using S = std::remove_const_t<std::remove_pointer_t<decltype(vals)>>;
                 launch_k((k_down_res_sell<V, VB, I, S>), dim3(blocks_for(L.A.n)), dim3(kBlock), s,
-                                   L.A.n, L.E.sp, ix, vals, dinv, p, b, pr, done);
+                                   L.A.n, L.E.sp, L.E.uni, L.E.su, ix, vals, dinv, p, b, pr, done);
             });
         if (part == 1) return;
         if (L.mstride == 4)
@@ -985,7 +1009,7 @@ void up_t(hipStream_t s, const Level &L, const V *a, const V *dinv, const V *p, 
                 using I = std::remove_const_t<std::remove_pointer_t<decltype(ix)>>;
                 using S = std::remove_const_t<std::remove_pointer_t<decltype(vals)>>;
                 launch_k((k_smooth_sell<V, VB, VX, I, S>), dim3(blocks_for(L.A.n)), dim3(kBlock), s,
-                                   L.A.n, L.E.sp, ix, vals, dinv, b, xp, x, done);
+                                   L.A.n, L.E.sp, L.E.uni, L.E.su, ix, vals, dinv, b, xp, x, done);
             });
             return;
         }
@@ -1192,7 +1216,7 @@ void launch_resid(hipStream_t s, const Level &L, int nb, const double *b, const 
         with_sell<double>(L.E, [&](auto *ix, auto *vals) {
             using I = std::remove_const_t<std::remove_pointer_t<decltype(ix)>>;
             using S = std::remove_const_t<std::remove_pointer_t<decltype(vals)>>;
-            hipLaunchKernelGGL((k_resid_sell<I, S>), dim3(nb), dim3(kBlock), 0, s, L.A.n, L.E.sp, ix, vals, b, u, r,
+            hipLaunchKernelGGL((k_resid_sell<I, S>), dim3(nb), dim3(kBlock), 0, s, L.A.n, L.E.sp, L.E.uni, L.E.su, ix, vals, b, u, r,
                                partials);
         });
         return;
@@ -1210,7 +1234,7 @@ void launch_spmv_dots(hipStream_t s, const Level &L, int nb, int first, const do
         with_sell<double>(L.E, [&](auto *ix, auto *vals) {
             using I = std::remove_const_t<std::remove_pointer_t<decltype(ix)>>;
             using S = std::remove_const_t<std::remove_pointer_t<decltype(vals)>>;
-            launch_k((k_spmv_dots_sell<I, S>), dim3(nb), dim3(kBlock), s, L.A.n, L.E.sp, ix, vals, w, r,
+            launch_k((k_spmv_dots_sell<I, S>), dim3(nb), dim3(kBlock), s, L.A.n, L.E.sp, L.E.uni, L.E.su, ix, vals, w, r,
                                q, v, partials, scal + 10);
         });
         return;

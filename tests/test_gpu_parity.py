@@ -332,6 +332,41 @@ def test_hierarchy_dense_blocks_and_hub_rows(B, ora, group):
     h.close()
 
 
+def test_sell_uniform_and_mixed_slices(B, ora):
+    # a 7-point grid (slices whose rows share one offset list: offsets read once
+    # per slice) with a few long couplings added (their slices store offsets per
+    # entry); both kinds in one matrix, against the oracle
+    rp, ci, va = P.poisson3d(40)
+    n = len(rp) - 1
+    A = sp.csr_matrix((va, ci, rp), shape=(n, n)).tolil()
+    rng = np.random.default_rng(31)
+    for _ in range(60):
+        i = int(rng.integers(0, n - 20000))
+        j = i + int(rng.integers(2, 20000))  # offsets within int16: the copy keeps int16 offsets
+        a = -rng.uniform(0.1, 0.5)
+        A[i, j] = A[j, i] = a
+        A[i, i] = A[i, i] - a
+        A[j, j] = A[j, j] - a
+    A = A.tocsr()
+    A.sort_indices()
+    rp, ci, va = A.indptr.astype(np.int32), A.indices.astype(np.int32), A.data.copy()
+    say(f"sliced ELL uniform and mixed slices n={n}")
+    for precision, bound in (("fp64", 1e-12), ("fp32", 1e-5)):
+        h = B.Hierarchy(rp, ci, va, max_coarse=100, precision=precision)
+        ho = ora.Hierarchy(rp, ci, va, np.ones(n), max_coarse=100)
+        if precision == "fp64":
+            _compare_hierarchy(h, ho)
+        r = P.uniform_rhs(n, 23)
+        z, zo = h.precond(r).cpu().numpy(), ho.vcycle(r)
+        assert np.linalg.norm(z - zo) <= bound * np.linalg.norm(zo)
+        b = P.uniform_rhs(n, 24)
+        x = h.solve(b, tol=1e-8).cpu().numpy()
+        assert np.linalg.norm(b - A @ x) <= 1e-8 * np.linalg.norm(b)
+        _, io = ho.solve(b, tol=1e-8)
+        assert abs(h.info()["iters"] - io["iters"]) <= (1 if precision == "fp64" else max(2, io["iters"] // 5))
+        h.close()
+
+
 def test_sell_int32_columns_for_long_range_couplings(B, ora):
     # offsets |col - row| beyond int16: the sliced-ELL copies keep int32 columns
     rp, ci, va = P.random_spd(70000, 4e-5, 23)
