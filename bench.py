@@ -223,6 +223,10 @@ ABLATIONS = {
     # one flexible-CG iteration replayed from a HIP graph, or every kernel launched
     "graph": [(f"{cy} {pr} {'graph replay' if g else 'eager launches'}", pr, dict(cycle=cy, graph=g))
               for cy in ("V", "W") for pr in ("fp64", "fp32") for g in (True, False)],
+    # V-cycle levels from the first with at most 2048 rows applied as one dense
+    # operator formed at setup, or level by level
+    "fold": [(f"V {pr} {'folded small levels' if f else 'level by level'}", pr, dict(fold=f))
+             for pr in ("fp64", "fp32") for f in (True, False)],
     # the smooth vector w the matching weights and prolongator are built from
     "smoothvec": [(f"w = {wk} {pr}", pr, dict(wvec=wk)) for pr in ("fp64", "fp32")
                   for wk in ("ones", "uniform[0.5,1.5)", "grid sine (lowest Laplacian mode)")],
