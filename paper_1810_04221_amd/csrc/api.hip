@@ -468,14 +468,13 @@ int build_hierarchy(bcm_handle *h, const bcm_csr *Ain, const double *win) {
             L.dinv32 = h->persist.get_n<float>(nl_);
             L.A.v32 = h->persist.get_n<float>(L.A.nnz);
             NOMEM(L.dinv32 && L.A.v32);
-            launch_cast(s, L.A.nnz, L.A.v, L.A.v32);
             if (l < h->nl - 1) {
                 L.p32 = h->persist.get_n<float>(nl_);
                 NOMEM(L.p32);
                 launch_cast(s, nl_, L.p, L.p32);
             }
         }
-        launch_diag_l1(s, L.G, nl_, L.A.rp, L.A.v, L.dinv, L.dinv32);
+        launch_diag_l1(s, L.G, nl_, L.A.rp, L.A.v, L.dinv, L.dinv32, L.A.v32);
         if (l < h->nl - 1 && nl_ >= kSplitUp) {
             L.xp = h->persist.get((fp32 ? sizeof(float) : sizeof(double)) * nl_);
             NOMEM(L.xp);

@@ -221,7 +221,7 @@ void launch_compose(hipStream_t s, int n, int nc_new, const int *agg_prev, const
                     const int *mem_prev, int stride_prev, const int *agg_s, const double *p_s,
                     const int *mem_s, int *agg_out, double *p_out, int *mem_out);
 void launch_diag_l1(hipStream_t s, int G, int n, const int *rp, const double *v, double *dinv,
-                    float *dinv32);
+                    float *dinv32, float *v32);
 void launch_cast(hipStream_t s, size_t n, const double *src, float *dst);
 // slice widths (64 * longest row of each slice) -> cnt[nslices]; *maxoff is
 // raised to the largest |col - row| of the matrix, *inexact to 1 if a value is

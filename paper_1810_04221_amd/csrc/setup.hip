@@ -603,13 +603,18 @@ k_compose_members(int nc_new, const int *__restrict__ mem_prev, int stride_prev,
 template <int G>
 __global__ void __launch_bounds__(kBlock)
 k_diag_l1(int n, const int *__restrict__ rp, const double *__restrict__ v, double *__restrict__ dinv,
-          float *__restrict__ dinv32) {
+          float *__restrict__ dinv32, float *__restrict__ v32) {
+    // (with v32 given, the row's values are also written rounded to float32)
     const int lane = threadIdx.x % G;
     const int row = (xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x) / G;
     if (row >= n) return;
     double s = 0.0;
     const int e = rp[row + 1];
-    for (int q = rp[row] + lane; q < e; q += G) s += fabs(v[q]);
+    for (int q = rp[row] + lane; q < e; q += G) {
+        const double a = v[q];
+        s += fabs(a);
+        if (v32) v32[q] = (float)a;
+    }
     s = group_sum<G>(s);
     if (lane == 0) {
         const double d = 1.0 / s;
@@ -619,9 +624,11 @@ k_diag_l1(int n, const int *__restrict__ rp, const double *__restrict__ v, doubl
 }
 
 // Sliced ELL: width of slice s (times 64) = 64 * max row length over its rows.
-// A slice is uniform when every row's column offsets (col - row, ascending) are
-// a subsequence of those of its first full-width row, the template: uni[s] = 1,
-// and the slots of the slices that are not add up in *mixed.
+// A slice of width at most 64 is uniform when every row's column offsets
+// (col - row, ascending) are a subsequence of those of its first full-width
+// row, the template: uni[s] = 1; the slots of the slices that are not add up in
+// *mixed.  The template's offsets are staged in LDS and each row's are loaded
+// eight at a time, so the comparison waits on few memory round trips.
 __global__ void __launch_bounds__(kBlock)
 k_sell_width(int n, const int *__restrict__ rp, const int *__restrict__ ci, const double *__restrict__ v,
              int *__restrict__ cnt, int *__restrict__ uni, int *__restrict__ maxoff, int *__restrict__ inexact,
@@ -631,6 +638,7 @@ k_sell_width(int n, const int *__restrict__ rp, const int *__restrict__ ci, cons
     static_assert(kBlock % kSlice == 0, "a block must hold whole slices");
     constexpr int kWaves = kBlock / kSlice;
     __shared__ int red[kWaves], redx[kWaves], redm[kWaves];
+    __shared__ int tmpl[kWaves][kSlice];
     const int ns = (n + kSlice - 1) / kSlice;
     const int lane = threadIdx.x % kSlice, wv = threadIdx.x / kSlice;
     int off = 0, inx = 0, mix = 0;
@@ -648,17 +656,27 @@ k_sell_width(int n, const int *__restrict__ rp, const int *__restrict__ ci, cons
         for (int o = kSlice / 2; o > 0; o >>= 1) w = max(w, __shfl_xor(w, o, kSlice));
         const int t = __ffsll((unsigned long long)__ballot(len == w)) - 1;
         const int it = sl * kSlice + t, qt = rp[it];
-        int ok = 1;
-        if (i < n) {
+        int *T = tmpl[wv];
+        if (lane < w) T[lane] = ci[qt + lane] - it;
+        wave_sync();
+        int ok = w <= kSlice ? 1 : 0;
+        if (i < n && ok) {
             // merge walk: each offset of this row must appear in the template, in order
             int k = 0;
-            for (int j = 0; j < len && ok; ++j) {
-                const int o = ci[q0 + j] - i;
-                while (k < w && ci[qt + k] - it != o) ++k;
-                if (k == w) ok = 0;
-                ++k;
+            for (int j0 = 0; j0 < len && ok; j0 += 8) {
+                int o[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) o[u] = j0 + u < len ? ci[q0 + j0 + u] - i : 0;
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    if (j0 + u >= len || !ok) continue;
+                    while (k < w && T[k] != o[u]) ++k;
+                    if (k == w) ok = 0;
+                    ++k;
+                }
             }
         }
+        wave_sync();  // the template slots are rewritten by this wave's next slice
         const bool u = __ballot(!ok) == 0;
         if (lane == 0) {
             cnt[sl] = w * kSlice;
@@ -703,21 +721,47 @@ k_sell_fill(int n, const int *__restrict__ rp, const int *__restrict__ ci, const
         if (sv32) sv32[base + k * kSlice] = (float)val;
     };
     if (su && uni[sl]) {
-        // the slice's template: its first row of full width (rows past n are inactive)
+        // the slice's template: its first row of full width (rows past n are
+        // inactive); uniform slices have w <= 64
+        __shared__ int tmpl[kBlock / kSlice][kSlice];
         const int t = __ffsll((unsigned long long)__ballot(len == w)) - 1;
         const int it = sl * kSlice + t, qt = rp[it];
+        int *T = tmpl[(threadIdx.x % kBlock) / kSlice];
         if (lane == t) {  // the template row is always active; the slice's last rows may not be
             short *u = su + sp[sl] / kSlice;
-            for (int k = 0; k < w; ++k) u[k] = (short)(ci[qt + k] - it);
+            for (int k = 0; k < w; ++k) {
+                const int o = ci[qt + k] - it;
+                u[k] = (short)o;
+                T[k] = o;
+            }
         }
-        int j = 0;
-        for (int k = 0; k < w; ++k) {
-            const int o = ci[qt + k] - it;
-            const bool hit = j < len && ci[q0 + j] - i == o;
-            int col = i + o;
+        wave_sync();
+        int k = 0;
+        for (int j0 = 0; j0 < len; j0 += 8) {
+            int c[8];
+            double a[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                c[u] = j0 + u < len ? ci[q0 + j0 + u] : i;
+                a[u] = j0 + u < len ? v[q0 + j0 + u] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                if (j0 + u >= len) continue;
+                // slots before this entry's offset hold zeros (the offset is in
+                // the template: the slice was checked uniform with the same one)
+                for (; k < w && T[k] != c[u] - i; ++k) {
+                    int col = i + T[k];
+                    if ((unsigned)col >= (unsigned)n) col = i;
+                    put(k, col, 0.0);
+                }
+                if (k < w) put(k++, c[u], a[u]);
+            }
+        }
+        for (; k < w; ++k) {
+            int col = i + T[k];
             if ((unsigned)col >= (unsigned)n) col = i;
-            put(k, hit ? ci[q0 + j] : col, hit ? v[q0 + j] : 0.0);
-            if (hit) ++j;
+            put(k, col, 0.0);
         }
         return;
     }
@@ -1042,11 +1086,11 @@ void launch_compose(hipStream_t s, int n, int nc_new, const int *agg_prev, const
 }
 
 void launch_diag_l1(hipStream_t s, int G, int n, const int *rp, const double *v, double *dinv,
-                    float *dinv32) {
+                    float *dinv32, float *v32) {
     with_G(G, [&](auto gc) {
         constexpr int g = decltype(gc)::value;
         hipLaunchKernelGGL(k_diag_l1<g>, dim3(blocks_for((long long)n * g)), dim3(kBlock), 0, s, n, rp, v, dinv,
-                           dinv32);
+                           dinv32, v32);
     });
 }
 
