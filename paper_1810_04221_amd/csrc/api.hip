@@ -568,22 +568,31 @@ int build_hierarchy(bcm_handle *h, const bcm_csr *Ain, const double *win) {
             }
         }
     }
-    if (P.fold && P.cycle == BCM_VCYCLE && h->nl >= 3 && h->lv[h->nl - 1].S) {
-        // V-cycle: the levels from the first k >= 1 with at most kFoldRows rows
-        // down to the coarsest, formed once as one dense operator (built upwards
-        // from the coarsest level's sweep operator)
+    if (P.fold && h->nl >= 3 && h->lv[h->nl - 1].S) {
+        // The cycle from the first level k >= 1 with at most kFoldRows rows down to
+        // the coarsest, formed once as one dense operator (built upwards from the
+        // coarsest level's sweep operator): V- and W-cycles, and K-cycles whose
+        // Krylov coarse solves all sit above that level.
         int kf = h->nl - 1;
         while (kf > 1 && h->lv[kf - 1].A.n <= kFoldRows) --kf;
-        if (kf < h->nl - 1) {
+        const bool wcyc = P.cycle == BCM_WCYCLE;
+        const bool linear = P.cycle != BCM_KCYCLE || (P.kcycle_levels > 0 && P.kcycle_levels <= kf);
+        if (kf < h->nl - 1 && linear) {
             tmp.rewind();
             const double *Tc = h->lv[h->nl - 1].S;
             for (int k = h->nl - 2; k >= kf; --k) {
-                const Level &L = h->lv[k];
-                const size_t nn2 = (size_t)L.A.n * L.A.n;
+                const Level &L = h->lv[k], &C = h->lv[k + 1];
+                const size_t nn2 = (size_t)L.A.n * L.A.n, nc2 = (size_t)C.A.n * C.A.n;
+                if (wcyc) {  // the coarse problem solved by two cycles of level k + 1
+                    double *M = tmp.get_n<double>(nc2), *W = tmp.get_n<double>(nc2);
+                    NOMEM(M && W);
+                    launch_fold_w(s, C, Tc, M, W);
+                    Tc = W;
+                }
                 double *T = k == kf ? h->persist.get_n<double>(nn2) : tmp.get_n<double>(nn2);
                 double *H = tmp.get_n<double>(nn2);
                 NOMEM(T && H);
-                launch_fold_level(s, L, Tc, h->lv[k + 1].A.n, H, T);
+                launch_fold_level(s, L, Tc, C.A.n, H, T);
                 Tc = T;
             }
             h->kf = kf;
@@ -748,11 +757,8 @@ double bytes_fold(const bcm_handle *h) {
 double bytes_cycle(const bcm_handle *h) {
     const double sv = h->prm.precision == BCM_FP32_CYCLE ? 4 : 8;
     double total = 0.0, visits = 1.0;
-    if (h->kf > 0) {
-        for (int k = 0; k < h->kf; ++k) total += bytes_down(h, k) + bytes_up(h, k);
-        return total + bytes_fold(h);
-    }
-    for (int k = 0; k + 1 < h->nl; ++k) {
+    const int kend = h->kf > 0 ? h->kf : h->nl - 1;  // levels below kend: the folded operator
+    for (int k = 0; k < kend; ++k) {
         total += visits * (bytes_down(h, k) + bytes_up(h, k));
         const Level &C = h->lv[k + 1];
         const double n = C.A.n, spmv = 4 * (n + 1) + (4 + sv) * C.A.nnz;
@@ -764,7 +770,7 @@ double bytes_cycle(const bcm_handle *h) {
             visits *= 2;
         }
     }
-    return total + visits * bytes_coarse(h);
+    return total + visits * (h->kf > 0 ? bytes_fold(h) : bytes_coarse(h));
 }
 double bytes_spmv_dots(const bcm_handle *h) {
     const Level &L = h->lv[0];
@@ -920,6 +926,12 @@ void cycle_level(bcm_handle *h, Prof &pf, int k, const double *done, int iter) {
     hipStream_t s = h->s;
     const int fp32 = h->prm.precision == BCM_FP32_CYCLE;
     Level &L = h->lv[k];
+    if (k == h->kf) {  // this level and every coarser one as one dense operator
+        int e = pf.begin(5);
+        launch_dense(s, L.A.n, h->fold, L.b, L.x, !fp32, !fp32, done);
+        pf.end(5, e, bytes_fold(h), iter);
+        return;
+    }
     if (k == h->kt) {  // this level and every coarser one in one workgroup
         int e = pf.begin(5);
         launch_tail(s, fp32, k, h->nl, h->tail, h->lv[h->nl - 1], h->prm.coarse_sweeps, h->tail_ops, h->n_tail_ops,

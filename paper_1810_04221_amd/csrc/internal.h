@@ -173,7 +173,8 @@ struct bcm_handle {
     double *ctmp[2] = {nullptr, nullptr};  // coarsest-level sweep buffers when n > kCoarseLds
     bcm::TailLevel *tail = nullptr;        // device table of levels for the tail kernel
     int kt = -1;                           // first level handled by the tail kernel (-1: none)
-    int kf = 0;                            // first level of the folded dense operator (0: none)
+    int kf = 0;                            // first level of the folded dense operator (0: none):
+                                           // the V- or W-cycle from level kf down, as one n_kf x n_kf map
     double *fold = nullptr;                // that operator, n_kf x n_kf row-major, float64
     int *tail_ops = nullptr;               // the tail kernel's program (device)
     int n_tail_ops = 0;
@@ -278,6 +279,9 @@ void launch_coarse_build(hipStream_t s, const Level &L, int sweeps, double *S);
 // (nc x nc): T = D + (I - D A)(D + P Tc P^T (I - A D)), n x n row-major; H is
 // n x n scratch.  A must be exactly symmetric (every coarse level is).
 void launch_fold_level(hipStream_t s, const Level &L, const double *Tc, int nc, double *H, double *T);
+// W-cycle coarse solve of the level above L by two cycles of L: W = 2T - T A T
+// (T, W n x n row-major; M n x n scratch)
+void launch_fold_w(hipStream_t s, const Level &L, const double *T, double *M, double *W);
 // T = D + (I - D A) H for dense n x n row-major H and T (level L's matrix)
 void launch_fold_left(hipStream_t s, const Level &L, const double *H, double *T);
 // x = T b with a dense n x n row-major float64 operator (float64 accumulation)

@@ -568,6 +568,33 @@ k_fold_h(int n, int nc, const int *__restrict__ rp, const int *__restrict__ ci, 
     H[idx] = (i == j ? dinv[i] : 0.0) + gij - dinv[j] * s;
 }
 
+// W-cycle: the coarse problem of a level is solved by two cycles of the level
+// below, the second on the residual of the first: W = T + T (I - A T) = 2T - T A T.
+// M = A T (sparse rows of A against the dense columns of T):
+__global__ void __launch_bounds__(kBlock)
+k_fold_at(int n, const int *__restrict__ rp, const int *__restrict__ ci, const double *__restrict__ a,
+          const double *__restrict__ T, double *__restrict__ M) {
+    const long long idx = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (idx >= (long long)n * n) return;
+    const int i = (int)(idx / n), j = (int)(idx % n);
+    double s = 0.0;
+    for (int q = rp[i]; q < rp[i + 1]; ++q) s += a[q] * T[(size_t)ci[q] * n + j];
+    M[idx] = s;
+}
+
+// W_ij = 2 T_ij - sum_k T_ik M_kj (one thread per entry; the row of T is
+// shared by the wave, the column of M read coalesced)
+__global__ void __launch_bounds__(kBlock)
+k_fold_w(int n, const double *__restrict__ T, const double *__restrict__ M, double *__restrict__ W) {
+    const long long idx = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (idx >= (long long)n * n) return;
+    const int i = (int)(idx / n), j = (int)(idx % n);
+    const double *ti = T + (size_t)i * n;
+    double s = 0.0;
+    for (int k = 0; k < n; ++k) s += ti[k] * M[(size_t)k * n + j];
+    W[idx] = 2.0 * T[idx] - s;
+}
+
 // T = D + (I - D A) H:  T_ij = [i = j] dinv_i + H_ij - dinv_i sum_{k in row i} a_ik H_kj
 __global__ void __launch_bounds__(kBlock)
 k_fold_t(int n, const int *__restrict__ rp, const int *__restrict__ ci, const double *__restrict__ a,
@@ -1187,6 +1214,13 @@ void launch_fold_level(hipStream_t s, const Level &L, const double *Tc, int nc, 
     const int nb = blocks_for((long long)n * n);
     hipLaunchKernelGGL(k_fold_h, dim3(nb), dim3(kBlock), 0, s, n, nc, L.A.rp, L.A.ci, L.A.v, L.dinv, L.p, L.agg, Tc, H);
     hipLaunchKernelGGL(k_fold_t, dim3(nb), dim3(kBlock), 0, s, n, L.A.rp, L.A.ci, L.A.v, L.dinv, H, T);
+}
+
+void launch_fold_w(hipStream_t s, const Level &L, const double *T, double *M, double *W) {
+    const int n = L.A.n;
+    const int nb = blocks_for((long long)n * n);
+    hipLaunchKernelGGL(k_fold_at, dim3(nb), dim3(kBlock), 0, s, n, L.A.rp, L.A.ci, L.A.v, T, M);
+    hipLaunchKernelGGL(k_fold_w, dim3(nb), dim3(kBlock), 0, s, n, T, M, W);
 }
 
 void launch_fold_left(hipStream_t s, const Level &L, const double *H, double *T) {

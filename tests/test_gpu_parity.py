@@ -147,20 +147,24 @@ def test_precond_fp32_cycle_error_bound(B, ora, name, scale):
 
 @pytest.mark.parametrize("name,scale", [("G1", 1.0), ("G2", 0.3), ("G5", 0.2), ("G4", 0.21)])
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
-def test_folded_coarse_levels(B, ora, name, scale, precision):
+@pytest.mark.parametrize("cycle,klevels", [("V", 0), ("W", 0), ("K", 1)])
+def test_folded_coarse_levels(B, ora, name, scale, precision, cycle, klevels):
     # the small levels' cycle applied as one precomputed float64 operator
     # (the default) against the level-by-level cycle and the oracle: the same
     # linear map, rounded differently (fold from level 1 in G1 and G4, from
-    # level 2 over four levels in G2)
+    # level 2 over four levels in G2).  W: each folded level's coarse problem
+    # is 2T - T A T of the level below; K on the finest level: its two Krylov
+    # steps use the folded cycle of level 1 and below.
     c = P.config(name, scale)
-    say(f"folded levels {precision} {c['name']}")
-    ho = ora.Hierarchy(c["rowptr"], c["col"], c["val"], c["w"], max_coarse=c["max_coarse"])
+    say(f"folded levels {cycle} {precision} {c['name']}")
+    ho = ora.Hierarchy(c["rowptr"], c["col"], c["val"], c["w"], max_coarse=c["max_coarse"], cycle=cycle,
+                       kcycle_levels=klevels)
     r = P.uniform_rhs(c["n"], 21)
     zo = ho.vcycle(r)
     zs = []
     for fold in (True, False):
         h = B.Hierarchy(c["rowptr"], c["col"], c["val"], c["w"], max_coarse=c["max_coarse"], precision=precision,
-                        fold=fold)
+                        fold=fold, cycle=cycle, kcycle_levels=klevels)
         zs.append(h.precond(r).cpu().numpy())
         h.close()
     bound = 1e-12 if precision == "fp64" else 1e-5
