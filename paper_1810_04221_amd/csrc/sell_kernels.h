@@ -1,0 +1,157 @@
+// Row-parallel kernels of the finest level and the other sliced-ELL levels:
+// the residual and the flexible-CG product with its dot products, the down
+// leg's residual, the up leg's smoothing, and the flexible-CG update.  Kept in
+// a file of their own so that the HBM counter traffic recorded for them is
+// tied to this source alone.  Included once, inside the solve library's
+// anonymous namespace.
+#pragma once
+#include "device.h"
+#include "internal.h"
+
+// Column of a sliced-ELL slot: int32 columns, or int16 offsets col - row.
+__device__ __forceinline__ int sell_col(int c, int) { return c; }
+__device__ __forceinline__ int sell_col(short d, int i) { return i + (int)d; }
+
+// Row i of a sliced ELL matrix: sum_k a_k * f(col_k), left to right over the
+// row's slots (CSR order, with zero terms in between or after).  Lane i % 64 of
+// a wave owns row i, so every slot load of the wave is one contiguous access
+// (64 x 2, 4 or 8 B); the caller's waves are aligned to slices.  Values are
+// stored as S and multiplied as V (S = float under V = double only when every
+// value of the level is exactly a float: the conversion is exact).
+// A uniform slice (uni[s] = 1: every row's offsets are a subsequence of one
+// list) reads its column offsets from that list (su, from sp[s] / 64), one per
+// slot for the whole wave, instead of one per entry; a slot a row does not
+// have holds the value 0 (its column clamped into the matrix when it would
+// leave it).
+template <typename V, typename S, typename I, typename F>
+__device__ __forceinline__ V sell_row(int n, const int *__restrict__ sp, const int *__restrict__ uni,
+                                      const short *__restrict__ su, const I *__restrict__ sc,
+                                      const S *__restrict__ sv, int i, F f) {
+    const int sl = __builtin_amdgcn_readfirstlane(i / kSlice), lane = i % kSlice;
+    const int beg = sp[sl], w = (sp[sl + 1] - beg) / kSlice;
+    const S *a = sv + beg + lane;
+    V s = V(0);
+    if (uni && uni[sl]) {
+        const short *u = su + beg / kSlice;
+#pragma unroll 4
+        for (int k = 0; k < w; ++k) {
+            const int c = i + (int)u[k];
+            s += (V)a[k * kSlice] * f((unsigned)c < (unsigned)n ? c : i);
+        }
+        return s;
+    }
+    const I *c = sc + beg + lane;
+#pragma unroll 4
+    for (int k = 0; k < w; ++k) s += (V)a[k * kSlice] * f(sell_col(c[k * kSlice], i));
+    return s;
+}
+
+
+// Large levels: the down leg as a row-parallel residual on the sliced ELL copy,
+//   pr_i = p_i (b_i - sum_j a_ij dinv_j b_j),
+// followed by the restriction b_c[E] = sum of pr over E's members in ascending
+// order (the order a serial P^T r takes).
+template <typename V, typename VB, typename I, typename S>
+__global__ void __launch_bounds__(kBlock)
+k_down_res_sell(int n, const int *__restrict__ sp, const int *__restrict__ uni,
+                const short *__restrict__ su, const I *__restrict__ sc,
+                const S *__restrict__ sv,
+                const V *__restrict__ dinv, const V *__restrict__ p, const VB *__restrict__ b, V *__restrict__ pr,
+                const double *__restrict__ done) {
+    if (done && *done != 0.0) return;
+    const int i = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const V s = sell_row<V, S, I>(n, sp, uni, su, sc, sv, i, [&](int j) { return dinv[j] * (V)b[j]; });
+    pr[i] = p[i] * ((V)b[i] - s);
+}
+
+
+// k_smooth on the sliced ELL copy, one thread per row.
+template <typename V, typename VB, typename VX, typename I, typename S>
+__global__ void __launch_bounds__(kBlock)
+k_smooth_sell(int n, const int *__restrict__ sp, const int *__restrict__ uni,
+                const short *__restrict__ su, const I *__restrict__ sc,
+              const S *__restrict__ sv,
+              const V *__restrict__ dinv, const VB *__restrict__ b, const V *__restrict__ xp, VX *__restrict__ x,
+              const double *__restrict__ done) {
+    if (done && *done != 0.0) return;
+    const int i = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const V s = sell_row<V, S, I>(n, sp, uni, su, sc, sv, i, [&](int j) { return xp[j]; });
+    x[i] = (VX)(xp[i] + dinv[i] * ((V)b[i] - s));
+}
+
+
+// Sliced-ELL variants: one thread per row, grid-stride; each row sum is taken
+// left to right exactly as a serial CSR product.
+template <typename I, typename S>
+__global__ void __launch_bounds__(kBlock)
+k_resid_sell(int n, const int *__restrict__ sp, const int *__restrict__ uni,
+                const short *__restrict__ su, const I *__restrict__ sc,
+             const S *__restrict__ sv,
+             const double *__restrict__ b, const double *__restrict__ u, double *__restrict__ r,
+             double *__restrict__ partials) {
+    const int blk = xcd_block(blockIdx.x, gridDim.x);
+    double acc[2] = {0.0, 0.0};
+    for (int i = blk * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+        const double s = sell_row<double, S, I>(n, sp, uni, su, sc, sv, i, [&](int j) { return u[j]; });
+        const double bi = b[i];
+        const double ri = bi - s;
+        r[i] = ri;
+        acc[0] += ri * ri;
+        acc[1] += bi * bi;
+    }
+    block_partials<2>(acc, partials);
+}
+
+template <typename I, typename S>
+__global__ void __launch_bounds__(kBlock)
+k_spmv_dots_sell(int n, const int *__restrict__ sp, const int *__restrict__ uni,
+                const short *__restrict__ su, const I *__restrict__ sc,
+                 const S *__restrict__ sv,
+                 const double *__restrict__ w, const double *__restrict__ r, const double *__restrict__ q,
+                 double *__restrict__ v, double *__restrict__ partials, const double *__restrict__ done) {
+    if (done && *done != 0.0) return;
+    const int blk = xcd_block(blockIdx.x, gridDim.x);
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (int i = blk * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+        const double s = sell_row<double, S, I>(n, sp, uni, su, sc, sv, i, [&](int j) { return w[j]; });
+        const double wi = w[i];
+        v[i] = s;
+        acc[0] += wi * r[i];
+        acc[1] += wi * s;
+        acc[2] += wi * q[i];
+    }
+    block_partials<3>(acc, partials);
+}
+
+
+// The two fused AXPY pairs of Algorithm 3 and partials of ||r||^2:
+//   d = w - g d ; u += an d ; q = v - g q ; r -= an q   (first step: d = w, q = v)
+// with g = gamma_i / rho_{i-1} and an = alpha_i / rho_i from the finalize step.
+__global__ void __launch_bounds__(kBlock)
+k_update(int n, int first, const double *__restrict__ w, const double *__restrict__ v, double *__restrict__ d,
+         double *__restrict__ u, double *__restrict__ q, double *__restrict__ r,
+         const double *__restrict__ scal, double *__restrict__ partials) {
+    if (scal[10] != 0.0) return;
+    const bool ok = scal[6] == 0.0;
+    const double g = scal[8], an = scal[9];
+    double acc[1] = {0.0};
+    if (ok) {
+        const int blk = xcd_block(blockIdx.x, gridDim.x);
+        for (int i = blk * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+            const double wi = w[i], vi = v[i];
+            double di, qi;
+            if (first) { di = wi; qi = vi; }
+            else { di = wi - g * d[i]; qi = vi - g * q[i]; }
+            d[i] = di;
+            q[i] = qi;
+            u[i] = u[i] + an * di;
+            const double ri = r[i] - an * qi;
+            r[i] = ri;
+            acc[0] += ri * ri;
+        }
+    }
+    block_partials<1>(acc, partials);
+}
+
