@@ -478,6 +478,10 @@ int build_hierarchy(bcm_handle *h, const bcm_csr *Ain, const double *win) {
         if (l < h->nl - 1 && nl_ >= kSplitUp) {
             L.xp = h->persist.get((fp32 ? sizeof(float) : sizeof(double)) * nl_);
             NOMEM(L.xp);
+            if (L.A.nnz >= (long long)kGatherRow * nl_) {
+                L.yb = h->persist.get((fp32 ? sizeof(float) : sizeof(double)) * nl_);
+                NOMEM(L.yb);
+            }
         }
         if (l > 0) {
             const size_t es = fp32 ? sizeof(float) : sizeof(double);
@@ -707,7 +711,8 @@ double bytes_down(const bcm_handle *h, int k) {
     const bool sell = L.E.sp && L.xp && (L.mstride == 2 || L.mstride == 4);
     const double base = 4 * (n + 1) + (index_bytes(L, sell) + value_bytes(L, sell, f32)) * z + sb * n + 2 * sv * n +
                         4.0 * nc * L.mstride + sv * nc;
-    return sell ? base + 2 * sv * n : base;
+    // split leg: p r written and read; with yb, dinv o b formed first (b, dinv read, y written)
+    return sell ? base + 2 * sv * n + (L.yb ? (sb + 2 * sv) * n : 0.0) : base;
 }
 // up leg: fused k_up, or k_prolong + k_smooth on large levels (xp written and read once)
 double bytes_up(const bcm_handle *h, int k) {

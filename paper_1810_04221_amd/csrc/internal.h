@@ -38,6 +38,8 @@ constexpr int kCoarseDense = 2048; // largest coarsest level applied as a precom
 constexpr int kCoarseBuildSweeps = 1024;  // up to this size S is built by sweeps on unit vectors
 constexpr int kFoldRows = 2048;    // V-cycle: levels from the first this small on form one dense operator
 constexpr int kSplitUp = 65536;    // levels at least this large run the up leg as prolong + smooth
+constexpr int kGatherRow = 16;     // sliced-ELL levels averaging this many entries per row gather dinv o b
+                                   // formed beforehand in the down leg (one vector instead of two)
 
 // Error flags raised by the validation kernel.
 enum : int {
@@ -125,6 +127,7 @@ struct Level {
     int *mem = nullptr;
     void *b = nullptr, *x = nullptr;  // cycle vectors for k >= 1 (cycle precision)
     void *xp = nullptr;               // prolonged iterate of the split up leg (cycle precision)
+    void *yb = nullptr;               // dinv o b of the down leg on sliced-ELL levels with long rows
     void *xs = nullptr;               // W/K-cycle: result of the second coarse cycle (cycle precision)
     void *kv = nullptr;               // K-cycle: A c1, the product of the first coarse direction
     double *S = nullptr;  // coarsest level only: dense sweep operator (n <= kCoarseDense)

@@ -57,11 +57,14 @@ k_down_res_sell(int n, const int *__restrict__ sp, const int *__restrict__ uni,
                 const short *__restrict__ su, const I *__restrict__ sc,
                 const S *__restrict__ sv,
                 const V *__restrict__ dinv, const V *__restrict__ p, const VB *__restrict__ b, V *__restrict__ pr,
-                const double *__restrict__ done) {
+                const V *__restrict__ y, const double *__restrict__ done) {
+    // y given (levels with long rows): dinv o b formed beforehand, one gather per term
     if (done && *done != 0.0) return;
     const int i = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
     if (i >= n) return;
-    const V s = sell_row<V, S, I>(n, sp, uni, su, sc, sv, i, [&](int j) { return dinv[j] * (V)b[j]; });
+    V s;
+    if (y) s = sell_row<V, S, I>(n, sp, uni, su, sc, sv, i, [&](int j) { return y[j]; });
+    else s = sell_row<V, S, I>(n, sp, uni, su, sc, sv, i, [&](int j) { return dinv[j] * (V)b[j]; });
     pr[i] = p[i] * ((V)b[i] - s);
 }
 

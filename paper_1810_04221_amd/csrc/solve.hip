@@ -150,6 +150,17 @@ k_down_loop(int nc, int mstride, const int *__restrict__ mem, const int *__restr
 }
 
 
+// y = dinv o b, the pre-smoothed iterate of the down leg, for the levels whose
+// residual kernel gathers it instead of dinv and b (long rows)
+template <typename V, typename VB>
+__global__ void __launch_bounds__(kBlock)
+k_scale(int n, const V *__restrict__ dinv, const VB *__restrict__ b, V *__restrict__ y,
+        const double *__restrict__ done) {
+    if (done && *done != 0.0) return;
+    const int i = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    if (i < n) y[i] = dinv[i] * (V)b[i];
+}
+
 template <typename V, int S>
 __global__ void __launch_bounds__(kBlock)
 k_restrict(int nc, const int *__restrict__ mem, const V *__restrict__ pr, V *__restrict__ bc,
@@ -664,16 +675,16 @@ k_tail(int kt, int nl, const TailLevel *__restrict__ tl, const double *__restric
     }
 }
 
-// One global l1-Jacobi sweep (coarsest levels larger than the LDS bound).
 // One l1-Jacobi sweep of a coarsest level too large for one workgroup's LDS:
 // xn = xo + D (b - A xo) (first: xo = 0, so xn = D b).  G lanes per row and R
-// rows per group, as in the cycle kernels.
-template <int G, int R, typename VB>
+// rows per group, as in the cycle kernels.  The last sweep of a solve writes
+// the caller's x (type VX) instead of xn.  The solve-ended flag is tested
+// before the stores only (as in k_down_seq).
+template <int G, int R, typename VB, typename VX>
 __global__ void __launch_bounds__(kBlock)
 k_jacobi_sweep(int n, const int *__restrict__ rp, const int *__restrict__ ci, const double *__restrict__ a,
                const double *__restrict__ dinv, const VB *__restrict__ b, const double *__restrict__ xo,
-               double *__restrict__ xn, int first, const double *__restrict__ done) {
-    if (done && *done != 0.0) return;
+               double *__restrict__ xn, VX *__restrict__ xout, int first, const double *__restrict__ done) {
     const int lane = threadIdx.x % G;
     const int g = (xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x) / G;
     int rows[R];
@@ -686,18 +697,16 @@ k_jacobi_sweep(int n, const int *__restrict__ rp, const int *__restrict__ ci, co
     } else {
         rows_dot<G, R, double>(rp, ci, a, rows, s, [&](int j) { return xo[j]; });
     }
+    const bool live = !(done && *done != 0.0);
 #pragma unroll
     for (int k = 0; k < R; ++k) {
         const int i = rows[k];
-        if (lane == k % G && i >= 0) xn[i] = (first ? 0.0 : xo[i]) + dinv[i] * ((double)b[i] - s[k]);
+        if (lane == k % G && i >= 0 && live) {
+            const double v = (first ? 0.0 : xo[i]) + dinv[i] * ((double)b[i] - s[k]);
+            if (xout) xout[i] = (VX)v;
+            else xn[i] = v;
+        }
     }
-}
-
-template <typename VX>
-__global__ void k_store(int n, const double *__restrict__ src, VX *__restrict__ dst, const double *__restrict__ done) {
-    if (done && *done != 0.0) return;
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i < n) dst[i] = (VX)src[i];
 }
 
 // ----------------------------------------------------------------------------
@@ -863,13 +872,18 @@ void down_t(hipStream_t s, const Level &L, const V *a, const V *dinv, const V *p
             const double *done, int part) {
     if (L.E.sp && L.xp && (L.mstride == 2 || L.mstride == 4)) {
         V *pr = (V *)L.xp;  // free during the down leg: the up leg of this level runs later
-        if (part != 2)
+        V *y = (V *)L.yb;
+        if (part != 2) {
+            if (y)
+                hipLaunchKernelGGL((k_scale<V, VB>), dim3(blocks_for(L.A.n)), dim3(kBlock), 0, s, L.A.n, dinv, b, y,
+                                   done);
             with_sell<V>(L.E, [&](auto *ix, auto *vals) {
                 using I = std::remove_const_t<std::remove_pointer_t<decltype(ix)>>;
                 using S = std::remove_const_t<std::remove_pointer_t<decltype(vals)>>;
                 launch_k((k_down_res_sell<V, VB, I, S>), dim3(blocks_for(L.A.n)), dim3(kBlock), s,
-                                   L.A.n, L.E.sp, L.E.uni, L.E.su, ix, vals, dinv, p, b, pr, done);
+                                   L.A.n, L.E.sp, L.E.uni, L.E.su, ix, vals, dinv, p, b, pr, (const V *)y, done);
             });
+        }
         if (part == 1) return;
         if (L.mstride == 4)
             hipLaunchKernelGGL((k_restrict<V, 4>), dim3(blocks_for(L.nc)), dim3(kBlock), 0, s, L.nc, L.mem, pr, bc,
@@ -939,13 +953,12 @@ void coarse_t(hipStream_t s, const Level &L, int sweeps, const VB *b, VX *x, dou
         constexpr int g = decltype(gc)::value;
         constexpr int R = 2;
         for (int t = 0; t < sweeps; ++t) {
-            hipLaunchKernelGGL((k_jacobi_sweep<g, R, VB>), dim3(blocks_for(((long long)n + R - 1) / R * g)),
-                               dim3(kBlock), 0, s, n, L.A.rp, L.A.ci, L.A.v, L.dinv, b, xo, xn, t == 0 ? 1 : 0,
-                               done);
+            hipLaunchKernelGGL((k_jacobi_sweep<g, R, VB, VX>), dim3(blocks_for(((long long)n + R - 1) / R * g)),
+                               dim3(kBlock), 0, s, n, L.A.rp, L.A.ci, L.A.v, L.dinv, b, xo, xn,
+                               t == sweeps - 1 ? x : (VX *)nullptr, t == 0 ? 1 : 0, done);
             double *tmp = xo; xo = xn; xn = tmp;
         }
     });
-    hipLaunchKernelGGL((k_store<VX>), dim3(blocks_for(n)), dim3(kBlock), 0, s, n, xo, x, done);
 }
 
 }  // namespace
