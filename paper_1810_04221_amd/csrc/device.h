@@ -61,6 +61,28 @@ __device__ __forceinline__ void block_sum(double (&v)[K], double *lds) {
     __syncthreads();
 }
 
+// s[k] += partials[k * nb + bk] over bk = threadIdx.x, + blockDim.x, ... in
+// that order; eight block indices' loads are issued before any is added, so
+// the partials (just written by another kernel) cost few memory round trips.
+template <int K>
+__device__ __forceinline__ void add_partials(double (&s)[K], const double *__restrict__ partials, int nb) {
+    constexpr int U = 8;
+    for (int b0 = threadIdx.x; b0 < nb; b0 += U * blockDim.x) {
+        double t[U][K];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int bk = b0 + u * blockDim.x;
+#pragma unroll
+            for (int k = 0; k < K; ++k) t[u][k] = bk < nb ? partials[(size_t)k * nb + bk] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+                if (b0 + u * blockDim.x < nb) s[k] += t[u][k];
+    }
+}
+
 // Block partial sums: thread 0 of every block stores the block's K sums at
 // partials[k * gridDim.x + blockIdx.x].  No inter-block synchronisation: a
 // following single-block kernel adds the partials in block order, so the

@@ -330,9 +330,7 @@ __global__ void __launch_bounds__(kBlock) k_kfinal(int nb, const double *__restr
     double s[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) s[k] = 0.0;
-    for (int bk = threadIdx.x; bk < nb; bk += blockDim.x)
-#pragma unroll
-        for (int k = 0; k < K; ++k) s[k] += partials[(size_t)k * nb + bk];
+    add_partials<K>(s, partials, nb);
     block_sum<K>(s, lds);
     if (threadIdx.x != 0) return;
     if (STEP == 1) {
@@ -803,9 +801,7 @@ __global__ void __launch_bounds__(kBlock) k_finalize(int nb, const double *__res
     double s[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) s[k] = 0.0;
-    for (int bk = threadIdx.x; bk < nb; bk += blockDim.x)
-#pragma unroll
-        for (int k = 0; k < K; ++k) s[k] += partials[(size_t)k * nb + bk];
+    add_partials<K>(s, partials, nb);
     block_sum<K>(s, lds);
     if (threadIdx.x != 0) return;
     if (mode == 0) {
