@@ -173,7 +173,8 @@ bool valid_group(int g) { return g == 0 || g == -1 || g == 4 || g == 8 || g == 1
 // formed: the validated input and the coarse matrices built from it; a bad
 // value there makes weights ineligible, never an out-of-bounds access).
 int match_sweep(hipStream_t s, Arena &tmp, const Csr &A, const double *w, int check_sym, int group, int **mate_out,
-                int **leader_out, double **c_out, int *flags_dev = nullptr, int G_hint = 0) {
+                int **leader_out, double **c_out, int *flags_dev = nullptr, int G_hint = 0,
+                const int *copy_src = nullptr) {
     const int m = A.n, G = G_hint > 0 ? G_hint : lanes_for(group, A);
     double *diag = tmp.get_n<double>(m);
     int *flags = flags_dev ? flags_dev : tmp.get_n<int>(16);
@@ -197,11 +198,11 @@ int match_sweep(hipStream_t s, Arena &tmp, const Csr &A, const double *w, int ch
     }
     // rows of a few dozen entries: own-row ranks with the weights; longer: sorted
     const bool sorted = A.nnz >= (long long)kSortedCandidatesAvg * m;
-    launch_weights(s, G, m, A.rp, A.ci, A.v, diag, w, c, sorted ? nullptr : rk);
+    launch_weights(s, G, m, A.rp, A.ci, A.v, diag, w, c, sorted ? nullptr : rk, ws);
     launch_candidates(s, G, m, sorted, A.rp, A.ci, c, rk, cand);
-    launch_fill_u64(s, m, ws, 0ull);
     launch_suitor(s, m, A.rp, cand, ws);
-    launch_mate(s, m, A.rp, A.ci, ws, mate, leader);
+    // (copy_src: an int for the caller's next read-back, to flags_dev[17])
+    launch_mate(s, m, A.rp, A.ci, ws, mate, leader, copy_src, copy_src ? flags_dev + 17 : nullptr);
     HIPCHK(hipGetLastError());
     *mate_out = mate;
     *leader_out = leader;
@@ -224,13 +225,12 @@ int pairwise_sweep(hipStream_t s, Arena &tmp, Arena &keep, Csr &A, const double 
     int *mate = nullptr, *leader = nullptr;
     int *ctl = tmp.get_n<int>(32);  // [0] validation flags, [16] aggregates, [17] A's entries
     NOMEM(ctl);
-    int rc = match_sweep(s, tmp, A, w, 0, group, &mate, &leader, nullptr, ctl, A.nnz_dev ? G_hint : 0);
+    int rc = match_sweep(s, tmp, A, w, 0, group, &mate, &leader, nullptr, ctl, A.nnz_dev ? G_hint : 0, A.nnz_dev);
     if (rc) return rc;
     int *ofs = leader;  // scanned in place
     void *stmp = tmp.get(scan_tmp_bytes(m));
     NOMEM(stmp);
     scan_exclusive(s, leader, ofs, m, ctl + 16, stmp);
-    if (A.nnz_dev) HIPCHK(hipMemcpyAsync(ctl + 17, A.nnz_dev, sizeof(int), hipMemcpyDeviceToDevice, s));
     int hc[18];
     rc = read_back(s, ctl, sizeof(hc), hc);
     if (rc) return rc;

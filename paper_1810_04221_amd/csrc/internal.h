@@ -205,7 +205,7 @@ int pick_G(double avg_nnz_per_row);
 void launch_validate(hipStream_t s, int G, int n, int nnz, const int *rp, const int *ci,
                      const double *v, const double *w, int check_sym, double *diag, int *flags);
 void launch_weights(hipStream_t s, int G, int n, const int *rp, const int *ci, const double *v, const double *diag,
-                    const double *w, double *c, unsigned *rk);
+                    const double *w, double *c, unsigned *rk, unsigned long long *ws);
 // Suitor candidate lists; matrices averaging at least kSortedCandidatesAvg
 // entries per row sort each row (own-row ranks in rk[nnz], scratch)
 constexpr int kSortedCandidatesAvg = 24;
@@ -213,7 +213,7 @@ void launch_candidates(hipStream_t s, int G, int n, bool sorted, const int *rp, 
                        unsigned *rk, unsigned long long *cand);
 void launch_suitor(hipStream_t s, int n, const int *rp, const unsigned long long *cand, unsigned long long *ws);
 void launch_mate(hipStream_t s, int n, const int *rp, const int *ci, const unsigned long long *ws, int *mate,
-                 int *leader);
+                 int *leader, const int *csrc = nullptr, int *cdst = nullptr);
 void launch_aggfill(hipStream_t s, int n, const int *mate, const int *ofs, const double *w,
                     int *agg, double *p, double *wc, int *mem2);
 void launch_gal_count(hipStream_t s, int G, int nc, const int *rp, const int *ci, const int *agg,

@@ -85,36 +85,43 @@ __global__ void __launch_bounds__(kBlock) k_scan_add(int *__restrict__ out, int 
     }
 }
 
-// Whole scan in one workgroup of 1024 threads for n <= kScanSmall: thread t
-// owns items [t K, t K + K), K = ceil(n / 1024).
+// Whole scan in one workgroup of 1024 threads for n <= kScanSmall.  Wave w owns
+// C = kScanSmall / 1024 consecutive chunks of 64 items; every load and store of
+// a wave is one contiguous 256-byte access (a single workgroup cannot afford
+// strided ones).  Each chunk is scanned across the wave's lanes, chunk totals
+// carry across the wave's chunks, then across the 16 waves.  In place is fine:
+// an item is read and written by the same lane.
 constexpr int kScanSmall = 16384;
 
-__global__ void __launch_bounds__(1024) k_scan_single(const int *__restrict__ in, int *__restrict__ out, int n,
-                                                        int *__restrict__ total) {
+__global__ void __launch_bounds__(1024) k_scan_single(const int *in, int *out, int n, int *__restrict__ total) {
+    constexpr int C = kScanSmall / 1024;
     __shared__ int wsum[16];
-    const int K = (n + 1023) / 1024;
-    const int b = threadIdx.x * K;
-    int v[kScanSmall / 1024];
-    int s = 0;
-#pragma unroll
-    for (int k = 0; k < kScanSmall / 1024; ++k) {
-        v[k] = (k < K && b + k < n) ? in[b + k] : 0;
-        s += v[k];
-    }
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    const int inc = wave_incl(s);
-    if (lane == 63) wsum[wid] = inc;
+    int v[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        const int e = (wid * C + c) * 64 + lane;
+        v[c] = e < n ? in[e] : 0;
+    }
+    int run = 0;  // the same in every lane of the wave
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        const int inc = wave_incl(v[c]);
+        const int x = v[c];
+        v[c] = run + inc - x;  // exclusive prefix within the wave's range
+        run += __shfl(inc, 63, 64);
+    }
+    if (lane == 0) wsum[wid] = run;
     __syncthreads();
     int base = 0, tot = 0;
     for (int w = 0; w < 16; ++w) {
         if (w < wid) base += wsum[w];
         tot += wsum[w];
     }
-    int run = base + inc - s;
 #pragma unroll
-    for (int k = 0; k < kScanSmall / 1024; ++k) {
-        if (k < K && b + k < n) out[b + k] = run;
-        run += v[k];
+    for (int c = 0; c < C; ++c) {
+        const int e = (wid * C + c) * 64 + lane;
+        if (e < n) out[e] = base + v[c];
     }
     if (threadIdx.x == 0) *total = tot;
 }

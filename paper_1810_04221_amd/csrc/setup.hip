@@ -91,7 +91,8 @@ k_validate(int n, int nnz, const int *__restrict__ rp, const int *__restrict__ c
 // Edge weights of compatible weighted matching (Section 2.2):
 //   c_ij = 1 - 2 a_ij w_i w_j / (a_ii w_i^2 + a_jj w_j^2)
 // with m = min(i, j), M = max(i, j) fixing the operand order, so both ends of
-// an edge compute the same double.  Diagonal positions get 0.  With rk given,
+// an edge compute the same double.  Diagonal positions get 0; ws (the
+// matching's best proposal per vertex) is cleared on the way.  With rk given,
 // also the own-row rank of every weight, rk[q] = #{ t in row(q) : c[t] < c[q] }
 // (needed by the candidate lists), compared in LDS for rows of at most 4 G
 // entries and in global memory for longer ones.
@@ -100,7 +101,7 @@ template <int G>
 __global__ void __launch_bounds__(kBlock)
 k_weights(int n, const int *__restrict__ rp, const int *__restrict__ ci, const double *__restrict__ v,
           const double *__restrict__ diag, const double *__restrict__ w, double *__restrict__ c,
-          unsigned *__restrict__ rk) {
+          unsigned *__restrict__ rk, unsigned long long *__restrict__ ws) {
     constexpr int LS = 4 * G;
     constexpr int NG = kBlock / G;
     __shared__ double sc[NG * LS];
@@ -110,6 +111,7 @@ k_weights(int n, const int *__restrict__ rp, const int *__restrict__ ci, const d
     const int s0 = rp[row], e = rp[row + 1], d = e - s0;
     const bool staged = rk && d <= LS;
     double *C = sc + g * LS;
+    if (ws && lane == 0) ws[row] = 0ull;  // the matching's proposal slots start empty
     for (int q = s0 + lane; q < e; q += G) {
         const int j = ci[q];
         double cq = 0.0;
@@ -404,8 +406,10 @@ k_suitor(int n, const int *__restrict__ rp, const unsigned long long *__restrict
 // smallest member of each aggregate of Algorithm 2.
 __global__ void __launch_bounds__(kBlock)
 k_mate(int n, const int *__restrict__ rp, const int *__restrict__ ci, const unsigned long long *__restrict__ ws,
-       int *__restrict__ mate, int *__restrict__ leader) {
+       int *__restrict__ mate, int *__restrict__ leader, const int *__restrict__ csrc, int *__restrict__ cdst) {
+    // (csrc given: one int copied to cdst on the way, for the host's next read-back)
     const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i == 0 && csrc) *cdst = *csrc;
     if (i >= n) return;
     // the suitor of i is the neighbour whose row holds the winning slot ts:
     // the last neighbour j of i with rp[j] <= ts (columns ascending, rp monotone)
@@ -816,11 +820,11 @@ void launch_validate(hipStream_t s, int G, int n, int nnz, const int *rp, const 
 }
 
 void launch_weights(hipStream_t s, int G, int n, const int *rp, const int *ci, const double *v, const double *diag,
-                    const double *w, double *c, unsigned *rk) {
+                    const double *w, double *c, unsigned *rk, unsigned long long *ws) {
     with_G(G, [&](auto gc) {
         constexpr int g = decltype(gc)::value;
         hipLaunchKernelGGL(k_weights<g>, dim3(blocks_for((long long)n * g)), dim3(kBlock), 0, s, n, rp, ci,
-                           v, diag, w, c, rk);
+                           v, diag, w, c, rk, ws);
     });
 }
 
@@ -847,8 +851,8 @@ void launch_suitor(hipStream_t s, int n, const int *rp, const unsigned long long
 }
 
 void launch_mate(hipStream_t s, int n, const int *rp, const int *ci, const unsigned long long *ws, int *mate,
-                 int *leader) {
-    hipLaunchKernelGGL(k_mate, dim3(blocks_for(n)), dim3(kBlock), 0, s, n, rp, ci, ws, mate, leader);
+                 int *leader, const int *csrc, int *cdst) {
+    hipLaunchKernelGGL(k_mate, dim3(blocks_for(n)), dim3(kBlock), 0, s, n, rp, ci, ws, mate, leader, csrc, cdst);
 }
 
 void launch_aggfill(hipStream_t s, int n, const int *mate, const int *ofs, const double *w, int *agg,
