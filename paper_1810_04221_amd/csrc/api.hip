@@ -196,9 +196,9 @@ int match_sweep(hipStream_t s, Arena &tmp, const Csr &A, const double *w, int ch
             return BCM_EINVAL;
         }
     }
-    // rows of a few dozen entries: own-row ranks with the weights; longer: sorted
+    // candidate lists: direct comparisons for rows of a few dozen entries, else sorted
     const bool sorted = A.nnz >= (long long)kSortedCandidatesAvg * m;
-    launch_weights(s, G, m, A.rp, A.ci, A.v, diag, w, c, sorted ? nullptr : rk, ws);
+    launch_weights(s, G, m, A.rp, A.ci, A.v, diag, w, c, ws);
     launch_candidates(s, G, m, sorted, A.rp, A.ci, c, rk, cand);
     launch_suitor(s, m, A.rp, cand, ws);
     // (copy_src: an int for the caller's next read-back, to flags_dev[17])

@@ -205,7 +205,7 @@ int pick_G(double avg_nnz_per_row);
 void launch_validate(hipStream_t s, int G, int n, int nnz, const int *rp, const int *ci,
                      const double *v, const double *w, int check_sym, double *diag, int *flags);
 void launch_weights(hipStream_t s, int G, int n, const int *rp, const int *ci, const double *v, const double *diag,
-                    const double *w, double *c, unsigned *rk, unsigned long long *ws);
+                    const double *w, double *c, unsigned long long *ws);
 // Suitor candidate lists; matrices averaging at least kSortedCandidatesAvg
 // entries per row sort each row (own-row ranks in rk[nnz], scratch)
 constexpr int kSortedCandidatesAvg = 24;

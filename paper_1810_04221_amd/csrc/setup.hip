@@ -92,27 +92,19 @@ k_validate(int n, int nnz, const int *__restrict__ rp, const int *__restrict__ c
 //   c_ij = 1 - 2 a_ij w_i w_j / (a_ii w_i^2 + a_jj w_j^2)
 // with m = min(i, j), M = max(i, j) fixing the operand order, so both ends of
 // an edge compute the same double.  Diagonal positions get 0; ws (the
-// matching's best proposal per vertex) is cleared on the way.  With rk given,
-// also the own-row rank of every weight, rk[q] = #{ t in row(q) : c[t] < c[q] }
-// (needed by the candidate lists), compared in LDS for rows of at most 4 G
-// entries and in global memory for longer ones.
+// matching's best proposal per vertex) is cleared on the way.
 // ----------------------------------------------------------------------------
 template <int G>
 __global__ void __launch_bounds__(kBlock)
 k_weights(int n, const int *__restrict__ rp, const int *__restrict__ ci, const double *__restrict__ v,
           const double *__restrict__ diag, const double *__restrict__ w, double *__restrict__ c,
-          unsigned *__restrict__ rk, unsigned long long *__restrict__ ws) {
-    constexpr int LS = 4 * G;
-    constexpr int NG = kBlock / G;
-    __shared__ double sc[NG * LS];
-    const int g = threadIdx.x / G, lane = threadIdx.x % G;
+          unsigned long long *__restrict__ ws) {
+    const int lane = threadIdx.x % G;
     const int row = (xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x) / G;
     if (row >= n) return;
-    const int s0 = rp[row], e = rp[row + 1], d = e - s0;
-    const bool staged = rk && d <= LS;
-    double *C = sc + g * LS;
-    if (ws && lane == 0) ws[row] = 0ull;  // the matching's proposal slots start empty
-    for (int q = s0 + lane; q < e; q += G) {
+    if (ws && lane == 0) ws[row] = 0ull;
+    const int e = rp[row + 1];
+    for (int q = rp[row] + lane; q < e; q += G) {
         const int j = ci[q];
         double cq = 0.0;
         if (j != row) {
@@ -123,16 +115,6 @@ k_weights(int n, const int *__restrict__ rp, const int *__restrict__ ci, const d
             cq = 1.0 - num / den;
         }
         c[q] = cq;
-        if (staged) C[q - s0] = cq;
-    }
-    if (!rk) return;
-    if (staged) wave_sync(); else __threadfence_block();
-    const double *R = staged ? C : c + s0;
-    for (int k = lane; k < d; k += G) {
-        const double cq = R[k];
-        unsigned r = 0;
-        for (int t = 0; t < d; ++t) r += (R[t] < cq) ? 1u : 0u;
-        rk[s0 + k] = r;
     }
 }
 
@@ -140,13 +122,13 @@ k_weights(int n, const int *__restrict__ rp, const int *__restrict__ ci, const d
 // Suitor candidate lists for short rows (same output as k_candidates below;
 // see there): the row's weights and columns are held in LDS (rows of at most
 // 4 G entries) and each eligible entry counts its place in the row's order
-// there; the rank of c_uv seen from v is the own-row rank (k_weights) of the
-// transposed entry, found by binary search.
+// there; the rank of c_uv seen from v is counted over row v's weights (c_vu
+// is the same double as c_uv), all of whose loads are issued together.
 // ----------------------------------------------------------------------------
 template <int G>
 __global__ void __launch_bounds__(kBlock)
 k_candidates_direct(int n, const int *__restrict__ rp, const int *__restrict__ ci, const double *__restrict__ c,
-                    const unsigned *__restrict__ rk_own, unsigned long long *__restrict__ cand) {
+                    unsigned long long *__restrict__ cand) {
     constexpr int LS = 4 * G;
     constexpr int NG = kBlock / G;
     __shared__ double sc[NG * LS];
@@ -155,16 +137,12 @@ k_candidates_direct(int n, const int *__restrict__ rp, const int *__restrict__ c
     const int row = (xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x) / G;
     if (row >= n) return;
     const int s0 = rp[row], e = rp[row + 1], d = e - s0;
-    // (a pattern that is not symmetric, accepted without the symmetry check,
-    // may lack the entry: rank 0 then, and no read outside row v)
-    auto rank_at = [&](int vtx) -> unsigned {
-        const int e2 = rp[vtx + 1];
-        int lo = rp[vtx], hi = e2;
-        while (lo < hi) {
-            const int mid = (lo + hi) >> 1;
-            if (ci[mid] < row) lo = mid + 1; else hi = mid;
-        }
-        return lo < e2 ? rk_own[lo] : 0u;
+    auto rank_at = [&](int vtx, double cq) -> unsigned {
+        const int b2 = rp[vtx], e2 = rp[vtx + 1];
+        unsigned r = 0;
+#pragma unroll 8
+        for (int t = b2; t < e2; ++t) r += (c[t] < cq) ? 1u : 0u;
+        return r;
     };
     const bool staged = d <= LS;
     double *C = sc + g * LS;
@@ -191,7 +169,7 @@ k_candidates_direct(int n, const int *__restrict__ rp, const int *__restrict__ c
             const bool elig = vt != row && ct > 0.0 && ct < INFINITY;
             before += (elig && (ct > cq || (ct == cq && vt > vtx))) ? 1 : 0;
         }
-        if (before < d - 1) cand[s0 + before] = ((unsigned long long)rank_at(vtx) << 32) | (unsigned)vtx;
+        if (before < d - 1) cand[s0 + before] = ((unsigned long long)rank_at(vtx, cq) << 32) | (unsigned)vtx;
     }
     nelig = min(group_sum<G>(nelig), max(d - 1, 0));
     for (int q = s0 + nelig + lane; q < e; q += G) cand[q] = ~0ull;
@@ -820,24 +798,23 @@ void launch_validate(hipStream_t s, int G, int n, int nnz, const int *rp, const 
 }
 
 void launch_weights(hipStream_t s, int G, int n, const int *rp, const int *ci, const double *v, const double *diag,
-                    const double *w, double *c, unsigned *rk, unsigned long long *ws) {
+                    const double *w, double *c, unsigned long long *ws) {
     with_G(G, [&](auto gc) {
         constexpr int g = decltype(gc)::value;
         hipLaunchKernelGGL(k_weights<g>, dim3(blocks_for((long long)n * g)), dim3(kBlock), 0, s, n, rp, ci,
-                           v, diag, w, c, rk, ws);
+                           v, diag, w, c, ws);
     });
 }
 
-// Rows of a few dozen entries compare directly (own-row ranks from
-// k_weights); longer rows sort (k_rank + k_candidates: O(d log d) per row
-// instead of O(d^2)).
+// Rows of a few dozen entries compare directly; longer rows sort (k_rank +
+// k_candidates: O(d log d) per row instead of O(d^2)).
 void launch_candidates(hipStream_t s, int G, int n, bool sorted, const int *rp, const int *ci, const double *c,
                        unsigned *rk, unsigned long long *cand) {
     with_G(G, [&](auto gc) {
         constexpr int g = decltype(gc)::value;
         if (!sorted) {
             hipLaunchKernelGGL(k_candidates_direct<g>, dim3(blocks_for((long long)n * g)), dim3(kBlock), 0, s, n, rp,
-                               ci, c, rk, cand);
+                               ci, c, cand);
             return;
         }
         hipLaunchKernelGGL(k_rank<g>, dim3(blocks_for((long long)n * g)), dim3(kBlock), 0, s, n, rp, c, rk);
