@@ -539,6 +539,9 @@ int build_hierarchy(bcm_handle *h, const bcm_csr *Ain, const double *win) {
                 L.E.mixed = ne ? (double)tots[96 + t] / (double)ne : 1.0;
             } else {
                 L.E.sc = h->persist.get_n<int>(ne);
+                // int32 columns: no uniform slices (the kernels read the flags regardless)
+                L.E.uni = uni[t];
+                launch_fill_i32(s, (size_t)L.E.nslices, uni[t], 0);
             }
             const bool exact32 = tots[64 + t] == 0;
             if (!exact32) L.E.sv = h->persist.get_n<double>(ne);

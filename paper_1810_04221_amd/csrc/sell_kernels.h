@@ -27,22 +27,47 @@ template <typename V, typename S, typename I, typename F>
 __device__ __forceinline__ V sell_row(int n, const int *__restrict__ sp, const int *__restrict__ uni,
                                       const short *__restrict__ su, const I *__restrict__ sc,
                                       const S *__restrict__ sv, int i, F f) {
+    // The slots are taken in batches of kB whose loads are all issued before
+    // any is used: a slot past the width re-reads the last one and is not
+    // added (w is the same for the whole wave), so no batch ends in a chain of
+    // one-slot steps.  uni is never null (all zero without uniform slices).
+    constexpr int kB = 4;
     const int sl = __builtin_amdgcn_readfirstlane(i / kSlice), lane = i % kSlice;
-    const int beg = sp[sl], w = (sp[sl + 1] - beg) / kSlice;
+    const int uf = uni[sl], beg = sp[sl], w = (sp[sl + 1] - beg) / kSlice;
     const S *a = sv + beg + lane;
     V s = V(0);
-    if (uni && uni[sl]) {
+    if (uf) {
         const short *u = su + beg / kSlice;
-#pragma unroll 4
-        for (int k = 0; k < w; ++k) {
-            const int c = i + (int)u[k];
-            s += (V)a[k * kSlice] * f((unsigned)c < (unsigned)n ? c : i);
+        for (int k0 = 0; k0 < w; k0 += kB) {
+            S av[kB];
+            V fv[kB];
+#pragma unroll
+            for (int t = 0; t < kB; ++t) {
+                const int k = min(k0 + t, w - 1);
+                av[t] = a[k * kSlice];
+                const int c = i + (int)u[k];
+                fv[t] = f((unsigned)c < (unsigned)n ? c : i);
+            }
+#pragma unroll
+            for (int t = 0; t < kB; ++t)
+                if (k0 + t < w) s += (V)av[t] * fv[t];
         }
         return s;
     }
     const I *c = sc + beg + lane;
-#pragma unroll 4
-    for (int k = 0; k < w; ++k) s += (V)a[k * kSlice] * f(sell_col(c[k * kSlice], i));
+    for (int k0 = 0; k0 < w; k0 += kB) {
+        S av[kB];
+        V fv[kB];
+#pragma unroll
+        for (int t = 0; t < kB; ++t) {
+            const int k = min(k0 + t, w - 1);
+            av[t] = a[k * kSlice];
+            fv[t] = f(sell_col(c[k * kSlice], i));
+        }
+#pragma unroll
+        for (int t = 0; t < kB; ++t)
+            if (k0 + t < w) s += (V)av[t] * fv[t];
+    }
     return s;
 }
 
@@ -118,12 +143,13 @@ k_spmv_dots_sell(int n, const int *__restrict__ sp, const int *__restrict__ uni,
     const int blk = xcd_block(blockIdx.x, gridDim.x);
     double acc[3] = {0.0, 0.0, 0.0};
     for (int i = blk * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+        // the row's own entries are loaded first, to overlap the product's loads
+        const double wi = w[i], ri = r[i], qi = q[i];
         const double s = sell_row<double, S, I>(n, sp, uni, su, sc, sv, i, [&](int j) { return w[j]; });
-        const double wi = w[i];
         v[i] = s;
-        acc[0] += wi * r[i];
+        acc[0] += wi * ri;
         acc[1] += wi * s;
-        acc[2] += wi * q[i];
+        acc[2] += wi * qi;
     }
     block_partials<3>(acc, partials);
 }
