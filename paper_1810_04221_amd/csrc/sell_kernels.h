@@ -31,7 +31,7 @@ __device__ __forceinline__ V sell_row(int n, const int *__restrict__ sp, const i
     // any is used: a slot past the width re-reads the last one and is not
     // added (w is the same for the whole wave), so no batch ends in a chain of
     // one-slot steps.  uni is never null (all zero without uniform slices).
-    constexpr int kB = 4;
+    constexpr int kB = 8;
     const int sl = __builtin_amdgcn_readfirstlane(i / kSlice), lane = i % kSlice;
     const int uf = uni[sl], beg = sp[sl], w = (sp[sl + 1] - beg) / kSlice;
     const S *a = sv + beg + lane;
@@ -87,10 +87,11 @@ k_down_res_sell(int n, const int *__restrict__ sp, const int *__restrict__ uni,
     if (done && *done != 0.0) return;
     const int i = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
     if (i >= n) return;
+    const V pi = p[i], bi = (V)b[i];  // loaded first, to overlap the product's loads
     V s;
     if (y) s = sell_row<V, S, I>(n, sp, uni, su, sc, sv, i, [&](int j) { return y[j]; });
     else s = sell_row<V, S, I>(n, sp, uni, su, sc, sv, i, [&](int j) { return dinv[j] * (V)b[j]; });
-    pr[i] = p[i] * ((V)b[i] - s);
+    pr[i] = pi * (bi - s);
 }
 
 
@@ -105,8 +106,9 @@ k_smooth_sell(int n, const int *__restrict__ sp, const int *__restrict__ uni,
     if (done && *done != 0.0) return;
     const int i = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
     if (i >= n) return;
+    const V xi = xp[i], di = dinv[i], bi = (V)b[i];  // loaded first, to overlap the product's loads
     const V s = sell_row<V, S, I>(n, sp, uni, su, sc, sv, i, [&](int j) { return xp[j]; });
-    x[i] = (VX)(xp[i] + dinv[i] * ((V)b[i] - s));
+    x[i] = (VX)(xi + di * (bi - s));
 }
 
 
@@ -122,8 +124,8 @@ k_resid_sell(int n, const int *__restrict__ sp, const int *__restrict__ uni,
     const int blk = xcd_block(blockIdx.x, gridDim.x);
     double acc[2] = {0.0, 0.0};
     for (int i = blk * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
-        const double s = sell_row<double, S, I>(n, sp, uni, su, sc, sv, i, [&](int j) { return u[j]; });
         const double bi = b[i];
+        const double s = sell_row<double, S, I>(n, sp, uni, su, sc, sv, i, [&](int j) { return u[j]; });
         const double ri = bi - s;
         r[i] = ri;
         acc[0] += ri * ri;
