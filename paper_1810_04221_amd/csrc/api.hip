@@ -543,6 +543,7 @@ int build_hierarchy(bcm_handle *h, const bcm_csr *Ain, const double *win) {
                 L.E.uni = uni[t];
                 launch_fill_i32(s, (size_t)L.E.nslices, uni[t], 0);
             }
+            L.E.wide = ne > (size_t)kWideSlots * kSlice * (size_t)L.E.nslices;
             const bool exact32 = tots[64 + t] == 0;
             if (!exact32) L.E.sv = h->persist.get_n<double>(ne);
             if (fp32 || exact32) L.E.sv32 = h->persist.get_n<float>(ne);

@@ -95,6 +95,9 @@ struct Csr {
 // is exactly a float32 only sv32 is kept and the float64 kernels widen it
 // (exactly) on load.
 constexpr int kSlice = 64;
+// Sliced-ELL levels whose slices average more than this many slots read their
+// rows in batches of 16 slots instead of 8.
+constexpr int kWideSlots = 12;
 struct Sell {
     int nslices = 0;
     int *sp = nullptr, *sc = nullptr;
@@ -106,6 +109,7 @@ struct Sell {
     double *sv = nullptr;
     float *sv32 = nullptr;
     double mixed = 1.0;  // fraction of the slots in slices that are not uniform
+    int wide = 0;        // slices average more than kWideSlots slots: batches of 16
 };
 
 // One level of the hierarchy.  Row i of A^k, its l1 inverse diagonal, the

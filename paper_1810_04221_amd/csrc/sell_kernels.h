@@ -12,6 +12,34 @@
 __device__ __forceinline__ int sell_col(int c, int) { return c; }
 __device__ __forceinline__ int sell_col(short d, int i) { return i + (int)d; }
 
+// Slots k0 .. w-1 of row i in batches of kB whose loads are all issued before
+// any is used: a slot past the width re-reads the last one and is not added
+// (w is the same for the whole wave), so no batch ends in a chain of one-slot
+// steps.  Accumulates into s left to right.  Uni: column offsets from the
+// slice's shared list u, else from the per-entry columns c.
+template <int kB, bool Uni, typename V, typename S, typename I, typename F>
+__device__ __forceinline__ V sell_slots(const S *a, const short *u, const I *c, int n, int i, int w, V s, F f) {
+    for (int k0 = 0; k0 < w; k0 += kB) {
+        S av[kB];
+        V fv[kB];
+#pragma unroll
+        for (int t = 0; t < kB; ++t) {
+            const int k = min(k0 + t, w - 1);
+            av[t] = a[k * kSlice];
+            if (Uni) {
+                const int cc = i + (int)u[k];
+                fv[t] = f((unsigned)cc < (unsigned)n ? cc : i);
+            } else {
+                fv[t] = f(sell_col(c[k * kSlice], i));
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < kB; ++t)
+            if (k0 + t < w) s += (V)av[t] * fv[t];
+    }
+    return s;
+}
+
 // Row i of a sliced ELL matrix: sum_k a_k * f(col_k), left to right over the
 // row's slots (CSR order, with zero terms in between or after).  Lane i % 64 of
 // a wave owns row i, so every slot load of the wave is one contiguous access
@@ -23,52 +51,20 @@ __device__ __forceinline__ int sell_col(short d, int i) { return i + (int)d; }
 // slot for the whole wave, instead of one per entry; a slot a row does not
 // have holds the value 0 (its column clamped into the matrix when it would
 // leave it).
-template <typename V, typename S, typename I, typename F>
+template <typename V, typename S, typename I, int kB, typename F>
 __device__ __forceinline__ V sell_row(int n, const int *__restrict__ sp, const int *__restrict__ uni,
                                       const short *__restrict__ su, const I *__restrict__ sc,
                                       const S *__restrict__ sv, int i, F f) {
-    // The slots are taken in batches of kB whose loads are all issued before
-    // any is used: a slot past the width re-reads the last one and is not
-    // added (w is the same for the whole wave), so no batch ends in a chain of
-    // one-slot steps.  uni is never null (all zero without uniform slices).
-    constexpr int kB = 8;
+    // uni is never null (all zero without uniform slices).  kB = 16 on levels
+    // of long rows (a few dozen entries): half as many dependent memory round
+    // trips per row, for twice the registers.
     const int sl = __builtin_amdgcn_readfirstlane(i / kSlice), lane = i % kSlice;
     const int uf = uni[sl], beg = sp[sl], w = (sp[sl + 1] - beg) / kSlice;
     const S *a = sv + beg + lane;
-    V s = V(0);
-    if (uf) {
-        const short *u = su + beg / kSlice;
-        for (int k0 = 0; k0 < w; k0 += kB) {
-            S av[kB];
-            V fv[kB];
-#pragma unroll
-            for (int t = 0; t < kB; ++t) {
-                const int k = min(k0 + t, w - 1);
-                av[t] = a[k * kSlice];
-                const int c = i + (int)u[k];
-                fv[t] = f((unsigned)c < (unsigned)n ? c : i);
-            }
-#pragma unroll
-            for (int t = 0; t < kB; ++t)
-                if (k0 + t < w) s += (V)av[t] * fv[t];
-        }
-        return s;
-    }
+    const short *u = su + beg / kSlice;
     const I *c = sc + beg + lane;
-    for (int k0 = 0; k0 < w; k0 += kB) {
-        S av[kB];
-        V fv[kB];
-#pragma unroll
-        for (int t = 0; t < kB; ++t) {
-            const int k = min(k0 + t, w - 1);
-            av[t] = a[k * kSlice];
-            fv[t] = f(sell_col(c[k * kSlice], i));
-        }
-#pragma unroll
-        for (int t = 0; t < kB; ++t)
-            if (k0 + t < w) s += (V)av[t] * fv[t];
-    }
-    return s;
+    if (uf) return sell_slots<kB, true>(a, u, c, n, i, w, V(0), f);
+    return sell_slots<kB, false>(a, u, c, n, i, w, V(0), f);
 }
 
 
@@ -76,7 +72,7 @@ __device__ __forceinline__ V sell_row(int n, const int *__restrict__ sp, const i
 //   pr_i = p_i (b_i - sum_j a_ij dinv_j b_j),
 // followed by the restriction b_c[E] = sum of pr over E's members in ascending
 // order (the order a serial P^T r takes).
-template <typename V, typename VB, typename I, typename S>
+template <typename V, typename VB, typename I, typename S, int kB>
 __global__ void __launch_bounds__(kBlock)
 k_down_res_sell(int n, const int *__restrict__ sp, const int *__restrict__ uni,
                 const short *__restrict__ su, const I *__restrict__ sc,
@@ -89,14 +85,14 @@ k_down_res_sell(int n, const int *__restrict__ sp, const int *__restrict__ uni,
     if (i >= n) return;
     const V pi = p[i], bi = (V)b[i];  // loaded first, to overlap the product's loads
     V s;
-    if (y) s = sell_row<V, S, I>(n, sp, uni, su, sc, sv, i, [&](int j) { return y[j]; });
-    else s = sell_row<V, S, I>(n, sp, uni, su, sc, sv, i, [&](int j) { return dinv[j] * (V)b[j]; });
+    if (y) s = sell_row<V, S, I, kB>(n, sp, uni, su, sc, sv, i, [&](int j) { return y[j]; });
+    else s = sell_row<V, S, I, kB>(n, sp, uni, su, sc, sv, i, [&](int j) { return dinv[j] * (V)b[j]; });
     pr[i] = pi * (bi - s);
 }
 
 
 // k_smooth on the sliced ELL copy, one thread per row.
-template <typename V, typename VB, typename VX, typename I, typename S>
+template <typename V, typename VB, typename VX, typename I, typename S, int kB>
 __global__ void __launch_bounds__(kBlock)
 k_smooth_sell(int n, const int *__restrict__ sp, const int *__restrict__ uni,
                 const short *__restrict__ su, const I *__restrict__ sc,
@@ -107,14 +103,14 @@ k_smooth_sell(int n, const int *__restrict__ sp, const int *__restrict__ uni,
     const int i = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
     if (i >= n) return;
     const V xi = xp[i], di = dinv[i], bi = (V)b[i];  // loaded first, to overlap the product's loads
-    const V s = sell_row<V, S, I>(n, sp, uni, su, sc, sv, i, [&](int j) { return xp[j]; });
+    const V s = sell_row<V, S, I, kB>(n, sp, uni, su, sc, sv, i, [&](int j) { return xp[j]; });
     x[i] = (VX)(xi + di * (bi - s));
 }
 
 
 // Sliced-ELL variants: one thread per row, grid-stride; each row sum is taken
 // left to right exactly as a serial CSR product.
-template <typename I, typename S>
+template <typename I, typename S, int kB>
 __global__ void __launch_bounds__(kBlock)
 k_resid_sell(int n, const int *__restrict__ sp, const int *__restrict__ uni,
                 const short *__restrict__ su, const I *__restrict__ sc,
@@ -125,7 +121,7 @@ k_resid_sell(int n, const int *__restrict__ sp, const int *__restrict__ uni,
     double acc[2] = {0.0, 0.0};
     for (int i = blk * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
         const double bi = b[i];
-        const double s = sell_row<double, S, I>(n, sp, uni, su, sc, sv, i, [&](int j) { return u[j]; });
+        const double s = sell_row<double, S, I, kB>(n, sp, uni, su, sc, sv, i, [&](int j) { return u[j]; });
         const double ri = bi - s;
         r[i] = ri;
         acc[0] += ri * ri;
@@ -134,7 +130,7 @@ k_resid_sell(int n, const int *__restrict__ sp, const int *__restrict__ uni,
     block_partials<2>(acc, partials);
 }
 
-template <typename I, typename S>
+template <typename I, typename S, int kB>
 __global__ void __launch_bounds__(kBlock)
 k_spmv_dots_sell(int n, const int *__restrict__ sp, const int *__restrict__ uni,
                 const short *__restrict__ su, const I *__restrict__ sc,
@@ -147,7 +143,7 @@ k_spmv_dots_sell(int n, const int *__restrict__ sp, const int *__restrict__ uni,
     for (int i = blk * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
         // the row's own entries are loaded first, to overlap the product's loads
         const double wi = w[i], ri = r[i], qi = q[i];
-        const double s = sell_row<double, S, I>(n, sp, uni, su, sc, sv, i, [&](int j) { return w[j]; });
+        const double s = sell_row<double, S, I, kB>(n, sp, uni, su, sc, sv, i, [&](int j) { return w[j]; });
         v[i] = s;
         acc[0] += wi * ri;
         acc[1] += wi * s;

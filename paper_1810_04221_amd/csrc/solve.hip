@@ -35,16 +35,21 @@ inline int blocks_for(long long threads) { return (int)((threads + kBlock - 1) /
 // or float32 values (float32 arithmetic, or values that are exact floats).
 template <typename V, typename Fn>
 void with_sell(const Sell &E, Fn &&fn) {
+    // fn(columns, values, batch): batch is std::integral_constant<int, 8 or 16>
+    auto go = [&](auto *ix, auto *vals) {
+        if (E.wide) fn(ix, vals, std::integral_constant<int, 16>());
+        else fn(ix, vals, std::integral_constant<int, 8>());
+    };
     if constexpr (std::is_same<V, float>::value) {
-        if (E.sd) fn(E.sd, E.sv32);
-        else fn(E.sc, E.sv32);
+        if (E.sd) go(E.sd, E.sv32);
+        else go(E.sc, E.sv32);
     } else {
         if (E.sd) {
-            if (E.sv) fn(E.sd, E.sv);
-            else fn(E.sd, E.sv32);
+            if (E.sv) go(E.sd, E.sv);
+            else go(E.sd, E.sv32);
         } else {
-            if (E.sv) fn(E.sc, E.sv);
-            else fn(E.sc, E.sv32);
+            if (E.sv) go(E.sc, E.sv);
+            else go(E.sc, E.sv32);
         }
     }
 }
@@ -873,10 +878,10 @@ void down_t(hipStream_t s, const Level &L, const V *a, const V *dinv, const V *p
             if (y)
                 hipLaunchKernelGGL((k_scale<V, VB>), dim3(blocks_for(L.A.n)), dim3(kBlock), 0, s, L.A.n, dinv, b, y,
                                    done);
-            with_sell<V>(L.E, [&](auto *ix, auto *vals) {
+            with_sell<V>(L.E, [&](auto *ix, auto *vals, auto kb) {
                 using I = std::remove_const_t<std::remove_pointer_t<decltype(ix)>>;
                 using S = std::remove_const_t<std::remove_pointer_t<decltype(vals)>>;
-                launch_k((k_down_res_sell<V, VB, I, S>), dim3(blocks_for(L.A.n)), dim3(kBlock), s,
+                launch_k((k_down_res_sell<V, VB, I, S, decltype(kb)::value>), dim3(blocks_for(L.A.n)), dim3(kBlock), s,
                                    L.A.n, L.E.sp, L.E.uni, L.E.su, ix, vals, dinv, p, b, pr, (const V *)y, done);
             });
         }
@@ -906,10 +911,10 @@ void up_t(hipStream_t s, const Level &L, const V *a, const V *dinv, const V *p, 
                                b, xc, xp, done);
         if (part == 1) return;
         if (L.E.sp) {
-            with_sell<V>(L.E, [&](auto *ix, auto *vals) {
+            with_sell<V>(L.E, [&](auto *ix, auto *vals, auto kb) {
                 using I = std::remove_const_t<std::remove_pointer_t<decltype(ix)>>;
                 using S = std::remove_const_t<std::remove_pointer_t<decltype(vals)>>;
-                launch_k((k_smooth_sell<V, VB, VX, I, S>), dim3(blocks_for(L.A.n)), dim3(kBlock), s,
+                launch_k((k_smooth_sell<V, VB, VX, I, S, decltype(kb)::value>), dim3(blocks_for(L.A.n)), dim3(kBlock), s,
                                    L.A.n, L.E.sp, L.E.uni, L.E.su, ix, vals, dinv, b, xp, x, done);
             });
             return;
@@ -1120,10 +1125,10 @@ void launch_coarse_build(hipStream_t s, const Level &L, int sweeps, double *S) {
 void launch_resid(hipStream_t s, const Level &L, int nb, const double *b, const double *u, double *r,
                   double *partials, double *scal) {
     if (L.E.sp) {
-        with_sell<double>(L.E, [&](auto *ix, auto *vals) {
+        with_sell<double>(L.E, [&](auto *ix, auto *vals, auto kb) {
             using I = std::remove_const_t<std::remove_pointer_t<decltype(ix)>>;
             using S = std::remove_const_t<std::remove_pointer_t<decltype(vals)>>;
-            hipLaunchKernelGGL((k_resid_sell<I, S>), dim3(nb), dim3(kBlock), 0, s, L.A.n, L.E.sp, L.E.uni, L.E.su, ix, vals, b, u, r,
+            hipLaunchKernelGGL((k_resid_sell<I, S, decltype(kb)::value>), dim3(nb), dim3(kBlock), 0, s, L.A.n, L.E.sp, L.E.uni, L.E.su, ix, vals, b, u, r,
                                partials);
         });
         return;
@@ -1138,10 +1143,10 @@ void launch_resid(hipStream_t s, const Level &L, int nb, const double *b, const 
 void launch_spmv_dots(hipStream_t s, const Level &L, int nb, int first, const double *w, const double *r,
                       const double *q, double *v, double *partials, double *scal) {
     if (L.E.sp) {
-        with_sell<double>(L.E, [&](auto *ix, auto *vals) {
+        with_sell<double>(L.E, [&](auto *ix, auto *vals, auto kb) {
             using I = std::remove_const_t<std::remove_pointer_t<decltype(ix)>>;
             using S = std::remove_const_t<std::remove_pointer_t<decltype(vals)>>;
-            launch_k((k_spmv_dots_sell<I, S>), dim3(nb), dim3(kBlock), s, L.A.n, L.E.sp, L.E.uni, L.E.su, ix, vals, w, r,
+            launch_k((k_spmv_dots_sell<I, S, decltype(kb)::value>), dim3(nb), dim3(kBlock), s, L.A.n, L.E.sp, L.E.uni, L.E.su, ix, vals, w, r,
                                q, v, partials, scal + 10);
         });
         return;
