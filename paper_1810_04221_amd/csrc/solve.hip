@@ -115,20 +115,13 @@ k_down_seq(int nc, const int *__restrict__ mem, const int *__restrict__ rp, cons
     int rows[S];
 #pragma unroll
     for (int t = 0; t < S; ++t) rows[t] = mem[(size_t)E * S + t];
-    // the members' own entries are loaded before the products, to overlap them
-    V pm[S], bm[S];
-#pragma unroll
-    for (int t = 0; t < S; ++t) {
-        const int i = rows[t] < 0 ? 0 : rows[t];
-        pm[t] = p[i];
-        bm[t] = (V)b[i];
-    }
     V s[S];
     rows_dot<G, S, V>(rp, ci, a, rows, s, [&](int j) { return dinv[j] * (V)b[j]; });
     V acc = V(0);
 #pragma unroll
     for (int t = 0; t < S; ++t) {
-        const V c = pm[t] * (bm[t] - s[t]);
+        const int i = rows[t] < 0 ? 0 : rows[t];
+        const V c = p[i] * ((V)b[i] - s[t]);
         acc += rows[t] < 0 ? V(0) : c;
     }
     if (lane == 0 && live && !(done && *done != 0.0)) bc[E] = acc;
@@ -207,16 +200,6 @@ k_up(int n, const int *__restrict__ rp, const int *__restrict__ ci, const V *__r
     int rows[R];
 #pragma unroll
     for (int k = 0; k < R; ++k) rows[k] = base + k * NG < n ? base + k * NG : -1;
-    // the rows' own entries (and their coarse values) are loaded before the
-    // products, to overlap them
-    V bo[R], dd[R], xo[R];
-#pragma unroll
-    for (int k = 0; k < R; ++k) {
-        const int i = rows[k] < 0 ? 0 : rows[k];
-        bo[k] = (V)b[i];
-        dd[k] = dinv[i];
-        xo[k] = p[i] * xc[agg[i]];
-    }
     V s[R];
     rows_dot<G, R, V>(rp, ci, a, rows, s, [&](int j) { return dinv[j] * (V)b[j] + p[j] * xc[agg[j]]; });
     if (lane == 0 && !(done && *done != 0.0)) {
@@ -224,8 +207,10 @@ k_up(int n, const int *__restrict__ rp, const int *__restrict__ ci, const V *__r
         for (int k = 0; k < R; ++k) {
             const int i = rows[k];
             if (i < 0) continue;
-            const V xi = dd[k] * bo[k] + xo[k];
-            x[i] = (VX)(xi + dd[k] * (bo[k] - s[k]));
+            const V bi = (V)b[i];
+            const V di = dinv[i];
+            const V xi = di * bi + p[i] * xc[agg[i]];
+            x[i] = (VX)(xi + di * (bi - s[k]));
         }
     }
 }
