@@ -172,11 +172,13 @@ bool valid_group(int g) { return g == 0 || g == -1 || g == 4 || g == 8 || g == 1
 // to read with its next read-back (only for matrices already known to be well
 // formed: the validated input and the coarse matrices built from it; a bad
 // value there makes weights ineligible, never an out-of-bounds access).
+// With diag_in given (the diagonal of a matrix already validated), the
+// validation pass is skipped.
 int match_sweep(hipStream_t s, Arena &tmp, const Csr &A, const double *w, int check_sym, int group, int **mate_out,
                 int **leader_out, double **c_out, int *flags_dev = nullptr, int G_hint = 0,
-                const int *copy_src = nullptr) {
+                const int *copy_src = nullptr, const double *diag_in = nullptr) {
     const int m = A.n, G = G_hint > 0 ? G_hint : lanes_for(group, A);
-    double *diag = tmp.get_n<double>(m);
+    double *diag = diag_in ? nullptr : tmp.get_n<double>(m);
     int *flags = flags_dev ? flags_dev : tmp.get_n<int>(16);
     double *c = tmp.get_n<double>(A.nnz);
     unsigned long long *cand = tmp.get_n<unsigned long long>(A.nnz);
@@ -184,10 +186,11 @@ int match_sweep(hipStream_t s, Arena &tmp, const Csr &A, const double *w, int ch
     unsigned long long *ws = tmp.get_n<unsigned long long>(m);
     int *mate = tmp.get_n<int>(m);
     int *leader = tmp.get_n<int>(m);
-    NOMEM(diag && flags && c && cand && rk && ws && mate && leader);
+    NOMEM((diag || diag_in) && flags && c && cand && rk && ws && mate && leader);
     launch_fill_i32(s, 1, flags, 0);
-    launch_validate(s, G, m, A.nnz_dev ? -1 : A.nnz, A.rp, A.ci, A.v, w, check_sym, diag, flags);
-    if (!flags_dev) {
+    if (diag_in) diag = const_cast<double *>(diag_in);  // read only below
+    else launch_validate(s, G, m, A.nnz_dev ? -1 : A.nnz, A.rp, A.ci, A.v, w, check_sym, diag, flags);
+    if (!flags_dev && !diag_in) {
         int f = 0;
         int rc = read_back(s, flags, sizeof(int), &f);
         if (rc) return rc;
@@ -216,7 +219,7 @@ int match_sweep(hipStream_t s, Arena &tmp, const Csr &A, const double *w, int ch
 // given (the level's final outputs, allocated where they stay).  out.nc == A.n
 // means that no pair was formed (nothing else is produced then).
 int pairwise_sweep(hipStream_t s, Arena &tmp, Arena &keep, Csr &A, const double *w, int group, int G_hint,
-                   SweepOut &out, Arena *finA, Arena *finP) {
+                   SweepOut &out, Arena *finA, Arena *finP, const double *diag_in = nullptr) {
     // A's exact entry count, when still on the device, comes back with this
     // sweep's first read-back (G_hint sizes the lanes of the kernels before it)
     Arena &oa = finA ? *finA : keep;
@@ -225,7 +228,8 @@ int pairwise_sweep(hipStream_t s, Arena &tmp, Arena &keep, Csr &A, const double 
     int *mate = nullptr, *leader = nullptr;
     int *ctl = tmp.get_n<int>(32);  // [0] validation flags, [16] aggregates, [17] A's entries
     NOMEM(ctl);
-    int rc = match_sweep(s, tmp, A, w, 0, group, &mate, &leader, nullptr, ctl, A.nnz_dev ? G_hint : 0, A.nnz_dev);
+    int rc = match_sweep(s, tmp, A, w, 0, group, &mate, &leader, nullptr, ctl, A.nnz_dev ? G_hint : 0, A.nnz_dev,
+                         diag_in);
     if (rc) return rc;
     int *ofs = leader;  // scanned in place
     void *stmp = tmp.get(scan_tmp_bytes(m));
@@ -365,8 +369,11 @@ int build_hierarchy(bcm_handle *h, const bcm_csr *Ain, const double *win) {
     L0.w = persist_copy(h, win, (size_t)n);
     NOMEM(L0.A.rp && L0.A.ci && L0.A.v && L0.w);
     {
-        // full validation of the input, symmetry included when asked
-        double *diag = tmp.get_n<double>(n);
+        // full validation of the input, symmetry included when asked.  The
+        // diagonal goes to the finest level's smoother array, which holds it
+        // for the first matching sweep until the smoother overwrites it.
+        L0.dinv = h->persist.get_n<double>(n);
+        double *diag = L0.dinv;
         int *flags = tmp.get_n<int>(16);
         NOMEM(diag && flags);
         launch_fill_i32(s, 1, flags, 0);
@@ -399,7 +406,7 @@ int build_hierarchy(bcm_handle *h, const bcm_csr *Ain, const double *win) {
             SweepOut so;
             const bool last = sw == P.sweeps - 1;
             int rc = pairwise_sweep(s, tmp, keep, Acur, wcur, P.group, g_hint, so, last ? &h->persist : nullptr,
-                                    last && !have ? &h->persist : nullptr);
+                                    last && !have ? &h->persist : nullptr, k == 0 && sw == 0 ? L0.dinv : nullptr);
             if (rc) return rc;
             if (sw == 0 && L.A.nnz_dev) {  // the level's own entry count is known now
                 L.A.nnz = Acur.nnz;
@@ -462,7 +469,7 @@ int build_hierarchy(bcm_handle *h, const bcm_csr *Ain, const double *win) {
         Level &L = h->lv[l];
         const int nl_ = L.A.n;
         L.G = lanes_for(P.group, L.A);
-        L.dinv = h->persist.get_n<double>(nl_);
+        if (!L.dinv) L.dinv = h->persist.get_n<double>(nl_);  // (the finest level's was allocated first)
         NOMEM(L.dinv);
         if (fp32) {
             L.dinv32 = h->persist.get_n<float>(nl_);
