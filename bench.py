@@ -18,6 +18,7 @@ cpu_baseline: the serial oracle (one thread) running one full setup + solve of
 the same workload.
 """
 import argparse
+import ctypes as C
 import hashlib
 import json
 import os
@@ -193,6 +194,8 @@ def main():
                          f"{sum(times):.1f} s on one host thread, mean {ts:.2f} s per setup + solve"}
         log(f"cpu baseline {cpu['value']:.3f} Mdof/s ({len(times)} runs, mean {ts:.2f} s)")
 
+    grad = gradient_leg(args, c, rp, ci, va, w, b, tol) if "xstar" in c else None
+
     f64 = results["fp64"]
     out = {
         "metric": METRIC, "value": f32["mdofs"], "unit": "Mdof/s", "n_gpus": 1, "steps": args.steps,
@@ -211,7 +214,60 @@ def main():
         "fp32_over_fp64_solve": f64["t_solve_ms"] / f32["t_solve_ms"],
         "roofline": roofline, "cpu_baseline": cpu,
     }
+    if grad is not None:
+        out["gradient"] = grad
     print(json.dumps(out), flush=True)
+
+
+def gradient_leg(args, c, rp, ci, va, w, b, tol):
+    """Backward pass of the differentiable workload (loss 1/2 ||x - x*||^2): the
+    adjoint solve A lambda = x - x* on the forward hierarchy (dL/db = lambda) and
+    the sampled outer product dL/da_ij = -lambda_i x_j on A's pattern.  The
+    adjoint solve is timed per call (synchronised); the outer product by events
+    around `reps` back-to-back launches on the library's stream."""
+    import numpy as np
+    import torch
+
+    from paper_1810_04221_amd import bcm
+
+    n, z = c["n"], len(c["col"])
+    xs = torch.as_tensor(c["xstar"], device=b.device)
+    h = bcm.Hierarchy(rp, ci, va, w, max_coarse=c["max_coarse"], precision="fp32", adjoint_tol=tol)
+    x = h.solve(b, tol=tol)
+    g = x - xs
+    lam = h.solve_adjoint(g)
+    h.sampled_outer(lam, x)
+    torch.cuda.synchronize()
+    t_adj = []
+    for _ in range(args.steps):
+        t0 = time.perf_counter()
+        lam = h.solve_adjoint(g)
+        torch.cuda.synchronize()
+        t_adj.append((time.perf_counter() - t0) * 1e3)
+    inf = h.info()
+    reps = 20
+    out = torch.empty(z, dtype=torch.float64, device=b.device)
+    lib = bcm.load_library()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    args_ = (h.h, C.c_void_p(lam.data_ptr()), C.c_void_p(x.data_ptr()), C.c_void_p(out.data_ptr()))
+    e0.record()
+    rcs = [lib.bcm_sampled_outer(*args_) for _ in range(reps)]
+    e1.record()
+    e1.synchronize()
+    if any(rcs):
+        raise RuntimeError(f"bcm_sampled_outer failed: {lib.bcm_last_error().decode()}")
+    us = e0.elapsed_time(e1) * 1e3 / reps
+    # row pointers, columns, lambda and x once (x gathered), the output written
+    alg = 4.0 * (n + 1) + 12.0 * z + 16.0 * n
+    h.close()
+    r = {"adjoint_ms": float(np.mean(t_adj)), "adjoint_iters": inf["iters"], "adjoint_relres": inf["relres"],
+         "sampled_outer_us": us, "sampled_outer_bytes": alg, "sampled_outer_GBs": alg / (us * 1e-6) / 1e9,
+         "sampled_outer_hbm_frac": alg / (us * 1e-6) / (HBM_PEAK_GBS * 1e9),
+         "timing": f"adjoint: mean of {args.steps} synchronised calls; outer product: events around {reps} launches"}
+    log(f"gradient: adjoint {r['adjoint_ms']:.2f} ms ({r['adjoint_iters']} iterations, relres "
+        f"{r['adjoint_relres']:.2e}); sampled outer product {us:.1f} us, {r['sampled_outer_GBs']:.0f} GB/s "
+        f"({100 * r['sampled_outer_hbm_frac']:.1f}% of 8 TB/s)")
+    return r
 
 
 ABLATIONS = {

@@ -835,17 +835,38 @@ __global__ void __launch_bounds__(kBlock) k_finalize(int nb, const double *__res
 }
 
 
-// dL/da_ij = -lambda_i x_j on the stored pattern
-template <int G>
+// dL/da_ij = -lambda_i x_j on the stored pattern.  R rows per group of G
+// lanes, the loads of their first G entries all issued before any store (as in
+// rows_dot), so a wave keeps R times more requests in flight.
+template <int G, int R>
 __global__ void __launch_bounds__(kBlock)
 k_sampled_outer(int n, const int *__restrict__ rp, const int *__restrict__ ci, const double *__restrict__ lam,
                 const double *__restrict__ x, double *__restrict__ out) {
+    constexpr int NG = kBlock / G;
     const int lane = threadIdx.x % G;
-    const int i = (xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x) / G;
-    if (i >= n) return;
-    const double li = lam[i];
-    const int e = rp[i + 1];
-    for (int q = rp[i] + lane; q < e; q += G) out[q] = -(li * x[ci[q]]);
+    const int base = xcd_block(blockIdx.x, gridDim.x) * NG * R + threadIdx.x / G;
+    int beg[R], end[R];
+    double li[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        const int i = base + k * NG;
+        const int ic = i < n ? i : 0;
+        beg[k] = rp[ic];
+        end[k] = i < n ? rp[ic + 1] : beg[k];
+        li[k] = lam[ic];
+    }
+    int j[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) j[k] = beg[k] + lane < end[k] ? ci[beg[k] + lane] : 0;
+    double xv[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) xv[k] = x[j[k]];
+#pragma unroll
+    for (int k = 0; k < R; ++k)
+        if (beg[k] + lane < end[k]) out[beg[k] + lane] = -(li[k] * xv[k]);
+#pragma unroll
+    for (int k = 0; k < R; ++k)
+        for (int q = beg[k] + lane + G; q < end[k]; q += G) out[q] = -(li[k] * x[ci[q]]);
 }
 
 template <int G, typename V, typename VB>
@@ -1172,8 +1193,9 @@ void launch_finalize(hipStream_t s, int mode, int nb, int first, const double *p
 void launch_sampled_outer(hipStream_t s, const Level &L, const double *lam, const double *x, double *G) {
     with_G(L.G, [&](auto gc) {
         constexpr int g = decltype(gc)::value;
-        hipLaunchKernelGGL(k_sampled_outer<g>, dim3(blocks_for((long long)L.A.n * g)), dim3(kBlock), 0, s, L.A.n,
-                           L.A.rp, L.A.ci, lam, x, G);
+        constexpr int R = 4;
+        hipLaunchKernelGGL((k_sampled_outer<g, R>), dim3(blocks_for(((long long)L.A.n + R - 1) / R * g)),
+                           dim3(kBlock), 0, s, L.A.n, L.A.rp, L.A.ci, lam, x, G);
     });
 }
 

@@ -28,10 +28,12 @@ def B():
     return bcm
 
 
-def test_sampled_outer_bitexact(B, ora):
-    c = P.config("G5", 0.15)
-    say(f"sampled outer {c['name']}")
-    h = B.Hierarchy(c["rowptr"], c["col"], c["val"], max_coarse=c["max_coarse"])
+@pytest.mark.parametrize("name,scale,group", [("G5", 0.15, 0), ("G4", 0.21, 0), ("G5", 0.15, 4)])
+def test_sampled_outer_bitexact(B, ora, name, scale, group):
+    # group 4: rows longer than the lane group (a second pass over each row)
+    c = P.config(name, scale)
+    say(f"sampled outer {c['name']} group={group}")
+    h = B.Hierarchy(c["rowptr"], c["col"], c["val"], max_coarse=c["max_coarse"], group=group)
     lam, x = P.uniform_rhs(c["n"], 21), P.uniform_rhs(c["n"], 22)
     G = h.sampled_outer(lam, x).cpu().numpy()
     Go = ora.sampled_outer(c["rowptr"], c["col"], lam, x)
