@@ -156,6 +156,50 @@ k_spmv_dots_sell(int n, const int *__restrict__ sp, const int *__restrict__ uni,
 // The two fused AXPY pairs of Algorithm 3 and partials of ||r||^2:
 //   d = w - g d ; u += an d ; q = v - g q ; r -= an q   (first step: d = w, q = v)
 // with g = gamma_i / rho_{i-1} and an = alpha_i / rho_i from the finalize step.
+// Two entries per thread and 16-byte accesses (the vectors are 256-byte
+// aligned); with n odd, thread 0 of the grid also takes entry n - 1.
+template <bool First>
+__device__ __forceinline__ void update_pair(double wi, double vi, double &di, double &qi, double &ui, double &ri,
+                                            double g, double an, double &acc) {
+    if (First) { di = wi; qi = vi; }
+    else { di = wi - g * di; qi = vi - g * qi; }
+    ui = ui + an * di;
+    ri = ri - an * qi;
+    acc += ri * ri;
+}
+
+template <bool First>
+__device__ __forceinline__ void update_range(int n, const double *__restrict__ w, const double *__restrict__ v,
+                                             double *__restrict__ d, double *__restrict__ u, double *__restrict__ q,
+                                             double *__restrict__ r, double g, double an, double &acc) {
+    const int blk = xcd_block(blockIdx.x, gridDim.x);
+    const int n2 = n / 2;
+    const double2 *w2 = reinterpret_cast<const double2 *>(w), *v2 = reinterpret_cast<const double2 *>(v);
+    double2 *d2 = reinterpret_cast<double2 *>(d), *u2 = reinterpret_cast<double2 *>(u);
+    double2 *q2 = reinterpret_cast<double2 *>(q), *r2 = reinterpret_cast<double2 *>(r);
+    for (int i = blk * kBlock + threadIdx.x; i < n2; i += gridDim.x * kBlock) {
+        const double2 wi = w2[i], vi = v2[i];
+        double2 di, qi;
+        if (!First) { di = d2[i]; qi = q2[i]; }
+        double2 ui = u2[i], ri = r2[i];
+        update_pair<First>(wi.x, vi.x, di.x, qi.x, ui.x, ri.x, g, an, acc);
+        update_pair<First>(wi.y, vi.y, di.y, qi.y, ui.y, ri.y, g, an, acc);
+        d2[i] = di;
+        q2[i] = qi;
+        u2[i] = ui;
+        r2[i] = ri;
+    }
+    if ((n & 1) && blk == 0 && threadIdx.x == 0) {
+        const int i = n - 1;
+        double di = First ? 0.0 : d[i], qi = First ? 0.0 : q[i], ui = u[i], ri = r[i];
+        update_pair<First>(w[i], v[i], di, qi, ui, ri, g, an, acc);
+        d[i] = di;
+        q[i] = qi;
+        u[i] = ui;
+        r[i] = ri;
+    }
+}
+
 __global__ void __launch_bounds__(kBlock)
 k_update(int n, int first, const double *__restrict__ w, const double *__restrict__ v, double *__restrict__ d,
          double *__restrict__ u, double *__restrict__ q, double *__restrict__ r,
@@ -165,20 +209,8 @@ k_update(int n, int first, const double *__restrict__ w, const double *__restric
     const double g = scal[8], an = scal[9];
     double acc[1] = {0.0};
     if (ok) {
-        const int blk = xcd_block(blockIdx.x, gridDim.x);
-        for (int i = blk * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
-            const double wi = w[i], vi = v[i];
-            double di, qi;
-            if (first) { di = wi; qi = vi; }
-            else { di = wi - g * d[i]; qi = vi - g * q[i]; }
-            d[i] = di;
-            q[i] = qi;
-            u[i] = u[i] + an * di;
-            const double ri = r[i] - an * qi;
-            r[i] = ri;
-            acc[0] += ri * ri;
-        }
+        if (first) update_range<true>(n, w, v, d, u, q, r, g, an, acc[0]);
+        else update_range<false>(n, w, v, d, u, q, r, g, an, acc[0]);
     }
     block_partials<1>(acc, partials);
 }
-
