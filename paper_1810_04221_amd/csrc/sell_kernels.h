@@ -156,8 +156,10 @@ k_spmv_dots_sell(int n, const int *__restrict__ sp, const int *__restrict__ uni,
 // The two fused AXPY pairs of Algorithm 3 and partials of ||r||^2:
 //   d = w - g d ; u += an d ; q = v - g q ; r -= an q   (first step: d = w, q = v)
 // with g = gamma_i / rho_{i-1} and an = alpha_i / rho_i from the finalize step.
-// Two entries per thread and 16-byte accesses (the vectors are 256-byte
-// aligned); with n odd, thread 0 of the grid also takes entry n - 1.
+// Vectors of at least four entries per thread of the grid go in pairs of
+// entries with 16-byte accesses (the vectors are 256-byte aligned; with n odd,
+// thread 0 of the grid also takes entry n - 1); shorter ones one entry at a
+// time, which keeps more waves in flight.
 template <bool First>
 __device__ __forceinline__ void update_pair(double wi, double vi, double &di, double &qi, double &ui, double &ri,
                                             double g, double an, double &acc) {
@@ -166,6 +168,22 @@ __device__ __forceinline__ void update_pair(double wi, double vi, double &di, do
     ui = ui + an * di;
     ri = ri - an * qi;
     acc += ri * ri;
+}
+
+template <bool First>
+__device__ __forceinline__ void update_range1(int n, const double *__restrict__ w, const double *__restrict__ v,
+                                              double *__restrict__ d, double *__restrict__ u,
+                                              double *__restrict__ q, double *__restrict__ r, double g, double an,
+                                              double &acc) {
+    const int blk = xcd_block(blockIdx.x, gridDim.x);
+    for (int i = blk * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+        double di = First ? 0.0 : d[i], qi = First ? 0.0 : q[i], ui = u[i], ri = r[i];
+        update_pair<First>(w[i], v[i], di, qi, ui, ri, g, an, acc);
+        d[i] = di;
+        q[i] = qi;
+        u[i] = ui;
+        r[i] = ri;
+    }
 }
 
 template <bool First>
@@ -209,8 +227,11 @@ k_update(int n, int first, const double *__restrict__ w, const double *__restric
     const double g = scal[8], an = scal[9];
     double acc[1] = {0.0};
     if (ok) {
-        if (first) update_range<true>(n, w, v, d, u, q, r, g, an, acc[0]);
-        else update_range<false>(n, w, v, d, u, q, r, g, an, acc[0]);
+        const bool pairs = (long long)n >= 4LL * gridDim.x * kBlock;
+        if (pairs && first) update_range<true>(n, w, v, d, u, q, r, g, an, acc[0]);
+        else if (pairs) update_range<false>(n, w, v, d, u, q, r, g, an, acc[0]);
+        else if (first) update_range1<true>(n, w, v, d, u, q, r, g, an, acc[0]);
+        else update_range1<false>(n, w, v, d, u, q, r, g, an, acc[0]);
     }
     block_partials<1>(acc, partials);
 }
