@@ -72,7 +72,7 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path (see DESIGN.md, sharding)",
+        print("bench.py measures one GPU only: the solver has no multi-GPU path; run it with --gpus 1",
               file=sys.stderr)
         sys.exit(2)
 
