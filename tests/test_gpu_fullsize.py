@@ -129,3 +129,25 @@ def test_fullsize_adjoint_and_sampled_outer(B):
 def torch_tensor(a, like):
     import torch
     return torch.as_tensor(a, dtype=torch.float64, device=like.device)
+
+
+def test_odd_length_vectors_in_pairs(B, ora):
+    # 129^3 = 2,146,689 rows: long enough for the flexible-CG update to take its
+    # entries in pairs, and odd, so the last entry goes the single-entry way
+    nx = 129
+    rp, ci, va = P.poisson3d(nx)
+    n = nx ** 3
+    b = P.uniform_rhs(n, 5)
+    mc = P.default_max_coarse(n)
+    say(f"gpu solve fp64 poisson3d_{nx}^3 n={n}")
+    h = B.Hierarchy(rp, ci, va, max_coarse=mc, precision="fp64")
+    x = h.solve(b, tol=1e-8).cpu().numpy()
+    inf = h.info()
+    A = sp.csr_matrix((va, ci, rp), shape=(n, n))
+    rel = np.linalg.norm(b - A @ x) / np.linalg.norm(b)
+    assert rel <= 1e-8, rel
+    say(f"oracle setup + solve poisson3d_{nx}^3")
+    ho = ora.Hierarchy(rp, ci, va, np.ones(n), max_coarse=mc)
+    _, io = ho.solve(b, tol=1e-8)
+    assert abs(inf["iters"] - io["iters"]) <= 1, (inf["iters"], io["iters"])
+    h.close()
