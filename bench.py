@@ -9,12 +9,17 @@ plain float64 path is timed the same way and reported beside it.
 
 value = n / (mean seconds per step) / 1e6  [Mdof/s]
 
-roofline: the kernel class with the largest share of solve time, timed with
-HIP events on the library's stream during a third timed leg (the FP32 form
-with eager launches, so that the event pair brackets exactly that kernel);
-achieved GB/s = its algorithmic bytes / its event time.  The two headline
-legs run without events.
-cpu_baseline: the serial oracle (one thread) running one full setup + solve of
+roofline: the single kernel with the largest event time per step over the
+whole step (setup kernels included), timed with HIP events taken by that
+kernel's own dispatch on the library's stream during a third timed leg (the
+FP32 form, eager launches); achieved GB/s = its algorithmic bytes / its event
+time.  The two headline legs run without events.
+setup_roofline: the setup's algorithmic bytes (sum over its pairwise sweeps of
+72 z + 80 m) over its time, with the event-timed setup classes beside it.
+roofline_hbm_160: the finest-level solve kernels on the 160^3 heterogeneous
+diffusion workload, whose matrix and vectors (about 0.8 GB) do not fit the
+256 MB Infinity Cache: an HBM-bound point, timed the same way.
+cpu_baseline: the serial oracle (one thread) running full setups + solves of
 the same workload.
 """
 import argparse
@@ -30,25 +35,32 @@ sys.path.insert(0, ROOT)
 
 METRIC = "setup+solve s to rel-res 1e-8 (Mdof/s, HBM %), FP32-cycle vs FP64 AMG-FCG"
 HBM_PEAK_GBS = 8000.0
-# the sources of the profiled kernels: recorded counter traffic applies while
+CSRC = os.path.join(ROOT, "paper_1810_04221_amd", "csrc")
+# the sources of each profiled kernel: recorded counter traffic applies while
 # they hash to the value stored with it
-TRAFFIC_KEY_FILES = ("sell_kernels.h", "device.h")
+TRAFFIC_SOURCES = {"down0": ("sell_kernels.h", "device.h"), "up0": ("sell_kernels.h", "device.h"),
+                   "spmv_dots": ("sell_kernels.h", "device.h"), "update": ("sell_kernels.h", "device.h"),
+                   "setup_suitor": ("setup.hip", "device.h")}
 
 
-def kernels_sha256():
+def sources_sha256(cls):
     h = hashlib.sha256()
-    for f in TRAFFIC_KEY_FILES:
-        h.update(open(os.path.join(ROOT, "paper_1810_04221_amd", "csrc", f), "rb").read())
+    for f in TRAFFIC_SOURCES.get(cls.replace("_160", ""), ()):
+        h.update(open(os.path.join(CSRC, f), "rb").read())
     return h.hexdigest()
 
 
-CLASSES = ["down0", "up0", "spmv_dots", "update", "coarse", "mid"]
-SINGLE_KERNEL = ["down0", "up0", "spmv_dots", "update", "coarse"]  # one launch per iteration
+SOLVE_CLASSES = ["down0", "up0", "spmv_dots", "update", "coarse", "mid"]
+SETUP_CLASSES = ["setup_match", "setup_suitor", "setup_galerkin"]
+CLASSES = SOLVE_CLASSES + SETUP_CLASSES
+# classes that are one kernel launch per bracket
+SINGLE_KERNEL = ["down0", "up0", "spmv_dots", "update", "coarse", "setup_suitor"]
 KERNEL_OF_CLASS = {"down0": "k_down_res_sell (finest level: p * (b - A D b), the down leg's residual)",
                    "up0": "k_smooth_sell (finest level: post-smoothing of the prolonged iterate)",
                    "spmv_dots": "k_spmv_dots_sell (v = A w and three dot products, finest level, FP64)",
                    "update": "k_update (four vector updates and ||r||^2)",
-                   "coarse": "coarsest-level solve (k_tail, k_coarse_dense or k_coarse)"}
+                   "coarse": "coarsest-level solve (k_coarse_dense on the folded levels, k_tail or k_coarse)",
+                   "setup_suitor": "k_suitor (Suitor matching, proposals raised by 64-bit atomicMax)"}
 
 
 def log(msg):
@@ -63,6 +75,8 @@ def main():
     ap.add_argument("--workload", default="G2")
     ap.add_argument("--scale", type=float, default=1.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-hbm-point", action="store_true",
+                    help="skip the 160^3 roofline point (HBM-bound finest-level kernels)")
     ap.add_argument("--calibration-copy-mb", type=int, default=0,
                     help="run one device copy of this many MiB first (reference for HBM counters)")
     ap.add_argument("--ablation", choices=sorted(ABLATIONS), default=None,
@@ -115,16 +129,24 @@ def main():
         return
 
     all_mask = sum(bcm.PROF.values())
-    # warm-up, and the class with the largest share of solve time
+    # warm-up, and the single kernel with the largest event time per step
+    # (setup and solve kernels alike)
     share = {k: 0.0 for k in CLASSES}
-    for it in range(max(1, args.warmup)):
+    setup_cls = {k: [0, 0.0, 0.0] for k in SETUP_CLASSES}
+    nwarm = max(1, args.warmup)
+    for it in range(nwarm):
         for prec in ("fp32", "fp64"):
             info, prof = step(prec, all_mask)
             if prec == "fp32":
                 for k, (nl_, ms, by) in prof.items():
-                    share[k] += ms
+                    share[k] += ms / nwarm
+                    if k in setup_cls:
+                        setup_cls[k][0] += nl_ / nwarm
+                        setup_cls[k][1] += ms / nwarm
+                        setup_cls[k][2] += by / nwarm
     dom = max(SINGLE_KERNEL, key=share.get)
-    log(f"event share of solve kernels (fp32 cycle, ms): {share}; dominant {dom}")
+    log("event time per step by class (fp32 cycle, ms): "
+        + ", ".join(f"{k} {v:.3f}" for k, v in sorted(share.items(), key=lambda kv: -kv[1])) + f"; dominant {dom}")
 
     # timed legs: FP32 cycle (the headline) and FP64, no profiling; then a third
     # timed leg of the FP32 form with the dominant kernel bracketed by HIP
@@ -148,34 +170,38 @@ def main():
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         ms_step = (t1 - t0) * 1e3 / args.steps
-        prec = leg
         inf = infos[-1]
-        results[prec] = dict(ms_per_step=ms_step, mdofs=n / (ms_step * 1e-3) / 1e6, iters=inf["iters"],
-                             relres=inf["relres"], t_setup_ms=float(np.mean([i["t_setup_ms"] for i in infos])),
-                             t_solve_ms=float(np.mean([i["t_solve_ms"] for i in infos])), levels=inf["n"],
-                             vcmplx=inf["vcmplx"], iter_bytes=inf["iter_bytes"],
-                             prof=(tot_l, tot_ms, tot_b))
-        r = results[prec]
+        results[leg] = dict(ms_per_step=ms_step, mdofs=n / (ms_step * 1e-3) / 1e6, iters=inf["iters"],
+                            relres=inf["relres"], t_setup_ms=float(np.mean([i["t_setup_ms"] for i in infos])),
+                            t_solve_ms=float(np.mean([i["t_solve_ms"] for i in infos])), levels=inf["n"],
+                            vcmplx=inf["vcmplx"], iter_bytes=inf["iter_bytes"], setup_bytes=inf["setup_bytes"],
+                            sweeps=inf["sweeps_run"], prof=(tot_l, tot_ms, tot_b))
+        r = results[leg]
         r["solve_hbm_frac"] = r["iter_bytes"] * r["iters"] / (r["t_solve_ms"] * 1e-3) / (HBM_PEAK_GBS * 1e9)
-        log(f"{prec}: {ms_step:.2f} ms/step ({r['t_setup_ms']:.2f} setup + {r['t_solve_ms']:.2f} solve), "
+        log(f"{leg}: {ms_step:.2f} ms/step ({r['t_setup_ms']:.2f} setup + {r['t_solve_ms']:.2f} solve), "
             f"{r['mdofs']:.1f} Mdof/s, iters {r['iters']}, relres {r['relres']:.2e}, levels {r['levels']}")
 
     f32 = results["fp32"]
     l_, ms, by = results["roofline"]["prof"]
-    achieved = (by / l_) / ((ms / l_) * 1e-3) / 1e9 if l_ else None
-    traffic = None
-    tpath = os.path.join(ROOT, "profiles", "traffic.json")
-    if os.path.exists(tpath):
-        t = json.load(open(tpath))
-        if t.get("kernels_sha256") == kernels_sha256() and dom in t.get("bytes_per_launch", {}):
-            traffic = t["bytes_per_launch"][dom]
-    roofline = {"bound": "hbm", "kernel": KERNEL_OF_CLASS[dom],
-                "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": traffic,
-                "algorithmic_bytes_per_launch": (by / l_) if l_ else None,
-                "avg_launch_us": (ms / l_ * 1e3) if l_ else None, "launches": l_,
-                "timed_leg": "FP32 cycle, eager launches, HIP events around the kernel",
-                "timed_leg_ms_per_step": results["roofline"]["ms_per_step"]}
+    roofline = {"bound": "hbm", "kernel": KERNEL_OF_CLASS[dom]}
+    roofline.update(class_roofline(dom, l_, ms, by))
+    roofline.update({"timed_leg": "FP32 cycle, eager launches, HIP events taken by the kernel's own dispatch",
+                     "timed_leg_ms_per_step": results["roofline"]["ms_per_step"]})
+
+    # the setup against its byte model
+    sb = f32["setup_bytes"]
+    setup_roofline = {"bound": "hbm", "achieved": sb / (f32["t_setup_ms"] * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
+                      "unit": "GB/s", "frac": sb / (f32["t_setup_ms"] * 1e-3) / (HBM_PEAK_GBS * 1e9),
+                      "algorithmic_bytes": sb, "sweeps": f32["sweeps"],
+                      "model": "sum over the pairwise sweeps on (m rows, z entries) of 72 z + 80 m",
+                      "setup_ms": f32["t_setup_ms"], "setup_fraction_of_step": f32["t_setup_ms"] / f32["ms_per_step"],
+                      "classes": {k: {"brackets": v[0], "ms": v[1], "algorithmic_bytes": v[2],
+                                      "GBs": (v[2] / (v[1] * 1e-3) / 1e9) if v[1] else None,
+                                      "frac": (v[2] / (v[1] * 1e-3) / (HBM_PEAK_GBS * 1e9)) if v[1] else None}
+                                  for k, v in setup_cls.items()},
+                      "timed": f"classes: HIP events per sweep over {nwarm} warm-up setup(s), FP32 form"}
+
+    hbm160 = None if args.no_hbm_point else hbm_point(args)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -191,8 +217,9 @@ def main():
         ts = sum(times) / len(times)
         cpu = {"value": n / ts / 1e6, "unit": "Mdof/s", "cores": 1, "kind": "oracle",
                "sample": f"{len(times)} full setups + solves of {c['name']} (n={n}, {io['iters']} iterations each), "
-                         f"{sum(times):.1f} s on one host thread, mean {ts:.2f} s per setup + solve"}
-        log(f"cpu baseline {cpu['value']:.3f} Mdof/s ({len(times)} runs, mean {ts:.2f} s)")
+                         f"{sum(times):.1f} s on one host thread, mean {ts:.2f} s per setup + solve",
+               "host": host_cpu()}
+        log(f"cpu baseline {cpu['value']:.3f} Mdof/s ({len(times)} runs, mean {ts:.2f} s) on {cpu['host']}")
 
     grad = gradient_leg(args, c, rp, ci, va, w, b, tol) if "xstar" in c else None
 
@@ -212,11 +239,73 @@ def main():
                  "solve_hbm_frac": f64["solve_hbm_frac"]},
         "fp32_over_fp64": f32["mdofs"] / f64["mdofs"],
         "fp32_over_fp64_solve": f64["t_solve_ms"] / f32["t_solve_ms"],
-        "roofline": roofline, "cpu_baseline": cpu,
+        # a solve bound by bandwidth alone would gain the ratio of the algorithmic bytes per iteration
+        "fp32_over_fp64_solve_byte_model": (f64["iter_bytes"] * f64["iters"]) / (f32["iter_bytes"] * f32["iters"]),
+        "roofline": roofline, "setup_roofline": setup_roofline, "cpu_baseline": cpu,
     }
+    if hbm160 is not None:
+        out["roofline_hbm_160"] = hbm160
     if grad is not None:
         out["gradient"] = grad
     print(json.dumps(out), flush=True)
+
+
+def class_roofline(cls, launches, ms, nbytes):
+    """achieved / peak of one event-timed class, with the counter traffic
+    recorded for it when its sources still hash to the recorded value."""
+    achieved = (nbytes / launches) / ((ms / launches) * 1e-3) / 1e9 if launches else None
+    traffic = None
+    tpath = os.path.join(ROOT, "profiles", "traffic.json")
+    if os.path.exists(tpath):
+        t = json.load(open(tpath)).get("per_class", {}).get(cls)
+        if t and t.get("sources_sha256") == sources_sha256(cls):
+            traffic = t["hbm_bytes"]
+    return {"achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": traffic,
+            "algorithmic_bytes_per_launch": (nbytes / launches) if launches else None,
+            "avg_launch_us": (ms / launches * 1e3) if launches else None, "launches": launches}
+
+
+def host_cpu():
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count()
+    return f"{model}; {avail} host threads available (nproc), 1 used"
+
+
+def hbm_point(args):
+    """The finest-level solve kernels on the 160^3 heterogeneous diffusion
+    workload (beyond the Infinity Cache), FP32 cycle, one setup + solve with
+    HIP events on three classes."""
+    import torch
+    from paper_1810_04221_amd import bcm, problems
+    c = problems.config("G3", 1.0)
+    dev = torch.device("cuda", 0)
+    t = {k: torch.as_tensor(c[k], device=dev) for k in ("rowptr", "col", "val", "w", "b")}
+    mask = bcm.PROF["down0"] | bcm.PROF["spmv_dots"] | bcm.PROF["update"] | bcm.PROF["up0"]
+    h = bcm.Hierarchy(t["rowptr"], t["col"], t["val"], t["w"], max_coarse=c["max_coarse"], precision="fp32",
+                      profile=mask, graph=False)
+    h.solve(t["b"], tol=c["tol"])
+    inf = h.info()
+    ks = {}
+    for cls, name in (("spmv_dots", "k_spmv_dots_sell"), ("down0", "k_down_res_sell"), ("up0", "k_smooth_sell"),
+                      ("update", "k_update")):
+        l_, ms, by = h.profile(cls)
+        ks[name] = class_roofline(cls + "_160", l_, ms, by)
+    h.close()
+    log("160^3 HBM point: " + ", ".join(f"{k} {v['frac'] * 100:.1f}%" for k, v in ks.items() if v["frac"]))
+    return {"workload": f"{c['name']} (n={c['n']}, nnz={len(c['col'])}), FP32 cycle, {inf['iters']} iterations",
+            "bound": "hbm", "kernels": ks,
+            "timed": "HIP events taken by each kernel's own dispatch, one setup + solve"}
 
 
 def gradient_leg(args, c, rp, ci, va, w, b, tol):

@@ -14,7 +14,8 @@
  *  - Work is enqueued on bcm_params.stream (a hipStream_t; NULL = the default
  *    stream).  Calls that return sizes or convergence information synchronise
  *    that stream before returning.
- *  - Return codes: BCM_OK (0), BCM_MAXIT (1, not fatal), or a negative error.
+ *  - Return codes: BCM_OK (0), BCM_MAXIT (1) or BCM_STAGNATED (2), both not
+ *    fatal, or a negative error.
  *    bcm_last_error() gives a message for the last failing call of the
  *    calling thread.  A handle must not be used by two threads at once.
  *  - CSR requirements: int32 row_ptr[n + 1] with row_ptr[0] = 0 and
@@ -39,6 +40,10 @@ extern "C" {
 enum {
     BCM_OK = 0,
     BCM_MAXIT = 1,        /* itmax reached before tol; x holds the last iterate */
+    BCM_STAGNATED = 2,    /* the recurrence residual met tol but the true residual
+                             b - A x stayed above it through every restart (rounding
+                             floor): x holds the last iterate, bcm_info its true
+                             relative residual */
     BCM_EINVAL = -1,      /* invalid argument or matrix (see bcm_last_error) */
     BCM_EBREAKDOWN = -2,  /* flexible CG breakdown: rho <= 0 or not finite */
     BCM_ENOMEM = -3,      /* device allocation failed */
@@ -62,11 +67,14 @@ typedef struct {
  * Parameters (Section 5, experimental settings, gives the defaults):
  *   max_levels     40    maximum number of levels
  *   max_coarse     0     stop coarsening once n_k <= max_coarse;
- *                        0 means round(40 * n^(1/3))
- *   min_ratio      0     a level formed with n_{k-1} / n_k < min_ratio is the
- *                        coarsest (coarsening has stalled); 0 means
- *                        sqrt(2^sweeps), i.e. 2 for double pairwise
- *                        aggregation; 1 stops only when the size is unchanged
+ *                        0 means round(40 * n^(1/3)).  With max_levels and a
+ *                        level that leaves the size unchanged, this is the
+ *                        stopping rule of Section 5.
+ *   min_ratio      0     <= 1: Section 5's rule alone.  > 1: also stop at the
+ *                        first level formed with n_{k-1} / n_k < min_ratio
+ *                        (coarsening that has stalled; a rule of this library,
+ *                        not of the paper: 2 = a level that did not halve the
+ *                        size under double pairwise aggregation)
  *   sweeps         2     pairwise matching sweeps composed per level
  *                        (2 = double pairwise aggregation, ratio <= 4); 1..4
  *   coarse_sweeps  20    l1-Jacobi sweeps from zero at the coarsest level
@@ -173,8 +181,9 @@ int bcm_setup(const bcm_csr *A, const double *w, const bcm_params *p, bcm_handle
  *   b   float64[n] device right-hand side.
  *   x   float64[n] device; in: initial guess, out: solution.
  *   tol stop when ||r||_2 / ||b||_2 <= tol (Section 5: relative residual);
- *       the true residual b - A x is recomputed at exit.
- * Returns BCM_OK, BCM_MAXIT, BCM_EBREAKDOWN or an error.
+ *       the true residual b - A x is recomputed at exit; while it misses
+ *       tol the solve restarts from x (at most three restarts).
+ * Returns BCM_OK, BCM_MAXIT, BCM_STAGNATED, BCM_EBREAKDOWN or an error.
  */
 int bcm_solve(bcm_handle *h, const double *b, double *x, double tol);
 
@@ -220,6 +229,10 @@ typedef struct {
     double t_solve_ms;
     double cycle_bytes;  /* algorithmic bytes of one preconditioner application */
     double iter_bytes;   /* algorithmic bytes of one outer iteration, cycle included */
+    double setup_bytes;  /* algorithmic bytes of the setup: sum over its pairwise sweeps on
+                            (m rows, z entries) of 72 z + 80 m, a lower bound */
+    int32_t sweeps_run;  /* pairwise sweeps the setup ran */
+    int32_t long_rows;   /* rows of all levels on the long-row path of the solve kernels */
 } bcm_info_t;
 
 int bcm_info(const bcm_handle *h, bcm_info_t *out);
@@ -249,13 +262,18 @@ enum {
     BCM_PROF_SPMV_DOTS = 4,    /* v = A w fused with the three dot products */
     BCM_PROF_UPDATE = 8,       /* the four fused vector updates + ||r||^2 */
     BCM_PROF_CYCLE_COARSE = 16, /* the coarsest-level solve */
-    BCM_PROF_CYCLE_MID = 32     /* every cycle kernel of levels 1 .. nl - 2 (several per cycle) */
+    BCM_PROF_CYCLE_MID = 32,    /* every cycle kernel of levels 1 .. nl - 2 (several per cycle) */
+    /* setup classes, one bracket per pairwise sweep, timed during bcm_setup */
+    BCM_PROF_SETUP_MATCH = 64,     /* edge weights and Suitor candidate lists (long rows included) */
+    BCM_PROF_SETUP_SUITOR = 128,   /* the Suitor matching kernel itself */
+    BCM_PROF_SETUP_GALERKIN = 256  /* Galerkin product: count, row pointers, fill */
 };
 
 /*
- * Event timings of the last bcm_solve for one kernel class: number of
- * launches, their summed duration in ms, and the summed algorithmic bytes
- * (the bytes the operation must move at least once).
+ * Event timings for one kernel class: number of launches (brackets), their
+ * summed duration in ms, and the summed algorithmic bytes (the bytes the
+ * operation must move at least once).  Solve classes: the last bcm_solve;
+ * setup classes: bcm_setup.
  */
 int bcm_profile(const bcm_handle *h, int32_t kclass, int64_t *launches, double *ms, double *bytes);
 

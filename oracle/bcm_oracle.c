@@ -352,15 +352,16 @@ void ora_free(void *hv) {
 }
 
 /*
- * Builds the hierarchy.  Level k is the coarsest when n_k <= max_coarse, or
- * k + 1 == max_levels, or its coarsening left the size unchanged, or it was
- * formed with a size ratio n_{k-1} / n_k below min_ratio (<= 0: the square root
- * of the largest ratio 2^sweeps, i.e. 2 for double pairwise aggregation).
- * Section 5 fixes the coarsest size, the level limit and the largest ratio but
- * not what ends a stalled coarsening; below that ratio the matching no longer
- * halves the size per level and further levels only add cost.  Each
- * coarsening composes `sweeps` pairwise sweeps; a sweep that forms no pair is
- * skipped.  Returns NULL on invalid input (status < 0).
+ * Builds the hierarchy.  Section 5 (experimental settings) stops the
+ * coarsening at a coarsest matrix of at most maxcoarseset * n^(1/3) rows and
+ * at 40 levels: level k is the coarsest when n_k <= max_coarse, or
+ * k + 1 == max_levels, or its coarsening left the size unchanged (no pair
+ * formed: every later sweep would form none either).  min_ratio > 1 adds a
+ * rule that is not the paper's: a level formed with a size ratio
+ * n_{k-1} / n_k below min_ratio is the coarsest (coarsening that has stalled);
+ * min_ratio <= 1 leaves it out.  Each coarsening composes `sweeps` pairwise
+ * sweeps; a sweep that forms no pair is skipped.  Returns NULL on invalid
+ * input (status < 0).
  */
 void *ora_setup(int n, const int *rp, const int *ci, const double *v, const double *w,
                 int max_levels, int max_coarse, int sweeps, int coarse_sweeps, int cycle,
@@ -380,7 +381,7 @@ void *ora_setup(int n, const int *rp, const int *ci, const double *v, const doub
         }
         if (!hasd) { *status = -1; return NULL; }
     }
-    const double rmin = min_ratio > 0.0 ? min_ratio : sqrt(ldexp(1.0, sweeps));
+    const double rmin = min_ratio > 1.0 ? min_ratio : 1.0;
     ohier *h = calloc(1, sizeof(ohier));
     h->coarse_sweeps = coarse_sweeps;
     h->cycle = cycle;
@@ -440,8 +441,8 @@ void *ora_setup(int n, const int *rp, const int *ci, const double *v, const doub
         h->lv[k + 1].A = Acur;
         h->lv[k + 1].w = wcur;
         k++;
-        /* coarsening has stalled: the new level is the coarsest */
-        if ((double)nk < rmin * (double)Acur.n) break;
+        /* min_ratio > 1 only: coarsening has stalled, the new level is the coarsest */
+        if (rmin > 1.0 && (double)nk < rmin * (double)Acur.n) break;
     }
     h->nl = k + 1;
     for (int l = 0; l < h->nl; l++) level_alloc_vectors(&h->lv[l]);

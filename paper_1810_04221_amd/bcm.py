@@ -15,10 +15,11 @@ import torch
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libbcm.so")
 
-BCM_OK, BCM_MAXIT, BCM_EINVAL, BCM_EBREAKDOWN, BCM_ENOMEM, BCM_EHIP = 0, 1, -1, -2, -3, -4
+BCM_OK, BCM_MAXIT, BCM_STAGNATED, BCM_EINVAL, BCM_EBREAKDOWN, BCM_ENOMEM, BCM_EHIP = 0, 1, 2, -1, -2, -3, -4
 BCM_FP64, BCM_FP32_CYCLE = 0, 1
 CYCLES = {"V": 1, "W": 2, "K": 3}  # BCM_VCYCLE, BCM_WCYCLE, BCM_KCYCLE
-PROF = {"down0": 1, "up0": 2, "spmv_dots": 4, "update": 8, "coarse": 16, "mid": 32}
+PROF = {"down0": 1, "up0": 2, "spmv_dots": 4, "update": 8, "coarse": 16, "mid": 32,
+        "setup_match": 64, "setup_suitor": 128, "setup_galerkin": 256}
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
 DEALLOC_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_size_t, C.c_void_p)
@@ -42,7 +43,8 @@ class BcmInfo(C.Structure):
     _fields_ = [("nl", C.c_int32), ("precision", C.c_int32), ("iters", C.c_int32), ("status", C.c_int32),
                 ("n", C.c_int32 * 64), ("nnz", C.c_int64 * 64), ("vcmplx", C.c_double), ("cratio", C.c_double),
                 ("cratio_nl", C.c_double), ("relres", C.c_double), ("t_setup_ms", C.c_double),
-                ("t_solve_ms", C.c_double), ("cycle_bytes", C.c_double), ("iter_bytes", C.c_double)]
+                ("t_solve_ms", C.c_double), ("cycle_bytes", C.c_double), ("iter_bytes", C.c_double),
+                ("setup_bytes", C.c_double), ("sweeps_run", C.c_int32), ("long_rows", C.c_int32)]
 
 
 EXPORTS = ["bcm_default_params", "bcm_setup", "bcm_solve", "bcm_precond", "bcm_solve_adjoint", "bcm_sampled_outer", "bcm_info",
@@ -153,7 +155,9 @@ class Hierarchy:
         self.stream = torch.cuda.current_stream(self.device).cuda_stream
         self.rowptr = _dev(rowptr, torch.int32, self.device)
         self.col = _dev(col, torch.int32, self.device)
-        self.val = _dev(val, torch.float64, self.device)
+        # a copy of its own: the values the hierarchy was built from, for
+        # check_values (a device tensor passed in would otherwise be aliased)
+        self.val = _dev(val, torch.float64, self.device).clone()
         self.n = self.rowptr.numel() - 1
         self.nnz = self.col.numel()
         w = torch.ones(self.n, dtype=torch.float64, device=self.device) if w is None else _dev(w, torch.float64, self.device)
@@ -177,34 +181,68 @@ class Hierarchy:
         except Exception:
             pass
 
+    # The library works on the stream captured at construction.  Inputs made on
+    # the caller's current stream are waited for before a call, and outputs are
+    # made visible to that stream after it.
+    def _enter(self):
+        cur = torch.cuda.current_stream(self.device)
+        if cur.cuda_stream == self.stream:
+            return cur, None
+        lib = torch.cuda.ExternalStream(self.stream, device=self.device)
+        lib.wait_stream(cur)
+        return cur, lib
+
+    def _leave(self, cur, lib):
+        if lib is not None:
+            cur.wait_stream(lib)
+
     def solve(self, b, x0=None, tol=1e-8, allow_maxit=False):
         b = _dev(b, torch.float64, self.device)
         x = torch.zeros(self.n, dtype=torch.float64, device=self.device) if x0 is None else _dev(x0, torch.float64, self.device).clone()
+        cur, lib = self._enter()
         rc = load_library().bcm_solve(self.h, C.c_void_p(b.data_ptr()), C.c_void_p(x.data_ptr()), float(tol))
-        _check(rc, (BCM_OK, BCM_MAXIT) if allow_maxit else (BCM_OK,))
+        self._leave(cur, lib)
+        _check(rc, (BCM_OK, BCM_MAXIT, BCM_STAGNATED) if allow_maxit else (BCM_OK,))
         return x
 
     def precond(self, r):
         """z = B(r): one cycle of the preconditioner."""
         r = _dev(r, torch.float64, self.device)
         z = torch.empty(self.n, dtype=torch.float64, device=self.device)
-        _check(load_library().bcm_precond(self.h, C.c_void_p(r.data_ptr()), C.c_void_p(z.data_ptr())))
+        cur, lib = self._enter()
+        rc = load_library().bcm_precond(self.h, C.c_void_p(r.data_ptr()), C.c_void_p(z.data_ptr()))
+        self._leave(cur, lib)
+        _check(rc)
         return z
 
     def solve_adjoint(self, g, allow_maxit=False):
         g = _dev(g, torch.float64, self.device)
         lam = torch.empty(self.n, dtype=torch.float64, device=self.device)
+        cur, lib = self._enter()
         rc = load_library().bcm_solve_adjoint(self.h, C.c_void_p(g.data_ptr()), C.c_void_p(lam.data_ptr()))
-        _check(rc, (BCM_OK, BCM_MAXIT) if allow_maxit else (BCM_OK,))
+        self._leave(cur, lib)
+        _check(rc, (BCM_OK, BCM_MAXIT, BCM_STAGNATED) if allow_maxit else (BCM_OK,))
         return lam
 
     def sampled_outer(self, lam, x):
         lam = _dev(lam, torch.float64, self.device)
         x = _dev(x, torch.float64, self.device)
         out = torch.empty(self.nnz, dtype=torch.float64, device=self.device)
-        _check(load_library().bcm_sampled_outer(self.h, C.c_void_p(lam.data_ptr()), C.c_void_p(x.data_ptr()),
-                                                C.c_void_p(out.data_ptr())))
+        cur, lib = self._enter()
+        rc = load_library().bcm_sampled_outer(self.h, C.c_void_p(lam.data_ptr()), C.c_void_p(x.data_ptr()),
+                                              C.c_void_p(out.data_ptr()))
+        self._leave(cur, lib)
+        _check(rc)
         return out
+
+    def check_values(self, val):
+        """Raises ValueError unless ``val`` holds exactly the values the
+        hierarchy was built from (the solve uses the hierarchy's copy of A)."""
+        v = val.detach() if isinstance(val, torch.Tensor) else torch.as_tensor(val)
+        v = v.to(device=self.device, dtype=torch.float64)
+        if v.numel() != self.nnz or not torch.equal(v.reshape(-1), self.val):
+            raise ValueError("val differs from the matrix values this Hierarchy was built from: "
+                             "build a new Hierarchy for the new values")
 
     def info(self) -> dict:
         i = BcmInfo()
@@ -213,7 +251,8 @@ class Hierarchy:
         return dict(nl=nl, n=list(i.n[:nl]), nnz=list(i.nnz[:nl]), vcmplx=i.vcmplx, cratio=i.cratio,
                     cratio_nl=i.cratio_nl, iters=i.iters, status=i.status, relres=i.relres,
                     t_setup_ms=i.t_setup_ms, t_solve_ms=i.t_solve_ms, cycle_bytes=i.cycle_bytes,
-                    iter_bytes=i.iter_bytes, precision=i.precision)
+                    iter_bytes=i.iter_bytes, precision=i.precision, setup_bytes=i.setup_bytes,
+                    sweeps_run=i.sweeps_run, long_rows=i.long_rows)
 
     def level(self, k: int) -> dict:
         """Level k copied to host numpy arrays."""
@@ -261,11 +300,14 @@ class BcmSolve(torch.autograd.Function):
     values of A and in b.  Backward solves A lambda = dL/dx with the same
     hierarchy (A symmetric) and returns dL/db = lambda and
     dL/da_ij = -lambda_i x_j on A's pattern.  ``val`` must hold the values the
-    hierarchy was built from.  With save_x=False the solution is recomputed in
-    backward instead of being kept."""
+    hierarchy was built from: forward compares them with the hierarchy's copy
+    and raises ValueError when they differ (after an optimiser step, build a
+    new Hierarchy).  With save_x=False the solution is recomputed in backward
+    instead of being kept."""
 
     @staticmethod
     def forward(ctx, val, b, hier: Hierarchy, tol: float = 1e-10, save_x: bool = True):
+        hier.check_values(val)
         x = hier.solve(b, tol=tol)
         ctx.hier, ctx.tol, ctx.save_x = hier, tol, save_x
         if save_x:

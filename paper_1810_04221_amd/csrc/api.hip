@@ -149,7 +149,15 @@ int read_back(hipStream_t s, const void *dev, size_t bytes, void *host) {
     return BCM_OK;
 }
 
+// The same without the pinned staging buffer (no host allocation at all).
+int read_back_plain(hipStream_t s, const void *dev, size_t bytes, void *host) {
+    HIPCHK(hipMemcpyAsync(host, dev, bytes, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return BCM_OK;
+}
+
 struct SweepOut {
+    int prof_gal = -1;  // setup profile bracket of this sweep's Galerkin product
     int nc = 0;
     int *agg = nullptr;
     double *p = nullptr;
@@ -158,8 +166,6 @@ struct SweepOut {
     Csr Ac;
 };
 
-// Weights, ranks, Suitor matching and mate/leader flags on (A, w): Section 2.2
-// and 3.1.  tmp-lifetime buffers come from `tmp`.
 // Lanes per row of the CSR row kernels: the forced width of the parameters,
 // else the rule on the average row length.
 int lanes_for(int group, const Csr &A) {
@@ -168,48 +174,254 @@ int lanes_for(int group, const Csr &A) {
 
 bool valid_group(int g) { return g == 0 || g == -1 || g == 4 || g == 8 || g == 16 || g == 32 || g == 64; }
 
+// Sub-allocation from one block of device memory in 256-byte steps (a null
+// base with an unbounded size measures a layout without touching memory).
+struct Carver {
+    char *cur = nullptr;
+    size_t left = 0;
+    size_t used = 0;
+    bool ok = true;
+    template <typename T>
+    T *get(size_t n) {
+        size_t b = (n * sizeof(T) + 255) & ~size_t(255);
+        if (b == 0) b = 256;
+        if (b > left) { ok = false; return nullptr; }
+        T *r = reinterpret_cast<T *>(cur);
+        if (cur) cur += b;
+        left -= b;
+        used += b;
+        return r;
+    }
+};
+
+// Event timing of the setup kernel classes (bcm_params.profile bits
+// BCM_PROF_SETUP_*): one event pair per bracket, taken by the kernel's own
+// dispatch for a single-kernel class, else recorded on the stream; summed
+// into the handle's class totals once setup has finished.
+struct SetupProf {
+    hipStream_t s = nullptr;
+    int mask = 0;
+    struct Rec {
+        int bit;
+        hipEvent_t a, b;
+        double bytes;
+    };
+    std::vector<Rec> rec;
+    int begin(int bit, bool single) {
+        if (!(mask & bit)) return -1;
+        hipEvent_t a, b;
+        if (hipEventCreate(&a) != hipSuccess) return -1;
+        if (hipEventCreate(&b) != hipSuccess) {
+            (void)hipEventDestroy(a);
+            return -1;
+        }
+        rec.push_back({bit, a, b, 0.0});
+        if (single) g_kernel_events = KernelEvents{a, b};
+        else (void)hipEventRecord(a, s);
+        return (int)rec.size() - 1;
+    }
+    void end(int idx, bool single, double bytes) {
+        if (idx < 0) return;
+        rec[idx].bytes = bytes;
+        if (!single) (void)hipEventRecord(rec[idx].b, s);
+        else if (g_kernel_events.start) {  // no kernel took the events: no sample
+            g_kernel_events = KernelEvents{};
+            rec[idx].bit = 0;
+        }
+    }
+    void set_bytes(int idx, double bytes) {
+        if (idx >= 0) rec[idx].bytes = bytes;
+    }
+    // adds the samples to prof[] (index = log2 of the class bit); call after a sync
+    void collect(bcm::ProfClass *prof) {
+        for (auto &r : rec) {
+            float ms = 0.f;
+            if (r.bit && hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+                int i = 0;
+                for (int b = r.bit; b > 1; b >>= 1) ++i;
+                prof[i].launches += 1;
+                prof[i].ms += ms;
+                prof[i].bytes += r.bytes;
+            }
+            (void)hipEventDestroy(r.a);
+            (void)hipEventDestroy(r.b);
+        }
+        rec.clear();
+    }
+    ~SetupProf() {
+        for (auto &r : rec) {
+            (void)hipEventDestroy(r.a);
+            (void)hipEventDestroy(r.b);
+        }
+    }
+};
+
+// Algorithmic bytes of the setup classes on a sweep over m rows, z entries,
+// nc aggregates and zc coarse entries (every array once, gathers cached).
+// weights: row pointers, columns, values, diagonal and w, c and ws written;
+// candidate lists: columns and c read, the lists written (+ the own-row ranks
+// written and read when the rows are sorted).
+double bytes_setup_match(double m, double z, bool sorted) {
+    return 2 * 4 * (m + 1) + 20 * z + 24 * m + 20 * z + (sorted ? 8 * z : 0.0);
+}
+// Suitor: each vertex reads its row bounds, at least one candidate and
+// raises at least one proposal word.
+double bytes_setup_suitor(double m) { return 8 * (m + 1) + 16 * m; }
+// Galerkin, both passes: members and their row bounds, columns and their
+// aggregates (twice), values and p once, counts, the scan, row pointers,
+// and the coarse columns and values written.
+double bytes_setup_galerkin(double m, double z, double nc, double zc) {
+    return 2 * (8 * nc + 8 * m + 4 * z + 4 * m) + 8 * z + 8 * m + 4 * nc + 8 * nc + 4 * nc + 12 * zc;
+}
+
+// Device scratch of one matching sweep on an m-row matrix with nnz entries.
+// c and mate may be the caller's arrays (c_ext, mate_ext); diag is absent when
+// the caller hands in the diagonal of an already validated matrix.  With
+// lmin > 0 it also holds the list of rows longer than lmin (at most
+// nnz / (lmin + 1) of them); the sort keys of those rows (2 x their total
+// length) are carved separately once that length or a bound is known.
+struct MatchScratch {
+    double *diag = nullptr;
+    int *flags = nullptr;
+    double *c = nullptr;
+    unsigned long long *cand = nullptr;
+    unsigned *rk = nullptr;
+    unsigned long long *ws = nullptr;
+    int *mate = nullptr;
+    int *leader = nullptr;
+    SegList seg;
+    int lmin = 0;  // 0: no long-row list
+    unsigned long long *k0 = nullptr, *k1 = nullptr;
+};
+
+int seg_cap(long long nnz, int lmin) { return (int)(nnz / (lmin + 1) + 1); }
+
+void carve_seg(Carver &cv, int cap, SegList &sg) {
+    sg.cap = cap;
+    sg.ctl = cv.get<int>(8);
+    sg.row = cv.get<int>(cap);
+    sg.len = cv.get<int>(cap);
+    sg.off = cv.get<int>((size_t)cap + 1);
+    sg.cb = cv.get<int>((size_t)cap + 1);
+}
+
+void carve_match(Carver &cv, int m, long long nnz, bool own_diag, double *c_ext, int *mate_ext, int lmin,
+                 MatchScratch &ms) {
+    ms.diag = own_diag ? cv.get<double>(m) : nullptr;
+    ms.flags = cv.get<int>(32);
+    ms.c = c_ext ? c_ext : cv.get<double>(nnz);
+    ms.cand = cv.get<unsigned long long>(nnz);
+    ms.rk = cv.get<unsigned>(nnz);
+    ms.ws = cv.get<unsigned long long>(m);
+    ms.mate = mate_ext ? mate_ext : cv.get<int>(m);
+    ms.leader = cv.get<int>(m);
+    ms.lmin = lmin;
+    if (lmin > 0) carve_seg(cv, seg_cap(nnz, lmin), ms.seg);
+}
+
+size_t match_scratch_bytes(int m, long long nnz, bool own_diag, bool c_ext, bool mate_ext, int lmin) {
+    Carver cv;
+    cv.left = ~size_t(0);
+    MatchScratch ms;
+    carve_match(cv, m, nnz, own_diag, c_ext ? reinterpret_cast<double *>(8) : nullptr,
+                mate_ext ? reinterpret_cast<int *>(8) : nullptr, lmin, ms);
+    return cv.used;
+}
+
+// Weights, ranks, Suitor matching and mate/leader flags on (A, w): Sections
+// 2.2 and 3.1, in the scratch ms.
 // With flags_dev given, the validation flags are left there for the caller
 // to read with its next read-back (only for matrices already known to be well
 // formed: the validated input and the coarse matrices built from it; a bad
 // value there makes weights ineligible, never an out-of-bounds access).
+// Without it the flags are read back here (pinned: through the thread's pinned
+// staging buffer, else a plain copy into host memory), together with the
+// long-row list's size, and the long rows' sort keys are then taken from
+// keys_from or keys_arena (exact size).  With flags_dev, rows longer than
+// ms.lmin may exist only when A.dmax (a bound) exceeds it; their keys must
+// already be in ms.k0/k1 (2 x nnz).
 // With diag_in given (the diagonal of a matrix already validated), the
 // validation pass is skipped.
-int match_sweep(hipStream_t s, Arena &tmp, const Csr &A, const double *w, int check_sym, int group, int **mate_out,
-                int **leader_out, double **c_out, int *flags_dev = nullptr, int G_hint = 0,
-                const int *copy_src = nullptr, const double *diag_in = nullptr) {
+int match_sweep(hipStream_t s, MatchScratch &ms, const Csr &A, const double *w, int check_sym, int group,
+                int *flags_dev = nullptr, int G_hint = 0, const int *copy_src = nullptr,
+                const double *diag_in = nullptr, bool pinned_ok = true, Carver *keys_from = nullptr,
+                Arena *keys_arena = nullptr, SetupProf *sp = nullptr, int *prof_idx = nullptr) {
     const int m = A.n, G = G_hint > 0 ? G_hint : lanes_for(group, A);
-    double *diag = diag_in ? nullptr : tmp.get_n<double>(m);
-    int *flags = flags_dev ? flags_dev : tmp.get_n<int>(16);
-    double *c = tmp.get_n<double>(A.nnz);
-    unsigned long long *cand = tmp.get_n<unsigned long long>(A.nnz);
-    unsigned *rk = tmp.get_n<unsigned>(A.nnz);
-    unsigned long long *ws = tmp.get_n<unsigned long long>(m);
-    int *mate = tmp.get_n<int>(m);
-    int *leader = tmp.get_n<int>(m);
-    NOMEM((diag || diag_in) && flags && c && cand && rk && ws && mate && leader);
+    const int dbound = A.dmax > 0 ? A.dmax : m;
+    bool lng = ms.lmin > 0 && dbound > ms.lmin;
+    int maxlen = dbound;
+    const SegList none;
+    const double *diag = diag_in ? diag_in : ms.diag;
+    int *flags = flags_dev ? flags_dev : ms.flags;
     launch_fill_i32(s, 1, flags, 0);
-    if (diag_in) diag = const_cast<double *>(diag_in);  // read only below
-    else launch_validate(s, G, m, A.nnz_dev ? -1 : A.nnz, A.rp, A.ci, A.v, w, check_sym, diag, flags);
+    if (lng) launch_fill_i32(s, 8, ms.seg.ctl, 0);
+    if (!diag_in) {
+        launch_validate(s, G, m, A.nnz_dev ? -1 : A.nnz, A.rp, A.ci, A.v, w, check_sym, ms.diag, flags,
+                        lng ? ms.seg : none, ms.lmin);
+    } else if (lng) {
+        launch_find_long(s, m, A.rp, ms.lmin, ms.seg, nullptr);
+    }
+    if (lng) {
+        launch_seg_fix(s, ms.seg);
+        if (!diag_in) launch_long_validate(s, m, A.nnz_dev ? -1 : A.nnz, A.rp, A.ci, A.v, check_sym, ms.seg, flags);
+    }
     if (!flags_dev && !diag_in) {
-        int f = 0;
-        int rc = read_back(s, flags, sizeof(int), &f);
+        int f[8] = {0};
+        int rc = pinned_ok ? read_back(s, flags, sizeof(int), f) : read_back_plain(s, flags, sizeof(int), f);
         if (rc) return rc;
-        if (f) {
-            set_error("invalid input:" + flag_text(f));
+        if (f[0]) {
+            set_error("invalid input:" + flag_text(f[0]));
             return BCM_EINVAL;
         }
+        if (lng) {
+            rc = pinned_ok ? read_back(s, ms.seg.ctl, 8 * sizeof(int), f)
+                           : read_back_plain(s, ms.seg.ctl, 8 * sizeof(int), f);
+            if (rc) return rc;
+            lng = f[0] > 0;
+            maxlen = f[3];
+            if (lng) {  // sort keys of the long rows, now that their total is known
+                const size_t tot = (size_t)f[1];
+                if (keys_from) {
+                    ms.k0 = keys_from->get<unsigned long long>(tot);
+                    ms.k1 = keys_from->get<unsigned long long>(tot);
+                } else if (keys_arena) {
+                    ms.k0 = keys_arena->get_n<unsigned long long>(tot);
+                    ms.k1 = keys_arena->get_n<unsigned long long>(tot);
+                }
+                if (!ms.k0 || !ms.k1) {
+                    set_error(keys_from ? "the long rows' sort keys do not fit the static scratch"
+                                        : "device allocation failed (long-row sort keys)");
+                    return keys_from ? BCM_EINVAL : BCM_ENOMEM;
+                }
+            }
+        }
     }
-    // candidate lists: direct comparisons for rows of a few dozen entries, else sorted
+    // candidate lists: direct comparisons for rows of a few dozen entries, else
+    // sorted; long rows through the segmented sorts
     const bool sorted = A.nnz >= (long long)kSortedCandidatesAvg * m;
-    launch_weights(s, G, m, A.rp, A.ci, A.v, diag, w, c, ws);
-    launch_candidates(s, G, m, sorted, A.rp, A.ci, c, rk, cand);
-    launch_suitor(s, m, A.rp, cand, ws);
-    // (copy_src: an int for the caller's next read-back, to flags_dev[17])
-    launch_mate(s, m, A.rp, A.ci, ws, mate, leader, copy_src, copy_src ? flags_dev + 17 : nullptr);
+    const int lm = lng ? ms.lmin : 0;
+    // (bytes of the brackets: set here when A's entry count is known, else by the caller)
+    const int pm = sp ? sp->begin(BCM_PROF_SETUP_MATCH, false) : -1;
+    launch_weights(s, G, m, A.rp, A.ci, A.v, diag, w, ms.c, ms.ws, lm);
+    if (lng) launch_long_weights(s, ms.seg, A.rp, A.ci, A.v, diag, w, ms.c);
+    if (sorted) {
+        launch_candidates(s, G, m, true, A.rp, A.ci, ms.c, ms.rk, ms.cand, lm, 1);
+        if (lng) launch_long_ranks(s, ms.seg, maxlen, A.rp, ms.c, ms.rk, ms.k0, ms.k1);
+        launch_candidates(s, G, m, true, A.rp, A.ci, ms.c, ms.rk, ms.cand, lm, 2);
+        if (lng) launch_long_candidates(s, ms.seg, maxlen, A.rp, A.ci, ms.c, ms.rk, lm, false, ms.cand, ms.k0, ms.k1);
+    } else {
+        if (lng) launch_long_ranks(s, ms.seg, maxlen, A.rp, ms.c, ms.rk, ms.k0, ms.k1);
+        launch_candidates(s, G, m, false, A.rp, A.ci, ms.c, ms.rk, ms.cand, lm, 2);
+        if (lng) launch_long_candidates(s, ms.seg, maxlen, A.rp, A.ci, ms.c, ms.rk, lm, true, ms.cand, ms.k0, ms.k1);
+    }
+    if (sp) sp->end(pm, false, A.nnz_dev ? 0.0 : bytes_setup_match(m, A.nnz, sorted));
+    const int ps = sp ? sp->begin(BCM_PROF_SETUP_SUITOR, true) : -1;
+    launch_suitor(s, m, A.rp, ms.cand, ms.ws);
+    if (sp) sp->end(ps, true, bytes_setup_suitor(m));
+    if (prof_idx) prof_idx[0] = pm;
+    // (copy_src: two ints for the caller's next read-back, to flags_dev[17..18])
+    launch_mate(s, m, A.rp, A.ci, ms.ws, ms.mate, ms.leader, copy_src, copy_src ? flags_dev + 17 : nullptr);
     HIPCHK(hipGetLastError());
-    *mate_out = mate;
-    *leader_out = leader;
-    if (c_out) *c_out = c;
     return BCM_OK;
 }
 
@@ -219,23 +431,50 @@ int match_sweep(hipStream_t s, Arena &tmp, const Csr &A, const double *w, int ch
 // given (the level's final outputs, allocated where they stay).  out.nc == A.n
 // means that no pair was formed (nothing else is produced then).
 int pairwise_sweep(hipStream_t s, Arena &tmp, Arena &keep, Csr &A, const double *w, int group, int G_hint,
-                   SweepOut &out, Arena *finA, Arena *finP, const double *diag_in = nullptr) {
-    // A's exact entry count, when still on the device, comes back with this
-    // sweep's first read-back (G_hint sizes the lanes of the kernels before it)
+                   SweepOut &out, Arena *finA, Arena *finP, const double *diag_in = nullptr,
+                   SetupProf *sp = nullptr, double *sweep_bytes = nullptr) {
+    // A's exact entry count and longest row, when still on the device, come
+    // back with this sweep's first read-back (G_hint sizes the lanes of the
+    // kernels before it, A.dmax bounds its rows)
     Arena &oa = finA ? *finA : keep;
     Arena &op = finP ? *finP : keep;
     const int m = A.n;
-    int *mate = nullptr, *leader = nullptr;
-    int *ctl = tmp.get_n<int>(32);  // [0] validation flags, [16] aggregates, [17] A's entries
+    const int Gm = A.nnz_dev && G_hint > 0 ? G_hint : lanes_for(group, A);
+    int *ctl = tmp.get_n<int>(32);  // [0] flags, [16] aggregates, [17] A's entries, [18] A's longest row
     NOMEM(ctl);
-    int rc = match_sweep(s, tmp, A, w, 0, group, &mate, &leader, nullptr, ctl, A.nnz_dev ? G_hint : 0, A.nnz_dev,
-                         diag_in);
+    MatchScratch ms;
+    {
+        const size_t bytes = match_scratch_bytes(m, A.nnz, !diag_in, false, false, long_min(Gm));
+        Carver cv;
+        cv.cur = static_cast<char *>(tmp.get(bytes));
+        cv.left = bytes;
+        NOMEM(cv.cur);
+        carve_match(cv, m, A.nnz, !diag_in, nullptr, nullptr, long_min(Gm), ms);
+    }
+    // sort keys of the long rows (matching, then the Galerkin product): at most
+    // every entry of A
+    unsigned long long *k0 = nullptr, *k1 = nullptr;
+    auto keys = [&]() {
+        if (!k0) {
+            k0 = tmp.get_n<unsigned long long>(A.nnz);
+            k1 = tmp.get_n<unsigned long long>(A.nnz);
+        }
+        return k0 && k1;
+    };
+    if ((A.dmax > 0 ? A.dmax : m) > ms.lmin) {
+        NOMEM(keys());
+        ms.k0 = k0;
+        ms.k1 = k1;
+    }
+    int pm = -1;
+    int rc = match_sweep(s, ms, A, w, 0, group, ctl, Gm, A.nnz_dev, diag_in, true, nullptr, nullptr, sp, &pm);
     if (rc) return rc;
+    int *mate = ms.mate, *leader = ms.leader;
     int *ofs = leader;  // scanned in place
     void *stmp = tmp.get(scan_tmp_bytes(m));
     NOMEM(stmp);
     scan_exclusive(s, leader, ofs, m, ctl + 16, stmp);
-    int hc[18];
+    int hc[19];
     rc = read_back(s, ctl, sizeof(hc), hc);
     if (rc) return rc;
     if (hc[0]) {
@@ -244,8 +483,11 @@ int pairwise_sweep(hipStream_t s, Arena &tmp, Arena &keep, Csr &A, const double 
     }
     if (A.nnz_dev) {
         A.nnz = hc[17];
+        A.dmax = hc[18];
         A.nnz_dev = nullptr;
+        if (sp) sp->set_bytes(pm, bytes_setup_match(m, A.nnz, A.nnz >= (long long)kSortedCandidatesAvg * m));
     }
+    if (sweep_bytes) *sweep_bytes = 72.0 * A.nnz + 80.0 * m;
     const int nc = hc[16], G = lanes_for(group, A);
     out.nc = nc;
     if (nc == m) return BCM_OK;
@@ -257,24 +499,57 @@ int pairwise_sweep(hipStream_t s, Arena &tmp, Arena &keep, Csr &A, const double 
     launch_aggfill(s, m, mate, ofs, w, out.agg, out.p, out.wc, out.mem2);
     // Galerkin product: count, scan to row pointers, fill.  Every coarse entry
     // (E, F) comes from at least one stored a_ij (i in E, j in F), so A's entry
-    // count bounds the coarse one; the exact count stays on the device
-    // (row_ptr[nc]) until the next read-back.
-    int *crp = oa.get_n<int>((size_t)nc + 1);
+    // count bounds the coarse one; the exact count and the longest coarse row
+    // stay on the device (row_ptr[nc], row_ptr[nc + 1]) until the next
+    // read-back.  A coarse row's candidates are its members' entries: more
+    // than lmin of them only when A has rows longer than lmin / 2.
+    const int lmin_g = long_min(G);
+    const bool gal_long = 2LL * A.dmax > lmin_g;
+    int *crp = oa.get_n<int>((size_t)nc + 2);
     int *gF = tmp.get_n<int>(A.nnz);
     int *gU = tmp.get_n<int>(A.nnz);
     void *stmp2 = tmp.get(scan_tmp_bytes(nc));
     NOMEM(crp && gF && gU && stmp2);
     const bool gsorted = A.nnz >= (long long)kSortedCandidatesAvg * A.n;
-    launch_gal_count(s, G, nc, A.rp, A.ci, out.agg, out.mem2, crp, gF, gU, gsorted);
-    scan_exclusive(s, crp, crp, nc, crp + nc, stmp2);
+    SegList sg;
+    unsigned long long *gkeys = nullptr;
+    const int pg = sp ? sp->begin(BCM_PROF_SETUP_GALERKIN, false) : -1;
+    if (gal_long) {
+        Carver cv;
+        Carver probe;
+        probe.left = ~size_t(0);
+        carve_seg(probe, seg_cap(A.nnz, lmin_g), sg);
+        cv.cur = static_cast<char *>(tmp.get(probe.used));
+        cv.left = probe.used;
+        NOMEM(cv.cur && keys());
+        carve_seg(cv, seg_cap(A.nnz, lmin_g), sg);
+        launch_fill_i32(s, 8, sg.ctl, 0);
+        launch_find_long_gal(s, nc, out.mem2, A.rp, lmin_g, sg);
+        launch_seg_fix(s, sg);
+        launch_gal_long_sort(s, sg, (int)std::min(2LL * A.dmax, (long long)A.nnz), A.rp, A.ci, out.agg, out.mem2, k0,
+                             k1, &gkeys);
+    }
+    launch_gal_count(s, G, nc, A.rp, A.ci, out.agg, out.mem2, crp, gF, gU, gsorted, gal_long ? lmin_g : 0);
+    if (gal_long)
+        launch_gal_long(s, 0, sg, gkeys, A.rp, A.ci, A.v, out.agg, out.p, out.mem2, crp, nullptr, nullptr, nullptr);
+    scan_exclusive(s, crp, crp, nc, crp + nc, stmp2, crp + nc + 1);
     out.Ac.n = nc;
     out.Ac.nnz = A.nnz;
     out.Ac.nnz_dev = crp + nc;
+    out.Ac.dmax = (int)std::min<long long>(2LL * A.dmax, nc);
     out.Ac.rp = crp;
     out.Ac.ci = oa.get_n<int>(A.nnz);
     out.Ac.v = oa.get_n<double>(A.nnz);
     NOMEM(out.Ac.ci && out.Ac.v);
-    launch_gal_fill(s, G, nc, A.rp, A.ci, A.v, out.agg, out.p, out.mem2, crp, out.Ac.ci, out.Ac.v, gF, gU, gsorted);
+    launch_gal_fill(s, G, nc, A.rp, A.ci, A.v, out.agg, out.p, out.mem2, crp, out.Ac.ci, out.Ac.v, gF, gU, gsorted,
+                    gal_long ? lmin_g : 0);
+    if (gal_long)
+        launch_gal_long(s, 1, sg, gkeys, A.rp, A.ci, A.v, out.agg, out.p, out.mem2, nullptr, crp, out.Ac.ci,
+                        out.Ac.v);
+    // (the coarse entry count is still on the device: A's bounds it; the bytes
+    // are corrected with the exact count in build_hierarchy's summary)
+    if (sp) sp->end(pg, false, bytes_setup_galerkin(m, A.nnz, nc, A.nnz));
+    out.prof_gal = pg;
     HIPCHK(hipGetLastError());
     return BCM_OK;
 }
@@ -371,23 +646,49 @@ int build_hierarchy(bcm_handle *h, const bcm_csr *Ain, const double *win) {
     {
         // full validation of the input, symmetry included when asked.  The
         // diagonal goes to the finest level's smoother array, which holds it
-        // for the first matching sweep until the smoother overwrites it.
+        // for the first matching sweep until the smoother overwrites it.  The
+        // longest row comes back with the flags: it decides the long-row paths.
+        // (flags: [0] errors, [1] longest row, [8..15] the long-row list's control)
         L0.dinv = h->persist.get_n<double>(n);
         double *diag = L0.dinv;
         int *flags = tmp.get_n<int>(16);
-        NOMEM(diag && flags);
-        launch_fill_i32(s, 1, flags, 0);
-        launch_validate(s, lanes_for(P.group, L0.A), n, nnz, L0.A.rp, L0.A.ci, L0.A.v, L0.w,
-                        P.check ? 1 : 0, diag, flags);
-        int f = 0;
-        int rc = read_back(s, flags, sizeof(int), &f);
+        const int G0 = lanes_for(P.group, L0.A), lmin0 = long_min(G0);
+        SegList sg;
+        Carver probe;
+        probe.left = ~size_t(0);
+        carve_seg(probe, seg_cap(nnz, lmin0), sg);
+        Carver cv;
+        cv.cur = static_cast<char *>(tmp.get(probe.used));
+        cv.left = probe.used;
+        NOMEM(diag && flags && cv.cur);
+        carve_seg(cv, seg_cap(nnz, lmin0), sg);
+        launch_fill_i32(s, 2, flags, 0);
+        launch_fill_i32(s, 8, sg.ctl, 0);
+        launch_validate(s, G0, n, nnz, L0.A.rp, L0.A.ci, L0.A.v, L0.w, P.check ? 1 : 0, diag, flags, sg, lmin0,
+                        flags + 1);
+        launch_seg_fix(s, sg);
+        launch_long_validate(s, n, nnz, L0.A.rp, L0.A.ci, L0.A.v, P.check ? 1 : 0, sg, flags);
+        HIPCHK(hipMemcpyAsync(flags + 8, sg.ctl, 8 * sizeof(int), hipMemcpyDeviceToDevice, s));
+        int f[16];
+        int rc = read_back(s, flags, sizeof(f), f);
         if (rc) return rc;
-        if (f) { set_error("invalid input:" + flag_text(f)); return BCM_EINVAL; }
+        if (f[0]) { set_error("invalid input:" + flag_text(f[0])); return BCM_EINVAL; }
+        L0.A.dmax = f[1];
     }
     const int max_coarse = P.max_coarse > 0 ? P.max_coarse : (int)std::lround(40.0 * std::cbrt((double)n));
-    const double rmin = P.min_ratio > 0.0 ? P.min_ratio : std::sqrt(std::ldexp(1.0, P.sweeps));
+    // Section 5 stops at max_coarse, max_levels or an unchanged size; min_ratio
+    // > 1 adds the stalled-coarsening rule (not the paper's)
+    const double rmin = P.min_ratio > 1.0 ? P.min_ratio : 1.0;
     int k = 0;
     int g_prev = lanes_for(P.group, L0.A);
+    SetupProf sp;
+    sp.s = s;
+    sp.mask = P.profile;
+    // the Galerkin bracket whose coarse entry count is still pending
+    struct {
+        int idx = -1;
+        double m = 0, z = 0, nc = 0;
+    } pend;
     for (;;) {
         Level &L = h->lv[k];
         const int nk = L.A.n;
@@ -405,11 +706,27 @@ int build_hierarchy(bcm_handle *h, const bcm_csr *Ain, const double *win) {
             tmp.rewind();
             SweepOut so;
             const bool last = sw == P.sweeps - 1;
+            double swb = 0.0;
             int rc = pairwise_sweep(s, tmp, keep, Acur, wcur, P.group, g_hint, so, last ? &h->persist : nullptr,
-                                    last && !have ? &h->persist : nullptr, k == 0 && sw == 0 ? L0.dinv : nullptr);
+                                    last && !have ? &h->persist : nullptr, k == 0 && sw == 0 ? L0.dinv : nullptr,
+                                    &sp, &swb);
             if (rc) return rc;
+            h->setup_bytes += swb;
+            h->sweeps_run += 1;
+            // this sweep's matrix came from the previous sweep's Galerkin product: its size is known now
+            if (pend.idx >= 0) {
+                sp.set_bytes(pend.idx, bytes_setup_galerkin(pend.m, pend.z, pend.nc, Acur.nnz));
+                pend.idx = -1;
+            }
+            if (so.nc != Acur.n) {
+                pend.idx = so.prof_gal;
+                pend.m = Acur.n;
+                pend.z = Acur.nnz;
+                pend.nc = so.nc;
+            }
             if (sw == 0 && L.A.nnz_dev) {  // the level's own entry count is known now
                 L.A.nnz = Acur.nnz;
+                L.A.dmax = Acur.dmax;
                 L.A.nnz_dev = nullptr;
             }
             g_hint = g_prev = lanes_for(P.group, Acur);
@@ -434,6 +751,7 @@ int build_hierarchy(bcm_handle *h, const bcm_csr *Ain, const double *win) {
         Level &C = h->lv[k + 1];
         C.A.n = Acur.n;
         C.A.nnz = Acur.nnz;
+        C.A.dmax = Acur.dmax;
         L.nc = Acur.n;
         L.mstride = cstride;
         if (final_done) {
@@ -453,22 +771,78 @@ int build_hierarchy(bcm_handle *h, const bcm_csr *Ain, const double *win) {
         // keep/tmp are rewound next: their memory is reused by later work on the
         // same stream, which runs after everything that reads it now
         ++k;
-        if ((double)nk < rmin * (double)C.A.n) break;  // coarsening has stalled: C is the coarsest
+        if (rmin > 1.0 && (double)nk < rmin * (double)C.A.n) break;  // stalled coarsening: C is the coarsest
     }
     h->nl = k + 1;
     {
         Csr &Ac = h->lv[h->nl - 1].A;  // the coarsest level ran no sweep: its entry count is still pending
         if (Ac.nnz_dev) {
-            int rc = read_back(s, Ac.nnz_dev, sizeof(int), &Ac.nnz);
+            int two[2];
+            int rc = read_back(s, Ac.nnz_dev, sizeof(two), two);
             if (rc) return rc;
+            Ac.nnz = two[0];
+            Ac.dmax = two[1];
             Ac.nnz_dev = nullptr;
+        }
+        if (pend.idx >= 0) sp.set_bytes(pend.idx, bytes_setup_galerkin(pend.m, pend.z, pend.nc, Ac.nnz));
+    }
+    {
+        // rows longer than long_min(G) of every level (G of the rule): their
+        // lists for the row kernels, found on the levels whose longest row
+        // exceeds that bound; their counts come back in one read-back
+        std::vector<int> lv_long;
+        std::vector<SegList> segs;
+        for (int l = 0; l < h->nl; ++l) {
+            Level &L = h->lv[l];
+            L.G = lanes_for(P.group, L.A);
+            const int lmin = long_min(L.G);
+            if (L.A.dmax <= lmin) continue;
+            SegList sg;
+            Carver probe;
+            probe.left = ~size_t(0);
+            carve_seg(probe, seg_cap(L.A.nnz, lmin), sg);
+            Carver cv;
+            cv.cur = static_cast<char *>(h->persist.get(probe.used));
+            cv.left = probe.used;
+            int *idx = h->persist.get_n<int>(L.A.n);
+            NOMEM(cv.cur && idx);
+            carve_seg(cv, seg_cap(L.A.nnz, lmin), sg);
+            launch_fill_i32(s, 8, sg.ctl, 0);
+            launch_find_long(s, L.A.n, L.A.rp, lmin, sg, idx);
+            launch_seg_fix(s, sg);
+            L.lr.lmin = lmin;
+            L.lr.idx = idx;
+            L.lr.rows = sg.row;
+            L.lr.cb = sg.cb;
+            lv_long.push_back(l);
+            segs.push_back(sg);
+        }
+        if (!lv_long.empty()) {
+            int *cnts = tmp.get_n<int>(8 * lv_long.size());
+            NOMEM(cnts);
+            for (size_t t = 0; t < lv_long.size(); ++t)
+                HIPCHK(hipMemcpyAsync(cnts + 8 * t, segs[t].ctl, 8 * sizeof(int), hipMemcpyDeviceToDevice, s));
+            std::vector<int> hc(8 * lv_long.size());
+            int rc = read_back(s, cnts, hc.size() * sizeof(int), hc.data());
+            if (rc) return rc;
+            int maxch = 1;
+            for (size_t t = 0; t < lv_long.size(); ++t) {
+                Level &L = h->lv[lv_long[t]];
+                L.lr.n = hc[8 * t];
+                L.lr.nchunks = hc[8 * t + 2];
+                maxch = std::max(maxch, L.lr.nchunks);
+                if (L.lr.n == 0) L.lr = LongRows();  // the bound was not reached after all
+            }
+            h->lpart = h->persist.get_n<double>(maxch);
+            NOMEM(h->lpart);
+            for (int l : lv_long)
+                if (h->lv[l].lr.n > 0) h->lv[l].lr.part = h->lpart;
         }
     }
     // smoother, FP32 copies, cycle vectors
     for (int l = 0; l < h->nl; ++l) {
         Level &L = h->lv[l];
         const int nl_ = L.A.n;
-        L.G = lanes_for(P.group, L.A);
         if (!L.dinv) L.dinv = h->persist.get_n<double>(nl_);  // (the finest level's was allocated first)
         NOMEM(L.dinv);
         if (fp32) {
@@ -481,7 +855,8 @@ int build_hierarchy(bcm_handle *h, const bcm_csr *Ain, const double *win) {
                 launch_cast(s, nl_, L.p, L.p32);
             }
         }
-        launch_diag_l1(s, L.G, nl_, L.A.rp, L.A.v, L.dinv, L.dinv32, L.A.v32);
+        launch_long_abs(s, L.lr, L.A.rp, L.A.v, h->lpart, L.A.v32);
+        launch_diag_l1(s, L.G, nl_, L.A.rp, L.A.v, L.dinv, L.dinv32, L.A.v32, L.lr, h->lpart);
         if (l < h->nl - 1 && nl_ >= kSplitUp) {
             L.xp = h->persist.get((fp32 ? sizeof(float) : sizeof(double)) * nl_);
             NOMEM(L.xp);
@@ -510,7 +885,7 @@ int build_hierarchy(bcm_handle *h, const bcm_csr *Ain, const double *win) {
         // level that runs the split up leg
         std::vector<int> lv_sell;
         for (int l = 0; l < h->nl && P.sell; ++l)
-            if (l == 0 || h->lv[l].xp) lv_sell.push_back(l);
+            if ((l == 0 || h->lv[l].xp) && h->lv[l].lr.n == 0) lv_sell.push_back(l);
         // per level t: tot[t] = total slots, tot[32 + t] = largest |col - row|,
         // tot[64 + t] = 1 if some value is not exactly a float32, tot[96 + t] =
         // slots of the slices without uniform column offsets
@@ -566,7 +941,7 @@ int build_hierarchy(bcm_handle *h, const bcm_csr *Ain, const double *win) {
             const size_t nn2 = (size_t)C.A.n * C.A.n;
             C.S = h->persist.get_n<double>(nn2);
             NOMEM(C.S);
-            if (C.A.n <= kCoarseBuildSweeps) {
+            if (C.A.n <= kCoarseBuildSweeps && C.lr.n == 0) {
                 // one workgroup per unit vector runs the sweeps
                 launch_coarse_build(s, C, P.coarse_sweeps, C.S);
             } else {
@@ -616,12 +991,13 @@ int build_hierarchy(bcm_handle *h, const bcm_csr *Ain, const double *win) {
     }
     if (h->kf == 0) {
         // tail kernel: the smallest levels (and the coarsest solve) in one workgroup
+        // (levels with long rows stay out of it: it gives a row at most 16 lanes)
         int kt = h->nl - 1;
-        while (kt > 1 && h->lv[kt - 1].A.n <= kTailRows) --kt;
+        while (kt > 1 && h->lv[kt - 1].A.n <= kTailRows && h->lv[kt - 1].lr.n == 0) --kt;
         const Level &C = h->lv[h->nl - 1];
         // K levels need dot products between cycles: the tail takes V and W levels only
         const bool plain = P.cycle != BCM_KCYCLE || (P.kcycle_levels > 0 && P.kcycle_levels <= kt);
-        if (plain && kt < h->nl - 1 && C.A.n <= kTailRows) {
+        if (plain && kt < h->nl - 1 && C.A.n <= kTailRows && C.lr.n == 0) {
             std::vector<TailLevel> tv(h->nl);
             for (int l = 0; l < h->nl; ++l) {
                 const Level &L = h->lv[l];
@@ -663,7 +1039,8 @@ int build_hierarchy(bcm_handle *h, const bcm_csr *Ain, const double *win) {
             h->kt = kt;
         }
     }
-    if (!h->lv[h->nl - 1].S && !coarse_in_lds(h->lv[h->nl - 1].A.n, h->lv[h->nl - 1].A.nnz)) {
+    if (!h->lv[h->nl - 1].S &&
+        !coarse_in_lds(h->lv[h->nl - 1].A.n, h->lv[h->nl - 1].A.nnz, h->lv[h->nl - 1].lr.n > 0)) {
         h->ctmp[0] = h->persist.get_n<double>(h->lv[h->nl - 1].A.n);
         h->ctmp[1] = h->persist.get_n<double>(h->lv[h->nl - 1].A.n);
         NOMEM(h->ctmp[0] && h->ctmp[1]);
@@ -693,6 +1070,8 @@ int build_hierarchy(bcm_handle *h, const bcm_csr *Ain, const double *win) {
         if (rc) return rc;
     }
     HIPCHK(hipStreamSynchronize(s));
+    for (int c = 6; c < 9; ++c) h->prof[c] = ProfClass{};
+    sp.collect(h->prof);
     return BCM_OK;
 }
 
@@ -892,7 +1271,7 @@ int prof_class_index(int bit) {
 // Accumulates the event pairs of iterations < iters (launches of a batch after
 // the solve ended returned at once and are not counted).
 void prof_collect(bcm_handle *h, int iters) {
-    for (auto &c : h->prof) c = ProfClass{};
+    for (int c = 0; c < 6; ++c) h->prof[c] = ProfClass{};  // the solve classes (setup ones stay)
     for (size_t t = 0; t < h->ev_pairs.size(); ++t) {
         if (h->ev_iter[t] >= iters) continue;
         const int cls = h->ev_pairs[t].first, idx = h->ev_pairs[t].second;
@@ -1209,8 +1588,12 @@ int fcg_run(bcm_handle *h, const double *b, double *x_user, double tol) {
         relres = std::sqrt(hs[4]) / bn;
         if (relres <= tol) { status = BCM_OK; break; }
         if (it >= itmax) { status = BCM_MAXIT; break; }
-        status = BCM_MAXIT;
+        // the recurrence met tol, the true residual did not: restart from x
+        status = BCM_STAGNATED;
     }
+    if (status == BCM_STAGNATED)
+        set_error("true residual stagnated above tol after 3 restarts: relative residual " + std::to_string(relres) +
+                  " after " + std::to_string(it) + " iterations");
     HIPCHK(hipGetLastError());
     prof_collect(h, it);
     h->iters = it;
@@ -1222,11 +1605,35 @@ int fcg_run(bcm_handle *h, const double *b, double *x_user, double tol) {
 // flexible CG on the handle's iterate; the caller's x is copied in and back out
 int fcg(bcm_handle *h, const double *b, double *x, double tol) {
     const int rc = fcg_run(h, b, x, tol);
-    if (rc == BCM_OK || rc == BCM_MAXIT || rc == BCM_EBREAKDOWN) {
+    if (rc == BCM_OK || rc == BCM_MAXIT || rc == BCM_STAGNATED || rc == BCM_EBREAKDOWN) {
         launch_copy_f64(h->s, h->lv[0].A.n, h->u, x);
         HIPCHK(hipStreamSynchronize(h->s));
     }
     return rc;
+}
+
+// Argument checks of bcm_match.
+int match_args(const bcm_csr *A, const double *w, const bcm_params *p, const int32_t *mate, bcm_params &prm) {
+    if (!A || !w || !mate || !A->row_ptr || !A->col || !A->val || A->n <= 0 || A->nnz < 0) {
+        set_error("NULL or empty argument");
+        return BCM_EINVAL;
+    }
+    if (p) prm = *p; else bcm_default_params(&prm);
+    if (!valid_group(prm.group) || (prm.alloc == nullptr) != (prm.dealloc == nullptr)) {
+        set_error("unsupported parameters (group 0, -1, 4, 8, 16, 32 or 64; alloc and dealloc both or neither)");
+        return BCM_EINVAL;
+    }
+    return BCM_OK;
+}
+
+Csr csr_view(const bcm_csr *A) {
+    Csr M;
+    M.n = A->n;
+    M.nnz = A->nnz;
+    M.rp = const_cast<int *>(A->row_ptr);
+    M.ci = const_cast<int *>(A->col);
+    M.v = const_cast<double *>(A->val);
+    return M;
 }
 
 }  // namespace
@@ -1354,6 +1761,9 @@ int bcm_info(const bcm_handle *h, bcm_info_t *o) {
     const double cyc = bytes_cycle(h);
     o->cycle_bytes = cyc;
     o->iter_bytes = cyc + bytes_spmv_dots(h) + bytes_update(h);
+    o->setup_bytes = h->setup_bytes;
+    o->sweeps_run = h->sweeps_run;
+    for (int k = 0; k < h->nl; ++k) o->long_rows += h->lv[k].lr.n;
     return BCM_OK;
 }
 
@@ -1378,46 +1788,34 @@ int bcm_level_copy(const bcm_handle *h, int32_t k, int32_t *row_ptr, int32_t *co
 
 int bcm_match(const bcm_csr *A, const double *w, const bcm_params *p, int32_t *mate, double *c) {
     g_err.clear();
-    if (!A || !w || !mate || !A->row_ptr || !A->col || !A->val || A->n <= 0) {
-        set_error("NULL or empty argument");
-        return BCM_EINVAL;
-    }
     bcm_params prm;
-    if (p) prm = *p; else bcm_default_params(&prm);
-    if (!valid_group(prm.group) || (prm.alloc == nullptr) != (prm.dealloc == nullptr)) {
-        set_error("unsupported parameters (group 0, -1, 4, 8, 16, 32 or 64; alloc and dealloc both or neither)");
-        return BCM_EINVAL;
-    }
+    int rc = match_args(A, w, p, mate, prm);
+    if (rc) return rc;
     hipStream_t s = (hipStream_t)prm.stream;
     Arena tmp;
     tmp.alloc = prm.alloc;
     tmp.dealloc = prm.dealloc;
     tmp.ctx = prm.alloc_ctx;
-    tmp.reserve((size_t)A->nnz * 24 + (size_t)A->n * 48 + (size_t(1) << 20));
-    Csr M;
-    M.n = A->n;
-    M.nnz = A->nnz;
-    M.rp = const_cast<int *>(A->row_ptr);
-    M.ci = const_cast<int *>(A->col);
-    M.v = const_cast<double *>(A->val);
-    int *dm = nullptr, *leader = nullptr;
-    double *dc = nullptr;
-    int rc = tmp.failed ? BCM_ENOMEM : match_sweep(s, tmp, M, w, prm.check ? 1 : 0, prm.group, &dm, &leader, &dc);
-    if (rc == BCM_ENOMEM) set_error("device allocation failed");
-    if (rc == BCM_OK) {
-        if (hipMemcpyAsync(mate, dm, (size_t)A->n * 4, hipMemcpyDeviceToDevice, s) != hipSuccess ||
-            (c && hipMemcpyAsync(c, dc, (size_t)A->nnz * 8, hipMemcpyDeviceToDevice, s) != hipSuccess)) {
-            set_error("HIP copy failed");
-            rc = BCM_EHIP;
-        }
+    const Csr M = csr_view(A);
+    const int lmin = long_min(lanes_for(prm.group, M));
+    const size_t bytes = match_scratch_bytes(A->n, A->nnz, true, c != nullptr, true, lmin);
+    Carver cv;
+    cv.cur = static_cast<char *>(tmp.get(bytes));
+    cv.left = bytes;
+    if (!cv.cur) {
+        set_error("device allocation failed");
+        return BCM_ENOMEM;
     }
+    MatchScratch ms;
+    carve_match(cv, A->n, A->nnz, true, c, mate, lmin, ms);
+    rc = match_sweep(s, ms, M, w, prm.check ? 1 : 0, prm.group, nullptr, 0, nullptr, nullptr, true, nullptr, &tmp);
     (void)hipStreamSynchronize(s);
     tmp.release();
     return rc;
 }
 
 int bcm_profile(const bcm_handle *h, int32_t kclass, int64_t *launches, double *ms, double *bytes) {
-    if (!h || kclass <= 0 || (kclass & (kclass - 1)) || kclass > BCM_PROF_CYCLE_MID) {
+    if (!h || kclass <= 0 || (kclass & (kclass - 1)) || kclass > BCM_PROF_SETUP_GALERKIN) {
         set_error("bad handle or kernel class");
         return BCM_EINVAL;
     }

@@ -41,6 +41,41 @@ constexpr int kSplitUp = 65536;    // levels at least this large run the up leg 
 constexpr int kGatherRow = 16;     // sliced-ELL levels averaging this many entries per row gather dinv o b
                                    // formed beforehand in the down leg (one vector instead of two)
 
+// Long rows.  The per-row kernels give each row a group of G lanes, G chosen
+// from the level's mean row length (Sections 3.1, 3.2: miniwarp per row).  A
+// row longer than kLongFactor * G entries (a hub: a vertex coupled to most of
+// its level, as coarsening produces on strongly heterogeneous problems) would
+// serialise its group, so such rows leave the per-row kernels and are spread
+// over whole workgroups instead: chunks of kSegChunk entries.
+constexpr int kLongFactor = 16;
+constexpr int kSegChunk = 2048;  // entries per chunk (one workgroup); keys per LDS sort chunk
+inline int long_min(int G) { return kLongFactor * G; }
+
+// A list of long segments (rows, or Galerkin coarse rows) found on the device:
+// the finding kernel appends (row, length) in any order; k_seg_fix then turns
+// the lengths into key offsets and first chunks.  cap bounds the count (a
+// segment is longer than lmin, so at most nnz / lmin + 1 of them exist).
+struct SegList {
+    int *ctl = nullptr;  // [0] segments [1] total length [2] chunks [3] longest [4] overflow
+    int *row = nullptr;  // [cap]
+    int *len = nullptr;  // [cap]
+    int *off = nullptr;  // [cap + 1] exclusive prefix of len
+    int *cb = nullptr;   // [cap + 1] exclusive prefix of ceil(len / kSegChunk)
+    int cap = 0;
+};
+
+// Long rows of one level for the solve kernels: rows longer than lmin, with
+// idx[i] = position of row i in rows (or -1) and cb their first chunks.  The
+// row kernels take such a row's dot product from the chunk partial sums that
+// a pre-pass (k_long_dot) leaves in part, summed in chunk order.
+struct LongRows {
+    int lmin = 0;     // 0: the level has no long rows
+    int n = 0;        // long rows
+    int nchunks = 0;  // chunks over them
+    const int *rows = nullptr, *cb = nullptr, *idx = nullptr;
+    void *part = nullptr;  // nchunks partial sums (cycle precision; float64 for the flexible-CG kernels)
+};
+
 // Error flags raised by the validation kernel.
 enum : int {
     kErrRowPtr = 1, kErrCol = 2, kErrUnsorted = 4, kErrNonFinite = 8, kErrNoDiag = 16,
@@ -81,8 +116,11 @@ struct Csr {
     double *v = nullptr;
     float *v32 = nullptr;
     // set while the exact entry count is still on the device only (setup): nnz
-    // then holds an upper bound, the capacity of ci and v
+    // then holds an upper bound, the capacity of ci and v; nnz_dev[1] holds the
+    // longest row's length
     const int *nnz_dev = nullptr;
+    // bound on the longest row (exact once read back; 0 = unknown: n)
+    int dmax = 0;
 };
 
 // Sliced ELL copy of a CSR matrix for the row-parallel solve kernels: rows in
@@ -118,6 +156,7 @@ struct Sell {
 // order, mstride slots per aggregate padded with -1.
 struct Level {
     Csr A;
+    LongRows lr;  // rows longer than long_min(G) of the rule (set at the end of setup)
     Sell E;  // sliced ELL copy (finest level, and levels that run the split up leg)
     double *w = nullptr;
     double *dinv = nullptr;
@@ -186,6 +225,7 @@ struct bcm_handle {
     int *tail_ops = nullptr;               // the tail kernel's program (device)
     int n_tail_ops = 0;
     double *partials = nullptr;
+    double *lpart = nullptr;  // chunk sums of the long rows (the largest level's chunk count)
     double *kpart = nullptr;  // K-cycle block partials (3 * kKPartBlocks)
     double *ks = nullptr;     // K-cycle scalars, 8 per level
     double *host_scal = nullptr;  // pinned
@@ -198,7 +238,9 @@ struct bcm_handle {
     std::vector<std::pair<int, int>> ev_pairs;  // (class, event index of the start)
     std::vector<double> ev_bytes;
     std::vector<int> ev_iter;
-    bcm::ProfClass prof[6];
+    bcm::ProfClass prof[9];
+    double setup_bytes = 0.0;  // sum over the pairwise sweeps of 72 z + 80 m
+    int sweeps_run = 0;
 };
 
 namespace bcm {
@@ -206,30 +248,75 @@ namespace bcm {
 int pick_G(double avg_nnz_per_row);
 
 // ---- setup kernels (setup.hip) ----
+// Validation (bounds, order, finiteness, diagonal; symmetry when check_sym);
+// the diagonal goes to diag.  With seg.ctl given, rows longer than lmin are
+// appended to seg and their entries are checked by launch_long_validate
+// (launched by the caller after this, once seg is fixed up).  dmax, when given
+// (starting at 0), gets the longest row's length.
 void launch_validate(hipStream_t s, int G, int n, int nnz, const int *rp, const int *ci,
-                     const double *v, const double *w, int check_sym, double *diag, int *flags);
+                     const double *v, const double *w, int check_sym, double *diag, int *flags,
+                     const SegList &seg = SegList(), int lmin = 0, int *dmax = nullptr);
+// weights of the rows up to lmin entries (lmin = 0: every row)
 void launch_weights(hipStream_t s, int G, int n, const int *rp, const int *ci, const double *v, const double *diag,
-                    const double *w, double *c, unsigned long long *ws);
+                    const double *w, double *c, unsigned long long *ws, int lmin = 0);
 // Suitor candidate lists; matrices averaging at least kSortedCandidatesAvg
-// entries per row sort each row (own-row ranks in rk[nnz], scratch)
+// entries per row sort each row (own-row ranks in rk[nnz], scratch).  Rows
+// longer than lmin (0: none) are left to launch_long_candidates; the direct
+// kernel then takes the rank of an entry seen from such a row from rk.
 constexpr int kSortedCandidatesAvg = 24;
 void launch_candidates(hipStream_t s, int G, int n, bool sorted, const int *rp, const int *ci, const double *c,
-                       unsigned *rk, unsigned long long *cand);
+                       unsigned *rk, unsigned long long *cand, int lmin = 0, int part = 0);
+// ---- long segments (setup.hip) ----
+// rows of (n, rp) longer than lmin appended to seg; idx (optional) gets each
+// row's position in seg or -1
+void launch_find_long(hipStream_t s, int n, const int *rp, int lmin, const SegList &seg, int *idx);
+// Galerkin coarse rows with more than lmin candidate entries (members' rows)
+void launch_find_long_gal(hipStream_t s, int nc, const int *mem2, const int *rp, int lmin, const SegList &seg);
+// offsets, chunk bases and totals of seg (one workgroup)
+void launch_seg_fix(hipStream_t s, const SegList &seg);
+// per-entry checks of the long rows in seg (as the validation kernel does)
+void launch_long_validate(hipStream_t s, int n, int nnz, const int *rp, const int *ci, const double *v,
+                          int check_sym, const SegList &seg, int *flags);
+void launch_long_weights(hipStream_t s, const SegList &seg, const int *rp, const int *ci, const double *v,
+                         const double *diag, const double *w, double *c);
+// Own-row ranks and candidate lists of the long rows (a segmented sort of each
+// row; keys scratch k0/k1 of 2 * total length, maxlen bounds the longest).
+// direct: rk holds ranks for the long rows only (the other rows count theirs).
+void launch_long_ranks(hipStream_t s, const SegList &seg, int maxlen, const int *rp, const double *c,
+                       unsigned *rk, unsigned long long *k0, unsigned long long *k1);
+void launch_long_candidates(hipStream_t s, const SegList &seg, int maxlen, const int *rp, const int *ci,
+                            const double *c, const unsigned *rk, int lmin, bool direct, unsigned long long *cand,
+                            unsigned long long *k0, unsigned long long *k1);
+// Galerkin coarse rows of seg: sort their candidates (keys left in *sorted),
+// then pass 0 counts distinct columns into cnt, pass 1 fills the entries
+void launch_gal_long_sort(hipStream_t s, const SegList &seg, int maxlen, const int *rp, const int *ci,
+                          const int *agg, const int *mem2, unsigned long long *k0, unsigned long long *k1,
+                          unsigned long long **sorted);
+void launch_gal_long(hipStream_t s, int pass, const SegList &seg, const unsigned long long *sorted, const int *rp,
+                     const int *ci, const double *v, const int *agg, const double *p, const int *mem2, int *cnt,
+                     const int *crp, int *cci, double *cv);
+// l1 row norms of the long rows of a level: chunk partial sums into part
+// (float64), float32 copies of their values into v32 when given
+void launch_long_abs(hipStream_t s, const LongRows &lr, const int *rp, const double *v, double *part, float *v32);
 void launch_suitor(hipStream_t s, int n, const int *rp, const unsigned long long *cand, unsigned long long *ws);
 void launch_mate(hipStream_t s, int n, const int *rp, const int *ci, const unsigned long long *ws, int *mate,
                  int *leader, const int *csrc = nullptr, int *cdst = nullptr);
 void launch_aggfill(hipStream_t s, int n, const int *mate, const int *ofs, const double *w,
                     int *agg, double *p, double *wc, int *mem2);
+// Galerkin product of one pairwise sweep (coarse rows with more than lmin
+// candidates are left to launch_gal_long; lmin = 0: none)
 void launch_gal_count(hipStream_t s, int G, int nc, const int *rp, const int *ci, const int *agg,
-                      const int *mem2, int *cnt, int *gF, int *gU, bool sorted);
+                      const int *mem2, int *cnt, int *gF, int *gU, bool sorted, int lmin = 0);
 void launch_gal_fill(hipStream_t s, int G, int nc, const int *rp, const int *ci, const double *v,
                      const int *agg, const double *p, const int *mem2, const int *crp, int *cci,
-                     double *cv, int *gF, int *gU, bool sorted);
+                     double *cv, int *gF, int *gU, bool sorted, int lmin = 0);
 void launch_compose(hipStream_t s, int n, int nc_new, const int *agg_prev, const double *p_prev,
                     const int *mem_prev, int stride_prev, const int *agg_s, const double *p_s,
                     const int *mem_s, int *agg_out, double *p_out, int *mem_out);
+// l1-Jacobi inverse diagonal; the level's long rows take their norms from
+// the partial sums of launch_long_abs (lr.n = 0: none)
 void launch_diag_l1(hipStream_t s, int G, int n, const int *rp, const double *v, double *dinv,
-                    float *dinv32, float *v32);
+                    float *dinv32, float *v32, const LongRows &lr = LongRows(), const double *part = nullptr);
 void launch_cast(hipStream_t s, size_t n, const double *src, float *dst);
 // slice widths (64 * longest row of each slice) -> cnt[nslices]; *maxoff is
 // raised to the largest |col - row| of the matrix, *inexact to 1 if a value is
@@ -246,8 +333,10 @@ void launch_copy_f64(hipStream_t s, size_t n, const double *src, double *dst);
 
 // ---- scan (scan.hip) ----
 size_t scan_tmp_bytes(int n);
-// out[i] = sum_{j<i} in[j] (in and out may alias); total written to *total_dev.
-void scan_exclusive(hipStream_t s, const int *in, int *out, int n, int *total_dev, void *tmp);
+// out[i] = sum_{j<i} in[j] (in and out may alias); total written to *total_dev,
+// and the largest in[i] to *max_dev when given.
+void scan_exclusive(hipStream_t s, const int *in, int *out, int n, int *total_dev, void *tmp,
+                    int *max_dev = nullptr);
 
 // ---- solve kernels (solve.hip) ----
 // Cycle kernels return at once when done != NULL and *done != 0 (the flexible
@@ -262,7 +351,7 @@ void launch_coarse(hipStream_t s, const Level &L, int sweeps, const void *b, voi
                    int x_f64, void *tmp_a, void *tmp_b, const double *done);
 // true when the coarsest level (without a dense operator) runs in one workgroup
 // with everything in LDS; otherwise launch_coarse needs two n-vectors tmp_a/b
-bool coarse_in_lds(int n, int nnz);
+bool coarse_in_lds(int n, int nnz, bool long_rows);
 // Each of these is a streaming kernel writing block partials; launch_finalize
 // (mode 0 after resid, 1 after spmv_dots, 2 after update) then sums them in
 // block order into scal[].

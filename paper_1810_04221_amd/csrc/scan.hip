@@ -40,16 +40,31 @@ __device__ __forceinline__ int block_excl(int x, int *total) {
     return base + inc - x;
 }
 
+// largest value over a workgroup of kBlock threads (valid in every thread)
+__device__ __forceinline__ int block_max(int x) {
+    __shared__ int wmax[kBlock / 64];
+    for (int o = 32; o > 0; o >>= 1) x = max(x, __shfl_xor(x, o, 64));
+    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = x;
+    __syncthreads();
+    int m = wmax[0];
+    for (int w = 1; w < kBlock / 64; ++w) m = max(m, wmax[w]);
+    __syncthreads();
+    return m;
+}
+
+// in and out may be the same array (each item is read before the barrier of
+// block_excl and written after it by the same thread): no restrict on them.
 __global__ void __launch_bounds__(kBlock)
-k_scan_tiles(const int *__restrict__ in, int *__restrict__ out, int n, int *__restrict__ tsum) {
+k_scan_tiles(const int *in, int *out, int n, int *__restrict__ tsum, int *__restrict__ tmax) {
     const size_t base = (size_t)blockIdx.x * kTile + (size_t)threadIdx.x * kItems;
     int v[kItems];
-    int s = 0;
+    int s = 0, mx = 0;
 #pragma unroll
     for (int k = 0; k < kItems; ++k) {
         const size_t i = base + k;
         v[k] = i < (size_t)n ? in[i] : 0;
         s += v[k];
+        mx = max(mx, v[k]);
     }
     int tot;
     int run = block_excl(s, &tot);
@@ -59,21 +74,31 @@ k_scan_tiles(const int *__restrict__ in, int *__restrict__ out, int n, int *__re
         if (i < (size_t)n) out[i] = run;
         run += v[k];
     }
-    if (threadIdx.x == 0) tsum[blockIdx.x] = tot;
+    if (tmax) mx = block_max(mx);
+    if (threadIdx.x == 0) {
+        tsum[blockIdx.x] = tot;
+        if (tmax) tmax[blockIdx.x] = mx;
+    }
 }
 
-__global__ void __launch_bounds__(kBlock) k_scan_totals(int *__restrict__ tsum, int nt, int *__restrict__ total) {
-    int carry = 0;
+__global__ void __launch_bounds__(kBlock) k_scan_totals(int *__restrict__ tsum, int nt, int *__restrict__ total,
+                                                        const int *__restrict__ tmax, int *__restrict__ max_out) {
+    int carry = 0, mx = 0;
     for (int b0 = 0; b0 < nt; b0 += kBlock) {
         const int i = b0 + threadIdx.x;
         const int x = i < nt ? tsum[i] : 0;
+        if (tmax && i < nt) mx = max(mx, tmax[i]);
         int tot;
         const int ex = block_excl(x, &tot);
         if (i < nt) tsum[i] = carry + ex;
         carry += tot;
         __syncthreads();
     }
-    if (threadIdx.x == 0) *total = carry;
+    if (tmax) mx = block_max(mx);
+    if (threadIdx.x == 0) {
+        *total = carry;
+        if (max_out) *max_out = mx;
+    }
 }
 
 __global__ void __launch_bounds__(kBlock) k_scan_add(int *__restrict__ out, int n, const int *__restrict__ tsum) {
@@ -93,15 +118,22 @@ __global__ void __launch_bounds__(kBlock) k_scan_add(int *__restrict__ out, int 
 // an item is read and written by the same lane.
 constexpr int kScanSmall = 16384;
 
-__global__ void __launch_bounds__(1024) k_scan_single(const int *in, int *out, int n, int *__restrict__ total) {
+__global__ void __launch_bounds__(1024) k_scan_single(const int *in, int *out, int n, int *__restrict__ total,
+                                                     int *__restrict__ max_out) {
     constexpr int C = kScanSmall / 1024;
-    __shared__ int wsum[16];
+    __shared__ int wsum[16], wmax[16];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     int v[C];
+    int mx = 0;
 #pragma unroll
     for (int c = 0; c < C; ++c) {
         const int e = (wid * C + c) * 64 + lane;
         v[c] = e < n ? in[e] : 0;
+        mx = max(mx, v[c]);
+    }
+    if (max_out) {
+        for (int o = 32; o > 0; o >>= 1) mx = max(mx, __shfl_xor(mx, o, 64));
+        if (lane == 0) wmax[wid] = mx;
     }
     int run = 0;  // the same in every lane of the wave
 #pragma unroll
@@ -123,26 +155,34 @@ __global__ void __launch_bounds__(1024) k_scan_single(const int *in, int *out, i
         const int e = (wid * C + c) * 64 + lane;
         if (e < n) out[e] = base + v[c];
     }
-    if (threadIdx.x == 0) *total = tot;
+    if (threadIdx.x == 0) {
+        *total = tot;
+        if (max_out) {
+            for (int w = 1; w < 16; ++w) mx = max(mx, wmax[w]);
+            *max_out = max(mx, wmax[0]);
+        }
+    }
 }
 
 }  // namespace
 
-size_t scan_tmp_bytes(int n) { return sizeof(int) * (size_t)((n + kTile - 1) / kTile + 1); }
+size_t scan_tmp_bytes(int n) { return 2 * sizeof(int) * (size_t)((n + kTile - 1) / kTile + 1); }
 
-void scan_exclusive(hipStream_t s, const int *in, int *out, int n, int *total_dev, void *tmp) {
+void scan_exclusive(hipStream_t s, const int *in, int *out, int n, int *total_dev, void *tmp, int *max_dev) {
     const int nt = (n + kTile - 1) / kTile;
     int *tsum = static_cast<int *>(tmp);
+    int *tmax = max_dev ? tsum + nt + 1 : nullptr;
     if (nt == 0) {
         launch_fill_i32(s, 1, total_dev, 0);
+        if (max_dev) launch_fill_i32(s, 1, max_dev, 0);
         return;
     }
     if (n <= kScanSmall) {
-        hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(1024), 0, s, in, out, n, total_dev);
+        hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(1024), 0, s, in, out, n, total_dev, max_dev);
         return;
     }
-    hipLaunchKernelGGL(k_scan_tiles, dim3(nt), dim3(kBlock), 0, s, in, out, n, tsum);
-    hipLaunchKernelGGL(k_scan_totals, dim3(1), dim3(kBlock), 0, s, tsum, nt, total_dev);
+    hipLaunchKernelGGL(k_scan_tiles, dim3(nt), dim3(kBlock), 0, s, in, out, n, tsum, tmax);
+    hipLaunchKernelGGL(k_scan_totals, dim3(1), dim3(kBlock), 0, s, tsum, nt, total_dev, tmax, max_dev);
     hipLaunchKernelGGL(k_scan_add, dim3(nt), dim3(kBlock), 0, s, out, n, tsum);
 }
 

@@ -8,6 +8,7 @@
 // -ffp-contract=off (no FMA contraction) and each operation below is one
 // correctly rounded binary64 add, multiply, divide or square root.
 #include <type_traits>
+#include <utility>
 
 #include "device.h"
 #include "internal.h"
@@ -35,11 +36,20 @@ inline int blocks_for(long long threads) { return (int)((threads + kBlock - 1) /
 // Validation and diagonal: one group of G lanes per row.  Every read is guarded
 // so that malformed input raises a flag instead of an out-of-bounds access.
 // ----------------------------------------------------------------------------
+// Appends (row, len) to a list of long segments.
+__device__ __forceinline__ void seg_append(const SegList &sg, int row, int len) {
+    const int t = atomicAdd(&sg.ctl[0], 1);
+    if (t < sg.cap) {
+        sg.row[t] = row;
+        sg.len[t] = len;
+    }
+}
+
 template <int G>
 __global__ void __launch_bounds__(kBlock)
 k_validate(int n, int nnz, const int *__restrict__ rp, const int *__restrict__ ci,
            const double *__restrict__ v, const double *__restrict__ w, int check_sym,
-           double *__restrict__ diag, int *__restrict__ flags) {
+           double *__restrict__ diag, int *__restrict__ flags, SegList sg, int lmin, int *__restrict__ dmax) {
     const int lane = threadIdx.x % G;
     const int row = (blockIdx.x * kBlock + threadIdx.x) / G;
     if (row >= n) return;
@@ -50,9 +60,25 @@ k_validate(int n, int nnz, const int *__restrict__ rp, const int *__restrict__ c
         if (lane == 0) atomicOr(flags, kErrRowPtr);
         return;
     }
+    // longest row: the atomic only when the (coherent) current value is exceeded
+    if (dmax && lane == 0 && e - s > load_agent(dmax)) atomicMax(dmax, e - s);
     int has_diag = 0;
     double dval = 0.0;
-    for (int q = s + lane; q < e; q += G) {
+    // a long row: its entries are checked by k_long_validate; here only its
+    // diagonal, found by a binary search of the (ascending) columns
+    const bool lng = sg.ctl && e - s > lmin;
+    if (lng) {
+        if (lane == 0) {
+            seg_append(sg, row, e - s);
+            int lo = s, hi = e;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (ci[mid] < row) lo = mid + 1; else hi = mid;
+            }
+            if (lo < e && ci[lo] == row) { has_diag = 1; dval = v[lo]; }
+        }
+    }
+    for (int q = s + lane; q < (lng ? s : e); q += G) {
         const int j = ci[q];
         const double a = v[q];
         if (j < 0 || j >= n) { f |= kErrCol; continue; }
@@ -94,28 +120,29 @@ k_validate(int n, int nnz, const int *__restrict__ rp, const int *__restrict__ c
 // an edge compute the same double.  Diagonal positions get 0; ws (the
 // matching's best proposal per vertex) is cleared on the way.
 // ----------------------------------------------------------------------------
+__device__ __forceinline__ double edge_weight(int row, int j, double a, const double *__restrict__ diag,
+                                              const double *__restrict__ w) {
+    if (j == row) return 0.0;
+    const int m = min(row, j), M = max(row, j);
+    const double wm = w[m], wM = w[M];
+    const double num = ((2.0 * a) * wm) * wM;
+    const double den = (diag[m] * wm) * wm + (diag[M] * wM) * wM;
+    return 1.0 - num / den;
+}
+
 template <int G>
 __global__ void __launch_bounds__(kBlock)
 k_weights(int n, const int *__restrict__ rp, const int *__restrict__ ci, const double *__restrict__ v,
           const double *__restrict__ diag, const double *__restrict__ w, double *__restrict__ c,
-          unsigned long long *__restrict__ ws) {
+          unsigned long long *__restrict__ ws, int lmin) {
+    // rows longer than lmin (> 0) are left to k_long_weights
     const int lane = threadIdx.x % G;
     const int row = (xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x) / G;
     if (row >= n) return;
     if (ws && lane == 0) ws[row] = 0ull;
-    const int e = rp[row + 1];
-    for (int q = rp[row] + lane; q < e; q += G) {
-        const int j = ci[q];
-        double cq = 0.0;
-        if (j != row) {
-            const int m = min(row, j), M = max(row, j);
-            const double wm = w[m], wM = w[M];
-            const double num = ((2.0 * v[q]) * wm) * wM;
-            const double den = (diag[m] * wm) * wm + (diag[M] * wM) * wM;
-            cq = 1.0 - num / den;
-        }
-        c[q] = cq;
-    }
+    const int b = rp[row], e = rp[row + 1];
+    if (lmin > 0 && e - b > lmin) return;
+    for (int q = b + lane; q < e; q += G) c[q] = edge_weight(row, ci[q], v[q], diag, w);
 }
 
 // ----------------------------------------------------------------------------
@@ -128,7 +155,10 @@ k_weights(int n, const int *__restrict__ rp, const int *__restrict__ ci, const d
 template <int G>
 __global__ void __launch_bounds__(kBlock)
 k_candidates_direct(int n, const int *__restrict__ rp, const int *__restrict__ ci, const double *__restrict__ c,
-                    unsigned long long *__restrict__ cand) {
+                    const unsigned *__restrict__ rk, unsigned long long *__restrict__ cand, int lmin) {
+    // rows longer than lmin (> 0) are left to the long-row kernels, which leave
+    // their own-row ranks in rk: the rank of c_uv seen from such a row v is read
+    // there (at the transposed position) instead of counted
     constexpr int LS = 4 * G;
     constexpr int NG = kBlock / G;
     __shared__ double sc[NG * LS];
@@ -137,8 +167,17 @@ k_candidates_direct(int n, const int *__restrict__ rp, const int *__restrict__ c
     const int row = (xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x) / G;
     if (row >= n) return;
     const int s0 = rp[row], e = rp[row + 1], d = e - s0;
+    if (lmin > 0 && d > lmin) return;
     auto rank_at = [&](int vtx, double cq) -> unsigned {
         const int b2 = rp[vtx], e2 = rp[vtx + 1];
+        if (lmin > 0 && e2 - b2 > lmin) {
+            int lo = b2, hi = e2;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (ci[mid] < row) lo = mid + 1; else hi = mid;
+            }
+            return (lo < e2 && ci[lo] == row) ? rk[lo] : 0u;
+        }
         unsigned r = 0;
 #pragma unroll 8
         for (int t = b2; t < e2; ++t) r += (c[t] < cq) ? 1u : 0u;
@@ -229,7 +268,7 @@ __device__ __forceinline__ int lower_bound_u64(const unsigned long long *keys, i
 // ----------------------------------------------------------------------------
 template <int G>
 __global__ void __launch_bounds__(kBlock)
-k_rank(int n, const int *__restrict__ rp, const double *__restrict__ c, unsigned *__restrict__ rk) {
+k_rank(int n, const int *__restrict__ rp, const double *__restrict__ c, unsigned *__restrict__ rk, int lmin) {
     constexpr int LMAX = 16 * G;
     constexpr int NG = kBlock / G;
     __shared__ unsigned long long sk[NG * LMAX];
@@ -237,6 +276,7 @@ k_rank(int n, const int *__restrict__ rp, const double *__restrict__ c, unsigned
     const int row = (xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x) / G;
     if (row >= n) return;
     const int s0 = rp[row], d = rp[row + 1] - s0;
+    if (lmin > 0 && d > lmin) return;  // a long row: k_long_rank
     if (d <= LMAX) {
         unsigned long long *keys = sk + g * LMAX;
         const int P = pow2_at_least(d);
@@ -273,7 +313,7 @@ k_rank(int n, const int *__restrict__ rp, const double *__restrict__ c, unsigned
 template <int G>
 __global__ void __launch_bounds__(kBlock)
 k_candidates(int n, const int *__restrict__ rp, const int *__restrict__ ci, const double *__restrict__ c,
-             const unsigned *__restrict__ rk_own, unsigned long long *__restrict__ cand) {
+             const unsigned *__restrict__ rk_own, unsigned long long *__restrict__ cand, int lmin) {
     constexpr int LMAX = 16 * G;
     constexpr int NG = kBlock / G;
     __shared__ unsigned long long sk[NG * LMAX];
@@ -281,6 +321,7 @@ k_candidates(int n, const int *__restrict__ rp, const int *__restrict__ ci, cons
     const int row = (xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x) / G;
     if (row >= n) return;
     const int s0 = rp[row], e = rp[row + 1], d = e - s0;
+    if (lmin > 0 && d > lmin) return;  // a long row: k_long_cand
     // rank of c_uv seen from v: the own-row rank of (v, u), found by binary search
     // (a pattern that is not symmetric, accepted without the symmetry check,
     // may lack the entry: rank 0 then, and no read outside row v)
@@ -291,7 +332,7 @@ k_candidates(int n, const int *__restrict__ rp, const int *__restrict__ ci, cons
             const int mid = (lo + hi) >> 1;
             if (ci[mid] < row) lo = mid + 1; else hi = mid;
         }
-        return lo < e2 ? rk_own[lo] : 0u;
+        return (lo < e2 && ci[lo] == row) ? rk_own[lo] : 0u;
     };
     if (d <= LMAX) {
         unsigned long long *keys = sk + g * LMAX;
@@ -362,6 +403,7 @@ k_suitor(int n, const int *__restrict__ rp, const unsigned long long *__restrict
     // Highest vertices first: workgroups are dispatched roughly in index order,
     // and the greedy order settles large indices first on equal weights.  (Cut
     // into several launches, highest chunk first, this ran slower.)
+    __shared__ unsigned long long wbest[kBlock / 64];
     const int u = n - 1 - (int)(blockIdx.x * kBlock + threadIdx.x);
     if (u < 0) return;
     int t = rp[u];
@@ -373,6 +415,23 @@ k_suitor(int n, const int *__restrict__ rp, const unsigned long long *__restrict
         if (e == ~0ull) break;  // no candidate left: this vertex stays unmatched
         const unsigned long long key = (e & 0xffffffff00000000ull) | (unsigned long long)(unsigned)(t + 1);
         const int v = (int)(e & 0xffffffffull);
+        // Every active lane of the wave proposing to the same vertex (the
+        // leaves of a hub): only the best of these proposals can win there (ws
+        // only grows, keys are distinct), so the others lose at once -- the
+        // outcome of any order in which the best one came first -- and the
+        // wave issues one atomic instead of 64.
+        const int v0 = __builtin_amdgcn_readfirstlane(v);
+        if (__ballot(v != v0) == 0ull) {
+            unsigned long long *slot = &wbest[threadIdx.x >> 6];
+            const int first = __ffsll((unsigned long long)__ballot(1)) - 1;
+            if ((int)(threadIdx.x & 63) == first) *slot = 0ull;
+            wave_sync();
+            atomicMax(slot, key);
+            wave_sync();
+            const unsigned long long best = *slot;
+            wave_sync();
+            if (key != best) { ++t; continue; }
+        }
         const unsigned long long old = atomicMax(&ws[v], key);
         if (old > key) { ++t; continue; }  // lost v for good (ws only grows): next slot
         if (old == 0ull) break;            // v had no suitor: done
@@ -385,9 +444,9 @@ k_suitor(int n, const int *__restrict__ rp, const unsigned long long *__restrict
 __global__ void __launch_bounds__(kBlock)
 k_mate(int n, const int *__restrict__ rp, const int *__restrict__ ci, const unsigned long long *__restrict__ ws,
        int *__restrict__ mate, int *__restrict__ leader, const int *__restrict__ csrc, int *__restrict__ cdst) {
-    // (csrc given: one int copied to cdst on the way, for the host's next read-back)
+    // (csrc given: two ints copied to cdst on the way, for the host's next read-back)
     const int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i == 0 && csrc) *cdst = *csrc;
+    if (i < 2 && csrc) cdst[i] = csrc[i];
     if (i >= n) return;
     // the suitor of i is the neighbour whose row holds the winning slot ts:
     // the last neighbour j of i with rp[j] <= ts (columns ascending, rp monotone)
@@ -585,17 +644,24 @@ k_compose_members(int nc_new, const int *__restrict__ mem_prev, int stride_prev,
 template <int G>
 __global__ void __launch_bounds__(kBlock)
 k_diag_l1(int n, const int *__restrict__ rp, const double *__restrict__ v, double *__restrict__ dinv,
-          float *__restrict__ dinv32, float *__restrict__ v32) {
-    // (with v32 given, the row's values are also written rounded to float32)
+          float *__restrict__ dinv32, float *__restrict__ v32, LongRows lr, const double *__restrict__ part) {
+    // (with v32 given, the row's values are also written rounded to float32).
+    // A long row (lr) takes its norm from the chunk sums of k_long_abs, which
+    // also wrote its float32 values.
     const int lane = threadIdx.x % G;
     const int row = (xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x) / G;
     if (row >= n) return;
     double s = 0.0;
-    const int e = rp[row + 1];
-    for (int q = rp[row] + lane; q < e; q += G) {
-        const double a = v[q];
-        s += fabs(a);
-        if (v32) v32[q] = (float)a;
+    const int b = rp[row], e = rp[row + 1];
+    if (lr.n > 0 && e - b > lr.lmin) {
+        const int t = lr.idx[row];
+        for (int c = lr.cb[t] + lane; c < lr.cb[t + 1]; c += G) s += part[c];
+    } else {
+        for (int q = b + lane; q < e; q += G) {
+            const double a = v[q];
+            s += fabs(a);
+            if (v32) v32[q] = (float)a;
+        }
     }
     s = group_sum<G>(s);
     if (lane == 0) {
@@ -773,6 +839,391 @@ __global__ void k_fill_u64(size_t n, unsigned long long *__restrict__ dst, unsig
         dst[i] = val;
 }
 
+// ============================================================================
+// Long segments: rows longer than the level's bound, and Galerkin coarse rows
+// with more candidates than that.  Their entries are processed in parallel
+// across workgroups, and the orderings the per-row kernels form in a group's
+// LDS (own-row ranks, the Suitor preference order, the distinct columns of a
+// coarse row) come from a segmented sort: every chunk of kSegChunk keys is
+// sorted in one workgroup's LDS, then runs are merged pairwise, each key
+// placed by one binary search in the partner run.
+// ============================================================================
+constexpr int kSegBlock = 1024;  // threads of the one-workgroup kernels below
+
+// largest t in [0, cnt) with base[t] <= x (base strictly ascending, base[0] = 0)
+__device__ __forceinline__ int seg_of(const int *__restrict__ base, int cnt, int x) {
+    int lo = 0, hi = cnt - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (base[mid] <= x) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// first index k < cnt with keys[k] > key (keys ascending)
+__device__ __forceinline__ int upper_bound_u64(const unsigned long long *keys, int cnt, unsigned long long key) {
+    int lo = 0, hi = cnt;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (keys[mid] <= key) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+// exclusive scan over a workgroup of kSegBlock threads; *total gets the sum
+__device__ __forceinline__ int seg_block_excl(int x, int *total) {
+    __shared__ int wsum[kSegBlock / 64];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    int inc = x;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int t = __shfl_up(inc, o, 64);
+        if (lane >= o) inc += t;
+    }
+    if (lane == 63) wsum[wid] = inc;
+    __syncthreads();
+    int base = 0, tot = 0;
+    for (int w = 0; w < kSegBlock / 64; ++w) {
+        if (w < wid) base += wsum[w];
+        tot += wsum[w];
+    }
+    __syncthreads();
+    *total = tot;
+    return base + inc - x;
+}
+
+// Offsets and first chunks of the segments found, in the order found.
+__global__ void __launch_bounds__(kSegBlock) k_seg_fix(SegList sg) {
+    const int found = sg.ctl[0];
+    const int cnt = min(found, sg.cap);
+    int carry_l = 0, carry_c = 0, mx = 0;
+    for (int b0 = 0; b0 < cnt; b0 += kSegBlock) {
+        const int t = b0 + threadIdx.x;
+        const int l = t < cnt ? sg.len[t] : 0;
+        const int ch = (l + kSegChunk - 1) / kSegChunk;
+        mx = max(mx, l);
+        int tl, tc;
+        const int el = seg_block_excl(l, &tl);
+        const int ec = seg_block_excl(ch, &tc);
+        if (t < cnt) {
+            sg.off[t] = carry_l + el;
+            sg.cb[t] = carry_c + ec;
+        }
+        carry_l += tl;
+        carry_c += tc;
+    }
+    for (int o = 32; o > 0; o >>= 1) mx = max(mx, __shfl_xor(mx, o, 64));
+    __shared__ int wmax[kSegBlock / 64];
+    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = mx;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < kSegBlock / 64; ++w) mx = max(mx, wmax[w]);
+        sg.off[cnt] = carry_l;
+        sg.cb[cnt] = carry_c;
+        sg.ctl[0] = cnt;
+        sg.ctl[1] = carry_l;
+        sg.ctl[2] = carry_c;
+        sg.ctl[3] = mx;
+        sg.ctl[4] = found > sg.cap ? 1 : 0;
+    }
+}
+
+// Rows of (n, rp) longer than lmin; idx[i] = position in the list or -1.
+__global__ void __launch_bounds__(kBlock)
+k_find_long(int n, const int *__restrict__ rp, int lmin, SegList sg, int *__restrict__ idx) {
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const int d = rp[i + 1] - rp[i];
+    int t = -1;
+    if (d > lmin) {
+        t = atomicAdd(&sg.ctl[0], 1);
+        if (t < sg.cap) {
+            sg.row[t] = i;
+            sg.len[t] = d;
+        } else {
+            t = -1;
+        }
+    }
+    if (idx) idx[i] = t;
+}
+
+// Coarse rows E of a pairwise sweep whose member rows hold more than lmin
+// entries together (the candidates of E's Galerkin row).
+__global__ void __launch_bounds__(kBlock)
+k_find_long_gal(int nc, const int *__restrict__ mem2, const int *__restrict__ rp, int lmin, SegList sg) {
+    const int E = blockIdx.x * kBlock + threadIdx.x;
+    if (E >= nc) return;
+    const int e0 = mem2[2 * E], e1 = mem2[2 * E + 1];
+    const int L = (rp[e0 + 1] - rp[e0]) + (e1 >= 0 ? rp[e1 + 1] - rp[e1] : 0);
+    if (L > lmin) seg_append(sg, E, L);
+}
+
+// Every entry of every segment, in a grid-stride loop: body(t, k, row).
+template <typename Body>
+__device__ __forceinline__ void for_seg_entries(const SegList &sg, Body body) {
+    const int cnt = sg.ctl[0], tot = sg.ctl[1];
+    for (int g = blockIdx.x * kBlock + threadIdx.x; g < tot; g += gridDim.x * kBlock) {
+        const int t = seg_of(sg.off, cnt, g);
+        body(t, g - sg.off[t], sg.row[t]);
+    }
+}
+
+// Per-entry checks of the long rows (the part of k_validate they skipped).
+__global__ void __launch_bounds__(kBlock)
+k_long_validate(int n, int nnz, const int *__restrict__ rp, const int *__restrict__ ci,
+                const double *__restrict__ v, int check_sym, SegList sg, int *__restrict__ flags) {
+    int f = 0;
+    for_seg_entries(sg, [&](int, int k, int row) {
+        const int q = rp[row] + k;
+        const int j = ci[q];
+        const double a = v[q];
+        if (j < 0 || j >= n) { f |= kErrCol; return; }
+        if (k > 0 && ci[q - 1] >= j) f |= kErrUnsorted;
+        if (!isfinite(a)) f |= kErrNonFinite;
+        if (check_sym && j != row) {
+            const int s2 = rp[j], e2 = rp[j + 1];
+            int found = -1;
+            if (s2 >= 0 && e2 >= s2 && (nnz < 0 || e2 <= nnz)) {
+                int lo = s2, hi = e2 - 1;
+                while (lo <= hi) {
+                    const int mid = (lo + hi) >> 1;
+                    const int cm = ci[mid];
+                    if (cm == row) { found = mid; break; }
+                    if (cm < row) lo = mid + 1; else hi = mid - 1;
+                }
+            }
+            if (found < 0 || __double_as_longlong(v[found]) != __double_as_longlong(a)) f |= kErrAsym;
+        }
+    });
+    if (f) atomicOr(flags, f);
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_long_weights(SegList sg, const int *__restrict__ rp, const int *__restrict__ ci, const double *__restrict__ v,
+               const double *__restrict__ diag, const double *__restrict__ w, double *__restrict__ c) {
+    for_seg_entries(sg, [&](int, int k, int row) {
+        const int q = rp[row] + k;
+        c[q] = edge_weight(row, ci[q], v[q], diag, w);
+    });
+}
+
+// Sort keys of the segmented sorts.  Own-row ranks: the weight's order key.
+struct KeyRank {
+    const int *rp;
+    const double *c;
+    __device__ unsigned long long operator()(int row, int, int k) const { return order_key(c[rp[row] + k]); }
+};
+// Suitor preference order of a row u: eligible entries by (own-row rank
+// desc, neighbour desc) -- the order k_candidates sorts -- then the others.
+struct KeyCand {
+    const int *rp, *ci;
+    const double *c;
+    const unsigned *rk;
+    __device__ unsigned long long operator()(int row, int, int k) const {
+        const int q = rp[row] + k, vtx = ci[q];
+        const double cq = c[q];
+        if (vtx != row && cq > 0.0 && cq < INFINITY)
+            return ((unsigned long long)(0x7fffffffu - rk[q]) << 32) | (0x7fffffffu - (unsigned)vtx);
+        return 0xffffffff00000000ull | (unsigned)k;
+    }
+};
+// Galerkin coarse row E: candidate k (an entry of E's member rows) keyed by
+// its coarse column, then k.
+struct KeyGal {
+    const int *rp, *ci, *agg, *mem2;
+    __device__ unsigned long long operator()(int E, int, int k) const {
+        const int e0 = mem2[2 * E], s0 = rp[e0], L0 = rp[e0 + 1] - s0;
+        const int q = k < L0 ? s0 + k : rp[mem2[2 * E + 1]] + (k - L0);
+        return ((unsigned long long)(unsigned)agg[ci[q]] << 32) | (unsigned)k;
+    }
+};
+
+// Sorts every chunk of kSegChunk keys of every segment in LDS (bitonic
+// network over the whole chunk, ~0 padding), writing them to out at the
+// segment's offset.
+template <typename Key>
+__global__ void __launch_bounds__(kBlock) k_seg_sort_chunks(SegList sg, Key key, unsigned long long *__restrict__ out) {
+    __shared__ unsigned long long keys[kSegChunk];
+    const int cnt = sg.ctl[0], nch = sg.ctl[2];
+    for (int ch = blockIdx.x; ch < nch; ch += gridDim.x) {
+        const int t = seg_of(sg.cb, cnt, ch);
+        const int L = sg.len[t], k0 = (ch - sg.cb[t]) * kSegChunk, m = min(kSegChunk, L - k0);
+        const int row = sg.row[t];
+        for (int k = threadIdx.x; k < kSegChunk; k += kBlock) keys[k] = k < m ? key(row, L, k0 + k) : ~0ull;
+        __syncthreads();
+        for (int size = 2; size <= kSegChunk; size <<= 1) {
+            for (int stride = size >> 1; stride > 0; stride >>= 1) {
+                for (int u = threadIdx.x; u < kSegChunk / 2; u += kBlock) {
+                    const int lo = 2 * stride * (u / stride) + (u % stride), hi = lo + stride;
+                    const bool up = (lo & size) == 0;
+                    const unsigned long long a = keys[lo], b = keys[hi];
+                    if ((a > b) == up) {
+                        keys[lo] = b;
+                        keys[hi] = a;
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        unsigned long long *dst = out + sg.off[t] + k0;
+        for (int k = threadIdx.x; k < m; k += kBlock) dst[k] = keys[k];
+        __syncthreads();
+    }
+}
+
+// One merge pass: sorted runs of `run` keys become runs of 2 run.  A key of a
+// left run goes before the equal keys of its right partner (stable), so equal
+// keys keep their chunk order.
+__global__ void __launch_bounds__(kBlock)
+k_seg_merge(SegList sg, int run, const unsigned long long *__restrict__ in, unsigned long long *__restrict__ out) {
+    const int cnt = sg.ctl[0], tot = sg.ctl[1];
+    for (int g = blockIdx.x * kBlock + threadIdx.x; g < tot; g += gridDim.x * kBlock) {
+        const int t = seg_of(sg.off, cnt, g);
+        const int k = g - sg.off[t], L = sg.len[t];
+        const unsigned long long *seg = in + sg.off[t];
+        const unsigned long long key = seg[k];
+        const int r = k / run, base = (r & ~1) * run;
+        int pos;
+        if ((r & 1) == 0) {
+            const int b0 = base + run, b1 = min(base + 2 * run, L);
+            pos = b0 >= L ? k : k + lower_bound_u64(seg + b0, b1 - b0, key);
+        } else {
+            pos = k - run + upper_bound_u64(seg + base, run, key);
+        }
+        out[sg.off[t] + pos] = key;
+    }
+}
+
+// Own-row ranks of the long rows: rk[q] = #{t in the row : c[t] < c[q]}, the
+// first position of c[q]'s key in the sorted row.
+__global__ void __launch_bounds__(kBlock)
+k_long_rank(SegList sg, const unsigned long long *__restrict__ sorted, const int *__restrict__ rp,
+            const double *__restrict__ c, unsigned *__restrict__ rk) {
+    for_seg_entries(sg, [&](int t, int k, int row) {
+        const int q = rp[row] + k;
+        rk[q] = (unsigned)lower_bound_u64(sorted + sg.off[t], sg.len[t], order_key(c[q]));
+    });
+}
+
+// Candidate lists of the long rows (the output k_candidates gives other rows):
+// each entry's key is found in the sorted row, which gives its slot.  The
+// rank of c_uv seen from v: from rk at the transposed position (every row in
+// the sorted family; long rows in the direct one), else counted over row v.
+__global__ void __launch_bounds__(kBlock)
+k_long_cand(SegList sg, const unsigned long long *__restrict__ sorted, const int *__restrict__ rp,
+            const int *__restrict__ ci, const double *__restrict__ c, const unsigned *__restrict__ rk, int lmin,
+            int direct, unsigned long long *__restrict__ cand) {
+    const KeyCand kc{rp, ci, c, rk};
+    for_seg_entries(sg, [&](int t, int k, int row) {
+        const unsigned long long key = kc(row, 0, k);
+        const int pos = lower_bound_u64(sorted + sg.off[t], sg.len[t], key);
+        const int q = rp[row] + k, vtx = ci[q];
+        unsigned long long out = ~0ull;
+        if ((key >> 32) != 0xffffffffull) {
+            const double cq = c[q];
+            const int b2 = rp[vtx], e2 = rp[vtx + 1];
+            unsigned r = 0;
+            if (!direct || e2 - b2 > lmin) {
+                int lo = b2, hi = e2;
+                while (lo < hi) {
+                    const int mid = (lo + hi) >> 1;
+                    if (ci[mid] < row) lo = mid + 1; else hi = mid;
+                }
+                r = (lo < e2 && ci[lo] == row) ? rk[lo] : 0u;
+            } else {
+                for (int u = b2; u < e2; ++u) r += (c[u] < cq) ? 1u : 0u;
+            }
+            out = ((unsigned long long)r << 32) | (unsigned)vtx;
+        }
+        cand[rp[row] + pos] = out;
+    });
+}
+
+// Galerkin coarse rows with many candidates, one workgroup per row over its
+// sorted candidate keys (column << 32 | candidate): a column starts where the
+// key's column differs from the previous one.  Pass 0 counts the distinct
+// columns; pass 1 numbers them by a scan over the workgroup and writes each
+// entry, its (at most four) terms summed in canonical (m, M) order as k_gal.
+__global__ void __launch_bounds__(kSegBlock)
+k_gal_long(int pass, SegList sg, const unsigned long long *__restrict__ sorted, const int *__restrict__ rp,
+           const int *__restrict__ ci, const double *__restrict__ v, const int *__restrict__ agg,
+           const double *__restrict__ p, const int *__restrict__ mem2, int *__restrict__ cnt,
+           const int *__restrict__ crp, int *__restrict__ cci, double *__restrict__ cv) {
+    const int nseg = sg.ctl[0];
+    for (int t = blockIdx.x; t < nseg; t += gridDim.x) {
+        const int E = sg.row[t], L = sg.len[t];
+        const unsigned long long *keys = sorted + sg.off[t];
+        auto col = [&](int k) { return (int)(keys[k] >> 32); };
+        const int C = (L + kSegBlock - 1) / kSegBlock;
+        const int k0 = min((int)threadIdx.x * C, L), k1 = min(k0 + C, L);
+        int mine = 0;
+        for (int k = k0; k < k1; ++k) mine += (k == 0 || col(k) != col(k - 1)) ? 1 : 0;
+        int total;
+        int rank = seg_block_excl(mine, &total);
+        if (pass == 0) {
+            if (threadIdx.x == 0) cnt[E] = total;
+            continue;
+        }
+        const int e0 = mem2[2 * E], e1 = mem2[2 * E + 1];
+        const int s0 = rp[e0], L0 = rp[e0 + 1] - s0;
+        const int s1 = e1 >= 0 ? rp[e1] : 0;
+        const int base = crp[E];
+        const unsigned long long NONE = ~0ull;
+        for (int k = k0; k < k1; ++k) {
+            if (!(k == 0 || col(k) != col(k - 1))) continue;
+            const int f = col(k);
+            unsigned long long kk[4];
+            double tt[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                kk[r] = NONE;
+                tt[r] = 0.0;
+                const int kr = k + r;
+                if (kr >= L || col(kr) != f) continue;
+                const int cidx = (int)(keys[kr] & 0xffffffffull);
+                const int q = cidx < L0 ? s0 + cidx : s1 + (cidx - L0);
+                const int i = cidx < L0 ? e0 : e1, j = ci[q];
+                const int m = min(i, j), M = max(i, j);
+                kk[r] = ((unsigned long long)(unsigned)m << 32) | (unsigned)M;
+                tt[r] = (p[m] * v[q]) * p[M];
+            }
+            cswap(kk[0], tt[0], kk[1], tt[1]);
+            cswap(kk[2], tt[2], kk[3], tt[3]);
+            cswap(kk[0], tt[0], kk[2], tt[2]);
+            cswap(kk[1], tt[1], kk[3], tt[3]);
+            cswap(kk[1], tt[1], kk[2], tt[2]);
+            double sum = tt[0];
+#pragma unroll
+            for (int r = 1; r < 4; ++r)
+                if (kk[r] != NONE) sum = sum + tt[r];
+            cci[base + rank] = f;
+            cv[base + rank] = sum;
+            ++rank;
+        }
+        __syncthreads();
+    }
+}
+
+// l1 norms of the long rows of a level: chunk c sums |a_q| over its kSegChunk
+// entries (eight per thread, then the workgroup in a fixed order).
+__global__ void __launch_bounds__(kBlock)
+k_long_abs(LongRows lr, const int *__restrict__ rp, const double *__restrict__ v, double *__restrict__ part,
+           float *__restrict__ v32) {
+    const int c = blockIdx.x;
+    const int t = seg_of(lr.cb, lr.n, c);
+    const int row = lr.rows[t];
+    const int q0 = rp[row] + (c - lr.cb[t]) * kSegChunk, q1 = min(q0 + kSegChunk, rp[row + 1]);
+    double s[1] = {0.0};
+    for (int q = q0 + threadIdx.x; q < q1; q += kBlock) {
+        const double a = v[q];
+        s[0] += fabs(a);
+        if (v32) v32[q] = (float)a;
+    }
+    __shared__ double lds[16];
+    block_sum<1>(s, lds);
+    if (threadIdx.x == 0) part[c] = s[0];
+}
+
 inline int stream_grid(size_t n) {
     size_t b = (n + kBlock - 1) / kBlock;
     if (b > 4096) b = 4096;
@@ -789,42 +1240,47 @@ int pick_G(double avg) {
 }
 
 void launch_validate(hipStream_t s, int G, int n, int nnz, const int *rp, const int *ci,
-                     const double *v, const double *w, int check_sym, double *diag, int *flags) {
+                     const double *v, const double *w, int check_sym, double *diag, int *flags,
+                     const SegList &seg, int lmin, int *dmax) {
     with_G(G, [&](auto gc) {
         constexpr int g = decltype(gc)::value;
         hipLaunchKernelGGL(k_validate<g>, dim3(blocks_for((long long)n * g)), dim3(kBlock), 0, s, n, nnz,
-                           rp, ci, v, w, check_sym, diag, flags);
+                           rp, ci, v, w, check_sym, diag, flags, seg, lmin, dmax);
     });
 }
 
 void launch_weights(hipStream_t s, int G, int n, const int *rp, const int *ci, const double *v, const double *diag,
-                    const double *w, double *c, unsigned long long *ws) {
+                    const double *w, double *c, unsigned long long *ws, int lmin) {
     with_G(G, [&](auto gc) {
         constexpr int g = decltype(gc)::value;
         hipLaunchKernelGGL(k_weights<g>, dim3(blocks_for((long long)n * g)), dim3(kBlock), 0, s, n, rp, ci,
-                           v, diag, w, c, ws);
+                           v, diag, w, c, ws, lmin);
     });
 }
 
 // Rows of a few dozen entries compare directly; longer rows sort (k_rank +
-// k_candidates: O(d log d) per row instead of O(d^2)).
+// k_candidates: O(d log d) per row instead of O(d^2)).  part: 0 = all, 1 =
+// the own-row ranks only (sorted), 2 = the candidate lists only.
 void launch_candidates(hipStream_t s, int G, int n, bool sorted, const int *rp, const int *ci, const double *c,
-                       unsigned *rk, unsigned long long *cand) {
+                       unsigned *rk, unsigned long long *cand, int lmin, int part) {
     with_G(G, [&](auto gc) {
         constexpr int g = decltype(gc)::value;
         if (!sorted) {
-            hipLaunchKernelGGL(k_candidates_direct<g>, dim3(blocks_for((long long)n * g)), dim3(kBlock), 0, s, n, rp,
-                               ci, c, cand);
+            if (part != 1)
+                hipLaunchKernelGGL(k_candidates_direct<g>, dim3(blocks_for((long long)n * g)), dim3(kBlock), 0, s, n,
+                                   rp, ci, c, rk, cand, lmin);
             return;
         }
-        hipLaunchKernelGGL(k_rank<g>, dim3(blocks_for((long long)n * g)), dim3(kBlock), 0, s, n, rp, c, rk);
-        hipLaunchKernelGGL(k_candidates<g>, dim3(blocks_for((long long)n * g)), dim3(kBlock), 0, s, n, rp, ci, c,
-                           rk, cand);
+        if (part != 2)
+            hipLaunchKernelGGL(k_rank<g>, dim3(blocks_for((long long)n * g)), dim3(kBlock), 0, s, n, rp, c, rk, lmin);
+        if (part != 1)
+            hipLaunchKernelGGL(k_candidates<g>, dim3(blocks_for((long long)n * g)), dim3(kBlock), 0, s, n, rp, ci, c,
+                               rk, cand, lmin);
     });
 }
 
 void launch_suitor(hipStream_t s, int n, const int *rp, const unsigned long long *cand, unsigned long long *ws) {
-    hipLaunchKernelGGL(k_suitor, dim3(blocks_for(n)), dim3(kBlock), 0, s, n, rp, cand, ws);
+    launch_k(k_suitor, dim3(blocks_for(n)), dim3(kBlock), s, n, rp, cand, ws);
 }
 
 void launch_mate(hipStream_t s, int n, const int *rp, const int *ci, const unsigned long long *ws, int *mate,
@@ -847,7 +1303,7 @@ __global__ void __launch_bounds__(kBlock)
 k_gal(int pass, int nc, const int *__restrict__ rp, const int *__restrict__ ci,
       const double *__restrict__ v, const int *__restrict__ agg, const double *__restrict__ p,
       const int *__restrict__ mem2, int *__restrict__ cnt, const int *__restrict__ crp,
-      int *__restrict__ cci, double *__restrict__ cv, int *__restrict__ gF, int *__restrict__ gU) {
+      int *__restrict__ cci, double *__restrict__ cv, int *__restrict__ gF, int *__restrict__ gU, int lmin) {
     constexpr int SL = 4;  // candidate slots per lane
     constexpr int LS = SL * G;
     constexpr int NG = kBlock / G;
@@ -863,6 +1319,7 @@ k_gal(int pass, int nc, const int *__restrict__ rp, const int *__restrict__ ci,
     const int s1 = e1 >= 0 ? rp[e1] : 0;
     const int L1 = e1 >= 0 ? rp[e1 + 1] - s1 : 0;
     const int L = L0 + L1;
+    if (lmin > 0 && L > lmin) return;  // a long coarse row: k_gal_long
     if (L > LS) {
         gal_row<G>(pass, E, lane, rp, ci, v, agg, p, e0, e1, s0, L0, s1, L1, cnt, crp, cci, cv, gF, gU, false);
         return;
@@ -950,7 +1407,7 @@ __global__ void __launch_bounds__(kBlock)
 k_gal_sorted(int pass, int nc, const int *__restrict__ rp, const int *__restrict__ ci,
              const double *__restrict__ v, const int *__restrict__ agg, const double *__restrict__ p,
              const int *__restrict__ mem2, int *__restrict__ cnt, const int *__restrict__ crp,
-             int *__restrict__ cci, double *__restrict__ cv, int *__restrict__ gF, int *__restrict__ gU) {
+             int *__restrict__ cci, double *__restrict__ cv, int *__restrict__ gF, int *__restrict__ gU, int lmin) {
     constexpr int LMAX = 16 * G;
     constexpr int NG = kBlock / G;
     __shared__ unsigned long long sk[NG * LMAX];
@@ -962,6 +1419,7 @@ k_gal_sorted(int pass, int nc, const int *__restrict__ rp, const int *__restrict
     const int s1 = e1 >= 0 ? rp[e1] : 0;
     const int L1 = e1 >= 0 ? rp[e1 + 1] - s1 : 0;
     const int L = L0 + L1;
+    if (lmin > 0 && L > lmin) return;  // a long coarse row: k_gal_long
     if (L > LMAX) {  // more candidates than LDS slots: k_gal's scratch path
         gal_row<G>(pass, E, lane, rp, ci, v, agg, p, e0, e1, s0, L0, s1, L1, cnt, crp, cci, cv, gF, gU, false);
         return;
@@ -1031,29 +1489,29 @@ k_gal_sorted(int pass, int nc, const int *__restrict__ rp, const int *__restrict
 }
 
 void launch_gal_count(hipStream_t s, int G, int nc, const int *rp, const int *ci, const int *agg,
-                      const int *mem2, int *cnt, int *gF, int *gU, bool sorted) {
+                      const int *mem2, int *cnt, int *gF, int *gU, bool sorted, int lmin) {
     with_G(G, [&](auto gc) {
         constexpr int g = decltype(gc)::value;
         if (sorted)
             hipLaunchKernelGGL(k_gal_sorted<g>, dim3(blocks_for((long long)nc * g)), dim3(kBlock), 0, s, 0, nc, rp, ci,
-                               nullptr, agg, nullptr, mem2, cnt, nullptr, nullptr, nullptr, gF, gU);
+                               nullptr, agg, nullptr, mem2, cnt, nullptr, nullptr, nullptr, gF, gU, lmin);
         else
             hipLaunchKernelGGL(k_gal<g>, dim3(blocks_for((long long)nc * g)), dim3(kBlock), 0, s, 0, nc, rp, ci,
-                               nullptr, agg, nullptr, mem2, cnt, nullptr, nullptr, nullptr, gF, gU);
+                               nullptr, agg, nullptr, mem2, cnt, nullptr, nullptr, nullptr, gF, gU, lmin);
     });
 }
 
 void launch_gal_fill(hipStream_t s, int G, int nc, const int *rp, const int *ci, const double *v,
                      const int *agg, const double *p, const int *mem2, const int *crp, int *cci,
-                     double *cv, int *gF, int *gU, bool sorted) {
+                     double *cv, int *gF, int *gU, bool sorted, int lmin) {
     with_G(G, [&](auto gc) {
         constexpr int g = decltype(gc)::value;
         if (sorted)
             hipLaunchKernelGGL(k_gal_sorted<g>, dim3(blocks_for((long long)nc * g)), dim3(kBlock), 0, s, 1, nc, rp, ci,
-                               v, agg, p, mem2, nullptr, crp, cci, cv, gF, gU);
+                               v, agg, p, mem2, nullptr, crp, cci, cv, gF, gU, lmin);
         else
             hipLaunchKernelGGL(k_gal<g>, dim3(blocks_for((long long)nc * g)), dim3(kBlock), 0, s, 1, nc, rp, ci, v,
-                               agg, p, mem2, nullptr, crp, cci, cv, gF, gU);
+                               agg, p, mem2, nullptr, crp, cci, cv, gF, gU, lmin);
     });
 }
 
@@ -1067,11 +1525,11 @@ void launch_compose(hipStream_t s, int n, int nc_new, const int *agg_prev, const
 }
 
 void launch_diag_l1(hipStream_t s, int G, int n, const int *rp, const double *v, double *dinv,
-                    float *dinv32, float *v32) {
+                    float *dinv32, float *v32, const LongRows &lr, const double *part) {
     with_G(G, [&](auto gc) {
         constexpr int g = decltype(gc)::value;
         hipLaunchKernelGGL(k_diag_l1<g>, dim3(blocks_for((long long)n * g)), dim3(kBlock), 0, s, n, rp, v, dinv,
-                           dinv32, v32);
+                           dinv32, v32, lr, part);
     });
 }
 
@@ -1102,6 +1560,78 @@ void launch_fill_i32(hipStream_t s, size_t n, int *dst, int val) {
 
 void launch_fill_u64(hipStream_t s, size_t n, unsigned long long *dst, unsigned long long val) {
     hipLaunchKernelGGL(k_fill_u64, dim3(stream_grid(n)), dim3(kBlock), 0, s, n, dst, val);
+}
+
+// Grid of the grid-stride long-segment kernels (their counts are on the device).
+constexpr int kSegGrid = 1024;
+
+void launch_find_long(hipStream_t s, int n, const int *rp, int lmin, const SegList &seg, int *idx) {
+    hipLaunchKernelGGL(k_find_long, dim3(blocks_for(n)), dim3(kBlock), 0, s, n, rp, lmin, seg, idx);
+}
+
+void launch_find_long_gal(hipStream_t s, int nc, const int *mem2, const int *rp, int lmin, const SegList &seg) {
+    hipLaunchKernelGGL(k_find_long_gal, dim3(blocks_for(nc)), dim3(kBlock), 0, s, nc, mem2, rp, lmin, seg);
+}
+
+void launch_seg_fix(hipStream_t s, const SegList &seg) {
+    hipLaunchKernelGGL(k_seg_fix, dim3(1), dim3(kSegBlock), 0, s, seg);
+}
+
+void launch_long_validate(hipStream_t s, int n, int nnz, const int *rp, const int *ci, const double *v,
+                          int check_sym, const SegList &seg, int *flags) {
+    hipLaunchKernelGGL(k_long_validate, dim3(kSegGrid), dim3(kBlock), 0, s, n, nnz, rp, ci, v, check_sym, seg, flags);
+}
+
+void launch_long_weights(hipStream_t s, const SegList &seg, const int *rp, const int *ci, const double *v,
+                         const double *diag, const double *w, double *c) {
+    hipLaunchKernelGGL(k_long_weights, dim3(kSegGrid), dim3(kBlock), 0, s, seg, rp, ci, v, diag, w, c);
+}
+
+namespace {
+// Chunk sort, then merge passes until runs cover maxlen; returns the buffer
+// holding the sorted segments (k0 or k1).
+template <typename Key>
+unsigned long long *seg_sort(hipStream_t s, const SegList &seg, int maxlen, Key key, unsigned long long *k0,
+                             unsigned long long *k1) {
+    hipLaunchKernelGGL((k_seg_sort_chunks<Key>), dim3(kSegGrid), dim3(kBlock), 0, s, seg, key, k0);
+    for (long long run = kSegChunk; run < maxlen; run *= 2) {
+        hipLaunchKernelGGL(k_seg_merge, dim3(kSegGrid), dim3(kBlock), 0, s, seg, (int)run, k0, k1);
+        std::swap(k0, k1);
+    }
+    return k0;
+}
+}  // namespace
+
+void launch_long_ranks(hipStream_t s, const SegList &seg, int maxlen, const int *rp, const double *c,
+                       unsigned *rk, unsigned long long *k0, unsigned long long *k1) {
+    unsigned long long *sorted = seg_sort(s, seg, maxlen, KeyRank{rp, c}, k0, k1);
+    hipLaunchKernelGGL(k_long_rank, dim3(kSegGrid), dim3(kBlock), 0, s, seg, sorted, rp, c, rk);
+}
+
+void launch_long_candidates(hipStream_t s, const SegList &seg, int maxlen, const int *rp, const int *ci,
+                            const double *c, const unsigned *rk, int lmin, bool direct, unsigned long long *cand,
+                            unsigned long long *k0, unsigned long long *k1) {
+    unsigned long long *sorted = seg_sort(s, seg, maxlen, KeyCand{rp, ci, c, rk}, k0, k1);
+    hipLaunchKernelGGL(k_long_cand, dim3(kSegGrid), dim3(kBlock), 0, s, seg, sorted, rp, ci, c, rk, lmin,
+                       direct ? 1 : 0, cand);
+}
+
+void launch_gal_long_sort(hipStream_t s, const SegList &seg, int maxlen, const int *rp, const int *ci,
+                          const int *agg, const int *mem2, unsigned long long *k0, unsigned long long *k1,
+                          unsigned long long **sorted) {
+    *sorted = seg_sort(s, seg, maxlen, KeyGal{rp, ci, agg, mem2}, k0, k1);
+}
+
+void launch_gal_long(hipStream_t s, int pass, const SegList &seg, const unsigned long long *sorted, const int *rp,
+                     const int *ci, const double *v, const int *agg, const double *p, const int *mem2, int *cnt,
+                     const int *crp, int *cci, double *cv) {
+    hipLaunchKernelGGL(k_gal_long, dim3(256), dim3(kSegBlock), 0, s, pass, seg, sorted, rp, ci, v, agg, p, mem2, cnt,
+                       crp, cci, cv);
+}
+
+void launch_long_abs(hipStream_t s, const LongRows &lr, const int *rp, const double *v, double *part, float *v32) {
+    if (lr.nchunks > 0)
+        hipLaunchKernelGGL(k_long_abs, dim3(lr.nchunks), dim3(kBlock), 0, s, lr, rp, v, part, v32);
 }
 
 }  // namespace bcm

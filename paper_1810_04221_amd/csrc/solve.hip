@@ -54,23 +54,124 @@ void with_sell(const Sell &E, Fn &&fn) {
     }
 }
 
+// ----------------------------------------------------------------------------
+// Long rows (longer than the level's lmin = kLongFactor * G): their dot
+// products are summed by a pre-pass over chunks of kSegChunk entries, one
+// workgroup per chunk (k_long_dot, with the same gathered operand f as the row
+// kernel that follows it), and the row kernel adds the chunk sums of such a
+// row in chunk order across its group instead of walking the row.
+// ----------------------------------------------------------------------------
+template <typename V>
+struct LongView {
+    int lmin = 0x7fffffff;  // no row is longer: the level has no long rows
+    const int *idx = nullptr, *cb = nullptr;
+    const V *part = nullptr;
+};
+
+template <typename V>
+LongView<V> long_view(const LongRows &lr) {
+    LongView<V> v;
+    if (lr.n > 0) {
+        v.lmin = lr.lmin;
+        v.idx = lr.idx;
+        v.cb = lr.cb;
+        v.part = static_cast<const V *>(lr.part);
+    }
+    return v;
+}
+
+// the dot product of long row `row` from its chunk sums (every lane of the group gets it)
+template <int G, typename V>
+__device__ __forceinline__ V long_sum(const LongView<V> &lv, int row) {
+    const int lane = threadIdx.x % G, t = lv.idx[row];
+    V s = V(0);
+    for (int c = lv.cb[t] + lane; c < lv.cb[t + 1]; c += G) s += lv.part[c];
+    return group_sum<G>(s);
+}
+
+// largest t in [0, cnt) with base[t] <= x (base strictly ascending, base[0] = 0)
+__device__ __forceinline__ int chunk_owner(const int *__restrict__ base, int cnt, int x) {
+    int lo = 0, hi = cnt - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (base[mid] <= x) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Chunk c of the long rows: part[c] = sum of a_q f(ci[q]) over its entries,
+// eight per thread (all loads issued first), then the workgroup in a fixed order.
+template <typename V, typename F>
+__global__ void __launch_bounds__(kBlock)
+k_long_dot(LongRows lr, const int *__restrict__ rp, const int *__restrict__ ci, const V *__restrict__ a, F f,
+           V *__restrict__ part, const double *__restrict__ done) {
+    if (done && *done != 0.0) return;
+    constexpr int U = kSegChunk / kBlock;
+    const int c = blockIdx.x;
+    const int t = chunk_owner(lr.cb, lr.n, c);
+    const int row = lr.rows[t];
+    const int q0 = rp[row] + (c - lr.cb[t]) * kSegChunk, q1 = min(q0 + kSegChunk, rp[row + 1]);
+    int j[U];
+    V av[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int q = q0 + (int)threadIdx.x + u * kBlock;
+        const bool in = q < q1;
+        j[u] = in ? ci[q] : row;
+        av[u] = in ? a[q] : V(0);
+    }
+    V s = V(0);
+#pragma unroll
+    for (int u = 0; u < U; ++u) s += av[u] * f(j[u]);
+    double d[1] = {(double)s};
+    __shared__ double lds[16];
+    block_sum<1>(d, lds);
+    if (threadIdx.x == 0) part[c] = (V)d[0];
+}
+
+// Gathered operands of the row kernels (one rounding per operation, as the
+// row kernels' own expressions).
+template <typename V, typename VB>
+struct FScaled {  // the pre-smoothed iterate from zero: dinv_j b_j
+    const V *dinv;
+    const VB *b;
+    __device__ V operator()(int j) const { return dinv[j] * (V)b[j]; }
+};
+template <typename V, typename VB>
+struct FProlonged {  // pre-smoothed iterate plus the coarse correction: dinv_j b_j + p_j xc[agg_j]
+    const V *dinv, *p;
+    const int *agg;
+    const VB *b;
+    const V *xc;
+    __device__ V operator()(int j) const { return dinv[j] * (V)b[j] + p[j] * xc[agg[j]]; }
+};
+template <typename V, typename T>
+struct FGather {  // a vector entry
+    const T *x;
+    __device__ V operator()(int j) const { return (V)x[j]; }
+};
+
 // R rows per group of G lanes.  All loads of the first pass over the R rows
 // are issued before any result is used (out-of-row lanes read entry beg[k] and
 // discard it), which keeps R times more memory requests in flight per lane than
-// one row at a time.  Rows longer than G finish in a second loop.
+// one row at a time.  Rows longer than G finish in a second loop; rows longer
+// than lv.lmin take their chunk sums instead.
 // s[k] = sum_q a[q] * f(ci[q]) over row rows[k] (rows[k] < 0: empty).
 template <int G, int R, typename V, typename F>
 __device__ __forceinline__ void rows_dot(const int *__restrict__ rp, const int *__restrict__ ci,
-                                         const V *__restrict__ a, const int (&rows)[R], V (&s)[R], F f) {
+                                         const V *__restrict__ a, const int (&rows)[R], V (&s)[R], F f,
+                                         const LongView<V> &lv = LongView<V>()) {
     const int lane = threadIdx.x % G;
     int beg[R], end[R];
+    bool lg[R];
 #pragma unroll
     for (int k = 0; k < R; ++k) {
         // both bounds loaded unconditionally: no branch between the R rows' loads
         const int i = rows[k] < 0 ? 0 : rows[k];
         const int b0 = rp[i], b1 = rp[i + 1];
+        lg[k] = rows[k] >= 0 && b1 - b0 > lv.lmin;
         beg[k] = b0;
-        end[k] = rows[k] < 0 ? b0 : b1;
+        end[k] = (rows[k] < 0 || lg[k]) ? b0 : b1;
     }
 #pragma unroll
     for (int k = 0; k < R; ++k) {
@@ -86,6 +187,9 @@ __device__ __forceinline__ void rows_dot(const int *__restrict__ rp, const int *
         for (int q = beg[k] + lane + G; q < end[k]; q += G) s[k] += a[q] * f(ci[q]);
 #pragma unroll
     for (int k = 0; k < R; ++k) s[k] = group_sum<G>(s[k]);
+#pragma unroll
+    for (int k = 0; k < R; ++k)
+        if (lg[k]) s[k] = long_sum<G>(lv, rows[k]);
 }
 
 
@@ -105,7 +209,7 @@ template <int G, int S, typename V, typename VB>
 __global__ void __launch_bounds__(kBlock)
 k_down_seq(int nc, const int *__restrict__ mem, const int *__restrict__ rp, const int *__restrict__ ci,
            const V *__restrict__ a, const V *__restrict__ dinv, const V *__restrict__ p,
-           const VB *__restrict__ b, V *__restrict__ bc, const double *__restrict__ done) {
+           const VB *__restrict__ b, V *__restrict__ bc, const double *__restrict__ done, LongView<V> lv) {
     // small levels: the solve-ended flag is only tested before the store, so
     // its load overlaps the row loads instead of preceding them
     const int lane = threadIdx.x % G;
@@ -116,7 +220,7 @@ k_down_seq(int nc, const int *__restrict__ mem, const int *__restrict__ rp, cons
 #pragma unroll
     for (int t = 0; t < S; ++t) rows[t] = mem[(size_t)E * S + t];
     V s[S];
-    rows_dot<G, S, V>(rp, ci, a, rows, s, [&](int j) { return dinv[j] * (V)b[j]; });
+    rows_dot<G, S, V>(rp, ci, a, rows, s, FScaled<V, VB>{dinv, b}, lv);
     V acc = V(0);
 #pragma unroll
     for (int t = 0; t < S; ++t) {
@@ -133,22 +237,24 @@ __global__ void __launch_bounds__(kBlock)
 k_down_loop(int nc, int mstride, const int *__restrict__ mem, const int *__restrict__ rp,
             const int *__restrict__ ci, const V *__restrict__ a, const V *__restrict__ dinv,
             const V *__restrict__ p, const VB *__restrict__ b, V *__restrict__ bc,
-            const double *__restrict__ done) {
+            const double *__restrict__ done, LongView<V> lv) {
     if (done && *done != 0.0) return;
     const int lane = threadIdx.x % G;
     const int E = (xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x) / G;
     if (E >= nc) return;
+    const FScaled<V, VB> f{dinv, b};
     V acc = V(0);
     for (int t = 0; t < mstride; ++t) {
         const int i = mem[(size_t)E * mstride + t];
         if (i < 0) break;
         V s = V(0);
-        const int e = rp[i + 1];
-        for (int q = rp[i] + lane; q < e; q += G) {
-            const int j = ci[q];
-            s += a[q] * (dinv[j] * (V)b[j]);
+        const int bq = rp[i], e = rp[i + 1];
+        if (e - bq > lv.lmin) {
+            s = long_sum<G>(lv, i);
+        } else {
+            for (int q = bq + lane; q < e; q += G) s += a[q] * f(ci[q]);
+            s = group_sum<G>(s);
         }
-        s = group_sum<G>(s);
         acc += p[i] * ((V)b[i] - s);
     }
     if (lane == 0) bc[E] = acc;
@@ -192,7 +298,8 @@ template <int G, int R, typename V, typename VB, typename VX>
 __global__ void __launch_bounds__(kBlock)
 k_up(int n, const int *__restrict__ rp, const int *__restrict__ ci, const V *__restrict__ a,
      const V *__restrict__ dinv, const V *__restrict__ p, const int *__restrict__ agg,
-     const VB *__restrict__ b, const V *__restrict__ xc, VX *__restrict__ x, const double *__restrict__ done) {
+     const VB *__restrict__ b, const V *__restrict__ xc, VX *__restrict__ x, const double *__restrict__ done,
+     LongView<V> lv) {
     // the solve-ended flag is tested before the stores only (as in k_down_seq)
     constexpr int NG = kBlock / G;
     const int lane = threadIdx.x % G;
@@ -201,7 +308,7 @@ k_up(int n, const int *__restrict__ rp, const int *__restrict__ ci, const V *__r
 #pragma unroll
     for (int k = 0; k < R; ++k) rows[k] = base + k * NG < n ? base + k * NG : -1;
     V s[R];
-    rows_dot<G, R, V>(rp, ci, a, rows, s, [&](int j) { return dinv[j] * (V)b[j] + p[j] * xc[agg[j]]; });
+    rows_dot<G, R, V>(rp, ci, a, rows, s, FProlonged<V, VB>{dinv, p, agg, b, xc}, lv);
     if (lane == 0 && !(done && *done != 0.0)) {
 #pragma unroll
         for (int k = 0; k < R; ++k) {
@@ -233,7 +340,7 @@ template <int G, int R, typename V, typename VB, typename VX>
 __global__ void __launch_bounds__(kBlock)
 k_smooth(int n, const int *__restrict__ rp, const int *__restrict__ ci, const V *__restrict__ a,
          const V *__restrict__ dinv, const VB *__restrict__ b, const V *__restrict__ xp, VX *__restrict__ x,
-         const double *__restrict__ done) {
+         const double *__restrict__ done, LongView<V> lv) {
     if (done && *done != 0.0) return;
     constexpr int NG = kBlock / G;
     const int lane = threadIdx.x % G;
@@ -242,7 +349,7 @@ k_smooth(int n, const int *__restrict__ rp, const int *__restrict__ ci, const V 
 #pragma unroll
     for (int k = 0; k < R; ++k) rows[k] = base + k * NG < n ? base + k * NG : -1;
     V s[R];
-    rows_dot<G, R, V>(rp, ci, a, rows, s, [&](int j) { return xp[j]; });
+    rows_dot<G, R, V>(rp, ci, a, rows, s, FGather<V, V>{xp}, lv);
     // lane k of the group finishes row k
 #pragma unroll
     for (int k = 0; k < R; ++k) {
@@ -257,15 +364,19 @@ k_smooth(int n, const int *__restrict__ rp, const int *__restrict__ ci, const V 
 template <int G, typename V>
 __global__ void __launch_bounds__(kBlock)
 k_resid_inplace(int n, const int *__restrict__ rp, const int *__restrict__ ci, const V *__restrict__ a,
-                const V *__restrict__ x, V *__restrict__ b, const double *__restrict__ done) {
+                const V *__restrict__ x, V *__restrict__ b, const double *__restrict__ done, LongView<V> lv) {
     if (done && *done != 0.0) return;
     const int lane = threadIdx.x % G;
     const int i = (xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x) / G;
     if (i >= n) return;
     V s = V(0);
-    const int e = rp[i + 1];
-    for (int q = rp[i] + lane; q < e; q += G) s += a[q] * x[ci[q]];
-    s = group_sum<G>(s);
+    const int bq = rp[i], e = rp[i + 1];
+    if (e - bq > lv.lmin) {
+        s = long_sum<G>(lv, i);
+    } else {
+        for (int q = bq + lane; q < e; q += G) s += a[q] * x[ci[q]];
+        s = group_sum<G>(s);
+    }
     if (lane == 0) b[i] = b[i] - s;
 }
 
@@ -297,7 +408,7 @@ template <int G, typename V, int STEP>
 __global__ void __launch_bounds__(kBlock)
 k_kdots(int n, const int *__restrict__ rp, const int *__restrict__ ci, const V *__restrict__ a,
         const V *__restrict__ c, const V *__restrict__ b, const V *__restrict__ vin, V *__restrict__ vout,
-        double *__restrict__ partials, const double *__restrict__ done) {
+        double *__restrict__ partials, const double *__restrict__ done, LongView<V> lv) {
     if (done && *done != 0.0) return;
     constexpr int K = STEP == 1 ? 2 : 3;
     double acc[K];
@@ -307,9 +418,13 @@ k_kdots(int n, const int *__restrict__ rp, const int *__restrict__ ci, const V *
     const int rows_per_grid = gridDim.x * (kBlock / G);
     for (int i = (xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x) / G; i < n; i += rows_per_grid) {
         V s = V(0);
-        const int e = rp[i + 1];
-        for (int q = rp[i] + lane; q < e; q += G) s += a[q] * c[ci[q]];
-        s = group_sum<G>(s);
+        const int bq = rp[i], e = rp[i + 1];
+        if (e - bq > lv.lmin) {
+            s = long_sum<G>(lv, i);
+        } else {
+            for (int q = bq + lane; q < e; q += G) s += a[q] * c[ci[q]];
+            s = group_sum<G>(s);
+        }
         if (lane == 0) {
             const double ci_ = (double)c[i];
             if (STEP == 1) {
@@ -400,8 +515,9 @@ constexpr int kCoarseLdsBytes = 65536;
 
 // The coarsest level is solved inside one workgroup when its matrix, inverse
 // diagonal and iterate fit that workgroup's LDS; otherwise one launch per sweep.
-bool coarse_in_lds(int n, int nnz) {
-    return n <= kCoarseLds && (size_t)n * 16 + (size_t)nnz * 12 + (size_t)(n + 1) * 4 <= (size_t)kCoarseLdsBytes;
+bool coarse_in_lds(int n, int nnz, bool long_rows) {
+    return !long_rows && n <= kCoarseLds &&
+           (size_t)n * 16 + (size_t)nnz * 12 + (size_t)(n + 1) * 4 <= (size_t)kCoarseLdsBytes;
 }
 
 namespace {
@@ -687,7 +803,8 @@ template <int G, int R, typename VB, typename VX>
 __global__ void __launch_bounds__(kBlock)
 k_jacobi_sweep(int n, const int *__restrict__ rp, const int *__restrict__ ci, const double *__restrict__ a,
                const double *__restrict__ dinv, const VB *__restrict__ b, const double *__restrict__ xo,
-               double *__restrict__ xn, VX *__restrict__ xout, int first, const double *__restrict__ done) {
+               double *__restrict__ xn, VX *__restrict__ xout, int first, const double *__restrict__ done,
+               LongView<double> lv) {
     const int lane = threadIdx.x % G;
     const int g = (xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x) / G;
     int rows[R];
@@ -698,7 +815,7 @@ k_jacobi_sweep(int n, const int *__restrict__ rp, const int *__restrict__ ci, co
 #pragma unroll
         for (int k = 0; k < R; ++k) s[k] = 0.0;
     } else {
-        rows_dot<G, R, double>(rp, ci, a, rows, s, [&](int j) { return xo[j]; });
+        rows_dot<G, R, double>(rp, ci, a, rows, s, FGather<double, double>{xo}, lv);
     }
     const bool live = !(done && *done != 0.0);
 #pragma unroll
@@ -727,7 +844,7 @@ template <int G>
 __global__ void __launch_bounds__(kBlock)
 k_resid(int n, const int *__restrict__ rp, const int *__restrict__ ci, const double *__restrict__ a,
         const double *__restrict__ b, const double *__restrict__ u, double *__restrict__ r,
-        double *__restrict__ partials) {
+        double *__restrict__ partials, LongView<double> lv) {
     constexpr int NG = kBlock / G, R = kRows;
     const int lane = threadIdx.x % G;
     const int blk = xcd_block(blockIdx.x, gridDim.x);
@@ -737,7 +854,7 @@ k_resid(int n, const int *__restrict__ rp, const int *__restrict__ ci, const dou
 #pragma unroll
         for (int k = 0; k < R; ++k) rows[k] = base + k * NG < n ? base + k * NG : -1;
         double s[R];
-        rows_dot<G, R, double>(rp, ci, a, rows, s, [&](int j) { return u[j]; });
+        rows_dot<G, R, double>(rp, ci, a, rows, s, FGather<double, double>{u}, lv);
         if (lane == 0) {
 #pragma unroll
             for (int k = 0; k < R; ++k) {
@@ -758,7 +875,8 @@ template <int G>
 __global__ void __launch_bounds__(kBlock)
 k_spmv_dots(int n, const int *__restrict__ rp, const int *__restrict__ ci, const double *__restrict__ a,
             const double *__restrict__ w, const double *__restrict__ r, const double *__restrict__ q,
-            double *__restrict__ v, double *__restrict__ partials, const double *__restrict__ done) {
+            double *__restrict__ v, double *__restrict__ partials, const double *__restrict__ done,
+            LongView<double> lv) {
     if (done && *done != 0.0) return;
     constexpr int NG = kBlock / G, R = kRows;
     const int lane = threadIdx.x % G;
@@ -769,7 +887,7 @@ k_spmv_dots(int n, const int *__restrict__ rp, const int *__restrict__ ci, const
 #pragma unroll
         for (int k = 0; k < R; ++k) rows[k] = base + k * NG < n ? base + k * NG : -1;
         double s[R];
-        rows_dot<G, R, double>(rp, ci, a, rows, s, [&](int j) { return w[j]; });
+        rows_dot<G, R, double>(rp, ci, a, rows, s, FGather<double, double>{w}, lv);
         if (lane == 0) {
 #pragma unroll
             for (int k = 0; k < R; ++k) {
@@ -841,7 +959,8 @@ __global__ void __launch_bounds__(kBlock) k_finalize(int nb, const double *__res
 template <int G, int R>
 __global__ void __launch_bounds__(kBlock)
 k_sampled_outer(int n, const int *__restrict__ rp, const int *__restrict__ ci, const double *__restrict__ lam,
-                const double *__restrict__ x, double *__restrict__ out) {
+                const double *__restrict__ x, double *__restrict__ out, int lmin) {
+    // rows longer than lmin are written by k_long_outer
     constexpr int NG = kBlock / G;
     const int lane = threadIdx.x % G;
     const int base = xcd_block(blockIdx.x, gridDim.x) * NG * R + threadIdx.x / G;
@@ -852,7 +971,8 @@ k_sampled_outer(int n, const int *__restrict__ rp, const int *__restrict__ ci, c
         const int i = base + k * NG;
         const int ic = i < n ? i : 0;
         beg[k] = rp[ic];
-        end[k] = i < n ? rp[ic + 1] : beg[k];
+        const int e = rp[ic + 1];
+        end[k] = (i < n && e - beg[k] <= lmin) ? e : beg[k];
         li[k] = lam[ic];
     }
     int j[R];
@@ -869,22 +989,44 @@ k_sampled_outer(int n, const int *__restrict__ rp, const int *__restrict__ ci, c
         for (int q = beg[k] + lane + G; q < end[k]; q += G) out[q] = -(li[k] * x[ci[q]]);
 }
 
+// The long rows of the sampled outer product, chunk by chunk.
+__global__ void __launch_bounds__(kBlock)
+k_long_outer(LongRows lr, const int *__restrict__ rp, const int *__restrict__ ci, const double *__restrict__ lam,
+             const double *__restrict__ x, double *__restrict__ out) {
+    const int c = blockIdx.x;
+    const int t = chunk_owner(lr.cb, lr.n, c);
+    const int row = lr.rows[t];
+    const int q0 = rp[row] + (c - lr.cb[t]) * kSegChunk, q1 = min(q0 + kSegChunk, rp[row + 1]);
+    const double li = lam[row];
+    for (int q = q0 + threadIdx.x; q < q1; q += kBlock) out[q] = -(li * x[ci[q]]);
+}
+
+// The chunk sums of level L's long rows for a row kernel with operand f.
+template <typename V, typename F>
+void long_pre(hipStream_t s, const Level &L, const V *a, F f, const double *done) {
+    if (L.lr.n > 0)
+        hipLaunchKernelGGL((k_long_dot<V, F>), dim3(L.lr.nchunks), dim3(kBlock), 0, s, L.lr, L.A.rp, L.A.ci, a, f,
+                           static_cast<V *>(L.lr.part), done);
+}
+
 template <int G, typename V, typename VB>
 void down_dispatch(hipStream_t s, const Level &L, const V *a, const V *dinv, const V *p, const VB *b, V *bc,
                    const double *done) {
     const int S = L.mstride;
     const dim3 grid(blocks_for((long long)L.nc * G));
+    const LongView<V> lv = long_view<V>(L.lr);
+    long_pre(s, L, a, FScaled<V, VB>{dinv, b}, done);
     auto seq = [&](auto sc) {
         constexpr int SS = decltype(sc)::value;
         launch_k((k_down_seq<G, SS, V, VB>), grid, dim3(kBlock), s, L.nc, L.mem, L.A.rp, L.A.ci, a,
-                           dinv, p, b, bc, done);
+                           dinv, p, b, bc, done, lv);
     };
     if (S == 1) seq(std::integral_constant<int, 1>{});
     else if (S == 2) seq(std::integral_constant<int, 2>{});
     else if (S == 4) seq(std::integral_constant<int, 4>{});
     else
         launch_k((k_down_loop<G, V, VB>), grid, dim3(kBlock), s, L.nc, L.mstride, L.mem, L.A.rp,
-                           L.A.ci, a, dinv, p, b, bc, done);
+                           L.A.ci, a, dinv, p, b, bc, done, lv);
 }
 
 // part: 0 = the whole leg, 1 = its first kernel, 2 = its second kernel (a
@@ -940,20 +1082,23 @@ void up_t(hipStream_t s, const Level &L, const V *a, const V *dinv, const V *p, 
             });
             return;
         }
+        long_pre(s, L, a, FGather<V, V>{xp}, done);
         with_G(L.G, [&](auto gc) {
             constexpr int g = decltype(gc)::value;
             constexpr int R = 2;
             launch_k((k_smooth<g, R, V, VB, VX>), dim3(blocks_for(((long long)L.A.n * g + R - 1) / R)),
-                               dim3(kBlock), s, L.A.n, L.A.rp, L.A.ci, a, dinv, b, xp, x, done);
+                               dim3(kBlock), s, L.A.n, L.A.rp, L.A.ci, a, dinv, b, xp, x, done, long_view<V>(L.lr));
         });
         return;
     }
     if (part == 1) return;
+    long_pre(s, L, a, FProlonged<V, VB>{dinv, p, L.agg, b, xc}, done);
     with_G(L.G, [&](auto gc) {
         constexpr int g = decltype(gc)::value;
         constexpr int R = 2;
         launch_k((k_up<g, R, V, VB, VX>), dim3(blocks_for(((long long)L.A.n * g + R - 1) / R)),
-                           dim3(kBlock), s, L.A.n, L.A.rp, L.A.ci, a, dinv, p, L.agg, b, xc, x, done);
+                           dim3(kBlock), s, L.A.n, L.A.rp, L.A.ci, a, dinv, p, L.agg, b, xc, x, done,
+                           long_view<V>(L.lr));
     });
 }
 
@@ -965,7 +1110,7 @@ void coarse_t(hipStream_t s, const Level &L, int sweeps, const VB *b, VX *x, dou
         hipLaunchKernelGGL((k_coarse_dense<VB, VX>), dim3(n), dim3(kBlock), 0, s, n, L.S, b, x, done);
         return;
     }
-    if (coarse_in_lds(n, L.A.nnz)) {
+    if (coarse_in_lds(n, L.A.nnz, L.lr.n > 0)) {
         hipLaunchKernelGGL((k_coarse<VB, VX>), dim3(1), dim3(1024), 0, s, n, L.A.nnz, L.A.rp, L.A.ci, L.A.v, L.dinv,
                            b, x, sweeps, 0, done);
         return;
@@ -975,9 +1120,10 @@ void coarse_t(hipStream_t s, const Level &L, int sweeps, const VB *b, VX *x, dou
         constexpr int g = decltype(gc)::value;
         constexpr int R = 2;
         for (int t = 0; t < sweeps; ++t) {
+            if (t > 0) long_pre(s, L, (const double *)L.A.v, FGather<double, double>{xo}, done);
             hipLaunchKernelGGL((k_jacobi_sweep<g, R, VB, VX>), dim3(blocks_for(((long long)n + R - 1) / R * g)),
                                dim3(kBlock), 0, s, n, L.A.rp, L.A.ci, L.A.v, L.dinv, b, xo, xn,
-                               t == sweeps - 1 ? x : (VX *)nullptr, t == 0 ? 1 : 0, done);
+                               t == sweeps - 1 ? x : (VX *)nullptr, t == 0 ? 1 : 0, done, long_view<double>(L.lr));
             double *tmp = xo; xo = xn; xn = tmp;
         }
     });
@@ -1035,14 +1181,18 @@ void launch_tail(hipStream_t s, int fp32, int kt, int nl, const TailLevel *tl, c
 }
 
 void launch_resid_inplace(hipStream_t s, const Level &L, int fp32, const void *x, void *b, const double *done) {
+    if (fp32) long_pre(s, L, (const float *)L.A.v32, FGather<float, float>{(const float *)x}, done);
+    else long_pre(s, L, (const double *)L.A.v, FGather<double, double>{(const double *)x}, done);
     with_G(L.G, [&](auto gc) {
         constexpr int g = decltype(gc)::value;
         if (fp32)
             hipLaunchKernelGGL((k_resid_inplace<g, float>), dim3(blocks_for((long long)L.A.n * g)), dim3(kBlock), 0, s,
-                               L.A.n, L.A.rp, L.A.ci, L.A.v32, (const float *)x, (float *)b, done);
+                               L.A.n, L.A.rp, L.A.ci, L.A.v32, (const float *)x, (float *)b, done,
+                               long_view<float>(L.lr));
         else
             hipLaunchKernelGGL((k_resid_inplace<g, double>), dim3(blocks_for((long long)L.A.n * g)), dim3(kBlock), 0,
-                               s, L.A.n, L.A.rp, L.A.ci, L.A.v, (const double *)x, (double *)b, done);
+                               s, L.A.n, L.A.rp, L.A.ci, L.A.v, (const double *)x, (double *)b, done,
+                               long_view<double>(L.lr));
     });
 }
 
@@ -1065,16 +1215,18 @@ int kcycle_blocks(const Level &L) {
 void launch_kcycle_step1(hipStream_t s, const Level &C, int fp32, const void *c1, const void *b, void *v1,
                          double *partials, double *ks, const double *done) {
     const int nb = kcycle_blocks(C);
+    if (fp32) long_pre(s, C, (const float *)C.A.v32, FGather<float, float>{(const float *)c1}, done);
+    else long_pre(s, C, (const double *)C.A.v, FGather<double, double>{(const double *)c1}, done);
     with_G(C.G, [&](auto gc) {
         constexpr int g = decltype(gc)::value;
         if (fp32)
             hipLaunchKernelGGL((k_kdots<g, float, 1>), dim3(nb), dim3(kBlock), 0, s, C.A.n, C.A.rp, C.A.ci, C.A.v32,
                                (const float *)c1, (const float *)b, (const float *)nullptr, (float *)v1, partials,
-                               done);
+                               done, long_view<float>(C.lr));
         else
             hipLaunchKernelGGL((k_kdots<g, double, 1>), dim3(nb), dim3(kBlock), 0, s, C.A.n, C.A.rp, C.A.ci, C.A.v,
                                (const double *)c1, (const double *)b, (const double *)nullptr, (double *)v1,
-                               partials, done);
+                               partials, done, long_view<double>(C.lr));
     });
     hipLaunchKernelGGL(k_kfinal<1>, dim3(1), dim3(kBlock), 0, s, nb, partials, ks, done);
     if (fp32)
@@ -1088,16 +1240,18 @@ void launch_kcycle_step1(hipStream_t s, const Level &C, int fp32, const void *c1
 void launch_kcycle_step2(hipStream_t s, const Level &C, int fp32, const void *c2, const void *b, const void *v1,
                          void *x, double *partials, double *ks, const double *done) {
     const int nb = kcycle_blocks(C);
+    if (fp32) long_pre(s, C, (const float *)C.A.v32, FGather<float, float>{(const float *)c2}, done);
+    else long_pre(s, C, (const double *)C.A.v, FGather<double, double>{(const double *)c2}, done);
     with_G(C.G, [&](auto gc) {
         constexpr int g = decltype(gc)::value;
         if (fp32)
             hipLaunchKernelGGL((k_kdots<g, float, 2>), dim3(nb), dim3(kBlock), 0, s, C.A.n, C.A.rp, C.A.ci, C.A.v32,
                                (const float *)c2, (const float *)b, (const float *)v1, (float *)nullptr, partials,
-                               done);
+                               done, long_view<float>(C.lr));
         else
             hipLaunchKernelGGL((k_kdots<g, double, 2>), dim3(nb), dim3(kBlock), 0, s, C.A.n, C.A.rp, C.A.ci, C.A.v,
                                (const double *)c2, (const double *)b, (const double *)v1, (double *)nullptr,
-                               partials, done);
+                               partials, done, long_view<double>(C.lr));
     });
     hipLaunchKernelGGL(k_kfinal<2>, dim3(1), dim3(kBlock), 0, s, nb, partials, ks, done);
     if (fp32)
@@ -1154,10 +1308,11 @@ void launch_resid(hipStream_t s, const Level &L, int nb, const double *b, const 
         });
         return;
     }
+    long_pre(s, L, (const double *)L.A.v, FGather<double, double>{u}, nullptr);
     with_G(L.G, [&](auto gc) {
         constexpr int g = decltype(gc)::value;
         hipLaunchKernelGGL(k_resid<g>, dim3(nb), dim3(kBlock), 0, s, L.A.n, L.A.rp, L.A.ci, L.A.v, b, u, r,
-                           partials);
+                           partials, long_view<double>(L.lr));
     });
 }
 
@@ -1172,10 +1327,11 @@ void launch_spmv_dots(hipStream_t s, const Level &L, int nb, int first, const do
         });
         return;
     }
+    long_pre(s, L, (const double *)L.A.v, FGather<double, double>{w}, scal + 10);
     with_G(L.G, [&](auto gc) {
         constexpr int g = decltype(gc)::value;
         launch_k((k_spmv_dots<g>), dim3(nb), dim3(kBlock), s, L.A.n, L.A.rp, L.A.ci, L.A.v, w, r, q, v,
-                           partials, scal + 10);
+                           partials, scal + 10, long_view<double>(L.lr));
     });
 }
 
@@ -1195,8 +1351,11 @@ void launch_sampled_outer(hipStream_t s, const Level &L, const double *lam, cons
         constexpr int g = decltype(gc)::value;
         constexpr int R = 4;
         hipLaunchKernelGGL((k_sampled_outer<g, R>), dim3(blocks_for(((long long)L.A.n + R - 1) / R * g)),
-                           dim3(kBlock), 0, s, L.A.n, L.A.rp, L.A.ci, lam, x, G);
+                           dim3(kBlock), 0, s, L.A.n, L.A.rp, L.A.ci, lam, x, G,
+                           L.lr.n > 0 ? L.lr.lmin : 0x7fffffff);
     });
+    if (L.lr.n > 0)
+        hipLaunchKernelGGL(k_long_outer, dim3(L.lr.nchunks), dim3(kBlock), 0, s, L.lr, L.A.rp, L.A.ci, lam, x, G);
 }
 
 }  // namespace bcm

@@ -180,7 +180,14 @@ def elasticity3d(ne: int, seed: int, nu: float = 0.3, nu_soft: float = 0.45,
     n = 3 * nfree
     A = sp.coo_matrix((v[keep], (r[keep], c[keep])), shape=(n, n)).tocsr()
     A.sum_duplicates()
-    A = (A + A.T.tocsr()) * 0.5  # a_ij + a_ji is commutative: bitwise symmetric
+    A.sort_indices()
+    # (A + A^T) / 2 on A's own pattern, every structural entry kept -- also the
+    # couplings whose element contributions cancel to exactly 0 (scipy's sparse
+    # addition would drop them).  a_ij + a_ji is commutative: bitwise symmetric.
+    AT = A.T.tocsr()
+    AT.sort_indices()
+    assert np.array_equal(A.indptr, AT.indptr) and np.array_equal(A.indices, AT.indices)
+    A = sp.csr_matrix(((A.data + AT.data) * 0.5, A.indices.copy(), A.indptr.copy()), shape=(n, n))
     f = np.zeros(n)
     zdofs = gd[:, 2::3].ravel()
     zdofs = zdofs[zdofs >= 0]

@@ -83,8 +83,9 @@ def test_struct_layouts_match_c(tmp_path):
         + 'printf("\\n");\n'
         'printf("%zu %zu %zu %zu %zu\\n", sizeof(bcm_params), offsetof(bcm_params, adjoint_tol),'
         " offsetof(bcm_params, alloc), offsetof(bcm_params, stream), sizeof(bcm_csr));\n"
-        'printf("%zu %zu %zu %zu\\n", sizeof(bcm_info_t), offsetof(bcm_info_t, nnz),'
-        " offsetof(bcm_info_t, vcmplx), offsetof(bcm_info_t, iter_bytes));\n"
+        'printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(bcm_info_t), offsetof(bcm_info_t, nnz),'
+        " offsetof(bcm_info_t, vcmplx), offsetof(bcm_info_t, iter_bytes), offsetof(bcm_info_t, setup_bytes),"
+        " offsetof(bcm_info_t, long_rows));\n"
         "return 0;}\n")
     exe = tmp_path / "probe"
     subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(probe), "-o", str(exe)])
@@ -93,4 +94,6 @@ def test_struct_layouts_match_c(tmp_path):
     assert [int(t) for t in f.split()] == [getattr(P, name).offset for name, _ in P._fields_]
     assert [int(t) for t in a.split()] == [C.sizeof(P), P.adjoint_tol.offset, P.alloc.offset, P.stream.offset,
                                            C.sizeof(bcm.BcmCsr)]
-    assert [int(t) for t in b.split()] == [C.sizeof(I), I.nnz.offset, I.vcmplx.offset, I.iter_bytes.offset]
+    assert [int(t) for t in b.split()] == [C.sizeof(I), I.nnz.offset, I.vcmplx.offset, I.iter_bytes.offset,
+                                           I.setup_bytes.offset, I.long_rows.offset]
+

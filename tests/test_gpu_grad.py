@@ -135,3 +135,24 @@ def test_fp32_cycle_gradient_error(B):
     D = A.toarray()
     ld = np.linalg.solve(D, np.linalg.solve(D, c["b"]) - c["xstar"])
     assert np.linalg.norm(b.grad.cpu().numpy() - ld) <= 1e-8 * np.linalg.norm(ld)
+
+
+def test_autograd_rejects_values_the_hierarchy_was_not_built_from(B):
+    # the solve uses the hierarchy's copy of A: values changed after the
+    # setup (an optimiser step) must not be silently ignored
+    import torch
+    c = P.config("G5", 0.1)
+    say("autograd stale values")
+    val = torch.tensor(c["val"], dtype=torch.float64, device="cuda", requires_grad=True)
+    b = torch.tensor(c["b"], dtype=torch.float64, device="cuda")
+    h = B.Hierarchy(c["rowptr"], c["col"], val.detach(), max_coarse=c["max_coarse"])
+    x = B.solve(val, b, h, 1e-10)
+    x.sum().backward()
+    assert val.grad is not None and torch.isfinite(val.grad).all().item()
+    with torch.no_grad():
+        val.mul_(1.01)
+    with pytest.raises(ValueError):
+        B.solve(val, b, h, 1e-10)
+    h2 = B.Hierarchy(c["rowptr"], c["col"], val.detach(), max_coarse=c["max_coarse"])
+    x2 = B.solve(val, b, h2, 1e-10)
+    assert torch.allclose(x2 * 1.01, x.detach(), rtol=1e-6, atol=1e-12)

@@ -34,6 +34,17 @@ def _bits(a):
     return np.ascontiguousarray(a, dtype=np.float64).view(np.uint64)
 
 
+def _close_entries(z, zo, rtol):
+    # entry by entry: |z_i - zo_i| <= rtol (|zo_i| + mean |zo|).  The scale
+    # mean |zo| stands for the size of the terms a rounding error in entry i
+    # is relative to (the cycle mixes neighbouring entries at every level).
+    z, zo = np.asarray(z, dtype=np.float64), np.asarray(zo, dtype=np.float64)
+    bound = rtol * (np.abs(zo) + np.mean(np.abs(zo)))
+    err = np.abs(z - zo)
+    worst = int(np.argmax(err / bound))
+    assert np.all(err <= bound), f"entry {worst}: |dz| = {err[worst]:.3e} > bound {bound[worst]:.3e}"
+
+
 def _star(n):
     A = sp.lil_matrix((n, n))
     for j in range(1, n):
@@ -493,3 +504,84 @@ def test_graph_profiling_times_one_class(B, cls):
     # the eager first iteration plus at least one replay sample
     assert 2 <= launches <= hg.info()["iters"]
     assert ms > 0.0 and by > 0.0
+
+
+# ----------------------------------------------------------------------------- long (hub) rows
+def _hubs(n_leaf=60000, hubs=(0,), path=True, seed=3, frac=1.0):
+    # hub rows coupled to (a fraction of) all other rows with random weights,
+    # plus a path through the non-hub rows: rows far longer than any lane
+    # group's bound (the per-row kernels hand them to the long-row path)
+    rng = np.random.default_rng(seed)
+    n = n_leaf + len(hubs)
+    hub_set = set(hubs)
+    others = np.array([i for i in range(n) if i not in hub_set])
+    rows, cols, vals = [], [], []
+    for h in hubs:
+        nb = others if frac >= 1.0 else rng.choice(others, int(frac * len(others)), replace=False)
+        a = -rng.uniform(0.1, 1.0, len(nb))
+        rows += [np.full(len(nb), h), nb]; cols += [nb, np.full(len(nb), h)]; vals += [a, a]
+    if path:
+        a = -rng.uniform(0.1, 1.0, len(others) - 1)
+        rows += [others[:-1], others[1:]]; cols += [others[1:], others[:-1]]; vals += [a, a]
+    A = sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))), shape=(n, n)).tocsr()
+    A = (A + A.T) * 0.5
+    A = A + sp.diags(np.asarray(abs(A).sum(axis=1)).ravel() + rng.uniform(0.05, 0.5, n))
+    A = A.tocsr()
+    A.sort_indices()
+    return A.indptr.astype(np.int32), A.indices.astype(np.int32), A.data.copy()
+
+
+LONG_CASES = {
+    "star60k": lambda: _hubs(path=False),
+    "star60k_equal": lambda: (lambda rp, ci, va: (rp, ci, np.where(va < 0, -0.5, va)))(*_hubs(path=False)),
+    "hubs3_path": lambda: _hubs(n_leaf=40000, hubs=(0, 17000, 40002), frac=0.5),
+}
+
+
+@pytest.mark.parametrize("case", list(LONG_CASES))
+def test_long_rows_matching_bitexact(B, ora, case):
+    rp, ci, va = LONG_CASES[case]()
+    n = len(rp) - 1
+    w = np.ones(n)
+    c_ref = ora.weights(rp, ci, va, w)
+    mate_ref = ora.match(rp, ci, c_ref)
+    say(f"long rows match {case} n={n} longest={np.diff(rp).max()}")
+    mate, c = B.match(rp, ci, va, w)
+    assert np.array_equal(_bits(c.cpu().numpy()), _bits(c_ref)), "edge weights differ"
+    assert np.array_equal(mate.cpu().numpy(), mate_ref), "matching differs from greedy"
+
+
+@pytest.mark.parametrize("case,group", [("hubs3_path", 0), ("hubs3_path", 64), ("star60k", 0)])
+def test_long_rows_hierarchy_cycle_solve(B, ora, case, group):
+    rp, ci, va = LONG_CASES[case]()
+    n = len(rp) - 1
+    say(f"long rows hierarchy {case} group={group} n={n}")
+    h = B.Hierarchy(rp, ci, va, max_coarse=50, group=group)
+    ho = ora.Hierarchy(rp, ci, va, np.ones(n), max_coarse=50)
+    _compare_hierarchy(h, ho)
+    r = P.uniform_rhs(n, 31)
+    z, zo = h.precond(r).cpu().numpy(), ho.vcycle(r)
+    _close_entries(z, zo, 1e-11)
+    b = P.uniform_rhs(n, 32)
+    x = h.solve(b, tol=1e-8).cpu().numpy()
+    _, io = ho.solve(b, tol=1e-8)
+    A = sp.csr_matrix((va, ci, rp), shape=(n, n))
+    assert np.linalg.norm(b - A @ x) <= 1e-8 * np.linalg.norm(b)
+    assert abs(h.info()["iters"] - io["iters"]) <= 1, (h.info()["iters"], io["iters"])
+    h.close()
+
+
+def test_true_residual_stagnation_status(B):
+    # a tolerance below the rounding floor of b - A x: the recurrence residual
+    # keeps falling, the true one cannot follow; after three restarts the solve
+    # reports BCM_STAGNATED (not BCM_MAXIT: far fewer than itmax iterations ran)
+    c = P.config("G1", 1.0)
+    say("stagnation below the rounding floor")
+    h = B.Hierarchy(c["rowptr"], c["col"], c["val"], c["w"], max_coarse=c["max_coarse"], precision="fp32")
+    h.solve(c["b"], tol=1e-17, allow_maxit=True)
+    inf = h.info()
+    assert inf["status"] == B.BCM_STAGNATED and inf["iters"] < 1000, inf
+    assert 1e-17 < inf["relres"] < 1e-12
+    with pytest.raises(B.BcmError) as e:
+        h.solve(c["b"], tol=1e-17)
+    assert e.value.code == B.BCM_STAGNATED and "stagnated" in str(e.value)

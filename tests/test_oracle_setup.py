@@ -369,29 +369,56 @@ def test_setup_rejects_invalid_input(ora):
         ora.Hierarchy(rp, ci, bad, np.ones(6))
 
 
-def test_stalled_coarsening_ends_the_hierarchy(ora):
-    # heterogeneous diffusion: the matching stops halving the size per level a
-    # few levels down; the first level formed with a ratio below
-    # sqrt(2^sweeps) = 2 is the coarsest.  min_ratio = 1 keeps coarsening until
-    # the size is unchanged or the level limit is hit.
+def test_stop_rule_closed_forms(ora):
+    # Section 5: stop at n_k <= maxcoarseset * n^(1/3) (maxcoarseset = 40), at
+    # 40 levels, or when a level leaves the size unchanged.  Sizes from the
+    # closed form of the 1-D Laplacian with w = 1 (pairs {2k, 2k+1} in every
+    # sweep, so double pairwise aggregation divides the size by 4):
+    # m = 2^16 -> 16384 -> 4096 -> 1024 <= round(40 * 65536^(1/3)) = 1613.
+    rp, ci, va = P.laplace1d(1 << 16)
+    h = ora.Hierarchy(rp, ci, va, np.ones(1 << 16))
+    assert P.default_max_coarse(1 << 16) == 1613
+    assert h.sizes() == [65536, 16384, 4096, 1024]
+    # the level cap
+    h = ora.Hierarchy(rp, ci, va, np.ones(1 << 16), max_levels=2)
+    assert h.sizes() == [65536, 16384]
+    # one sweep per level: halving, 65536 / 2^6 = 1024 is the first size <= 1613
+    h = ora.Hierarchy(rp, ci, va, np.ones(1 << 16), sweeps=1)
+    assert h.sizes() == [65536 >> k for k in range(7)]
+    # no edge to match (a diagonal matrix): the first level leaves the size unchanged
+    n = 5000
+    h = ora.Hierarchy(np.arange(n + 1), np.arange(n), np.full(n, 3.0), np.ones(n), max_coarse=10)
+    assert h.sizes() == [n]
+
+
+def test_stalled_coarsening_default_and_ratio_rule(ora):
+    # heterogeneous diffusion: the matching stops halving the size a few levels
+    # down.  The paper's rule (default) keeps coarsening while pairs form, up
+    # to the 40-level cap here (the star-shaped coarse levels then form one
+    # pair per sweep); the library's optional ratio rule (min_ratio = 2) ends
+    # at the first level that did not halve the size.
     c = P.config("G5", 0.5)
     h = ora.Hierarchy(c["rowptr"], c["col"], c["val"], c["w"], max_coarse=c["max_coarse"])
     s = h.sizes()
-    r = [a / b for a, b in zip(s[:-1], s[1:])]
+    assert len(s) == 40 and all(a > b for a, b in zip(s[:-1], s[1:])) and s[-1] > c["max_coarse"]
+    h2 = ora.Hierarchy(c["rowptr"], c["col"], c["val"], c["w"], max_coarse=c["max_coarse"], min_ratio=2.0)
+    s2 = h2.sizes()
+    r = [a / b for a, b in zip(s2[:-1], s2[1:])]
     assert all(x >= 2.0 for x in r[:-1]) and r[-1] < 2.0
-    assert s[-1] > c["max_coarse"]
-    h1 = ora.Hierarchy(c["rowptr"], c["col"], c["val"], c["w"], max_coarse=c["max_coarse"], min_ratio=1.0)
-    s1 = h1.sizes()
-    assert s1[:len(s)] == s and len(s1) > len(s) + 5
+    assert s[:len(s2)] == s2 and len(s) > len(s2) + 5
+    # a stalled level is a star: one row coupled to all others, which hold two entries
+    L = h.level(len(s) - 1)
+    d = np.diff(L["rowptr"])
+    assert d.max() == L["n"] and np.sum(d == 2) == L["n"] - 1
     _, i = h.solve(c["b"], tol=1e-8)
-    _, i1 = h1.solve(c["b"], tol=1e-8)
-    assert i["status"] == 0 and i["iters"] < i1["iters"]
+    _, i2 = h2.solve(c["b"], tol=1e-8)
+    assert i["status"] == 0 and i2["status"] == 0 and i2["iters"] < i["iters"]
 
 
 def test_ratio_rule_leaves_regular_grids_alone(ora):
     for name, scale in [("G1", 1.0), ("G2", 0.5)]:
         c = P.config(name, scale)
         h = ora.Hierarchy(c["rowptr"], c["col"], c["val"], c["w"], max_coarse=c["max_coarse"])
-        h1 = ora.Hierarchy(c["rowptr"], c["col"], c["val"], c["w"], max_coarse=c["max_coarse"], min_ratio=1.0)
-        assert h.sizes() == h1.sizes()
+        h2 = ora.Hierarchy(c["rowptr"], c["col"], c["val"], c["w"], max_coarse=c["max_coarse"], min_ratio=2.0)
+        assert h.sizes() == h2.sizes()
         assert h.sizes()[-1] <= c["max_coarse"]

@@ -31,3 +31,18 @@ def test_generators_are_symmetric_and_sorted():
             row = c["col"][c["rowptr"][i]:c["rowptr"][i + 1]]
             assert (np.diff(row) > 0).all()
         assert len(c["b"]) == c["n"] and len(c["w"]) == c["n"]
+
+
+def test_elasticity_keeps_every_structural_entry():
+    # Q1 elements couple every pair of nodes within one element of each other
+    # (3 x 3 x 3 neighbourhood), 3 x 3 dofs per node pair: with the x = 0 face
+    # clamped there are (3 ne - 2) (3 (ne + 1) - 2)^2 free node pairs, and every
+    # one of them is stored -- also those whose element contributions cancel
+    # to exactly 0 (the full-size 48^3 count is 26,869,950)
+    ne = 8
+    rp, ci, va, f = P.elasticity3d(ne, seed=4)
+    assert len(ci) == 9 * (3 * ne - 2) * (3 * (ne + 1) - 2) ** 2
+    assert (va == 0).sum() > 0
+    A = _A(rp, ci, va)
+    assert np.array_equal(A.T.tocsr().sorted_indices().indices, ci)
+    assert 9 * (3 * 48 - 2) * (3 * 49 - 2) ** 2 == 26869950
