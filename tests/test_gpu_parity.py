@@ -42,7 +42,23 @@ def _close_entries(z, zo, rtol):
     bound = rtol * (np.abs(zo) + np.mean(np.abs(zo)))
     err = np.abs(z - zo)
     worst = int(np.argmax(err / bound))
+    say(f"entry-wise: worst |dz| / (|zo| + mean |zo|) = {err[worst] / bound[worst] * rtol:.2e} (bound {rtol:.0e})")
     assert np.all(err <= bound), f"entry {worst}: |dz| = {err[worst]:.3e} > bound {bound[worst]:.3e}"
+
+
+# Entry-wise bounds of one preconditioner application against the FP64
+# oracle, on the scale |zo_i| + mean |zo|.  FP64: the two sides differ only in
+# the order of the sums (dense folded operators, sliced-ELL rows, block
+# partials), a few ulp per operation carried through the levels; FP32: float32
+# storage and accumulation, eps 6e-8 per operation carried the same way.  The
+# norm-wise bounds (1e-12 and 1e-5 relative) are checked beside these.
+ENTRY_FP64, ENTRY_FP32 = 1e-11, 1e-4
+
+
+# FP32 cycle: a perturbed preconditioner; the iteration count may differ from
+# the FP64 oracle's either way, by at most this much
+def _fp32_allowance(it):
+    return max(2, it // 20)
 
 
 def _star(n):
@@ -124,7 +140,7 @@ def test_hierarchy_bitexact(B, ora, name, scale):
 def test_hierarchy_sweeps_1_and_3_and_random_w(B, ora):
     c = P.config("G3", 0.15)
     w = np.random.default_rng(1).uniform(0.5, 2.0, c["n"])
-    for sweeps in (1, 3):
+    for sweeps in (1, 3, 4):
         say(f"setup sweeps={sweeps} {c['name']}")
         h = B.Hierarchy(c["rowptr"], c["col"], c["val"], w, max_coarse=30, sweeps=sweeps)
         ho = ora.Hierarchy(c["rowptr"], c["col"], c["val"], w, max_coarse=30, sweeps=sweeps)
@@ -141,6 +157,7 @@ def test_precond_fp64_parity(B, ora, name, scale):
     z = h.precond(r).cpu().numpy()
     zo = ho.vcycle(r)
     assert np.linalg.norm(z - zo) <= 1e-12 * np.linalg.norm(zo)
+    _close_entries(z, zo, ENTRY_FP64)
 
 
 @pytest.mark.parametrize("name,scale", [("G1", 1.0), ("G2", 0.3), ("G4", 0.21)])
@@ -154,6 +171,7 @@ def test_precond_fp32_cycle_error_bound(B, ora, name, scale):
     z = h.precond(r).cpu().numpy()
     zo = ho.vcycle(r)
     assert np.linalg.norm(z - zo) <= 1e-5 * np.linalg.norm(zo)
+    _close_entries(z, zo, ENTRY_FP32)
 
 
 @pytest.mark.parametrize("name,scale", [("G1", 1.0), ("G2", 0.3), ("G5", 0.2), ("G4", 0.21)])
@@ -181,6 +199,7 @@ def test_folded_coarse_levels(B, ora, name, scale, precision, cycle, klevels):
     bound = 1e-12 if precision == "fp64" else 1e-5
     for z in zs:
         assert np.linalg.norm(z - zo) <= bound * np.linalg.norm(zo)
+        _close_entries(z, zo, ENTRY_FP64 if precision == "fp64" else ENTRY_FP32)
     assert np.linalg.norm(zs[0] - zs[1]) <= bound * np.linalg.norm(zo)
 
 
@@ -201,12 +220,9 @@ def test_solve_parity(B, ora, name, scale, precision):
     assert abs(inf["relres"] - rel) <= 1e-3 * rel + 1e-15
     ho = ora.Hierarchy(c["rowptr"], c["col"], c["val"], c["w"], max_coarse=c["max_coarse"])
     xo, io = ho.solve(c["b"], tol=c["tol"])
-    if precision == "fp64":
-        assert abs(inf["iters"] - io["iters"]) <= 1, (inf["iters"], io["iters"])
-    else:
-        # FP32 cycle: a perturbed preconditioner; stated bound on extra iterations
-        assert inf["iters"] <= io["iters"] + max(2, io["iters"] // 5), (inf["iters"], io["iters"])
     say(f"solve {precision} {c['name']} iters gpu={inf['iters']} oracle={io['iters']} relres={rel:.3e}")
+    allow = 1 if precision == "fp64" else _fp32_allowance(io["iters"])
+    assert abs(inf["iters"] - io["iters"]) <= allow, (inf["iters"], io["iters"])
 
 
 def test_solve_edge_cases(B):
@@ -252,6 +268,7 @@ def test_large_coarsest_level_global_sweeps(B, ora):
     r = P.uniform_rhs(c["n"], 3)
     z, zo = h.precond(r).cpu().numpy(), ho.vcycle(r)
     assert np.linalg.norm(z - zo) <= 1e-12 * np.linalg.norm(zo)
+    _close_entries(z, zo, ENTRY_FP64)
 
 
 def test_invalid_inputs_rejected(B):
@@ -302,6 +319,7 @@ def test_lane_width_and_sell_settings(B, ora, name, scale, group, sell):
     r = P.uniform_rhs(c["n"], 16)
     z, zo = h.precond(r).cpu().numpy(), ho.vcycle(r)
     assert np.linalg.norm(z - zo) <= 1e-12 * np.linalg.norm(zo)
+    _close_entries(z, zo, ENTRY_FP64)
     x = h.solve(c["b"], tol=c["tol"]).cpu().numpy()
     _, io = ho.solve(c["b"], tol=c["tol"])
     A = sp.csr_matrix((c["val"], c["col"], c["rowptr"]), shape=(c["n"], c["n"]))
@@ -374,11 +392,12 @@ def test_sell_uniform_and_mixed_slices(B, ora):
         r = P.uniform_rhs(n, 23)
         z, zo = h.precond(r).cpu().numpy(), ho.vcycle(r)
         assert np.linalg.norm(z - zo) <= bound * np.linalg.norm(zo)
+        _close_entries(z, zo, ENTRY_FP64 if precision == "fp64" else ENTRY_FP32)
         b = P.uniform_rhs(n, 24)
         x = h.solve(b, tol=1e-8).cpu().numpy()
         assert np.linalg.norm(b - A @ x) <= 1e-8 * np.linalg.norm(b)
         _, io = ho.solve(b, tol=1e-8)
-        assert abs(h.info()["iters"] - io["iters"]) <= (1 if precision == "fp64" else max(2, io["iters"] // 5))
+        assert abs(h.info()["iters"] - io["iters"]) <= (1 if precision == "fp64" else _fp32_allowance(io["iters"]))
         h.close()
 
 
@@ -394,6 +413,7 @@ def test_sell_int32_columns_for_long_range_couplings(B, ora):
     r = P.uniform_rhs(n, 18)
     z, zo = h.precond(r).cpu().numpy(), ho.vcycle(r)
     assert np.linalg.norm(z - zo) <= 1e-12 * np.linalg.norm(zo)
+    _close_entries(z, zo, ENTRY_FP64)
     b = P.uniform_rhs(n, 19)
     x = h.solve(b, tol=1e-8).cpu().numpy()
     _, io = ho.solve(b, tol=1e-8)
@@ -415,14 +435,15 @@ def test_w_cycle_parity(B, ora, name, scale, precision):
     z, zo = h.precond(r).cpu().numpy(), ho.vcycle(r)
     bound = 1e-12 if precision == "fp64" else 1e-5
     assert np.linalg.norm(z - zo) <= bound * np.linalg.norm(zo)
+    _close_entries(z, zo, ENTRY_FP64 if precision == "fp64" else ENTRY_FP32)
     x = h.solve(c["b"], tol=c["tol"]).cpu().numpy()
     xo, io = ho.solve(c["b"], tol=c["tol"])
     inf = h.info()
     A = sp.csr_matrix((c["val"], c["col"], c["rowptr"]), shape=(c["n"], c["n"]))
     assert np.linalg.norm(c["b"] - A @ x) <= c["tol"] * np.linalg.norm(c["b"])
-    if precision == "fp64":
-        assert abs(inf["iters"] - io["iters"]) <= 1, (inf["iters"], io["iters"])
     say(f"W-cycle {precision} {c['name']} iters gpu={inf['iters']} oracle={io['iters']}")
+    allow = 1 if precision == "fp64" else _fp32_allowance(io["iters"])
+    assert abs(inf["iters"] - io["iters"]) <= allow, (inf["iters"], io["iters"])
 
 
 # ----------------------------------------------------------------------------- K-cycle
@@ -441,6 +462,9 @@ def test_k_cycle_parity(B, ora, name, scale, precision, klevels):
     err = np.linalg.norm(z - zo) / np.linalg.norm(zo)
     say(f"K-cycle {precision} {c['name']} precond rel err {err:.2e}")
     assert err <= (1e-11 if precision == "fp64" else 1e-4)
+    # the K-cycle is nonlinear (its coarse steps divide by dot products): ten
+    # times the linear cycles' entry-wise bounds
+    _close_entries(z, zo, 10 * (ENTRY_FP64 if precision == "fp64" else ENTRY_FP32))
     x = h.solve(c["b"], tol=c["tol"]).cpu().numpy()
     xo, io = ho.solve(c["b"], tol=c["tol"])
     inf = h.info()
