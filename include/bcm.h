@@ -255,6 +255,30 @@ int bcm_level_copy(const bcm_handle *h, int32_t k, int32_t *row_ptr, int32_t *co
  */
 int bcm_match(const bcm_csr *A, const double *w, const bcm_params *p, int32_t *mate, double *c);
 
+/* Size of the device scratch array of bcm_match_noalloc: 64 MiB per GPU. */
+#define BCM_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+
+/*
+ * bcm_match without any allocation, for callers that cannot allocate: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same arguments, results and errors as bcm_match (p's allocator
+ * is ignored).  Its scratch lives in one static device array of
+ * BCM_NOALLOC_SCRATCH_BYTES on each GPU the library runs on, held until the
+ * process ends; its address is looked up once per device, on the first call
+ * made with that device current.  Host read-backs go to plain host memory
+ * (no pinned staging buffer).
+ *  - Limit: the scratch of a call is, in 256-byte-rounded pieces, about
+ *    20 n + 12 nnz bytes (+ 8 nnz when c is NULL), plus the long-row lists
+ *    and 16 bytes per entry of rows longer than 16 x the lanes per row.  A
+ *    call that needs more returns BCM_EINVAL with a message and leaves mate
+ *    unspecified.
+ *  - Every call on one GPU shares that GPU's array and finds the previous
+ *    call's contents there (everything a call reads it first writes).  Calls
+ *    that overlap on one GPU (two streams, two threads) race: the caller
+ *    serialises them.  bcm_params.stream must belong to the current device.
+ */
+int bcm_match_noalloc(const bcm_csr *A, const double *w, const bcm_params *p, int32_t *mate, double *c);
+
 /* Kernel classes that bcm_params.profile can time. */
 enum {
     BCM_PROF_CYCLE_DOWN0 = 1,  /* finest-level pre-smooth + residual + restriction */

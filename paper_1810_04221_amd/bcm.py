@@ -48,7 +48,7 @@ class BcmInfo(C.Structure):
 
 
 EXPORTS = ["bcm_default_params", "bcm_setup", "bcm_solve", "bcm_precond", "bcm_solve_adjoint", "bcm_sampled_outer", "bcm_info",
-           "bcm_level_copy", "bcm_match", "bcm_profile", "bcm_free", "bcm_last_error"]
+           "bcm_level_copy", "bcm_match", "bcm_match_noalloc", "bcm_profile", "bcm_free", "bcm_last_error"]
 
 _lib = None
 
@@ -78,6 +78,7 @@ def load_library(path: str = LIB_PATH):
     L.bcm_info.argtypes = [P, C.POINTER(BcmInfo)]
     L.bcm_level_copy.argtypes = [P, I32, P, P, P, P, P, P, P]
     L.bcm_match.argtypes = [C.POINTER(BcmCsr), P, C.POINTER(BcmParams), P, P]
+    L.bcm_match_noalloc.argtypes = [C.POINTER(BcmCsr), P, C.POINTER(BcmParams), P, P]
     L.bcm_profile.argtypes = [P, I32, C.POINTER(C.c_int64), C.POINTER(C.c_double), C.POINTER(C.c_double)]
     L.bcm_free.argtypes = [P]
     L.bcm_free.restype = None
@@ -277,21 +278,25 @@ class Hierarchy:
         return launches.value, ms.value, nbytes.value
 
 
-def match(rowptr, col, val, w=None, check=True, device=None):
-    """One matching sweep on the GPU: returns (mate int32[n], weights float64[nnz])."""
+def match(rowptr, col, val, w=None, check=True, device=None, noalloc=False, weights=True):
+    """One matching sweep on the GPU: returns (mate int32[n], weights float64[nnz]
+    or None when weights=False).  noalloc=True calls bcm_match_noalloc, whose
+    scratch is the library's static device array (no allocation inside the
+    call; calls on one GPU must not overlap)."""
     L = _gpu_lib()
     device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
     rp, ci, va = _dev(rowptr, torch.int32, device), _dev(col, torch.int32, device), _dev(val, torch.float64, device)
     n = rp.numel() - 1
     w = torch.ones(n, dtype=torch.float64, device=device) if w is None else _dev(w, torch.float64, device)
     stream = torch.cuda.current_stream(device).cuda_stream
-    alloc = _TorchAllocator(device, stream)
+    alloc = None if noalloc else _TorchAllocator(device, stream)
     p = make_params(check=check, stream=stream, allocator=alloc)
     mate = torch.empty(n, dtype=torch.int32, device=device)
-    c = torch.empty(ci.numel(), dtype=torch.float64, device=device)
+    c = torch.empty(ci.numel(), dtype=torch.float64, device=device) if weights else None
     A = BcmCsr(n, ci.numel(), rp.data_ptr(), ci.data_ptr(), va.data_ptr())
-    _check(L.bcm_match(C.byref(A), C.c_void_p(w.data_ptr()), C.byref(p), C.c_void_p(mate.data_ptr()),
-                       C.c_void_p(c.data_ptr())))
+    fn = L.bcm_match_noalloc if noalloc else L.bcm_match
+    _check(fn(C.byref(A), C.c_void_p(w.data_ptr()), C.byref(p), C.c_void_p(mate.data_ptr()),
+              C.c_void_p(c.data_ptr() if c is not None else None)))
     return mate, c
 
 

@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstring>
 #include <functional>
+#include <mutex>
 #include <string>
 
 #include "internal.h"
@@ -120,6 +121,11 @@ using namespace bcm;
             return BCM_ENOMEM;                                        \
         }                                                             \
     } while (0)
+
+// Device scratch of the allocation-free matching entry point: one array on
+// each GPU, kept until the process ends.  Host code passes the address that
+// noalloc_scratch() looked up for the current device, never this name.
+static __device__ __align__(256) unsigned char scratch[BCM_NOALLOC_SCRATCH_BYTES];
 
 namespace {
 
@@ -1626,6 +1632,33 @@ int match_args(const bcm_csr *A, const double *w, const bcm_params *p, const int
     return BCM_OK;
 }
 
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_dev[kMaxDevices] = {};
+
+// Address of the static scratch array on the current device, looked up on the
+// first call made with that device current.
+int noalloc_scratch(void **out) {
+    int dev = -1;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) {
+        set_error("bcm_match_noalloc: device index out of range");
+        return BCM_EINVAL;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *p = nullptr;
+        HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) {
+            set_error("bcm_match_noalloc: no address for the static scratch array");
+            return BCM_EHIP;
+        }
+        g_scratch_dev[dev] = p;
+    }
+    *out = g_scratch_dev[dev];
+    return BCM_OK;
+}
+
 Csr csr_view(const bcm_csr *A) {
     Csr M;
     M.n = A->n;
@@ -1811,6 +1844,35 @@ int bcm_match(const bcm_csr *A, const double *w, const bcm_params *p, int32_t *m
     rc = match_sweep(s, ms, M, w, prm.check ? 1 : 0, prm.group, nullptr, 0, nullptr, nullptr, true, nullptr, &tmp);
     (void)hipStreamSynchronize(s);
     tmp.release();
+    return rc;
+}
+
+int bcm_match_noalloc(const bcm_csr *A, const double *w, const bcm_params *p, int32_t *mate, double *c) {
+    g_err.clear();
+    bcm_params prm;
+    int rc = match_args(A, w, p, mate, prm);
+    if (rc) return rc;
+    void *base = nullptr;
+    rc = noalloc_scratch(&base);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)prm.stream;
+    const Csr M = csr_view(A);
+    const int lmin = long_min(lanes_for(prm.group, M));
+    const size_t bytes = match_scratch_bytes(A->n, A->nnz, true, c != nullptr, true, lmin);
+    if (bytes > BCM_NOALLOC_SCRATCH_BYTES) {
+        set_error("bcm_match_noalloc: the matching needs " + std::to_string(bytes) + " bytes of scratch, more than the " +
+                  std::to_string((size_t)BCM_NOALLOC_SCRATCH_BYTES) + "-byte static array");
+        return BCM_EINVAL;
+    }
+    Carver cv;
+    cv.cur = static_cast<char *>(base);
+    cv.left = BCM_NOALLOC_SCRATCH_BYTES;
+    MatchScratch ms;
+    carve_match(cv, A->n, A->nnz, true, c, mate, lmin, ms);
+    // the long rows' sort keys, if any, come from what is left of the array
+    rc = match_sweep(s, ms, M, w, prm.check ? 1 : 0, prm.group, nullptr, 0, nullptr, nullptr, false, &cv, nullptr);
+    if (rc == BCM_OK) HIPCHK(hipStreamSynchronize(s));
+    else (void)hipStreamSynchronize(s);
     return rc;
 }
 
