@@ -519,6 +519,7 @@ int pairwise_sweep(hipStream_t s, Arena &tmp, Arena &keep, Csr &A, const double 
     const bool gsorted = A.nnz >= (long long)kSortedCandidatesAvg * A.n;
     SegList sg;
     unsigned long long *gkeys = nullptr;
+    int *gcc = nullptr;  // column starts per chunk of the long coarse rows' sorted keys
     const int pg = sp ? sp->begin(BCM_PROF_SETUP_GALERKIN, false) : -1;
     if (gal_long) {
         Carver cv;
@@ -527,7 +528,8 @@ int pairwise_sweep(hipStream_t s, Arena &tmp, Arena &keep, Csr &A, const double 
         carve_seg(probe, seg_cap(A.nnz, lmin_g), sg);
         cv.cur = static_cast<char *>(tmp.get(probe.used));
         cv.left = probe.used;
-        NOMEM(cv.cur && keys());
+        gcc = tmp.get_n<int>((size_t)(A.nnz / kSegChunk) + seg_cap(A.nnz, lmin_g) + 1);
+        NOMEM(cv.cur && keys() && gcc);
         carve_seg(cv, seg_cap(A.nnz, lmin_g), sg);
         launch_fill_i32(s, 8, sg.ctl, 0);
         launch_find_long_gal(s, nc, out.mem2, A.rp, lmin_g, sg);
@@ -537,7 +539,8 @@ int pairwise_sweep(hipStream_t s, Arena &tmp, Arena &keep, Csr &A, const double 
     }
     launch_gal_count(s, G, nc, A.rp, A.ci, out.agg, out.mem2, crp, gF, gU, gsorted, gal_long ? lmin_g : 0);
     if (gal_long)
-        launch_gal_long(s, 0, sg, gkeys, A.rp, A.ci, A.v, out.agg, out.p, out.mem2, crp, nullptr, nullptr, nullptr);
+        launch_gal_long(s, 0, sg, gkeys, A.rp, A.ci, A.v, out.agg, out.p, out.mem2, crp, gcc, nullptr, nullptr,
+                        nullptr);
     scan_exclusive(s, crp, crp, nc, crp + nc, stmp2, crp + nc + 1);
     out.Ac.n = nc;
     out.Ac.nnz = A.nnz;
@@ -550,7 +553,7 @@ int pairwise_sweep(hipStream_t s, Arena &tmp, Arena &keep, Csr &A, const double 
     launch_gal_fill(s, G, nc, A.rp, A.ci, A.v, out.agg, out.p, out.mem2, crp, out.Ac.ci, out.Ac.v, gF, gU, gsorted,
                     gal_long ? lmin_g : 0);
     if (gal_long)
-        launch_gal_long(s, 1, sg, gkeys, A.rp, A.ci, A.v, out.agg, out.p, out.mem2, nullptr, crp, out.Ac.ci,
+        launch_gal_long(s, 1, sg, gkeys, A.rp, A.ci, A.v, out.agg, out.p, out.mem2, nullptr, gcc, crp, out.Ac.ci,
                         out.Ac.v);
     // (the coarse entry count is still on the device: A's bounds it; the bytes
     // are corrected with the exact count in build_hierarchy's summary)

@@ -294,7 +294,7 @@ void launch_gal_long_sort(hipStream_t s, const SegList &seg, int maxlen, const i
                           unsigned long long **sorted);
 void launch_gal_long(hipStream_t s, int pass, const SegList &seg, const unsigned long long *sorted, const int *rp,
                      const int *ci, const double *v, const int *agg, const double *p, const int *mem2, int *cnt,
-                     const int *crp, int *cci, double *cv);
+                     int *cc, const int *crp, int *cci, double *cv);
 // l1 row norms of the long rows of a level: chunk partial sums into part
 // (float64), float32 copies of their values into v32 when given
 void launch_long_abs(hipStream_t s, const LongRows &lr, const int *rp, const double *v, double *part, float *v32);

@@ -1,7 +1,8 @@
-// Exclusive prefix sum of int32 for gfx950: tiles of 2048 items (256 threads x
-// 8), a single-workgroup scan of the tile totals, then a fix-up pass.  Used to
-// number aggregates by their smallest member (Algorithm 2) and to turn coarse
-// row counts into row pointers.
+// Exclusive prefix sum of int32 for gfx950: up to 65536 items in one
+// workgroup; longer inputs in tiles of 2048 items (256 threads x 8), a pass of
+// tile sums, then one pass in which every tile adds the sums before it and
+// scans itself.  Used to number aggregates by their smallest member
+// (Algorithm 2) and to turn coarse row counts into row pointers.
 #include "device.h"
 #include "internal.h"
 
@@ -52,28 +53,20 @@ __device__ __forceinline__ int block_max(int x) {
     return m;
 }
 
-// in and out may be the same array (each item is read before the barrier of
-// block_excl and written after it by the same thread): no restrict on them.
+// Tile sums (and largest items) of the input, tiles of kTile items.
 __global__ void __launch_bounds__(kBlock)
-k_scan_tiles(const int *in, int *out, int n, int *__restrict__ tsum, int *__restrict__ tmax) {
+k_scan_reduce(const int *in, int n, int *__restrict__ tsum, int *__restrict__ tmax) {
     const size_t base = (size_t)blockIdx.x * kTile + (size_t)threadIdx.x * kItems;
-    int v[kItems];
     int s = 0, mx = 0;
 #pragma unroll
     for (int k = 0; k < kItems; ++k) {
         const size_t i = base + k;
-        v[k] = i < (size_t)n ? in[i] : 0;
-        s += v[k];
-        mx = max(mx, v[k]);
+        const int v = i < (size_t)n ? in[i] : 0;
+        s += v;
+        mx = max(mx, v);
     }
     int tot;
-    int run = block_excl(s, &tot);
-#pragma unroll
-    for (int k = 0; k < kItems; ++k) {
-        const size_t i = base + k;
-        if (i < (size_t)n) out[i] = run;
-        run += v[k];
-    }
+    (void)block_excl(s, &tot);
     if (tmax) mx = block_max(mx);
     if (threadIdx.x == 0) {
         tsum[blockIdx.x] = tot;
@@ -81,46 +74,59 @@ k_scan_tiles(const int *in, int *out, int n, int *__restrict__ tsum, int *__rest
     }
 }
 
-__global__ void __launch_bounds__(kBlock) k_scan_totals(int *__restrict__ tsum, int nt, int *__restrict__ total,
-                                                        const int *__restrict__ tmax, int *__restrict__ max_out) {
-    int carry = 0, mx = 0;
-    for (int b0 = 0; b0 < nt; b0 += kBlock) {
-        const int i = b0 + threadIdx.x;
-        const int x = i < nt ? tsum[i] : 0;
-        if (tmax && i < nt) mx = max(mx, tmax[i]);
-        int tot;
-        const int ex = block_excl(x, &tot);
-        if (i < nt) tsum[i] = carry + ex;
-        carry += tot;
-        __syncthreads();
+// Tile b: its offset is the sum of the tile sums before it (added by this
+// block itself, in a fixed order), then the tile is scanned and written.  The
+// last tile also writes the total and the largest item.  In place is fine: an
+// item is read and written by the same thread, and no other block reads it.
+__global__ void __launch_bounds__(kBlock)
+k_scan_apply(const int *in, int *out, int n, const int *__restrict__ tsum, int nt, int *__restrict__ total,
+             const int *__restrict__ tmax, int *__restrict__ max_out) {
+    const int b = blockIdx.x;
+    const bool last = b == nt - 1;
+    int pre = 0, mx = 0;
+    for (int i = threadIdx.x; i < (last ? nt : b); i += kBlock) {
+        if (i < b) pre += tsum[i];
+        if (last && tmax) mx = max(mx, tmax[i]);
     }
-    if (tmax) mx = block_max(mx);
-    if (threadIdx.x == 0) {
-        *total = carry;
-        if (max_out) *max_out = mx;
-    }
-}
-
-__global__ void __launch_bounds__(kBlock) k_scan_add(int *__restrict__ out, int n, const int *__restrict__ tsum) {
-    const int add = tsum[blockIdx.x];
-    const size_t base = (size_t)blockIdx.x * kTile;
-    for (int k = threadIdx.x; k < kTile; k += kBlock) {
+    int ptot;
+    (void)block_excl(pre, &ptot);
+    const size_t base = (size_t)b * kTile + (size_t)threadIdx.x * kItems;
+    int v[kItems];
+    int sum = 0;
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
         const size_t i = base + k;
-        if (i < (size_t)n) out[i] += add;
+        v[k] = i < (size_t)n ? in[i] : 0;
+        sum += v[k];
+    }
+    int tot;
+    int run = ptot + block_excl(sum, &tot);
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+        const size_t i = base + k;
+        if (i < (size_t)n) out[i] = run;
+        run += v[k];
+    }
+    if (last) {
+        if (tmax) mx = block_max(mx);
+        if (threadIdx.x == 0) {
+            *total = ptot + tot;
+            if (max_out) *max_out = mx;
+        }
     }
 }
 
-// Whole scan in one workgroup of 1024 threads for n <= kScanSmall.  Wave w owns
-// C = kScanSmall / 1024 consecutive chunks of 64 items; every load and store of
-// a wave is one contiguous 256-byte access (a single workgroup cannot afford
-// strided ones).  Each chunk is scanned across the wave's lanes, chunk totals
-// carry across the wave's chunks, then across the 16 waves.  In place is fine:
-// an item is read and written by the same lane.
-constexpr int kScanSmall = 16384;
+// Whole scan in one workgroup of 1024 threads for n <= 1024 * C.  Wave w owns
+// C consecutive chunks of 64 items; every load and store of a wave is one
+// contiguous 256-byte access (a single workgroup cannot afford strided ones).
+// Each chunk is scanned across the wave's lanes, chunk totals carry across the
+// wave's chunks, then across the 16 waves.  In place is fine: an item is read
+// and written by the same lane.
+constexpr int kScanSmall = 16384, kScanMid = 65536;
 
+template <int C>
 __global__ void __launch_bounds__(1024) k_scan_single(const int *in, int *out, int n, int *__restrict__ total,
                                                      int *__restrict__ max_out) {
-    constexpr int C = kScanSmall / 1024;
     __shared__ int wsum[16], wmax[16];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     int v[C];
@@ -178,12 +184,15 @@ void scan_exclusive(hipStream_t s, const int *in, int *out, int n, int *total_de
         return;
     }
     if (n <= kScanSmall) {
-        hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(1024), 0, s, in, out, n, total_dev, max_dev);
+        hipLaunchKernelGGL(k_scan_single<kScanSmall / 1024>, dim3(1), dim3(1024), 0, s, in, out, n, total_dev, max_dev);
         return;
     }
-    hipLaunchKernelGGL(k_scan_tiles, dim3(nt), dim3(kBlock), 0, s, in, out, n, tsum, tmax);
-    hipLaunchKernelGGL(k_scan_totals, dim3(1), dim3(kBlock), 0, s, tsum, nt, total_dev, tmax, max_dev);
-    hipLaunchKernelGGL(k_scan_add, dim3(nt), dim3(kBlock), 0, s, out, n, tsum);
+    if (n <= kScanMid) {
+        hipLaunchKernelGGL(k_scan_single<kScanMid / 1024>, dim3(1), dim3(1024), 0, s, in, out, n, total_dev, max_dev);
+        return;
+    }
+    hipLaunchKernelGGL(k_scan_reduce, dim3(nt), dim3(kBlock), 0, s, in, n, tsum, tmax);
+    hipLaunchKernelGGL(k_scan_apply, dim3(nt), dim3(kBlock), 0, s, in, out, n, tsum, nt, total_dev, tmax, max_dev);
 }
 
 }  // namespace bcm

@@ -45,6 +45,10 @@ __device__ __forceinline__ void seg_append(const SegList &sg, int row, int len) 
     }
 }
 
+// Rows j of at most kSymScan entries are searched for the transposed entry
+// by loading all their columns at once (no chain of dependent loads).
+constexpr int kSymScan = 8;
+
 template <int G>
 __global__ void __launch_bounds__(kBlock)
 k_validate(int n, int nnz, const int *__restrict__ rp, const int *__restrict__ ci,
@@ -89,12 +93,21 @@ k_validate(int n, int nnz, const int *__restrict__ rp, const int *__restrict__ c
             const int s2 = rp[j], e2 = rp[j + 1];
             int found = -1;
             if (s2 >= 0 && e2 >= s2 && (nnz < 0 || e2 <= nnz)) {
-                int lo = s2, hi = e2 - 1;
-                while (lo <= hi) {
-                    const int mid = (lo + hi) >> 1;
-                    const int cm = ci[mid];
-                    if (cm == row) { found = mid; break; }
-                    if (cm < row) lo = mid + 1; else hi = mid - 1;
+                if (e2 - s2 <= kSymScan) {  // a short row j: all its columns in one round of loads
+                    int cs[kSymScan];
+#pragma unroll
+                    for (int t = 0; t < kSymScan; ++t) cs[t] = s2 + t < e2 ? ci[s2 + t] : -1;
+#pragma unroll
+                    for (int t = 0; t < kSymScan; ++t)
+                        if (cs[t] == row) found = s2 + t;
+                } else {
+                    int lo = s2, hi = e2 - 1;
+                    while (lo <= hi) {
+                        const int mid = (lo + hi) >> 1;
+                        const int cm = ci[mid];
+                        if (cm == row) { found = mid; break; }
+                        if (cm < row) lo = mid + 1; else hi = mid - 1;
+                    }
                 }
             }
             if (found < 0 || __double_as_longlong(v[found]) != __double_as_longlong(a)) f |= kErrAsym;
@@ -420,10 +433,13 @@ k_suitor(int n, const int *__restrict__ rp, const unsigned long long *__restrict
         // only grows, keys are distinct), so the others lose at once -- the
         // outcome of any order in which the best one came first -- and the
         // wave issues one atomic instead of 64.
+        // (one active lane, the usual case in the tail of displacement
+        // chains, goes straight to the atomic)
         const int v0 = __builtin_amdgcn_readfirstlane(v);
-        if (__ballot(v != v0) == 0ull) {
+        const unsigned long long act = __ballot(1);
+        if ((act & (act - 1)) != 0ull && __ballot(v != v0) == 0ull) {
             unsigned long long *slot = &wbest[threadIdx.x >> 6];
-            const int first = __ffsll((unsigned long long)__ballot(1)) - 1;
+            const int first = __ffsll(act) - 1;
             if ((int)(threadIdx.x & 63) == first) *slot = 0ull;
             wave_sync();
             atomicMax(slot, key);
@@ -984,12 +1000,21 @@ k_long_validate(int n, int nnz, const int *__restrict__ rp, const int *__restric
             const int s2 = rp[j], e2 = rp[j + 1];
             int found = -1;
             if (s2 >= 0 && e2 >= s2 && (nnz < 0 || e2 <= nnz)) {
-                int lo = s2, hi = e2 - 1;
-                while (lo <= hi) {
-                    const int mid = (lo + hi) >> 1;
-                    const int cm = ci[mid];
-                    if (cm == row) { found = mid; break; }
-                    if (cm < row) lo = mid + 1; else hi = mid - 1;
+                if (e2 - s2 <= kSymScan) {  // a short row j: all its columns in one round of loads
+                    int cs[kSymScan];
+#pragma unroll
+                    for (int t = 0; t < kSymScan; ++t) cs[t] = s2 + t < e2 ? ci[s2 + t] : -1;
+#pragma unroll
+                    for (int t = 0; t < kSymScan; ++t)
+                        if (cs[t] == row) found = s2 + t;
+                } else {
+                    int lo = s2, hi = e2 - 1;
+                    while (lo <= hi) {
+                        const int mid = (lo + hi) >> 1;
+                        const int cm = ci[mid];
+                        if (cm == row) { found = mid; break; }
+                        if (cm < row) lo = mid + 1; else hi = mid - 1;
+                    }
                 }
             }
             if (found < 0 || __double_as_longlong(v[found]) != __double_as_longlong(a)) f |= kErrAsym;
@@ -1040,33 +1065,48 @@ struct KeyGal {
 
 // Sorts every chunk of kSegChunk keys of every segment in LDS (bitonic
 // network over the whole chunk, ~0 padding), writing them to out at the
-// segment's offset.
+// segment's offset.  One compare-exchange per thread and stage (kSegChunk / 2
+// threads).  A stage of stride <= 64 pairs keys inside one wave's 128-key
+// block (the wave's 64 threads cover exactly that block), so only the stages
+// of longer strides wait for the whole workgroup; the others order the LDS
+// accesses of one wave.
+constexpr int kSortThreads = kSegChunk / 2;
 template <typename Key>
-__global__ void __launch_bounds__(kBlock) k_seg_sort_chunks(SegList sg, Key key, unsigned long long *__restrict__ out) {
+__global__ void __launch_bounds__(kSortThreads)
+k_seg_sort_chunks(SegList sg, Key key, unsigned long long *__restrict__ out) {
+    static_assert((kSegChunk & (kSegChunk - 1)) == 0 && kSortThreads % 64 == 0, "power-of-two chunk");
     __shared__ unsigned long long keys[kSegChunk];
     const int cnt = sg.ctl[0], nch = sg.ctl[2];
+    const int u = threadIdx.x;
+    constexpr int LOG = __builtin_ctz(kSegChunk);
     for (int ch = blockIdx.x; ch < nch; ch += gridDim.x) {
         const int t = seg_of(sg.cb, cnt, ch);
         const int L = sg.len[t], k0 = (ch - sg.cb[t]) * kSegChunk, m = min(kSegChunk, L - k0);
         const int row = sg.row[t];
-        for (int k = threadIdx.x; k < kSegChunk; k += kBlock) keys[k] = k < m ? key(row, L, k0 + k) : ~0ull;
+        const unsigned long long a0 = u < m ? key(row, L, k0 + u) : ~0ull;
+        const unsigned long long a1 = u + kSortThreads < m ? key(row, L, k0 + u + kSortThreads) : ~0ull;
+        keys[u] = a0;
+        keys[u + kSortThreads] = a1;
         __syncthreads();
-        for (int size = 2; size <= kSegChunk; size <<= 1) {
-            for (int stride = size >> 1; stride > 0; stride >>= 1) {
-                for (int u = threadIdx.x; u < kSegChunk / 2; u += kBlock) {
-                    const int lo = 2 * stride * (u / stride) + (u % stride), hi = lo + stride;
-                    const bool up = (lo & size) == 0;
-                    const unsigned long long a = keys[lo], b = keys[hi];
-                    if ((a > b) == up) {
-                        keys[lo] = b;
-                        keys[hi] = a;
-                    }
+        for (int ls = 1; ls <= LOG; ++ls) {         // sorted runs of 2^ls keys
+            for (int lt = ls - 1; lt >= 0; --lt) {  // stride 2^lt
+                const int lo = ((u >> lt) << (lt + 1)) | (u & ((1 << lt) - 1)), hi = lo + (1 << lt);
+                const bool up = ((lo >> ls) & 1) == 0;
+                const unsigned long long a = keys[lo], b = keys[hi];
+                if ((a > b) == up) {
+                    keys[lo] = b;
+                    keys[hi] = a;
                 }
-                __syncthreads();
+                // the next stage pairs keys of other waves: stride >= 128 (this
+                // stage's, or the next size's first one after stride 1)
+                if (lt > 6 || (lt == 0 && ls >= 7 && ls < LOG)) __syncthreads();
+                else wave_sync();
             }
         }
+        __syncthreads();
         unsigned long long *dst = out + sg.off[t] + k0;
-        for (int k = threadIdx.x; k < m; k += kBlock) dst[k] = keys[k];
+        if (u < m) dst[u] = keys[u];
+        if (u + kSortThreads < m) dst[u + kSortThreads] = keys[u + kSortThreads];
         __syncthreads();
     }
 }
@@ -1139,50 +1179,74 @@ k_long_cand(SegList sg, const unsigned long long *__restrict__ sorted, const int
     });
 }
 
-// Galerkin coarse rows with many candidates, one workgroup per row over its
-// sorted candidate keys (column << 32 | candidate): a column starts where the
-// key's column differs from the previous one.  Pass 0 counts the distinct
-// columns; pass 1 numbers them by a scan over the workgroup and writes each
-// entry, its (at most four) terms summed in canonical (m, M) order as k_gal.
+// Galerkin coarse rows with many candidates, over their sorted candidate keys
+// (column << 32 | candidate), one workgroup per chunk of kSegChunk keys: a
+// column starts where the key's column differs from the previous key's.
+// Pass 0 stores the chunk's column starts in cc[chunk] and adds them to the
+// row's count (zeroed by the count pass of k_gal); pass 1 numbers them from
+// the row's first entry plus the starts of the row's earlier chunks and writes
+// each entry, its (at most four) terms summed in canonical (m, M) order as
+// k_gal.  A column's run of keys may continue into the next chunk: its start
+// owns it.
 __global__ void __launch_bounds__(kSegBlock)
 k_gal_long(int pass, SegList sg, const unsigned long long *__restrict__ sorted, const int *__restrict__ rp,
            const int *__restrict__ ci, const double *__restrict__ v, const int *__restrict__ agg,
            const double *__restrict__ p, const int *__restrict__ mem2, int *__restrict__ cnt,
-           const int *__restrict__ crp, int *__restrict__ cci, double *__restrict__ cv) {
-    const int nseg = sg.ctl[0];
-    for (int t = blockIdx.x; t < nseg; t += gridDim.x) {
+           int *__restrict__ cc, const int *__restrict__ crp, int *__restrict__ cci, double *__restrict__ cv) {
+    constexpr int PER = kSegChunk / kSegBlock;  // keys per thread
+    const int nseg = sg.ctl[0], nch = sg.ctl[2];
+    for (int ch = blockIdx.x; ch < nch; ch += gridDim.x) {
+        const int t = seg_of(sg.cb, nseg, ch);
         const int E = sg.row[t], L = sg.len[t];
         const unsigned long long *keys = sorted + sg.off[t];
-        auto col = [&](int k) { return (int)(keys[k] >> 32); };
-        const int C = (L + kSegBlock - 1) / kSegBlock;
-        const int k0 = min((int)threadIdx.x * C, L), k1 = min(k0 + C, L);
+        const int k0 = min((ch - sg.cb[t]) * kSegChunk + (int)threadIdx.x * PER, L);
+        // the thread's keys and the one before them, all loaded first
+        int col[PER + 1];
+        col[0] = k0 > 0 ? (int)(keys[k0 - 1] >> 32) : -1;
+#pragma unroll
+        for (int r = 0; r < PER; ++r) col[r + 1] = k0 + r < L ? (int)(keys[k0 + r] >> 32) : -1;
         int mine = 0;
-        for (int k = k0; k < k1; ++k) mine += (k == 0 || col(k) != col(k - 1)) ? 1 : 0;
+#pragma unroll
+        for (int r = 0; r < PER; ++r) mine += (k0 + r < L && (k0 + r == 0 || col[r + 1] != col[r])) ? 1 : 0;
         int total;
         int rank = seg_block_excl(mine, &total);
         if (pass == 0) {
-            if (threadIdx.x == 0) cnt[E] = total;
+            if (threadIdx.x == 0) {
+                cc[ch] = total;
+                atomicAdd(&cnt[E], total);
+            }
             continue;
         }
+        int before = 0;
+        for (int c = sg.cb[t] + (int)threadIdx.x; c < ch; c += kSegBlock) before += cc[c];
+        int btot;
+        (void)seg_block_excl(before, &btot);
         const int e0 = mem2[2 * E], e1 = mem2[2 * E + 1];
         const int s0 = rp[e0], L0 = rp[e0 + 1] - s0;
         const int s1 = e1 >= 0 ? rp[e1] : 0;
-        const int base = crp[E];
+        const int base = crp[E] + btot;
         const unsigned long long NONE = ~0ull;
-        for (int k = k0; k < k1; ++k) {
-            if (!(k == 0 || col(k) != col(k - 1))) continue;
-            const int f = col(k);
+#pragma unroll
+        for (int r0 = 0; r0 < PER; ++r0) {
+            const int k = k0 + r0;
+            if (!(k < L && (k == 0 || col[r0 + 1] != col[r0]))) continue;
+            const int f = col[r0 + 1];
+            // the run's keys k .. k + 3 (a column has at most four candidates)
             unsigned long long kk[4];
             double tt[4];
+            int cidx[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const unsigned long long key = k + r < L ? keys[k + r] : NONE;
+                cidx[r] = (key != NONE && (int)(key >> 32) == f) ? (int)(key & 0xffffffffull) : -1;
+            }
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 kk[r] = NONE;
                 tt[r] = 0.0;
-                const int kr = k + r;
-                if (kr >= L || col(kr) != f) continue;
-                const int cidx = (int)(keys[kr] & 0xffffffffull);
-                const int q = cidx < L0 ? s0 + cidx : s1 + (cidx - L0);
-                const int i = cidx < L0 ? e0 : e1, j = ci[q];
+                if (cidx[r] < 0) continue;
+                const int q = cidx[r] < L0 ? s0 + cidx[r] : s1 + (cidx[r] - L0);
+                const int i = cidx[r] < L0 ? e0 : e1, j = ci[q];
                 const int m = min(i, j), M = max(i, j);
                 kk[r] = ((unsigned long long)(unsigned)m << 32) | (unsigned)M;
                 tt[r] = (p[m] * v[q]) * p[M];
@@ -1319,7 +1383,10 @@ k_gal(int pass, int nc, const int *__restrict__ rp, const int *__restrict__ ci,
     const int s1 = e1 >= 0 ? rp[e1] : 0;
     const int L1 = e1 >= 0 ? rp[e1 + 1] - s1 : 0;
     const int L = L0 + L1;
-    if (lmin > 0 && L > lmin) return;  // a long coarse row: k_gal_long
+    if (lmin > 0 && L > lmin) {  // a long coarse row: k_gal_long adds its count
+        if (pass == 0 && lane == 0) cnt[E] = 0;
+        return;
+    }
     if (L > LS) {
         gal_row<G>(pass, E, lane, rp, ci, v, agg, p, e0, e1, s0, L0, s1, L1, cnt, crp, cci, cv, gF, gU, false);
         return;
@@ -1419,7 +1486,10 @@ k_gal_sorted(int pass, int nc, const int *__restrict__ rp, const int *__restrict
     const int s1 = e1 >= 0 ? rp[e1] : 0;
     const int L1 = e1 >= 0 ? rp[e1 + 1] - s1 : 0;
     const int L = L0 + L1;
-    if (lmin > 0 && L > lmin) return;  // a long coarse row: k_gal_long
+    if (lmin > 0 && L > lmin) {  // a long coarse row: k_gal_long adds its count
+        if (pass == 0 && lane == 0) cnt[E] = 0;
+        return;
+    }
     if (L > LMAX) {  // more candidates than LDS slots: k_gal's scratch path
         gal_row<G>(pass, E, lane, rp, ci, v, agg, p, e0, e1, s0, L0, s1, L1, cnt, crp, cci, cv, gF, gU, false);
         return;
@@ -1593,7 +1663,7 @@ namespace {
 template <typename Key>
 unsigned long long *seg_sort(hipStream_t s, const SegList &seg, int maxlen, Key key, unsigned long long *k0,
                              unsigned long long *k1) {
-    hipLaunchKernelGGL((k_seg_sort_chunks<Key>), dim3(kSegGrid), dim3(kBlock), 0, s, seg, key, k0);
+    hipLaunchKernelGGL((k_seg_sort_chunks<Key>), dim3(kSegGrid), dim3(kSortThreads), 0, s, seg, key, k0);
     for (long long run = kSegChunk; run < maxlen; run *= 2) {
         hipLaunchKernelGGL(k_seg_merge, dim3(kSegGrid), dim3(kBlock), 0, s, seg, (int)run, k0, k1);
         std::swap(k0, k1);
@@ -1624,9 +1694,9 @@ void launch_gal_long_sort(hipStream_t s, const SegList &seg, int maxlen, const i
 
 void launch_gal_long(hipStream_t s, int pass, const SegList &seg, const unsigned long long *sorted, const int *rp,
                      const int *ci, const double *v, const int *agg, const double *p, const int *mem2, int *cnt,
-                     const int *crp, int *cci, double *cv) {
-    hipLaunchKernelGGL(k_gal_long, dim3(256), dim3(kSegBlock), 0, s, pass, seg, sorted, rp, ci, v, agg, p, mem2, cnt,
-                       crp, cci, cv);
+                     int *cc, const int *crp, int *cci, double *cv) {
+    hipLaunchKernelGGL(k_gal_long, dim3(kSegGrid), dim3(kSegBlock), 0, s, pass, seg, sorted, rp, ci, v, agg, p, mem2,
+                       cnt, cc, crp, cci, cv);
 }
 
 void launch_long_abs(hipStream_t s, const LongRows &lr, const int *rp, const double *v, double *part, float *v32) {
