@@ -145,6 +145,9 @@ def main():
                         setup_cls[k][1] += ms / nwarm
                         setup_cls[k][2] += by / nwarm
     dom = max(SINGLE_KERNEL, key=share.get)
+    # the dominant solve kernel (the bandwidth-bound part), timed in a leg of its
+    # own when the step's dominant kernel is a setup kernel
+    dom_solve = max([k for k in SINGLE_KERNEL if k in SOLVE_CLASSES], key=share.get)
     log("event time per step by class (fp32 cycle, ms): "
         + ", ".join(f"{k} {v:.3f}" for k, v in sorted(share.items(), key=lambda kv: -kv[1])) + f"; dominant {dom}")
 
@@ -153,10 +156,12 @@ def main():
     # events on the library's stream, for the roofline (all legs launch every
     # kernel eagerly: faster here than replaying the iteration from a graph)
     results = {}
-    for leg in ("fp32", "fp64", "roofline"):
+    legs = ("fp32", "fp64", "roofline") + (("roofline_solve",) if dom_solve != dom else ())
+    for leg in legs:
         prec = "fp64" if leg == "fp64" else "fp32"
-        mask = bcm.PROF[dom] if leg == "roofline" else 0
-        kw = dict(graph=False) if leg == "roofline" else {}
+        cls = dom_solve if leg == "roofline_solve" else dom
+        mask = bcm.PROF[cls] if leg.startswith("roofline") else 0
+        kw = dict(graph=False) if leg.startswith("roofline") else {}
         tot_l, tot_ms, tot_b = 0, 0.0, 0.0
         infos = []
         torch.cuda.synchronize()
@@ -164,8 +169,8 @@ def main():
         for _ in range(args.steps):
             info, prof = step(prec, mask, **kw)
             infos.append(info)
-            if dom in prof:
-                l_, ms, by = prof[dom]
+            if cls in prof:
+                l_, ms, by = prof[cls]
                 tot_l += l_; tot_ms += ms; tot_b += by
         torch.cuda.synchronize()
         t1 = time.perf_counter()
@@ -187,6 +192,18 @@ def main():
     roofline.update(class_roofline(dom, l_, ms, by))
     roofline.update({"timed_leg": "FP32 cycle, eager launches, HIP events taken by the kernel's own dispatch",
                      "timed_leg_ms_per_step": results["roofline"]["ms_per_step"]})
+    if dom == "setup_suitor":
+        roofline["note"] = ("latency-bound: each proposal that displaces another suitor continues that "
+                            "vertex's list, so the kernel's time is its longest chain of dependent steps (an "
+                            "atomicMax, then a candidate load) times their latency, not its bytes over the "
+                            "bandwidth; the algorithmic bytes count one candidate and one proposal word per vertex")
+    roofline_solve = None
+    if "roofline_solve" in results:
+        l_, ms, by = results["roofline_solve"]["prof"]
+        roofline_solve = {"bound": "hbm", "kernel": KERNEL_OF_CLASS[dom_solve]}
+        roofline_solve.update(class_roofline(dom_solve, l_, ms, by))
+        roofline_solve.update({"timed_leg": "FP32 cycle, eager launches, HIP events taken by the kernel's own "
+                                            "dispatch", "timed_leg_ms_per_step": results["roofline_solve"]["ms_per_step"]})
 
     # the setup against its byte model
     sb = f32["setup_bytes"]
@@ -243,6 +260,8 @@ def main():
         "fp32_over_fp64_solve_byte_model": (f64["iter_bytes"] * f64["iters"]) / (f32["iter_bytes"] * f32["iters"]),
         "roofline": roofline, "setup_roofline": setup_roofline, "cpu_baseline": cpu,
     }
+    if roofline_solve is not None:
+        out["roofline_solve"] = roofline_solve
     if hbm160 is not None:
         out["roofline_hbm_160"] = hbm160
     if grad is not None:

@@ -816,6 +816,10 @@ int build_hierarchy(bcm_handle *h, const bcm_csr *Ain, const double *win) {
             int *idx = h->persist.get_n<int>(L.A.n);
             NOMEM(cv.cur && idx);
             carve_seg(cv, seg_cap(L.A.nnz, lmin), sg);
+            // arrival counters of the single-launch cycle legs (zero between launches)
+            int *cnt = h->persist.get_n<int>((size_t)sg.cap);
+            NOMEM(cnt);
+            launch_fill_i32(s, (size_t)sg.cap, cnt, 0);
             launch_fill_i32(s, 8, sg.ctl, 0);
             launch_find_long(s, L.A.n, L.A.rp, lmin, sg, idx);
             launch_seg_fix(s, sg);
@@ -823,6 +827,7 @@ int build_hierarchy(bcm_handle *h, const bcm_csr *Ain, const double *win) {
             L.lr.idx = idx;
             L.lr.rows = sg.row;
             L.lr.cb = sg.cb;
+            L.lr.cnt = cnt;
             lv_long.push_back(l);
             segs.push_back(sg);
         }

@@ -74,6 +74,9 @@ struct LongRows {
     int nchunks = 0;  // chunks over them
     const int *rows = nullptr, *cb = nullptr, *idx = nullptr;
     void *part = nullptr;  // nchunks partial sums (cycle precision; float64 for the flexible-CG kernels)
+    // Row-wise cycle legs in one launch (chunk blocks after the row blocks):
+    // per long row, an arrival counter of its chunks (zero between launches).
+    int *cnt = nullptr;
 };
 
 // Error flags raised by the validation kernel.

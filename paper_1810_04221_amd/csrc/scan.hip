@@ -1,4 +1,4 @@
-// Exclusive prefix sum of int32 for gfx950: up to 65536 items in one
+// Exclusive prefix sum of int32 for gfx950: up to 16384 items in one
 // workgroup; longer inputs in tiles of 2048 items (256 threads x 8), a pass of
 // tile sums, then one pass in which every tile adds the sums before it and
 // scans itself.  Used to number aggregates by their smallest member
@@ -116,52 +116,59 @@ k_scan_apply(const int *in, int *out, int n, const int *__restrict__ tsum, int n
     }
 }
 
-// Whole scan in one workgroup of 1024 threads for n <= 1024 * C.  Wave w owns
-// C consecutive chunks of 64 items; every load and store of a wave is one
-// contiguous 256-byte access (a single workgroup cannot afford strided ones).
-// Each chunk is scanned across the wave's lanes, chunk totals carry across the
-// wave's chunks, then across the 16 waves.  In place is fine: an item is read
-// and written by the same lane.
-constexpr int kScanSmall = 16384, kScanMid = 65536;
+// Whole scan in one workgroup of 1024 threads for n <= kScanSmall: the items
+// are loaded with contiguous wave accesses into LDS, then thread t scans its
+// kPer consecutive items (t * kPer ...) in registers, the thread totals are
+// scanned across the wave's lanes and then across the 16 waves, and the
+// results go back through LDS to contiguous stores.  LDS rows are padded by
+// one word per kPer items, so the lanes of a wave reading their own runs hit
+// distinct banks.  In place is fine: every item is loaded before any is stored.
+constexpr int kScanSmall = 16384, kPer = kScanSmall / 1024;
 
-template <int C>
+__device__ __forceinline__ int pad_idx(int i) { return i + i / kPer; }
+
 __global__ void __launch_bounds__(1024) k_scan_single(const int *in, int *out, int n, int *__restrict__ total,
                                                      int *__restrict__ max_out) {
+    __shared__ int sh[kScanSmall + kScanSmall / kPer];
     __shared__ int wsum[16], wmax[16];
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    int v[C];
+    const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
     int mx = 0;
 #pragma unroll
-    for (int c = 0; c < C; ++c) {
-        const int e = (wid * C + c) * 64 + lane;
-        v[c] = e < n ? in[e] : 0;
-        mx = max(mx, v[c]);
+    for (int c = 0; c < kPer; ++c) {
+        const int e = c * 1024 + t;
+        const int x = e < n ? in[e] : 0;
+        mx = max(mx, x);
+        sh[pad_idx(e)] = x;
     }
     if (max_out) {
         for (int o = 32; o > 0; o >>= 1) mx = max(mx, __shfl_xor(mx, o, 64));
         if (lane == 0) wmax[wid] = mx;
     }
-    int run = 0;  // the same in every lane of the wave
-#pragma unroll
-    for (int c = 0; c < C; ++c) {
-        const int inc = wave_incl(v[c]);
-        const int x = v[c];
-        v[c] = run + inc - x;  // exclusive prefix within the wave's range
-        run += __shfl(inc, 63, 64);
-    }
-    if (lane == 0) wsum[wid] = run;
     __syncthreads();
-    int base = 0, tot = 0;
+    int v[kPer];
+    int run = 0;
+#pragma unroll
+    for (int c = 0; c < kPer; ++c) {
+        v[c] = run;  // exclusive within the thread's run
+        run += sh[pad_idx(t * kPer + c)];
+    }
+    const int inc = wave_incl(run);
+    if (lane == 63) wsum[wid] = inc;
+    __syncthreads();
+    int base = inc - run, tot = 0;
     for (int w = 0; w < 16; ++w) {
         if (w < wid) base += wsum[w];
         tot += wsum[w];
     }
 #pragma unroll
-    for (int c = 0; c < C; ++c) {
-        const int e = (wid * C + c) * 64 + lane;
-        if (e < n) out[e] = base + v[c];
+    for (int c = 0; c < kPer; ++c) sh[pad_idx(t * kPer + c)] = base + v[c];
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < kPer; ++c) {
+        const int e = c * 1024 + t;
+        if (e < n) out[e] = sh[pad_idx(e)];
     }
-    if (threadIdx.x == 0) {
+    if (t == 0) {
         *total = tot;
         if (max_out) {
             for (int w = 1; w < 16; ++w) mx = max(mx, wmax[w]);
@@ -184,11 +191,7 @@ void scan_exclusive(hipStream_t s, const int *in, int *out, int n, int *total_de
         return;
     }
     if (n <= kScanSmall) {
-        hipLaunchKernelGGL(k_scan_single<kScanSmall / 1024>, dim3(1), dim3(1024), 0, s, in, out, n, total_dev, max_dev);
-        return;
-    }
-    if (n <= kScanMid) {
-        hipLaunchKernelGGL(k_scan_single<kScanMid / 1024>, dim3(1), dim3(1024), 0, s, in, out, n, total_dev, max_dev);
+        hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(1024), 0, s, in, out, n, total_dev, max_dev);
         return;
     }
     hipLaunchKernelGGL(k_scan_reduce, dim3(nt), dim3(kBlock), 0, s, in, n, tsum, tmax);

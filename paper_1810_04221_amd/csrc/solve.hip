@@ -83,6 +83,7 @@ LongView<V> long_view(const LongRows &lr) {
 // the dot product of long row `row` from its chunk sums (every lane of the group gets it)
 template <int G, typename V>
 __device__ __forceinline__ V long_sum(const LongView<V> &lv, int row) {
+    if (!lv.part) return V(0);  // single-launch leg: the row's finishing block writes its result
     const int lane = threadIdx.x % G, t = lv.idx[row];
     V s = V(0);
     for (int c = lv.cb[t] + lane; c < lv.cb[t + 1]; c += G) s += lv.part[c];
@@ -157,10 +158,11 @@ struct FGather {  // a vector entry
 // one row at a time.  Rows longer than G finish in a second loop; rows longer
 // than lv.lmin take their chunk sums instead.
 // s[k] = sum_q a[q] * f(ci[q]) over row rows[k] (rows[k] < 0: empty).
+// *lgm (when given) gets bit k set when row rows[k] is long.
 template <int G, int R, typename V, typename F>
 __device__ __forceinline__ void rows_dot(const int *__restrict__ rp, const int *__restrict__ ci,
                                          const V *__restrict__ a, const int (&rows)[R], V (&s)[R], F f,
-                                         const LongView<V> &lv = LongView<V>()) {
+                                         const LongView<V> &lv = LongView<V>(), int *lgm = nullptr) {
     const int lane = threadIdx.x % G;
     int beg[R], end[R];
     bool lg[R];
@@ -190,6 +192,73 @@ __device__ __forceinline__ void rows_dot(const int *__restrict__ rp, const int *
 #pragma unroll
     for (int k = 0; k < R; ++k)
         if (lg[k]) s[k] = long_sum<G>(lv, rows[k]);
+    if (lgm) {
+        int m = 0;
+#pragma unroll
+        for (int k = 0; k < R; ++k) m |= lg[k] ? (1 << k) : 0;
+        *lgm = m;
+    }
+}
+
+// ----------------------------------------------------------------------------
+// Row-wise cycle legs (up leg, coarsest sweeps) of levels with long rows in
+// one launch.  The blocks after the row kernel's nrb row blocks take the long
+// rows' chunks: each sums its chunk exactly as k_long_dot, stores the partial
+// and counts its arrival on the row; the block that brings a row's last chunk
+// adds the row's partials (all loaded at once, in a fixed order) and writes
+// the row's output (fin).  The row blocks leave the long rows alone.  The partial stores and the
+// arrival count are ordered by device-scope fences (release before the count,
+// acquire after it in the finishing block): a few dozen blocks per launch do
+// this.  The counter is back at zero for the next launch.
+// ----------------------------------------------------------------------------
+struct LongFused {
+    int nrb = 0;  // row blocks; 0: no chunk blocks (long rows summed by a pre-pass)
+    LongRows lr;
+};
+
+template <typename V, typename F, typename Fin>
+__device__ __forceinline__ void long_chunk(int c, const LongRows &lr, const int *__restrict__ rp,
+                                           const int *__restrict__ ci, const V *__restrict__ a, F f, Fin fin) {
+    constexpr int U = kSegChunk / kBlock;
+    __shared__ double lds[16];
+    __shared__ int last;
+    __shared__ V srow;
+    const int t = chunk_owner(lr.cb, lr.n, c);
+    const int row = lr.rows[t];
+    const int q0 = rp[row] + (c - lr.cb[t]) * kSegChunk, q1 = min(q0 + kSegChunk, rp[row + 1]);
+    int j[U];
+    V av[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int q = q0 + (int)threadIdx.x + u * kBlock;
+        const bool in = q < q1;
+        j[u] = in ? ci[q] : row;
+        av[u] = in ? a[q] : V(0);
+    }
+    V sum = V(0);
+#pragma unroll
+    for (int u = 0; u < U; ++u) sum += av[u] * f(j[u]);
+    double d[1] = {(double)sum};
+    block_sum<1>(d, lds);
+    V *part = static_cast<V *>(lr.part);
+    if (threadIdx.x == 0) {
+        part[c] = (V)d[0];
+        __threadfence();  // the partial before the arrival
+        last = atomicAdd(&lr.cnt[t], 1) == lr.cb[t + 1] - lr.cb[t] - 1 ? 1 : 0;
+    }
+    __syncthreads();
+    if (!last) return;
+    __threadfence();  // every chunk's partial after its arrival
+    // the row's partials, all loads at once, added in a fixed order
+    double r[1] = {0.0};
+    for (int k = lr.cb[t] + (int)threadIdx.x; k < lr.cb[t + 1]; k += kBlock) r[0] += (double)part[k];
+    block_sum<1>(r, lds);
+    if (threadIdx.x == 0) {
+        srow = (V)r[0];
+        lr.cnt[t] = 0;
+    }
+    __syncthreads();
+    fin(row, srow);
 }
 
 
@@ -294,26 +363,39 @@ k_restrict(int nc, const int *__restrict__ mem, const V *__restrict__ pr, V *__r
 //   x_j = dinv_j b_j + p_j xc[agg_j]          (pre-smoothed x plus P x_c)
 //   x_i <- x_i + dinv_i (b_i - sum_j a_ij x_j)
 // ----------------------------------------------------------------------------
-template <int G, int R, typename V, typename VB, typename VX>
+template <int G, int R, typename V, typename VB, typename VX, bool LF>
 __global__ void __launch_bounds__(kBlock)
 k_up(int n, const int *__restrict__ rp, const int *__restrict__ ci, const V *__restrict__ a,
      const V *__restrict__ dinv, const V *__restrict__ p, const int *__restrict__ agg,
      const VB *__restrict__ b, const V *__restrict__ xc, VX *__restrict__ x, const double *__restrict__ done,
-     LongView<V> lv) {
+     LongView<V> lv, LongFused lf) {
+    if (LF && (int)blockIdx.x >= lf.nrb) {  // a chunk of a long row (see long_chunk)
+        if (done && *done != 0.0) return;
+        long_chunk<V>((int)blockIdx.x - lf.nrb, lf.lr, rp, ci, a, FProlonged<V, VB>{dinv, p, agg, b, xc},
+                      [&](int i, V sl) {
+                          if (threadIdx.x != 0) return;
+                          const V bi = (V)b[i];
+                          const V di = dinv[i];
+                          const V xi = di * bi + p[i] * xc[agg[i]];
+                          x[i] = (VX)(xi + di * (bi - sl));
+                      });
+        return;
+    }
     // the solve-ended flag is tested before the stores only (as in k_down_seq)
     constexpr int NG = kBlock / G;
     const int lane = threadIdx.x % G;
-    const int base = xcd_block(blockIdx.x, gridDim.x) * NG * R + threadIdx.x / G;
+    const int base = xcd_block(blockIdx.x, LF ? lf.nrb : gridDim.x) * NG * R + threadIdx.x / G;
     int rows[R];
 #pragma unroll
     for (int k = 0; k < R; ++k) rows[k] = base + k * NG < n ? base + k * NG : -1;
     V s[R];
-    rows_dot<G, R, V>(rp, ci, a, rows, s, FProlonged<V, VB>{dinv, p, agg, b, xc}, lv);
+    int lgm = 0;
+    rows_dot<G, R, V>(rp, ci, a, rows, s, FProlonged<V, VB>{dinv, p, agg, b, xc}, lv, &lgm);
     if (lane == 0 && !(done && *done != 0.0)) {
 #pragma unroll
         for (int k = 0; k < R; ++k) {
             const int i = rows[k];
-            if (i < 0) continue;
+            if (i < 0 || (LF && ((lgm >> k) & 1))) continue;
             const V bi = (V)b[i];
             const V di = dinv[i];
             const V xi = di * bi + p[i] * xc[agg[i]];
@@ -799,29 +881,41 @@ k_tail(int kt, int nl, const TailLevel *__restrict__ tl, const double *__restric
 // rows per group, as in the cycle kernels.  The last sweep of a solve writes
 // the caller's x (type VX) instead of xn.  The solve-ended flag is tested
 // before the stores only (as in k_down_seq).
-template <int G, int R, typename VB, typename VX>
+template <int G, int R, typename VB, typename VX, bool LF>
 __global__ void __launch_bounds__(kBlock)
 k_jacobi_sweep(int n, const int *__restrict__ rp, const int *__restrict__ ci, const double *__restrict__ a,
                const double *__restrict__ dinv, const VB *__restrict__ b, const double *__restrict__ xo,
                double *__restrict__ xn, VX *__restrict__ xout, int first, const double *__restrict__ done,
-               LongView<double> lv) {
+               LongView<double> lv, LongFused lf) {
+    if (LF && (int)blockIdx.x >= lf.nrb) {  // a chunk of a long row (see long_chunk); never the first sweep
+        if (done && *done != 0.0) return;
+        long_chunk<double>((int)blockIdx.x - lf.nrb, lf.lr, rp, ci, a, FGather<double, double>{xo},
+                           [&](int i, double sl) {
+                               if (threadIdx.x != 0) return;
+                               const double v = xo[i] + dinv[i] * ((double)b[i] - sl);
+                               if (xout) xout[i] = (VX)v;
+                               else xn[i] = v;
+                           });
+        return;
+    }
     const int lane = threadIdx.x % G;
-    const int g = (xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x) / G;
+    const int g = (xcd_block(blockIdx.x, LF ? lf.nrb : gridDim.x) * kBlock + threadIdx.x) / G;
     int rows[R];
 #pragma unroll
     for (int k = 0; k < R; ++k) rows[k] = g * R + k < n ? g * R + k : -1;
     double s[R];
+    int lgm = 0;
     if (first) {
 #pragma unroll
         for (int k = 0; k < R; ++k) s[k] = 0.0;
     } else {
-        rows_dot<G, R, double>(rp, ci, a, rows, s, FGather<double, double>{xo}, lv);
+        rows_dot<G, R, double>(rp, ci, a, rows, s, FGather<double, double>{xo}, lv, &lgm);
     }
     const bool live = !(done && *done != 0.0);
 #pragma unroll
     for (int k = 0; k < R; ++k) {
         const int i = rows[k];
-        if (lane == k % G && i >= 0 && live) {
+        if (lane == k % G && i >= 0 && live && !(LF && ((lgm >> k) & 1))) {
             const double v = (first ? 0.0 : xo[i]) + dinv[i] * ((double)b[i] - s[k]);
             if (xout) xout[i] = (VX)v;
             else xn[i] = v;
@@ -1009,17 +1103,30 @@ void long_pre(hipStream_t s, const Level &L, const V *a, F f, const double *done
                            static_cast<V *>(L.lr.part), done);
 }
 
+// The long rows of a level in the row kernel's own launch (LongFused), when
+// the level has their arrival counters.
+LongFused long_fused(const Level &L, int nrb) {
+    LongFused lf;
+    if (L.lr.n > 0 && L.lr.cnt) {
+        lf.nrb = nrb;
+        lf.lr = L.lr;
+    }
+    return lf;
+}
+
 template <int G, typename V, typename VB>
 void down_dispatch(hipStream_t s, const Level &L, const V *a, const V *dinv, const V *p, const VB *b, V *bc,
                    const double *done) {
     const int S = L.mstride;
     const dim3 grid(blocks_for((long long)L.nc * G));
     const LongView<V> lv = long_view<V>(L.lr);
+    // (the down leg keeps the pre-pass: its finishing block would have to
+    // build a whole aggregate, which measured slower than the separate launch)
     long_pre(s, L, a, FScaled<V, VB>{dinv, b}, done);
     auto seq = [&](auto sc) {
         constexpr int SS = decltype(sc)::value;
-        launch_k((k_down_seq<G, SS, V, VB>), grid, dim3(kBlock), s, L.nc, L.mem, L.A.rp, L.A.ci, a,
-                           dinv, p, b, bc, done, lv);
+        launch_k((k_down_seq<G, SS, V, VB>), grid, dim3(kBlock), s, L.nc, L.mem, L.A.rp, L.A.ci, a, dinv, p, b, bc,
+                 done, lv);
     };
     if (S == 1) seq(std::integral_constant<int, 1>{});
     else if (S == 2) seq(std::integral_constant<int, 2>{});
@@ -1092,13 +1199,24 @@ void up_t(hipStream_t s, const Level &L, const V *a, const V *dinv, const V *p, 
         return;
     }
     if (part == 1) return;
-    long_pre(s, L, a, FProlonged<V, VB>{dinv, p, L.agg, b, xc}, done);
     with_G(L.G, [&](auto gc) {
         constexpr int g = decltype(gc)::value;
         constexpr int R = 2;
-        launch_k((k_up<g, R, V, VB, VX>), dim3(blocks_for(((long long)L.A.n * g + R - 1) / R)),
-                           dim3(kBlock), s, L.A.n, L.A.rp, L.A.ci, a, dinv, p, L.agg, b, xc, x, done,
-                           long_view<V>(L.lr));
+        dim3 grid(blocks_for(((long long)L.A.n * g + R - 1) / R));
+        LongView<V> lv = long_view<V>(L.lr);
+        const LongFused lf = long_fused(L, (int)grid.x);
+        if (lf.nrb > 0) {
+            grid.x += L.lr.nchunks;
+            lv.part = nullptr;
+        } else {
+            long_pre(s, L, a, FProlonged<V, VB>{dinv, p, L.agg, b, xc}, done);
+        }
+        if (lf.nrb > 0)
+            launch_k((k_up<g, R, V, VB, VX, true>), grid, dim3(kBlock), s, L.A.n, L.A.rp, L.A.ci, a, dinv, p, L.agg, b,
+                     xc, x, done, lv, lf);
+        else
+            launch_k((k_up<g, R, V, VB, VX, false>), grid, dim3(kBlock), s, L.A.n, L.A.rp, L.A.ci, a, dinv, p, L.agg,
+                     b, xc, x, done, lv, lf);
     });
 }
 
@@ -1120,10 +1238,23 @@ void coarse_t(hipStream_t s, const Level &L, int sweeps, const VB *b, VX *x, dou
         constexpr int g = decltype(gc)::value;
         constexpr int R = 2;
         for (int t = 0; t < sweeps; ++t) {
-            if (t > 0) long_pre(s, L, (const double *)L.A.v, FGather<double, double>{xo}, done);
-            hipLaunchKernelGGL((k_jacobi_sweep<g, R, VB, VX>), dim3(blocks_for(((long long)n + R - 1) / R * g)),
-                               dim3(kBlock), 0, s, n, L.A.rp, L.A.ci, L.A.v, L.dinv, b, xo, xn,
-                               t == sweeps - 1 ? x : (VX *)nullptr, t == 0 ? 1 : 0, done, long_view<double>(L.lr));
+            dim3 grid(blocks_for(((long long)n + R - 1) / R * g));
+            LongView<double> lv = long_view<double>(L.lr);
+            // (the first sweep, from zero, has no products)
+            const LongFused lf = t > 0 ? long_fused(L, (int)grid.x) : LongFused();
+            if (lf.nrb > 0) {
+                grid.x += L.lr.nchunks;
+                lv.part = nullptr;
+            } else if (t > 0) {
+                long_pre(s, L, (const double *)L.A.v, FGather<double, double>{xo}, done);
+            }
+            if (lf.nrb > 0)
+                hipLaunchKernelGGL((k_jacobi_sweep<g, R, VB, VX, true>), grid, dim3(kBlock), 0, s, n, L.A.rp, L.A.ci,
+                                   L.A.v, L.dinv, b, xo, xn, t == sweeps - 1 ? x : (VX *)nullptr, 0, done, lv, lf);
+            else
+                hipLaunchKernelGGL((k_jacobi_sweep<g, R, VB, VX, false>), grid, dim3(kBlock), 0, s, n, L.A.rp, L.A.ci,
+                                   L.A.v, L.dinv, b, xo, xn, t == sweeps - 1 ? x : (VX *)nullptr, t == 0 ? 1 : 0, done,
+                                   lv, lf);
             double *tmp = xo; xo = xn; xn = tmp;
         }
     });
