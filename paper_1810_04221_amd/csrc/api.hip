@@ -929,7 +929,7 @@ int build_hierarchy(bcm_handle *h, const bcm_csr *Ain, const double *win) {
             const size_t ne = (size_t)tots[t];
             if (tots[32 + t] <= 32767) {
                 L.E.sd = h->persist.get_n<short>(ne);
-                L.E.su = h->persist.get_n<short>(ne / kSlice);
+                L.E.su = h->persist.get_n<int>(ne / kSlice);
                 L.E.uni = uni[t];
                 NOMEM(L.E.sd && L.E.su);
                 L.E.mixed = ne ? (double)tots[96 + t] / (double)ne : 1.0;

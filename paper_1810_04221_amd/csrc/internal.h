@@ -146,7 +146,7 @@ struct Sell {
     // int16 copies only: uni[s] = 1 when the rows of slice s share one list of
     // column offsets, held in su from index sp[s] / 64 (one per slot column)
     int *uni = nullptr;
-    short *su = nullptr;
+    int *su = nullptr;
     double *sv = nullptr;
     float *sv32 = nullptr;
     double mixed = 1.0;  // fraction of the slots in slices that are not uniform
@@ -328,7 +328,7 @@ void launch_sell_width(hipStream_t s, int n, const int *rp, const int *ci, const
                        int *maxoff, int *inexact, int *mixed);
 // fills the slots: int32 columns into sc, or int16 offsets into sd (one is null)
 void launch_sell_fill(hipStream_t s, int n, const int *rp, const int *ci, const double *v, const int *sp,
-                      const int *uni, short *su, int *sc, short *sd, double *sv, float *sv32);
+                      const int *uni, int *su, int *sc, short *sd, double *sv, float *sv32);
 void launch_fill_i32(hipStream_t s, size_t n, int *dst, int val);
 void launch_fill_u64(hipStream_t s, size_t n, unsigned long long *dst, unsigned long long val);
 void launch_copy_f64(hipStream_t s, size_t n, const double *src, double *dst);

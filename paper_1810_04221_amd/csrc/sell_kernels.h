@@ -18,7 +18,7 @@ __device__ __forceinline__ int sell_col(short d, int i) { return i + (int)d; }
 // steps.  Accumulates into s left to right.  Uni: column offsets from the
 // slice's shared list u, else from the per-entry columns c.
 template <int kB, bool Uni, typename V, typename S, typename I, typename F>
-__device__ __forceinline__ V sell_slots(const S *a, const short *u, const I *c, int n, int i, int w, V s, F f) {
+__device__ __forceinline__ V sell_slots(const S *a, const int *u, const I *c, int n, int i, int w, V s, F f) {
     for (int k0 = 0; k0 < w; k0 += kB) {
         S av[kB];
         V fv[kB];
@@ -27,7 +27,7 @@ __device__ __forceinline__ V sell_slots(const S *a, const short *u, const I *c, 
             const int k = min(k0 + t, w - 1);
             av[t] = a[k * kSlice];
             if (Uni) {
-                const int cc = i + (int)u[k];
+                const int cc = i + u[k];
                 fv[t] = f((unsigned)cc < (unsigned)n ? cc : i);
             } else {
                 fv[t] = f(sell_col(c[k * kSlice], i));
@@ -53,7 +53,7 @@ __device__ __forceinline__ V sell_slots(const S *a, const short *u, const I *c, 
 // leave it).
 template <typename V, typename S, typename I, int kB, typename F>
 __device__ __forceinline__ V sell_row(int n, const int *__restrict__ sp, const int *__restrict__ uni,
-                                      const short *__restrict__ su, const I *__restrict__ sc,
+                                      const int *__restrict__ su, const I *__restrict__ sc,
                                       const S *__restrict__ sv, int i, F f) {
     // uni is never null (all zero without uniform slices).  kB = 16 on levels
     // of long rows (a few dozen entries): half as many dependent memory round
@@ -61,7 +61,7 @@ __device__ __forceinline__ V sell_row(int n, const int *__restrict__ sp, const i
     const int sl = __builtin_amdgcn_readfirstlane(i / kSlice), lane = i % kSlice;
     const int uf = uni[sl], beg = sp[sl], w = (sp[sl + 1] - beg) / kSlice;
     const S *a = sv + beg + lane;
-    const short *u = su + beg / kSlice;
+    const int *u = su + beg / kSlice;
     const I *c = sc + beg + lane;
     if (uf) return sell_slots<kB, true>(a, u, c, n, i, w, V(0), f);
     return sell_slots<kB, false>(a, u, c, n, i, w, V(0), f);
@@ -75,7 +75,7 @@ __device__ __forceinline__ V sell_row(int n, const int *__restrict__ sp, const i
 template <typename V, typename VB, typename I, typename S, int kB>
 __global__ void __launch_bounds__(kBlock)
 k_down_res_sell(int n, const int *__restrict__ sp, const int *__restrict__ uni,
-                const short *__restrict__ su, const I *__restrict__ sc,
+                const int *__restrict__ su, const I *__restrict__ sc,
                 const S *__restrict__ sv,
                 const V *__restrict__ dinv, const V *__restrict__ p, const VB *__restrict__ b, V *__restrict__ pr,
                 const V *__restrict__ y, const double *__restrict__ done) {
@@ -95,7 +95,7 @@ k_down_res_sell(int n, const int *__restrict__ sp, const int *__restrict__ uni,
 template <typename V, typename VB, typename VX, typename I, typename S, int kB>
 __global__ void __launch_bounds__(kBlock)
 k_smooth_sell(int n, const int *__restrict__ sp, const int *__restrict__ uni,
-                const short *__restrict__ su, const I *__restrict__ sc,
+                const int *__restrict__ su, const I *__restrict__ sc,
               const S *__restrict__ sv,
               const V *__restrict__ dinv, const VB *__restrict__ b, const V *__restrict__ xp, VX *__restrict__ x,
               const double *__restrict__ done) {
@@ -113,7 +113,7 @@ k_smooth_sell(int n, const int *__restrict__ sp, const int *__restrict__ uni,
 template <typename I, typename S, int kB>
 __global__ void __launch_bounds__(kBlock)
 k_resid_sell(int n, const int *__restrict__ sp, const int *__restrict__ uni,
-                const short *__restrict__ su, const I *__restrict__ sc,
+                const int *__restrict__ su, const I *__restrict__ sc,
              const S *__restrict__ sv,
              const double *__restrict__ b, const double *__restrict__ u, double *__restrict__ r,
              double *__restrict__ partials) {
@@ -133,7 +133,7 @@ k_resid_sell(int n, const int *__restrict__ sp, const int *__restrict__ uni,
 template <typename I, typename S, int kB>
 __global__ void __launch_bounds__(kBlock)
 k_spmv_dots_sell(int n, const int *__restrict__ sp, const int *__restrict__ uni,
-                const short *__restrict__ su, const I *__restrict__ sc,
+                const int *__restrict__ su, const I *__restrict__ sc,
                  const S *__restrict__ sv,
                  const double *__restrict__ w, const double *__restrict__ r, const double *__restrict__ q,
                  double *__restrict__ v, double *__restrict__ partials, const double *__restrict__ done) {

@@ -771,7 +771,7 @@ k_sell_width(int n, const int *__restrict__ rp, const int *__restrict__ ci, cons
 // (the column the uniform read takes too).
 __global__ void __launch_bounds__(kBlock)
 k_sell_fill(int n, const int *__restrict__ rp, const int *__restrict__ ci, const double *__restrict__ v,
-            const int *__restrict__ sp, const int *__restrict__ uni, short *__restrict__ su, int *__restrict__ sc,
+            const int *__restrict__ sp, const int *__restrict__ uni, int *__restrict__ su, int *__restrict__ sc,
             short *__restrict__ sd, double *__restrict__ sv, float *__restrict__ sv32) {
     const int i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
@@ -792,10 +792,10 @@ k_sell_fill(int n, const int *__restrict__ rp, const int *__restrict__ ci, const
         const int it = sl * kSlice + t, qt = rp[it];
         int *T = tmpl[(threadIdx.x % kBlock) / kSlice];
         if (lane == t) {  // the template row is always active; the slice's last rows may not be
-            short *u = su + sp[sl] / kSlice;
+            int *u = su + sp[sl] / kSlice;
             for (int k = 0; k < w; ++k) {
                 const int o = ci[qt + k] - it;
-                u[k] = (short)o;
+                u[k] = o;
                 T[k] = o;
             }
         }
@@ -1611,7 +1611,7 @@ void launch_sell_width(hipStream_t s, int n, const int *rp, const int *ci, const
 }
 
 void launch_sell_fill(hipStream_t s, int n, const int *rp, const int *ci, const double *v, const int *sp,
-                      const int *uni, short *su, int *sc, short *sd, double *sv, float *sv32) {
+                      const int *uni, int *su, int *sc, short *sd, double *sv, float *sv32) {
     hipLaunchKernelGGL(k_sell_fill, dim3(blocks_for(n)), dim3(kBlock), 0, s, n, rp, ci, v, sp, uni, su, sc, sd, sv,
                        sv32);
 }
