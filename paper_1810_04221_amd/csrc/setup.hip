@@ -45,10 +45,6 @@ __device__ __forceinline__ void seg_append(const SegList &sg, int row, int len) 
     }
 }
 
-// Rows j of at most kSymScan entries are searched for the transposed entry
-// by loading all their columns at once (no chain of dependent loads).
-constexpr int kSymScan = 8;
-
 template <int G>
 __global__ void __launch_bounds__(kBlock)
 k_validate(int n, int nnz, const int *__restrict__ rp, const int *__restrict__ ci,
@@ -93,21 +89,12 @@ k_validate(int n, int nnz, const int *__restrict__ rp, const int *__restrict__ c
             const int s2 = rp[j], e2 = rp[j + 1];
             int found = -1;
             if (s2 >= 0 && e2 >= s2 && (nnz < 0 || e2 <= nnz)) {
-                if (e2 - s2 <= kSymScan) {  // a short row j: all its columns in one round of loads
-                    int cs[kSymScan];
-#pragma unroll
-                    for (int t = 0; t < kSymScan; ++t) cs[t] = s2 + t < e2 ? ci[s2 + t] : -1;
-#pragma unroll
-                    for (int t = 0; t < kSymScan; ++t)
-                        if (cs[t] == row) found = s2 + t;
-                } else {
-                    int lo = s2, hi = e2 - 1;
-                    while (lo <= hi) {
-                        const int mid = (lo + hi) >> 1;
-                        const int cm = ci[mid];
-                        if (cm == row) { found = mid; break; }
-                        if (cm < row) lo = mid + 1; else hi = mid - 1;
-                    }
+                int lo = s2, hi = e2 - 1;
+                while (lo <= hi) {
+                    const int mid = (lo + hi) >> 1;
+                    const int cm = ci[mid];
+                    if (cm == row) { found = mid; break; }
+                    if (cm < row) lo = mid + 1; else hi = mid - 1;
                 }
             }
             if (found < 0 || __double_as_longlong(v[found]) != __double_as_longlong(a)) f |= kErrAsym;
@@ -1000,21 +987,12 @@ k_long_validate(int n, int nnz, const int *__restrict__ rp, const int *__restric
             const int s2 = rp[j], e2 = rp[j + 1];
             int found = -1;
             if (s2 >= 0 && e2 >= s2 && (nnz < 0 || e2 <= nnz)) {
-                if (e2 - s2 <= kSymScan) {  // a short row j: all its columns in one round of loads
-                    int cs[kSymScan];
-#pragma unroll
-                    for (int t = 0; t < kSymScan; ++t) cs[t] = s2 + t < e2 ? ci[s2 + t] : -1;
-#pragma unroll
-                    for (int t = 0; t < kSymScan; ++t)
-                        if (cs[t] == row) found = s2 + t;
-                } else {
-                    int lo = s2, hi = e2 - 1;
-                    while (lo <= hi) {
-                        const int mid = (lo + hi) >> 1;
-                        const int cm = ci[mid];
-                        if (cm == row) { found = mid; break; }
-                        if (cm < row) lo = mid + 1; else hi = mid - 1;
-                    }
+                int lo = s2, hi = e2 - 1;
+                while (lo <= hi) {
+                    const int mid = (lo + hi) >> 1;
+                    const int cm = ci[mid];
+                    if (cm == row) { found = mid; break; }
+                    if (cm < row) lo = mid + 1; else hi = mid - 1;
                 }
             }
             if (found < 0 || __double_as_longlong(v[found]) != __double_as_longlong(a)) f |= kErrAsym;
