@@ -75,6 +75,9 @@ def main():
     ap.add_argument("--workload", default="G2")
     ap.add_argument("--scale", type=float, default=1.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--min-ratio", type=float, default=0.0,
+                    help="also stop coarsening at the first level formed with n_(k-1)/n_k below this "
+                         "(a rule of this library, not the paper's; 0 = Section 5's rule alone)")
     ap.add_argument("--no-hbm-point", action="store_true",
                     help="skip the 160^3 roofline point (HBM-bound finest-level kernels)")
     ap.add_argument("--calibration-copy-mb", type=int, default=0,
@@ -116,6 +119,7 @@ def main():
         del src, dst
 
     def step(precision, mask, wvec=None, **kw):
+        kw.setdefault("min_ratio", args.min_ratio)
         h = bcm.Hierarchy(rp, ci, va, w if wvec is None else wvec, max_coarse=c["max_coarse"],
                           precision=precision, profile=mask, **kw)
         h.solve(b, tol=tol)
@@ -247,7 +251,8 @@ def main():
         "vs_baseline": None, "dtype": "f32 cycle + f64 outer CG", "data": "synthetic",
         "config": {"workload": f"3-D Poisson 7-point {c['name']}, n={n}, nnz={len(c['col'])}, b~U[-1,1) seed 1, "
                                f"w=1, coarsest<{c['max_coarse'] + 1} rows, tol {tol:g}, FP32 V-cycle in FP64 FCG"
-                   if args.workload == "G2" else c["name"]},
+                   if args.workload == "G2" else c["name"] + (f", coarsening also stopped at n_(k-1)/n_k < {args.min_ratio:g}"
+                                                               if args.min_ratio > 1 else "")},
         "setup_ms": f32["t_setup_ms"], "solve_ms": f32["t_solve_ms"], "iters": f32["iters"],
         "relres": f32["relres"], "levels": f32["levels"], "vcmplx": f32["vcmplx"],
         "solve_hbm_frac": f32["solve_hbm_frac"],
