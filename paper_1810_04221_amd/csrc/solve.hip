@@ -54,6 +54,13 @@ void with_sell(const Sell &E, Fn &&fn) {
     }
 }
 
+// Wide levels (batches of 16) with at most kSplitRows rows take the
+// slot-split kernels: at one thread per row they would hold fewer than about
+// 32 waves per CU.  Larger wide levels fill the chip already, and there the
+// split's LDS reduction costs more than it gains.
+constexpr int kSplitRows = 1 << 19;
+inline bool split_slots(const Level &L, int kb) { return kb == 16 && L.A.n <= kSplitRows; }
+
 // ----------------------------------------------------------------------------
 // Long rows (longer than the level's lmin = kLongFactor * G): their dot
 // products are summed by a pre-pass over chunks of kSegChunk entries, one
@@ -263,6 +270,7 @@ __device__ __forceinline__ void long_chunk(int c, const LongRows &lr, const int 
 
 
 #include "sell_kernels.h"
+#include "sell_split.h"
 
 // ----------------------------------------------------------------------------
 // Down leg of the cycle at level k (Algorithm 1, zero initial guess):
@@ -1151,8 +1159,12 @@ void down_t(hipStream_t s, const Level &L, const V *a, const V *dinv, const V *p
             with_sell<V>(L.E, [&](auto *ix, auto *vals, auto kb) {
                 using I = std::remove_const_t<std::remove_pointer_t<decltype(ix)>>;
                 using S = std::remove_const_t<std::remove_pointer_t<decltype(vals)>>;
-                launch_k((k_down_res_sell<V, VB, I, S, decltype(kb)::value>), dim3(blocks_for(L.A.n)), dim3(kBlock), s,
-                                   L.A.n, L.E.sp, L.E.uni, L.E.su, ix, vals, dinv, p, b, pr, (const V *)y, done);
+                if (split_slots(L, decltype(kb)::value))
+                    launch_k((k_down_res_sell_p<V, VB, I, S, 8>), dim3(L.E.nslices), dim3(kBlock), s, L.A.n, L.E.sp,
+                             L.E.uni, L.E.su, ix, vals, dinv, p, b, pr, (const V *)y, done);
+                else
+                    launch_k((k_down_res_sell<V, VB, I, S, decltype(kb)::value>), dim3(blocks_for(L.A.n)), dim3(kBlock),
+                             s, L.A.n, L.E.sp, L.E.uni, L.E.su, ix, vals, dinv, p, b, pr, (const V *)y, done);
             });
         }
         if (part == 1) return;
@@ -1184,8 +1196,12 @@ void up_t(hipStream_t s, const Level &L, const V *a, const V *dinv, const V *p, 
             with_sell<V>(L.E, [&](auto *ix, auto *vals, auto kb) {
                 using I = std::remove_const_t<std::remove_pointer_t<decltype(ix)>>;
                 using S = std::remove_const_t<std::remove_pointer_t<decltype(vals)>>;
-                launch_k((k_smooth_sell<V, VB, VX, I, S, decltype(kb)::value>), dim3(blocks_for(L.A.n)), dim3(kBlock), s,
-                                   L.A.n, L.E.sp, L.E.uni, L.E.su, ix, vals, dinv, b, xp, x, done);
+                if (split_slots(L, decltype(kb)::value))
+                    launch_k((k_smooth_sell_p<V, VB, VX, I, S, 8>), dim3(L.E.nslices), dim3(kBlock), s, L.A.n, L.E.sp,
+                             L.E.uni, L.E.su, ix, vals, dinv, b, xp, x, done);
+                else
+                    launch_k((k_smooth_sell<V, VB, VX, I, S, decltype(kb)::value>), dim3(blocks_for(L.A.n)),
+                             dim3(kBlock), s, L.A.n, L.E.sp, L.E.uni, L.E.su, ix, vals, dinv, b, xp, x, done);
             });
             return;
         }
