@@ -1070,6 +1070,16 @@ int build_hierarchy(bcm_handle *h, const bcm_csr *Ain, const double *win) {
     h->red_blocks = reduce_blocks(n);
     h->partials = h->persist.get_n<double>(4 * (size_t)h->red_blocks);
     NOMEM(h->r && h->w && h->d && h->v && h->q && h->u && h->scal && h->partials);
+    {
+        const Level &F = h->lv[0];
+        // levels whose down leg gathers dinv o b (long rows) get it from the
+        // update instead of a launch of its own; on the others the extra
+        // stream through the update costs as much as the second gather saves
+        if (h->nl > 1 && F.E.sp && F.xp && F.yb && (F.mstride == 2 || F.mstride == 4)) {
+            h->y0 = h->persist.get((P.precision == BCM_FP32_CYCLE ? sizeof(float) : sizeof(double)) * (size_t)n);
+            NOMEM(h->y0);
+        }
+    }
     if (P.cycle == BCM_KCYCLE) {
         h->kpart = h->persist.get_n<double>(3 * (size_t)kKPartBlocks);
         h->ks = h->persist.get_n<double>(8 * (size_t)h->nl);
@@ -1115,8 +1125,10 @@ double bytes_down(const bcm_handle *h, int k) {
     const bool sell = L.E.sp && L.xp && (L.mstride == 2 || L.mstride == 4);
     const double base = 4 * (n + 1) + (index_bytes(L, sell) + value_bytes(L, sell, f32)) * z + sb * n + 2 * sv * n +
                         4.0 * nc * L.mstride + sv * nc;
-    // split leg: p r written and read; with yb, dinv o b formed first (b, dinv read, y written)
-    return sell ? base + 2 * sv * n + (L.yb ? (sb + 2 * sv) * n : 0.0) : base;
+    // split leg: p r written and read; with yb, dinv o b formed first (b, dinv read, y written),
+    // except on the finest level with y0, where the flexible-CG update forms it
+    const bool scale = L.yb && !(k == 0 && h->y0);
+    return sell ? base + 2 * sv * n + (scale ? (sb + 2 * sv) * n : 0.0) : base;
 }
 // up leg: fused k_up, or k_prolong + k_smooth on large levels (xp written and read once)
 double bytes_up(const bcm_handle *h, int k) {
@@ -1187,7 +1199,11 @@ double bytes_spmv_dots(const bcm_handle *h) {
     // algorithmic: every stored entry once (ELL padding not counted)
     return 4 * (n + 1) + (index_bytes(L, L.E.sp != nullptr) + value_bytes(L, L.E.sp != nullptr, false)) * z + 32 * n;
 }
-double bytes_update(const bcm_handle *h) { return 80.0 * h->lv[0].A.n; }
+// ten float64 vector streams; with y0, dinv read and y0 written in the cycle's type
+double bytes_update(const bcm_handle *h) {
+    const double sv = h->prm.precision == BCM_FP32_CYCLE ? 4 : 8;
+    return (80.0 + (h->y0 ? 2 * sv : 0.0)) * h->lv[0].A.n;
+}
 
 // Bytes of one bracket of a class launched once per iteration (0..4).
 double class_bytes(const bcm_handle *h, int cls) {
@@ -1363,7 +1379,9 @@ void cycle_level(bcm_handle *h, Prof &pf, int k, const double *done, int iter) {
 
 // --------------------------------------------------------------- V-cycle
 // One cycle of Algorithm 1 from a zero guess: z = B(r).  done: see launch_down.
-void vcycle(bcm_handle *h, Prof &pf, const double *rin, double *wout, const double *done, int iter) {
+// y0: dinv o r of the finest level already formed (the update's h->y0), or null.
+void vcycle(bcm_handle *h, Prof &pf, const double *rin, double *wout, const double *done, int iter,
+            const void *y0 = nullptr) {
     hipStream_t s = h->s;
     const int fp32 = h->prm.precision == BCM_FP32_CYCLE;
     const int nl = h->nl;
@@ -1379,7 +1397,7 @@ void vcycle(bcm_handle *h, Prof &pf, const double *rin, double *wout, const doub
         // finest level here (f64 in/out), coarse levels recursively
         Level &L = h->lv[0], &N = h->lv[1];
         int e = pf.begin(0);
-        launch_down(s, L, fp32, rin, N.b, 1, done, 1);
+        launch_down(s, L, fp32, rin, N.b, 1, done, 1, y0);
         pf.end(0, e, class_bytes(h, 0), iter);
         launch_down(s, L, fp32, rin, N.b, 1, done, 2);
         coarse_solve(h, pf, 0, done, iter);
@@ -1397,7 +1415,7 @@ void vcycle(bcm_handle *h, Prof &pf, const double *rin, double *wout, const doub
         const int io = (k == 0 || !fp32) ? 1 : 0;
         if (k == 0) {  // the finest level's main kernel alone is class 0
             int e = pf.begin(0);
-            launch_down(s, L, fp32, bk, h->lv[1].b, io, done, 1);
+            launch_down(s, L, fp32, bk, h->lv[1].b, io, done, 1, y0);
             pf.end(0, e, class_bytes(h, 0), iter);
             launch_down(s, L, fp32, bk, h->lv[1].b, io, done, 2);
         } else {
@@ -1446,6 +1464,11 @@ void vcycle(bcm_handle *h, Prof &pf, const double *rin, double *wout, const doub
 // the handle's vectors into HIP graphs: one graph, or with prof_cls >= 0 (a
 // class bracketed once per iteration) three: before the class, the class's
 // kernels, after it.  Recaptured when prof_cls changes.
+// the finest level's dinv in the cycle's type (read by the update with h->y0)
+const void *y0_dinv(const bcm_handle *h) {
+    return h->prm.precision == BCM_FP32_CYCLE ? (const void *)h->lv[0].dinv32 : (const void *)h->lv[0].dinv;
+}
+
 void destroy_iteration_graphs(bcm_handle *h) {
     for (auto &g : h->iter_exec)
         if (g) { (void)hipGraphExecDestroy(g); g = nullptr; }
@@ -1464,13 +1487,14 @@ int capture_iteration(bcm_handle *h, int prof_cls) {
     hipStream_t keep = h->s;
     h->s = h->cap;
     sc.begin();
-    vcycle(h, gp, h->r, h->w, h->scal + 10, 0);
+    vcycle(h, gp, h->r, h->w, h->scal + 10, 0, h->y0);
     int e = gp.begin(2);
     launch_spmv_dots(h->cap, L0, nb, 0, h->w, h->r, h->q, h->v, h->partials, h->scal);
     gp.end(2, e, 0.0, 0);
     launch_finalize(h->cap, 1, nb, 0, h->partials, h->scal);
     e = gp.begin(3);
-    launch_update(h->cap, n, nb, 0, h->w, h->v, h->d, h->u, h->q, h->r, h->partials, h->scal);
+    launch_update(h->cap, n, nb, 0, h->w, h->v, h->d, h->u, h->q, h->r, h->partials, h->scal, y0_dinv(h), h->y0,
+                  h->prm.precision == BCM_FP32_CYCLE);
     gp.end(3, e, 0.0, 0);
     launch_finalize(h->cap, 2, nb, 0, h->partials, h->scal);
     sc.end();
@@ -1563,13 +1587,15 @@ int fcg_run(bcm_handle *h, const double *b, double *x_user, double tol) {
                     ++launched;
                     continue;
                 }
-                vcycle(h, pf, h->r, h->w, done, launched);
+                // the first iteration's r comes from the residual kernel: no y0 yet
+                vcycle(h, pf, h->r, h->w, done, launched, first ? nullptr : h->y0);
                 int e = pf.begin(2);
                 launch_spmv_dots(s, L0, nb, first, h->w, h->r, h->q, h->v, h->partials, h->scal);
                 pf.end(2, e, bytes_spmv_dots(h), launched);
                 launch_finalize(s, 1, nb, first, h->partials, h->scal);
                 e = pf.begin(3);
-                launch_update(s, n, nb, first, h->w, h->v, h->d, x, h->q, h->r, h->partials, h->scal);
+                launch_update(s, n, nb, first, h->w, h->v, h->d, x, h->q, h->r, h->partials, h->scal, y0_dinv(h),
+                              h->y0, h->prm.precision == BCM_FP32_CYCLE);
                 pf.end(3, e, bytes_update(h), launched);
                 launch_finalize(s, 2, nb, 0, h->partials, h->scal);
                 first = 0;

@@ -209,6 +209,8 @@ struct bcm_handle {
     // flexible CG vectors (float64, n of the finest level)
     double *r = nullptr, *w = nullptr, *d = nullptr, *v = nullptr, *q = nullptr;
     double *u = nullptr;                  // iterate of the solve (the caller's x is copied in and out)
+    void *y0 = nullptr;  // dinv o r of the finest level in the cycle's type, written by the update
+                         // (finest levels whose sliced-ELL down leg gathers dinv o b; else null)
     hipStream_t cap = nullptr;            // internal stream used only to capture the iteration graph
     // one general flexible-CG iteration as one graph, or three when one kernel
     // class is profiled (before it, the class, after it); null: empty segment
@@ -346,8 +348,10 @@ void scan_exclusive(hipStream_t s, const int *in, int *out, int n, int *total_de
 // CG loop's "solve ended" flag); done = NULL outside that loop.
 // part: 0 = the whole leg; 1 / 2 = its first / second kernel only (a leg of one
 // kernel: that kernel is part 1 of the down leg and part 2 of the up leg)
+// yr (part 0 or 1 of a sliced-ELL level's down leg): dinv o b already formed,
+// in the cycle's type; null: formed here when the level needs it
 void launch_down(hipStream_t s, const Level &L, int fp32, const void *b, void *bc, int b_is_f64,
-                 const double *done, int part = 0);
+                 const double *done, int part = 0, const void *yr = nullptr);
 void launch_up(hipStream_t s, const Level &L, int fp32, const void *b, const void *xc, void *x,
                int b_is_f64, int x_is_f64, const double *done, int part = 0);
 void launch_coarse(hipStream_t s, const Level &L, int sweeps, const void *b, void *x, int b_f64,
@@ -390,8 +394,10 @@ void launch_resid(hipStream_t s, const Level &L, int nb, const double *b, const 
                   double *partials, double *scal);
 void launch_spmv_dots(hipStream_t s, const Level &L, int nb, int first, const double *w, const double *r,
                       const double *q, double *v, double *partials, double *scal);
+// with y: also y = dinv o r (float when y_f32, else double; dinv of that type)
 void launch_update(hipStream_t s, int n, int nb, int first, const double *w, const double *v,
-                   double *d, double *u, double *q, double *r, double *partials, double *scal);
+                   double *d, double *u, double *q, double *r, double *partials, double *scal,
+                   const void *dinv = nullptr, void *y = nullptr, int y_f32 = 0);
 void launch_finalize(hipStream_t s, int mode, int nb, int first, const double *partials, double *scal);
 void launch_sampled_outer(hipStream_t s, const Level &L, const double *lam, const double *x,
                           double *G);

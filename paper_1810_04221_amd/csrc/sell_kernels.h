@@ -156,6 +156,10 @@ k_spmv_dots_sell(int n, const int *__restrict__ sp, const int *__restrict__ uni,
 // The two fused AXPY pairs of Algorithm 3 and partials of ||r||^2:
 //   d = w - g d ; u += an d ; q = v - g q ; r -= an q   (first step: d = w, q = v)
 // with g = gamma_i / rho_{i-1} and an = alpha_i / rho_i from the finalize step.
+// With y given, also y = dinv o r in the cycle's arithmetic type YV: the
+// finest level's pre-smoothed iterate (the first Jacobi step of Algorithm 1
+// from a zero guess) for the next preconditioner application, whose down-leg
+// residual then gathers one array instead of dinv and r.
 // Vectors of at least four entries per thread of the grid go in pairs of
 // entries with 16-byte accesses (the vectors are 256-byte aligned; with n odd,
 // thread 0 of the grid also takes entry n - 1); shorter ones one entry at a
@@ -170,10 +174,11 @@ __device__ __forceinline__ void update_pair(double wi, double vi, double &di, do
     acc += ri * ri;
 }
 
-template <bool First>
+template <bool First, typename YV>
 __device__ __forceinline__ void update_range1(int n, const double *__restrict__ w, const double *__restrict__ v,
                                               double *__restrict__ d, double *__restrict__ u,
-                                              double *__restrict__ q, double *__restrict__ r, double g, double an,
+                                              double *__restrict__ q, double *__restrict__ r,
+                                              const YV *__restrict__ dinv, YV *__restrict__ y, double g, double an,
                                               double &acc) {
     const int blk = xcd_block(blockIdx.x, gridDim.x);
     for (int i = blk * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
@@ -183,18 +188,27 @@ __device__ __forceinline__ void update_range1(int n, const double *__restrict__ 
         q[i] = qi;
         u[i] = ui;
         r[i] = ri;
+        if (y) y[i] = dinv[i] * (YV)ri;
     }
 }
 
-template <bool First>
+template <typename YV> struct Pair2;
+template <> struct Pair2<float> { using T = float2; };
+template <> struct Pair2<double> { using T = double2; };
+
+template <bool First, typename YV>
 __device__ __forceinline__ void update_range(int n, const double *__restrict__ w, const double *__restrict__ v,
                                              double *__restrict__ d, double *__restrict__ u, double *__restrict__ q,
-                                             double *__restrict__ r, double g, double an, double &acc) {
+                                             double *__restrict__ r, const YV *__restrict__ dinv,
+                                             YV *__restrict__ y, double g, double an, double &acc) {
+    using Y2 = typename Pair2<YV>::T;
     const int blk = xcd_block(blockIdx.x, gridDim.x);
     const int n2 = n / 2;
     const double2 *w2 = reinterpret_cast<const double2 *>(w), *v2 = reinterpret_cast<const double2 *>(v);
     double2 *d2 = reinterpret_cast<double2 *>(d), *u2 = reinterpret_cast<double2 *>(u);
     double2 *q2 = reinterpret_cast<double2 *>(q), *r2 = reinterpret_cast<double2 *>(r);
+    const Y2 *dinv2 = reinterpret_cast<const Y2 *>(dinv);
+    Y2 *y2 = reinterpret_cast<Y2 *>(y);
     for (int i = blk * kBlock + threadIdx.x; i < n2; i += gridDim.x * kBlock) {
         const double2 wi = w2[i], vi = v2[i];
         double2 di, qi;
@@ -206,6 +220,13 @@ __device__ __forceinline__ void update_range(int n, const double *__restrict__ w
         q2[i] = qi;
         u2[i] = ui;
         r2[i] = ri;
+        if (y) {
+            const Y2 dv = dinv2[i];
+            Y2 yv;
+            yv.x = dv.x * (YV)ri.x;
+            yv.y = dv.y * (YV)ri.y;
+            y2[i] = yv;
+        }
     }
     if ((n & 1) && blk == 0 && threadIdx.x == 0) {
         const int i = n - 1;
@@ -215,23 +236,26 @@ __device__ __forceinline__ void update_range(int n, const double *__restrict__ w
         q[i] = qi;
         u[i] = ui;
         r[i] = ri;
+        if (y) y[i] = dinv[i] * (YV)ri;
     }
 }
 
+// YV: float or double, the type of dinv and y (y may be null)
+template <typename YV>
 __global__ void __launch_bounds__(kBlock)
 k_update(int n, int first, const double *__restrict__ w, const double *__restrict__ v, double *__restrict__ d,
-         double *__restrict__ u, double *__restrict__ q, double *__restrict__ r,
-         const double *__restrict__ scal, double *__restrict__ partials) {
+         double *__restrict__ u, double *__restrict__ q, double *__restrict__ r, const YV *__restrict__ dinv,
+         YV *__restrict__ y, const double *__restrict__ scal, double *__restrict__ partials) {
     if (scal[10] != 0.0) return;
     const bool ok = scal[6] == 0.0;
     const double g = scal[8], an = scal[9];
     double acc[1] = {0.0};
     if (ok) {
         const bool pairs = (long long)n >= 4LL * gridDim.x * kBlock;
-        if (pairs && first) update_range<true>(n, w, v, d, u, q, r, g, an, acc[0]);
-        else if (pairs) update_range<false>(n, w, v, d, u, q, r, g, an, acc[0]);
-        else if (first) update_range1<true>(n, w, v, d, u, q, r, g, an, acc[0]);
-        else update_range1<false>(n, w, v, d, u, q, r, g, an, acc[0]);
+        if (pairs && first) update_range<true>(n, w, v, d, u, q, r, dinv, y, g, an, acc[0]);
+        else if (pairs) update_range<false>(n, w, v, d, u, q, r, dinv, y, g, an, acc[0]);
+        else if (first) update_range1<true>(n, w, v, d, u, q, r, dinv, y, g, an, acc[0]);
+        else update_range1<false>(n, w, v, d, u, q, r, dinv, y, g, an, acc[0]);
     }
     block_partials<1>(acc, partials);
 }

@@ -1146,16 +1146,17 @@ void down_dispatch(hipStream_t s, const Level &L, const V *a, const V *dinv, con
 
 // part: 0 = the whole leg, 1 = its first kernel, 2 = its second kernel (a
 // leg of one kernel has it as part 1 of the down leg and part 2 of the up leg)
+// yr: dinv o b already formed by the caller (the flexible-CG update), or null
 template <typename V, typename VB>
 void down_t(hipStream_t s, const Level &L, const V *a, const V *dinv, const V *p, const VB *b, V *bc,
-            const double *done, int part) {
+            const double *done, int part, const V *yr) {
     if (L.E.sp && L.xp && (L.mstride == 2 || L.mstride == 4)) {
         V *pr = (V *)L.xp;  // free during the down leg: the up leg of this level runs later
-        V *y = (V *)L.yb;
+        const V *y = yr ? yr : (const V *)L.yb;
         if (part != 2) {
-            if (y)
-                hipLaunchKernelGGL((k_scale<V, VB>), dim3(blocks_for(L.A.n)), dim3(kBlock), 0, s, L.A.n, dinv, b, y,
-                                   done);
+            if (!yr && L.yb)
+                hipLaunchKernelGGL((k_scale<V, VB>), dim3(blocks_for(L.A.n)), dim3(kBlock), 0, s, L.A.n, dinv, b,
+                                   (V *)L.yb, done);
             with_sell<V>(L.E, [&](auto *ix, auto *vals, auto kb) {
                 using I = std::remove_const_t<std::remove_pointer_t<decltype(ix)>>;
                 using S = std::remove_const_t<std::remove_pointer_t<decltype(vals)>>;
@@ -1286,13 +1287,16 @@ int reduce_blocks(int n) {
 }
 
 void launch_down(hipStream_t s, const Level &L, int fp32, const void *b, void *bc, int b_is_f64,
-                 const double *done, int part) {
+                 const double *done, int part, const void *yr) {
     if (!fp32) {
-        down_t<double, double>(s, L, L.A.v, L.dinv, L.p, (const double *)b, (double *)bc, done, part);
+        down_t<double, double>(s, L, L.A.v, L.dinv, L.p, (const double *)b, (double *)bc, done, part,
+                               (const double *)yr);
     } else if (b_is_f64) {
-        down_t<float, double>(s, L, L.A.v32, L.dinv32, L.p32, (const double *)b, (float *)bc, done, part);
+        down_t<float, double>(s, L, L.A.v32, L.dinv32, L.p32, (const double *)b, (float *)bc, done, part,
+                              (const float *)yr);
     } else {
-        down_t<float, float>(s, L, L.A.v32, L.dinv32, L.p32, (const float *)b, (float *)bc, done, part);
+        down_t<float, float>(s, L, L.A.v32, L.dinv32, L.p32, (const float *)b, (float *)bc, done, part,
+                             (const float *)yr);
     }
 }
 
@@ -1483,8 +1487,14 @@ void launch_spmv_dots(hipStream_t s, const Level &L, int nb, int first, const do
 }
 
 void launch_update(hipStream_t s, int n, int nb, int first, const double *w, const double *v, double *d,
-                   double *u, double *q, double *r, double *partials, double *scal) {
-    launch_k((k_update), dim3(nb), dim3(kBlock), s, n, first, w, v, d, u, q, r, scal, partials);
+                   double *u, double *q, double *r, double *partials, double *scal, const void *dinv, void *y,
+                   int y_f32) {
+    if (y && y_f32)
+        launch_k((k_update<float>), dim3(nb), dim3(kBlock), s, n, first, w, v, d, u, q, r, (const float *)dinv,
+                 (float *)y, scal, partials);
+    else
+        launch_k((k_update<double>), dim3(nb), dim3(kBlock), s, n, first, w, v, d, u, q, r, (const double *)dinv,
+                 (double *)y, scal, partials);
 }
 
 void launch_finalize(hipStream_t s, int mode, int nb, int first, const double *partials, double *scal) {
