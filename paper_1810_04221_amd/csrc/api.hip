@@ -591,7 +591,7 @@ int autotune_lanes(bcm_handle *h) {
     for (int l = 0; l < last && err == hipSuccess; ++l) {
         Level &L = h->lv[l];
         Level &C = h->lv[l + 1];
-        if (L.E.sp && L.xp && (L.mstride == 2 || L.mstride == 4) && L.A.n >= kSplitUp) continue;
+        if (down_on_sell(L) && L.A.n >= kSplitUp) continue;
         if (l > 0) launch_fill_i32(s, es * L.A.n / 4, (int *)L.b, 0);
         launch_fill_i32(s, es * C.A.n / 4, (int *)C.x, 0);
         const void *b = l == 0 ? (const void *)h->r : L.b;
@@ -1075,10 +1075,16 @@ int build_hierarchy(bcm_handle *h, const bcm_csr *Ain, const double *win) {
         // levels whose down leg gathers dinv o b (long rows) get it from the
         // update instead of a launch of its own; on the others the extra
         // stream through the update costs as much as the second gather saves
-        if (h->nl > 1 && F.E.sp && F.xp && F.yb && (F.mstride == 2 || F.mstride == 4)) {
+        if (h->nl > 1 && F.yb && down_on_sell(F)) {
             h->y0 = h->persist.get((P.precision == BCM_FP32_CYCLE ? sizeof(float) : sizeof(double)) * (size_t)n);
             NOMEM(h->y0);
         }
+    }
+    {
+        // the product's partials: one per slice where it takes one workgroup per slice
+        const int nbs = spmv_dots_grid(h->lv[0], h->red_blocks);
+        h->spart = nbs > h->red_blocks ? h->persist.get_n<double>(3 * (size_t)nbs) : h->partials;
+        NOMEM(h->spart);
     }
     if (P.cycle == BCM_KCYCLE) {
         h->kpart = h->persist.get_n<double>(3 * (size_t)kKPartBlocks);
@@ -1117,18 +1123,30 @@ double value_bytes(const Level &L, bool sell_path, bool f32) {
     return f32 || (sell_path && !L.E.sv && L.E.sv32) ? 4.0 : 8.0;
 }
 
+// levels 0 .. cycle_levels(h) - 1 run their own down and up legs in the
+// V-cycle; the rest are the folded operator, the tail kernel or the coarsest solve
+int cycle_levels(const bcm_handle *h) { return h->kf > 0 ? h->kf : (h->kt > 0 ? h->kt : h->nl - 1); }
+// level k (>= 1) of the V-cycle gets its dinv o b from level k - 1's restriction
+bool y_by_restrict(const bcm_handle *h, int k) {
+    return h->prm.cycle == BCM_VCYCLE && k >= 1 && k < cycle_levels(h) && h->lv[k].yb && down_on_sell(h->lv[k]) &&
+           down_on_sell(h->lv[k - 1]);
+}
+
 double bytes_down(const bcm_handle *h, int k) {
     const Level &L = h->lv[k];
     const bool f32 = h->prm.precision == BCM_FP32_CYCLE;
     const double sv = f32 ? 4 : 8, sb = (k == 0 || !f32) ? 8 : 4;
     const double n = L.A.n, z = L.A.nnz, nc = L.nc;
-    const bool sell = L.E.sp && L.xp && (L.mstride == 2 || L.mstride == 4);
+    const bool sell = down_on_sell(L);
     const double base = 4 * (n + 1) + (index_bytes(L, sell) + value_bytes(L, sell, f32)) * z + sb * n + 2 * sv * n +
                         4.0 * nc * L.mstride + sv * nc;
     // split leg: p r written and read; with yb, dinv o b formed first (b, dinv read, y written),
-    // except on the finest level with y0, where the flexible-CG update forms it
-    const bool scale = L.yb && !(k == 0 && h->y0);
-    return sell ? base + 2 * sv * n + (scale ? (sb + 2 * sv) * n : 0.0) : base;
+    // except where the flexible-CG update (finest level, y0) or the finer
+    // level's restriction forms it; the restriction forming the coarser
+    // level's reads its dinv and writes its y
+    const bool scale = L.yb && !(k == 0 && h->y0) && !y_by_restrict(h, k);
+    const double cy = y_by_restrict(h, k + 1) ? 2 * sv * nc : 0.0;
+    return sell ? base + 2 * sv * n + (scale ? (sb + 2 * sv) * n : 0.0) + cy : base;
 }
 // up leg: fused k_up, or k_prolong + k_smooth on large levels (xp written and read once)
 double bytes_up(const bcm_handle *h, int k) {
@@ -1148,8 +1166,7 @@ double bytes_down_main(const bcm_handle *h, int k) {
     const Level &L = h->lv[k];
     const bool f32 = h->prm.precision == BCM_FP32_CYCLE;
     const double sv = f32 ? 4 : 8, sb = (k == 0 || !f32) ? 8 : 4, n = L.A.n, z = L.A.nnz;
-    const bool sell = L.E.sp && L.xp && (L.mstride == 2 || L.mstride == 4);
-    if (!sell) return bytes_down(h, k);
+    if (!down_on_sell(L)) return bytes_down(h, k);
     return 4 * (n + 1) + (index_bytes(L, true) + value_bytes(L, true, f32)) * z + sb * n + 3 * sv * n;
 }
 double bytes_up_main(const bcm_handle *h, int k) {
@@ -1408,19 +1425,21 @@ void vcycle(bcm_handle *h, Prof &pf, const double *rin, double *wout, const doub
         return;
     }
     // levels below kt: the folded operator, the tail kernel, or the coarsest solve
-    const int kt = h->kf > 0 ? h->kf : (h->kt > 0 ? h->kt : nl - 1);
+    const int kt = cycle_levels(h);
     for (int k = 0; k < kt; ++k) {
         Level &L = h->lv[k];
         const void *bk = k == 0 ? (const void *)rin : L.b;
         const int io = (k == 0 || !fp32) ? 1 : 0;
+        // the restriction forms the coarser level's dinv o b when that level gathers it
+        const Level *next = y_by_restrict(h, k + 1) ? &h->lv[k + 1] : nullptr;
         if (k == 0) {  // the finest level's main kernel alone is class 0
             int e = pf.begin(0);
             launch_down(s, L, fp32, bk, h->lv[1].b, io, done, 1, y0);
             pf.end(0, e, class_bytes(h, 0), iter);
-            launch_down(s, L, fp32, bk, h->lv[1].b, io, done, 2);
+            launch_down(s, L, fp32, bk, h->lv[1].b, io, done, 2, nullptr, next);
         } else {
             int e = pf.begin(5);
-            launch_down(s, L, fp32, bk, h->lv[k + 1].b, io, done);
+            launch_down(s, L, fp32, bk, h->lv[k + 1].b, io, done, 0, y_by_restrict(h, k) ? L.yb : nullptr, next);
             pf.end(5, e, bytes_down(h, k), iter);
         }
     }
@@ -1489,9 +1508,10 @@ int capture_iteration(bcm_handle *h, int prof_cls) {
     sc.begin();
     vcycle(h, gp, h->r, h->w, h->scal + 10, 0, h->y0);
     int e = gp.begin(2);
-    launch_spmv_dots(h->cap, L0, nb, 0, h->w, h->r, h->q, h->v, h->partials, h->scal);
+    const int nbs = spmv_dots_grid(L0, nb);
+    launch_spmv_dots(h->cap, L0, nbs, 0, h->w, h->r, h->q, h->v, h->spart, h->scal);
     gp.end(2, e, 0.0, 0);
-    launch_finalize(h->cap, 1, nb, 0, h->partials, h->scal);
+    launch_finalize(h->cap, 1, nbs, 0, h->spart, h->scal);
     e = gp.begin(3);
     launch_update(h->cap, n, nb, 0, h->w, h->v, h->d, h->u, h->q, h->r, h->partials, h->scal, y0_dinv(h), h->y0,
                   h->prm.precision == BCM_FP32_CYCLE);
@@ -1521,7 +1541,7 @@ int capture_iteration(bcm_handle *h, int prof_cls) {
 int fcg_run(bcm_handle *h, const double *b, double *x_user, double tol) {
     hipStream_t s = h->s;
     const Level &L0 = h->lv[0];
-    const int n = L0.A.n, nb = h->red_blocks;
+    const int n = L0.A.n, nb = h->red_blocks, nbs = spmv_dots_grid(L0, nb);
     Prof pf{h, h->prm.profile};
     // graph mode: a profile mask of one class bracketed once per iteration
     // (down0, up0, spmv_dots, update, coarse) is timed by events recorded
@@ -1590,9 +1610,9 @@ int fcg_run(bcm_handle *h, const double *b, double *x_user, double tol) {
                 // the first iteration's r comes from the residual kernel: no y0 yet
                 vcycle(h, pf, h->r, h->w, done, launched, first ? nullptr : h->y0);
                 int e = pf.begin(2);
-                launch_spmv_dots(s, L0, nb, first, h->w, h->r, h->q, h->v, h->partials, h->scal);
+                launch_spmv_dots(s, L0, nbs, first, h->w, h->r, h->q, h->v, h->spart, h->scal);
                 pf.end(2, e, bytes_spmv_dots(h), launched);
-                launch_finalize(s, 1, nb, first, h->partials, h->scal);
+                launch_finalize(s, 1, nbs, first, h->spart, h->scal);
                 e = pf.begin(3);
                 launch_update(s, n, nb, first, h->w, h->v, h->d, x, h->q, h->r, h->partials, h->scal, y0_dinv(h),
                               h->y0, h->prm.precision == BCM_FP32_CYCLE);

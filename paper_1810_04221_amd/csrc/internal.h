@@ -230,6 +230,7 @@ struct bcm_handle {
     int *tail_ops = nullptr;               // the tail kernel's program (device)
     int n_tail_ops = 0;
     double *partials = nullptr;
+    double *spart = nullptr;  // the finest product's partials (partials, or one per slice when it splits rows)
     double *lpart = nullptr;  // chunk sums of the long rows (the largest level's chunk count)
     double *kpart = nullptr;  // K-cycle block partials (3 * kKPartBlocks)
     double *ks = nullptr;     // K-cycle scalars, 8 per level
@@ -348,10 +349,14 @@ void scan_exclusive(hipStream_t s, const int *in, int *out, int n, int *total_de
 // CG loop's "solve ended" flag); done = NULL outside that loop.
 // part: 0 = the whole leg; 1 / 2 = its first / second kernel only (a leg of one
 // kernel: that kernel is part 1 of the down leg and part 2 of the up leg)
+// true when level L's down leg runs as the sliced-ELL residual + restriction
+inline bool down_on_sell(const Level &L) { return L.E.sp && L.xp && (L.mstride == 2 || L.mstride == 4); }
 // yr (part 0 or 1 of a sliced-ELL level's down leg): dinv o b already formed,
-// in the cycle's type; null: formed here when the level needs it
+// in the cycle's type; null: formed here when the level needs it.  next (part
+// 0 or 2 of such a leg): the coarser level, whose dinv o b the restriction
+// then also writes into next->yb; null: it does not.
 void launch_down(hipStream_t s, const Level &L, int fp32, const void *b, void *bc, int b_is_f64,
-                 const double *done, int part = 0, const void *yr = nullptr);
+                 const double *done, int part = 0, const void *yr = nullptr, const Level *next = nullptr);
 void launch_up(hipStream_t s, const Level &L, int fp32, const void *b, const void *xc, void *x,
                int b_is_f64, int x_is_f64, const double *done, int part = 0);
 void launch_coarse(hipStream_t s, const Level &L, int sweeps, const void *b, void *x, int b_f64,
@@ -392,6 +397,10 @@ void launch_dense(hipStream_t s, int n, const double *T, const void *b, void *x,
                   const double *done);
 void launch_resid(hipStream_t s, const Level &L, int nb, const double *b, const double *u, double *r,
                   double *partials, double *scal);
+// workgroups of the flexible-CG product on level L (nb: the reduction grid of
+// the vector kernels): one per slice on the levels whose rows it splits, else nb.
+// launch_spmv_dots takes this count and writes that many partials per product.
+int spmv_dots_grid(const Level &L, int nb);
 void launch_spmv_dots(hipStream_t s, const Level &L, int nb, int first, const double *w, const double *r,
                       const double *q, double *v, double *partials, double *scal);
 // with y: also y = dinv o r (float when y_f32, else double; dinv of that type)

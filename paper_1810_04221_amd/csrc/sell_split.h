@@ -99,3 +99,29 @@ k_smooth_sell_p(int n, const int *__restrict__ sp, const int *__restrict__ uni, 
     const V t = parts_sum(s, red);
     if (threadIdx.x < kSlice && i < n) x[i] = (VX)(xp[i] + dinv[i] * ((V)b[i] - t));
 }
+
+// The flexible-CG product v = A w with the dot products (w.r, w.v, w.q) of
+// Algorithm 3, one slice per workgroup: a grid of one workgroup per slice, each
+// writing its own partials (summed in workgroup order by the finalize step).
+template <typename I, typename S, int kB>
+__global__ void __launch_bounds__(kBlock)
+k_spmv_dots_sell_p(int n, const int *__restrict__ sp, const int *__restrict__ uni, const int *__restrict__ su,
+                   const I *__restrict__ sc, const S *__restrict__ sv, const double *__restrict__ w,
+                   const double *__restrict__ r, const double *__restrict__ q, double *__restrict__ v,
+                   double *__restrict__ partials, const double *__restrict__ done) {
+    __shared__ double red[kParts][kSlice];
+    if (done && *done != 0.0) return;
+    const int sl = xcd_block(blockIdx.x, gridDim.x);
+    const int i = sl * kSlice + (int)threadIdx.x % kSlice;
+    const double s = sell_row_part<double, S, I, kB>(n, sp, uni, su, sc, sv, sl, [&](int j) { return w[j]; });
+    const double t = parts_sum(s, red);
+    double acc[3] = {0.0, 0.0, 0.0};
+    if (threadIdx.x < kSlice && i < n) {
+        const double wi = w[i];
+        v[i] = t;
+        acc[0] = wi * r[i];
+        acc[1] = wi * t;
+        acc[2] = wi * q[i];
+    }
+    block_partials<3>(acc, partials);
+}

@@ -352,7 +352,7 @@ k_scale(int n, const V *__restrict__ dinv, const VB *__restrict__ b, V *__restri
 template <typename V, int S>
 __global__ void __launch_bounds__(kBlock)
 k_restrict(int nc, const int *__restrict__ mem, const V *__restrict__ pr, V *__restrict__ bc,
-           const double *__restrict__ done) {
+           const V *__restrict__ cd, V *__restrict__ cy, const double *__restrict__ done) {
     if (done && *done != 0.0) return;
     const int E = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
     if (E >= nc) return;
@@ -363,6 +363,7 @@ k_restrict(int nc, const int *__restrict__ mem, const V *__restrict__ pr, V *__r
 #pragma unroll
     for (int t = 0; t < S; ++t) acc += m[t] >= 0 ? pr[m[t]] : V(0);
     bc[E] = acc;
+    if (cy) cy[E] = cd[E] * acc;  // the coarser level's dinv o b, as k_scale forms it
 }
 
 // ----------------------------------------------------------------------------
@@ -1018,8 +1019,13 @@ k_spmv_dots(int n, const int *__restrict__ rp, const int *__restrict__ ci, const
 // every kernel of a later iteration returns at once.  Mode 2 sets it when
 // ||r||^2 <= scal[12] (= tol^2 ||b||^2) or scal[11] >= scal[13] (itmax); mode 1
 // sets it, with scal[6], on breakdown.
+// One workgroup: kBlock threads for up to 8 x kBlock partials (their loads in
+// flight in one round trip), kFinalize threads beyond that (the product that
+// takes one workgroup per slice writes one partial per slice).
+constexpr int kFinalize = 1024;
+inline int finalize_threads(int nb) { return nb > 8 * kBlock ? kFinalize : kBlock; }
 template <int K>
-__global__ void __launch_bounds__(kBlock) k_finalize(int nb, const double *__restrict__ partials,
+__global__ void __launch_bounds__(kFinalize) k_finalize(int nb, const double *__restrict__ partials,
                                                      double *__restrict__ scal, int mode, int first) {
     if (mode != 0 && scal[10] != 0.0) return;
     __shared__ double lds[K * 16];
@@ -1146,11 +1152,13 @@ void down_dispatch(hipStream_t s, const Level &L, const V *a, const V *dinv, con
 
 // part: 0 = the whole leg, 1 = its first kernel, 2 = its second kernel (a
 // leg of one kernel has it as part 1 of the down leg and part 2 of the up leg)
-// yr: dinv o b already formed by the caller (the flexible-CG update), or null
+// yr: dinv o b already formed by the caller (the flexible-CG update, or the
+// finer level's restriction), or null.  cd, cy: the coarser level's dinv and
+// dinv o b, formed by the restriction here when cy is given.
 template <typename V, typename VB>
 void down_t(hipStream_t s, const Level &L, const V *a, const V *dinv, const V *p, const VB *b, V *bc,
-            const double *done, int part, const V *yr) {
-    if (L.E.sp && L.xp && (L.mstride == 2 || L.mstride == 4)) {
+            const double *done, int part, const V *yr, const V *cd, V *cy) {
+    if (down_on_sell(L)) {
         V *pr = (V *)L.xp;  // free during the down leg: the up leg of this level runs later
         const V *y = yr ? yr : (const V *)L.yb;
         if (part != 2) {
@@ -1171,10 +1179,10 @@ void down_t(hipStream_t s, const Level &L, const V *a, const V *dinv, const V *p
         if (part == 1) return;
         if (L.mstride == 4)
             hipLaunchKernelGGL((k_restrict<V, 4>), dim3(blocks_for(L.nc)), dim3(kBlock), 0, s, L.nc, L.mem, pr, bc,
-                               done);
+                               cd, cy, done);
         else
             hipLaunchKernelGGL((k_restrict<V, 2>), dim3(blocks_for(L.nc)), dim3(kBlock), 0, s, L.nc, L.mem, pr, bc,
-                               done);
+                               cd, cy, done);
         return;
     }
     if (part == 2) return;
@@ -1287,16 +1295,17 @@ int reduce_blocks(int n) {
 }
 
 void launch_down(hipStream_t s, const Level &L, int fp32, const void *b, void *bc, int b_is_f64,
-                 const double *done, int part, const void *yr) {
+                 const double *done, int part, const void *yr, const Level *next) {
+    void *cy = next ? next->yb : nullptr;
     if (!fp32) {
         down_t<double, double>(s, L, L.A.v, L.dinv, L.p, (const double *)b, (double *)bc, done, part,
-                               (const double *)yr);
+                               (const double *)yr, cy ? next->dinv : nullptr, (double *)cy);
     } else if (b_is_f64) {
         down_t<float, double>(s, L, L.A.v32, L.dinv32, L.p32, (const double *)b, (float *)bc, done, part,
-                              (const float *)yr);
+                              (const float *)yr, cy ? next->dinv32 : nullptr, (float *)cy);
     } else {
         down_t<float, float>(s, L, L.A.v32, L.dinv32, L.p32, (const float *)b, (float *)bc, done, part,
-                             (const float *)yr);
+                             (const float *)yr, cy ? next->dinv32 : nullptr, (float *)cy);
     }
 }
 
@@ -1467,14 +1476,20 @@ void launch_resid(hipStream_t s, const Level &L, int nb, const double *b, const 
     });
 }
 
+int spmv_dots_grid(const Level &L, int nb) { return L.E.sp && split_slots(L, L.E.wide ? 16 : 8) ? L.E.nslices : nb; }
+
 void launch_spmv_dots(hipStream_t s, const Level &L, int nb, int first, const double *w, const double *r,
                       const double *q, double *v, double *partials, double *scal) {
     if (L.E.sp) {
         with_sell<double>(L.E, [&](auto *ix, auto *vals, auto kb) {
             using I = std::remove_const_t<std::remove_pointer_t<decltype(ix)>>;
             using S = std::remove_const_t<std::remove_pointer_t<decltype(vals)>>;
-            launch_k((k_spmv_dots_sell<I, S, decltype(kb)::value>), dim3(nb), dim3(kBlock), s, L.A.n, L.E.sp, L.E.uni, L.E.su, ix, vals, w, r,
-                               q, v, partials, scal + 10);
+            if (split_slots(L, decltype(kb)::value))  // nb = L.E.nslices (spmv_dots_grid)
+                launch_k((k_spmv_dots_sell_p<I, S, 8>), dim3(nb), dim3(kBlock), s, L.A.n, L.E.sp, L.E.uni, L.E.su,
+                         ix, vals, w, r, q, v, partials, scal + 10);
+            else
+                launch_k((k_spmv_dots_sell<I, S, decltype(kb)::value>), dim3(nb), dim3(kBlock), s, L.A.n, L.E.sp,
+                         L.E.uni, L.E.su, ix, vals, w, r, q, v, partials, scal + 10);
         });
         return;
     }
@@ -1498,9 +1513,10 @@ void launch_update(hipStream_t s, int n, int nb, int first, const double *w, con
 }
 
 void launch_finalize(hipStream_t s, int mode, int nb, int first, const double *partials, double *scal) {
-    if (mode == 0) hipLaunchKernelGGL(k_finalize<2>, dim3(1), dim3(kBlock), 0, s, nb, partials, scal, 0, 0);
-    else if (mode == 1) hipLaunchKernelGGL(k_finalize<3>, dim3(1), dim3(kBlock), 0, s, nb, partials, scal, 1, first);
-    else hipLaunchKernelGGL(k_finalize<1>, dim3(1), dim3(kBlock), 0, s, nb, partials, scal, 2, 0);
+    const dim3 t(finalize_threads(nb));
+    if (mode == 0) hipLaunchKernelGGL(k_finalize<2>, dim3(1), t, 0, s, nb, partials, scal, 0, 0);
+    else if (mode == 1) hipLaunchKernelGGL(k_finalize<3>, dim3(1), t, 0, s, nb, partials, scal, 1, first);
+    else hipLaunchKernelGGL(k_finalize<1>, dim3(1), t, 0, s, nb, partials, scal, 2, 0);
 }
 
 void launch_sampled_outer(hipStream_t s, const Level &L, const double *lam, const double *x, double *G) {
