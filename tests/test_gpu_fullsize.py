@@ -123,6 +123,40 @@ def test_fullsize_solve(B, ora, name, precision):
     h.close()
 
 
+def _close_entries(z, zo, rtol):
+    # entry by entry: |z_i - zo_i| <= rtol (|zo_i| + mean |zo|)
+    bound = rtol * (np.abs(zo) + np.mean(np.abs(zo)))
+    err = np.abs(z - zo)
+    worst = int(np.argmax(err / bound))
+    say(f"entry-wise: worst |dx| / (|xo| + mean |xo|) = {err[worst] / bound[worst] * rtol:.2e} (bound {rtol:.0e})")
+    assert np.all(err <= bound), f"entry {worst}: |dx| = {err[worst]:.3e} > bound {bound[worst]:.3e}"
+
+
+# bounds: FP64 a few ulp per operation carried through three cycles (measured
+# 8e-15); FP32 float32 rounding of the cycle, damped by the FP64 outer
+# iteration over three steps (measured 5e-8)
+@pytest.mark.parametrize("precision,rtol", [("fp64", 1e-12), ("fp32", 1e-6)])
+def test_fullsize_first_iterations_entrywise(B, ora, precision, rtol):
+    # Elasticity at full size takes every solve path of its wide levels: the
+    # flexible-CG product split over a workgroup's waves with one partial per
+    # slice (5,402), the finest level's dinv o r formed by the update (from the
+    # second iteration on), level 1's formed by the restriction, and the
+    # slot-split residual and smoother.  Three iterations against the oracle's
+    # three, entry by entry: FP64 differs only in the order of the sums; the
+    # FP32 cycle is a preconditioner perturbed by float32 rounding.
+    c = _config("G4")
+    say(f"gpu 3 iterations {precision} {c['name']}")
+    h = B.Hierarchy(c["rowptr"], c["col"], c["val"], c["w"], max_coarse=c["max_coarse"], precision=precision,
+                    itmax=3)
+    x = h.solve(c["b"], tol=1e-30, allow_maxit=True).cpu().numpy()
+    assert h.info()["iters"] == 3 and h.info()["status"] == B.BCM_MAXIT
+    h.close()
+    say(f"oracle 3 iterations {c['name']}")
+    xo, io = _oracle(ora, "G4").solve(c["b"], tol=1e-30, itmax=3)
+    assert io["iters"] == 3
+    _close_entries(x, xo, rtol)
+
+
 def test_fullsize_adjoint_and_sampled_outer(B, ora):
     c = _config("G5")
     say(f"gpu forward + adjoint {c['name']}")
