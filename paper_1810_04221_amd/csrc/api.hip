@@ -591,7 +591,7 @@ int autotune_lanes(bcm_handle *h) {
     for (int l = 0; l < last && err == hipSuccess; ++l) {
         Level &L = h->lv[l];
         Level &C = h->lv[l + 1];
-        if (down_on_sell(L) && L.A.n >= kSplitUp) continue;
+        if (down_on_sell(L) && L.xp) continue;
         if (l > 0) launch_fill_i32(s, es * L.A.n / 4, (int *)L.b, 0);
         launch_fill_i32(s, es * C.A.n / 4, (int *)C.x, 0);
         const void *b = l == 0 ? (const void *)h->r : L.b;
@@ -871,7 +871,7 @@ int build_hierarchy(bcm_handle *h, const bcm_csr *Ain, const double *win) {
         }
         launch_long_abs(s, L.lr, L.A.rp, L.A.v, h->lpart, L.A.v32);
         launch_diag_l1(s, L.G, nl_, L.A.rp, L.A.v, L.dinv, L.dinv32, L.A.v32, L.lr, h->lpart);
-        if (l < h->nl - 1 && nl_ >= kSplitUp) {
+        if (l < h->nl - 1 && split_legs(nl_, L.A.nnz)) {
             L.xp = h->persist.get((fp32 ? sizeof(float) : sizeof(double)) * nl_);
             NOMEM(L.xp);
             if (L.A.nnz >= (long long)kGatherRow * nl_) {
@@ -1154,7 +1154,7 @@ double bytes_up(const bcm_handle *h, int k) {
     const bool f32 = h->prm.precision == BCM_FP32_CYCLE;
     const double sv = f32 ? 4 : 8, sb = (k == 0 || !f32) ? 8 : 4;
     const double n = L.A.n, z = L.A.nnz, nc = L.nc;
-    if (L.xp && L.A.n >= kSplitUp)
+    if (L.xp)
         return (sb * n + 2 * sv * n + 4 * n + sv * nc + sv * n) +
                (4 * (n + 1) + (index_bytes(L, L.E.sp != nullptr) + value_bytes(L, L.E.sp != nullptr, f32)) * z +
                 2 * sv * n + 2 * sb * n);
@@ -1173,7 +1173,7 @@ double bytes_up_main(const bcm_handle *h, int k) {
     const Level &L = h->lv[k];
     const bool f32 = h->prm.precision == BCM_FP32_CYCLE;
     const double sv = f32 ? 4 : 8, sb = (k == 0 || !f32) ? 8 : 4, n = L.A.n, z = L.A.nnz;
-    if (!(L.xp && L.A.n >= kSplitUp)) return bytes_up(h, k);
+    if (!L.xp) return bytes_up(h, k);
     return 4 * (n + 1) + (index_bytes(L, L.E.sp != nullptr) + value_bytes(L, L.E.sp != nullptr, f32)) * z +
            2 * sv * n + 2 * sb * n;
 }

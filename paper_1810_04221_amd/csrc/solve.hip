@@ -1195,7 +1195,7 @@ void down_t(hipStream_t s, const Level &L, const V *a, const V *dinv, const V *p
 template <typename V, typename VB, typename VX>
 void up_t(hipStream_t s, const Level &L, const V *a, const V *dinv, const V *p, const VB *b, const V *xc,
           VX *x, const double *done, int part) {
-    if (L.xp && L.A.n >= kSplitUp) {
+    if (L.xp) {
         V *xp = (V *)L.xp;
         if (part != 2)
             hipLaunchKernelGGL((k_prolong<V, VB>), dim3(blocks_for(L.A.n)), dim3(kBlock), 0, s, L.A.n, dinv, p, L.agg,
