@@ -751,15 +751,38 @@ k_fold_w(int n, const double *__restrict__ T, const double *__restrict__ M, doub
 }
 
 // T = D + (I - D A) H:  T_ij = [i = j] dinv_i + H_ij - dinv_i sum_{k in row i} a_ik H_kj
+// One wave per row i and 64 consecutive columns j: row i's entries are the
+// same for the whole wave (scalar loads), each H load is one contiguous
+// access, and four entries' loads are issued per step.  The sum runs over
+// row i in order, as with one thread per entry.
+constexpr int kFoldCols = 64;
+inline long long fold_t_threads(int n) { return (long long)n * ((n + kFoldCols - 1) / kFoldCols) * kFoldCols; }
 __global__ void __launch_bounds__(kBlock)
 k_fold_t(int n, const int *__restrict__ rp, const int *__restrict__ ci, const double *__restrict__ a,
          const double *__restrict__ dinv, const double *__restrict__ H, double *__restrict__ T) {
-    const long long idx = (long long)blockIdx.x * kBlock + threadIdx.x;
-    if (idx >= (long long)n * n) return;
-    const int i = (int)(idx / n), j = (int)(idx % n);
+    const int nch = (n + kFoldCols - 1) / kFoldCols;
+    const long long wv = ((long long)blockIdx.x * kBlock + threadIdx.x) / kFoldCols;
+    if (wv >= (long long)n * nch) return;
+    const int i = __builtin_amdgcn_readfirstlane((int)(wv / nch));
+    const int jc = __builtin_amdgcn_readfirstlane((int)(wv % nch));
+    const int j = jc * kFoldCols + (int)(threadIdx.x % kFoldCols);
+    const int jj = j < n ? j : n - 1;  // lanes past the last column read a valid one and store nothing
+    const int e = rp[i + 1];
+    int q = rp[i];
     double s = 0.0;
-    for (int q = rp[i]; q < rp[i + 1]; ++q) s += a[q] * H[(size_t)ci[q] * n + j];
-    T[idx] = (i == j ? dinv[i] : 0.0) + H[idx] - dinv[i] * s;
+    for (; q + 4 <= e; q += 4) {
+        const double h0 = H[(size_t)ci[q] * n + jj], h1 = H[(size_t)ci[q + 1] * n + jj];
+        const double h2 = H[(size_t)ci[q + 2] * n + jj], h3 = H[(size_t)ci[q + 3] * n + jj];
+        s += a[q] * h0;
+        s += a[q + 1] * h1;
+        s += a[q + 2] * h2;
+        s += a[q + 3] * h3;
+    }
+    for (; q < e; ++q) s += a[q] * H[(size_t)ci[q] * n + jj];
+    if (j < n) {
+        const size_t idx = (size_t)i * n + j;
+        T[idx] = (i == j ? dinv[i] : 0.0) + H[idx] - dinv[i] * s;
+    }
 }
 
 // ----------------------------------------------------------------------------
@@ -1426,7 +1449,8 @@ void launch_fold_level(hipStream_t s, const Level &L, const double *Tc, int nc, 
     const int n = L.A.n;
     const int nb = blocks_for((long long)n * n);
     hipLaunchKernelGGL(k_fold_h, dim3(nb), dim3(kBlock), 0, s, n, nc, L.A.rp, L.A.ci, L.A.v, L.dinv, L.p, L.agg, Tc, H);
-    hipLaunchKernelGGL(k_fold_t, dim3(nb), dim3(kBlock), 0, s, n, L.A.rp, L.A.ci, L.A.v, L.dinv, H, T);
+    hipLaunchKernelGGL(k_fold_t, dim3(blocks_for(fold_t_threads(n))), dim3(kBlock), 0, s, n, L.A.rp, L.A.ci, L.A.v,
+                       L.dinv, H, T);
 }
 
 void launch_fold_w(hipStream_t s, const Level &L, const double *T, double *M, double *W) {
@@ -1438,7 +1462,7 @@ void launch_fold_w(hipStream_t s, const Level &L, const double *T, double *M, do
 
 void launch_fold_left(hipStream_t s, const Level &L, const double *H, double *T) {
     const int n = L.A.n;
-    hipLaunchKernelGGL(k_fold_t, dim3(blocks_for((long long)n * n)), dim3(kBlock), 0, s, n, L.A.rp, L.A.ci, L.A.v,
+    hipLaunchKernelGGL(k_fold_t, dim3(blocks_for(fold_t_threads(n))), dim3(kBlock), 0, s, n, L.A.rp, L.A.ci, L.A.v,
                        L.dinv, H, T);
 }
 
