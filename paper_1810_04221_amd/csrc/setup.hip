@@ -761,10 +761,9 @@ k_sell_fill(int n, const int *__restrict__ rp, const int *__restrict__ ci, const
             const int *__restrict__ sp, const int *__restrict__ uni, int *__restrict__ su, int *__restrict__ sc,
             short *__restrict__ sd, double *__restrict__ sv, float *__restrict__ sv32) {
     const int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i >= n) return;
     const int sl = i / kSlice, lane = i % kSlice;
+    if (sl * kSlice >= n) return;  // (whole waves past the last slice)
     const int base = sp[sl] + lane, w = (sp[sl + 1] - sp[sl]) / kSlice;
-    const int q0 = rp[i], len = rp[i + 1] - q0;
     auto put = [&](int k, int col, double val) {
         if (sd) sd[base + k * kSlice] = (short)(col - i);
         else sc[base + k * kSlice] = col;
@@ -772,6 +771,8 @@ k_sell_fill(int n, const int *__restrict__ rp, const int *__restrict__ ci, const
         if (sv32) sv32[base + k * kSlice] = (float)val;
     };
     if (su && uni[sl]) {
+        if (i >= n) return;
+        const int q0 = rp[i], len = rp[i + 1] - q0;
         // the slice's template: its first row of full width (rows past n are
         // inactive); uniform slices have w <= 64
         __shared__ int tmpl[kBlock / kSlice][kSlice];
@@ -816,9 +817,34 @@ k_sell_fill(int n, const int *__restrict__ rp, const int *__restrict__ ci, const
         }
         return;
     }
-    for (int k = 0; k < w; ++k) {
-        const bool in = k < len;
-        put(k, in ? ci[q0 + k] : i, in ? v[q0 + k] : 0.0);
+    // Other slices: CSR order, then padding slots (col = row, value 0).  The
+    // slots go KC at a time through LDS: eight lanes per row load KC
+    // consecutive entries of that row (a contiguous access per row, eight rows
+    // per pass), then every lane writes its own row's KC slots (a contiguous
+    // access per slot).  Every lane of the wave takes part in the loads.
+    constexpr int KC = 8, RP = kSlice / KC;  // rows per pass
+    __shared__ int tci[kBlock / kSlice][kSlice][KC + 1];
+    __shared__ double tva[kBlock / kSlice][kSlice][KC + 1];
+    const int wv = (threadIdx.x % kBlock) / kSlice, c = lane % KC;
+    int qr[KC], lr[KC];
+#pragma unroll
+    for (int ps = 0; ps < KC; ++ps) {
+        const int ir = sl * kSlice + ps * RP + lane / KC;
+        qr[ps] = ir < n ? rp[ir] : 0;
+        lr[ps] = ir < n ? rp[ir + 1] - qr[ps] : 0;
+    }
+    for (int k0 = 0; k0 < w; k0 += KC) {
+#pragma unroll
+        for (int ps = 0; ps < KC; ++ps) {
+            const int r = ps * RP + lane / KC;
+            const bool in = k0 + c < lr[ps];
+            tci[wv][r][c] = in ? ci[qr[ps] + k0 + c] : sl * kSlice + r;
+            tva[wv][r][c] = in ? v[qr[ps] + k0 + c] : 0.0;
+        }
+        wave_sync();
+        if (i < n)
+            for (int cc = 0; cc < KC && k0 + cc < w; ++cc) put(k0 + cc, tci[wv][lane][cc], tva[wv][lane][cc]);
+        wave_sync();  // the tile is refilled by the next step
     }
 }
 
