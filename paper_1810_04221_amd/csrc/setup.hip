@@ -161,8 +161,11 @@ k_candidates_direct(int n, const int *__restrict__ rp, const int *__restrict__ c
     // there (at the transposed position) instead of counted
     constexpr int LS = 4 * G;
     constexpr int NG = kBlock / G;
-    __shared__ double sc[NG * LS];
-    __shared__ int sv[NG * LS];
+    // groups' slots one element apart (stride LS + 1): the groups of a wave
+    // reading the same slot index hit different LDS banks
+    constexpr int LSP = LS + 1;
+    __shared__ double sc[NG * LSP];
+    __shared__ int sv[NG * LSP];
     const int g = threadIdx.x / G, lane = threadIdx.x % G;
     const int row = (xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x) / G;
     if (row >= n) return;
@@ -184,8 +187,8 @@ k_candidates_direct(int n, const int *__restrict__ rp, const int *__restrict__ c
         return r;
     };
     const bool staged = d <= LS;
-    double *C = sc + g * LS;
-    int *V = sv + g * LS;
+    double *C = sc + g * LSP;
+    int *V = sv + g * LSP;
     if (staged) {
         for (int k = lane; k < d; k += G) {
             C[k] = c[s0 + k];
@@ -271,14 +274,14 @@ __global__ void __launch_bounds__(kBlock)
 k_rank(int n, const int *__restrict__ rp, const double *__restrict__ c, unsigned *__restrict__ rk, int lmin) {
     constexpr int LMAX = 16 * G;
     constexpr int NG = kBlock / G;
-    __shared__ unsigned long long sk[NG * LMAX];
+    __shared__ unsigned long long sk[NG * (LMAX + 1)];  // groups one element apart: distinct banks
     const int g = threadIdx.x / G, lane = threadIdx.x % G;
     const int row = (xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x) / G;
     if (row >= n) return;
     const int s0 = rp[row], d = rp[row + 1] - s0;
     if (lmin > 0 && d > lmin) return;  // a long row: k_long_rank
     if (d <= LMAX) {
-        unsigned long long *keys = sk + g * LMAX;
+        unsigned long long *keys = sk + g * (LMAX + 1);
         const int P = pow2_at_least(d);
         for (int k = lane; k < P; k += G) keys[k] = k < d ? order_key(c[s0 + k]) : ~0ull;
         wave_sync();
@@ -316,7 +319,7 @@ k_candidates(int n, const int *__restrict__ rp, const int *__restrict__ ci, cons
              const unsigned *__restrict__ rk_own, unsigned long long *__restrict__ cand, int lmin) {
     constexpr int LMAX = 16 * G;
     constexpr int NG = kBlock / G;
-    __shared__ unsigned long long sk[NG * LMAX];
+    __shared__ unsigned long long sk[NG * (LMAX + 1)];  // groups one element apart: distinct banks
     const int g = threadIdx.x / G, lane = threadIdx.x % G;
     const int row = (xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x) / G;
     if (row >= n) return;
@@ -335,7 +338,7 @@ k_candidates(int n, const int *__restrict__ rp, const int *__restrict__ ci, cons
         return (lo < e2 && ci[lo] == row) ? rk_own[lo] : 0u;
     };
     if (d <= LMAX) {
-        unsigned long long *keys = sk + g * LMAX;
+        unsigned long long *keys = sk + g * (LMAX + 1);
         const int P = pow2_at_least(d);
         int nelig = 0;
         for (int k = lane; k < P; k += G) {
@@ -1375,10 +1378,13 @@ k_gal(int pass, int nc, const int *__restrict__ rp, const int *__restrict__ ci,
     constexpr int SL = 4;  // candidate slots per lane
     constexpr int LS = SL * G;
     constexpr int NG = kBlock / G;
-    __shared__ int sf[NG * LS];
-    __shared__ int sfirst[NG * LS];
-    __shared__ unsigned long long skey[NG * LS];
-    __shared__ double st[NG * LS];
+    // groups' slots one element apart (stride LS + 1): the groups of a wave
+    // reading the same slot index hit different LDS banks
+    constexpr int LSP = LS + 1;
+    __shared__ int sf[NG * LSP];
+    __shared__ int sfirst[NG * LSP];
+    __shared__ unsigned long long skey[NG * LSP];
+    __shared__ double st[NG * LSP];
     const int g = threadIdx.x / G, lane = threadIdx.x % G;
     const int E = xcd_block(blockIdx.x, gridDim.x) * NG + g;
     if (E >= nc) return;
@@ -1395,9 +1401,9 @@ k_gal(int pass, int nc, const int *__restrict__ rp, const int *__restrict__ ci,
         gal_row<G>(pass, E, lane, rp, ci, v, agg, p, e0, e1, s0, L0, s1, L1, cnt, crp, cci, cv, gF, gU, false);
         return;
     }
-    int *F = sf + g * LS, *first = sfirst + g * LS;
-    unsigned long long *K = skey + g * LS;
-    double *T = st + g * LS;
+    int *F = sf + g * LSP, *first = sfirst + g * LSP;
+    unsigned long long *K = skey + g * LSP;
+    double *T = st + g * LSP;
     const double pe0 = pass ? p[e0] : 0.0, pe1 = (pass && e1 >= 0) ? p[e1] : 0.0;
 #pragma unroll
     for (int sl = 0; sl < SL; ++sl) {
@@ -1481,7 +1487,7 @@ k_gal_sorted(int pass, int nc, const int *__restrict__ rp, const int *__restrict
              int *__restrict__ cci, double *__restrict__ cv, int *__restrict__ gF, int *__restrict__ gU, int lmin) {
     constexpr int LMAX = 16 * G;
     constexpr int NG = kBlock / G;
-    __shared__ unsigned long long sk[NG * LMAX];
+    __shared__ unsigned long long sk[NG * (LMAX + 1)];  // groups one element apart: distinct banks
     const int g = threadIdx.x / G, lane = threadIdx.x % G;
     const int E = xcd_block(blockIdx.x, gridDim.x) * NG + g;
     if (E >= nc) return;
@@ -1498,7 +1504,7 @@ k_gal_sorted(int pass, int nc, const int *__restrict__ rp, const int *__restrict
         gal_row<G>(pass, E, lane, rp, ci, v, agg, p, e0, e1, s0, L0, s1, L1, cnt, crp, cci, cv, gF, gU, false);
         return;
     }
-    unsigned long long *keys = sk + g * LMAX;
+    unsigned long long *keys = sk + g * (LMAX + 1);
     const int P = pow2_at_least(L);
     for (int k = lane; k < P; k += G) {
         unsigned long long key = ~0ull;
