@@ -39,15 +39,15 @@ constexpr int kCoarseBuildSweeps = 1024;  // up to this size S is built by sweep
 constexpr int kFoldRows = 2048;    // V-cycle: levels from the first this small on form one dense operator
 constexpr int kSplitUp = 65536;    // levels at least this large run the up leg as prolong + smooth
 constexpr int kGatherRow = 16;     // sliced-ELL levels averaging this many entries per row gather dinv o b
-// ... and so do levels of long rows (kGatherRow or more entries per row on
-// average) holding at least kSplitEntries entries: their split legs take the
-// slot-split sliced-ELL kernels.  Such a level gets the buffer L.xp, whose
-// presence then selects the split legs.
+                                   // formed beforehand in the down leg (one vector instead of two)
+// Levels of long rows (kGatherRow or more entries per row on average) holding
+// at least kSplitEntries entries run split legs too, below kSplitUp rows: on
+// the sliced-ELL copy they take the slot-split kernels.  A level that runs
+// split legs gets the buffer L.xp, whose presence then selects them.
 constexpr long long kSplitEntries = 1LL << 20;
 inline bool split_legs(long long n, long long nnz) {
     return n >= kSplitUp || (nnz >= (long long)kGatherRow * n && nnz >= kSplitEntries);
 }
-                                   // formed beforehand in the down leg (one vector instead of two)
 
 // Long rows.  The per-row kernels give each row a group of G lanes, G chosen
 // from the level's mean row length (Sections 3.1, 3.2: miniwarp per row).  A
