@@ -224,11 +224,15 @@ k_candidates_direct(int n, const int *__restrict__ rp, const int *__restrict__ c
 // ----------------------------------------------------------------------------
 template <int G>
 __device__ __forceinline__ void group_sort(unsigned long long *keys, int P, int lane) {
-    for (int size = 2; size <= P; size <<= 1) {
-        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+    // size = 2^ls, stride = 2^lt: the pair indices by shifts and masks (a
+    // division by a stride the compiler cannot see to be a power of two costs
+    // dozens of instructions)
+    for (int ls = 1; (1 << ls) <= P; ++ls) {
+        for (int lt = ls - 1; lt >= 0; --lt) {
+            const int stride = 1 << lt;
             for (int t = lane; t < (P >> 1); t += G) {
-                const int lo = 2 * stride * (t / stride) + (t % stride), hi = lo + stride;
-                const bool up = (lo & size) == 0;
+                const int lo = ((t >> lt) << (lt + 1)) | (t & (stride - 1)), hi = lo + stride;
+                const bool up = (lo & (1 << ls)) == 0;
                 const unsigned long long a = keys[lo], b = keys[hi];
                 if ((a > b) == up) {
                     keys[lo] = b;
