@@ -1508,8 +1508,10 @@ void launch_spmv_dots(hipStream_t s, const Level &L, int nb, int first, const do
         with_sell<double>(L.E, [&](auto *ix, auto *vals, auto kb) {
             using I = std::remove_const_t<std::remove_pointer_t<decltype(ix)>>;
             using S = std::remove_const_t<std::remove_pointer_t<decltype(vals)>>;
-            if (split_slots(L, decltype(kb)::value))  // nb = L.E.nslices (spmv_dots_grid)
-                launch_k((k_spmv_dots_sell_p<I, S, 8>), dim3(nb), dim3(kBlock), s, L.A.n, L.E.sp, L.E.uni, L.E.su,
+            // nb = L.E.nslices (spmv_dots_grid); batches of four slots per wave, which
+            // measured faster than eight here (the residual and smoother keep eight)
+            if (split_slots(L, decltype(kb)::value))
+                launch_k((k_spmv_dots_sell_p<I, S, 4>), dim3(nb), dim3(kBlock), s, L.A.n, L.E.sp, L.E.uni, L.E.su,
                          ix, vals, w, r, q, v, partials, scal + 10);
             else
                 launch_k((k_spmv_dots_sell<I, S, decltype(kb)::value>), dim3(nb), dim3(kBlock), s, L.A.n, L.E.sp,
