@@ -422,6 +422,40 @@ def test_sell_int32_columns_for_long_range_couplings(B, ora):
     assert abs(h.info()["iters"] - io["iters"]) <= 1
 
 
+def test_wide_rows_int32_columns_split_kernels(B, ora):
+    # 70,000 rows averaging 38 entries, couplings beyond int16 offsets: the
+    # finest level takes the slot-split kernels (residual, smoother and the
+    # flexible-CG product with one partial per slice) on int32 columns and gets
+    # dinv o r from the update; level 1 (17,928 rows, about 2M entries) runs
+    # split legs too, its dinv o b formed by the restriction
+    rp, ci, va = P.random_spd(70000, 2.5e-4, 29)
+    n = len(rp) - 1
+    assert len(ci) >= 16 * n and np.abs(ci - np.repeat(np.arange(n), np.diff(rp))).max() > 32767
+    say(f"wide rows, int32 columns n={n} nnz={len(ci)}")
+    h = B.Hierarchy(rp, ci, va, max_coarse=200)
+    ho = ora.Hierarchy(rp, ci, va, np.ones(n), max_coarse=200)
+    _compare_hierarchy(h, ho)
+    r = P.uniform_rhs(n, 18)
+    z, zo = h.precond(r).cpu().numpy(), ho.vcycle(r)
+    _close_entries(z, zo, ENTRY_FP64)
+    b = P.uniform_rhs(n, 19)
+    _, io = ho.solve(b, tol=1e-8)
+    A = sp.csr_matrix((va, ci, rp), shape=(n, n))
+    for precision, rtol in (("fp64", 1e-12), ("fp32", 1e-5)):
+        say(f"wide rows: three iterations {precision}")
+        h3 = B.Hierarchy(rp, ci, va, max_coarse=200, precision=precision, itmax=3)
+        x3 = h3.solve(b, tol=1e-30, allow_maxit=True).cpu().numpy()
+        h3.close()
+        xo3, _ = ho.solve(b, tol=1e-30, itmax=3)
+        _close_entries(x3, xo3, rtol)
+        hs = B.Hierarchy(rp, ci, va, max_coarse=200, precision=precision)
+        x = hs.solve(b, tol=1e-8).cpu().numpy()
+        assert np.linalg.norm(b - A @ x) <= 1e-8 * np.linalg.norm(b)
+        allow = 1 if precision == "fp64" else _fp32_allowance(io["iters"])
+        assert abs(hs.info()["iters"] - io["iters"]) <= allow, (hs.info()["iters"], io["iters"])
+        hs.close()
+
+
 # ----------------------------------------------------------------------------- W-cycle
 @pytest.mark.parametrize("name,scale,precision", [("G1", 1.0, "fp64"), ("G2", 0.3, "fp64"), ("G4", 0.21, "fp64"),
                                                   ("G2", 0.3, "fp32")])
