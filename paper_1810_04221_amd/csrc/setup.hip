@@ -1425,7 +1425,9 @@ k_gal(int pass, int nc, const int *__restrict__ rp, const int *__restrict__ ci,
         }
     }
     wave_sync();
-    // first occurrence of each column among the candidates
+    // first occurrence of each column among the candidates; first[k] holds the
+    // column and that flag together, (F << 1) | flag, so the rank loop below
+    // reads one word per candidate
     int nu = 0;
 #pragma unroll
     for (int sl = 0; sl < SL; ++sl) {
@@ -1434,7 +1436,7 @@ k_gal(int pass, int nc, const int *__restrict__ rp, const int *__restrict__ ci,
         const int f = F[k];
         int fk = 1;
         for (int k2 = 0; k2 < k; ++k2) fk = (F[k2] == f) ? 0 : fk;
-        first[k] = fk;
+        first[k] = (f << 1) | fk;
         nu += fk;
     }
     if (pass == 0) {
@@ -1448,20 +1450,28 @@ k_gal(int pass, int nc, const int *__restrict__ rp, const int *__restrict__ ci,
 #pragma unroll
     for (int sl = 0; sl < SL; ++sl) {
         const int k = lane + sl * G;
-        if (k >= L || !first[k]) continue;
+        if (k >= L || !(first[k] & 1)) continue;
         const int f = F[k];
-        // rank among the distinct columns; the terms of column f in candidate order
-        int rank = 0, nt = 0;
-        unsigned long long key[4] = {NONE, NONE, NONE, NONE};
-        double t[4] = {0.0, 0.0, 0.0, 0.0};
+        // rank among the distinct columns; the (at most four) candidates of
+        // column f in candidate order, their terms loaded after the scan
+        int rank = 0, c0 = -1, c1 = -1, c2 = -1, c3 = -1;
         for (int k2 = 0; k2 < L; ++k2) {
-            const int f2 = F[k2];
-            rank += (first[k2] && f2 < f) ? 1 : 0;
-            if (f2 == f && nt < 4) {
-                key[nt] = K[k2];
-                t[nt] = T[k2];
-                ++nt;
+            const int pf = first[k2], f2 = pf >> 1;
+            rank += ((pf & 1) && f2 < f) ? 1 : 0;
+            if (f2 == f) {
+                if (c0 < 0) c0 = k2;
+                else if (c1 < 0) c1 = k2;
+                else if (c2 < 0) c2 = k2;
+                else if (c3 < 0) c3 = k2;
             }
+        }
+        const int cs[4] = {c0, c1, c2, c3};
+        unsigned long long key[4];
+        double t[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            key[r] = cs[r] >= 0 ? K[max(cs[r], 0)] : NONE;
+            t[r] = cs[r] >= 0 ? T[max(cs[r], 0)] : 0.0;
         }
         cswap(key[0], t[0], key[1], t[1]);
         cswap(key[2], t[2], key[3], t[3]);
