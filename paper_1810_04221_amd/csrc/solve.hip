@@ -1500,7 +1500,14 @@ void launch_resid(hipStream_t s, const Level &L, int nb, const double *b, const 
     });
 }
 
-int spmv_dots_grid(const Level &L, int nb) { return L.E.sp && split_slots(L, L.E.wide ? 16 : 8) ? L.E.nslices : nb; }
+// The grid-stride product runs on at most 1024 workgroups (eight or more rows
+// per thread on the largest grids: 160^3 product 84 -> 81 us, and half the
+// partials for its finalize step); the vector update keeps the 2048 of nb
+// (with 1024 it measured 55 -> 60 us there).
+constexpr int kSpmvBlocks = 1024;
+int spmv_dots_grid(const Level &L, int nb) {
+    return L.E.sp && split_slots(L, L.E.wide ? 16 : 8) ? L.E.nslices : std::min(nb, kSpmvBlocks);
+}
 
 void launch_spmv_dots(hipStream_t s, const Level &L, int nb, int first, const double *w, const double *r,
                       const double *q, double *v, double *partials, double *scal) {
