@@ -55,7 +55,7 @@ SETUP_CLASSES = ["setup_match", "setup_suitor", "setup_galerkin"]
 CLASSES = SOLVE_CLASSES + SETUP_CLASSES
 # classes that are one kernel launch per bracket
 SINGLE_KERNEL = ["down0", "up0", "spmv_dots", "update", "coarse", "setup_suitor"]
-KERNEL_OF_CLASS = {"down0": "k_down_res_sell (finest level: p * (b - A D b), the down leg's residual)",
+KERNEL_OF_CLASS = {"down0": "k_down_res_sell_ad (finest level: p * (b - (A D) b), the down leg's residual, on the values of A D)",
                    "up0": "k_smooth_sell (finest level: post-smoothing of the prolonged iterate)",
                    "spmv_dots": "k_spmv_dots_sell (v = A w and three dot products, finest level, FP64)",
                    "update": "k_update (four vector updates and ||r||^2)",

@@ -946,6 +946,15 @@ int build_hierarchy(bcm_handle *h, const bcm_csr *Ain, const double *win) {
             NOMEM((L.E.sc || L.E.sd) && (L.E.sv || L.E.sv32));
             launch_sell_fill(s, L.A.n, L.A.rp, L.A.ci, L.A.v, L.E.sp, uni[t], L.E.su, L.E.sc, L.E.sd, L.E.sv,
                              L.E.sv32);
+            // FP32 cycle, finest level on the split down leg with one thread per
+            // row: the values of A D for its residual (the long-row levels
+            // gather dinv o b instead)
+            if (lv_sell[t] == 0 && fp32 && down_on_sell(L) && !L.yb && !L.E.wide) {
+                L.E.svd = h->persist.get_n<float>(ne);
+                NOMEM(L.E.svd);
+                launch_sell_scale_cols(s, L.A.n, L.E.nslices, L.E.sp, L.E.uni, L.E.su, L.E.sc, L.E.sd, L.E.sv32,
+                                       L.dinv32, L.E.svd);
+            }
         }
     }
     {
@@ -1146,7 +1155,8 @@ double bytes_down(const bcm_handle *h, int k) {
     // level's reads its dinv and writes its y
     const bool scale = L.yb && !(k == 0 && h->y0) && !y_by_restrict(h, k);
     const double cy = y_by_restrict(h, k + 1) ? 2 * sv * nc : 0.0;
-    return sell ? base + 2 * sv * n + (scale ? (sb + 2 * sv) * n : 0.0) + cy : base;
+    const double ad = L.E.svd ? sv * n : 0.0;  // values of A D: dinv not read
+    return sell ? base + 2 * sv * n + (scale ? (sb + 2 * sv) * n : 0.0) + cy - ad : base;
 }
 // up leg: fused k_up, or k_prolong + k_smooth on large levels (xp written and read once)
 double bytes_up(const bcm_handle *h, int k) {
@@ -1167,7 +1177,8 @@ double bytes_down_main(const bcm_handle *h, int k) {
     const bool f32 = h->prm.precision == BCM_FP32_CYCLE;
     const double sv = f32 ? 4 : 8, sb = (k == 0 || !f32) ? 8 : 4, n = L.A.n, z = L.A.nnz;
     if (!down_on_sell(L)) return bytes_down(h, k);
-    return 4 * (n + 1) + (index_bytes(L, true) + value_bytes(L, true, f32)) * z + sb * n + 3 * sv * n;
+    // b read; p read and p r written; dinv read unless the values are those of A D
+    return 4 * (n + 1) + (index_bytes(L, true) + value_bytes(L, true, f32)) * z + sb * n + (L.E.svd ? 2 : 3) * sv * n;
 }
 double bytes_up_main(const bcm_handle *h, int k) {
     const Level &L = h->lv[k];

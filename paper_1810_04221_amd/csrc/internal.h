@@ -157,6 +157,9 @@ struct Sell {
     int *su = nullptr;
     double *sv = nullptr;
     float *sv32 = nullptr;
+    // finest level, FP32 cycle: sv32 scaled by the inverse l1 diagonal of each
+    // slot's column (the values of A D), read by the down leg's residual
+    float *svd = nullptr;
     double mixed = 1.0;  // fraction of the slots in slices that are not uniform
     int wide = 0;        // slices average more than kWideSlots slots: batches of 16
 };
@@ -340,6 +343,10 @@ void launch_sell_width(hipStream_t s, int n, const int *rp, const int *ci, const
 // fills the slots: int32 columns into sc, or int16 offsets into sd (one is null)
 void launch_sell_fill(hipStream_t s, int n, const int *rp, const int *ci, const double *v, const int *sp,
                       const int *uni, int *su, int *sc, short *sd, double *sv, float *sv32);
+// svd[slot] = sv32[slot] * dinv32[column of the slot] over every slot of the
+// sliced-ELL copy (rows past n: 0)
+void launch_sell_scale_cols(hipStream_t s, int n, int nslices, const int *sp, const int *uni, const int *su,
+                            const int *sc, const short *sd, const float *sv32, const float *dinv32, float *svd);
 void launch_fill_i32(hipStream_t s, size_t n, int *dst, int val);
 void launch_fill_u64(hipStream_t s, size_t n, unsigned long long *dst, unsigned long long val);
 void launch_copy_f64(hipStream_t s, size_t n, const double *src, double *dst);

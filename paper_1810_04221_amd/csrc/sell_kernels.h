@@ -68,6 +68,22 @@ __device__ __forceinline__ V sell_row(int n, const int *__restrict__ sp, const i
 }
 
 
+// FP32 cycle, finest level: the same residual with the values of A D (each
+// slot's value times its column's inverse l1 diagonal, formed at setup), so
+// each term gathers one vector:  pr_i = p_i (b_i - sum_j (a_ij dinv_j) b_j).
+template <typename VB, typename I, int kB>
+__global__ void __launch_bounds__(kBlock)
+k_down_res_sell_ad(int n, const int *__restrict__ sp, const int *__restrict__ uni, const int *__restrict__ su,
+                   const I *__restrict__ sc, const float *__restrict__ svd, const float *__restrict__ p,
+                   const VB *__restrict__ b, float *__restrict__ pr, const double *__restrict__ done) {
+    if (done && *done != 0.0) return;
+    const int i = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const float pi = p[i], bi = (float)b[i];  // loaded first, to overlap the product's loads
+    const float s = sell_row<float, float, I, kB>(n, sp, uni, su, sc, svd, i, [&](int j) { return (float)b[j]; });
+    pr[i] = pi * (bi - s);
+}
+
 // Large levels: the down leg as a row-parallel residual on the sliced ELL copy,
 //   pr_i = p_i (b_i - sum_j a_ij dinv_j b_j),
 // followed by the restriction b_c[E] = sum of pr over E's members in ascending

@@ -855,6 +855,37 @@ k_sell_fill(int n, const int *__restrict__ rp, const int *__restrict__ ci, const
     }
 }
 
+// The finest level's sliced-ELL values scaled by the inverse l1 diagonal of
+// their columns, svd = sv32 * dinv32[col] in float32, for the FP32 cycle's
+// down-leg residual b - (A D) b.  One thread per row lane of a slice; columns
+// as the row kernels read them (uniform offsets clamped to the row itself,
+// int16 offsets, or int32 columns).  Padding slots hold 0 and stay 0.
+__global__ void __launch_bounds__(kBlock)
+k_sell_scale_cols(int n, int nslices, const int *__restrict__ sp, const int *__restrict__ uni,
+                  const int *__restrict__ su, const int *__restrict__ sc, const short *__restrict__ sd,
+                  const float *__restrict__ sv32, const float *__restrict__ dinv32, float *__restrict__ svd) {
+    const int t = blockIdx.x * kBlock + threadIdx.x;
+    const int sl = t / kSlice, lane = t % kSlice;
+    if (sl >= nslices) return;
+    const int i = sl * kSlice + lane, beg = sp[sl], w = (sp[sl + 1] - beg) / kSlice;
+    const bool uf = su && uni[sl];
+    for (int k = 0; k < w; ++k) {
+        const int q = beg + k * kSlice + lane;
+        if (i >= n) {
+            svd[q] = 0.0f;
+            continue;
+        }
+        int col;
+        if (uf) {
+            const int cc = i + su[beg / kSlice + k];
+            col = (unsigned)cc < (unsigned)n ? cc : i;
+        } else {
+            col = sd ? i + (int)sd[q] : sc[q];
+        }
+        svd[q] = sv32[q] * dinv32[col];
+    }
+}
+
 __global__ void k_cast(size_t n, const double *__restrict__ src, float *__restrict__ dst) {
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
         dst[i] = (float)src[i];
@@ -1638,6 +1669,12 @@ void launch_sell_fill(hipStream_t s, int n, const int *rp, const int *ci, const 
                       const int *uni, int *su, int *sc, short *sd, double *sv, float *sv32) {
     hipLaunchKernelGGL(k_sell_fill, dim3(blocks_for(n)), dim3(kBlock), 0, s, n, rp, ci, v, sp, uni, su, sc, sd, sv,
                        sv32);
+}
+
+void launch_sell_scale_cols(hipStream_t s, int n, int nslices, const int *sp, const int *uni, const int *su,
+                            const int *sc, const short *sd, const float *sv32, const float *dinv32, float *svd) {
+    hipLaunchKernelGGL(k_sell_scale_cols, dim3(blocks_for((long long)nslices * kSlice)), dim3(kBlock), 0, s, n,
+                       nslices, sp, uni, su, sc, sd, sv32, dinv32, svd);
 }
 
 void launch_cast(hipStream_t s, size_t n, const double *src, float *dst) {

@@ -1194,6 +1194,10 @@ void down_t(hipStream_t s, const Level &L, const V *a, const V *dinv, const V *p
                 if (split_slots(L, decltype(kb)::value))
                     launch_k((k_down_res_sell_p<V, VB, I, S, 8>), dim3(L.E.nslices), dim3(kBlock), s, L.A.n, L.E.sp,
                              L.E.uni, L.E.su, ix, vals, dinv, p, b, pr, (const V *)y, done);
+                else if (std::is_same<V, float>::value && L.E.svd && !y)  // values of A D: one gather per term
+                    launch_k((k_down_res_sell_ad<VB, I, decltype(kb)::value>), dim3(blocks_for(L.A.n)), dim3(kBlock),
+                             s, L.A.n, L.E.sp, L.E.uni, L.E.su, ix, (const float *)L.E.svd, (const float *)p, b,
+                             (float *)pr, done);
                 else
                     launch_k((k_down_res_sell<V, VB, I, S, decltype(kb)::value>), dim3(blocks_for(L.A.n)), dim3(kBlock),
                              s, L.A.n, L.E.sp, L.E.uni, L.E.su, ix, vals, dinv, p, b, pr, (const V *)y, done);
