@@ -946,10 +946,13 @@ int build_hierarchy(bcm_handle *h, const bcm_csr *Ain, const double *win) {
             NOMEM((L.E.sc || L.E.sd) && (L.E.sv || L.E.sv32));
             launch_sell_fill(s, L.A.n, L.A.rp, L.A.ci, L.A.v, L.E.sp, uni[t], L.E.su, L.E.sc, L.E.sd, L.E.sv,
                              L.E.sv32);
-            // FP32 cycle, finest level on the split down leg with one thread per
-            // row: the values of A D for its residual (the long-row levels
-            // gather dinv o b instead)
-            if (lv_sell[t] == 0 && fp32 && down_on_sell(L) && !L.yb && !L.E.wide) {
+            // FP32 cycle, levels whose down leg is the sliced-ELL residual with
+            // one thread per row: the values of A D for it (the long-row levels
+            // gather dinv o b instead, the slot-split ones keep dinv and b).
+            // Below 2^19 rows the residual runs near its latency either way
+            // (250k rows: 4.6 against 4.7 us a launch, less over a solve than
+            // the scaling costs the setup), so only larger levels take it.
+            if (fp32 && down_on_sell(L) && !L.yb && !slot_split_level(L) && (lv_sell[t] == 0 || L.A.n >= (1 << 19))) {
                 L.E.svd = h->persist.get_n<float>(ne);
                 NOMEM(L.E.svd);
                 launch_sell_scale_cols(s, L.A.n, L.E.nslices, L.E.sp, L.E.uni, L.E.su, L.E.sc, L.E.sd, L.E.sv32,

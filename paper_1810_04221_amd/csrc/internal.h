@@ -416,6 +416,8 @@ void launch_resid(hipStream_t s, const Level &L, int nb, const double *b, const 
 // the vector kernels): one per slice on the levels whose rows it splits, else nb.
 // launch_spmv_dots takes this count and writes that many partials per product.
 int spmv_dots_grid(const Level &L, int nb);
+// level L's sliced-ELL legs take the slot-split kernels (wide slices, at most 2^19 rows)
+bool slot_split_level(const Level &L);
 void launch_spmv_dots(hipStream_t s, const Level &L, int nb, int first, const double *w, const double *r,
                       const double *q, double *v, double *partials, double *scal);
 // with y: also y = dinv o r (float when y_f32, else double; dinv of that type)

@@ -1509,6 +1509,8 @@ void launch_resid(hipStream_t s, const Level &L, int nb, const double *b, const 
 // partials for its finalize step); the vector update keeps the 2048 of nb
 // (with 1024 it measured 55 -> 60 us there).
 constexpr int kSpmvBlocks = 1024;
+bool slot_split_level(const Level &L) { return L.E.sp && split_slots(L, L.E.wide ? 16 : 8); }
+
 int spmv_dots_grid(const Level &L, int nb) {
     return L.E.sp && split_slots(L, L.E.wide ? 16 : 8) ? L.E.nslices : std::min(nb, kSpmvBlocks);
 }
