@@ -1095,7 +1095,9 @@ int build_hierarchy(bcm_handle *h, const bcm_csr *Ain, const double *win) {
     {
         // the product's partials: one per slice where it takes one workgroup per slice
         const int nbs = spmv_dots_grid(h->lv[0], h->red_blocks);
-        h->spart = nbs > h->red_blocks ? h->persist.get_n<double>(3 * (size_t)nbs) : h->partials;
+        // a buffer of its own: the update reads these partials while its
+        // workgroups write their own into h->partials
+        h->spart = h->persist.get_n<double>(3 * (size_t)nbs);
         NOMEM(h->spart);
     }
     if (P.cycle == BCM_KCYCLE) {
@@ -1525,10 +1527,11 @@ int capture_iteration(bcm_handle *h, int prof_cls) {
     const int nbs = spmv_dots_grid(L0, nb);
     launch_spmv_dots(h->cap, L0, nbs, 0, h->w, h->r, h->q, h->v, h->spart, h->scal);
     gp.end(2, e, 0.0, 0);
-    launch_finalize(h->cap, 1, nbs, 0, h->spart, h->scal);
+    const bool fuse = update_takes_dots(nbs);
+    if (!fuse) launch_finalize(h->cap, 1, nbs, 0, h->spart, h->scal);
     e = gp.begin(3);
     launch_update(h->cap, n, nb, 0, h->w, h->v, h->d, h->u, h->q, h->r, h->partials, h->scal, y0_dinv(h), h->y0,
-                  h->prm.precision == BCM_FP32_CYCLE);
+                  h->prm.precision == BCM_FP32_CYCLE, fuse ? h->spart : nullptr, nbs);
     gp.end(3, e, 0.0, 0);
     launch_finalize(h->cap, 2, nb, 0, h->partials, h->scal);
     sc.end();
@@ -1626,10 +1629,11 @@ int fcg_run(bcm_handle *h, const double *b, double *x_user, double tol) {
                 int e = pf.begin(2);
                 launch_spmv_dots(s, L0, nbs, first, h->w, h->r, h->q, h->v, h->spart, h->scal);
                 pf.end(2, e, bytes_spmv_dots(h), launched);
-                launch_finalize(s, 1, nbs, first, h->spart, h->scal);
+                const bool fuse = update_takes_dots(nbs);
+                if (!fuse) launch_finalize(s, 1, nbs, first, h->spart, h->scal);
                 e = pf.begin(3);
                 launch_update(s, n, nb, first, h->w, h->v, h->d, x, h->q, h->r, h->partials, h->scal, y0_dinv(h),
-                              h->y0, h->prm.precision == BCM_FP32_CYCLE);
+                              h->y0, h->prm.precision == BCM_FP32_CYCLE, fuse ? h->spart : nullptr, nbs);
                 pf.end(3, e, bytes_update(h), launched);
                 launch_finalize(s, 2, nb, 0, h->partials, h->scal);
                 first = 0;

@@ -62,11 +62,11 @@ __device__ __forceinline__ void block_sum(double (&v)[K], double *lds) {
 }
 
 // s[k] += partials[k * nb + bk] over bk = threadIdx.x, + blockDim.x, ... in
-// that order; eight block indices' loads are issued before any is added, so
-// the partials (just written by another kernel) cost few memory round trips.
-template <int K>
+// that order (whatever U); U block indices' loads are issued before any is
+// added, so the partials (just written by another kernel) cost few memory
+// round trips.
+template <int K, int U = 8>
 __device__ __forceinline__ void add_partials(double (&s)[K], const double *__restrict__ partials, int nb) {
-    constexpr int U = 8;
     for (int b0 = threadIdx.x; b0 < nb; b0 += U * blockDim.x) {
         double t[U][K];
 #pragma unroll

@@ -241,7 +241,7 @@ struct bcm_handle {
     int *tail_ops = nullptr;               // the tail kernel's program (device)
     int n_tail_ops = 0;
     double *partials = nullptr;
-    double *spart = nullptr;  // the finest product's partials (partials, or one per slice when it splits rows)
+    double *spart = nullptr;  // the finest product's partials (never aliases partials: the update reads them)
     double *lpart = nullptr;  // chunk sums of the long rows (the largest level's chunk count)
     double *kpart = nullptr;  // K-cycle block partials (3 * kKPartBlocks)
     double *ks = nullptr;     // K-cycle scalars, 8 per level
@@ -420,10 +420,15 @@ int spmv_dots_grid(const Level &L, int nb);
 bool slot_split_level(const Level &L);
 void launch_spmv_dots(hipStream_t s, const Level &L, int nb, int first, const double *w, const double *r,
                       const double *q, double *v, double *partials, double *scal);
-// with y: also y = dinv o r (float when y_f32, else double; dinv of that type)
+// with y: also y = dinv o r (float when y_f32, else double; dinv of that type).
+// with dots: the update adds the product's ndots partials and forms the step
+// scalars itself (no mode-1 finalize before it); allowed when
+// update_takes_dots(ndots).
 void launch_update(hipStream_t s, int n, int nb, int first, const double *w, const double *v,
                    double *d, double *u, double *q, double *r, double *partials, double *scal,
-                   const void *dinv = nullptr, void *y = nullptr, int y_f32 = 0);
+                   const void *dinv = nullptr, void *y = nullptr, int y_f32 = 0, const double *dots = nullptr,
+                   int ndots = 0);
+bool update_takes_dots(int nbs);
 void launch_finalize(hipStream_t s, int mode, int nb, int first, const double *partials, double *scal);
 void launch_sampled_outer(hipStream_t s, const Level &L, const double *lam, const double *x,
                           double *G);

@@ -256,15 +256,69 @@ __device__ __forceinline__ void update_range(int n, const double *__restrict__ w
     }
 }
 
-// YV: float or double, the type of dinv and y (y may be null)
+// The step scalars of Algorithm 3 from the sums s = (alpha, beta, gamma) of
+// the product's dot products: rho_i = beta - gamma^2 / rho_{i-1} (first step:
+// beta), g = gamma / rho_{i-1}, an = alpha / rho_i; false on breakdown (rho_i
+// not positive, or a scalar not finite).  rho_{i-1} sits in the slot of a
+// two-entry ring (scal[14], scal[15]) picked by the iteration count scal[11],
+// rho_i goes to the other one, so that every workgroup of the update can form
+// the scalars itself while one of them stores the new rho.  With write set the
+// caller also stores alpha, beta, gamma, g, an and the breakdown flags.
+__device__ __forceinline__ bool fcg_scalars(const double (&s)[3], int first, double *scal, bool write, double &g,
+                                            double &an) {
+    const double alpha = s[0], beta = s[1], gamma = s[2];
+    const int slot = (int)scal[11] & 1;
+    double rho;
+    if (first) { rho = beta; g = 0.0; }
+    else { const double rho_prev = scal[14 + slot]; rho = beta - gamma * gamma / rho_prev; g = gamma / rho_prev; }
+    an = alpha / rho;
+    const bool ok = (rho > 0.0) && isfinite(rho) && isfinite(an) && isfinite(g);
+    if (write) {
+        scal[0] = alpha;
+        scal[1] = beta;
+        scal[2] = gamma;
+        scal[6] = ok ? 0.0 : 1.0;
+        if (ok) { scal[15 - slot] = rho; scal[8] = g; scal[9] = an; }
+        else scal[10] = 1.0;
+    }
+    return ok;
+}
+
+// YV: float or double, the type of dinv and y (y may be null).
+// dots null: the step scalars come from scal (a k_finalize launch formed them).
+// dots set: every workgroup first adds the product's ndots block partials in
+// the order the one-block finalize takes with kBlock threads (bit-identical
+// sums) and forms the scalars itself; workgroup 0 stores them.
 template <typename YV>
 __global__ void __launch_bounds__(kBlock)
 k_update(int n, int first, const double *__restrict__ w, const double *__restrict__ v, double *__restrict__ d,
          double *__restrict__ u, double *__restrict__ q, double *__restrict__ r, const YV *__restrict__ dinv,
-         YV *__restrict__ y, const double *__restrict__ scal, double *__restrict__ partials) {
+         YV *__restrict__ y, double *__restrict__ scal, double *__restrict__ partials,
+         const double *__restrict__ dots, int ndots) {
     if (scal[10] != 0.0) return;
-    const bool ok = scal[6] == 0.0;
-    const double g = scal[8], an = scal[9];
+    bool ok;
+    double g, an;
+    if (dots) {
+        __shared__ double lds[3 * 16];
+        __shared__ double bc[3];
+        double s[3] = {0.0, 0.0, 0.0};
+        add_partials<3, 4>(s, dots, ndots);  // four loads a value: few registers
+        block_sum<3>(s, lds);
+        if (threadIdx.x == 0) {
+            const bool k = fcg_scalars(s, first, scal, blockIdx.x == 0, g, an);
+            bc[0] = k ? 1.0 : 0.0;
+            bc[1] = g;
+            bc[2] = an;
+        }
+        __syncthreads();
+        ok = bc[0] != 0.0;
+        g = bc[1];
+        an = bc[2];
+    } else {
+        ok = scal[6] == 0.0;
+        g = scal[8];
+        an = scal[9];
+    }
     double acc[1] = {0.0};
     if (ok) {
         const bool pairs = (long long)n >= 4LL * gridDim.x * kBlock;

@@ -1033,10 +1033,11 @@ k_spmv_dots(int n, const int *__restrict__ rp, const int *__restrict__ ci, const
 
 // Finalize: sums the block partials in block order, then
 //   mode 0 (residual):  scal[4] = ||r||^2, scal[5] = ||b||^2
-//   mode 1 (dots):      alpha, beta, gamma and the scalars of Algorithm 3:
-//                       rho_i = beta - gamma^2 / rho_{i-1} (first step: beta),
-//                       scal[8] = gamma / rho_{i-1}, scal[9] = alpha / rho_i,
-//                       scal[6] = 1 if rho_i <= 0 or not finite (breakdown)
+//   mode 1 (dots):      alpha, beta, gamma and the scalars of Algorithm 3
+//                       (fcg_scalars): scal[8] = gamma / rho_{i-1},
+//                       scal[9] = alpha / rho_i, scal[6] = 1 on breakdown
+//                       (the update forms them itself when it gets the
+//                       product's partials: no mode-1 launch then)
 //   mode 2 (norm):      scal[4] = ||r||^2, scal[11] += 1 (iterations done)
 // In the iteration loop (modes 1, 2) scal[10] != 0 means the solve has ended:
 // every kernel of a later iteration returns at once.  Mode 2 sets it when
@@ -1068,18 +1069,9 @@ __global__ void __launch_bounds__(kFinalize) k_finalize(int nb, const double *__
         if (!isfinite(s[0])) { scal[6] = 1.0; scal[10] = 1.0; }
         else if (s[0] <= scal[12] || it >= scal[13]) scal[10] = 1.0;
     } else {
-        const double alpha = s[0], beta = s[1 % K], gamma = s[2 % K];
-        double rho, g;
-        if (first) { rho = beta; g = 0.0; }
-        else { const double rho_prev = scal[3]; rho = beta - gamma * gamma / rho_prev; g = gamma / rho_prev; }
-        const double an = alpha / rho;
-        const bool ok = (rho > 0.0) && isfinite(rho) && isfinite(an) && isfinite(g);
-        scal[0] = alpha;
-        scal[1] = beta;
-        scal[2] = gamma;
-        scal[6] = ok ? 0.0 : 1.0;
-        if (ok) { scal[3] = rho; scal[8] = g; scal[9] = an; }
-        else scal[10] = 1.0;
+        const double d3[3] = {s[0], s[1 % K], s[2 % K]};
+        double g, an;
+        (void)fcg_scalars(d3, first, scal, true, g, an);
     }
 }
 
@@ -1540,15 +1532,20 @@ void launch_spmv_dots(hipStream_t s, const Level &L, int nb, int first, const do
     });
 }
 
+// Up to kSpmvBlocks product partials every update workgroup adds them itself
+// (24 KB of L2-resident loads each) instead of a one-block finalize launch; the
+// one-workgroup-per-slice product's thousands of partials keep that launch.
+bool update_takes_dots(int nbs) { return nbs <= kSpmvBlocks; }
+
 void launch_update(hipStream_t s, int n, int nb, int first, const double *w, const double *v, double *d,
                    double *u, double *q, double *r, double *partials, double *scal, const void *dinv, void *y,
-                   int y_f32) {
+                   int y_f32, const double *dots, int ndots) {
     if (y && y_f32)
         launch_k((k_update<float>), dim3(nb), dim3(kBlock), s, n, first, w, v, d, u, q, r, (const float *)dinv,
-                 (float *)y, scal, partials);
+                 (float *)y, scal, partials, dots, ndots);
     else
         launch_k((k_update<double>), dim3(nb), dim3(kBlock), s, n, first, w, v, d, u, q, r, (const double *)dinv,
-                 (double *)y, scal, partials);
+                 (double *)y, scal, partials, dots, ndots);
 }
 
 void launch_finalize(hipStream_t s, int mode, int nb, int first, const double *partials, double *scal) {
