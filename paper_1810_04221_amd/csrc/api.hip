@@ -1413,8 +1413,10 @@ void cycle_level(bcm_handle *h, Prof &pf, int k, const double *done, int iter) {
 // --------------------------------------------------------------- V-cycle
 // One cycle of Algorithm 1 from a zero guess: z = B(r).  done: see launch_down.
 // y0: dinv o r of the finest level already formed (the update's h->y0), or null.
+// st: the stop test of the flexible-CG update before this cycle, taken by the
+// finest level's first kernel (only where cycle_takes_stop(h)); default none.
 void vcycle(bcm_handle *h, Prof &pf, const double *rin, double *wout, const double *done, int iter,
-            const void *y0 = nullptr) {
+            const void *y0 = nullptr, StopTest st = {}) {
     hipStream_t s = h->s;
     const int fp32 = h->prm.precision == BCM_FP32_CYCLE;
     const int nl = h->nl;
@@ -1430,7 +1432,7 @@ void vcycle(bcm_handle *h, Prof &pf, const double *rin, double *wout, const doub
         // finest level here (f64 in/out), coarse levels recursively
         Level &L = h->lv[0], &N = h->lv[1];
         int e = pf.begin(0);
-        launch_down(s, L, fp32, rin, N.b, 1, done, 1, y0);
+        launch_down(s, L, fp32, rin, N.b, 1, done, 1, y0, nullptr, st);
         pf.end(0, e, class_bytes(h, 0), iter);
         launch_down(s, L, fp32, rin, N.b, 1, done, 2);
         coarse_solve(h, pf, 0, done, iter);
@@ -1450,7 +1452,7 @@ void vcycle(bcm_handle *h, Prof &pf, const double *rin, double *wout, const doub
         const Level *next = y_by_restrict(h, k + 1) ? &h->lv[k + 1] : nullptr;
         if (k == 0) {  // the finest level's main kernel alone is class 0
             int e = pf.begin(0);
-            launch_down(s, L, fp32, bk, h->lv[1].b, io, done, 1, y0);
+            launch_down(s, L, fp32, bk, h->lv[1].b, io, done, 1, y0, nullptr, st);
             pf.end(0, e, class_bytes(h, 0), iter);
             launch_down(s, L, fp32, bk, h->lv[1].b, io, done, 2, nullptr, next);
         } else {
@@ -1504,6 +1506,16 @@ const void *y0_dinv(const bcm_handle *h) {
     return h->prm.precision == BCM_FP32_CYCLE ? (const void *)h->lv[0].dinv32 : (const void *)h->lv[0].dinv;
 }
 
+// The flexible-CG stop test after an update is taken by workgroup 0 of the
+// next cycle's first kernel where that is a sliced-ELL residual kernel (it
+// hides behind the other workgroups); elsewhere a one-block finalize launch
+// after the update takes it.
+bool cycle_takes_stop(const bcm_handle *h) { return h->nl > 1 && down_on_sell(h->lv[0]); }
+
+StopTest stop_test_of(const bcm_handle *h) {
+    return cycle_takes_stop(h) ? StopTest{h->partials, h->scal, h->red_blocks} : StopTest{};
+}
+
 void destroy_iteration_graphs(bcm_handle *h) {
     for (auto &g : h->iter_exec)
         if (g) { (void)hipGraphExecDestroy(g); g = nullptr; }
@@ -1522,7 +1534,7 @@ int capture_iteration(bcm_handle *h, int prof_cls) {
     hipStream_t keep = h->s;
     h->s = h->cap;
     sc.begin();
-    vcycle(h, gp, h->r, h->w, h->scal + 10, 0, h->y0);
+    vcycle(h, gp, h->r, h->w, h->scal + 10, 0, h->y0, stop_test_of(h));
     int e = gp.begin(2);
     const int nbs = spmv_dots_grid(L0, nb);
     launch_spmv_dots(h->cap, L0, nbs, 0, h->w, h->r, h->q, h->v, h->spart, h->scal);
@@ -1533,7 +1545,7 @@ int capture_iteration(bcm_handle *h, int prof_cls) {
     launch_update(h->cap, n, nb, 0, h->w, h->v, h->d, h->u, h->q, h->r, h->partials, h->scal, y0_dinv(h), h->y0,
                   h->prm.precision == BCM_FP32_CYCLE, fuse ? h->spart : nullptr, nbs);
     gp.end(3, e, 0.0, 0);
-    launch_finalize(h->cap, 2, nb, 0, h->partials, h->scal);
+    if (!cycle_takes_stop(h)) launch_finalize(h->cap, 2, nb, 0, h->partials, h->scal);
     sc.end();
     h->s = keep;
     hipError_t err = sc.err;
@@ -1625,7 +1637,7 @@ int fcg_run(bcm_handle *h, const double *b, double *x_user, double tol) {
                     continue;
                 }
                 // the first iteration's r comes from the residual kernel: no y0 yet
-                vcycle(h, pf, h->r, h->w, done, launched, first ? nullptr : h->y0);
+                vcycle(h, pf, h->r, h->w, done, launched, first ? nullptr : h->y0, stop_test_of(h));
                 int e = pf.begin(2);
                 launch_spmv_dots(s, L0, nbs, first, h->w, h->r, h->q, h->v, h->spart, h->scal);
                 pf.end(2, e, bytes_spmv_dots(h), launched);
@@ -1635,10 +1647,12 @@ int fcg_run(bcm_handle *h, const double *b, double *x_user, double tol) {
                 launch_update(s, n, nb, first, h->w, h->v, h->d, x, h->q, h->r, h->partials, h->scal, y0_dinv(h),
                               h->y0, h->prm.precision == BCM_FP32_CYCLE, fuse ? h->spart : nullptr, nbs);
                 pf.end(3, e, bytes_update(h), launched);
-                launch_finalize(s, 2, nb, 0, h->partials, h->scal);
+                if (!cycle_takes_stop(h)) launch_finalize(s, 2, nb, 0, h->partials, h->scal);
                 first = 0;
                 ++launched;
             }
+            // the batch's last stop test (a no-op where it has been taken)
+            launch_finalize(s, 2, nb, 0, h->partials, h->scal);
             rc = read_back(s, h->scal, 16 * sizeof(double), hs);
             if (rc) return rc;
             it = (int)hs[11];

@@ -96,4 +96,40 @@ __device__ __forceinline__ void block_partials(double (&v)[K], double *partials)
         for (int k = 0; k < K; ++k) partials[(size_t)k * gridDim.x + blockIdx.x] = v[k];
 }
 
+// The flexible-CG stop test on rr = ||r||^2 of the update just run: stores it
+// in scal[4], counts the iteration in scal[11], and ends the loop (scal[10] =
+// 1) when rr <= scal[12] (= tol^2 ||b||^2), the count reaches scal[13]
+// (itmax) or rr is not finite (then also scal[6] = 1, breakdown).  Clears
+// scal[7], the update's mark of partials not yet taken.  True when it ended.
+__device__ __forceinline__ bool stop_norm(double rr, double *scal) {
+    scal[4] = rr;
+    const double it = scal[11] + 1.0;
+    scal[11] = it;
+    bool end = false;
+    if (!isfinite(rr)) { scal[6] = 1.0; end = true; }
+    else if (rr <= scal[12] || it >= scal[13]) end = true;
+    if (end) scal[10] = 1.0;
+    scal[7] = 0.0;
+    return end;
+}
+
+// The stop test taken by workgroup 0 of the first kernel of a cycle (all its
+// threads call it, before any returns): when the update left partials not yet
+// taken (scal[7] != 0), adds its nb partials in the order of the one-block
+// finalize with kBlock threads and applies stop_norm.  True when the loop has
+// ended (scal[10] set now or before): the workgroup then skips its work.  The
+// kernel's other workgroups run on; the kernels after it see scal[10].
+__device__ __forceinline__ bool stop_test(const double *__restrict__ part, double *scal, int nb) {
+    __shared__ double lds[16];
+    __shared__ int end;
+    if (scal[10] != 0.0) return true;
+    if (scal[7] == 0.0) return false;
+    double s[1] = {0.0};
+    add_partials<1>(s, part, nb);
+    block_sum<1>(s, lds);
+    if (threadIdx.x == 0) end = stop_norm(s[0], scal) ? 1 : 0;
+    __syncthreads();
+    return end != 0;
+}
+
 }  // namespace bcm

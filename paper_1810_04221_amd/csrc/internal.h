@@ -211,6 +211,15 @@ struct ProfClass {
 
 }  // namespace bcm
 
+// The flexible-CG loop's stop test after an update, handed to the first kernel
+// of the next cycle: part holds the update's nb block partials of ||r||^2 and
+// scal the loop's scalars; part null: no stop test.
+struct StopTest {
+    const double *part;
+    double *scal;
+    int nb;
+};
+
 struct bcm_handle {
     bcm_params prm{};
     hipStream_t s = nullptr;
@@ -370,8 +379,11 @@ inline bool down_on_sell(const Level &L) { return L.E.sp && L.xp && (L.mstride =
 // in the cycle's type; null: formed here when the level needs it.  next (part
 // 0 or 2 of such a leg): the coarser level, whose dinv o b the restriction
 // then also writes into next->yb; null: it does not.
+// st (part 1 of a sliced-ELL level's leg): the flexible-CG stop test that
+// workgroup 0 of its residual kernel takes first (StopTest); default: none.
 void launch_down(hipStream_t s, const Level &L, int fp32, const void *b, void *bc, int b_is_f64,
-                 const double *done, int part = 0, const void *yr = nullptr, const Level *next = nullptr);
+                 const double *done, int part = 0, const void *yr = nullptr, const Level *next = nullptr,
+                 StopTest st = {});
 void launch_up(hipStream_t s, const Level &L, int fp32, const void *b, const void *xc, void *x,
                int b_is_f64, int x_is_f64, const double *done, int part = 0);
 void launch_coarse(hipStream_t s, const Level &L, int sweeps, const void *b, void *x, int b_f64,

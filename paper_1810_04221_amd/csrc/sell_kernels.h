@@ -75,8 +75,11 @@ template <typename VB, typename I, int kB>
 __global__ void __launch_bounds__(kBlock)
 k_down_res_sell_ad(int n, const int *__restrict__ sp, const int *__restrict__ uni, const int *__restrict__ su,
                    const I *__restrict__ sc, const float *__restrict__ svd, const float *__restrict__ p,
-                   const VB *__restrict__ b, float *__restrict__ pr, const double *__restrict__ done) {
-    if (done && *done != 0.0) return;
+                   const VB *__restrict__ b, float *__restrict__ pr, const double *__restrict__ done,
+                   StopTest st) {
+    if (st.part && blockIdx.x == 0) {
+        if (stop_test(st.part, st.scal, st.nb)) return;
+    } else if (done && *done != 0.0) return;
     const int i = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
     if (i >= n) return;
     const float pi = p[i], bi = (float)b[i];  // loaded first, to overlap the product's loads
@@ -94,9 +97,11 @@ k_down_res_sell(int n, const int *__restrict__ sp, const int *__restrict__ uni,
                 const int *__restrict__ su, const I *__restrict__ sc,
                 const S *__restrict__ sv,
                 const V *__restrict__ dinv, const V *__restrict__ p, const VB *__restrict__ b, V *__restrict__ pr,
-                const V *__restrict__ y, const double *__restrict__ done) {
+                const V *__restrict__ y, const double *__restrict__ done, StopTest st) {
     // y given (levels with long rows): dinv o b formed beforehand, one gather per term
-    if (done && *done != 0.0) return;
+    if (st.part && blockIdx.x == 0) {
+        if (stop_test(st.part, st.scal, st.nb)) return;
+    } else if (done && *done != 0.0) return;
     const int i = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
     if (i >= n) return;
     const V pi = p[i], bi = (V)b[i];  // loaded first, to overlap the product's loads
@@ -328,4 +333,5 @@ k_update(int n, int first, const double *__restrict__ w, const double *__restric
         else update_range1<false>(n, w, v, d, u, q, r, dinv, y, g, an, acc[0]);
     }
     block_partials<1>(acc, partials);
+    if (blockIdx.x == 0 && threadIdx.x == 0) scal[7] = 1.0;  // partials for the stop test
 }

@@ -74,9 +74,11 @@ __global__ void __launch_bounds__(kBlock)
 k_down_res_sell_p(int n, const int *__restrict__ sp, const int *__restrict__ uni, const int *__restrict__ su,
                   const I *__restrict__ sc, const S *__restrict__ sv, const V *__restrict__ dinv,
                   const V *__restrict__ p, const VB *__restrict__ b, V *__restrict__ pr, const V *__restrict__ y,
-                  const double *__restrict__ done) {
+                  const double *__restrict__ done, StopTest st) {
     __shared__ V red[kParts][kSlice];
-    if (done && *done != 0.0) return;
+    if (st.part && blockIdx.x == 0) {
+        if (stop_test(st.part, st.scal, st.nb)) return;
+    } else if (done && *done != 0.0) return;
     const int sl = xcd_block(blockIdx.x, gridDim.x);
     const int i = sl * kSlice + (int)threadIdx.x % kSlice;
     V s;

@@ -1038,7 +1038,9 @@ k_spmv_dots(int n, const int *__restrict__ rp, const int *__restrict__ ci, const
 //                       scal[9] = alpha / rho_i, scal[6] = 1 on breakdown
 //                       (the update forms them itself when it gets the
 //                       product's partials: no mode-1 launch then)
-//   mode 2 (norm):      scal[4] = ||r||^2, scal[11] += 1 (iterations done)
+//   mode 2 (norm):      the stop test (stop_norm): scal[4] = ||r||^2,
+//                       scal[11] += 1 (iterations done); a no-op when the
+//                       first kernel of the next cycle has taken it already
 // In the iteration loop (modes 1, 2) scal[10] != 0 means the solve has ended:
 // every kernel of a later iteration returns at once.  Mode 2 sets it when
 // ||r||^2 <= scal[12] (= tol^2 ||b||^2) or scal[11] >= scal[13] (itmax); mode 1
@@ -1052,6 +1054,7 @@ template <int K>
 __global__ void __launch_bounds__(kFinalize) k_finalize(int nb, const double *__restrict__ partials,
                                                      double *__restrict__ scal, int mode, int first) {
     if (mode != 0 && scal[10] != 0.0) return;
+    if (mode == 2 && scal[7] == 0.0) return;  // the next cycle's stop test took them
     __shared__ double lds[K * 16];
     double s[K];
 #pragma unroll
@@ -1062,12 +1065,9 @@ __global__ void __launch_bounds__(kFinalize) k_finalize(int nb, const double *__
     if (mode == 0) {
         scal[4] = s[0];
         scal[5] = s[1 % K];
+        scal[7] = 0.0;
     } else if (mode == 2) {
-        scal[4] = s[0];
-        const double it = scal[11] + 1.0;
-        scal[11] = it;
-        if (!isfinite(s[0])) { scal[6] = 1.0; scal[10] = 1.0; }
-        else if (s[0] <= scal[12] || it >= scal[13]) scal[10] = 1.0;
+        (void)stop_norm(s[0], scal);
     } else {
         const double d3[3] = {s[0], s[1 % K], s[2 % K]};
         double g, an;
@@ -1172,7 +1172,7 @@ void down_dispatch(hipStream_t s, const Level &L, const V *a, const V *dinv, con
 // dinv o b, formed by the restriction here when cy is given.
 template <typename V, typename VB>
 void down_t(hipStream_t s, const Level &L, const V *a, const V *dinv, const V *p, const VB *b, V *bc,
-            const double *done, int part, const V *yr, const V *cd, V *cy) {
+            const double *done, int part, const V *yr, const V *cd, V *cy, StopTest st) {
     if (down_on_sell(L)) {
         V *pr = (V *)L.xp;  // free during the down leg: the up leg of this level runs later
         const V *y = yr ? yr : (const V *)L.yb;
@@ -1185,14 +1185,14 @@ void down_t(hipStream_t s, const Level &L, const V *a, const V *dinv, const V *p
                 using S = std::remove_const_t<std::remove_pointer_t<decltype(vals)>>;
                 if (split_slots(L, decltype(kb)::value))
                     launch_k((k_down_res_sell_p<V, VB, I, S, 8>), dim3(L.E.nslices), dim3(kBlock), s, L.A.n, L.E.sp,
-                             L.E.uni, L.E.su, ix, vals, dinv, p, b, pr, (const V *)y, done);
+                             L.E.uni, L.E.su, ix, vals, dinv, p, b, pr, (const V *)y, done, st);
                 else if (std::is_same<V, float>::value && L.E.svd && !y)  // values of A D: one gather per term
                     launch_k((k_down_res_sell_ad<VB, I, decltype(kb)::value>), dim3(blocks_for(L.A.n)), dim3(kBlock),
                              s, L.A.n, L.E.sp, L.E.uni, L.E.su, ix, (const float *)L.E.svd, (const float *)p, b,
-                             (float *)pr, done);
+                             (float *)pr, done, st);
                 else
                     launch_k((k_down_res_sell<V, VB, I, S, decltype(kb)::value>), dim3(blocks_for(L.A.n)), dim3(kBlock),
-                             s, L.A.n, L.E.sp, L.E.uni, L.E.su, ix, vals, dinv, p, b, pr, (const V *)y, done);
+                             s, L.A.n, L.E.sp, L.E.uni, L.E.su, ix, vals, dinv, p, b, pr, (const V *)y, done, st);
             });
         }
         if (part == 1) return;
@@ -1314,17 +1314,17 @@ int reduce_blocks(int n) {
 }
 
 void launch_down(hipStream_t s, const Level &L, int fp32, const void *b, void *bc, int b_is_f64,
-                 const double *done, int part, const void *yr, const Level *next) {
+                 const double *done, int part, const void *yr, const Level *next, StopTest st) {
     void *cy = next ? next->yb : nullptr;
     if (!fp32) {
         down_t<double, double>(s, L, L.A.v, L.dinv, L.p, (const double *)b, (double *)bc, done, part,
-                               (const double *)yr, cy ? next->dinv : nullptr, (double *)cy);
+                               (const double *)yr, cy ? next->dinv : nullptr, (double *)cy, st);
     } else if (b_is_f64) {
         down_t<float, double>(s, L, L.A.v32, L.dinv32, L.p32, (const double *)b, (float *)bc, done, part,
-                              (const float *)yr, cy ? next->dinv32 : nullptr, (float *)cy);
+                              (const float *)yr, cy ? next->dinv32 : nullptr, (float *)cy, st);
     } else {
         down_t<float, float>(s, L, L.A.v32, L.dinv32, L.p32, (const float *)b, (float *)bc, done, part,
-                             (const float *)yr, cy ? next->dinv32 : nullptr, (float *)cy);
+                             (const float *)yr, cy ? next->dinv32 : nullptr, (float *)cy, st);
     }
 }
 
