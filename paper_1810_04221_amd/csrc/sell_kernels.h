@@ -16,8 +16,10 @@ __device__ __forceinline__ int sell_col(short d, int i) { return i + (int)d; }
 // any is used: a slot past the width re-reads the last one and is not added
 // (w is the same for the whole wave), so no batch ends in a chain of one-slot
 // steps.  Accumulates into s left to right.  Uni: column offsets from the
-// slice's shared list u, else from the per-entry columns c.
-template <int kB, bool Uni, typename V, typename S, typename I, typename F>
+// slice's shared list u, else from the per-entry columns c.  NT: the values
+// are loaded non-temporally (streamed past the L2, which then keeps more of
+// the gathered vector).
+template <int kB, bool Uni, typename V, typename S, typename I, typename F, bool NT = false>
 __device__ __forceinline__ V sell_slots(const S *a, const int *u, const I *c, int n, int i, int w, V s, F f) {
     for (int k0 = 0; k0 < w; k0 += kB) {
         S av[kB];
@@ -25,7 +27,8 @@ __device__ __forceinline__ V sell_slots(const S *a, const int *u, const I *c, in
 #pragma unroll
         for (int t = 0; t < kB; ++t) {
             const int k = min(k0 + t, w - 1);
-            av[t] = a[k * kSlice];
+            if (NT) av[t] = __builtin_nontemporal_load(&a[k * kSlice]);
+            else av[t] = a[k * kSlice];
             if (Uni) {
                 const int cc = i + u[k];
                 fv[t] = f((unsigned)cc < (unsigned)n ? cc : i);
@@ -51,7 +54,7 @@ __device__ __forceinline__ V sell_slots(const S *a, const int *u, const I *c, in
 // slot for the whole wave, instead of one per entry; a slot a row does not
 // have holds the value 0 (its column clamped into the matrix when it would
 // leave it).
-template <typename V, typename S, typename I, int kB, typename F>
+template <typename V, typename S, typename I, int kB, typename F, bool NT = false>
 __device__ __forceinline__ V sell_row(int n, const int *__restrict__ sp, const int *__restrict__ uni,
                                       const int *__restrict__ su, const I *__restrict__ sc,
                                       const S *__restrict__ sv, int i, F f) {
@@ -63,8 +66,8 @@ __device__ __forceinline__ V sell_row(int n, const int *__restrict__ sp, const i
     const S *a = sv + beg + lane;
     const int *u = su + beg / kSlice;
     const I *c = sc + beg + lane;
-    if (uf) return sell_slots<kB, true>(a, u, c, n, i, w, V(0), f);
-    return sell_slots<kB, false>(a, u, c, n, i, w, V(0), f);
+    if (uf) return sell_slots<kB, true, V, S, I, F, NT>(a, u, c, n, i, w, V(0), f);
+    return sell_slots<kB, false, V, S, I, F, NT>(a, u, c, n, i, w, V(0), f);
 }
 
 
@@ -151,7 +154,29 @@ k_resid_sell(int n, const int *__restrict__ sp, const int *__restrict__ uni,
     block_partials<2>(acc, partials);
 }
 
-template <typename I, typename S, int kB>
+// The rows a workgroup of a grid-stride kernel walks, XCD by XCD: when the
+// grid is a multiple of the eight XCDs, the workgroups of one XCD (consecutive
+// logical blocks under xcd_block) take one contiguous eighth of the rows and
+// stride through it together, kBlock rows per workgroup and step.  The far
+// neighbours of a row (the z-neighbours of a 3-D grid, about n^(2/3) rows
+// away) are then rows the same XCD has just loaded or is about to, in its own
+// L2, instead of rows of another XCD's window of the same step.
+struct XcdRows {
+    int first, end, stride;
+};
+__device__ __forceinline__ XcdRows xcd_rows(int n, int blk, int nb) {
+    constexpr int X = 8;
+    if (nb % X != 0) return XcdRows{blk * kBlock, n, nb * kBlock};
+    const int per = nb / X, x = blk / per, j = blk - x * per;
+    const long long chunk = ((long long)n + X - 1) / X;
+    const long long len = (chunk + kBlock - 1) / kBlock * kBlock;
+    const long long lo = x * len, hi = lo + len < n ? lo + len : n;
+    return XcdRows{(int)(lo + (long long)j * kBlock), (int)hi, per * kBlock};
+}
+
+// NT: the matrix values streamed non-temporally (levels whose values exceed
+// the Infinity Cache's share: the gathered w then stays in each XCD's L2).
+template <typename I, typename S, int kB, bool NT>
 __global__ void __launch_bounds__(kBlock)
 k_spmv_dots_sell(int n, const int *__restrict__ sp, const int *__restrict__ uni,
                 const int *__restrict__ su, const I *__restrict__ sc,
@@ -159,12 +184,13 @@ k_spmv_dots_sell(int n, const int *__restrict__ sp, const int *__restrict__ uni,
                  const double *__restrict__ w, const double *__restrict__ r, const double *__restrict__ q,
                  double *__restrict__ v, double *__restrict__ partials, const double *__restrict__ done) {
     if (done && *done != 0.0) return;
-    const int blk = xcd_block(blockIdx.x, gridDim.x);
+    const XcdRows xr = xcd_rows(n, xcd_block(blockIdx.x, gridDim.x), gridDim.x);
     double acc[3] = {0.0, 0.0, 0.0};
-    for (int i = blk * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+    for (int i = xr.first + threadIdx.x; i < xr.end; i += xr.stride) {
         // the row's own entries are loaded first, to overlap the product's loads
         const double wi = w[i], ri = r[i], qi = q[i];
-        const double s = sell_row<double, S, I, kB>(n, sp, uni, su, sc, sv, i, [&](int j) { return w[j]; });
+        auto g = [&](int j) { return w[j]; };
+        const double s = sell_row<double, S, I, kB, decltype(g), NT>(n, sp, uni, su, sc, sv, i, g);
         v[i] = s;
         acc[0] += wi * ri;
         acc[1] += wi * s;
