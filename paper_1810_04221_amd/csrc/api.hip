@@ -959,6 +959,16 @@ int build_hierarchy(bcm_handle *h, const bcm_csr *Ain, const double *win) {
                                        L.dinv32, L.E.svd);
             }
         }
+        // the values one solve iteration reads: both legs of every sliced-ELL
+        // level in the cycle's type, and the finest level's product
+        long long vb = 0;
+        for (size_t t = 0; t < lv_sell.size(); ++t) {
+            const Level &L = h->lv[lv_sell[t]];
+            const long long ne = tots[t];
+            vb += 2 * ne * (fp32 || !L.E.sv ? 4 : 8);
+            if (lv_sell[t] == 0) vb += ne * (L.E.sv ? 8 : 4);
+        }
+        for (size_t t = 0; t < lv_sell.size(); ++t) h->lv[lv_sell[t]].E.stream = vb > kStreamSolve;
     }
     {
         // coarsest level: precompute the sweep operator when it is small

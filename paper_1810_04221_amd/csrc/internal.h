@@ -162,7 +162,19 @@ struct Sell {
     float *svd = nullptr;
     double mixed = 1.0;  // fraction of the slots in slices that are not uniform
     int wide = 0;        // slices average more than kWideSlots slots: batches of 16
+    // the solve's one-thread-per-row kernels load the values non-temporally: set
+    // on every level when the values a solve iteration reads exceed kStreamSolve
+    int stream = 0;
 };
+
+// Bytes of matrix values per solve iteration (both cycle legs of every
+// sliced-ELL level and the finest level's product) above which the values
+// are streamed: below it they stay in the 256 MB Infinity Cache between
+// iterations, and non-temporal loads that skip it measured slower (100^3:
+// about 0.1 GB, solve +4.6%); above it the cache cannot hold them and the L2
+// keeps the gathered vectors instead (160^3 residual 43.0 -> 40.4 us, product
+// 78.6 -> 74.8 us; 128^3 and 160^3 ratio-rule solves -4.6% and -1.4%).
+constexpr long long kStreamSolve = 192LL << 20;
 
 // One level of the hierarchy.  Row i of A^k, its l1 inverse diagonal, the
 // composed prolongator P^k (one nonzero per row: column agg[i], value p[i]),

@@ -74,7 +74,7 @@ __device__ __forceinline__ V sell_row(int n, const int *__restrict__ sp, const i
 // FP32 cycle, finest level: the same residual with the values of A D (each
 // slot's value times its column's inverse l1 diagonal, formed at setup), so
 // each term gathers one vector:  pr_i = p_i (b_i - sum_j (a_ij dinv_j) b_j).
-template <typename VB, typename I, int kB>
+template <typename VB, typename I, int kB, bool NT>
 __global__ void __launch_bounds__(kBlock)
 k_down_res_sell_ad(int n, const int *__restrict__ sp, const int *__restrict__ uni, const int *__restrict__ su,
                    const I *__restrict__ sc, const float *__restrict__ svd, const float *__restrict__ p,
@@ -86,7 +86,8 @@ k_down_res_sell_ad(int n, const int *__restrict__ sp, const int *__restrict__ un
     const int i = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
     if (i >= n) return;
     const float pi = p[i], bi = (float)b[i];  // loaded first, to overlap the product's loads
-    const float s = sell_row<float, float, I, kB>(n, sp, uni, su, sc, svd, i, [&](int j) { return (float)b[j]; });
+    auto g = [&](int j) { return (float)b[j]; };
+    const float s = sell_row<float, float, I, kB, decltype(g), NT>(n, sp, uni, su, sc, svd, i, g);
     pr[i] = pi * (bi - s);
 }
 
@@ -115,8 +116,9 @@ k_down_res_sell(int n, const int *__restrict__ sp, const int *__restrict__ uni,
 }
 
 
-// k_smooth on the sliced ELL copy, one thread per row.
-template <typename V, typename VB, typename VX, typename I, typename S, int kB>
+// k_smooth on the sliced ELL copy, one thread per row.  NT: the values are
+// streamed non-temporally (Sell::stream).
+template <typename V, typename VB, typename VX, typename I, typename S, int kB, bool NT>
 __global__ void __launch_bounds__(kBlock)
 k_smooth_sell(int n, const int *__restrict__ sp, const int *__restrict__ uni,
                 const int *__restrict__ su, const I *__restrict__ sc,
@@ -127,7 +129,8 @@ k_smooth_sell(int n, const int *__restrict__ sp, const int *__restrict__ uni,
     const int i = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
     if (i >= n) return;
     const V xi = xp[i], di = dinv[i], bi = (V)b[i];  // loaded first, to overlap the product's loads
-    const V s = sell_row<V, S, I, kB>(n, sp, uni, su, sc, sv, i, [&](int j) { return xp[j]; });
+    auto g = [&](int j) { return xp[j]; };
+    const V s = sell_row<V, S, I, kB, decltype(g), NT>(n, sp, uni, su, sc, sv, i, g);
     x[i] = (VX)(xi + di * (bi - s));
 }
 
@@ -174,8 +177,8 @@ __device__ __forceinline__ XcdRows xcd_rows(int n, int blk, int nb) {
     return XcdRows{(int)(lo + (long long)j * kBlock), (int)hi, per * kBlock};
 }
 
-// NT: the matrix values streamed non-temporally (levels whose values exceed
-// the Infinity Cache's share: the gathered w then stays in each XCD's L2).
+// NT: the matrix values streamed non-temporally (Sell::stream: the gathered
+// w then stays in each XCD's L2).
 template <typename I, typename S, int kB, bool NT>
 __global__ void __launch_bounds__(kBlock)
 k_spmv_dots_sell(int n, const int *__restrict__ sp, const int *__restrict__ uni,

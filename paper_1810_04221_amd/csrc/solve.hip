@@ -1186,10 +1186,14 @@ void down_t(hipStream_t s, const Level &L, const V *a, const V *dinv, const V *p
                 if (split_slots(L, decltype(kb)::value))
                     launch_k((k_down_res_sell_p<V, VB, I, S, 8>), dim3(L.E.nslices), dim3(kBlock), s, L.A.n, L.E.sp,
                              L.E.uni, L.E.su, ix, vals, dinv, p, b, pr, (const V *)y, done, st);
-                else if (std::is_same<V, float>::value && L.E.svd && !y)  // values of A D: one gather per term
-                    launch_k((k_down_res_sell_ad<VB, I, decltype(kb)::value>), dim3(blocks_for(L.A.n)), dim3(kBlock),
-                             s, L.A.n, L.E.sp, L.E.uni, L.E.su, ix, (const float *)L.E.svd, (const float *)p, b,
-                             (float *)pr, done, st);
+                else if (std::is_same<V, float>::value && L.E.svd && !y && L.E.stream)  // values of A D
+                    launch_k((k_down_res_sell_ad<VB, I, decltype(kb)::value, true>), dim3(blocks_for(L.A.n)),
+                             dim3(kBlock), s, L.A.n, L.E.sp, L.E.uni, L.E.su, ix, (const float *)L.E.svd,
+                             (const float *)p, b, (float *)pr, done, st);
+                else if (std::is_same<V, float>::value && L.E.svd && !y)  // one gather per term
+                    launch_k((k_down_res_sell_ad<VB, I, decltype(kb)::value, false>), dim3(blocks_for(L.A.n)),
+                             dim3(kBlock), s, L.A.n, L.E.sp, L.E.uni, L.E.su, ix, (const float *)L.E.svd,
+                             (const float *)p, b, (float *)pr, done, st);
                 else
                     launch_k((k_down_res_sell<V, VB, I, S, decltype(kb)::value>), dim3(blocks_for(L.A.n)), dim3(kBlock),
                              s, L.A.n, L.E.sp, L.E.uni, L.E.su, ix, vals, dinv, p, b, pr, (const V *)y, done, st);
@@ -1227,8 +1231,11 @@ void up_t(hipStream_t s, const Level &L, const V *a, const V *dinv, const V *p, 
                 if (split_slots(L, decltype(kb)::value))
                     launch_k((k_smooth_sell_p<V, VB, VX, I, S, 8>), dim3(L.E.nslices), dim3(kBlock), s, L.A.n, L.E.sp,
                              L.E.uni, L.E.su, ix, vals, dinv, b, xp, x, done);
+                else if (L.E.stream)  // values streamed non-temporally
+                    launch_k((k_smooth_sell<V, VB, VX, I, S, decltype(kb)::value, true>), dim3(blocks_for(L.A.n)),
+                             dim3(kBlock), s, L.A.n, L.E.sp, L.E.uni, L.E.su, ix, vals, dinv, b, xp, x, done);
                 else
-                    launch_k((k_smooth_sell<V, VB, VX, I, S, decltype(kb)::value>), dim3(blocks_for(L.A.n)),
+                    launch_k((k_smooth_sell<V, VB, VX, I, S, decltype(kb)::value, false>), dim3(blocks_for(L.A.n)),
                              dim3(kBlock), s, L.A.n, L.E.sp, L.E.uni, L.E.su, ix, vals, dinv, b, xp, x, done);
             });
             return;
@@ -1501,10 +1508,6 @@ void launch_resid(hipStream_t s, const Level &L, int nb, const double *b, const 
 // partials for its finalize step); the vector update keeps the 2048 of nb
 // (with 1024 it measured 55 -> 60 us there).
 constexpr int kSpmvBlocks = 1024;
-// Matrix values beyond this many bytes are streamed non-temporally by the
-// product (160^3: 228 MB of float64 values, 78.6 -> 74.8 us; 128^3's 117 MB
-// unchanged; 100^3's 28 MB of float32 values stay in the Infinity Cache).
-constexpr long long kStreamValues = 64LL << 20;
 bool slot_split_level(const Level &L) { return L.E.sp && split_slots(L, L.E.wide ? 16 : 8); }
 
 int spmv_dots_grid(const Level &L, int nb) {
@@ -1522,12 +1525,11 @@ void launch_spmv_dots(hipStream_t s, const Level &L, int nb, int first, const do
             if (split_slots(L, decltype(kb)::value))
                 launch_k((k_spmv_dots_sell_p<I, S, 4>), dim3(nb), dim3(kBlock), s, L.A.n, L.E.sp, L.E.uni, L.E.su,
                          ix, vals, w, r, q, v, partials, scal + 10);
-            else
-                if ((long long)L.A.nnz * (long long)sizeof(S) > kStreamValues)
-                    launch_k((k_spmv_dots_sell<I, S, decltype(kb)::value, true>), dim3(nb), dim3(kBlock), s, L.A.n, L.E.sp,
+            else if (L.E.stream)  // values streamed non-temporally
+                launch_k((k_spmv_dots_sell<I, S, decltype(kb)::value, true>), dim3(nb), dim3(kBlock), s, L.A.n, L.E.sp,
                          L.E.uni, L.E.su, ix, vals, w, r, q, v, partials, scal + 10);
-                else
-                    launch_k((k_spmv_dots_sell<I, S, decltype(kb)::value, false>), dim3(nb), dim3(kBlock), s, L.A.n, L.E.sp,
+            else
+                launch_k((k_spmv_dots_sell<I, S, decltype(kb)::value, false>), dim3(nb), dim3(kBlock), s, L.A.n, L.E.sp,
                          L.E.uni, L.E.su, ix, vals, w, r, q, v, partials, scal + 10);
         });
         return;
