@@ -95,7 +95,7 @@ k_down_res_sell_ad(int n, const int *__restrict__ sp, const int *__restrict__ un
 //   pr_i = p_i (b_i - sum_j a_ij dinv_j b_j),
 // followed by the restriction b_c[E] = sum of pr over E's members in ascending
 // order (the order a serial P^T r takes).
-template <typename V, typename VB, typename I, typename S, int kB>
+template <typename V, typename VB, typename I, typename S, int kB, bool NT>
 __global__ void __launch_bounds__(kBlock)
 k_down_res_sell(int n, const int *__restrict__ sp, const int *__restrict__ uni,
                 const int *__restrict__ su, const I *__restrict__ sc,
@@ -110,8 +110,10 @@ k_down_res_sell(int n, const int *__restrict__ sp, const int *__restrict__ uni,
     if (i >= n) return;
     const V pi = p[i], bi = (V)b[i];  // loaded first, to overlap the product's loads
     V s;
-    if (y) s = sell_row<V, S, I, kB>(n, sp, uni, su, sc, sv, i, [&](int j) { return y[j]; });
-    else s = sell_row<V, S, I, kB>(n, sp, uni, su, sc, sv, i, [&](int j) { return dinv[j] * (V)b[j]; });
+    auto gy = [&](int j) { return y[j]; };
+    auto gd = [&](int j) { return dinv[j] * (V)b[j]; };
+    if (y) s = sell_row<V, S, I, kB, decltype(gy), NT>(n, sp, uni, su, sc, sv, i, gy);
+    else s = sell_row<V, S, I, kB, decltype(gd), NT>(n, sp, uni, su, sc, sv, i, gd);
     pr[i] = pi * (bi - s);
 }
 

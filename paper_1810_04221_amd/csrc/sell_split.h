@@ -17,7 +17,7 @@
 // ----------------------------------------------------------------------------
 constexpr int kParts = kBlock / kSlice;
 
-template <int kB, bool Uni, typename V, typename S, typename I, typename F>
+template <int kB, bool Uni, typename V, typename S, typename I, typename F, bool NT = false>
 __device__ __forceinline__ V sell_part(const S *a, const int *u, const I *c, int n, int i, int w, int q, F f) {
     V s = V(0);
     for (int k0 = q; k0 < w; k0 += kB * kParts) {
@@ -26,7 +26,8 @@ __device__ __forceinline__ V sell_part(const S *a, const int *u, const I *c, int
 #pragma unroll
         for (int t = 0; t < kB; ++t) {
             const int k = min(k0 + t * kParts, w - 1);
-            av[t] = a[k * kSlice];
+            if (NT) av[t] = __builtin_nontemporal_load(&a[k * kSlice]);
+            else av[t] = a[k * kSlice];
             if (Uni) {
                 const int cc = i + u[k];
                 fv[t] = f((unsigned)cc < (unsigned)n ? cc : i);
@@ -42,7 +43,7 @@ __device__ __forceinline__ V sell_part(const S *a, const int *u, const I *c, int
 }
 
 // Wave q's part of row sl * 64 + lane (0 for rows past n).
-template <typename V, typename S, typename I, int kB, typename F>
+template <typename V, typename S, typename I, int kB, typename F, bool NT = false>
 __device__ __forceinline__ V sell_row_part(int n, const int *__restrict__ sp, const int *__restrict__ uni,
                                            const int *__restrict__ su, const I *__restrict__ sc,
                                            const S *__restrict__ sv, int sl, F f) {
@@ -52,8 +53,8 @@ __device__ __forceinline__ V sell_row_part(int n, const int *__restrict__ sp, co
     const S *a = sv + beg + lane;
     const int *u = su + beg / kSlice;
     const I *c = sc + beg + lane;
-    if (uf) return sell_part<kB, true, V>(a, u, c, n, i, w, q, f);
-    return sell_part<kB, false, V>(a, u, c, n, i, w, q, f);
+    if (uf) return sell_part<kB, true, V, S, I, F, NT>(a, u, c, n, i, w, q, f);
+    return sell_part<kB, false, V, S, I, F, NT>(a, u, c, n, i, w, q, f);
 }
 
 // The P partial sums of each row of the slice, added in wave order (valid in wave 0).
@@ -69,7 +70,9 @@ __device__ __forceinline__ V parts_sum(V s, V (&red)[kParts][kSlice]) {
     return t;
 }
 
-template <typename V, typename VB, typename I, typename S, int kB>
+// NT: the values streamed non-temporally (Sell::stream; the slot-split
+// smoother keeps them cached: streaming measured slower there).
+template <typename V, typename VB, typename I, typename S, int kB, bool NT>
 __global__ void __launch_bounds__(kBlock)
 k_down_res_sell_p(int n, const int *__restrict__ sp, const int *__restrict__ uni, const int *__restrict__ su,
                   const I *__restrict__ sc, const S *__restrict__ sv, const V *__restrict__ dinv,
@@ -82,8 +85,10 @@ k_down_res_sell_p(int n, const int *__restrict__ sp, const int *__restrict__ uni
     const int sl = xcd_block(blockIdx.x, gridDim.x);
     const int i = sl * kSlice + (int)threadIdx.x % kSlice;
     V s;
-    if (y) s = sell_row_part<V, S, I, kB>(n, sp, uni, su, sc, sv, sl, [&](int j) { return y[j]; });
-    else s = sell_row_part<V, S, I, kB>(n, sp, uni, su, sc, sv, sl, [&](int j) { return dinv[j] * (V)b[j]; });
+    auto gy = [&](int j) { return y[j]; };
+    auto gd = [&](int j) { return dinv[j] * (V)b[j]; };
+    if (y) s = sell_row_part<V, S, I, kB, decltype(gy), NT>(n, sp, uni, su, sc, sv, sl, gy);
+    else s = sell_row_part<V, S, I, kB, decltype(gd), NT>(n, sp, uni, su, sc, sv, sl, gd);
     const V t = parts_sum(s, red);
     if (threadIdx.x < kSlice && i < n) pr[i] = p[i] * ((V)b[i] - t);
 }
@@ -105,7 +110,7 @@ k_smooth_sell_p(int n, const int *__restrict__ sp, const int *__restrict__ uni, 
 // The flexible-CG product v = A w with the dot products (w.r, w.v, w.q) of
 // Algorithm 3, one slice per workgroup: a grid of one workgroup per slice, each
 // writing its own partials (summed in workgroup order by the finalize step).
-template <typename I, typename S, int kB>
+template <typename I, typename S, int kB, bool NT>
 __global__ void __launch_bounds__(kBlock)
 k_spmv_dots_sell_p(int n, const int *__restrict__ sp, const int *__restrict__ uni, const int *__restrict__ su,
                    const I *__restrict__ sc, const S *__restrict__ sv, const double *__restrict__ w,
@@ -115,7 +120,8 @@ k_spmv_dots_sell_p(int n, const int *__restrict__ sp, const int *__restrict__ un
     if (done && *done != 0.0) return;
     const int sl = xcd_block(blockIdx.x, gridDim.x);
     const int i = sl * kSlice + (int)threadIdx.x % kSlice;
-    const double s = sell_row_part<double, S, I, kB>(n, sp, uni, su, sc, sv, sl, [&](int j) { return w[j]; });
+    auto g = [&](int j) { return w[j]; };
+    const double s = sell_row_part<double, S, I, kB, decltype(g), NT>(n, sp, uni, su, sc, sv, sl, g);
     const double t = parts_sum(s, red);
     double acc[3] = {0.0, 0.0, 0.0};
     if (threadIdx.x < kSlice && i < n) {

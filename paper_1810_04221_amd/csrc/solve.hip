@@ -1183,20 +1183,23 @@ void down_t(hipStream_t s, const Level &L, const V *a, const V *dinv, const V *p
             with_sell<V>(L.E, [&](auto *ix, auto *vals, auto kb) {
                 using I = std::remove_const_t<std::remove_pointer_t<decltype(ix)>>;
                 using S = std::remove_const_t<std::remove_pointer_t<decltype(vals)>>;
-                if (split_slots(L, decltype(kb)::value))
-                    launch_k((k_down_res_sell_p<V, VB, I, S, 8>), dim3(L.E.nslices), dim3(kBlock), s, L.A.n, L.E.sp,
-                             L.E.uni, L.E.su, ix, vals, dinv, p, b, pr, (const V *)y, done, st);
-                else if (std::is_same<V, float>::value && L.E.svd && !y && L.E.stream)  // values of A D
-                    launch_k((k_down_res_sell_ad<VB, I, decltype(kb)::value, true>), dim3(blocks_for(L.A.n)),
-                             dim3(kBlock), s, L.A.n, L.E.sp, L.E.uni, L.E.su, ix, (const float *)L.E.svd,
-                             (const float *)p, b, (float *)pr, done, st);
-                else if (std::is_same<V, float>::value && L.E.svd && !y)  // one gather per term
-                    launch_k((k_down_res_sell_ad<VB, I, decltype(kb)::value, false>), dim3(blocks_for(L.A.n)),
-                             dim3(kBlock), s, L.A.n, L.E.sp, L.E.uni, L.E.su, ix, (const float *)L.E.svd,
-                             (const float *)p, b, (float *)pr, done, st);
-                else
-                    launch_k((k_down_res_sell<V, VB, I, S, decltype(kb)::value>), dim3(blocks_for(L.A.n)), dim3(kBlock),
-                             s, L.A.n, L.E.sp, L.E.uni, L.E.su, ix, vals, dinv, p, b, pr, (const V *)y, done, st);
+                // NT: the values streamed non-temporally (Sell::stream)
+                auto go = [&](auto nt) {
+                    constexpr bool NT = decltype(nt)::value;
+                    constexpr int B = decltype(kb)::value;
+                    if (split_slots(L, B))
+                        launch_k((k_down_res_sell_p<V, VB, I, S, 8, NT>), dim3(L.E.nslices), dim3(kBlock), s, L.A.n,
+                                 L.E.sp, L.E.uni, L.E.su, ix, vals, dinv, p, b, pr, (const V *)y, done, st);
+                    else if (std::is_same<V, float>::value && L.E.svd && !y)  // values of A D: one gather per term
+                        launch_k((k_down_res_sell_ad<VB, I, B, NT>), dim3(blocks_for(L.A.n)), dim3(kBlock), s, L.A.n,
+                                 L.E.sp, L.E.uni, L.E.su, ix, (const float *)L.E.svd, (const float *)p, b, (float *)pr,
+                                 done, st);
+                    else
+                        launch_k((k_down_res_sell<V, VB, I, S, B, NT>), dim3(blocks_for(L.A.n)), dim3(kBlock), s,
+                                 L.A.n, L.E.sp, L.E.uni, L.E.su, ix, vals, dinv, p, b, pr, (const V *)y, done, st);
+                };
+                if (L.E.stream) go(std::true_type{});
+                else go(std::false_type{});
             });
         }
         if (part == 1) return;
@@ -1522,15 +1525,17 @@ void launch_spmv_dots(hipStream_t s, const Level &L, int nb, int first, const do
             using S = std::remove_const_t<std::remove_pointer_t<decltype(vals)>>;
             // nb = L.E.nslices (spmv_dots_grid); batches of four slots per wave, which
             // measured faster than eight here (the residual and smoother keep eight)
-            if (split_slots(L, decltype(kb)::value))
-                launch_k((k_spmv_dots_sell_p<I, S, 4>), dim3(nb), dim3(kBlock), s, L.A.n, L.E.sp, L.E.uni, L.E.su,
-                         ix, vals, w, r, q, v, partials, scal + 10);
-            else if (L.E.stream)  // values streamed non-temporally
-                launch_k((k_spmv_dots_sell<I, S, decltype(kb)::value, true>), dim3(nb), dim3(kBlock), s, L.A.n, L.E.sp,
-                         L.E.uni, L.E.su, ix, vals, w, r, q, v, partials, scal + 10);
-            else
-                launch_k((k_spmv_dots_sell<I, S, decltype(kb)::value, false>), dim3(nb), dim3(kBlock), s, L.A.n, L.E.sp,
-                         L.E.uni, L.E.su, ix, vals, w, r, q, v, partials, scal + 10);
+            auto go = [&](auto nt) {  // NT: the values streamed non-temporally (Sell::stream)
+                constexpr bool NT = decltype(nt)::value;
+                if (split_slots(L, decltype(kb)::value))
+                    launch_k((k_spmv_dots_sell_p<I, S, 4, NT>), dim3(nb), dim3(kBlock), s, L.A.n, L.E.sp, L.E.uni,
+                             L.E.su, ix, vals, w, r, q, v, partials, scal + 10);
+                else
+                    launch_k((k_spmv_dots_sell<I, S, decltype(kb)::value, NT>), dim3(nb), dim3(kBlock), s, L.A.n,
+                             L.E.sp, L.E.uni, L.E.su, ix, vals, w, r, q, v, partials, scal + 10);
+            };
+            if (L.E.stream) go(std::true_type{});
+            else go(std::false_type{});
         });
         return;
     }
