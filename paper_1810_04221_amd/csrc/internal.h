@@ -162,8 +162,9 @@ struct Sell {
     float *svd = nullptr;
     double mixed = 1.0;  // fraction of the slots in slices that are not uniform
     int wide = 0;        // slices average more than kWideSlots slots: batches of 16
-    // the solve's one-thread-per-row kernels load the values non-temporally: set
-    // on every level when the values a solve iteration reads exceed kStreamSolve
+    // the solve's product, its down-leg residuals and its one-thread-per-row
+    // smoother load the values non-temporally: set on every level when the
+    // values a solve iteration reads exceed kStreamSolve
     int stream = 0;
 };
 
@@ -173,7 +174,9 @@ struct Sell {
 // iterations, and non-temporal loads that skip it measured slower (100^3:
 // about 0.1 GB, solve +4.6%); above it the cache cannot hold them and the L2
 // keeps the gathered vectors instead (160^3 residual 43.0 -> 40.4 us, product
-// 78.6 -> 74.8 us; 128^3 and 160^3 ratio-rule solves -4.6% and -1.4%).
+// 78.6 -> 74.8 us; 128^3 and 160^3 ratio-rule solves -4.6% and -1.4%,
+// elasticity -4.9%).  The slot-split smoother measured slower streamed and
+// keeps cached loads.
 constexpr long long kStreamSolve = 192LL << 20;
 
 // One level of the hierarchy.  Row i of A^k, its l1 inverse diagonal, the
