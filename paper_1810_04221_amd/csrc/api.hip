@@ -162,6 +162,84 @@ int read_back_plain(hipStream_t s, const void *dev, size_t bytes, void *host) {
     return BCM_OK;
 }
 
+// The coarsest level's StarView when it is a star (one hub row, every other
+// row holding only its diagonal and the hub entry); otherwise L.star stays
+// unset and the coarse solve keeps its sweep kernels.  The matrix is read back
+// once; E's weights F_m are formed here in FP64, in the hub row's order.
+int build_star(bcm_handle *h, hipStream_t s, Level &L, int sweeps) {
+    const int n = L.A.n, nnz = L.A.nnz;
+    std::vector<int> rp(n + 1), ci(nnz);
+    std::vector<double> a(nnz), dinv(n);
+    int rc = read_back(s, L.A.rp, sizeof(int) * (n + 1), rp.data());
+    if (!rc) rc = read_back(s, L.A.ci, sizeof(int) * nnz, ci.data());
+    if (!rc) rc = read_back(s, L.A.v, sizeof(double) * nnz, a.data());
+    if (!rc) rc = read_back(s, L.dinv, sizeof(double) * n, dinv.data());
+    if (rc) return rc;
+    int hub = -1;
+    for (int i = 0; i < n; ++i)
+        if (rp[i + 1] - rp[i] > 2) {
+            if (hub >= 0) return BCM_OK;  // two rows beyond two entries: not a star
+            hub = i;
+        }
+    if (hub < 0) return BCM_OK;
+    // every other row: its diagonal, and at most the hub besides
+    std::vector<double> c(n, 0.0), f(n, 0.0);
+    for (int j = 0; j < n; ++j) {
+        if (j == hub) continue;
+        bool diag = false;
+        double ajj = 0.0, ajh = 0.0;
+        for (int q = rp[j]; q < rp[j + 1]; ++q) {
+            if (ci[q] == j) { diag = true; ajj = a[q]; }
+            else if (ci[q] == hub) ajh = a[q];
+            else return BCM_OK;
+        }
+        if (!diag) return BCM_OK;
+        c[j] = 1.0 - dinv[j] * ajj;
+        f[j] = dinv[j] * ajh;
+    }
+    std::vector<int> hj;
+    std::vector<double> ha;
+    double ahh = 0.0;
+    for (int q = rp[hub]; q < rp[hub + 1]; ++q) {
+        if (ci[q] == hub) ahh = a[q];
+        else { hj.push_back(ci[q]); ha.push_back(a[q]); }
+    }
+    const int M = sweeps - 1;
+    std::vector<double> F(std::max(M, 1), 0.0);
+    for (size_t q = 0; q < hj.size(); ++q) {
+        const int j = hj[q];
+        double t = ha[q] * f[j];
+        for (int m = 0; m < M; ++m) { F[m] += t; t *= c[j]; }
+    }
+    StarView &sv = L.star;
+    const int nh = (int)hj.size();
+    int *dhj = h->persist.get_n<int>(std::max(nh, 1));
+    double *dha = h->persist.get_n<double>(std::max(nh, 1));
+    double *dc = h->persist.get_n<double>(n);
+    double *dF = h->persist.get_n<double>(F.size());
+    double *dpart = h->persist.get_n<double>((size_t)(kStarMaxSweeps - 1) * kStarBlocks);
+    double *dxh = h->persist.get_n<double>(kStarMaxSweeps + 1);
+    NOMEM(dhj && dha && dc && dF && dpart && dxh);
+    if (nh) {
+        HIPCHK(hipMemcpyAsync(dhj, hj.data(), sizeof(int) * nh, hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(dha, ha.data(), sizeof(double) * nh, hipMemcpyHostToDevice, s));
+    }
+    HIPCHK(hipMemcpyAsync(dc, c.data(), sizeof(double) * n, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(dF, F.data(), sizeof(double) * F.size(), hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+    sv.hub = hub;
+    sv.nh = nh;
+    sv.hj = dhj;
+    sv.ha = dha;
+    sv.c = dc;
+    sv.F = dF;
+    sv.part = dpart;
+    sv.xh = dxh;
+    sv.ahh = ahh;
+    sv.dh = dinv[hub];
+    return BCM_OK;
+}
+
 struct SweepOut {
     int prof_gal = -1;  // setup profile bracket of this sweep's Galerkin product
     int nc = 0;
@@ -1080,6 +1158,10 @@ int build_hierarchy(bcm_handle *h, const bcm_csr *Ain, const double *win) {
         h->ctmp[0] = h->persist.get_n<double>(h->lv[h->nl - 1].A.n);
         h->ctmp[1] = h->persist.get_n<double>(h->lv[h->nl - 1].A.n);
         NOMEM(h->ctmp[0] && h->ctmp[1]);
+        if (P.coarse_sweeps >= 1 && P.coarse_sweeps <= kStarMaxSweeps && h->lv[h->nl - 1].lr.n == 1) {
+            const int rc = build_star(h, s, h->lv[h->nl - 1], P.coarse_sweeps);
+            if (rc) return rc;
+        }
     }
     // flexible CG state
     h->r = h->persist.get_n<double>(n);

@@ -179,6 +179,30 @@ struct Sell {
 // keeps cached loads.
 constexpr long long kStreamSolve = 192LL << 20;
 
+// A coarsest level shaped as a star: one hub row coupled to every other row,
+// each of which holds only its diagonal and the hub entry.  The coarse solve's
+// sweeps from zero are then a recurrence in the hub's value alone (k_star_*):
+// with c_j = 1 - d_j a_jj, row j after k sweeps is
+//   sum_{t<k} c_j^(k-1-t) d_j (b_j - a_jh x_h^(t)),
+// so the hub row's product after k sweeps is
+//   sum_{t<k} (E_(k-1-t) - F_(k-1-t) x_h^(t)),
+//   E_m = sum_j a_hj c_j^m d_j b_j,  F_m = sum_j a_hj c_j^m d_j a_jh
+// (j over the hub row's columns off the diagonal).  F depends on the matrix
+// alone and is formed at setup; E takes one pass over the hub row.
+constexpr int kStarBlocks = 64;      // workgroups of the pass that forms E
+constexpr int kStarMaxSweeps = 32;   // sweeps beyond this keep the sweep kernels
+struct StarView {
+    int hub = -1;                  // -1: not a star
+    int nh = 0;                    // hub-row entries off the diagonal
+    const int *hj = nullptr;       // their columns
+    const double *ha = nullptr;    // their values a_hj
+    const double *c = nullptr;     // c_j = 1 - d_j a_jj per row
+    const double *F = nullptr;     // F_m, m < sweeps - 1
+    double *part = nullptr;        // E partials: (kStarMaxSweeps - 1) x kStarBlocks
+    double *xh = nullptr;          // x_h after t sweeps, t = 0 .. sweeps
+    double ahh = 0.0, dh = 0.0;    // the hub's diagonal and inverse l1 diagonal
+};
+
 // One level of the hierarchy.  Row i of A^k, its l1 inverse diagonal, the
 // composed prolongator P^k (one nonzero per row: column agg[i], value p[i]),
 // and the members of every coarse aggregate (P^k transposed) in ascending
@@ -203,6 +227,7 @@ struct Level {
     void *xs = nullptr;               // W/K-cycle: result of the second coarse cycle (cycle precision)
     void *kv = nullptr;               // K-cycle: A c1, the product of the first coarse direction
     double *S = nullptr;  // coarsest level only: dense sweep operator (n <= kCoarseDense)
+    StarView star;        // coarsest level only: the star recurrence (hub >= 0)
 };
 
 // Device-side view of one level for the single-workgroup tail kernel

@@ -955,12 +955,95 @@ k_jacobi_sweep(int n, const int *__restrict__ rp, const int *__restrict__ ci, co
     }
 }
 
+// The coarse solve on a star level (StarView): E_m over the hub row's
+// entries, m < sweeps - 1, one partial per workgroup and m.
+template <typename VB>
+__global__ void __launch_bounds__(kBlock)
+k_star_sums(StarView sv, int sweeps, const double *__restrict__ dinv, const VB *__restrict__ b,
+            const double *__restrict__ done) {
+    if (done && *done != 0.0) return;
+    constexpr int K = kStarMaxSweeps - 1;
+    double acc[K];
+#pragma unroll
+    for (int m = 0; m < K; ++m) acc[m] = 0.0;
+    for (int q = blockIdx.x * kBlock + threadIdx.x; q < sv.nh; q += gridDim.x * kBlock) {
+        const int j = sv.hj[q];
+        const double cj = sv.c[j];
+        double t = sv.ha[q] * (dinv[j] * (double)b[j]);
+#pragma unroll
+        for (int m = 0; m < K; ++m)
+            if (m < sweeps - 1) {
+                acc[m] += t;
+                t *= cj;
+            }
+    }
+    block_partials<K>(acc, sv.part);
+}
+
+// One workgroup: E_m from the partials (in workgroup order), then the hub's
+// values x_h^(t), t = 0 .. sweeps, by the recurrence; writes x at the hub.
+template <typename VB, typename VX>
+__global__ void __launch_bounds__(kBlock)
+k_star_hub(StarView sv, int sweeps, const VB *__restrict__ b, VX *__restrict__ x, const double *__restrict__ done) {
+    if (done && *done != 0.0) return;
+    constexpr int K = kStarMaxSweeps - 1;
+    __shared__ double lds[K * 16];
+    double e[K];
+#pragma unroll
+    for (int m = 0; m < K; ++m) e[m] = 0.0;
+    add_partials<K, 1>(e, sv.part, kStarBlocks);
+    block_sum<K>(e, lds);
+    if (threadIdx.x != 0) return;
+    __shared__ double se[K], xh[kStarMaxSweeps + 1];  // one thread: indexed at run time
+#pragma unroll
+    for (int m = 0; m < K; ++m) se[m] = e[m];
+    const double bh = (double)b[sv.hub];
+    xh[0] = 0.0;
+    for (int k = 0; k < sweeps; ++k) {
+        double sum = 0.0;  // the hub row's product after k sweeps, off the diagonal
+        for (int t = 0; t < k; ++t) sum += se[k - 1 - t] - sv.F[k - 1 - t] * xh[t];
+        xh[k + 1] = xh[k] + sv.dh * (bh - (sv.ahh * xh[k] + sum));
+    }
+    for (int t = 0; t <= sweeps; ++t) sv.xh[t] = xh[t];
+    x[sv.hub] = (VX)xh[sweeps];
+}
+
+// Every row but the hub: its sweeps with the hub's values x_h^(t), each in
+// the order and rounding of k_jacobi_sweep (the row's two products in column
+// order).
+template <typename VB, typename VX>
+__global__ void __launch_bounds__(kBlock)
+k_star_rows(StarView sv, int n, int sweeps, const int *__restrict__ rp, const int *__restrict__ ci,
+            const double *__restrict__ a, const double *__restrict__ dinv, const VB *__restrict__ b,
+            VX *__restrict__ x, const double *__restrict__ done) {
+    if (done && *done != 0.0) return;
+    const int j = blockIdx.x * kBlock + threadIdx.x;
+    if (j >= n || j == sv.hub) return;
+    const int s0 = rp[j], e0 = rp[j + 1];
+    double ajj = 0.0, ajh = 0.0;
+    bool hub_first = false;
+    for (int q = s0; q < e0; ++q) {
+        if (ci[q] == j) ajj = a[q];
+        else { ajh = a[q]; hub_first = q == s0; }
+    }
+    const double dj = dinv[j], bj = (double)b[j];
+    double xj = 0.0;
+    for (int t = 0; t < sweeps; ++t) {
+        const double xt = sv.xh[t];
+        const double rs = hub_first ? ajh * xt + ajj * xj : ajj * xj + ajh * xt;
+        xj = xj + dj * (bj - rs);
+    }
+    x[j] = (VX)xj;
+}
+
 // ----------------------------------------------------------------------------
 // Flexible CG kernels (Algorithm 3).  Fixed grid of nb blocks with a
 // grid-stride loop over row groups; every block stores its partial sums and a
 // one-block finalize kernel adds them in block order (deterministic).
-// scal: [0] alpha [1] beta [2] gamma [3] rho (of the last step) [4] ||r||^2
-//       [5] ||b||^2 [6] breakdown flag [8] gamma_i / rho_{i-1} [9] alpha_i / rho_i
+// scal: [0] alpha [1] beta [2] gamma [4] ||r||^2 [5] ||b||^2 [6] breakdown
+//       flag [7] update partials not yet taken by the stop test
+//       [8] gamma_i / rho_{i-1} [9] alpha_i / rho_i [10] loop ended
+//       [11] iterations [12] tol^2 ||b||^2 [13] itmax [14], [15] rho ring
 // ----------------------------------------------------------------------------
 
 constexpr int kRows = 4;  // rows per lane group in the streaming row kernels
@@ -1285,6 +1368,14 @@ void coarse_t(hipStream_t s, const Level &L, int sweeps, const VB *b, VX *x, dou
     if (coarse_in_lds(n, L.A.nnz, L.lr.n > 0)) {
         hipLaunchKernelGGL((k_coarse<VB, VX>), dim3(1), dim3(1024), 0, s, n, L.A.nnz, L.A.rp, L.A.ci, L.A.v, L.dinv,
                            b, x, sweeps, 0, done);
+        return;
+    }
+    if (L.star.hub >= 0 && sweeps >= 1 && sweeps <= kStarMaxSweeps) {
+        // a star: the sweeps as the hub's recurrence (three launches instead of one per sweep)
+        hipLaunchKernelGGL((k_star_sums<VB>), dim3(kStarBlocks), dim3(kBlock), 0, s, L.star, sweeps, L.dinv, b, done);
+        hipLaunchKernelGGL((k_star_hub<VB, VX>), dim3(1), dim3(kBlock), 0, s, L.star, sweeps, b, x, done);
+        hipLaunchKernelGGL((k_star_rows<VB, VX>), dim3(blocks_for(n)), dim3(kBlock), 0, s, L.star, n, sweeps, L.A.rp,
+                           L.A.ci, L.A.v, L.dinv, b, x, done);
         return;
     }
     double *xo = ta, *xn = tb;

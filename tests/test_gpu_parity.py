@@ -655,6 +655,44 @@ def test_long_rows_hierarchy_cycle_solve(B, ora, case, group, precision):
     h.close()
 
 
+def _random_star(n, seed):
+    # one hub (row 0) coupled to every other row, each of which holds only its
+    # diagonal and the hub entry; random couplings and diagonal dominance
+    rng = np.random.default_rng(seed)
+    a = -rng.uniform(0.1, 1.0, n - 1)
+    rows = np.concatenate([np.zeros(n - 1, int), np.arange(1, n), np.arange(n)])
+    cols = np.concatenate([np.arange(1, n), np.zeros(n - 1, int), np.arange(n)])
+    diag = np.concatenate([[1.1 * np.abs(a).sum()], np.abs(a) * rng.uniform(1.0, 2.0, n - 1)])
+    A = sp.csr_matrix((np.concatenate([a, a, diag]), (rows, cols)), shape=(n, n))
+    A.sort_indices()
+    return A.indptr.astype(np.int32), A.indices.astype(np.int32), A.data.copy()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_star_coarsest_level_recurrence(B, ora, precision):
+    # a coarsest level shaped as a star (too large for the dense operator, its
+    # hub a long row) takes the hub recurrence instead of one launch per
+    # sweep: the same 20 sweeps up to the rounding of the hub's sums
+    n = 6000
+    rp, ci, va = _random_star(n, 5)
+    say(f"star coarsest level {precision} n={n}")
+    h = B.Hierarchy(rp, ci, va, max_coarse=2 * n, precision=precision)
+    ho = ora.Hierarchy(rp, ci, va, np.ones(n), max_coarse=2 * n)
+    assert h.info()["nl"] == 1 and h.info()["long_rows"] >= 1
+    for seed in (41, 42):
+        r = P.uniform_rhs(n, seed)
+        z, zo = h.precond(r).cpu().numpy(), ho.vcycle(r)
+        _close_entries(z, zo, 1e-12 if precision == "fp64" else ENTRY_FP32)
+    b = P.uniform_rhs(n, 43)
+    x = h.solve(b, tol=1e-9).cpu().numpy()
+    _, io = ho.solve(b, tol=1e-9)
+    A = sp.csr_matrix((va, ci, rp), shape=(n, n))
+    assert np.linalg.norm(b - A @ x) <= 1e-9 * np.linalg.norm(b)
+    allow = 1 if precision == "fp64" else _fp32_allowance(io["iters"])
+    assert abs(h.info()["iters"] - io["iters"]) <= allow, (h.info()["iters"], io["iters"])
+    h.close()
+
+
 def test_true_residual_stagnation_status(B):
     # a tolerance below the rounding floor of b - A x: the recurrence residual
     # keeps falling, the true one cannot follow; after three restarts the solve
