@@ -955,6 +955,26 @@ k_jacobi_sweep(int n, const int *__restrict__ rp, const int *__restrict__ ci, co
     }
 }
 
+// block_sum with its final additions spread over the threads:
+// thread k (k < K, K <= blockDim.x) returns sum k, added in block_sum's order.
+template <int K>
+__device__ __forceinline__ double block_sum_spread(double (&v)[K], double *lds) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] = group_sum<64>(v[k]);
+    if (lane == 0)
+#pragma unroll
+        for (int k = 0; k < K; ++k) lds[k * 16 + wid] = v[k];
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x < K) {
+        s = lds[threadIdx.x * 16];
+        for (int w = 1; w < nw; ++w) s += lds[threadIdx.x * 16 + w];
+    }
+    __syncthreads();
+    return s;
+}
+
 // The coarse solve on a star level (StarView): E_m over the hub row's
 // entries, m < sweeps - 1, one partial per workgroup and m.
 template <typename VB>
@@ -963,6 +983,7 @@ k_star_sums(StarView sv, int sweeps, const double *__restrict__ dinv, const VB *
             const double *__restrict__ done) {
     if (done && *done != 0.0) return;
     constexpr int K = kStarMaxSweeps - 1;
+    __shared__ double lds[K * 16];
     double acc[K];
 #pragma unroll
     for (int m = 0; m < K; ++m) acc[m] = 0.0;
@@ -977,7 +998,9 @@ k_star_sums(StarView sv, int sweeps, const double *__restrict__ dinv, const VB *
                 t *= cj;
             }
     }
-    block_partials<K>(acc, sv.part);
+    // the workgroup's sums, each finished by its own thread
+    const double e = block_sum_spread<K>(acc, lds);
+    if (threadIdx.x < K) sv.part[(size_t)threadIdx.x * gridDim.x + blockIdx.x] = e;
 }
 
 // One workgroup: E_m from the partials (in workgroup order), then the hub's
@@ -988,20 +1011,21 @@ k_star_hub(StarView sv, int sweeps, const VB *__restrict__ b, VX *__restrict__ x
     if (done && *done != 0.0) return;
     constexpr int K = kStarMaxSweeps - 1;
     __shared__ double lds[K * 16];
+    __shared__ double se[K], sf[K], xh[kStarMaxSweeps + 1];  // the recurrence reads these at run-time indices
+    if (threadIdx.x < K) sf[threadIdx.x] = threadIdx.x < sweeps - 1 ? sv.F[threadIdx.x] : 0.0;
     double e[K];
 #pragma unroll
     for (int m = 0; m < K; ++m) e[m] = 0.0;
     add_partials<K, 1>(e, sv.part, kStarBlocks);
-    block_sum<K>(e, lds);
+    const double em = block_sum_spread<K>(e, lds);
+    if (threadIdx.x < K) se[threadIdx.x] = em;
+    __syncthreads();
     if (threadIdx.x != 0) return;
-    __shared__ double se[K], xh[kStarMaxSweeps + 1];  // one thread: indexed at run time
-#pragma unroll
-    for (int m = 0; m < K; ++m) se[m] = e[m];
     const double bh = (double)b[sv.hub];
     xh[0] = 0.0;
     for (int k = 0; k < sweeps; ++k) {
         double sum = 0.0;  // the hub row's product after k sweeps, off the diagonal
-        for (int t = 0; t < k; ++t) sum += se[k - 1 - t] - sv.F[k - 1 - t] * xh[t];
+        for (int t = 0; t < k; ++t) sum += se[k - 1 - t] - sf[k - 1 - t] * xh[t];
         xh[k + 1] = xh[k] + sv.dh * (bh - (sv.ahh * xh[k] + sum));
     }
     for (int t = 0; t <= sweeps; ++t) sv.xh[t] = xh[t];
