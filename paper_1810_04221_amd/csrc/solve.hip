@@ -1005,6 +1005,26 @@ k_star_sums(StarView sv, int sweeps, const double *__restrict__ dinv, const VB *
 
 // One workgroup: E_m from the partials (in workgroup order), then the hub's
 // values x_h^(t), t = 0 .. sweeps, by the recurrence; writes x at the hub.
+// The hub's recurrence for S sweeps known at compile time, every value in a
+// register; the same operations in the same order as the loop in k_star_hub.
+constexpr int kCoarseSweeps = 20;  // the coarse solve's default sweep count
+template <int S>
+__device__ __forceinline__ void star_recurrence(const double *se, const double *sf, double bh, const StarView &sv) {
+    double e[S], f[S], xh[S + 1];
+#pragma unroll
+    for (int m = 0; m < S - 1; ++m) { e[m] = se[m]; f[m] = sf[m]; }
+    xh[0] = 0.0;
+#pragma unroll
+    for (int k = 0; k < S; ++k) {
+        double sum = 0.0;
+#pragma unroll
+        for (int t = 0; t < k; ++t) sum += e[k - 1 - t] - f[k - 1 - t] * xh[t];
+        xh[k + 1] = xh[k] + sv.dh * (bh - (sv.ahh * xh[k] + sum));
+    }
+#pragma unroll
+    for (int t = 0; t <= S; ++t) sv.xh[t] = xh[t];
+}
+
 template <typename VB, typename VX>
 __global__ void __launch_bounds__(kBlock)
 k_star_hub(StarView sv, int sweeps, const VB *__restrict__ b, VX *__restrict__ x, const double *__restrict__ done) {
@@ -1022,14 +1042,18 @@ k_star_hub(StarView sv, int sweeps, const VB *__restrict__ b, VX *__restrict__ x
     __syncthreads();
     if (threadIdx.x != 0) return;
     const double bh = (double)b[sv.hub];
-    xh[0] = 0.0;
-    for (int k = 0; k < sweeps; ++k) {
-        double sum = 0.0;  // the hub row's product after k sweeps, off the diagonal
-        for (int t = 0; t < k; ++t) sum += se[k - 1 - t] - sf[k - 1 - t] * xh[t];
-        xh[k + 1] = xh[k] + sv.dh * (bh - (sv.ahh * xh[k] + sum));
+    if (sweeps == kCoarseSweeps) {
+        star_recurrence<kCoarseSweeps>(se, sf, bh, sv);  // in registers: no LDS round trip per term
+    } else {
+        xh[0] = 0.0;
+        for (int k = 0; k < sweeps; ++k) {
+            double sum = 0.0;  // the hub row's product after k sweeps, off the diagonal
+            for (int t = 0; t < k; ++t) sum += se[k - 1 - t] - sf[k - 1 - t] * xh[t];
+            xh[k + 1] = xh[k] + sv.dh * (bh - (sv.ahh * xh[k] + sum));
+        }
+        for (int t = 0; t <= sweeps; ++t) sv.xh[t] = xh[t];
     }
-    for (int t = 0; t <= sweeps; ++t) sv.xh[t] = xh[t];
-    x[sv.hub] = (VX)xh[sweeps];
+    x[sv.hub] = (VX)sv.xh[sweeps];
 }
 
 // Every row but the hub: its sweeps with the hub's values x_h^(t), each in
