@@ -181,7 +181,9 @@ constexpr long long kStreamSolve = 192LL << 20;
 
 // A coarsest level shaped as a star: one hub row coupled to every other row,
 // each of which holds only its diagonal and the hub entry.  The coarse solve's
-// sweeps from zero are then a recurrence in the hub's value alone (k_star_*):
+// sweeps from zero (the coarsest step of Algorithm 1: l1-Jacobi sweeps, 20 in
+// the Section 5 settings) are then a recurrence in the hub's value alone
+// (k_star_*), the same operator evaluated in another order:
 // with c_j = 1 - d_j a_jj, row j after k sweeps is
 //   sum_{t<k} c_j^(k-1-t) d_j (b_j - a_jh x_h^(t)),
 // so the hub row's product after k sweeps is
