@@ -58,8 +58,9 @@ SINGLE_KERNEL = ["down0", "up0", "spmv_dots", "update", "coarse", "setup_suitor"
 KERNEL_OF_CLASS = {"down0": "k_down_res_sell_ad (finest level: p * (b - (A D) b), the down leg's residual, on the values of A D)",
                    "up0": "k_smooth_sell (finest level: post-smoothing of the prolonged iterate)",
                    "spmv_dots": "k_spmv_dots_sell (v = A w and three dot products, finest level, FP64)",
-                   "update": "k_update (four vector updates and ||r||^2)",
-                   "coarse": "coarsest-level solve (k_coarse_dense on the folded levels, k_tail or k_coarse)",
+                   "update": "k_update (the step scalars from the product's partials, four vector updates and ||r||^2)",
+                   "coarse": "coarsest-level solve (k_coarse_dense on the folded levels, k_tail or k_coarse, the "
+                             "k_star_* recurrence on a star level, else k_jacobi_sweep)",
                    "setup_suitor": "k_suitor (Suitor matching, proposals raised by 64-bit atomicMax)"}
 
 
